@@ -1,0 +1,191 @@
+"""ctypes front end of the CPU FP64 reference (oracle/oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg. The GPU library never imports, links or calls it.
+
+Arrays are numpy float64 / int32 / uint8, C-contiguous. Layouts follow the C file:
+seeds SoA [6][S], tracks AoS [K+1][3], wire endpoints [n_w][6], CSR offsets [n_w+1].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+          "-shared", "-Wall", "-Wextra"]
+
+
+def build(src: str = SRC, out: str = LIB, extra=()) -> str:
+    """Compile the oracle with gcc (plain C, no FMA contraction, OpenMP over seeds)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", *CFLAGS, *extra, src, "-lm", "-o", tmp], check=True)
+    os.replace(tmp, out)
+    return out
+
+
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+_u8 = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _bind(lib):
+    lib.oracle_axis_value.restype = ctypes.c_double
+    lib.oracle_axis_value.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.c_int32]
+    lib.oracle_seed.restype = None
+    lib.oracle_seed.argtypes = [_d, _i32, ctypes.c_int64, _d]
+    lib.oracle_seed_grid.restype = None
+    lib.oracle_seed_grid.argtypes = [_d, _i32, _d]
+    lib.oracle_refine_grid.restype = None
+    lib.oracle_refine_grid.argtypes = [_d, _i32, ctypes.c_int64]
+    lib.oracle_track.restype = None
+    lib.oracle_track.argtypes = [_d, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int32, _d]
+    lib.oracle_wire_frame.restype = None
+    lib.oracle_wire_frame.argtypes = [_d, _d]
+    lib.oracle_dca2.restype = ctypes.c_double
+    lib.oracle_dca2.argtypes = [_d, ctypes.c_int32, _d, _i32]
+    lib.oracle_rss_track.restype = ctypes.c_double
+    lib.oracle_rss_track.argtypes = [_d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d,
+                                     ctypes.c_double]
+    lib.oracle_scan.restype = ctypes.c_int32
+    lib.oracle_scan.argtypes = [_d, ctypes.c_int64, _d, ctypes.c_int32, _d, ctypes.c_int32,
+                                _i32, _d, _d, ctypes.c_int32]
+    lib.oracle_argmin.restype = ctypes.c_int64
+    lib.oracle_argmin.argtypes = [_d, ctypes.c_int64]
+    lib.oracle_classify.restype = ctypes.c_int32
+    lib.oracle_classify.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _u8,
+                                    _d]
+    lib.oracle_scan_partition.restype = ctypes.c_int64
+    lib.oracle_scan_partition.argtypes = [_d, _i32, _d, ctypes.c_int32, ctypes.c_int32, _d,
+                                          ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _i32,
+                                          ctypes.c_int32]
+    return lib
+
+
+def load(path: str = LIB, rebuild: bool = False):
+    """Load the oracle, building it first when it is missing or older than its source."""
+    global _lib
+    if path == LIB and _lib is not None and not rebuild:
+        return _lib
+    if rebuild or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+        build(out=path)
+    lib = _bind(ctypes.CDLL(path))
+    if path == LIB:
+        _lib = lib
+    return lib
+
+
+def _p(a, t=_d):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32a(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Oracle:
+    """Thin numpy wrappers over one loaded oracle library."""
+
+    def __init__(self, lib=None):
+        self.lib = lib if lib is not None else load()
+
+    def axis_value(self, centre, half, n, i):
+        return self.lib.oracle_axis_value(centre, half, n, i)
+
+    def seed(self, grid, n, index):
+        out = np.empty(6)
+        self.lib.oracle_seed(_p(_f64(grid)), _p(_i32a(n), _i32), index, _p(out))
+        return out
+
+    def seed_grid(self, grid, n):
+        n = _i32a(n)
+        out = np.empty((6, int(np.prod(n.astype(np.int64)))))
+        self.lib.oracle_seed_grid(_p(_f64(grid)), _p(n, _i32), _p(out))
+        return out
+
+    def refine_grid(self, grid, n, best):
+        g = _f64(grid).copy()
+        self.lib.oracle_refine_grid(_p(g), _p(_i32a(n), _i32), int(best))
+        return g
+
+    def track(self, seed, bz, charge, h, K):
+        out = np.empty((K + 1, 3))
+        self.lib.oracle_track(_p(_f64(seed)), bz, charge, h, K, _p(out))
+        return out
+
+    def wire_frame(self, ends):
+        out = np.empty(8)
+        self.lib.oracle_wire_frame(_p(_f64(ends)), _p(out))
+        return out
+
+    def dca2(self, pts, frame):
+        pts = _f64(pts)
+        k = np.zeros(1, dtype=np.int32)
+        v = self.lib.oracle_dca2(_p(pts), pts.shape[0], _p(_f64(frame)), _p(k, _i32))
+        return v, int(k[0])
+
+    def rss_track(self, pts, wire_ends, offsets, drift, lam):
+        pts = _f64(pts)
+        ends = _f64(wire_ends)
+        frames = np.stack([self.wire_frame(e) for e in ends]) if len(ends) else np.zeros((1, 8))
+        return self.lib.oracle_rss_track(_p(pts), pts.shape[0], _p(_f64(frames)), len(ends),
+                                         _p(_i32a(offsets), _i32), _p(_f64(drift)), lam)
+
+    def scan(self, seeds, cfg, K, wire_ends, offsets, drift, n_threads=0):
+        """RSS of every seed (seeds SoA [6][S]); returns (rss, threads used)."""
+        seeds = _f64(seeds)
+        S = seeds.shape[1]
+        rss = np.empty(S)
+        ends = _f64(wire_ends).reshape(-1, 6)
+        used = self.lib.oracle_scan(_p(seeds), S, _p(_f64(cfg)), K, _p(ends), ends.shape[0],
+                                    _p(_i32a(offsets), _i32), _p(_f64(drift)), _p(rss),
+                                    n_threads)
+        return rss, used
+
+    def argmin(self, rss):
+        rss = _f64(rss)
+        return int(self.lib.oracle_argmin(_p(rss), rss.size))
+
+    def classify(self, seed, cfg, K, wire_ends, offsets, drift):
+        ends = _f64(wire_ends).reshape(-1, 6)
+        drift = _f64(drift)
+        mask = np.zeros(drift.size, dtype=np.uint8)
+        dca = np.empty(ends.shape[0])
+        nb = self.lib.oracle_classify(_p(_f64(seed)), _p(_f64(cfg)), K, _p(ends), ends.shape[0],
+                                      _p(_i32a(offsets), _i32), _p(drift), _p(mask, _u8),
+                                      _p(dca))
+        return mask, dca, int(nb)
+
+    def scan_partition(self, grid, n, cfg, K, n_refine, wire_ends, offsets, drift,
+                       n_threads=0):
+        """Coarse scan, n_refine re-scans, classification. Returns a dict."""
+        g = _f64(grid).copy()
+        n = _i32a(n)
+        S = int(np.prod(n.astype(np.int64)))
+        ends = _f64(wire_ends).reshape(-1, 6)
+        drift = _f64(drift)
+        rss = np.empty(S)
+        best_seed = np.zeros(6)
+        best_rss = np.zeros(1)
+        mask = np.zeros(drift.size, dtype=np.uint8)
+        nb = np.zeros(1, dtype=np.int32)
+        b = self.lib.oracle_scan_partition(_p(g), _p(n, _i32), _p(_f64(cfg)), K, n_refine,
+                                           _p(ends), ends.shape[0], _p(_i32a(offsets), _i32),
+                                           _p(drift), _p(rss), _p(best_seed), _p(best_rss),
+                                           _p(mask, _u8), _p(nb, _i32), n_threads)
+        return {"best": int(b), "grid": g, "rss": rss, "best_seed": best_seed,
+                "best_rss": float(best_rss[0]), "mask": mask, "n_borderline": int(nb[0])}

@@ -1,0 +1,380 @@
+"""Pins of the CPU reference: checks against what the paper and the mathematics fix.
+
+Every check takes an `oracle.Oracle` and raises AssertionError when the reference
+disagrees with something that does not come from it: closed forms (the RK4 step
+polynomial of a linear ODE, the analytic helix, skew-line distances), hand-computed
+cases with exactly representable answers, invariants (rotation about the field
+axis), special cases (a seed far from every wire gives N lambda^2), and a brute-force
+recomputation in long double with the plain 3-D distance formula.
+
+The same checks run on planted-mistake copies of the reference (test_oracle_mutants)
+to show that each plausible slip fails at least one of them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_1911_09340_amd import synth
+
+KAPPA = 0.299792458
+LD = np.longdouble
+
+
+# ------------------------------------------------------------------ RK4
+def rk4_closed_form(seed, bz, charge, h, K):
+    """Positions after n = 0..K classical RK4 steps of dx/ds = p/p0, dp/ds = c (p_y, -p_x, 0).
+
+    With P = p_x + i p_y the momentum obeys P' = lam P, lam = -i c, c = KAPPA q bz / p0.
+    One RK4 step of a linear ODE multiplies P by T(z) = 1 + z + z^2/2 + z^3/6 + z^4/24
+    (z = lam h) and adds (h/p0) P (1 + z/2 + z^2/6 + z^3/24) to X = x + i y, so that
+    X_n = X_0 + P_0 (T^n - 1) / (lam p0); z moves by h p_z / p0 per step.
+    Evaluated in long double.
+    """
+    x0, y0, z0, px, py, pz = (LD(v) for v in seed)
+    p0 = np.sqrt(px * px + py * py + pz * pz)
+    n = np.arange(K + 1)
+    P0 = np.clongdouble(px) + np.clongdouble(1j) * np.clongdouble(py)
+    X0 = np.clongdouble(x0) + np.clongdouble(1j) * np.clongdouble(y0)
+    c = LD(KAPPA) * LD(charge) * LD(bz) / p0
+    if c == 0:
+        X = X0 + P0 * (LD(h) / p0) * n.astype(LD)
+    else:
+        lam = np.clongdouble(-1j) * np.clongdouble(c)
+        zz = lam * np.clongdouble(h)
+        T = 1 + zz + zz * zz / 2 + zz ** 3 / 6 + zz ** 4 / 24
+        Tn = np.array([T ** int(k) for k in n], dtype=np.clongdouble)
+        X = X0 + P0 * (Tn - 1) / (lam * np.clongdouble(p0))
+    z = z0 + n.astype(LD) * LD(h) * pz / p0
+    return np.stack([X.real, X.imag, z], axis=1)
+
+
+def pin_rk4_closed_form(o):
+    cases = [
+        ((164.7, -472.1, 348.9, 85.06, -16.27, 50.0), 1.0, -1.0, 2.0, 1000),
+        ((-405.1, 293.0, -553.0, -100.55, -19.77, 17.73), 1.0, -1.0, 2.0, 600),
+        ((10.0, 20.0, -30.0, 40.0, 55.0, -25.0), 1.3, 1.0, 1.5, 700),
+        ((0.0, -99.0, 0.0, 0.0, 1.0, 0.3), 0.0, -1.0, 3.0, 40),
+    ]
+    for seed, bz, q, h, K in cases:
+        got = o.track(seed, bz, q, h, K)
+        want = rk4_closed_form(seed, bz, q, h, K)
+        err = np.max(np.abs(got.astype(LD) - want))
+        assert err < 1e-9, ("RK4 vs closed form", seed, float(err))
+
+
+def pin_rk4_helix(o):
+    """RK4 tracks the analytic helix (Lorentz force) to ~n y^5 R / 120 (y = c h)."""
+    for seed, q, h, K in [
+        ((164.74335769, -472.08010559, 348.90822619, 85.05979043, -16.27366127, 50.0), -1.0, 2.0, 1000),
+        ((300.0, 400.0, 0.0, -60.0, 80.0, 10.0), 1.0, 2.0, 1000),
+    ]:
+        got = o.track(seed, 1.0, q, h, K)
+        s = h * np.arange(K + 1)
+        want = synth.helix_state(seed, q, 1.0, s)[:, :3]
+        err = np.max(np.linalg.norm(got - want, axis=1))
+        assert err < 1e-6, ("RK4 vs helix", seed, err)
+
+
+# ------------------------------------------------------------------ geometry
+def _line_dist2_ld(p, a, b):
+    """Squared distance of points p [..., 3] to the line through a and b, long double."""
+    p, a, b = (np.asarray(v, dtype=LD) for v in (p, a, b))
+    n = (b - a) / np.sqrt(np.sum((b - a) ** 2))
+    cr = np.cross(p - a, n)
+    return np.sum(cr * cr, axis=-1)
+
+
+def _random_wires(rng, n):
+    ends = []
+    for _ in range(n):
+        a = rng.uniform(-800, 800, 3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        ends.append(np.concatenate([a, a + rng.uniform(100, 1600) * d]))
+    ends.append([5.0, 0.0, -750.0, 5.0, 0.0, 750.0])      # +z exactly
+    ends.append([5.0, 0.0, 750.0, 5.0, 0.0, -750.0])      # -z exactly
+    ends.append([0.0, -300.0, 2.0, 0.0, 300.0, 2.0])      # transverse
+    return np.array(ends)
+
+
+def pin_frame(o):
+    rng = np.random.default_rng(7)
+    wires = np.concatenate([_random_wires(rng, 40), synth.chamber_wires()[::97]])
+    for e in wires:
+        f = o.wire_frame(e)
+        e1, e2 = f[0:3], f[4:7]
+        n = (e[3:] - e[:3]) / np.linalg.norm(e[3:] - e[:3])
+        assert abs(e1 @ e1 - 1) < 1e-14 and abs(e2 @ e2 - 1) < 1e-14, ("frame norm", e)
+        assert abs(e1 @ e2) < 1e-14 and abs(e1 @ n) < 1e-14 and abs(e2 @ n) < 1e-14, ("frame orth", e)
+        # distance of random points via a degenerate one-point "track" (both points equal)
+        for p in rng.uniform(-900, 900, (6, 3)):
+            d2, k = o.dca2(np.stack([p, p]), f)
+            want = _line_dist2_ld(p, e[:3], e[3:])
+            assert abs(np.sqrt(LD(d2)) - np.sqrt(want)) < 1e-10, ("projected distance", e, p)
+
+
+def _z_wire(x, y=0.0):
+    return np.array([x, y, -750.0, x, y, 750.0])
+
+
+def pin_dca_hand(o):
+    f5 = o.wire_frame(_z_wire(5.0))
+    # chord crossing the foot of the perpendicular: D^2 = 25; equal vertices -> first index
+    d2, k = o.dca2(np.array([[0.0, -1.0, 0.0], [0.0, 1.0, 0.0]]), f5)
+    assert abs(d2 - 25.0) < 1e-12 and k == 0, ("interior chord", d2, k)
+    # chord ending before the foot: clamps to the end vertex, 1 + 25
+    d2, k = o.dca2(np.array([[0.0, -3.0, 0.0], [0.0, -1.0, 0.0]]), f5)
+    assert abs(d2 - 26.0) < 1e-12 and k == 1, ("clamped chord", d2, k)
+    # chord parallel to the wire: constant distance
+    d2, k = o.dca2(np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.0]]), f5)
+    assert abs(d2 - 25.0) < 1e-12 and k == 0, ("parallel chord", d2, k)
+    # minimum inside the chord BEFORE the closest vertex
+    d2, k = o.dca2(np.array([[0.0, -2.0, 0.0], [0.0, 1.0, 0.0], [0.0, 4.0, 0.0]]), f5)
+    assert abs(d2 - 25.0) < 1e-12 and k == 1, ("previous chord", d2, k)
+    # minimum inside the chord AFTER the closest vertex
+    d2, k = o.dca2(np.array([[0.0, -4.0, 0.0], [0.0, -1.0, 0.0], [0.0, 2.0, 0.0]]), f5)
+    assert abs(d2 - 25.0) < 1e-12 and k == 1, ("next chord", d2, k)
+    # equal closest vertices far apart: the first one wins
+    d2, k = o.dca2(np.array([[0.0, -1.0, 0.0], [0.0, 9.0, 3.0], [0.0, 1.0, 0.0]]), f5)
+    assert k == 0, ("first closest vertex", k)
+    # skew lines: interior chord distance = |(a - A) . (u x w)| / |u x w|
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        A = rng.uniform(-50, 50, 3)
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        f = o.wire_frame(np.concatenate([A, A + 400 * w]))
+        # a short chord that straddles the common perpendicular
+        u = rng.normal(size=3)
+        u -= (u @ w) * w
+        u /= np.linalg.norm(u)
+        v = np.cross(w, u)
+        foot = A + rng.uniform(-100, 100) * w + rng.uniform(0.5, 8.0) * v
+        a = foot - rng.uniform(0.2, 1.8) * u
+        b = a + 2.0 * u
+        d2, _ = o.dca2(np.stack([a, b]), f)
+        au, bu, Aw = (np.asarray(t, dtype=LD) for t in (a, b - a, A))
+        cr = np.cross(bu, np.asarray(w, dtype=LD))
+        want = abs(np.sum((au - Aw) * cr)) / np.sqrt(np.sum(cr * cr))
+        assert abs(np.sqrt(LD(d2)) - want) < 1e-10, ("skew lines", float(want), d2)
+
+
+def pin_residual(o):
+    lam = 0.8
+    pts = np.stack([np.zeros(21), np.arange(-30.0, 31.0, 3.0), np.zeros(21)], axis=1)
+    ends = np.stack([_z_wire(5.0), _z_wire(100.0), _z_wire(-5.0), _z_wire(-5.0)])
+    # wire 0: hits 4.5 and 5.25 -> 0.25; wire 1: far -> lambda; wire 2: no hits -> lambda;
+    # wire 3: a hit with |e| = 2 > lambda -> lambda
+    offsets = np.array([0, 2, 3, 3, 4], dtype=np.int32)
+    drift = np.array([4.5, 5.25, 1.0, 7.0])
+    got = o.rss_track(pts, ends, offsets, drift, lam)
+    want = 0.0
+    for d in (0.25, lam, lam, lam):
+        want = want + d * d
+    assert got == want, ("Eq. 1 hand case", got, want)
+
+
+def pin_far_seed(o, ev, lam=0.8):
+    """A track far from every wire gives RSS = N lambda^2 exactly (sequential sum)."""
+    seed = np.array([0.0, 0.0, 6000.0, 10.0, 0.0, 100.0])
+    pts = o.track(seed, 1.0, -1.0, 2.0, 400)
+    got = o.rss_track(pts, ev.wire_ends, ev.wire_offsets, ev.drift, lam)
+    want = 0.0
+    for _ in range(ev.n_wires):
+        want = want + lam * lam
+    assert got == want, ("far seed", got, want)
+    rss, _ = o.scan(seed[:, None], [1.0, -1.0, 2.0, lam], 400, ev.wire_ends, ev.wire_offsets,
+                    ev.drift)
+    assert rss[0] == want, ("far seed via scan", rss[0], want)
+
+
+def pin_classify(o):
+    """Straight track (bz = 0) along +y at x = 0, steps of exactly 3 mm: D = |x_wire|."""
+    seed = np.array([0.0, -99.0, 0.0, 0.0, 1.0, 0.0])
+    cfg = [0.0, -1.0, 3.0, 1.0]
+    ends = np.stack([_z_wire(5.0), _z_wire(-5.0), _z_wire(7.0), _z_wire(50.0)])
+    offsets = np.array([0, 1, 3, 5, 6], dtype=np.int32)
+    drift = np.array([4.0,        # |e| = 1 = lambda: not classified, borderline
+                      3.0, 5.5,   # closest is 5.5 (|e| = 0.5): classified
+                      6.5, 7.5,   # tie at 0.5: the lower index wins
+                      2.0])       # far: not classified
+    mask, dca, nb = o.classify(seed, cfg, 66, ends, offsets, drift)
+    assert list(dca) == [5.0, 5.0, 7.0, 50.0], ("classify DCA", dca)
+    assert list(mask) == [2, 0, 1, 1, 0, 0], ("classify mask", mask)
+    assert nb == 1, ("borderline count", nb)
+
+
+def pin_argmin(o):
+    assert o.argmin(np.array([3.0, 1.0, 1.0, 2.0])) == 1
+    assert o.argmin(np.array([np.nan, 2.0, 2.0])) == 1
+    assert o.argmin(np.array([np.nan, np.nan])) == -1
+    assert o.argmin(np.array([np.inf, np.inf])) == 0
+    assert o.argmin(np.array([5.0, 4.0, 3.0, 2.0, 1.0, 1.0])) == 4
+
+
+# ------------------------------------------------------------------ seed grid
+def pin_grid(o):
+    ref = np.array([164.74, -472.08, 348.9, 85.06, -16.27, 50.0])
+    grid = np.concatenate([ref, [1.0, 101.0, 0.01, -0.02], [5.0, 5.0, 0.05, 0.05]])
+    n = np.array([3, 4, 5, 2], dtype=np.int32)
+    seeds = o.seed_grid(grid, n)
+    assert seeds.shape == (6, 120)
+    r0 = np.hypot(ref[0], ref[1])
+    th0 = np.arccos(ref[5] / np.linalg.norm(ref[3:]))
+    ph0 = np.arctan2(ref[4], ref[3])
+    pos0 = np.arctan2(ref[1], ref[0])
+    for s in range(120):
+        i = np.unravel_index(s, tuple(n))       # row-major: the last axis runs fastest
+        v = [grid[6 + a] + grid[10 + a] * (2 * i[a] - (n[a] - 1)) / (n[a] - 1) for a in range(4)]
+        st = seeds[:, s]
+        assert abs(np.hypot(st[0], st[1]) - r0) < 1e-10, ("seed radius", s)
+        assert st[2] == ref[2], ("seed z", s)
+        dpos = np.angle(np.exp(1j * (np.arctan2(st[1], st[0]) - pos0)))
+        assert abs(dpos - 2 * np.arctan(v[0] / (2 * r0))) < 1e-12, ("arc offset", s)
+        p = np.linalg.norm(st[3:])
+        assert abs(p - v[1]) < 1e-12, ("|p|", s)
+        assert abs(np.arccos(st[5] / p) - th0 - 2 * np.arctan(v[2] / 2)) < 1e-10, ("polar", s)
+        dph = np.angle(np.exp(1j * (np.arctan2(st[4], st[3]) - ph0)))
+        assert abs(dph - 2 * np.arctan(v[3] / 2)) < 1e-12, ("azimuth", s)
+    # a one-point axis sits at its centre
+    g1 = grid.copy()
+    seeds1 = o.seed_grid(g1, np.array([1, 1, 1, 1], dtype=np.int32))
+    assert abs(np.linalg.norm(seeds1[3:, 0]) - 101.0) < 1e-12
+
+
+def pin_refine(o):
+    ref = np.array([164.74, -472.08, 348.9, 85.06, -16.27, 50.0])
+    grid = np.concatenate([ref, [0.0, 100.0, 0.0, 0.0], [5.0, 5.0, 0.05, 0.05]])
+    n = np.array([5, 3, 1, 7], dtype=np.int32)
+    seeds = o.seed_grid(grid, n)
+    best = 3 * 21 + 2 * 7 + 5                    # indices (3, 2, 0, 5)
+    g2 = o.refine_grid(grid, n, best)
+    idx = (3, 2, 0, 5)
+    for a in range(4):
+        if n[a] > 1:
+            want_c = grid[6 + a] + grid[10 + a] * (2 * idx[a] - (n[a] - 1)) / (n[a] - 1)
+            assert abs(g2[6 + a] - want_c) < 1e-15 * max(1.0, abs(want_c)), ("centre", a)
+            assert abs(g2[10 + a] - 2 * grid[10 + a] / (n[a] - 1)) < 1e-15 * grid[10 + a] * 4
+        else:
+            assert g2[6 + a] == grid[6 + a] and g2[10 + a] == grid[10 + a]
+    # the centre of the refined grid (odd n) is the chosen seed itself
+    centre = ((n[0] // 2) * n[1] + n[1] // 2) * n[2] * n[3] + (n[2] // 2) * n[3] + n[3] // 2
+    assert np.array_equal(o.seed_grid(g2, n)[:, centre], seeds[:, best]), "refined centre seed"
+
+
+# ------------------------------------------------------------------ event-level
+def pin_truth_seed(o, ev_exact, lam=1.0, h=2.0, K=1000):
+    """sigma = 0: the truth seed's residuals are only the chord error, <= h^2 / (8 R)."""
+    ref = ev_exact.ref_states[0]
+    R = np.hypot(ref[3], ref[4]) / (KAPPA * ev_exact.bz)
+    bound = h * h / (8 * R) + 1e-6
+    pts = o.track(ref, ev_exact.bz, ev_exact.charge, h, K)
+    rss = o.rss_track(pts, ev_exact.wire_ends, ev_exact.wire_offsets, ev_exact.drift, lam)
+    assert rss <= ev_exact.n_wires * bound ** 2, ("truth RSS", rss, ev_exact.n_wires * bound ** 2)
+    mask, dca, _ = o.classify(ref, [ev_exact.bz, ev_exact.charge, h, lam], K, ev_exact.wire_ends,
+                              ev_exact.wire_offsets, ev_exact.drift)
+    assert np.all(mask[ev_exact.hit_turn >= 0] & 1), "truth seed classifies every signal hit"
+
+
+def pin_grid_argmin(o, ev_exact, lam=1.0):
+    """sigma = 0, odd grid centred on the truth: the centre seed is the argmin."""
+    cfg = synth.ScanConfig("t", (5, 5, 5, 5), (2.0, 2.0, 0.02, 0.02), 1000, 2.0, lam)
+    grid = synth.grid_descriptor(ev_exact.ref_states[0], cfg)
+    n = np.array(cfg.n, dtype=np.int32)
+    rss, _ = o.scan(o.seed_grid(grid, n), [ev_exact.bz, ev_exact.charge, 2.0, lam], 1000,
+                    ev_exact.wire_ends, ev_exact.wire_offsets, ev_exact.drift)
+    assert o.argmin(rss) == 312, ("grid argmin", o.argmin(rss))
+
+
+def pin_rotation(o, ev, lam=1.0):
+    """Rotating wires and seed about the field axis leaves the RSS unchanged."""
+    a = 0.7
+    R = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1]])
+    ends = ev.wire_ends.reshape(-1, 2, 3) @ R.T
+    ends = ends.reshape(-1, 6)
+    grid = synth.grid_descriptor(ev.ref_states[0], synth.C0)
+    seeds = o.seed_grid(grid, np.array([2, 2, 2, 2], dtype=np.int32))
+    rot = seeds.copy()
+    rot[0:3] = R @ seeds[0:3]
+    rot[3:6] = R @ seeds[3:6]
+    cfg = [ev.bz, ev.charge, 2.0, lam]
+    r1, _ = o.scan(seeds, cfg, 1000, ev.wire_ends, ev.wire_offsets, ev.drift)
+    r2, _ = o.scan(rot, cfg, 1000, ends, ev.wire_offsets, ev.drift)
+    assert np.max(np.abs(r1 - r2) / r1) < 1e-10, ("rotation invariance", r1, r2)
+
+
+def _brute_rss(pts, ends, offsets, drift, lam):
+    """Independent long-double RSS: plain 3-D point/chord-to-line distances.
+
+    Returns (rss, D_local [n_w], D_global [n_w]): D_local refines from the closest
+    recorded point over its two chords, D_global is the minimum over every chord.
+    """
+    P = np.asarray(pts, dtype=LD)
+    n_w = ends.shape[0]
+    Dl = np.empty(n_w, dtype=LD)
+    Dg = np.empty(n_w, dtype=LD)
+    for i in range(n_w):
+        A = np.asarray(ends[i, :3], dtype=LD)
+        w = np.asarray(ends[i, 3:], dtype=LD) - A
+        w = w / np.sqrt(np.sum(w * w))
+        a = P - A
+        aperp = a - (a @ w)[:, None] * w
+        q = np.sum(aperp * aperp, axis=1)
+        u = aperp[1:] - aperp[:-1]
+        den = np.sum(u * u, axis=1)
+        g = np.sum(aperp[:-1] * u, axis=1)
+        t = np.where(den > 0, np.clip(-g / np.where(den > 0, den, 1), 0, 1), 0)
+        c = aperp[:-1] + t[:, None] * u
+        seg = np.sum(c * c, axis=1)
+        k = int(np.argmin(q))
+        cand = [q[k]]
+        if k > 0:
+            cand.append(seg[k - 1])
+        if k < len(q) - 1:
+            cand.append(seg[k])
+        Dl[i] = np.sqrt(min(cand))
+        Dg[i] = np.sqrt(seg.min())
+    rss = LD(0)
+    for i in range(n_w):
+        d = LD(lam)
+        for j in range(offsets[i], offsets[i + 1]):
+            d = min(d, abs(Dl[i] - LD(drift[j])))
+        rss += d * d
+    return rss, Dl, Dg
+
+
+def pin_brute_force(o, ev, lam=1.0, K=1000, h=2.0):
+    """3^4 grid: every RSS against the long-double recomputation; same argmin and hit set."""
+    cfg = synth.ScanConfig("t", (3, 3, 3, 3), (5.0, 5.0, 0.05, 0.05), K, h, lam)
+    grid = synth.grid_descriptor(ev.ref_states[0], cfg)
+    n = np.array(cfg.n, dtype=np.int32)
+    seeds = o.seed_grid(grid, n)
+    rss, _ = o.scan(seeds, [ev.bz, ev.charge, h, lam], K, ev.wire_ends, ev.wire_offsets, ev.drift)
+    want = np.empty(seeds.shape[1], dtype=LD)
+    for s in range(seeds.shape[1]):
+        pts = o.track(seeds[:, s], ev.bz, ev.charge, h, K)
+        want[s], Dl, Dg = _brute_rss(pts, ev.wire_ends, ev.wire_offsets, ev.drift, lam)
+        near = Dl < 9.0
+        assert np.all(np.abs(Dl[near] - Dg[near]) < 1e-9), ("local vs global chord minimum", s)
+    rel = np.abs(rss.astype(LD) - want) / want
+    assert np.max(rel) < 1e-12, ("brute-force RSS", float(np.max(rel)))
+    b = o.argmin(rss)
+    assert b == int(np.argmin(want)), ("brute-force argmin", b, int(np.argmin(want)))
+    # classification of the best seed against the long-double D
+    mask, dca, _ = o.classify(seeds[:, b], [ev.bz, ev.charge, h, lam], K, ev.wire_ends,
+                              ev.wire_offsets, ev.drift)
+    _, Dl, _ = _brute_rss(o.track(seeds[:, b], ev.bz, ev.charge, h, K), ev.wire_ends,
+                          ev.wire_offsets, ev.drift, lam)
+    assert np.max(np.abs(dca.astype(LD) - Dl)) < 1e-10, "classify DCA vs long double"
+    for i in range(ev.n_wires):
+        j0, j1 = ev.wire_offsets[i], ev.wire_offsets[i + 1]
+        e = np.abs(Dl[i] - ev.drift[j0:j1].astype(LD))
+        jb = int(np.argmin(e))
+        want_m = np.zeros(j1 - j0, dtype=np.uint8)
+        want_m[jb] = 1 if e[jb] < lam else 0
+        assert np.array_equal(mask[j0:j1] & 1, want_m), ("hit set", i)
+
+
+ALL_SIMPLE = [pin_rk4_closed_form, pin_rk4_helix, pin_frame, pin_dca_hand, pin_residual,
+              pin_classify, pin_argmin, pin_grid, pin_refine]
+ALL_EVENT = [pin_far_seed, pin_truth_seed, pin_grid_argmin, pin_rotation, pin_brute_force]

@@ -1,0 +1,82 @@
+"""Planted mistakes in the CPU reference must each fail at least one pin.
+
+Each case copies oracle/oracle.c, applies one plausible slip (a dropped term, a
+wrong sign, index or operand, an off-by-one tie rule), builds it with gcc on the
+CPU and runs the pins against it. A mutant that passes every pin would mean the
+pins cannot tell that slip from the real thing.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from paper_1911_09340_amd import synth
+
+MUTANTS = {
+    "rk4_drop_factor2": ("x = x + h6 * (((v1x + 2.0 * v2x)", "x = x + h6 * (((v1x + v2x)"),
+    "rk4_full_half_step": ("double hh = 0.5 * h;", "double hh = h;"),
+    "rk4_force_sign": ("double f1x = c * py, f1y = -(c * px);", "double f1x = c * py, f1y = (c * px);"),
+    "rk4_stage4_uses_f2": ("qx = px + h * f3x;", "qx = px + h * f2x;"),
+    "rk4_h6": ("double h6 = h / 6.0;", "double h6 = h / 5.0;"),
+    "grid_half_angle_sin": ("*s = (2.0 * tau) / den;", "*s = (tau) / den;"),
+    "grid_py_uses_cp": ("out[4] = v1 * (st * sp);", "out[4] = v1 * (st * cp);"),
+    "grid_axis_order": ("int32_t i3 = (int32_t)(index % n[3]);", "int32_t i3 = (int32_t)(index % n[2]);"),
+    "grid_soa_transposed": ("seeds[c * S + s] = st[c];", "seeds[s * 6 + c] = st[c];"),
+    "refine_keeps_span": ("grid[10 + a] = (2.0 * grid[10 + a]) / (double)(n[a] - 1);", "grid[10 + a] = grid[10 + a];"),
+    "frame_e2z_sign": ("double e2x = b, e2y = s + (ny * ny) * a, e2z = -ny;", "double e2x = b, e2y = s + (ny * ny) * a, e2z = ny;"),
+    "frame_offset_sign": ("frame[3] = -((e1x * ax + e1y * ay) + e1z * az);", "frame[3] = ((e1x * ax + e1y * ay) + e1z * az);"),
+    "project_index": ("*xi = fma(f[0], p[0], fma(f[1], p[1], fma(f[2], p[2], f[3])));", "*xi = fma(f[0], p[0], fma(f[1], p[2], fma(f[2], p[1], f[3])));"),
+    "closest_last_index": ("        if (q < qb) {\n            qb = q;\n            kb = k;", "        if (q <= qb) {\n            qb = q;\n            kb = k;"),
+    "chord_t_sign": ("double t = -g / den;", "double t = g / den;"),
+    "chord_wrong_base_point": ("double pxi = fma(t, uxi, axi), peta = fma(t, ueta, aeta);", "double pxi = fma(t, uxi, bxi), peta = fma(t, ueta, aeta);"),
+    "chord_den_missing_term": ("double den = fma(uxi, uxi, ueta * ueta);", "double den = uxi * uxi;"),
+    "drop_previous_chord": ("    if (kb > 0) {", "    if (0) {"),
+    "drop_next_chord": ("    if (kb < P - 1) {", "    if (0) {"),
+    "residual_uncapped": ("    double d = lambda;\n    for (int32_t j = j0;", "    double d = INFINITY;\n    for (int32_t j = j0;"),
+    "residual_signed": ("double e = fabs(D - drift[j]);\n        if (e < d)", "double e = (D - drift[j]);\n        if (e < d)"),
+    "rss_not_squared": ("rss = rss + d * d;", "rss = rss + d;"),
+    "classify_not_strict": ("if (eb < cfg[3])", "if (eb <= cfg[3])"),
+    "classify_last_tie": ("            if (e < eb) {\n                eb = e;", "            if (e <= eb) {\n                eb = e;"),
+    "argmin_last_tie": ("if (rss[s] < v || (b < 0 && rss[s] == v)) {", "if (rss[s] <= v) {"),
+    "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
+}
+
+
+def _run_all_pins(o, ev, ev_exact):
+    failed = []
+    for check in pins.ALL_SIMPLE:
+        try:
+            check(o)
+        except AssertionError:
+            failed.append(check.__name__)
+    for check, e in [(pins.pin_far_seed, ev), (pins.pin_truth_seed, ev_exact),
+                     (pins.pin_grid_argmin, ev_exact), (pins.pin_rotation, ev),
+                     (pins.pin_brute_force, ev)]:
+        try:
+            check(o, e)
+        except AssertionError:
+            failed.append(check.__name__)
+    return failed
+
+
+@pytest.fixture(scope="module")
+def events():
+    return synth.event_plain(0), synth.event_plain(0, sigma=0.0)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, events):
+    old, new = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, "mutation anchor not found exactly once: %s" % name
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "mutant.c")
+        with open(path, "w") as f:
+            f.write(src.replace(old, new))
+        lib = oracle.load(oracle.build(src=path, out=os.path.join(d, "libmutant.so")))
+        with np.errstate(all="ignore"):
+            failed = _run_all_pins(oracle.Oracle(lib), *events)
+    assert failed, "planted mistake %s passed every pin" % name
