@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of the seed-scan path on one MI355X.
+
+Workload (one "step"): the signal-like three-turn event (227 hits on 172 wires,
+10 % noise), and for each of its three turn partitions the whole path of the paper's
+Sec. 2.1: a 16^4 seed grid (65 536 seeds) -> RK4 track recording, 1500 x 2 mm ->
+DCA and Eq. 1 RSS (lambda = 0.8 mm) -> argmin, then two finer re-scans around the
+best seed, then hit classification. Inputs are synthetic and already resident in
+device memory when the timed region starts.
+
+Prints one JSON line. `value` = seed x hit DCA evaluations per second (sum over
+scans of seeds x hits, divided by wall time of the timed steps). `roofline` covers
+the dominant kernel (the DCA scan): algorithmic FP64 flops per launch / its average
+device time from HIP events recorded on its stream. `cpu_baseline` times the CPU
+reference (oracle/) on a bounded sample of the same workload on the host cores.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py --sweep             # time every DCA kernel shape
+  python bench.py --calibrate-copy    # a plain 1 GiB device copy, for counter scaling
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, dense
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+FLOP_PER_POINT_WIRE = 15  # 6 FMA (in-plane coordinates) + 1 MUL + 1 FMA (squared distance)
+METRIC = ("seed×hit DCA evals/s and events/s (FP64 % peak); "
+          "grad-refine vs fine-grid time")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dca_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1911_09340_amd", "csrc", "comet.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per DCA launch from the committed counter runs, if still current."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def calibrate_copy():
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
+def cpu_baseline(ev, sc, target_s: float):
+    """The CPU reference on a bounded sample of partition 0's first grid."""
+    import numpy as np
+    import oracle
+    from paper_1911_09340_amd import synth
+    o = oracle.Oracle()
+    grid = synth.grid_descriptor(ev.ref_states[0], sc)
+    n = np.array(sc.n, dtype=np.int32)
+    cfg = [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+    all_seeds = o.seed_grid(grid, n)
+    t0 = time.perf_counter()
+    _, used = o.scan(all_seeds[:, :512], cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+    per_seed = (time.perf_counter() - t0) / 512
+    m = int(min(sc.n_seeds, max(64, target_s / max(per_seed, 1e-9))))
+    idx = np.linspace(0, sc.n_seeds - 1, m).astype(np.int64)
+    seeds = np.ascontiguousarray(all_seeds[:, idx])
+    t0 = time.perf_counter()
+    _, used = o.scan(seeds, cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+    dt = time.perf_counter() - t0
+    return {"value": m * ev.n_hits / dt, "unit": "seed×hit DCA evals/s", "cores": int(used),
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": "%d of the 65536 seeds of turn partition 0's 16^4 grid (evenly spaced "
+                      "indices), 1500 x 2 mm RK4, %d hits on %d wires, one scan" %
+                      (m, ev.n_hits, ev.n_wires)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variant", type=int, default=None, help="DCA kernel shape id")
+    ap.add_argument("--sweep", action="store_true", help="time every DCA kernel shape")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+              "(--gpus 1); multi-GPU sharding is described in DESIGN.md, not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_09340_amd import comet, scan, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    comet.load()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    ev = synth.event_signal(0)
+    sc = synth.C1
+    cfg = scan.config_for(ev, sc)
+    dev = scan.DeviceEvent.from_event(ev)
+    grids = [scan.grid_tensor(ev.ref_states[t], sc) for t in range(ev.n_turns)]
+    runners = [scan.PartitionScanner(sc.n, cfg, ev.n_wires, ev.n_hits) for _ in range(ev.n_turns)]
+    scans_per_step = ev.n_turns * (sc.n_refine + 1)
+    evals_per_step = scans_per_step * sc.n_seeds * ev.n_hits
+    P = sc.n_steps + 1
+
+    def step():
+        for t in range(ev.n_turns):
+            runners[t].run(dev, grids[t], sc.n_refine)
+
+    def timed(steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        comet.profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return t1 - t0, comet.profile_end()
+
+    variants = comet.dca_variants()
+    if args.sweep:
+        for i, v in enumerate(variants):
+            comet.set_dca_variant(i)
+            dt, prof = timed(max(2, args.steps // 2), 1)
+            ms, n = prof["dca"]
+            tfl = FLOP_PER_POINT_WIRE * sc.n_seeds * ev.n_wires * P / (ms / n * 1e-3) / 1e12
+            log("variant %d %s: %.3f ms/step, dca %.3f ms/launch, %.1f TFLOP/s (%.1f %% of FP64 peak)"
+                % (i, v, dt / max(2, args.steps // 2) * 1e3, ms / n, tfl, 100 * tfl / PEAK_FP64_TFLOPS))
+    variant = 0 if args.variant is None else args.variant
+    comet.set_dca_variant(variant)
+
+    log("warmup %d, timing %d steps (%d scans of %d seeds x %d hits each) ..."
+        % (args.warmup, args.steps, scans_per_step, sc.n_seeds, ev.n_hits))
+    dt, prof = timed(args.steps, args.warmup)
+    log("timed region %.3f s" % dt)
+    ms_dca, n_dca = prof["dca"]
+    dca_s = ms_dca / n_dca * 1e-3
+    flops = FLOP_PER_POINT_WIRE * sc.n_seeds * ev.n_wires * P
+    achieved = flops / dca_s / 1e12
+    ms_trk, n_trk = prof["track"]
+    trk_bytes = 8 * 3 * P * sc.n_seeds + 8 * 6 * sc.n_seeds
+    traffic = stored_traffic()
+
+    out = {
+        "metric": METRIC,
+        "value": evals_per_step * args.steps / dt,
+        "unit": "seed×hit DCA evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "signal-like e- event, 104 MeV/c, 3 turn partitions; per partition a "
+                        "16^4 seed grid (65536 seeds) + 2 finer re-scans + classification; "
+                        "RK4 1500 x 2 mm, 1 T; %d hits on %d wires (10%% noise); lambda 0.8 mm"
+                        % (ev.n_hits, ev.n_wires),
+            "seeds_per_scan": sc.n_seeds,
+            "scans_per_step": scans_per_step,
+            "hits": ev.n_hits,
+            "wires": ev.n_wires,
+            "rk4_steps": sc.n_steps,
+            "dca_kernel_shape": variants[variant],
+        },
+        "events_per_s": args.steps / dt,
+        "roofline": {
+            "kernel": "dca_kernel",
+            "bound": "fp64-valu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": traffic,
+            "avg_launch_ms": dca_s * 1e3,
+            "launches": n_dca,
+            "flop_per_launch": flops,
+            "flop_unit": "%d FP64 flop per (seed, wire, track point)" % FLOP_PER_POINT_WIRE,
+        },
+        "track_recording": {
+            "kernel": "rk4_record_kernel",
+            "bound": "hbm",
+            "achieved": trk_bytes / (ms_trk / n_trk * 1e-3) / 1e9,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": trk_bytes / (ms_trk / n_trk * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "avg_launch_ms": ms_trk / n_trk,
+        },
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("CPU reference baseline (~%.0f s) ..." % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(ev, sc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

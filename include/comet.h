@@ -1,0 +1,176 @@
+/*
+ * comet.h -- C ABI of the MI355X (gfx950) seed-scan library.
+ *
+ * The operations are those of Yeo, Lee and Kuno, "GPU-accelerated event
+ * reconstruction for the COMET Phase-I experiment" (arXiv:1911.09340): seeds on a
+ * grid over prior ranges (Sec. 2.1, Sec. 3.1) are extrapolated into recorded tracks
+ * (Sec. 2.2.1, Alg. 1); every wire's distance of closest approach to each track
+ * (Sec. 2.2.2, Alg. 2) gives the residual sum of squares of Eq. 1; the lowest-RSS
+ * seed is chosen, re-scanned on a finer grid around it, and the hits whose residual
+ * is below the cutoff are classified to it (Sec. 2.1).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers (memory of the current HIP device) unless
+ *     marked "host". The caller owns all memory; the library never allocates,
+ *     frees or synchronises in these calls.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Calls
+ *     are asynchronous on it; a fault inside a kernel surfaces at the caller's
+ *     next synchronisation, not in the return code.
+ *   - Return 0 (COMET_OK) or a negative status; comet_status_string() explains it,
+ *     comet_last_error() gives details of the last failure on the calling thread.
+ *     Argument checks cover what is visible on the host (NULL pointers, sizes,
+ *     configuration values); the contents of device arrays are not inspected.
+ *   - Units: mm, MeV/c, tesla, charge in units of e.
+ *   - Floating point is IEEE binary64 throughout, evaluated in a fixed order
+ *     without contraction, so results are deterministic run to run.
+ *   - Only gfx950 devices are supported (COMET_EUNSUPPORTED otherwise).
+ */
+#ifndef COMET_H
+#define COMET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum comet_status {
+    COMET_OK = 0,
+    COMET_EINVAL = -1,      /* invalid argument (NULL pointer, bad size or value) */
+    COMET_EWORKSPACE = -2,  /* workspace NULL or smaller than required */
+    COMET_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+    COMET_EUNSUPPORTED = -4 /* current device is not gfx950, or an unsupported option */
+};
+
+/* Host struct. Track stepping and Eq. 1 settings.
+ *   bz_tesla  uniform axial field B_z (finite)
+ *   charge_e  particle charge in e (finite; electron = -1)
+ *   step_mm   RK4 path-length step h (> 0, finite)
+ *   n_steps   K >= 1; a recorded track has K + 1 points
+ *   lambda_mm cutoff lambda of Eq. 1 and of the classification (> 0, finite) */
+typedef struct comet_config {
+    double bz_tesla;
+    double charge_e;
+    double step_mm;
+    int32_t n_steps;
+    int32_t reserved; /* must be 0 */
+    double lambda_mm;
+} comet_config;
+
+/* Seed grid (Sec. 2.1: a grid search over the prior range of each seed component;
+ * Sec. 3.1: the seed set combines the grids of the components).
+ *   grid   device double[14]: reference state (x, y, z, px, py, pz), axis centres
+ *          (arc offset along the circle of the reference radius [mm], |p| [MeV/c],
+ *          polar-angle offset [rad], azimuth offset [rad]), axis half-spans (same units)
+ *   n      host int32[4]: points per axis (each >= 1); axis 3 runs fastest
+ *   seeds6 device double[6][n_seeds] (SoA: x, y, z, px, py, pz), written
+ *   n_seeds must equal n[0] n[1] n[2] n[3]
+ * Axis value i is centre + half (2i - (n-1)) / (n-1) (the centre when n = 1); an
+ * offset v rotates by 2 atan(tau) with tau = v / (2 r0) for the arc offset (r0 =
+ * transverse radius of the reference point) and tau = v / 2 for the angles.
+ * The reference momentum must have a non-zero transverse part. */
+int comet_seed_grid(const double *grid, const int32_t n[4], double *seeds6, int64_t n_seeds,
+                    void *stream);
+
+/* Finer re-scan around the chosen seed (Sec. 2.1): for each axis with n > 1 the
+ * centre moves to the value at the chosen seed's index and the half-span becomes
+ * one spacing of the previous grid, 2 half / (n - 1).
+ *   grid  device double[14], updated in place
+ *   n     host int32[4], the grid's points per axis
+ *   best  device int64[1]: chosen seed index of the current grid (< 0: no change) */
+int comet_refine_grid(double *grid, const int32_t n[4], const int64_t *best, void *stream);
+
+/* Track recording (Sec. 2.2.1, Alg. 1): each seed is stepped with fixed-step
+ * classical RK4 in path length through the uniform field (|p| constant) and every
+ * position is recorded.
+ *   seeds6    device double[6][n_seeds] (SoA)
+ *   cfg       host; uses bz_tesla, charge_e, step_mm, n_steps
+ *   track_xyz device double[3][n_steps + 1][n_seeds], written: coordinate-major,
+ *             then step, then seed (consecutive seeds are adjacent in memory) */
+int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                            double *track_xyz, void *stream);
+
+/* Bytes of workspace comet_dca_rss needs for n_seeds seeds and n_wires wires. */
+size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_wires);
+
+/* Distance of closest approach and Eq. 1 (Sec. 2.1, Sec. 2.2.2, Alg. 2).
+ * For every seed and wire: the recorded point closest to the wire line (first
+ * index on ties) is refined over its two adjacent chords to the DCA D; the wire
+ * contributes d^2 with d = min(lambda, min_j |D - r_j|) over its hits j (lambda for
+ * a wire without hits); rss[s] is the sum over wires in wire order.
+ *   track_xyz    device double[3][n_points][n_seeds] from comet_extrapolate_seeds
+ *   n_points     must equal cfg->n_steps + 1
+ *   wire_ends    device double[n_wires][6]: both endpoints of each wire (the wire is
+ *                the infinite line through them; they must differ)
+ *   wire_offsets device int32[n_wires + 1]: CSR, hits of wire i are
+ *                [wire_offsets[i], wire_offsets[i+1]); wire_offsets[0] = 0,
+ *                non-decreasing, wire_offsets[n_wires] = n_hits
+ *   drift        device double[n_hits]: drift distances r_j (finite)
+ *   rss          device double[n_seeds], written
+ *   workspace    device, >= comet_dca_workspace_bytes(n_seeds, n_wires) bytes,
+ *                256-byte aligned; contents on entry are ignored */
+int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
+                  const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                  const double *drift, int32_t n_hits, const comet_config *cfg, double *rss,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* Seed selection and hit classification (Sec. 2.1).
+ * best[0] = index of the lowest rss (ties: lowest index; NaN never chosen; -1 if
+ * every value is NaN). When hit_mask is not NULL the chosen seed's track is read
+ * from track_xyz, D is recomputed for every wire, and on each wire the hit with
+ * the smallest |D - r_j| (lowest index on ties) gets bit 0 of hit_mask when that
+ * residual is below lambda (strictly) and bit 1 when it lies within 1e-9 mm of
+ * lambda (borderline); all other hits get 0.
+ *   top_k        must be 1
+ *   best         device int64[1], written
+ *   hit_mask     device uint8[n_hits] or NULL (selection only)
+ *   n_borderline device int32[1] or NULL: number of borderline hits
+ *   dca_best     device double[n_wires] or NULL: D of each wire for the chosen seed
+ * The track and wire arguments are as in comet_dca_rss (ignored when hit_mask,
+ * n_borderline and dca_best are all NULL). */
+int comet_select_classify(const double *rss, int64_t n_seeds, const double *track_xyz,
+                          int32_t n_points, const double *wire_ends, int32_t n_wires,
+                          const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                          const comet_config *cfg, int32_t top_k, int64_t *best,
+                          uint8_t *hit_mask, int32_t *n_borderline, double *dca_best,
+                          void *stream);
+
+/* ------------------------------------------------------------ diagnostics
+ * Per-kernel device time. After comet_profile_begin() every kernel launched by the
+ * calls above is bracketed by two HIP events recorded on its stream (the events are
+ * created on first use and reused afterwards; recording adds no synchronisation).
+ * comet_profile_end() waits for the recorded events, writes per kernel kind the
+ * summed duration in milliseconds and the number of launches, and stops recording.
+ * Kinds: 0 track recording, 1 DCA scan, 2 RSS sum, 3 selection and classification.
+ * Both return COMET_OK or COMET_EHIP; profiling state is process-wide. */
+#define COMET_PROFILE_KINDS 4
+int comet_profile_begin(void);
+int comet_profile_end(double ms[COMET_PROFILE_KINDS], int64_t launches[COMET_PROFILE_KINDS]);
+
+/* ------------------------------------------------------------ tuning
+ * The DCA kernel exists in several shapes: W wires per wave, NWV waves per block,
+ * C track points per LDS chunk, and whether the first closest index is tracked per
+ * point (0) or per chunk with a final rescan (1). All shapes give identical results.
+ * comet_dca_variant_info() describes shape `id` (0 <= id < comet_dca_variant_count());
+ * comet_dca_set_variant() selects the shape later comet_dca_rss calls use
+ * (process-wide; the default is 0). */
+int comet_dca_variant_count(void);
+int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
+                           int32_t *chunk_argmin);
+int comet_dca_set_variant(int id);
+
+/* Static description of a status code. */
+const char *comet_status_string(int status);
+
+/* Details of the last failure on the calling thread ("" if none). */
+const char *comet_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int comet_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COMET_H */

@@ -1,0 +1,223 @@
+"""Python binding of the C ABI in include/comet.h (argument marshalling only).
+
+Every function takes torch tensors on the current HIP device, checks their dtype,
+shape, device and contiguity, and passes raw pointers plus the current stream to
+the library; the work runs in the library's HIP kernels. There is no CPU fallback:
+importing this module on a machine without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcomet.so")
+
+OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+
+EXPORTS = ("comet_seed_grid", "comet_refine_grid", "comet_extrapolate_seeds",
+           "comet_dca_workspace_bytes", "comet_dca_rss", "comet_select_classify",
+           "comet_status_string", "comet_last_error", "comet_version")
+
+
+class CometError(RuntimeError):
+    def __init__(self, status: int, call: str, detail: str):
+        super().__init__("%s failed: %s (%d): %s" % (call, status_string(status), status, detail))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    """comet_config (host struct)."""
+    _fields_ = [("bz_tesla", ctypes.c_double), ("charge_e", ctypes.c_double),
+                ("step_mm", ctypes.c_double), ("n_steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lambda_mm", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libcomet.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    I4 = ctypes.POINTER(ctypes.c_int32)
+    lib.comet_seed_grid.argtypes = [_vp, I4, _vp, _i64, _vp]
+    lib.comet_refine_grid.argtypes = [_vp, I4, _vp, _vp]
+    lib.comet_extrapolate_seeds.argtypes = [_vp, _i64, ctypes.POINTER(Config), _vp, _vp]
+    lib.comet_dca_workspace_bytes.argtypes = [_i64, _i32]
+    lib.comet_dca_workspace_bytes.restype = ctypes.c_size_t
+    lib.comet_dca_rss.argtypes = [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _i32,
+                                  ctypes.POINTER(Config), _vp, _vp, ctypes.c_size_t, _vp]
+    lib.comet_select_classify.argtypes = [_vp, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _i32,
+                                          ctypes.POINTER(Config), _i32, _vp, _vp, _vp, _vp, _vp]
+    lib.comet_status_string.argtypes = [ctypes.c_int]
+    lib.comet_status_string.restype = ctypes.c_char_p
+    lib.comet_last_error.argtypes = []
+    lib.comet_last_error.restype = ctypes.c_char_p
+    lib.comet_version.restype = ctypes.c_int
+    lib.comet_dca_variant_count.restype = ctypes.c_int
+    lib.comet_dca_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4]
+    lib.comet_profile_begin.restype = ctypes.c_int
+    lib.comet_profile_end.restype = ctypes.c_int
+    lib.comet_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.comet_dca_set_variant.argtypes = [ctypes.c_int]
+    for name in ("comet_seed_grid", "comet_refine_grid", "comet_extrapolate_seeds",
+                 "comet_dca_rss", "comet_select_classify", "comet_dca_set_variant",
+                 "comet_dca_variant_info"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().comet_status_string(status).decode()
+
+
+def _check(status: int, call: str):
+    if status != OK:
+        raise CometError(status, call, load().comet_last_error().decode())
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, name, shape=None, optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError("%s is required" % name)
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError("%s must be a tensor on the GPU" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return _vp(t.data_ptr())
+
+
+def _n4(n):
+    arr = (ctypes.c_int32 * 4)(*[int(v) for v in n])
+    return arr
+
+
+def make_config(bz: float, charge: float, step_mm: float, n_steps: int, lambda_mm: float):
+    return Config(float(bz), float(charge), float(step_mm), int(n_steps), 0, float(lambda_mm))
+
+
+# ------------------------------------------------------------------ entry points
+def seed_grid(grid: torch.Tensor, n, seeds: torch.Tensor) -> None:
+    """comet_seed_grid: grid f64[14] -> seeds f64[6, S], S = prod(n)."""
+    S = int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
+    _check(load().comet_seed_grid(_ptr(grid, torch.float64, "grid", (14,)), _n4(n),
+                                  _ptr(seeds, torch.float64, "seeds", (6, S)), S, _stream()),
+           "comet_seed_grid")
+
+
+def refine_grid(grid: torch.Tensor, n, best: torch.Tensor) -> None:
+    """comet_refine_grid: re-centre grid f64[14] on best i64[1] in place."""
+    _check(load().comet_refine_grid(_ptr(grid, torch.float64, "grid", (14,)), _n4(n),
+                                    _ptr(best, torch.int64, "best", (1,)), _stream()),
+           "comet_refine_grid")
+
+
+def extrapolate_seeds(seeds: torch.Tensor, cfg: Config, track: torch.Tensor) -> None:
+    """comet_extrapolate_seeds: seeds f64[6, S] -> track f64[3, K+1, S]."""
+    S = int(seeds.shape[1]) if seeds.dim() == 2 else -1
+    _check(load().comet_extrapolate_seeds(
+        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
+        _ptr(track, torch.float64, "track", (3, cfg.n_steps + 1, S)), _stream()),
+        "comet_extrapolate_seeds")
+
+
+def dca_workspace_bytes(n_seeds: int, n_wires: int) -> int:
+    return int(load().comet_dca_workspace_bytes(int(n_seeds), int(n_wires)))
+
+
+def dca_workspace(n_seeds: int, n_wires: int, device=None) -> torch.Tensor:
+    """A workspace tensor large enough for comet_dca_rss (256-byte aligned)."""
+    nbytes = max(dca_workspace_bytes(n_seeds, n_wires), 8)
+    return torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device or "cuda")
+
+
+def dca_rss(track: torch.Tensor, wire_ends: torch.Tensor, wire_offsets: torch.Tensor,
+            drift: torch.Tensor, cfg: Config, rss: torch.Tensor, workspace: torch.Tensor) -> None:
+    """comet_dca_rss: Eq. 1 RSS of every seed's recorded track."""
+    if track.dim() != 3 or track.shape[0] != 3:
+        raise ValueError("track must have shape (3, K+1, S)")
+    P, S = int(track.shape[1]), int(track.shape[2])
+    n_w = int(wire_ends.shape[0])
+    n_h = int(drift.shape[0])
+    ws = _ptr(workspace, torch.float64, "workspace")
+    _check(load().comet_dca_rss(
+        _ptr(track, torch.float64, "track"), S, P,
+        _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(drift, torch.float64, "drift", (n_h,)), n_h, ctypes.byref(cfg),
+        _ptr(rss, torch.float64, "rss", (S,)), ws, workspace.numel() * 8, _stream()),
+        "comet_dca_rss")
+
+
+def select_classify(rss: torch.Tensor, best: torch.Tensor, cfg: Config, track=None,
+                    wire_ends=None, wire_offsets=None, drift=None, hit_mask=None,
+                    n_borderline=None, dca_best=None, top_k: int = 1) -> None:
+    """comet_select_classify: argmin of rss into best; optionally classify the hits."""
+    S = int(rss.shape[0])
+    n_w = int(wire_ends.shape[0]) if wire_ends is not None else 0
+    n_h = int(drift.shape[0]) if drift is not None else 0
+    P = int(track.shape[1]) if track is not None else 0
+    _check(load().comet_select_classify(
+        _ptr(rss, torch.float64, "rss", (S,)), S,
+        _ptr(track, torch.float64, "track", optional=True), P,
+        _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6), optional=True), n_w,
+        _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,), optional=True),
+        _ptr(drift, torch.float64, "drift", (n_h,), optional=True), n_h, ctypes.byref(cfg),
+        int(top_k), _ptr(best, torch.int64, "best", (1,)),
+        _ptr(hit_mask, torch.uint8, "hit_mask", (n_h,), optional=True),
+        _ptr(n_borderline, torch.int32, "n_borderline", (1,), optional=True),
+        _ptr(dca_best, torch.float64, "dca_best", (n_w,), optional=True), _stream()),
+        "comet_select_classify")
+
+
+# ------------------------------------------------------------------ tuning hooks
+def dca_variants():
+    lib = load()
+    out = []
+    for i in range(lib.comet_dca_variant_count()):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib.comet_dca_variant_info(i, *[ctypes.byref(x) for x in v]),
+               "comet_dca_variant_info")
+        out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value,
+                        chunk_argmin=bool(v[3].value)))
+    return out
+
+
+def set_dca_variant(i: int) -> None:
+    _check(load().comet_dca_set_variant(int(i)), "comet_dca_set_variant")
+
+
+PROFILE_KINDS = ("track", "dca", "rss_sum", "select")
+
+
+def profile_begin() -> None:
+    _check(load().comet_profile_begin(), "comet_profile_begin")
+
+
+def profile_end() -> dict:
+    """{kind: (total_ms, launches)} since profile_begin (waits for the events)."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    _check(load().comet_profile_end(ms, n), "comet_profile_end")
+    return {k: (ms[i], n[i]) for i, k in enumerate(PROFILE_KINDS)}

@@ -1,0 +1,96 @@
+"""Device buffers and the launch sequence of one turn partition's seed scan.
+
+One partition runs (Sec. 2.1): seed grid -> track recording (Alg. 1) -> DCA and
+Eq. 1 RSS (Alg. 2) -> argmin, then `n_refine` finer re-scans around the best seed,
+then classification of the hits at the final best seed. Every step is a call into
+the HIP library through `comet`; this module only allocates buffers and orders
+the launches on the current stream (no host synchronisation inside `run`).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import comet
+
+
+@dataclass
+class DeviceEvent:
+    """An event's wires and hits in device memory (CSR by wire)."""
+    wire_ends: torch.Tensor     # f64 [n_w, 6]
+    wire_offsets: torch.Tensor  # i32 [n_w + 1]
+    drift: torch.Tensor         # f64 [n_h]
+
+    @classmethod
+    def from_event(cls, ev, device="cuda"):
+        return cls(torch.as_tensor(np.ascontiguousarray(ev.wire_ends), device=device),
+                   torch.as_tensor(np.ascontiguousarray(ev.wire_offsets, dtype=np.int32),
+                                   device=device),
+                   torch.as_tensor(np.ascontiguousarray(ev.drift), device=device))
+
+    @property
+    def n_wires(self) -> int:
+        return int(self.wire_ends.shape[0])
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.drift.shape[0])
+
+
+class PartitionScanner:
+    """Buffers sized for one grid shape, step count and event size."""
+
+    def __init__(self, n, cfg: comet.Config, n_wires: int, n_hits: int, device="cuda"):
+        self.n = tuple(int(v) for v in n)
+        self.S = int(np.prod(self.n))
+        self.cfg = cfg
+        self.P = cfg.n_steps + 1
+        f64 = dict(dtype=torch.float64, device=device)
+        self.grid = torch.empty(14, **f64)
+        self.seeds = torch.empty(6, self.S, **f64)
+        self.track = torch.empty(3, self.P, self.S, **f64)
+        self.rss = torch.empty(self.S, **f64)
+        self.best = torch.empty(1, dtype=torch.int64, device=device)
+        self.workspace = comet.dca_workspace(self.S, n_wires, device)
+        self.mask = torch.empty(n_hits, dtype=torch.uint8, device=device)
+        self.n_border = torch.empty(1, dtype=torch.int32, device=device)
+        self.dca_best = torch.empty(n_wires, **f64)
+
+    def run(self, ev: DeviceEvent, grid0: torch.Tensor, n_refine: int) -> None:
+        """The whole path for one partition; results stay in the buffers."""
+        self.grid.copy_(grid0)
+        for it in range(n_refine + 1):
+            if it:
+                comet.refine_grid(self.grid, self.n, self.best)
+            comet.seed_grid(self.grid, self.n, self.seeds)
+            comet.extrapolate_seeds(self.seeds, self.cfg, self.track)
+            comet.dca_rss(self.track, ev.wire_ends, ev.wire_offsets, ev.drift, self.cfg,
+                          self.rss, self.workspace)
+            last = it == n_refine
+            comet.select_classify(self.rss, self.best, self.cfg, self.track, ev.wire_ends,
+                                  ev.wire_offsets, ev.drift,
+                                  hit_mask=self.mask if last else None,
+                                  n_borderline=self.n_border if last else None,
+                                  dca_best=self.dca_best if last else None)
+
+    def result(self) -> dict:
+        """Copy the partition's results to the host (synchronises)."""
+        b = int(self.best.item())
+        out = {"best": b, "grid": self.grid.cpu().numpy(), "mask": self.mask.cpu().numpy(),
+               "n_borderline": int(self.n_border.item()), "dca_best": self.dca_best.cpu().numpy()}
+        if b >= 0:
+            out["best_seed"] = self.seeds[:, b].cpu().numpy()
+            out["best_rss"] = float(self.rss[b].item())
+        return out
+
+
+def grid_tensor(ref_state, scan_cfg, device="cuda") -> torch.Tensor:
+    from .synth import grid_descriptor
+    return torch.as_tensor(grid_descriptor(ref_state, scan_cfg), device=device)
+
+
+def config_for(ev, scan_cfg) -> comet.Config:
+    return comet.make_config(ev.bz, ev.charge, scan_cfg.step_mm, scan_cfg.n_steps,
+                             scan_cfg.lambda_mm)

@@ -1,0 +1,155 @@
+"""The C ABI on the host: every declared symbol is exported, and host-visible
+argument errors are rejected before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1911_09340_amd import comet
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "comet.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(comet_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return comet.load()
+
+
+def test_header_declares_the_three_calls():
+    names = declared_functions()
+    for n in ("comet_extrapolate_seeds", "comet_dca_rss", "comet_select_classify"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for st in (comet.OK, comet.EINVAL, comet.EWORKSPACE, comet.EHIP, comet.EUNSUPPORTED):
+        assert comet.status_string(st) and comet.status_string(st) != "unknown status"
+    assert comet.status_string(42) == "unknown status"
+    assert lib.comet_version() >= 100
+
+
+def _cfg(**kw):
+    c = dict(bz=1.0, charge=-1.0, step_mm=2.0, n_steps=10, lambda_mm=1.0)
+    c.update(kw)
+    return comet.make_config(**c)
+
+
+def _p(v=0x1000):
+    return ctypes.c_void_p(v)
+
+
+def _n4(*n):
+    return (ctypes.c_int32 * 4)(*n)
+
+
+def test_workspace_bytes(lib):
+    assert lib.comet_dca_workspace_bytes(0, 10) == 0
+    assert lib.comet_dca_workspace_bytes(10, -1) == 0
+    a = lib.comet_dca_workspace_bytes(64, 10)
+    b = lib.comet_dca_workspace_bytes(128, 10)
+    assert a % 256 == 0 and b > a
+    assert a >= 8 * 64 * 10 + 8 * 8 * 10
+
+
+@pytest.mark.parametrize("case", ["null_grid", "bad_n", "count_mismatch"])
+def test_seed_grid_rejects(lib, case):
+    n = _n4(2, 2, 2, 2)
+    args = {"null_grid": (None, n, _p(), 16), "bad_n": (_p(), _n4(2, 0, 2, 2), _p(), 0),
+            "count_mismatch": (_p(), n, _p(), 17)}[case]
+    assert lib.comet_seed_grid(*args, None) == comet.EINVAL
+    assert lib.comet_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("n_steps", 0), ("step_mm", 0.0), ("step_mm", float("nan")),
+                                          ("lambda_mm", -1.0), ("lambda_mm", float("inf")),
+                                          ("bz", float("nan")), ("charge", float("inf"))])
+def test_extrapolate_rejects_config(lib, field, value):
+    cfg = _cfg(**{field: value})
+    assert lib.comet_extrapolate_seeds(_p(), 64, ctypes.byref(cfg), _p(), None) == comet.EINVAL
+
+
+def test_extrapolate_rejects_pointers_and_sizes(lib):
+    cfg = _cfg()
+    assert lib.comet_extrapolate_seeds(None, 64, ctypes.byref(cfg), _p(), None) == comet.EINVAL
+    assert lib.comet_extrapolate_seeds(_p(), 0, ctypes.byref(cfg), _p(), None) == comet.EINVAL
+    assert lib.comet_extrapolate_seeds(_p(), 64, None, _p(), None) == comet.EINVAL
+    bad = _cfg()
+    bad.reserved = 1
+    assert lib.comet_extrapolate_seeds(_p(), 64, ctypes.byref(bad), _p(), None) == comet.EINVAL
+
+
+def _dca(lib, track=_p(), S=64, P=11, ends=_p(), n_w=4, offs=_p(), drift=_p(), n_h=5, cfg=None,
+         rss=_p(), ws=_p(0x100000), ws_bytes=1 << 30):
+    cfg = cfg or _cfg()
+    return lib.comet_dca_rss(track, S, P, ends, n_w, offs, drift, n_h, ctypes.byref(cfg), rss, ws,
+                             ws_bytes, None)
+
+
+def test_dca_rss_rejects(lib):
+    assert _dca(lib, track=None) == comet.EINVAL
+    assert _dca(lib, rss=None) == comet.EINVAL
+    assert _dca(lib, S=0) == comet.EINVAL
+    assert _dca(lib, P=10) == comet.EINVAL          # n_points != n_steps + 1
+    assert _dca(lib, n_w=-1) == comet.EINVAL
+    assert _dca(lib, ends=None) == comet.EINVAL
+    assert _dca(lib, offs=None) == comet.EINVAL
+    assert _dca(lib, drift=None) == comet.EINVAL
+    assert _dca(lib, cfg=_cfg(lambda_mm=0.0)) == comet.EINVAL
+    assert _dca(lib, ws=None) == comet.EWORKSPACE
+    assert _dca(lib, ws_bytes=16) == comet.EWORKSPACE
+    assert _dca(lib, ws=_p(0x100008)) == comet.EINVAL  # misaligned
+
+
+def test_select_classify_rejects(lib):
+    cfg = _cfg()
+    best = _p()
+    # top_k other than 1 is not supported
+    assert lib.comet_select_classify(_p(), 64, None, 0, None, 0, None, None, 0, ctypes.byref(cfg),
+                                     2, best, None, None, None, None) == comet.EUNSUPPORTED
+    assert lib.comet_select_classify(None, 64, None, 0, None, 0, None, None, 0, ctypes.byref(cfg),
+                                     1, best, None, None, None, None) == comet.EINVAL
+    assert lib.comet_select_classify(_p(), 64, None, 0, None, 0, None, None, 0, ctypes.byref(cfg),
+                                     1, None, None, None, None, None) == comet.EINVAL
+    # classification needs the track and a matching point count
+    assert lib.comet_select_classify(_p(), 64, None, 11, _p(), 4, _p(), _p(), 5, ctypes.byref(cfg),
+                                     1, best, _p(), None, None, None) == comet.EINVAL
+    assert lib.comet_select_classify(_p(), 64, _p(), 12, _p(), 4, _p(), _p(), 5, ctypes.byref(cfg),
+                                     1, best, _p(), None, None, None) == comet.EINVAL
+
+
+def test_refine_rejects(lib):
+    assert lib.comet_refine_grid(None, _n4(2, 2, 2, 2), _p(), None) == comet.EINVAL
+    assert lib.comet_refine_grid(_p(), _n4(2, 2, 0, 2), _p(), None) == comet.EINVAL
+
+
+def test_valid_call_without_gpu_fails_loudly(lib):
+    """On a machine without a GPU a well-formed call reports a HIP error; nothing
+    falls back to the CPU."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = _cfg()
+    st = lib.comet_extrapolate_seeds(_p(), 64, ctypes.byref(cfg), _p(), None)
+    assert st in (comet.EHIP, comet.EUNSUPPORTED)
+    assert lib.comet_last_error()
+
+
+def test_binding_validates_tensors():
+    import torch
+    cfg = _cfg()
+    with pytest.raises(ValueError):
+        comet.extrapolate_seeds(torch.zeros(6, 64, dtype=torch.float64), cfg,
+                                torch.zeros(3, 11, 64, dtype=torch.float64))
