@@ -34,7 +34,8 @@ FLOP_PER_POINT_WIRE = 15  # 6 FMA (in-plane coordinates) + 1 MUL + 1 FMA (square
 METRIC = ("seed×hit DCA evals/s and events/s (FP64 % peak); "
           "grad-refine vs fine-grid time")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dca_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1911_09340_amd", "csrc", "comet.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1911_09340_amd", "csrc", f)
+               for f in ("comet.hip", "device_math.h")]
 
 
 def log(*a):
@@ -42,8 +43,12 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources of the forward-path kernels (traffic numbers go stale with them)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic():
@@ -153,6 +158,13 @@ def main():
         return t1 - t0, comet.profile_end()
 
     variants = comet.dca_variants()
+    # autotune the DCA kernel shape on the first partition's live buffers
+    step()
+    r0 = runners[0]
+    tuned, tune_ms = comet.dca_autotune(r0.track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg,
+                                        r0.rss, r0.workspace, reps=2)
+    log("autotune: shape %d %s (%.3f ms); all: %s" % (tuned, variants[tuned], tune_ms[tuned],
+                                                      ", ".join("%.3f" % m for m in tune_ms)))
     if args.sweep:
         for i, v in enumerate(variants):
             comet.set_dca_variant(i)
@@ -161,8 +173,8 @@ def main():
             tfl = FLOP_PER_POINT_WIRE * sc.n_seeds * ev.n_wires * P / (ms / n * 1e-3) / 1e12
             log("variant %d %s: %.3f ms/step, dca %.3f ms/launch, %.1f TFLOP/s (%.1f %% of FP64 peak)"
                 % (i, v, dt / max(2, args.steps // 2) * 1e3, ms / n, tfl, 100 * tfl / PEAK_FP64_TFLOPS))
-    variant = 0 if args.variant is None else args.variant
-    comet.set_dca_variant(variant)
+    comet.set_dca_variant(-1 if args.variant is None else args.variant)
+    variant = comet.dca_variant_for(sc.n_seeds, P, ev.n_wires)
 
     log("warmup %d, timing %d steps (%d scans of %d seeds x %d hits each) ..."
         % (args.warmup, args.steps, scans_per_step, sc.n_seeds, ev.n_hits))

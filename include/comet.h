@@ -150,15 +150,32 @@ int comet_profile_end(double ms[COMET_PROFILE_KINDS], int64_t launches[COMET_PRO
 
 /* ------------------------------------------------------------ tuning
  * The DCA kernel exists in several shapes: W wires per wave, NWV waves per block,
- * C track points per LDS chunk, and whether the first closest index is tracked per
- * point (0) or per chunk with a final rescan (1). All shapes give identical results.
- * comet_dca_variant_info() describes shape `id` (0 <= id < comet_dca_variant_count());
- * comet_dca_set_variant() selects the shape later comet_dca_rss calls use
- * (process-wide; the default is 0). */
+ * C track points per LDS chunk, whether the first closest index is tracked per point
+ * (chunk_argmin = 0) or per chunk with a final rescan (1), and whether blocks are
+ * remapped so that one seed tile's wire groups share an XCD. Every shape gives the
+ * same results bit for bit; only speed differs.
+ *
+ * comet_dca_autotune() takes the arguments of comet_dca_rss (same checks, same
+ * result in rss) plus: reps (1..1000) timed launches per shape, best_id (host, may be
+ * NULL) receiving the fastest shape, ms (host, may be NULL, comet_dca_variant_count()
+ * entries) receiving each shape's mean kernel time. It records the fastest shape for
+ * this (n_seeds, n_points, n_wires) and later comet_dca_rss calls of that shape use
+ * it. Unlike the other calls it creates two HIP events and synchronises `stream`: it
+ * is a set-up call, not one for a timed loop.
+ *
+ * comet_dca_set_variant(id) forces shape id for every call (-1 removes the override);
+ * comet_dca_variant_for() reports the shape a call of that size would use;
+ * comet_dca_variant_info() describes shape id (0 <= id < comet_dca_variant_count()). */
 int comet_dca_variant_count(void);
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
-                           int32_t *chunk_argmin);
+                           int32_t *chunk_argmin, int32_t *xcd_remap);
 int comet_dca_set_variant(int id);
+int comet_dca_variant_for(int64_t n_seeds, int32_t n_points, int32_t n_wires);
+int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_points,
+                       const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                       const double *drift, int32_t n_hits, const comet_config *cfg, double *rss,
+                       void *workspace, size_t workspace_bytes, int32_t reps, int32_t *best_id,
+                       double *ms, void *stream);
 
 /* Static description of a status code. */
 const char *comet_status_string(int status);

@@ -65,7 +65,14 @@ def load(path: str = LIB_PATH):
     lib.comet_last_error.restype = ctypes.c_char_p
     lib.comet_version.restype = ctypes.c_int
     lib.comet_dca_variant_count.restype = ctypes.c_int
-    lib.comet_dca_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4]
+    lib.comet_dca_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4, I4]
+    lib.comet_dca_variant_for.argtypes = [_i64, _i32, _i32]
+    lib.comet_dca_variant_for.restype = ctypes.c_int
+    lib.comet_dca_autotune.argtypes = [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _i32,
+                                       ctypes.POINTER(Config), _vp, _vp, ctypes.c_size_t, _i32,
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_double), _vp]
+    lib.comet_dca_autotune.restype = ctypes.c_int
     lib.comet_profile_begin.restype = ctypes.c_int
     lib.comet_profile_end.restype = ctypes.c_int
     lib.comet_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double),
@@ -196,16 +203,43 @@ def dca_variants():
     lib = load()
     out = []
     for i in range(lib.comet_dca_variant_count()):
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32() for _ in range(5)]
         _check(lib.comet_dca_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_dca_variant_info")
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value,
-                        chunk_argmin=bool(v[3].value)))
+                        chunk_argmin=bool(v[3].value), xcd_remap=bool(v[4].value)))
     return out
 
 
 def set_dca_variant(i: int) -> None:
+    """Force DCA kernel shape i for every call (-1 removes the override)."""
     _check(load().comet_dca_set_variant(int(i)), "comet_dca_set_variant")
+
+
+def dca_variant_for(n_seeds: int, n_points: int, n_wires: int) -> int:
+    return int(load().comet_dca_variant_for(int(n_seeds), int(n_points), int(n_wires)))
+
+
+def dca_autotune(track: torch.Tensor, wire_ends: torch.Tensor, wire_offsets: torch.Tensor,
+                 drift: torch.Tensor, cfg: Config, rss: torch.Tensor, workspace: torch.Tensor,
+                 reps: int = 3):
+    """comet_dca_autotune: time every DCA shape on these inputs, keep the fastest for
+    this shape. Returns (best id, [ms per shape]). Synchronises the current stream."""
+    P, S = int(track.shape[1]), int(track.shape[2])
+    n_w = int(wire_ends.shape[0])
+    n_h = int(drift.shape[0])
+    nv = load().comet_dca_variant_count()
+    ms = (ctypes.c_double * nv)()
+    best = ctypes.c_int32(-1)
+    _check(load().comet_dca_autotune(
+        _ptr(track, torch.float64, "track"), S, P,
+        _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(drift, torch.float64, "drift", (n_h,)), n_h, ctypes.byref(cfg),
+        _ptr(rss, torch.float64, "rss", (S,)), _ptr(workspace, torch.float64, "workspace"),
+        workspace.numel() * 8, int(reps), ctypes.byref(best), ms, _stream()),
+        "comet_dca_autotune")
+    return best.value, list(ms)
 
 
 PROFILE_KINDS = ("track", "dca", "rss_sum", "select")

@@ -27,156 +27,22 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
 #include <vector>
 
 #include "comet.h"
+#include "device_math.h"
+#include "host_common.h"
 
 namespace {
 
-constexpr double kKappa = 0.299792458;  // MeV/c per (T mm)
-constexpr int kVersion = 100;            // 0.1.0
+constexpr int kVersion = 100;  // 0.1.0
 
-thread_local char g_last_error[512] = "";
-
-int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int status, const char *fmt, ...)
-{
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
-    va_end(ap);
-    return status;
-}
-
-// Only gfx950 is supported; the answer is cached per device.
-int check_device()
-{
-    static std::mutex mu;
-    static int cached[64];  // 0 unknown, 1 ok, -1 unsupported
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess)
-        return fail(COMET_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
-    if (dev < 0 || dev >= 64)
-        return fail(COMET_EUNSUPPORTED, "device index %d out of range", dev);
-    {
-        std::lock_guard<std::mutex> lock(mu);
-        if (cached[dev] == 0) {
-            hipDeviceProp_t prop;
-            e = hipGetDeviceProperties(&prop, dev);
-            if (e != hipSuccess)
-                return fail(COMET_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
-            cached[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
-            if (cached[dev] < 0)
-                snprintf(g_last_error, sizeof(g_last_error), "device %d is %s, not gfx950", dev,
-                         prop.gcnArchName);
-        }
-        if (cached[dev] < 0)
-            return COMET_EUNSUPPORTED;
-    }
-    return COMET_OK;
-}
-
-int launched(const char *what)
-{
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return fail(COMET_EHIP, "%s launch: %s", what, hipGetErrorString(e));
-    return COMET_OK;
-}
-
-// ------------------------------------------------------------------ profiling
-// Optional per-kernel device time: pairs of HIP events recorded around launches.
-struct ProfRecord {
-    hipEvent_t start, stop;
-    int kind;
-};
-std::mutex g_prof_mu;
-bool g_prof_on = false;
-std::vector<ProfRecord> g_prof_records;
-std::vector<hipEvent_t> g_prof_pool;
-
-hipEvent_t prof_event()
-{
-    if (!g_prof_pool.empty()) {
-        hipEvent_t e = g_prof_pool.back();
-        g_prof_pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess)
-        return nullptr;
-    return e;
-}
-
-// Brackets one launch on `stream` with events when profiling is on.
-class ProfScope {
-  public:
-    ProfScope(int kind, hipStream_t stream) : stream_(stream), kind_(kind)
-    {
-        std::lock_guard<std::mutex> lock(g_prof_mu);
-        if (!g_prof_on)
-            return;
-        start_ = prof_event();
-        stop_ = prof_event();
-        if (start_ && stop_)
-            hipEventRecord(start_, stream_);
-    }
-    ~ProfScope()
-    {
-        if (!start_ || !stop_)
-            return;
-        hipEventRecord(stop_, stream_);
-        std::lock_guard<std::mutex> lock(g_prof_mu);
-        g_prof_records.push_back({start_, stop_, kind_});
-    }
-
-  private:
-    hipStream_t stream_;
-    int kind_;
-    hipEvent_t start_ = nullptr, stop_ = nullptr;
-};
-
-enum { kProfTrack = 0, kProfDca = 1, kProfSum = 2, kProfSelect = 3 };
-
-bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
-
-int check_config(const comet_config *cfg)
-{
-    if (!cfg)
-        return fail(COMET_EINVAL, "cfg is NULL");
-    if (!isfinite(cfg->bz_tesla) || !isfinite(cfg->charge_e))
-        return fail(COMET_EINVAL, "bz_tesla and charge_e must be finite");
-    if (!finite_pos(cfg->step_mm))
-        return fail(COMET_EINVAL, "step_mm must be finite and > 0");
-    if (cfg->n_steps < 1 || cfg->n_steps > (1 << 24))
-        return fail(COMET_EINVAL, "n_steps must be in [1, 2^24]");
-    if (!finite_pos(cfg->lambda_mm))
-        return fail(COMET_EINVAL, "lambda_mm must be finite and > 0");
-    if (cfg->reserved != 0)
-        return fail(COMET_EINVAL, "reserved must be 0");
-    return COMET_OK;
-}
+using namespace cdev;
+using namespace chost;
 
 // ------------------------------------------------------------------ seed grid
-// Axis value i of n: centre (n == 1) or centre + half ((2i - (n-1)) / (n-1)).
-__device__ __forceinline__ double axis_value(double centre, double half, int n, int i)
-{
-    if (n == 1)
-        return centre;
-    return centre + half * ((double)(2 * i - (n - 1)) / (double)(n - 1));
-}
-
-// Rotation by 2 atan(tau): cos = (1 - tau^2) / (1 + tau^2), sin = (2 tau) / (1 + tau^2).
-__device__ __forceinline__ void half_angle_rotation(double tau, double &c, double &s)
-{
-    const double t2 = tau * tau;
-    const double den = 1.0 + t2;
-    c = (1.0 - t2) / den;
-    s = (2.0 * tau) / den;
-}
-
 // One thread per seed (Sec. 3.1: the seed set is the product of the component grids).
 __global__ void seed_grid_kernel(const double *__restrict__ grid, int n0, int n1, int n2, int n3,
                                  int64_t S, double *__restrict__ seeds)
@@ -243,10 +109,8 @@ __global__ void refine_grid_kernel(double *__restrict__ grid, int n0, int n1, in
 }
 
 // ------------------------------------------------------------------ RK4 recording
-// Alg. 1, one seed per lane. ODE in path length: dx/ds = p / p0,
-// dp/ds = c (p_y, -p_x, 0), c = ((kappa q) B_z) / p0 (as c = ((kappa q) B_z) * inv).
-// Classical RK4 with fixed h; y <- y + h/6 (((k1 + 2 k2) + 2 k3) + k4); p_z constant.
-// The store of point k writes 64 consecutive doubles per coordinate row per wave.
+// Alg. 1, one seed per lane (the step is cdev::rk4_step). The store of point k
+// writes 64 consecutive doubles per coordinate row per wave.
 __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restrict__ seeds,
                                                          int64_t S, double bz, double charge,
                                                          double h, int K,
@@ -258,38 +122,16 @@ __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restric
     double x = seeds[0 * S + s], y = seeds[1 * S + s], z = seeds[2 * S + s];
     double px = seeds[3 * S + s], py = seeds[4 * S + s];
     const double pz = seeds[5 * S + s];
-    const double p0 = sqrt((px * px + py * py) + pz * pz);
-    const double inv = 1.0 / p0;
-    const double c = ((kKappa * charge) * bz) * inv;
-    const double hh = 0.5 * h;
-    const double h6 = h / 6.0;
-    const double vz = pz * inv;
+    const cdev::StepConsts k = cdev::step_consts(px, py, pz, bz, charge, h);
     const int64_t P = (int64_t)K + 1;
     double *tx = track + s;
     double *ty = track + P * S + s;
     double *tz = track + 2 * P * S + s;
-    for (int k = 0; k < K; ++k) {
-        tx[(int64_t)k * S] = x;
-        ty[(int64_t)k * S] = y;
-        tz[(int64_t)k * S] = z;
-        const double v1x = px * inv, v1y = py * inv;
-        const double f1x = c * py, f1y = -(c * px);
-        double qx = px + hh * f1x, qy = py + hh * f1y;
-        const double v2x = qx * inv, v2y = qy * inv;
-        const double f2x = c * qy, f2y = -(c * qx);
-        qx = px + hh * f2x;
-        qy = py + hh * f2y;
-        const double v3x = qx * inv, v3y = qy * inv;
-        const double f3x = c * qy, f3y = -(c * qx);
-        qx = px + h * f3x;
-        qy = py + h * f3y;
-        const double v4x = qx * inv, v4y = qy * inv;
-        const double f4x = c * qy, f4y = -(c * qx);
-        x = x + h6 * (((v1x + 2.0 * v2x) + 2.0 * v3x) + v4x);
-        y = y + h6 * (((v1y + 2.0 * v2y) + 2.0 * v3y) + v4y);
-        z = z + h6 * (((vz + 2.0 * vz) + 2.0 * vz) + vz);
-        px = px + h6 * (((f1x + 2.0 * f2x) + 2.0 * f3x) + f4x);
-        py = py + h6 * (((f1y + 2.0 * f2y) + 2.0 * f3y) + f4y);
+    for (int j = 0; j < K; ++j) {
+        tx[(int64_t)j * S] = x;
+        ty[(int64_t)j * S] = y;
+        tz[(int64_t)j * S] = z;
+        cdev::rk4_step(k, x, y, z, px, py);
     }
     tx[(int64_t)K * S] = x;
     ty[(int64_t)K * S] = y;
@@ -297,34 +139,6 @@ __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restric
 }
 
 // ------------------------------------------------------------------ wire frames
-// The distance of a point to a wire is the length of its offset from the wire
-// projected on the plane normal to the unit direction n; (e1, e2) spans that plane
-// (branch-free orthonormal basis of Duff et al., JCGT 2017):
-//   s = copysign(1, n_z), a = -1 / (s + n_z), b = (n_x n_y) a,
-//   e1 = (1 + ((s n_x) n_x) a, s b, -(s n_x)),  e2 = (b, s + (n_y n_y) a, -n_y),
-//   nc = -((e_x A_x + e_y A_y) + e_z A_z) for endpoint A.
-// frame = (e1x, e1y, e1z, nc1, e2x, e2y, e2z, nc2).
-__device__ __forceinline__ void wire_frame(const double *__restrict__ ends, double f[8])
-{
-    const double ax = ends[0], ay = ends[1], az = ends[2];
-    const double dx = ends[3] - ax, dy = ends[4] - ay, dz = ends[5] - az;
-    const double len = sqrt((dx * dx + dy * dy) + dz * dz);
-    const double nx = dx / len, ny = dy / len, nz = dz / len;
-    const double s = copysign(1.0, nz);
-    const double a = -1.0 / (s + nz);
-    const double b = (nx * ny) * a;
-    const double e1x = 1.0 + ((s * nx) * nx) * a, e1y = s * b, e1z = -(s * nx);
-    const double e2x = b, e2y = s + (ny * ny) * a, e2z = -ny;
-    f[0] = e1x;
-    f[1] = e1y;
-    f[2] = e1z;
-    f[3] = -((e1x * ax + e1y * ay) + e1z * az);
-    f[4] = e2x;
-    f[5] = e2y;
-    f[6] = e2z;
-    f[7] = -((e2x * ax + e2y * ay) + e2z * az);
-}
-
 // frames[w] for w < n_w; zero frames pad the array to n_pad entries.
 __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad,
                              double *__restrict__ frames)
@@ -337,78 +151,6 @@ __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad
         wire_frame(ends + 6 * (int64_t)w, f);
     for (int j = 0; j < 8; ++j)
         frames[8 * (int64_t)w + j] = f[j];
-}
-
-// In-plane coordinates: xi = fma(e1x, x, fma(e1y, y, fma(e1z, z, nc1))), eta likewise.
-__device__ __forceinline__ void project(const double f[8], double x, double y, double z,
-                                        double &xi, double &eta)
-{
-    xi = fma(f[0], x, fma(f[1], y, fma(f[2], z, f[3])));
-    eta = fma(f[4], x, fma(f[5], y, fma(f[6], z, f[7])));
-}
-
-// Squared distance from the wire to the chord a -> b (in-plane coordinates):
-// u = b - a, g = fma(a_xi, u_xi, a_eta u_eta), den = fma(u_xi, u_xi, u_eta u_eta);
-// t = 0 (g >= 0) gives qa, t = 1 (-g >= den) gives qb, otherwise t = -g / den and
-// the point a + t u gives fma(p_xi, p_xi, p_eta p_eta).
-__device__ __forceinline__ double chord_distance2(double axi, double aeta, double qa, double bxi,
-                                                  double beta, double qb)
-{
-    const double uxi = bxi - axi, ueta = beta - aeta;
-    const double g = fma(axi, uxi, aeta * ueta);
-    const double den = fma(uxi, uxi, ueta * ueta);
-    if (!(g < 0.0))
-        return qa;
-    if (-g >= den)
-        return qb;
-    const double t = -g / den;
-    const double pxi = fma(t, uxi, axi), peta = fma(t, ueta, aeta);
-    return fma(pxi, pxi, peta * peta);
-}
-
-// Alg. 2's local refinement from the closest recorded point k (value qk): the
-// squared DCA is min(qk, chord(k-1 -> k), chord(k -> k+1)). Point j of seed s is
-// track[(c P + j) S + s].
-__device__ __forceinline__ double refine_dca2(const double *__restrict__ track, int64_t S, int P,
-                                              int64_t s, const double f[8], int k, double qk)
-{
-    const int64_t PS = (int64_t)P * S;
-    const double *t = track + s;
-    double cxi, ceta;
-    project(f, t[(int64_t)k * S], t[PS + (int64_t)k * S], t[2 * PS + (int64_t)k * S], cxi, ceta);
-    double d2 = qk;
-    if (k > 0) {
-        const int64_t o = (int64_t)(k - 1) * S;
-        double xi, eta;
-        project(f, t[o], t[PS + o], t[2 * PS + o], xi, eta);
-        const double q = fma(xi, xi, eta * eta);
-        const double v = chord_distance2(xi, eta, q, cxi, ceta, qk);
-        if (v < d2)
-            d2 = v;
-    }
-    if (k < P - 1) {
-        const int64_t o = (int64_t)(k + 1) * S;
-        double xi, eta;
-        project(f, t[o], t[PS + o], t[2 * PS + o], xi, eta);
-        const double q = fma(xi, xi, eta * eta);
-        const double v = chord_distance2(cxi, ceta, qk, xi, eta, q);
-        if (v < d2)
-            d2 = v;
-    }
-    return d2;
-}
-
-// Eq. 1 for one wire: d = min(lambda, min_j |D - r_j|).
-__device__ __forceinline__ double capped_residual(double D, const double *__restrict__ drift,
-                                                  int j0, int j1, double lambda)
-{
-    double d = lambda;
-    for (int j = j0; j < j1; ++j) {
-        const double e = fabs(D - drift[j]);
-        if (e < d)
-            d = e;
-    }
-    return d;
 }
 
 // ------------------------------------------------------------------ DCA / Eq. 1
@@ -425,20 +167,21 @@ __device__ __forceinline__ double capped_residual(double D, const double *__rest
 // residual is formed, and d^2 is stored to dsq[wire][seed].
 //
 // Block -> work mapping: consecutive blocks are dealt round-robin over the 8 XCDs;
-// the mapping below makes the wire groups of one seed tile consecutive within one
-// XCD so that they read the tile's track through the same L2.
+// with xcd_remap the wire groups of one seed tile become consecutive within one
+// XCD so that they can read the tile's track through the same L2 (without it,
+// consecutive block indices take consecutive groups).
 template <int W, int NWV, int C, bool CHUNK_ARGMIN>
 __global__ __launch_bounds__(64 * NWV) void dca_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames,
     int n_w, const int32_t *__restrict__ offsets, const double *__restrict__ drift,
-    double lambda, double *__restrict__ dsq, int n_groups, int n_blocks)
+    double lambda, double *__restrict__ dsq, int n_groups, int n_blocks, int xcd_remap)
 {
     __shared__ __align__(16) double lds[3 * C * 64];
 
     const int b = blockIdx.x;
     const int q8 = n_blocks >> 3, r8 = n_blocks & 7;
     const int xcd = b & 7;
-    const int L = xcd * q8 + min(xcd, r8) + (b >> 3);
+    const int L = xcd_remap ? xcd * q8 + min(xcd, r8) + (b >> 3) : b;
     const int tile = L / n_groups;
     const int group = L - tile * n_groups;
 
@@ -756,30 +499,41 @@ __global__ void fill_kernel(double *__restrict__ out, int64_t n, double v)
 
 // ------------------------------------------------------------------ DCA variants
 struct DcaVariant {
-    int w, nwv, c, chunk_argmin;
+    int w, nwv, c, chunk_argmin, xcd_remap;
     void (*kernel)(const double *, int64_t, int, const double *, int, const int32_t *,
-                   const double *, double, double *, int, int);
+                   const double *, double, double *, int, int, int);
 };
 
 const DcaVariant kDcaVariants[] = {
-    {4, 8, 32, 1, dca_kernel<4, 8, 32, true>},
-    {4, 8, 32, 0, dca_kernel<4, 8, 32, false>},
-    {4, 4, 32, 1, dca_kernel<4, 4, 32, true>},
-    {2, 8, 32, 1, dca_kernel<2, 8, 32, true>},
-    {4, 8, 16, 1, dca_kernel<4, 8, 16, true>},
-    {4, 16, 16, 1, dca_kernel<4, 16, 16, true>},
-    {5, 8, 32, 1, dca_kernel<5, 8, 32, true>},
-    {4, 8, 64, 1, dca_kernel<4, 8, 64, true>},
-    {5, 8, 16, 1, dca_kernel<5, 8, 16, true>},
-    {6, 8, 16, 1, dca_kernel<6, 8, 16, true>},
-    {3, 8, 32, 1, dca_kernel<3, 8, 32, true>},
+    {6, 8, 16, 1, 1, dca_kernel<6, 8, 16, true>},
+    {6, 8, 16, 1, 0, dca_kernel<6, 8, 16, true>},
+    {6, 16, 16, 1, 1, dca_kernel<6, 16, 16, true>},
+    {5, 16, 16, 1, 1, dca_kernel<5, 16, 16, true>},
+    {4, 16, 16, 1, 1, dca_kernel<4, 16, 16, true>},
+    {4, 8, 32, 0, 1, dca_kernel<4, 8, 32, false>},
+    {4, 8, 32, 1, 1, dca_kernel<4, 8, 32, true>},
+    {4, 8, 16, 1, 1, dca_kernel<4, 8, 16, true>},
+    {5, 8, 16, 1, 1, dca_kernel<5, 8, 16, true>},
+    {3, 8, 32, 1, 1, dca_kernel<3, 8, 32, true>},
+    {2, 8, 32, 1, 1, dca_kernel<2, 8, 32, true>},
+    {4, 4, 32, 1, 1, dca_kernel<4, 4, 32, true>},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
-int g_dca_variant = 0;
+constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above
 
-constexpr int kMaxWiresPerGroup = 64;  // largest W * NWV in the table above
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+// Variant choice: an explicit process-wide override, else the autotuned choice for
+// the call's shape, else variant 0.
+struct ShapeKey {
+    int64_t S;
+    int P, n_w;
+    bool operator<(const ShapeKey &o) const
+    {
+        return S != o.S ? S < o.S : (P != o.P ? P < o.P : n_w < o.n_w);
+    }
+};
+std::mutex g_tune_mu;
+std::map<ShapeKey, int> g_tuned;
+int g_dca_variant = -1;  // explicit override; -1 = tuned or default
 
 // Frames are padded so that any variant's last wire group stays in bounds:
 // n_groups * (W * NWV) <= n_w + (W * NWV) - 1 <= wire_pad(n_w).
@@ -794,8 +548,6 @@ int wire_pad(int n_w)
 extern "C" {
 
 int comet_version(void) { return kVersion; }
-
-const char *comet_last_error(void) { return g_last_error; }
 
 const char *comet_status_string(int status)
 {
@@ -818,7 +570,7 @@ const char *comet_status_string(int status)
 int comet_seed_grid(const double *grid, const int32_t n[4], double *seeds6, int64_t n_seeds,
                     void *stream)
 {
-    g_last_error[0] = 0;
+    clear_error();
     if (!grid || !n || !seeds6)
         return fail(COMET_EINVAL, "comet_seed_grid: NULL pointer");
     int64_t S = 1;
@@ -844,7 +596,7 @@ int comet_seed_grid(const double *grid, const int32_t n[4], double *seeds6, int6
 
 int comet_refine_grid(double *grid, const int32_t n[4], const int64_t *best, void *stream)
 {
-    g_last_error[0] = 0;
+    clear_error();
     if (!grid || !n || !best)
         return fail(COMET_EINVAL, "comet_refine_grid: NULL pointer");
     for (int a = 0; a < 4; ++a)
@@ -861,7 +613,7 @@ int comet_refine_grid(double *grid, const int32_t n[4], const int64_t *best, voi
 int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
                             double *track_xyz, void *stream)
 {
-    g_last_error[0] = 0;
+    clear_error();
     if (!seeds6 || !track_xyz)
         return fail(COMET_EINVAL, "comet_extrapolate_seeds: NULL pointer");
     if (n_seeds < 1 || n_seeds > ((int64_t)1 << 40))
@@ -889,35 +641,96 @@ size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_wires)
            align256(sizeof(double) * (size_t)n_wires * (size_t)n_seeds);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host-side checks shared by comet_dca_rss and comet_dca_autotune.
+int check_dca_args(const char *who, const double *track_xyz, int64_t n_seeds, int32_t n_points,
+                   const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                   const double *drift, int32_t n_hits, const comet_config *cfg, const double *rss,
+                   const void *workspace, size_t workspace_bytes)
+{
+    if (!track_xyz || !rss)
+        return fail(COMET_EINVAL, "%s: NULL pointer", who);
+    if (n_seeds < 1 || n_seeds > ((int64_t)1 << 40))
+        return fail(COMET_EINVAL, "%s: n_seeds = %lld", who, (long long)n_seeds);
+    if (n_wires < 0 || n_hits < 0)
+        return fail(COMET_EINVAL, "%s: negative n_wires or n_hits", who);
+    if (n_wires > 0 && (!wire_ends || !wire_offsets || (n_hits > 0 && !drift)))
+        return fail(COMET_EINVAL, "%s: NULL wire or hit array", who);
+    int st = check_config(cfg);
+    if (st)
+        return st;
+    if (n_points != cfg->n_steps + 1)
+        return fail(COMET_EINVAL, "%s: n_points %d != n_steps + 1", who, n_points);
+    if ((int64_t)(n_seeds + 63) / 64 * (int64_t)((n_wires + 15) / 16) > (int64_t)1 << 30)
+        return fail(COMET_EINVAL, "%s: problem too large for one launch", who);
+    if (n_wires > 0) {
+        const size_t need = comet_dca_workspace_bytes(n_seeds, n_wires);
+        if (!workspace || workspace_bytes < need)
+            return fail(COMET_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, workspace_bytes,
+                        need);
+        if (((uintptr_t)workspace & 255) != 0)
+            return fail(COMET_EINVAL, "%s: workspace not 256-byte aligned", who);
+    }
+    return COMET_OK;
+}
+
+double *dca_frames(void *workspace) { return (double *)workspace; }
+
+double *dca_dsq(void *workspace, int n_wires)
+{
+    return (double *)((char *)workspace + align256(sizeof(double) * 8 * (size_t)wire_pad(n_wires)));
+}
+
+int launch_frames(const double *wire_ends, int n_wires, void *workspace, hipStream_t hs)
+{
+    const int pad = wire_pad(n_wires);
+    hipLaunchKernelGGL(frame_kernel, dim3((pad + 63) / 64), dim3(64), 0, hs, wire_ends, n_wires,
+                       pad, dca_frames(workspace));
+    return launched("frame_kernel");
+}
+
+int launch_dca(int id, const double *track_xyz, int64_t n_seeds, int32_t n_points, int n_wires,
+               const int32_t *wire_offsets, const double *drift, double lambda, void *workspace,
+               hipStream_t hs)
+{
+    const DcaVariant &v = kDcaVariants[id];
+    const int per_group = v.w * v.nwv;
+    const int n_groups = (n_wires + per_group - 1) / per_group;
+    const int64_t n_tiles = (n_seeds + 63) / 64;
+    const int64_t n_blocks = n_tiles * n_groups;
+    hipLaunchKernelGGL(v.kernel, dim3((unsigned)n_blocks), dim3(64 * v.nwv), 0, hs, track_xyz,
+                       n_seeds, n_points, (const double *)dca_frames(workspace), n_wires,
+                       wire_offsets, drift, lambda, dca_dsq(workspace, n_wires), n_groups,
+                       (int)n_blocks, v.xcd_remap);
+    return launched("dca_kernel");
+}
+
+int choose_variant(int64_t S, int P, int n_w)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (g_dca_variant >= 0)
+        return g_dca_variant;
+    auto it = g_tuned.find(ShapeKey{S, P, n_w});
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
+}  // namespace
+
+extern "C" {
+
 int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
                   const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
                   const double *drift, int32_t n_hits, const comet_config *cfg, double *rss,
                   void *workspace, size_t workspace_bytes, void *stream)
 {
-    g_last_error[0] = 0;
-    if (!track_xyz || !rss)
-        return fail(COMET_EINVAL, "comet_dca_rss: NULL pointer");
-    if (n_seeds < 1 || n_seeds > ((int64_t)1 << 40))
-        return fail(COMET_EINVAL, "comet_dca_rss: n_seeds = %lld", (long long)n_seeds);
-    if (n_wires < 0 || n_hits < 0)
-        return fail(COMET_EINVAL, "comet_dca_rss: negative n_wires or n_hits");
-    if (n_wires > 0 && (!wire_ends || !wire_offsets || (n_hits > 0 && !drift)))
-        return fail(COMET_EINVAL, "comet_dca_rss: NULL wire or hit array");
-    int st = check_config(cfg);
+    clear_error();
+    int st = check_dca_args("comet_dca_rss", track_xyz, n_seeds, n_points, wire_ends, n_wires,
+                            wire_offsets, drift, n_hits, cfg, rss, workspace, workspace_bytes);
     if (st)
         return st;
-    if (n_points != cfg->n_steps + 1)
-        return fail(COMET_EINVAL, "comet_dca_rss: n_points %d != n_steps + 1", n_points);
-    if ((int64_t)(n_seeds + 63) / 64 * (int64_t)((n_wires + 63) / 64) > (int64_t)1 << 30)
-        return fail(COMET_EINVAL, "comet_dca_rss: problem too large for one launch");
-    if (n_wires > 0) {
-        const size_t need = comet_dca_workspace_bytes(n_seeds, n_wires);
-        if (!workspace || workspace_bytes < need)
-            return fail(COMET_EWORKSPACE, "comet_dca_rss: workspace %zu < %zu bytes",
-                        workspace_bytes, need);
-        if (((uintptr_t)workspace & 255) != 0)
-            return fail(COMET_EINVAL, "comet_dca_rss: workspace not 256-byte aligned");
-    }
     st = check_device();
     if (st)
         return st;
@@ -927,33 +740,88 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
                            rss, n_seeds, 0.0);
         return launched("fill_kernel");
     }
-    const int pad = wire_pad(n_wires);
-    double *frames = (double *)workspace;
-    double *dsq = (double *)((char *)workspace + align256(sizeof(double) * 8 * (size_t)pad));
-
-    hipLaunchKernelGGL(frame_kernel, dim3((pad + 63) / 64), dim3(64), 0, hs, wire_ends, n_wires,
-                       pad, frames);
-    st = launched("frame_kernel");
+    st = launch_frames(wire_ends, n_wires, workspace, hs);
     if (st)
         return st;
-
-    const DcaVariant &v = kDcaVariants[g_dca_variant];
-    const int per_group = v.w * v.nwv;
-    const int n_groups = (n_wires + per_group - 1) / per_group;
-    const int64_t n_tiles = (n_seeds + 63) / 64;
-    const int64_t n_blocks = n_tiles * n_groups;
     {
         ProfScope prof(kProfDca, hs);
-        hipLaunchKernelGGL(v.kernel, dim3((unsigned)n_blocks), dim3(64 * v.nwv), 0, hs,
-                           track_xyz, n_seeds, n_points, (const double *)frames, n_wires,
-                           wire_offsets, drift, cfg->lambda_mm, dsq, n_groups, (int)n_blocks);
-        st = launched("dca_kernel");
+        st = launch_dca(choose_variant(n_seeds, n_points, n_wires), track_xyz, n_seeds, n_points,
+                        n_wires, wire_offsets, drift, cfg->lambda_mm, workspace, hs);
     }
     if (st)
         return st;
     ProfScope prof(kProfSum, hs);
     hipLaunchKernelGGL(rss_sum_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256), 0, hs,
-                       (const double *)dsq, n_wires, n_seeds, rss);
+                       (const double *)dca_dsq(workspace, n_wires), n_wires, n_seeds, rss);
+    return launched("rss_sum_kernel");
+}
+
+int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_points,
+                       const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                       const double *drift, int32_t n_hits, const comet_config *cfg, double *rss,
+                       void *workspace, size_t workspace_bytes, int32_t reps, int32_t *best_id,
+                       double *ms, void *stream)
+{
+    clear_error();
+    int st = check_dca_args("comet_dca_autotune", track_xyz, n_seeds, n_points, wire_ends,
+                            n_wires, wire_offsets, drift, n_hits, cfg, rss, workspace,
+                            workspace_bytes);
+    if (st)
+        return st;
+    if (reps < 1 || reps > 1000)
+        return fail(COMET_EINVAL, "comet_dca_autotune: reps must be in [1, 1000]");
+    if (n_wires == 0)
+        return fail(COMET_EINVAL, "comet_dca_autotune: nothing to tune without wires");
+    st = check_device();
+    if (st)
+        return st;
+    hipStream_t hs = (hipStream_t)stream;
+    st = launch_frames(wire_ends, n_wires, workspace, hs);
+    if (st)
+        return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        return fail(COMET_EHIP, "comet_dca_autotune: hipEventCreate failed");
+    }
+    int best = -1;
+    float best_ms = 0.0f;
+    for (int id = 0; id < kNumDcaVariants && st == COMET_OK; ++id) {
+        st = launch_dca(id, track_xyz, n_seeds, n_points, n_wires, wire_offsets, drift,
+                        cfg->lambda_mm, workspace, hs);  // warm-up
+        (void)hipEventRecord(e0, hs);
+        for (int r = 0; r < reps && st == COMET_OK; ++r)
+            st = launch_dca(id, track_xyz, n_seeds, n_points, n_wires, wire_offsets, drift,
+                            cfg->lambda_mm, workspace, hs);
+        (void)hipEventRecord(e1, hs);
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(e1);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess && st == COMET_OK)
+            st = fail(COMET_EHIP, "comet_dca_autotune: %s", hipGetErrorString(e));
+        t /= (float)reps;
+        if (ms)
+            ms[id] = t;
+        if (st == COMET_OK && (best < 0 || t < best_ms)) {
+            best = id;
+            best_ms = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st)
+        return st;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[ShapeKey{n_seeds, n_points, n_wires}] = best;
+    }
+    if (best_id)
+        *best_id = best;
+    // leave rss consistent with the inputs
+    hipLaunchKernelGGL(rss_sum_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256), 0, hs,
+                       (const double *)dca_dsq(workspace, n_wires), n_wires, n_seeds, rss);
     return launched("rss_sum_kernel");
 }
 
@@ -964,7 +832,7 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
                           uint8_t *hit_mask, int32_t *n_borderline, double *dca_best,
                           void *stream)
 {
-    g_last_error[0] = 0;
+    clear_error();
     if (!rss || !best)
         return fail(COMET_EINVAL, "comet_select_classify: NULL rss or best");
     if (n_seeds < 1 || n_seeds > ((int64_t)1 << 40))
@@ -1005,66 +873,30 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
 int comet_dca_variant_count(void) { return kNumDcaVariants; }
 
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
-                           int32_t *chunk_argmin)
+                           int32_t *chunk_argmin, int32_t *xcd_remap)
 {
-    if (id < 0 || id >= kNumDcaVariants || !w || !nwv || !chunk || !chunk_argmin)
+    if (id < 0 || id >= kNumDcaVariants || !w || !nwv || !chunk || !chunk_argmin || !xcd_remap)
         return fail(COMET_EINVAL, "comet_dca_variant_info: bad id or NULL pointer");
     *w = kDcaVariants[id].w;
     *nwv = kDcaVariants[id].nwv;
     *chunk = kDcaVariants[id].c;
     *chunk_argmin = kDcaVariants[id].chunk_argmin;
+    *xcd_remap = kDcaVariants[id].xcd_remap;
     return COMET_OK;
-}
-
-int comet_profile_begin(void)
-{
-    std::lock_guard<std::mutex> lock(g_prof_mu);
-    for (auto &r : g_prof_records) {
-        g_prof_pool.push_back(r.start);
-        g_prof_pool.push_back(r.stop);
-    }
-    g_prof_records.clear();
-    g_prof_on = true;
-    return COMET_OK;
-}
-
-int comet_profile_end(double ms[COMET_PROFILE_KINDS], int64_t launches[COMET_PROFILE_KINDS])
-{
-    std::lock_guard<std::mutex> lock(g_prof_mu);
-    g_prof_on = false;
-    int status = COMET_OK;
-    for (int k = 0; k < COMET_PROFILE_KINDS; ++k) {
-        if (ms)
-            ms[k] = 0.0;
-        if (launches)
-            launches[k] = 0;
-    }
-    for (auto &r : g_prof_records) {
-        float t = 0.0f;
-        hipError_t e = hipEventSynchronize(r.stop);
-        if (e == hipSuccess)
-            e = hipEventElapsedTime(&t, r.start, r.stop);
-        if (e != hipSuccess) {
-            status = fail(COMET_EHIP, "comet_profile_end: %s", hipGetErrorString(e));
-        } else if (r.kind >= 0 && r.kind < COMET_PROFILE_KINDS) {
-            if (ms)
-                ms[r.kind] += t;
-            if (launches)
-                launches[r.kind] += 1;
-        }
-        g_prof_pool.push_back(r.start);
-        g_prof_pool.push_back(r.stop);
-    }
-    g_prof_records.clear();
-    return status;
 }
 
 int comet_dca_set_variant(int id)
 {
-    if (id < 0 || id >= kNumDcaVariants)
+    if (id < -1 || id >= kNumDcaVariants)
         return fail(COMET_EINVAL, "comet_dca_set_variant: id %d out of range", id);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
     g_dca_variant = id;
     return COMET_OK;
+}
+
+int comet_dca_variant_for(int64_t n_seeds, int32_t n_points, int32_t n_wires)
+{
+    return choose_variant(n_seeds, n_points, n_wires);
 }
 
 }  // extern "C"

@@ -23,7 +23,7 @@ def gpu():
     torch.cuda.set_device(0)
     comet.load()
     yield
-    comet.set_dca_variant(0)
+    comet.set_dca_variant(-1)
 
 
 def _n(*n):
@@ -97,7 +97,7 @@ def test_track_bitwise(orc, bz, charge, h, K):
 
 
 # ------------------------------------------------------------------ A3/A4 RSS
-@pytest.mark.parametrize("variant", range(7))
+@pytest.mark.parametrize("variant", range(12))
 def test_rss_bitwise_plain_every_variant(orc, ev_plain, variant):
     """Ragged 7x9x8x9 grid (4536 seeds, 71 tiles with a partial last tile)."""
     if variant >= len(comet.dca_variants()):
@@ -114,7 +114,7 @@ def test_rss_bitwise_plain_every_variant(orc, ev_plain, variant):
         got = rss.cpu().numpy()
         assert np.array_equal(got, want), np.max(np.abs(got - want) / want)
     finally:
-        comet.set_dca_variant(0)
+        comet.set_dca_variant(-1)
 
 
 def test_rss_signal_full_grid_sampled(orc, ev_signal):
@@ -303,3 +303,23 @@ def test_workspace_too_small_raises(ev_plain):
         comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss,
                       torch.empty(4, dtype=torch.float64, device="cuda"))
     assert ei.value.status == comet.EWORKSPACE
+
+
+def test_autotune_picks_a_shape_and_keeps_results(orc, ev_plain):
+    sc = synth.C0
+    g = synth.grid_descriptor(ev_plain.ref_states[0], sc)
+    n = _n(5, 5, 6, 7)
+    cfg = scan.config_for(ev_plain, sc)
+    seeds = gpu_seeds(g, n)
+    rss, track, dev = gpu_rss(ev_plain, seeds, cfg)
+    ws = comet.dca_workspace(seeds.shape[1], dev.n_wires)
+    rss2 = torch.empty_like(rss)
+    best, ms = comet.dca_autotune(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss2, ws,
+                                  reps=1)
+    assert 0 <= best < len(comet.dca_variants()) and len(ms) == len(comet.dca_variants())
+    assert all(m > 0 for m in ms) and ms[best] == min(ms)
+    assert comet.dca_variant_for(seeds.shape[1], sc.n_steps + 1, dev.n_wires) == best
+    assert torch.equal(rss, rss2)
+    rss3 = torch.empty_like(rss)
+    comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss3, ws)
+    assert torch.equal(rss, rss3)
