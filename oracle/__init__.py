@@ -69,6 +69,12 @@ def _bind(lib):
     lib.oracle_scan_partition.argtypes = [_d, _i32, _d, ctypes.c_int32, ctypes.c_int32, _d,
                                           ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _i32,
                                           ctypes.c_int32]
+    lib.oracle_rss_jacobian.restype = ctypes.c_double
+    lib.oracle_rss_jacobian.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _d,
+                                        _d, _d, _u8, _d]
+    lib.oracle_lm_refine.restype = ctypes.c_double
+    lib.oracle_lm_refine.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d,
+                                     ctypes.c_int32, ctypes.c_double, _i32]
     return lib
 
 
@@ -189,3 +195,27 @@ class Oracle:
                                            _p(mask, _u8), _p(nb, _i32), n_threads)
         return {"best": int(b), "grid": g, "rss": rss, "best_seed": best_seed,
                 "best_rss": float(best_rss[0]), "mask": mask, "n_borderline": int(nb[0])}
+
+    def rss_jacobian(self, seed, cfg, K, wire_ends, offsets, drift):
+        """Dual-number derivatives: dict(rss, grad[6], D[n_w], J[n_w, 6], resid[n_w], active)."""
+        ends = _f64(wire_ends).reshape(-1, 6)
+        n_w = ends.shape[0]
+        D = np.empty(n_w)
+        J = np.empty((n_w, 6))
+        e = np.empty(n_w)
+        act = np.zeros(n_w, dtype=np.uint8)
+        grad = np.empty(6)
+        rss = self.lib.oracle_rss_jacobian(_p(_f64(seed)), _p(_f64(cfg)), K, _p(ends), n_w,
+                                           _p(_i32a(offsets), _i32), _p(_f64(drift)), _p(D),
+                                           _p(J), _p(e), _p(act, _u8), _p(grad))
+        return {"rss": rss, "grad": grad, "D": D, "J": J, "resid": e, "active": act.astype(bool)}
+
+    def lm_refine(self, seed, cfg, K, wire_ends, offsets, drift, n_iter, mu0):
+        """Levenberg-Marquardt refinement of one seed: (seed[6], rss, accepted steps)."""
+        s = _f64(seed).copy()
+        ends = _f64(wire_ends).reshape(-1, 6)
+        acc = np.zeros(1, dtype=np.int32)
+        rss = self.lib.oracle_lm_refine(_p(s), _p(_f64(cfg)), K, _p(ends), ends.shape[0],
+                                        _p(_i32a(offsets), _i32), _p(_f64(drift)), n_iter,
+                                        float(mu0), _p(acc, _i32))
+        return s, rss, int(acc[0])

@@ -458,3 +458,354 @@ int64_t oracle_scan_partition(double grid[14], const int32_t n[4], const double 
         free(rss);
     return b;
 }
+
+/* ------------------------------------------------------------ derivatives
+ * Forward-mode dual numbers: every quantity carries its value and its derivatives
+ * with respect to the six seed components (x, y, z, px, py, pz). The value parts are
+ * computed with exactly the operations above, so closest points, chords and hits
+ * are chosen as in the plain functions; the derivative parts follow the chain rule
+ * of each operation. This is the oracle of the GPU adjoint (reverse mode), which
+ * shares nothing with it but the mathematics. */
+typedef struct {
+    double v;
+    double d[6];
+} dual;
+
+static dual dc(double v)
+{
+    dual r;
+    r.v = v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = 0.0;
+    return r;
+}
+
+static dual dvar(double v, int i)
+{
+    dual r = dc(v);
+    r.d[i] = 1.0;
+    return r;
+}
+
+static dual dadd(dual a, dual b)
+{
+    dual r;
+    r.v = a.v + b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = a.d[i] + b.d[i];
+    return r;
+}
+
+static dual dsub(dual a, dual b)
+{
+    dual r;
+    r.v = a.v - b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = a.d[i] - b.d[i];
+    return r;
+}
+
+static dual dneg(dual a)
+{
+    dual r;
+    r.v = -a.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = -a.d[i];
+    return r;
+}
+
+static dual dmul(dual a, dual b)
+{
+    dual r;
+    r.v = a.v * b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+    return r;
+}
+
+static dual ddiv(dual a, dual b)
+{
+    dual r;
+    r.v = a.v / b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
+    return r;
+}
+
+static dual dsqrt(dual a)
+{
+    dual r;
+    r.v = sqrt(a.v);
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = r.v > 0.0 ? a.d[i] / (2.0 * r.v) : 0.0;
+    return r;
+}
+
+/* fma(a, b, c): value rounded once, derivative a' b + a b' + c' */
+static dual dfma(dual a, dual b, dual c)
+{
+    dual r;
+    r.v = fma(a.v, b.v, c.v);
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = a.d[i] * b.v + a.v * b.d[i] + c.d[i];
+    return r;
+}
+
+/* RK4 track of the seed in dual numbers; pts: [K+1][3] duals. */
+static void dual_track(const double seed[6], double bz, double charge, double h, int32_t K,
+                       dual *pts)
+{
+    dual x = dvar(seed[0], 0), y = dvar(seed[1], 1), z = dvar(seed[2], 2);
+    dual px = dvar(seed[3], 3), py = dvar(seed[4], 4), pz = dvar(seed[5], 5);
+    dual p0 = dsqrt(dadd(dadd(dmul(px, px), dmul(py, py)), dmul(pz, pz)));
+    dual inv = ddiv(dc(1.0), p0);
+    dual c = dmul(dc((ORACLE_KAPPA * charge) * bz), inv);
+    dual hh = dc(0.5 * h), hd = dc(h), h6 = dc(h / 6.0), two = dc(2.0);
+    dual vz = dmul(pz, inv);
+    for (int32_t k = 0; k < K; ++k) {
+        pts[3 * k + 0] = x;
+        pts[3 * k + 1] = y;
+        pts[3 * k + 2] = z;
+        dual v1x = dmul(px, inv), v1y = dmul(py, inv);
+        dual f1x = dmul(c, py), f1y = dneg(dmul(c, px));
+        dual qx = dadd(px, dmul(hh, f1x)), qy = dadd(py, dmul(hh, f1y));
+        dual v2x = dmul(qx, inv), v2y = dmul(qy, inv);
+        dual f2x = dmul(c, qy), f2y = dneg(dmul(c, qx));
+        qx = dadd(px, dmul(hh, f2x));
+        qy = dadd(py, dmul(hh, f2y));
+        dual v3x = dmul(qx, inv), v3y = dmul(qy, inv);
+        dual f3x = dmul(c, qy), f3y = dneg(dmul(c, qx));
+        qx = dadd(px, dmul(hd, f3x));
+        qy = dadd(py, dmul(hd, f3y));
+        dual v4x = dmul(qx, inv), v4y = dmul(qy, inv);
+        dual f4x = dmul(c, qy), f4y = dneg(dmul(c, qx));
+        x = dadd(x, dmul(h6, dadd(dadd(dadd(v1x, dmul(two, v2x)), dmul(two, v3x)), v4x)));
+        y = dadd(y, dmul(h6, dadd(dadd(dadd(v1y, dmul(two, v2y)), dmul(two, v3y)), v4y)));
+        z = dadd(z, dmul(h6, dadd(dadd(dadd(vz, dmul(two, vz)), dmul(two, vz)), vz)));
+        px = dadd(px, dmul(h6, dadd(dadd(dadd(f1x, dmul(two, f2x)), dmul(two, f3x)), f4x)));
+        py = dadd(py, dmul(h6, dadd(dadd(dadd(f1y, dmul(two, f2y)), dmul(two, f3y)), f4y)));
+    }
+    pts[3 * K + 0] = x;
+    pts[3 * K + 1] = y;
+    pts[3 * K + 2] = z;
+}
+
+static void dual_project(const double f[8], const dual *p, dual *xi, dual *eta)
+{
+    *xi = dfma(dc(f[0]), p[0], dfma(dc(f[1]), p[1], dfma(dc(f[2]), p[2], dc(f[3]))));
+    *eta = dfma(dc(f[4]), p[0], dfma(dc(f[5]), p[1], dfma(dc(f[6]), p[2], dc(f[7]))));
+}
+
+static dual dual_chord(dual axi, dual aeta, dual qa, dual bxi, dual beta, dual qb)
+{
+    dual uxi = dsub(bxi, axi), ueta = dsub(beta, aeta);
+    dual g = dfma(axi, uxi, dmul(aeta, ueta));
+    dual den = dfma(uxi, uxi, dmul(ueta, ueta));
+    if (!(g.v < 0.0))
+        return qa;
+    if (-g.v >= den.v)
+        return qb;
+    dual t = ddiv(dneg(g), den);
+    dual pxi = dfma(t, uxi, axi), peta = dfma(t, ueta, aeta);
+    return dfma(pxi, pxi, dmul(peta, peta));
+}
+
+/* The squared DCA of one wire in dual numbers (same choices as oracle_dca2). */
+static dual dual_dca2(const dual *pts, int32_t P, const double frame[8])
+{
+    int32_t kb = 0;
+    double qbv = INFINITY;
+    for (int32_t k = 0; k < P; ++k) {
+        double xi, eta;
+        double pv[3] = {pts[3 * k].v, pts[3 * k + 1].v, pts[3 * k + 2].v};
+        project(frame, pv, &xi, &eta);
+        double q = fma(xi, xi, eta * eta);
+        if (q < qbv) {
+            qbv = q;
+            kb = k;
+        }
+    }
+    dual cxi, ceta;
+    dual_project(frame, pts + 3 * kb, &cxi, &ceta);
+    dual qb = dfma(cxi, cxi, dmul(ceta, ceta));
+    dual d2 = qb;
+    if (kb > 0) {
+        dual xi, eta;
+        dual_project(frame, pts + 3 * (kb - 1), &xi, &eta);
+        dual q = dfma(xi, xi, dmul(eta, eta));
+        dual v = dual_chord(xi, eta, q, cxi, ceta, qb);
+        if (v.v < d2.v)
+            d2 = v;
+    }
+    if (kb < P - 1) {
+        dual xi, eta;
+        dual_project(frame, pts + 3 * (kb + 1), &xi, &eta);
+        dual q = dfma(xi, xi, dmul(eta, eta));
+        dual v = dual_chord(cxi, ceta, qb, xi, eta, q);
+        if (v.v < d2.v)
+            d2 = v;
+    }
+    return d2;
+}
+
+/* Per wire: D_i and its derivatives J_i = dD_i/d(seed) [n_w][6], the signed residual
+ * e_i = D_i - r_j of the wire's closest hit (NaN without hits) and whether it is
+ * active (|e_i| < lambda). Returns the RSS of Eq. 1 and writes its gradient
+ * sum over active wires of 2 e_i J_i to grad[6]. Any output pointer may be NULL. */
+double oracle_rss_jacobian(const double seed[6], const double cfg[4], int32_t K,
+                           const double *wire_ends, int32_t n_wires, const int32_t *offsets,
+                           const double *drift, double *D, double *J, double *resid,
+                           uint8_t *active, double grad[6])
+{
+    dual *pts = (dual *)malloc(sizeof(dual) * 3 * (size_t)(K + 1));
+    dual_track(seed, cfg[0], cfg[1], cfg[2], K, pts);
+    double lambda = cfg[3];
+    double rss = 0.0;
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t i = 0; i < n_wires; ++i) {
+        double frame[8];
+        oracle_wire_frame(wire_ends + 6 * i, frame);
+        dual Dd = dsqrt(dual_dca2(pts, K + 1, frame));
+        double e = NAN, eb = INFINITY;
+        for (int32_t j = offsets[i]; j < offsets[i + 1]; ++j) {
+            double a = fabs(Dd.v - drift[j]);
+            if (a < eb) {
+                eb = a;
+                e = Dd.v - drift[j];
+            }
+        }
+        double d = eb < lambda ? eb : lambda;
+        rss = rss + d * d;
+        int act = eb < lambda;
+        if (act)
+            for (int c = 0; c < 6; ++c)
+                g[c] += 2.0 * e * Dd.d[c];
+        if (D)
+            D[i] = Dd.v;
+        if (J)
+            for (int c = 0; c < 6; ++c)
+                J[6 * i + c] = Dd.d[c];
+        if (resid)
+            resid[i] = e;
+        if (active)
+            active[i] = (uint8_t)act;
+    }
+    if (grad)
+        for (int c = 0; c < 6; ++c)
+            grad[c] = g[c];
+    free(pts);
+    return rss;
+}
+
+/* ------------------------------------------------------------ Gauss-Newton / LM
+ * Refinement of one seed by Levenberg-Marquardt on the active residuals e_i
+ * (|e_i| < lambda) with rows J_i: A = sum J_i J_i^T, b = sum J_i e_i; the step solves
+ * (A + mu diag(A)) delta = -b by Cholesky; it is accepted when the RSS of Eq. 1
+ * decreases (then mu <- mu / 10 and A, b are re-formed), otherwise mu <- 10 mu. A
+ * matrix that is not positive definite counts as a rejected step. n_iter steps. */
+static void normal_equations(const double seed[6], const double cfg[4], int32_t K,
+                             const double *wire_ends, int32_t n_wires, const int32_t *offsets,
+                             const double *drift, double A[36], double b[6], double *rss)
+{
+    double *J = (double *)malloc(sizeof(double) * 6 * (size_t)(n_wires > 0 ? n_wires : 1));
+    double *e = (double *)malloc(sizeof(double) * (size_t)(n_wires > 0 ? n_wires : 1));
+    uint8_t *act = (uint8_t *)malloc((size_t)(n_wires > 0 ? n_wires : 1));
+    *rss = oracle_rss_jacobian(seed, cfg, K, wire_ends, n_wires, offsets, drift, NULL, J, e,
+                               act, NULL);
+    for (int r = 0; r < 36; ++r)
+        A[r] = 0.0;
+    for (int r = 0; r < 6; ++r)
+        b[r] = 0.0;
+    for (int32_t i = 0; i < n_wires; ++i) {
+        if (!act[i])
+            continue;
+        for (int r = 0; r < 6; ++r) {
+            b[r] += J[6 * i + r] * e[i];
+            for (int c = 0; c < 6; ++c)
+                A[6 * r + c] += J[6 * i + r] * J[6 * i + c];
+        }
+    }
+    free(J);
+    free(e);
+    free(act);
+}
+
+/* Solves M x = r for symmetric positive definite M (6x6) by Cholesky; 0 if M is not
+ * positive definite. */
+static int cholesky_solve6(const double M[36], const double r[6], double x[6])
+{
+    double L[36] = {0};
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = M[6 * i + j];
+            for (int k = 0; k < j; ++k)
+                s -= L[6 * i + k] * L[6 * j + k];
+            if (i == j) {
+                if (!(s > 0.0))
+                    return 0;
+                L[6 * i + i] = sqrt(s);
+            } else {
+                L[6 * i + j] = s / L[6 * j + j];
+            }
+        }
+    }
+    double y[6];
+    for (int i = 0; i < 6; ++i) {
+        double s = r[i];
+        for (int k = 0; k < i; ++k)
+            s -= L[6 * i + k] * y[k];
+        y[i] = s / L[6 * i + i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < 6; ++k)
+            s -= L[6 * k + i] * x[k];
+        x[i] = s / L[6 * i + i];
+    }
+    return 1;
+}
+
+/* Refines seed[6] in place; returns the final RSS; *accepted counts accepted steps. */
+double oracle_lm_refine(double seed[6], const double cfg[4], int32_t K, const double *wire_ends,
+                        int32_t n_wires, const int32_t *offsets, const double *drift,
+                        int32_t n_iter, double mu0, int32_t *accepted)
+{
+    double A[36], b[6], rss;
+    normal_equations(seed, cfg, K, wire_ends, n_wires, offsets, drift, A, b, &rss);
+    double mu = mu0;
+    int32_t n_acc = 0;
+    for (int32_t it = 0; it < n_iter; ++it) {
+        double M[36], rhs[6], delta[6];
+        for (int r = 0; r < 36; ++r)
+            M[r] = A[r];
+        for (int r = 0; r < 6; ++r) {
+            M[6 * r + r] = A[6 * r + r] + mu * A[6 * r + r];
+            rhs[r] = -b[r];
+        }
+        if (!cholesky_solve6(M, rhs, delta)) {
+            mu = mu * 10.0;
+            continue;
+        }
+        double trial[6];
+        for (int r = 0; r < 6; ++r)
+            trial[r] = seed[r] + delta[r];
+        double A2[36], b2[6], rss2;
+        normal_equations(trial, cfg, K, wire_ends, n_wires, offsets, drift, A2, b2, &rss2);
+        if (rss2 < rss) {
+            for (int r = 0; r < 6; ++r) {
+                seed[r] = trial[r];
+                b[r] = b2[r];
+            }
+            for (int r = 0; r < 36; ++r)
+                A[r] = A2[r];
+            rss = rss2;
+            mu = mu / 10.0;
+            n_acc += 1;
+        } else {
+            mu = mu * 10.0;
+        }
+    }
+    if (accepted)
+        *accepted = n_acc;
+    return rss;
+}

@@ -106,8 +106,10 @@ def turn_length(state0, charge: float, bz: float) -> float:
 def _line_distance(pts, a, u):
     """Distance from points [..., 3] to the infinite lines through a with unit direction u."""
     d = pts - a
-    cr = np.cross(d, u)
-    return np.sqrt(np.sum(cr * cr, axis=-1))
+    cx = d[..., 1] * u[..., 2] - d[..., 2] * u[..., 1]
+    cy = d[..., 2] * u[..., 0] - d[..., 0] * u[..., 2]
+    cz = d[..., 0] * u[..., 1] - d[..., 1] * u[..., 0]
+    return np.sqrt(cx * cx + cy * cy + cz * cz)
 
 
 def _outward_crossing(state0, charge, bz, s_len, radius=SEED_RADIUS, ds=0.5):
@@ -147,11 +149,18 @@ def helix_hits(state0, charge: float, bz: float, s_len: float, ds: float = 0.5):
         sel = np.nonzero(np.abs(r - rl) < 20.0)[0]
         if sel.size == 0:
             continue
-        w_ids = np.arange(layer * WIRES_PER_LAYER, (layer + 1) * WIRES_PER_LAYER)
+        # only wires whose azimuth at the samples' heights lies near the samples
+        a_st = STEREO if layer % 2 == 0 else -STEREO
+        shift = np.tan(a_st) * pos[sel, 2] / rl
+        cell = 2.0 * np.pi / WIRES_PER_LAYER
+        centre = (np.arctan2(pos[sel, 1], pos[sel, 0]) - shift) / cell - 0.5 * (layer % 2)
+        near = (np.round(centre)[:, None].astype(np.int64) + np.arange(-4, 5)[None]) % WIRES_PER_LAYER
+        w_local = np.unique(near)
+        w_ids = layer * WIRES_PER_LAYER + w_local
         a = wires[w_ids, :3]
         u = wires[w_ids, 3:] - a
         u = u / np.linalg.norm(u, axis=1, keepdims=True)
-        dist = _line_distance(pos[sel][:, None, :], a[None], u[None])  # [n_sel, 320]
+        dist = _line_distance(pos[sel][:, None, :], a[None], u[None])  # [n_sel, n_near]
         # local minima along contiguous runs of selected samples
         n = sel.size
         contig_prev = np.zeros(n, dtype=bool)
@@ -186,7 +195,7 @@ def helix_hits(state0, charge: float, bz: float, s_len: float, ds: float = 0.5):
     c = hi - g * (hi - lo)
     d = lo + g * (hi - lo)
     fc, fd = f(c), f(d)
-    for _ in range(70):
+    for _ in range(48):
         left = fc < fd
         hi = np.where(left, d, hi)
         lo = np.where(left, lo, c)
@@ -366,3 +375,65 @@ def event_signal(seed: int = 0, sigma: float = 0.2) -> Event:
     az = rng.uniform(0.0, 2.0 * np.pi)
     st = vertex_state(104.0, polar, az, vertex=(0.0, 0.0, -650.0))
     return make_event(st, 3, rng, sigma=sigma, noise_per_signal=0.10)
+
+
+# ---------------------------------------------------------------- batched event mix
+def entry_state(p: float, pz: float, r_max: float, psi: float, z0: float, charge: float = -1.0,
+                bz: float = 1.0) -> np.ndarray:
+    """Start state on the innermost point of a transverse circle.
+
+    The circle has radius R = p_T / (KAPPA |q| B) and its centre sits at distance
+    r_max - R from the axis in direction psi, so the track's largest radius is r_max.
+    The start point is the circle's point closest to the axis, with the momentum
+    tangent to the circle in the sense the field turns it.
+    """
+    pt = np.sqrt(p * p - pz * pz)
+    R = pt / (KAPPA * abs(charge) * bz)
+    d = r_max - R
+    u = np.array([np.cos(psi), np.sin(psi)])
+    pos = (d - R) * u
+    # counter-clockwise (seen from +z) for q B < 0, clockwise otherwise
+    sense = 1.0 if charge * bz < 0 else -1.0
+    tang = sense * np.array([u[1], -u[0]])
+    return np.array([pos[0], pos[1], z0, pt * tang[0], pt * tang[1], pz])
+
+
+def event_mix(seed: int, sigma: float = 0.2, noise_frac: float = 0.20, turns=(1, 5),
+              hits=(40, 400), p_range=(60.0, 105.0), max_tries: int = 200) -> Event:
+    """One event of the batched mix (falling momentum spectrum, 1-5 turns, 20 % noise).
+
+    |p| follows (105 - p)^5 on [60, 105] MeV/c; P ~ U{turns}; p_z ~ U[0.3, 1] x 66.8 / P
+    MeV/c so that P turns fit in the chamber; the largest track radius ~ U[560, 830] mm;
+    the track starts at its innermost point at z = -700 mm (plus a small offset) and
+    must cross r = 500 mm outward in every turn. Noise hits make up `noise_frac` of all
+    hits. Drawn again until the hit count lies in `hits`.
+    """
+    rng = np.random.default_rng([seed, 7])
+    lo, hi = p_range
+    for _ in range(max_tries):
+        p = hi - (hi - lo) * rng.uniform() ** (1.0 / 6.0)
+        n_turns = int(rng.integers(turns[0], turns[1] + 1))
+        pz = rng.uniform(0.3, 1.0) * 66.8 / n_turns
+        if pz >= p:
+            continue
+        r_max = rng.uniform(560.0, 830.0)
+        R = np.sqrt(p * p - pz * pz) / KAPPA
+        if r_max - 2.0 * R > 480.0 or r_max - R < 0.0:
+            continue  # never comes inside the seed radius
+        st = entry_state(p, pz, r_max, rng.uniform(0.0, 2.0 * np.pi), -700.0 + rng.uniform(0, 40))
+        try:
+            ev = make_event(st, n_turns, rng, sigma=sigma,
+                            noise_per_signal=noise_frac / (1.0 - noise_frac))
+        except ValueError:
+            continue
+        if hits[0] <= ev.n_hits <= hits[1] and ev.meta["n_signal"] > 0:
+            ev.meta.update(p=float(p), n_turns=n_turns, r_max=float(r_max), seed=seed)
+            return ev
+    raise RuntimeError("event_mix(%d): no event within %s hits" % (seed, hits))
+
+
+# Batched mix: 32768 seeds per partition (8 x 16 x 16 x 16), 1000 x 2 mm, lambda 0.8 mm.
+C2 = ScanConfig("mix-batched", (8, 16, 16, 16), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8)
+# Differentiation workload: coarse 8^4 grid (then Gauss-Newton) vs fine 32^4 grid.
+C3_COARSE = ScanConfig("mix-coarse", (8, 8, 8, 8), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)
+C3_FINE = ScanConfig("mix-fine", (32, 32, 32, 32), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)

@@ -378,3 +378,104 @@ def pin_brute_force(o, ev, lam=1.0, K=1000, h=2.0):
 ALL_SIMPLE = [pin_rk4_closed_form, pin_rk4_helix, pin_frame, pin_dca_hand, pin_residual,
               pin_classify, pin_argmin, pin_grid, pin_refine]
 ALL_EVENT = [pin_far_seed, pin_truth_seed, pin_grid_argmin, pin_rotation, pin_brute_force]
+
+
+# ------------------------------------------------------------------ derivatives
+def _kink_free(o, seed, ev, cfg, K, margin=2e-3):
+    """True when no active residual is within `margin` of lambda or of a hit switch, and
+    no wire's refinement point sits within 1e-3 of a chord end (a kink of the polyline)."""
+    r = o.rss_jacobian(seed, cfg, K, ev.wire_ends, ev.wire_offsets, ev.drift)
+    lam = cfg[3]
+    for i in range(ev.n_wires):
+        j0, j1 = ev.wire_offsets[i], ev.wire_offsets[i + 1]
+        e = np.sort(np.abs(r["D"][i] - ev.drift[j0:j1]))
+        if abs(e[0] - lam) < margin or (len(e) > 1 and e[1] - e[0] < margin):
+            return False
+    return True
+
+
+def _fd(f, seed, rel=1e-6):
+    g = []
+    for c in range(6):
+        h = rel * max(abs(seed[c]), 1.0)
+        sp, sm = seed.copy(), seed.copy()
+        sp[c] += h
+        sm[c] -= h
+        g.append((f(sp) - f(sm)) / (2 * h))
+    return np.array(g)
+
+
+def pin_gradient_fd(o, ev, lam=1.0, K=1000, h=2.0):
+    """Dual-number RSS gradient and per-wire DCA rows vs central differences (1e-7)."""
+    cfg = [ev.bz, ev.charge, h, lam]
+    rng = np.random.default_rng(5)
+    tested = 0
+    for _ in range(12):
+        seed = ev.ref_states[0] * (1 + rng.normal(0, 2e-3, 6))
+        if not _kink_free(o, seed, ev, cfg, K):
+            continue
+        r = o.rss_jacobian(seed, cfg, K, ev.wire_ends, ev.wire_offsets, ev.drift)
+
+        def rss(s):
+            return o.rss_track(o.track(s, ev.bz, ev.charge, h, K), ev.wire_ends, ev.wire_offsets,
+                               ev.drift, lam)
+        fd = _fd(rss, seed)
+        scale = np.max(np.abs(r["grad"]))
+        assert np.max(np.abs(r["grad"] - fd)) < 1e-7 * scale, ("RSS gradient vs FD", r["grad"], fd)
+        near = np.nonzero(r["D"] < 9.0)[0][:6]
+        for i in near:
+            ends = ev.wire_ends[i]
+            f = o.wire_frame(ends)
+
+            def dca(s):
+                return np.sqrt(o.dca2(o.track(s, ev.bz, ev.charge, h, K), f)[0])
+            fdi = _fd(dca, seed)
+            sc = np.max(np.abs(r["J"][i]))
+            assert np.max(np.abs(r["J"][i] - fdi)) < 1e-7 * sc, ("DCA row vs FD", i)
+        tested += 1
+        if tested == 3:
+            break
+    assert tested >= 2, "too few kink-free test points"
+
+
+def pin_jacobian_straight(o):
+    """B = 0: a straight track in the xy plane past a wire along z at (5, 0):
+    D = |(x0 - 5) p_y - y0 p_x| / p_T, so dD/dx0 = -p_y/p_T, dD/dy0 = p_x/p_T,
+    dD/dz0 = 0, dD/dp_x = (-y0 - D dp_T/dp_x ...) in closed form below, dD/dp_z = 0."""
+    x0, y0 = 0.3, -90.0
+    px, py = 0.02, 1.0
+    seed = np.array([x0, y0, 0.0, px, py, 0.0])
+    cfg = [0.0, -1.0, 3.0, 2.0]
+    ends = np.array([[5.0, 0.0, -750.0, 5.0, 0.0, 750.0]])
+    r = o.rss_jacobian(seed, cfg, 60, ends, np.array([0, 1], np.int32), np.array([4.0]))
+    pt = np.hypot(px, py)
+    num = (x0 - 5.0) * py - y0 * px
+    D = abs(num) / pt
+    sgn = np.sign(num)
+    want = np.array([sgn * py / pt, -sgn * px / pt, 0.0,
+                     sgn * (-y0) / pt - D * px / pt ** 2,
+                     sgn * (x0 - 5.0) / pt - D * py / pt ** 2, 0.0])
+    assert abs(r["D"][0] - D) < 1e-12, ("straight D", r["D"][0], D)
+    assert np.max(np.abs(r["J"][0] - want)) < 1e-12, ("straight J", r["J"][0], want)
+    assert r["active"][0] and abs(r["resid"][0] - (D - 4.0)) < 1e-12
+
+
+def pin_lm_truth(o, ev_exact, lam=1.0, K=1000, h=2.0):
+    """sigma = 0: Levenberg-Marquardt from a perturbed truth seed recovers |p| of the
+    truth to 5e-3 MeV/c and never raises the RSS. (The fit absorbs the chords' sagitta,
+    h^2 / 8R ~ 1.7 um, which moves |p| by ~1e-3 MeV/c; the fine grid's spacing is 0.3.)"""
+    cfg = [ev_exact.bz, ev_exact.charge, h, lam]
+    truth = ev_exact.ref_states[0]
+    start = truth * np.array([1.0, 1.0, 1.0, 1.002, 0.998, 1.003])
+    start[0] += 0.2
+    pts = o.track(start, ev_exact.bz, ev_exact.charge, h, K)
+    rss0 = o.rss_track(pts, ev_exact.wire_ends, ev_exact.wire_offsets, ev_exact.drift, lam)
+    s, rss, acc = o.lm_refine(start, cfg, K, ev_exact.wire_ends, ev_exact.wire_offsets,
+                              ev_exact.drift, 12, 1e-3)
+    assert rss <= rss0 and acc >= 1
+    assert abs(np.linalg.norm(s[3:]) - np.linalg.norm(truth[3:])) < 5e-3, (s, truth)
+    assert rss < 1e-4, rss
+
+
+ALL_SIMPLE.append(pin_jacobian_straight)
+ALL_EVENT.extend([pin_gradient_fd, pin_lm_truth])

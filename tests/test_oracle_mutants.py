@@ -33,14 +33,20 @@ MUTANTS = {
     "chord_t_sign": ("double t = -g / den;", "double t = g / den;"),
     "chord_wrong_base_point": ("double pxi = fma(t, uxi, axi), peta = fma(t, ueta, aeta);", "double pxi = fma(t, uxi, bxi), peta = fma(t, ueta, aeta);"),
     "chord_den_missing_term": ("double den = fma(uxi, uxi, ueta * ueta);", "double den = uxi * uxi;"),
-    "drop_previous_chord": ("    if (kb > 0) {", "    if (0) {"),
-    "drop_next_chord": ("    if (kb < P - 1) {", "    if (0) {"),
+    "drop_previous_chord": ("    if (kb > 0) {\n        double xi, eta;", "    if (0) {\n        double xi, eta;"),
+    "drop_next_chord": ("    if (kb < P - 1) {\n        double xi, eta;", "    if (0) {\n        double xi, eta;"),
     "residual_uncapped": ("    double d = lambda;\n    for (int32_t j = j0;", "    double d = INFINITY;\n    for (int32_t j = j0;"),
     "residual_signed": ("double e = fabs(D - drift[j]);\n        if (e < d)", "double e = (D - drift[j]);\n        if (e < d)"),
-    "rss_not_squared": ("rss = rss + d * d;", "rss = rss + d;"),
+    "rss_not_squared": ("lambda);\n        rss = rss + d * d;", "lambda);\n        rss = rss + d;"),
     "classify_not_strict": ("if (eb < cfg[3])", "if (eb <= cfg[3])"),
     "classify_last_tie": ("            if (e < eb) {\n                eb = e;", "            if (e <= eb) {\n                eb = e;"),
     "argmin_last_tie": ("if (rss[s] < v || (b < 0 && rss[s] == v)) {", "if (rss[s] <= v) {"),
+    "dual_mul_drops_term": ("        r.d[i] = a.d[i] * b.v + a.v * b.d[i];\n    return r;\n}\n\nstatic dual ddiv", "        r.d[i] = a.d[i] * b.v;\n    return r;\n}\n\nstatic dual ddiv"),
+    "dual_sqrt_factor": ("r.d[i] = r.v > 0.0 ? a.d[i] / (2.0 * r.v) : 0.0;", "r.d[i] = r.v > 0.0 ? a.d[i] / (r.v) : 0.0;"),
+    "dual_grad_sign": ("g[c] += 2.0 * e * Dd.d[c];", "g[c] -= 2.0 * e * Dd.d[c];"),
+    "dual_fma_drops_c": ("r.d[i] = a.d[i] * b.v + a.v * b.d[i] + c.d[i];", "r.d[i] = a.d[i] * b.v + a.v * b.d[i];"),
+    "lm_accepts_worse": ("        if (rss2 < rss) {\n            for (int r = 0; r < 6; ++r) {", "        if (rss2 > rss) {\n            for (int r = 0; r < 6; ++r) {"),
+    "lm_gradient_sign": ("            rhs[r] = -b[r];", "            rhs[r] = b[r];"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
@@ -54,10 +60,11 @@ def _run_all_pins(o, ev, ev_exact):
             failed.append(check.__name__)
     for check, e in [(pins.pin_far_seed, ev), (pins.pin_truth_seed, ev_exact),
                      (pins.pin_grid_argmin, ev_exact), (pins.pin_rotation, ev),
-                     (pins.pin_brute_force, ev)]:
+                     (pins.pin_brute_force, ev), (pins.pin_gradient_fd, ev),
+                     (pins.pin_lm_truth, ev_exact)]:
         try:
             check(o, e)
-        except AssertionError:
+        except (AssertionError, ValueError, FloatingPointError):
             failed.append(check.__name__)
     return failed
 

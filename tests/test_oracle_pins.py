@@ -43,3 +43,11 @@ def test_scan_threads_deterministic(orc, ev_signal):
                          ev_signal.drift, n_threads=4)
     assert used1 == 1
     assert np.array_equal(r1, r4)
+
+
+def test_gradient_vs_central_differences(orc, ev_plain):
+    pins.pin_gradient_fd(orc, ev_plain)
+
+
+def test_lm_recovers_truth(orc, ev_plain_exact):
+    pins.pin_lm_truth(orc, ev_plain_exact)
