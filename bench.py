@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -100,6 +102,44 @@ def cpu_baseline(ev, sc, target_s: float):
                       (m, ev.n_hits, ev.n_wires)}
 
 
+def bench_batch(events, sc, reps: int = 2):
+    """Every partition of `events` through the batched path, captured in a HIP graph."""
+    import torch
+    from paper_1911_09340_amd import comet, scan
+    runner = scan.BatchRunner(events, sc)
+    runner.capture()
+    runner.replay()
+    torch.cuda.synchronize()
+    comet.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        runner.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    prof = comet.profile_end()  # graph replays record no events; eager run below
+    comet.profile_begin()
+    runner.run()
+    torch.cuda.synchronize()
+    prof = comet.profile_end()
+    pw = 0
+    hits = [ev.n_hits for ev in events]
+    for e, ev in enumerate(events):
+        pw += ev.n_turns * ev.n_wires
+    scans = sc.n_refine + 1
+    flops = FLOP_PER_POINT_WIRE * sc.n_seeds * (sc.n_steps + 1) * pw * scans
+    scan_ms = prof["dca"][0]
+    return {"events": len(events), "partitions": runner.n_part, "seeds_per_partition": sc.n_seeds,
+            "scans_per_partition": scans, "rk4_steps": sc.n_steps,
+            "hits_min_mean_max": [min(hits), float(np.mean(hits)), max(hits)],
+            "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "evals_per_s": runner.evals_per_run / dt,
+            "scan_kernel_ms_per_run": scan_ms,
+            "scan_fp64_tflops": flops / (scan_ms * 1e-3) / 1e12,
+            "scan_fp64_frac": flops / (scan_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "graph": "one HIP graph per run (frames, per scan: refine, counter reset, "
+                     "persistent scan, argmin; classification)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +150,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--batch-events", type=int, default=64,
+                    help="events of the batched mix timed through the persistent batched path "
+                         "(0 = skip; 1024 = the full batching workload)")
+    ap.add_argument("--grad-events", type=int, default=32,
+                    help="events of the batched mix for the coarse+LM vs fine-grid comparison "
+                         "(0 = skip; 256 = the full differentiation workload)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -118,6 +164,17 @@ def main():
               "(--gpus 1); multi-GPU sharding is described in DESIGN.md, not run.",
               file=sys.stderr)
         sys.exit(2)
+
+    # events for the gradient comparison are drawn before the GPU is touched, so that
+    # worker processes can be forked safely
+    grad_events, batch_events = [], []
+    n_mix = max(args.grad_events, args.batch_events)
+    if n_mix > 0 and not args.calibrate_copy:
+        from paper_1911_09340_amd import synth as _synth
+        t0 = time.perf_counter()
+        mix = _synth.event_mix_batch(range(n_mix), workers=min(16, os.cpu_count() or 1))
+        grad_events, batch_events = mix[:args.grad_events], mix[:args.batch_events]
+        log("drew %d mix events in %.1f s" % (len(mix), time.perf_counter() - t0))
 
     import torch
     from paper_1911_09340_amd import comet, scan, synth
@@ -238,6 +295,21 @@ def main():
         },
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
     }
+    if batch_events:
+        log("batched mix: %d events, persistent scans, HIP graph ..." % len(batch_events))
+        out["batch"] = bench_batch(batch_events, synth.C2)
+        log("  %.1f events/s, %.3g seed x hit evals/s, scan kernel %.1f %% of FP64 peak"
+            % (out["batch"]["events_per_s"], out["batch"]["evals_per_s"],
+               100 * out["batch"]["scan_fp64_frac"]))
+    if grad_events:
+        from paper_1911_09340_amd import refine
+        log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))
+        out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE)
+        g = out["grad_refine"]
+        log("  coarse+LM %.2f s, |p| residual rms %.3f core %.3f MeV/c; fine grid %.2f s, rms %.3f "
+            "core %.3f" % (g["coarse_lm"]["seconds"], g["coarse_lm"]["rms"],
+                           g["coarse_lm"]["core_sigma"], g["fine_grid"]["seconds"],
+                           g["fine_grid"]["rms"], g["fine_grid"]["core_sigma"]))
     if not args.no_cpu_baseline:
         log("CPU reference baseline (~%.0f s) ..." % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(ev, sc, args.cpu_seconds)

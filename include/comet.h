@@ -122,8 +122,10 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
  * the smallest |D - r_j| (lowest index on ties) gets bit 0 of hit_mask when that
  * residual is below lambda (strictly) and bit 1 when it lies within 1e-9 mm of
  * lambda (borderline); all other hits get 0.
- *   top_k        must be 1
- *   best         device int64[1], written
+ *   top_k        1..1024: best[0..top_k) receives the top_k smallest RSS in increasing
+ *                order (ties: lower index; -1 past the last non-NaN value); the hits
+ *                are classified for best[0]
+ *   best         device int64[top_k], written
  *   hit_mask     device uint8[n_hits] or NULL (selection only)
  *   n_borderline device int32[1] or NULL: number of borderline hits
  *   dca_best     device double[n_wires] or NULL: D of each wire for the chosen seed
@@ -135,6 +137,123 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
                           const comet_config *cfg, int32_t top_k, int64_t *best,
                           uint8_t *hit_mask, int32_t *n_borderline, double *dca_best,
                           void *stream);
+
+/* ------------------------------------------------------------ derivatives
+ * Eq. 1's RSS is not smooth (Sec. 2.1), but it is smooth piecewise: with each wire's
+ * closest recorded point, winning chord and closest hit fixed, D_i and the capped
+ * residuals are differentiable in the six seed components (x, y, z, px, py, pz).
+ *
+ * comet_rss_adjoint: for every seed, the track is recomputed (the same RK4 steps as
+ * comet_extrapolate_seeds, so every D_i and choice equals the forward path's) and
+ * a reverse sweep runs from each active wire's chord back through the RK4 steps,
+ * recomputing the momenta from checkpoints every 8 steps (nothing is stored per
+ * step). A wire is active when its closest hit's residual e_i = D_i - r_j satisfies
+ * |e_i| < lambda; its row is J_i = dD_i/d(seed).
+ *   seeds6       device double[6][n_seeds] (SoA)
+ *   cfg          host; n_steps <= 2400
+ *   wire_ends, wire_offsets, drift: as in comet_dca_rss
+ *   event_wires  device int32[E+1] or NULL; seed_event device int32[n_seeds] or NULL
+ *                (both or neither): seed s uses the wires
+ *                [event_wires[seed_event[s]], event_wires[seed_event[s]+1]); with
+ *                NULL every seed uses all wires
+ * Outputs (device, each may be NULL):
+ *   rss   double[n_seeds]: Eq. 1 (summed in a fixed tree order: equal to
+ *         comet_dca_rss up to rounding, identical run to run)
+ *   grad  double[n_seeds][6]: d rss / d seed = sum over active wires of 2 e_i J_i
+ *   jtj   double[n_seeds][21]: sum over active wires of J_i J_i^T, packed upper
+ *         triangle, row-major ((0,0), (0,1), ..., (0,5), (1,1), ...)
+ *   jte   double[n_seeds][6]: sum over active wires of J_i e_i
+ *   dca, resid  double[n_seeds][n_wires]: D_i and e_i (NaN for a wire without hits)
+ *   jac   double[n_seeds][n_wires][6]: J_i for active wires, 0 for capped ones
+ * Per-wire outputs are written only for the seed's own event's wires. */
+int comet_rss_adjoint(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                      const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                      const double *drift, int32_t n_hits, const int32_t *event_wires,
+                      const int32_t *seed_event, double *rss, double *grad, double *jtj,
+                      double *jte, double *dca, double *resid, double *jac, void *stream);
+
+/* Bytes of workspace comet_lm_refine needs for n_seeds seeds. */
+size_t comet_lm_workspace_bytes(int64_t n_seeds);
+
+/* Levenberg-Marquardt refinement of every seed in place, on the device, with a
+ * fixed number of iterations (no host synchronisation, so it can be captured in a
+ * HIP graph). Each iteration solves (A + mu diag(A)) delta = -b by Cholesky, where A
+ * and b are comet_rss_adjoint's jtj and jte at the current seed, evaluates the trial
+ * seed, and accepts it when its RSS is lower (mu <- mu / 10), otherwise keeps the seed
+ * (mu <- 10 mu); a matrix that is not positive definite counts as a rejection.
+ *   seeds6     device double[6][n_seeds], updated
+ *   n_iter     0..1000 iterations; mu0 > 0 initial damping
+ *   rss        device double[n_seeds]: RSS at the final seeds
+ *   n_accepted device int32[n_seeds] or NULL: accepted steps per seed
+ *   workspace  device, >= comet_lm_workspace_bytes(n_seeds), 256-byte aligned
+ * Other arguments as in comet_rss_adjoint. */
+int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                    const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                    const double *drift, int32_t n_hits, const int32_t *event_wires,
+                    const int32_t *seed_event, int32_t n_iter, double mu0, double *rss,
+                    int32_t *n_accepted, void *workspace, size_t workspace_bytes,
+                    void *stream);
+
+/* ------------------------------------------------------------ batches of events
+ * The whole Sec. 2.1 path (grid scan, argmin, n_refine finer re-scans, classification)
+ * for every turn partition of many events with uneven wire, hit and turn counts.
+ * Events are packed in one CSR: event e owns wires [event_wires[e], event_wires[e+1]),
+ * wire i owns hits [wire_offsets[i], wire_offsets[i+1]). Partition p belongs to
+ * event part_event[p] and starts from the grid descriptor grids[p] (layout as in
+ * comet_seed_grid; every partition uses the same n, so S = n0 n1 n2 n3 seeds).
+ *
+ * Each scan is one persistent launch: blocks take (partition, 64-seed tile) items
+ * from an atomic counter, build the seeds from the descriptor, record their RK4
+ * tracks into per-block scratch (no track array in HBM) and scan the partition's
+ * event wires; per-seed RSS are summed in wire order and equal those of
+ * comet_dca_rss bit for bit. The calls on `stream` are: a wire-frame kernel, then per
+ * scan [refine (not before the first), counter reset, scan, per-partition argmin],
+ * then classification. No host synchronisation and no allocation: capturable.
+ *   wire_ends, wire_offsets, drift   packed events, device (n_wires >= 1)
+ *   event_wires  device int32[n_events + 1]; part_event device int32[n_partitions]
+ *   grids_init   device double[n_partitions][14] or NULL: copied into grids first (by
+ *                a kernel), so that a replayed graph starts from the same grids
+ *   grids        device double[n_partitions][14], updated by the re-scans
+ *   n            host int32[4]; cfg host (n_steps <= 2400); n_refine 0..100
+ *   rss          device double[n_partitions][S]: the last scan's RSS
+ *   best         device int64[n_partitions]: argmin in the last grid (-1: all NaN)
+ *   best_seed    device double[n_partitions][6] or NULL: the chosen seed (NaN if none)
+ *   best_rss     device double[n_partitions] or NULL
+ *   hit_mask     device uint8[n_partitions][mask_stride] or NULL: bits as in
+ *                comet_select_classify for the partition's event hits, indexed by
+ *                hit - wire_offsets[event_wires[e]]; mask_stride >= the most hits of an
+ *                event
+ *   n_borderline device int32[n_partitions] or NULL
+ *   max_items    > 0: scan only the first max_items (partition, tile) items of every
+ *                scan (for timing shapes; the other RSS are not written)
+ *   workspace    >= comet_batch_workspace_bytes(n_wires, n_steps), 256-byte aligned */
+size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps);
+int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                     const double *drift, int32_t n_hits, const int32_t *event_wires,
+                     int32_t n_events, const int32_t *part_event, int32_t n_partitions,
+                     const double *grids_init, double *grids, const int32_t n[4],
+                     const comet_config *cfg, int32_t n_refine, double *rss, int64_t *best,
+                     double *best_seed, double *best_rss, uint8_t *hit_mask,
+                     int64_t mask_stride, int32_t *n_borderline, int64_t max_items,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Several reference seeds per partition (Sec. 2.1 selects several low-RSS seeds as
+ * references for the next scan). comet_topk: for each of n_segments rows of n values,
+ * idx[row][0..k) = the k smallest values' indices in increasing order (ties: lower
+ * index; NaN never chosen; -1 past the last non-NaN value); k 1..1024.
+ * comet_grid_seeds: seeds6[:, p k + r] = seed idx[p k + r] of grids[p] (NaN for -1),
+ * seeds6 device double[6][n_partitions k]. */
+int comet_topk(const double *values, int64_t n, int32_t n_segments, int32_t k, int64_t *idx,
+               void *stream);
+int comet_grid_seeds(const double *grids, int32_t n_partitions, const int32_t n[4],
+                     const int64_t *idx, int32_t k, double *seeds6, void *stream);
+
+/* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
+ * per LDS chunk, the persistent block count on the current device); every shape
+ * gives the same results. comet_batch_set_variant selects the shape (default 0). */
+int comet_batch_variant_count(void);
+int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks);
+int comet_batch_set_variant(int id);
 
 /* ------------------------------------------------------------ diagnostics
  * Per-kernel device time. After comet_profile_begin() every kernel launched by the

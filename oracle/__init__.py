@@ -72,6 +72,8 @@ def _bind(lib):
     lib.oracle_rss_jacobian.restype = ctypes.c_double
     lib.oracle_rss_jacobian.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _d,
                                         _d, _d, _u8, _d]
+    lib.oracle_topk.restype = None
+    lib.oracle_topk.argtypes = [_d, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_lm_refine.restype = ctypes.c_double
     lib.oracle_lm_refine.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d,
                                      ctypes.c_int32, ctypes.c_double, _i32]
@@ -219,3 +221,9 @@ class Oracle:
                                         _p(_i32a(offsets), _i32), _p(_f64(drift)), n_iter,
                                         float(mu0), _p(acc, _i32))
         return s, rss, int(acc[0])
+
+    def topk(self, values, k):
+        v = _f64(values)
+        out = np.empty(k, dtype=np.int64)
+        self.lib.oracle_topk(_p(v), v.size, k, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        return out

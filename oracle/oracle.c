@@ -809,3 +809,38 @@ double oracle_lm_refine(double seed[6], const double cfg[4], int32_t K, const do
         *accepted = n_acc;
     return rss;
 }
+
+/* ------------------------------------------------------------ several references
+ * Sec. 2.1: several seeds with the lowest RSS become references for the next scan.
+ * The k smallest values in increasing order, ties to the lower index, NaN excluded;
+ * -1 fills the rest when fewer than k values are not NaN. Plain sort of the pairs. */
+typedef struct {
+    double v;
+    int64_t i;
+} oracle_pair;
+
+static int pair_cmp(const void *a, const void *b)
+{
+    const oracle_pair *x = (const oracle_pair *)a, *y = (const oracle_pair *)b;
+    if (x->v < y->v)
+        return -1;
+    if (x->v > y->v)
+        return 1;
+    return x->i < y->i ? -1 : (x->i > y->i ? 1 : 0);
+}
+
+void oracle_topk(const double *values, int64_t n, int32_t k, int64_t *out)
+{
+    oracle_pair *p = (oracle_pair *)malloc(sizeof(oracle_pair) * (size_t)(n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t s = 0; s < n; ++s)
+        if (!isnan(values[s])) {
+            p[m].v = values[s];
+            p[m].i = s;
+            ++m;
+        }
+    qsort(p, (size_t)m, sizeof(oracle_pair), pair_cmp);
+    for (int32_t r = 0; r < k; ++r)
+        out[r] = r < m ? p[r].i : -1;
+    free(p);
+}

@@ -255,3 +255,161 @@ def profile_end() -> dict:
     n = (ctypes.c_int64 * 4)()
     _check(load().comet_profile_end(ms, n), "comet_profile_end")
     return {k: (ms[i], n[i]) for i, k in enumerate(PROFILE_KINDS)}
+
+
+# ------------------------------------------------------------------ derivatives
+def _bind_derivatives(lib):
+    if getattr(lib, "_derivs_bound", False):
+        return lib
+    lib.comet_rss_adjoint.argtypes = [_vp, _i64, ctypes.POINTER(Config), _vp, _i32, _vp, _vp, _i32,
+                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.comet_rss_adjoint.restype = ctypes.c_int
+    lib.comet_lm_workspace_bytes.argtypes = [_i64]
+    lib.comet_lm_workspace_bytes.restype = ctypes.c_size_t
+    lib.comet_lm_refine.argtypes = [_vp, _i64, ctypes.POINTER(Config), _vp, _i32, _vp, _vp, _i32,
+                                    _vp, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp]
+    lib.comet_lm_refine.restype = ctypes.c_int
+    lib._derivs_bound = True
+    return lib
+
+
+def rss_adjoint(seeds: torch.Tensor, cfg: Config, wire_ends: torch.Tensor,
+                wire_offsets: torch.Tensor, drift: torch.Tensor, rss=None, grad=None, jtj=None,
+                jte=None, dca=None, resid=None, jac=None, event_wires=None,
+                seed_event=None) -> None:
+    """comet_rss_adjoint: RSS, its seed gradient [S, 6], normal equations and per-wire rows."""
+    lib = _bind_derivatives(load())
+    S = int(seeds.shape[1]) if seeds.dim() == 2 else -1
+    n_w, n_h = int(wire_ends.shape[0]), int(drift.shape[0])
+    _check(lib.comet_rss_adjoint(
+        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
+        _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(drift, torch.float64, "drift", (n_h,)), n_h,
+        _ptr(event_wires, torch.int32, "event_wires", optional=True),
+        _ptr(seed_event, torch.int32, "seed_event", (S,), optional=True),
+        _ptr(rss, torch.float64, "rss", (S,), optional=True),
+        _ptr(grad, torch.float64, "grad", (S, 6), optional=True),
+        _ptr(jtj, torch.float64, "jtj", (S, 21), optional=True),
+        _ptr(jte, torch.float64, "jte", (S, 6), optional=True),
+        _ptr(dca, torch.float64, "dca", (S, n_w), optional=True),
+        _ptr(resid, torch.float64, "resid", (S, n_w), optional=True),
+        _ptr(jac, torch.float64, "jac", (S, n_w, 6), optional=True), _stream()),
+        "comet_rss_adjoint")
+
+
+def lm_workspace(n_seeds: int, device=None) -> torch.Tensor:
+    nbytes = int(_bind_derivatives(load()).comet_lm_workspace_bytes(int(n_seeds)))
+    return torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=device or "cuda")
+
+
+def lm_refine(seeds: torch.Tensor, cfg: Config, wire_ends: torch.Tensor,
+              wire_offsets: torch.Tensor, drift: torch.Tensor, n_iter: int, mu0: float,
+              rss: torch.Tensor, workspace: torch.Tensor, n_accepted=None, event_wires=None,
+              seed_event=None) -> None:
+    """comet_lm_refine: Levenberg-Marquardt refinement of seeds [6, S] in place."""
+    lib = _bind_derivatives(load())
+    S = int(seeds.shape[1]) if seeds.dim() == 2 else -1
+    n_w, n_h = int(wire_ends.shape[0]), int(drift.shape[0])
+    _check(lib.comet_lm_refine(
+        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
+        _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(drift, torch.float64, "drift", (n_h,)), n_h,
+        _ptr(event_wires, torch.int32, "event_wires", optional=True),
+        _ptr(seed_event, torch.int32, "seed_event", (S,), optional=True),
+        int(n_iter), float(mu0), _ptr(rss, torch.float64, "rss", (S,)),
+        _ptr(n_accepted, torch.int32, "n_accepted", (S,), optional=True),
+        _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()),
+        "comet_lm_refine")
+
+
+# ------------------------------------------------------------------ batches
+def _bind_batch(lib):
+    if getattr(lib, "_batch_bound", False):
+        return lib
+    I4 = ctypes.POINTER(ctypes.c_int32)
+    lib.comet_batch_workspace_bytes.argtypes = [_i32, _i32]
+    lib.comet_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.comet_batch_scan.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp, I4,
+                                     ctypes.POINTER(Config), _i32, _vp, _vp, _vp, _vp, _vp, _i64,
+                                     _vp, _i64, _vp, ctypes.c_size_t, _vp]
+    lib.comet_batch_scan.restype = ctypes.c_int
+    lib.comet_batch_variant_count.restype = ctypes.c_int
+    lib.comet_batch_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4]
+    lib.comet_batch_variant_info.restype = ctypes.c_int
+    lib.comet_batch_set_variant.argtypes = [ctypes.c_int]
+    lib.comet_batch_set_variant.restype = ctypes.c_int
+    lib.comet_topk.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp]
+    lib.comet_topk.restype = ctypes.c_int
+    lib.comet_grid_seeds.argtypes = [_vp, _i32, I4, _vp, _i32, _vp, _vp]
+    lib.comet_grid_seeds.restype = ctypes.c_int
+    lib._batch_bound = True
+    return lib
+
+
+def batch_workspace(n_wires: int, n_steps: int, device=None) -> torch.Tensor:
+    nbytes = int(_bind_batch(load()).comet_batch_workspace_bytes(int(n_wires), int(n_steps)))
+    return torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=device or "cuda")
+
+
+def batch_scan(packed, part_event: torch.Tensor, grids: torch.Tensor, n, cfg: Config,
+               n_refine: int, rss: torch.Tensor, best: torch.Tensor, workspace: torch.Tensor,
+               best_seed=None, best_rss=None, hit_mask=None, n_borderline=None,
+               max_items: int = 0, grids_init=None) -> None:
+    """comet_batch_scan over packed events (scan.PackedEvents)."""
+    lib = _bind_batch(load())
+    NP = int(part_event.shape[0])
+    S = int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
+    n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
+    n_e = int(packed.event_wires.shape[0]) - 1
+    stride = int(hit_mask.shape[1]) if hit_mask is not None else 0
+    _check(lib.comet_batch_scan(
+        _ptr(packed.wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(packed.drift, torch.float64, "drift", (n_h,)), n_h,
+        _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e,
+        _ptr(part_event, torch.int32, "part_event", (NP,)), NP,
+        _ptr(grids_init, torch.float64, "grids_init", (NP, 14), optional=True),
+        _ptr(grids, torch.float64, "grids", (NP, 14)), _n4(n), ctypes.byref(cfg), int(n_refine),
+        _ptr(rss, torch.float64, "rss", (NP, S)), _ptr(best, torch.int64, "best", (NP,)),
+        _ptr(best_seed, torch.float64, "best_seed", (NP, 6), optional=True),
+        _ptr(best_rss, torch.float64, "best_rss", (NP,), optional=True),
+        _ptr(hit_mask, torch.uint8, "hit_mask", (NP, stride), optional=True), stride,
+        _ptr(n_borderline, torch.int32, "n_borderline", (NP,), optional=True), int(max_items),
+        _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()),
+        "comet_batch_scan")
+
+
+def batch_variants():
+    lib = _bind_batch(load())
+    out = []
+    for i in range(lib.comet_batch_variant_count()):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib.comet_batch_variant_info(i, *[ctypes.byref(x) for x in v]),
+               "comet_batch_variant_info")
+        out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value, blocks=v[3].value))
+    return out
+
+
+def set_batch_variant(i: int) -> None:
+    _check(_bind_batch(load()).comet_batch_set_variant(int(i)), "comet_batch_set_variant")
+
+
+def topk(values: torch.Tensor, k: int, out: torch.Tensor) -> None:
+    """comet_topk: values [segments, n] -> out [segments, k] (int64)."""
+    lib = _bind_batch(load())
+    seg, n = int(values.shape[0]), int(values.shape[1])
+    _check(lib.comet_topk(_ptr(values, torch.float64, "values", (seg, n)), n, seg, int(k),
+                          _ptr(out, torch.int64, "out", (seg, k)), _stream()), "comet_topk")
+
+
+def grid_seeds(grids: torch.Tensor, n, idx: torch.Tensor, out: torch.Tensor) -> None:
+    """comet_grid_seeds: seeds of grids [NP, 14] at idx [NP, k] -> out [6, NP * k]."""
+    lib = _bind_batch(load())
+    NP, k = int(idx.shape[0]), int(idx.shape[1])
+    _check(lib.comet_grid_seeds(_ptr(grids, torch.float64, "grids", (NP, 14)), NP, _n4(n),
+                                _ptr(idx, torch.int64, "idx", (NP, k)), k,
+                                _ptr(out, torch.float64, "out", (6, NP * k)), _stream()),
+           "comet_grid_seeds")

@@ -1,0 +1,597 @@
+// batch.hip -- the seed scan of many events with uneven hit and turn counts in
+// persistent launches: every turn partition of every event goes through the paper's
+// Sec. 2.1 path (grid scan, argmin, finer re-scans, classification).
+//
+// Paper: Yeo, Lee and Kuno, arXiv:1911.09340, Sec. 2 (Alg. 1-3, Eq. 1).
+//
+// Events are packed in one CSR (event -> wires -> hits); partition p belongs to event
+// part_event[p] and scans the grid descriptor grids[p] (the same n per axis for all
+// partitions, S seeds). The scan kernel is persistent: each block takes (partition,
+// 64-seed tile) items from an atomic work counter until none are left, builds the
+// tile's seeds from the partition's descriptor, records their RK4 track into the
+// block's own scratch rows, and scans the partition's event wires group by group
+// with the same tile scan as the single-event kernel (cdev::TileScan). Each wire
+// group's d^2 values go to LDS and one wave adds them to the per-seed RSS in wire
+// order, so every RSS equals the single-event path's bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "comet.h"
+#include "dca_scan.h"
+#include "device_math.h"
+#include "host_common.h"
+
+namespace {
+
+using namespace cdev;
+using namespace chost;
+
+constexpr int kMaxBatchBlocks = 2048;  // persistent blocks (scratch rows) at most
+
+struct BatchArgs {
+    const double *frames;     // [W_pad][8]
+    const int32_t *offsets;   // [W + 1] global hit CSR
+    const double *drift;      // [H]
+    const int32_t *ev_wires;  // [E + 1]
+    const int32_t *part_event;
+    const double *grids;      // [NP][14]
+    int n0, n1, n2, n3;
+    int64_t S;
+    int tiles;                // tiles per partition
+    int64_t n_items;
+    double bz, charge, h, lambda;
+    int K;
+    double *scratch;          // [blocks][3][P][64]
+    int *counter;
+    double *rss;              // [NP][S]
+};
+
+template <int W, int NWV, int C>
+__global__ __launch_bounds__(64 * NWV) void batch_scan_kernel(BatchArgs a)
+{
+    using Scan = TileScan<W, NWV, C, true>;
+    constexpr int G = W * NWV;  // wires per group
+    __shared__ __align__(16) double lds[Scan::kLdsDoubles];
+    __shared__ double dd[G * 64];
+    __shared__ int64_t item_s;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int P = a.K + 1;
+    const int64_t row = (int64_t)P * 64;
+    double *sx = a.scratch + (int64_t)blockIdx.x * 3 * row;
+    double *sy = sx + row, *sz = sy + row;
+
+    for (;;) {
+        if (threadIdx.x == 0)
+            item_s = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int64_t item = item_s;
+        __syncthreads();
+        if (item >= a.n_items)
+            break;
+        const int p = (int)(item / a.tiles);
+        const int64_t s0 = (item - (int64_t)p * a.tiles) * 64;
+        const int n_valid = (int)min((int64_t)64, a.S - s0);
+        const int e = a.part_event[p];
+        const int w0 = a.ev_wires[e], w1 = a.ev_wires[e + 1];
+
+        // seeds of the tile and their tracks (one wave, one seed per lane)
+        if (wave == 0 && lane < n_valid) {
+            double st[6];
+            seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, s0 + lane, st);
+            double x = st[0], y = st[1], z = st[2], px = st[3], py = st[4];
+            const StepConsts kc = step_consts(px, py, st[5], a.bz, a.charge, a.h);
+            for (int k = 0; k < a.K; ++k) {
+                sx[(int64_t)k * 64 + lane] = x;
+                sy[(int64_t)k * 64 + lane] = y;
+                sz[(int64_t)k * 64 + lane] = z;
+                rk4_step(kc, x, y, z, px, py);
+            }
+            sx[(int64_t)a.K * 64 + lane] = x;
+            sy[(int64_t)a.K * 64 + lane] = y;
+            sz[(int64_t)a.K * 64 + lane] = z;
+        }
+        __syncthreads();
+
+        double acc = 0.0;  // RSS of this lane's seed (wave 0)
+        for (int g0 = w0; g0 < w1; g0 += G) {
+            const int wbase = g0 + wave * W;
+            const int nw = max(0, min(W, w1 - wbase));
+            double f[W][8];
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    f[w][j] = a.frames[8 * (int64_t)(wbase + w) + j];
+            double d2[W];
+            Scan::run(sx, sy, sz, 64, P, n_valid, true, f, nw, a.offsets + (nw > 0 ? wbase : 0),
+                      a.drift, a.lambda, lds, d2);
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                dd[(wave * W + w) * 64 + lane] = d2[w];
+            __syncthreads();
+            if (wave == 0) {
+                const int ng = min(G, w1 - g0);
+                for (int j = 0; j < ng; ++j)
+                    acc = acc + dd[j * 64 + lane];
+            }
+            __syncthreads();
+        }
+        if (wave == 0 && lane < n_valid)
+            a.rss[(int64_t)p * a.S + s0 + lane] = acc;
+    }
+}
+
+// One block per partition: argmin of its RSS (first index of the smallest, NaN never).
+__global__ __launch_bounds__(kSelectThreads) void batch_argmin_kernel(const double *__restrict__ rss,
+                                                                      int64_t S,
+                                                                      int64_t *__restrict__ best)
+{
+    const int64_t b = block_argmin(rss + (int64_t)blockIdx.x * S, S);
+    if (threadIdx.x == 0)
+        best[blockIdx.x] = b;
+}
+
+__global__ void batch_refine_kernel(int n_part, double *__restrict__ grids, int n0, int n1, int n2,
+                                    int n3, const int64_t *__restrict__ best)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n_part)
+        refine_grid_desc(grids + 14 * (int64_t)p, n0, n1, n2, n3, best[p]);
+}
+
+// One block per partition: the chosen seed (its descriptor and index), its RSS, and the
+// classification of its event's hits (Sec. 2.1): per wire the hit with the smallest
+// |D - r_j| (first on ties) gets bit 0 when below lambda and bit 1 within 1e-9 mm of
+// lambda. The seed's track is recomputed into LDS (thread 0).
+constexpr int kBatchClassifyThreads = 256;
+
+__global__ __launch_bounds__(kBatchClassifyThreads) void batch_classify_kernel(
+    const double *__restrict__ grids, int n0, int n1, int n2, int n3, int64_t S,
+    const int64_t *__restrict__ best, const double *__restrict__ rss,
+    const double *__restrict__ ends, const int32_t *__restrict__ offsets,
+    const double *__restrict__ drift, const int32_t *__restrict__ ev_wires,
+    const int32_t *__restrict__ part_event, double bz, double charge, double h, int K,
+    double lambda, double *__restrict__ best_seed, double *__restrict__ best_rss,
+    uint8_t *__restrict__ mask, int64_t mask_stride, int32_t *__restrict__ n_border)
+{
+    extern __shared__ double pts[];  // [3][K + 1]
+    __shared__ int32_t border;
+    const int p = blockIdx.x;
+    const int P = K + 1;
+    const int64_t b = best[p];
+    const int e = part_event[p];
+    const int w0 = ev_wires[e], w1 = ev_wires[e + 1];
+    const int h0 = offsets[w0];
+    if (threadIdx.x == 0) {
+        border = 0;
+        double st[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
+        if (b >= 0) {
+            seed_from_grid(grids + 14 * (int64_t)p, n0, n1, n2, n3, b, st);
+            double x = st[0], y = st[1], z = st[2], px = st[3], py = st[4];
+            const StepConsts kc = step_consts(px, py, st[5], bz, charge, h);
+            for (int k = 0; k < K; ++k) {
+                pts[k] = x;
+                pts[P + k] = y;
+                pts[2 * P + k] = z;
+                rk4_step(kc, x, y, z, px, py);
+            }
+            pts[K] = x;
+            pts[P + K] = y;
+            pts[2 * P + K] = z;
+        }
+        if (best_seed)
+            for (int c = 0; c < 6; ++c)
+                best_seed[6 * (int64_t)p + c] = st[c];
+        if (best_rss)
+            best_rss[p] = b >= 0 ? rss[(int64_t)p * S + b] : NAN;
+    }
+    __syncthreads();
+    for (int wi = w0 + threadIdx.x; wi < w1; wi += kBatchClassifyThreads) {
+        const int j0 = offsets[wi], j1 = offsets[wi + 1];
+        uint8_t *m = mask ? mask + (int64_t)p * mask_stride - h0 : nullptr;
+        if (m)
+            for (int j = j0; j < j1; ++j)
+                m[j] = 0;
+        if (b < 0)
+            continue;
+        double f[8];
+        wire_frame(ends + 6 * (int64_t)wi, f);
+        double qb = INFINITY;
+        int kb = 0;
+        for (int k = 0; k < P; ++k) {
+            double xi, eta;
+            project(f, pts[k], pts[P + k], pts[2 * P + k], xi, eta);
+            const double q = fma(xi, xi, eta * eta);
+            if (q < qb) {
+                qb = q;
+                kb = k;
+            }
+        }
+        const double D = sqrt(refine_dca2(pts, pts + P, pts + 2 * P, 1, P, f, kb, qb));
+        int jb = -1;
+        double eb = INFINITY;
+        for (int j = j0; j < j1; ++j) {
+            const double r = fabs(D - drift[j]);
+            if (r < eb) {
+                eb = r;
+                jb = j;
+            }
+        }
+        if (jb >= 0) {
+            uint8_t bits = 0;
+            if (eb < lambda)
+                bits |= 1;
+            if (fabs(eb - lambda) < 1e-9) {
+                bits |= 2;
+                atomicAdd(&border, 1);  // LDS counter: integer, order-independent
+            }
+            if (m)
+                m[jb] = bits;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && n_border)
+        n_border[p] = border;
+}
+
+// k smallest (value, index) pairs of each segment in increasing order (ties: lower
+// index; NaN never chosen; -1 when fewer than k values are not NaN). Round r takes the
+// smallest pair strictly above round r-1's, so no membership test is needed.
+__global__ __launch_bounds__(kSelectThreads) void topk_kernel(const double *__restrict__ v,
+                                                              int64_t n, int k,
+                                                              int64_t *__restrict__ out)
+{
+    __shared__ double sv[kSelectThreads / 64];
+    __shared__ int64_t si[kSelectThreads / 64];
+    __shared__ double prev_v;
+    __shared__ int64_t prev_i;
+    const double *seg = v + (int64_t)blockIdx.x * n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        prev_v = -INFINITY;
+        prev_i = -1;
+    }
+    __syncthreads();
+    for (int r = 0; r < k; ++r) {
+        const double pv = prev_v;
+        const int64_t pi = prev_i;
+        MinLoc m{INFINITY, -1};
+        for (int64_t s = threadIdx.x; s < n; s += kSelectThreads) {
+            const double x = seg[s];
+            const bool above = x > pv || (x == pv && s > pi);  // NaN is never above
+            if (above && (x < m.v || (m.i < 0 && x == m.v))) {
+                m.v = x;
+                m.i = s;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            MinLoc o{__shfl_xor(m.v, off), __shfl_xor(m.i, off)};
+            if (beats(o, m))
+                m = o;
+        }
+        if (lane == 0) {
+            sv[wave] = m.v;
+            si[wave] = m.i;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            MinLoc a{INFINITY, -1};
+            if (lane < kSelectThreads / 64) {
+                a.v = sv[lane];
+                a.i = si[lane];
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                MinLoc o{__shfl_xor(a.v, off), __shfl_xor(a.i, off)};
+                if (beats(o, a))
+                    a = o;
+            }
+            if (lane == 0) {
+                out[(int64_t)blockIdx.x * k + r] = a.i;
+                if (a.i >= 0) {
+                    prev_v = a.v;
+                    prev_i = a.i;
+                } else {
+                    prev_v = NAN;  // nothing is above NaN: later rounds give -1
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Seeds at chosen grid indices: out[:, p k + r] = seed idx[p k + r] of grids[p]
+// (NaN for idx < 0). One thread per (partition, rank).
+__global__ void grid_seeds_kernel(const double *__restrict__ grids, int n0, int n1, int n2, int n3,
+                                  const int64_t *__restrict__ idx, int n_part, int k,
+                                  double *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)n_part * k;
+    if (t >= total)
+        return;
+    const int p = (int)(t / k);
+    double st[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
+    if (idx[t] >= 0)
+        seed_from_grid(grids + 14 * (int64_t)p, n0, n1, n2, n3, idx[t], st);
+    for (int c = 0; c < 6; ++c)
+        out[c * total + t] = st[c];
+}
+
+__global__ void batch_frames_kernel(const double *__restrict__ ends, int n_w, int n_pad,
+                                    double *__restrict__ frames)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_pad)
+        return;
+    double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (w < n_w)
+        wire_frame(ends + 6 * (int64_t)w, f);
+    for (int j = 0; j < 8; ++j)
+        frames[8 * (int64_t)w + j] = f[j];
+}
+
+__global__ void zero_counter_kernel(int *c) { *c = 0; }
+
+__global__ void copy_kernel(const double *__restrict__ src, double *__restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ shapes
+struct BatchVariant {
+    int w, nwv, c;
+    void (*kernel)(BatchArgs);
+};
+
+const BatchVariant kBatchVariants[] = {
+    {5, 8, 16, batch_scan_kernel<5, 8, 16>},
+    {6, 8, 16, batch_scan_kernel<6, 8, 16>},
+    {4, 8, 16, batch_scan_kernel<4, 8, 16>},
+    {4, 8, 32, batch_scan_kernel<4, 8, 32>},
+    {4, 12, 16, batch_scan_kernel<4, 12, 16>},
+    {3, 8, 32, batch_scan_kernel<3, 8, 32>},
+};
+constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
+constexpr int kBatchWirePad = 64;  // >= the largest W * NWV above
+
+std::mutex g_batch_mu;
+int g_batch_variant = 0;
+int g_batch_blocks[kNumBatchVariants][64];  // persistent grid per (variant, device)
+
+// Persistent blocks for a shape: every block that can be resident at once.
+int batch_blocks(int id)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 0;
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    int &nb = g_batch_blocks[id][dev];
+    if (nb == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        const BatchVariant &v = kBatchVariants[id];
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)v.kernel,
+                                                         64 * v.nwv, 0) != hipSuccess)
+            return 0;
+        nb = min(kMaxBatchBlocks, max(1, cus * max(1, per_cu)));
+    }
+    return nb;
+}
+
+size_t batch_scratch_bytes(int K) { return sizeof(double) * 3 * (size_t)(K + 1) * 64; }
+
+int frames_pad(int n_w) { return ((n_w + 63) / 64) * 64 + kBatchWirePad; }
+
+struct BatchLayout {
+    double *frames;
+    int *counter;
+    double *scratch;
+};
+
+BatchLayout batch_layout(void *ws, int n_wires)
+{
+    char *p = (char *)ws;
+    BatchLayout l;
+    l.frames = (double *)p;
+    p += align256(sizeof(double) * 8 * (size_t)frames_pad(n_wires));
+    l.counter = (int *)p;
+    p += 256;
+    l.scratch = (double *)p;
+    return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps)
+{
+    if (n_wires < 0 || n_steps < 1)
+        return 0;
+    return align256(sizeof(double) * 8 * (size_t)frames_pad(n_wires)) + 256 +
+           (size_t)kMaxBatchBlocks * batch_scratch_bytes(n_steps);
+}
+
+int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                     const double *drift, int32_t n_hits, const int32_t *event_wires,
+                     int32_t n_events, const int32_t *part_event, int32_t n_partitions,
+                     const double *grids_init, double *grids, const int32_t n[4],
+                     const comet_config *cfg, int32_t n_refine, double *rss, int64_t *best,
+                     double *best_seed, double *best_rss, uint8_t *hit_mask,
+                     int64_t mask_stride, int32_t *n_borderline, int64_t max_items,
+                     void *workspace, size_t workspace_bytes, void *stream)
+{
+    clear_error();
+    if (!wire_ends || !wire_offsets || !event_wires || !part_event || !grids || !n || !rss ||
+        !best)
+        return fail(COMET_EINVAL, "comet_batch_scan: NULL pointer");
+    if (n_wires < 1 || n_hits < 0 || (n_hits > 0 && !drift) || n_events < 1 || n_partitions < 1)
+        return fail(COMET_EINVAL, "comet_batch_scan: bad sizes");
+    if (n_refine < 0 || n_refine > 100)
+        return fail(COMET_EINVAL, "comet_batch_scan: n_refine must be in [0, 100]");
+    int64_t S = 1;
+    for (int a = 0; a < 4; ++a) {
+        if (n[a] < 1)
+            return fail(COMET_EINVAL, "comet_batch_scan: n[%d] < 1", a);
+        S *= n[a];
+    }
+    if (S > ((int64_t)1 << 31) ||
+        (int64_t)n_partitions * ((S + 63) / 64) + kMaxBatchBlocks > ((int64_t)1 << 31) - 1)
+        return fail(COMET_EINVAL, "comet_batch_scan: too many work items for one launch");
+    int st = check_config(cfg);
+    if (st)
+        return st;
+    if (cfg->n_steps > 2400)
+        return fail(COMET_EUNSUPPORTED, "comet_batch_scan: n_steps %d > 2400", cfg->n_steps);
+    if (hit_mask && mask_stride < 1)
+        return fail(COMET_EINVAL, "comet_batch_scan: mask_stride must be >= 1");
+    const size_t need = comet_batch_workspace_bytes(n_wires, cfg->n_steps);
+    if (!workspace || workspace_bytes < need)
+        return fail(COMET_EWORKSPACE, "comet_batch_scan: workspace %zu < %zu bytes",
+                    workspace_bytes, need);
+    if (((uintptr_t)workspace & 255) != 0)
+        return fail(COMET_EINVAL, "comet_batch_scan: workspace not 256-byte aligned");
+    st = check_device();
+    if (st)
+        return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const BatchLayout l = batch_layout(workspace, n_wires);
+    if (grids_init) {
+        const int64_t nd = 14 * (int64_t)n_partitions;
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, hs,
+                           grids_init, grids, nd);
+        st = launched("copy_kernel");
+        if (st)
+            return st;
+    }
+    const int pad = frames_pad(n_wires);
+    hipLaunchKernelGGL(batch_frames_kernel, dim3((pad + 63) / 64), dim3(64), 0, hs, wire_ends,
+                       n_wires, pad, l.frames);
+    st = launched("batch_frames_kernel");
+    if (st)
+        return st;
+    int id;
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mu);
+        id = g_batch_variant;
+    }
+    const BatchVariant &v = kBatchVariants[id];
+    const int blocks = batch_blocks(id);
+    if (blocks < 1)
+        return fail(COMET_EHIP, "comet_batch_scan: occupancy query failed");
+    const int tiles = (int)((S + 63) / 64);
+    int64_t items = (int64_t)n_partitions * tiles;
+    if (max_items > 0 && max_items < items)
+        items = max_items;
+    BatchArgs args{l.frames, wire_offsets, drift, event_wires, part_event, grids, n[0], n[1],
+                   n[2], n[3], S, tiles, items, cfg->bz_tesla, cfg->charge_e, cfg->step_mm,
+                   cfg->lambda_mm, cfg->n_steps, l.scratch, l.counter, rss};
+    for (int it = 0; it <= n_refine && st == COMET_OK; ++it) {
+        if (it) {
+            hipLaunchKernelGGL(batch_refine_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0,
+                               hs, n_partitions, grids, n[0], n[1], n[2], n[3],
+                               (const int64_t *)best);
+            st = launched("batch_refine_kernel");
+            if (st)
+                break;
+        }
+        hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, hs, l.counter);
+        st = launched("zero_counter_kernel");
+        if (st)
+            break;
+        {
+            ProfScope prof(kProfDca, hs);
+            hipLaunchKernelGGL(v.kernel, dim3(blocks), dim3(64 * v.nwv), 0, hs, args);
+            st = launched("batch_scan_kernel");
+        }
+        if (st)
+            break;
+        ProfScope prof(kProfSelect, hs);
+        hipLaunchKernelGGL(batch_argmin_kernel, dim3(n_partitions), dim3(kSelectThreads), 0, hs,
+                           (const double *)rss, S, best);
+        st = launched("batch_argmin_kernel");
+    }
+    if (st)
+        return st;
+    const size_t lds = sizeof(double) * 3 * (size_t)(cfg->n_steps + 1);
+    hipLaunchKernelGGL(batch_classify_kernel, dim3(n_partitions), dim3(kBatchClassifyThreads), lds,
+                       hs, (const double *)grids, n[0], n[1], n[2], n[3], S,
+                       (const int64_t *)best, (const double *)rss, wire_ends, wire_offsets, drift,
+                       event_wires, part_event, cfg->bz_tesla, cfg->charge_e, cfg->step_mm,
+                       cfg->n_steps, cfg->lambda_mm, best_seed, best_rss, hit_mask, mask_stride,
+                       n_borderline);
+    return launched("batch_classify_kernel");
+}
+
+int comet_topk(const double *values, int64_t n, int32_t n_segments, int32_t k, int64_t *idx,
+               void *stream)
+{
+    clear_error();
+    if (!values || !idx)
+        return fail(COMET_EINVAL, "comet_topk: NULL pointer");
+    if (n < 1 || n_segments < 1 || k < 1 || k > 1024)
+        return fail(COMET_EINVAL, "comet_topk: bad sizes (n %lld, segments %d, k %d)",
+                    (long long)n, n_segments, k);
+    int st = check_device();
+    if (st)
+        return st;
+    ProfScope prof(kProfSelect, (hipStream_t)stream);
+    hipLaunchKernelGGL(topk_kernel, dim3(n_segments), dim3(kSelectThreads), 0, (hipStream_t)stream,
+                       values, n, k, idx);
+    return launched("topk_kernel");
+}
+
+int comet_grid_seeds(const double *grids, int32_t n_partitions, const int32_t n[4],
+                     const int64_t *idx, int32_t k, double *seeds6, void *stream)
+{
+    clear_error();
+    if (!grids || !n || !idx || !seeds6)
+        return fail(COMET_EINVAL, "comet_grid_seeds: NULL pointer");
+    if (n_partitions < 1 || k < 1 || (int64_t)n_partitions * k > (1 << 30))
+        return fail(COMET_EINVAL, "comet_grid_seeds: bad sizes");
+    for (int a = 0; a < 4; ++a)
+        if (n[a] < 1)
+            return fail(COMET_EINVAL, "comet_grid_seeds: n[%d] < 1", a);
+    int st = check_device();
+    if (st)
+        return st;
+    const int64_t total = (int64_t)n_partitions * k;
+    hipLaunchKernelGGL(grid_seeds_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, grids, n[0], n[1], n[2], n[3], idx, n_partitions, k,
+                       seeds6);
+    return launched("grid_seeds_kernel");
+}
+
+int comet_batch_variant_count(void) { return kNumBatchVariants; }
+
+int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks)
+{
+    if (id < 0 || id >= kNumBatchVariants || !w || !nwv || !chunk)
+        return fail(COMET_EINVAL, "comet_batch_variant_info: bad id or NULL pointer");
+    *w = kBatchVariants[id].w;
+    *nwv = kBatchVariants[id].nwv;
+    *chunk = kBatchVariants[id].c;
+    if (blocks)
+        *blocks = batch_blocks(id);
+    return COMET_OK;
+}
+
+int comet_batch_set_variant(int id)
+{
+    if (id < 0 || id >= kNumBatchVariants)
+        return fail(COMET_EINVAL, "comet_batch_set_variant: id %d out of range", id);
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    g_batch_variant = id;
+    return COMET_OK;
+}
+
+}  // extern "C"

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "comet.h"
+#include "dca_scan.h"
 #include "device_math.h"
 #include "host_common.h"
 
@@ -50,62 +51,17 @@ __global__ void seed_grid_kernel(const double *__restrict__ grid, int n0, int n1
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S)
         return;
-    const int i3 = (int)(s % n3);
-    int64_t rest = s / n3;
-    const int i2 = (int)(rest % n2);
-    rest /= n2;
-    const int i1 = (int)(rest % n1);
-    const int i0 = (int)(rest / n1);
-    const double v0 = axis_value(grid[6], grid[10], n0, i0);
-    const double v1 = axis_value(grid[7], grid[11], n1, i1);
-    const double v2 = axis_value(grid[8], grid[12], n2, i2);
-    const double v3 = axis_value(grid[9], grid[13], n3, i3);
-
-    const double x0 = grid[0], y0 = grid[1], z0 = grid[2];
-    const double px0 = grid[3], py0 = grid[4], pz0 = grid[5];
-    const double r0 = sqrt(x0 * x0 + y0 * y0);
-    double ca, sa;
-    half_angle_rotation(v0 / (2.0 * r0), ca, sa);
-    const double pt0 = sqrt(px0 * px0 + py0 * py0);
-    const double p0 = sqrt((px0 * px0 + py0 * py0) + pz0 * pz0);
-    const double ct0 = pz0 / p0, st0 = pt0 / p0;
-    const double cp0 = px0 / pt0, sp0 = py0 / pt0;
-    double cdt, sdt, cdp, sdp;
-    half_angle_rotation(v2 * 0.5, cdt, sdt);
-    half_angle_rotation(v3 * 0.5, cdp, sdp);
-    const double ct = ct0 * cdt - st0 * sdt;
-    const double st = st0 * cdt + ct0 * sdt;
-    const double cp = cp0 * cdp - sp0 * sdp;
-    const double sp = sp0 * cdp + cp0 * sdp;
-    seeds[0 * S + s] = x0 * ca - y0 * sa;
-    seeds[1 * S + s] = y0 * ca + x0 * sa;
-    seeds[2 * S + s] = z0;
-    seeds[3 * S + s] = v1 * (st * cp);
-    seeds[4 * S + s] = v1 * (st * sp);
-    seeds[5 * S + s] = v1 * ct;
+    double st[6];
+    seed_from_grid(grid, n0, n1, n2, n3, s, st);
+    for (int c = 0; c < 6; ++c)
+        seeds[c * S + s] = st[c];
 }
 
 // Finer re-scan around the chosen seed (Sec. 2.1). One thread.
 __global__ void refine_grid_kernel(double *__restrict__ grid, int n0, int n1, int n2, int n3,
                                    const int64_t *__restrict__ best)
 {
-    const int64_t b = best[0];
-    if (b < 0)
-        return;
-    const int n[4] = {n0, n1, n2, n3};
-    int idx[4];
-    int64_t rest = b;
-    for (int a = 3; a >= 0; --a) {
-        idx[a] = (int)(rest % n[a]);
-        rest /= n[a];
-    }
-    for (int a = 0; a < 4; ++a) {
-        if (n[a] > 1) {
-            const double v = axis_value(grid[6 + a], grid[10 + a], n[a], idx[a]);
-            grid[6 + a] = v;
-            grid[10 + a] = (2.0 * grid[10 + a]) / (double)(n[a] - 1);
-        }
-    }
+    refine_grid_desc(grid, n0, n1, n2, n3, best[0]);
 }
 
 // ------------------------------------------------------------------ RK4 recording
@@ -154,17 +110,8 @@ __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad
 }
 
 // ------------------------------------------------------------------ DCA / Eq. 1
-// Work item: a tile of 64 seeds (one per lane) x a group of W * NWV wires. Each of
-// the NWV waves owns W wires whose frames sit in scalar registers. The tile's
-// track streams through LDS in chunks of C points (loaded once, read by all
-// waves), and every lane keeps, per wire, the smallest q seen so far (Alg. 2: the
-// recorded state closest to the wire). The first index reaching it is tracked
-// either per point (CHUNK_ARGMIN = false: compare + select per point), or per
-// chunk (CHUNK_ARGMIN = true: only a running min per point; the chunk holding the
-// first minimum is recorded and rescanned from HBM once at the end, recomputing q
-// with the same arithmetic so that equality identifies the first index). After
-// the last chunk the closest point is refined over its two chords, Eq. 1's capped
-// residual is formed, and d^2 is stored to dsq[wire][seed].
+// Work item: a tile of 64 seeds (one per lane) x a group of W * NWV wires, scanned by
+// cdev::TileScan (dca_scan.h); d^2 of every (wire, seed) goes to dsq[wire][seed].
 //
 // Block -> work mapping: consecutive blocks are dealt round-robin over the 8 XCDs;
 // with xcd_remap the wire groups of one seed tile become consecutive within one
@@ -176,7 +123,8 @@ __global__ __launch_bounds__(64 * NWV) void dca_kernel(
     int n_w, const int32_t *__restrict__ offsets, const double *__restrict__ drift,
     double lambda, double *__restrict__ dsq, int n_groups, int n_blocks, int xcd_remap)
 {
-    __shared__ __align__(16) double lds[3 * C * 64];
+    using Scan = TileScan<W, NWV, C, CHUNK_ARGMIN>;
+    __shared__ __align__(16) double lds[Scan::kLdsDoubles];
 
     const int b = blockIdx.x;
     const int q8 = n_blocks >> 3, r8 = n_blocks & 7;
@@ -188,9 +136,9 @@ __global__ __launch_bounds__(64 * NWV) void dca_kernel(
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t s0 = (int64_t)tile * 64;
-    const int64_t s = s0 + lane;
+    const int n_valid = (int)min((int64_t)64, S - s0);
     const int wbase = group * (W * NWV) + wave * W;
-    const bool active = wbase < n_w;  // wave-uniform
+    const int nw = max(0, min(W, n_w - wbase));  // wave-uniform
 
     double f[W][8];
 #pragma unroll
@@ -198,134 +146,18 @@ __global__ __launch_bounds__(64 * NWV) void dca_kernel(
 #pragma unroll
         for (int j = 0; j < 8; ++j)
             f[w][j] = frames[8 * (int64_t)(wbase + w) + j];
-    double best[W], cmin[W];
-    int kbest[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        best[w] = INFINITY;
-        cmin[w] = INFINITY;
-        kbest[w] = 0;
-    }
 
-    // Track chunk staging. Each thread owns UNITS / T slots of two consecutive seeds
-    // (16 bytes); the next chunk's loads are issued before the current chunk is
-    // scanned, so their latency hides behind the scan.
-    constexpr int T = 64 * NWV;
-    constexpr int UNITS = 3 * C * 32;
-    constexpr int PER_T = (UNITS + T - 1) / T;
+    const int64_t PS = (int64_t)P * S;
     // 16-byte loads when every row start is 16-byte aligned (even S, aligned base)
     const bool pairs = (S & 1) == 0 && ((uintptr_t)track & 15) == 0;
-    double2 pre[PER_T];
-    auto fetch = [&](int k0) {
+    double d2[W];
+    Scan::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid, pairs, f, nw,
+              offsets + (nw > 0 ? wbase : 0), drift, lambda, lds, d2);
+    if (lane < n_valid)
 #pragma unroll
-        for (int u = 0; u < PER_T; ++u) {
-            const int idx = threadIdx.x + u * T;
-            const int c = idx / (C * 32);
-            const int r = idx - c * (C * 32);
-            const int kk = r >> 5;
-            const int l2 = (r & 31) * 2;
-            const int k = k0 + kk;
-            const int64_t ss = s0 + l2;
-            double2 v = make_double2(0.0, 0.0);
-            if (idx < UNITS && k < P) {
-                const double *src = track + ((int64_t)c * P + k) * S + ss;
-                if (pairs && ss + 1 < S) {
-                    v = *reinterpret_cast<const double2 *>(src);
-                } else {
-                    if (ss < S)
-                        v.x = src[0];
-                    if (ss + 1 < S)
-                        v.y = src[1];
-                }
-            }
-            pre[u] = v;
-        }
-    };
-    auto stash = [&]() {
-#pragma unroll
-        for (int u = 0; u < PER_T; ++u) {
-            const int idx = threadIdx.x + u * T;
-            if (idx < UNITS)
-                *reinterpret_cast<double2 *>(&lds[2 * idx]) = pre[u];
-        }
-    };
-
-    fetch(0);
-    for (int k0 = 0; k0 < P; k0 += C) {
-        __syncthreads();
-        stash();
-        __syncthreads();
-        if (k0 + C < P)
-            fetch(k0 + C);
-        if (active) {
-            auto body = [&](int kk) {
-                const double x = lds[(0 * C + kk) * 64 + lane];
-                const double y = lds[(1 * C + kk) * 64 + lane];
-                const double z = lds[(2 * C + kk) * 64 + lane];
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    double xi, eta;
-                    project(f[w], x, y, z, xi, eta);
-                    const double q = fma(xi, xi, eta * eta);
-                    if (CHUNK_ARGMIN) {
-                        cmin[w] = fmin(cmin[w], q);
-                    } else {
-                        kbest[w] = q < best[w] ? k0 + kk : kbest[w];
-                        best[w] = fmin(best[w], q);
-                    }
-                }
-            };
-            const int kn = min(C, P - k0);
-            if (kn == C) {
-#pragma unroll 4
-                for (int kk = 0; kk < C; ++kk)
-                    body(kk);
-            } else {
-                for (int kk = 0; kk < kn; ++kk)
-                    body(kk);
-            }
-            if (CHUNK_ARGMIN) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    if (cmin[w] < best[w]) {
-                        best[w] = cmin[w];
-                        kbest[w] = k0;
-                    }
-                    cmin[w] = INFINITY;
-                }
-            }
-        }
-    }
-
-    if (!active || s >= S)
-        return;
-    const int64_t PS = (int64_t)P * S;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        const int wi = wbase + w;
-        if (wi < n_w) {
-            int k = kbest[w];
-            if (CHUNK_ARGMIN) {
-                // first index in the recorded chunk whose q equals the minimum
-                const int kend = min(k + C, P);
-                int kf = k;
-                for (int j = k; j < kend; ++j) {
-                    const int64_t o = (int64_t)j * S + s;
-                    double xi, eta;
-                    project(f[w], track[o], track[PS + o], track[2 * PS + o], xi, eta);
-                    if (fma(xi, xi, eta * eta) == best[w]) {
-                        kf = j;
-                        break;
-                    }
-                }
-                k = kf;
-            }
-            const double d2 = refine_dca2(track, S, P, s, f[w], k, best[w]);
-            const double D = sqrt(d2);
-            const double d = capped_residual(D, drift, offsets[wi], offsets[wi + 1], lambda);
-            dsq[(int64_t)wi * S + s] = d * d;
-        }
-    }
+        for (int w = 0; w < W; ++w)
+            if (w < nw)
+                dsq[(int64_t)(wbase + w) * S + s0 + lane] = d2[w];
 }
 
 // Eq. 1's sum over wires in wire order: rss = ((0 + d_0^2) + d_1^2) + ...
@@ -342,63 +174,13 @@ __global__ void rss_sum_kernel(const double *__restrict__ dsq, int n_w, int64_t 
 }
 
 // ------------------------------------------------------------------ selection
-// (value, index) pairs; index < 0 means "nothing yet". a beats b when b is empty,
-// or a.v < b.v, or a.v == b.v and a.i < b.i. NaN is never stored.
-struct MinLoc {
-    double v;
-    int64_t i;
-};
-
-__device__ __forceinline__ bool beats(const MinLoc &a, const MinLoc &b)
-{
-    if (a.i < 0)
-        return false;
-    if (b.i < 0)
-        return true;
-    return a.v < b.v || (a.v == b.v && a.i < b.i);
-}
-
-constexpr int kSelectThreads = 1024;
-
 __global__ __launch_bounds__(kSelectThreads) void argmin_kernel(const double *__restrict__ rss,
                                                                 int64_t S,
                                                                 int64_t *__restrict__ best)
 {
-    __shared__ double sv[kSelectThreads / 64];
-    __shared__ int64_t si[kSelectThreads / 64];
-    MinLoc m{INFINITY, -1};
-    for (int64_t s = threadIdx.x; s < S; s += kSelectThreads) {
-        const double v = rss[s];
-        if (v < m.v || (m.i < 0 && v == m.v)) {
-            m.v = v;
-            m.i = s;
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        MinLoc o{__shfl_xor(m.v, off), __shfl_xor(m.i, off)};
-        if (beats(o, m))
-            m = o;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        sv[wave] = m.v;
-        si[wave] = m.i;
-    }
-    __syncthreads();
-    if (wave == 0) {
-        MinLoc a{INFINITY, -1};
-        if (lane < kSelectThreads / 64) {
-            a.v = sv[lane];
-            a.i = si[lane];
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            MinLoc o{__shfl_xor(a.v, off), __shfl_xor(a.i, off)};
-            if (beats(o, a))
-                a = o;
-        }
-        if (lane == 0)
-            best[0] = a.i;
-    }
+    const int64_t b = block_argmin(rss, S);
+    if (threadIdx.x == 0)
+        best[0] = b;
 }
 
 // Classification of the chosen seed (Sec. 2.1): per wire (one thread each), the
@@ -837,8 +619,8 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
         return fail(COMET_EINVAL, "comet_select_classify: NULL rss or best");
     if (n_seeds < 1 || n_seeds > ((int64_t)1 << 40))
         return fail(COMET_EINVAL, "comet_select_classify: n_seeds = %lld", (long long)n_seeds);
-    if (top_k != 1)
-        return fail(COMET_EUNSUPPORTED, "comet_select_classify: top_k must be 1");
+    if (top_k < 1 || top_k > 1024)
+        return fail(COMET_EINVAL, "comet_select_classify: top_k must be in [1, 1024]");
     const bool classify = hit_mask || n_borderline || dca_best;
     if (classify) {
         if (!track_xyz)
@@ -858,9 +640,17 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
     if (st)
         return st;
     hipStream_t hs = (hipStream_t)stream;
+    if (top_k > 1) {
+        st = comet_topk(rss, n_seeds, 1, top_k, best, stream);
+        if (st)
+            return st;
+    }
     ProfScope prof(kProfSelect, hs);
-    hipLaunchKernelGGL(argmin_kernel, dim3(1), dim3(kSelectThreads), 0, hs, rss, n_seeds, best);
-    st = launched("argmin_kernel");
+    if (top_k == 1) {
+        hipLaunchKernelGGL(argmin_kernel, dim3(1), dim3(kSelectThreads), 0, hs, rss, n_seeds,
+                           best);
+        st = launched("argmin_kernel");
+    }
     if (st || !classify)
         return st;
     hipLaunchKernelGGL(classify_kernel, dim3(1), dim3(kClassifyThreads), 0, hs, track_xyz,

@@ -37,6 +37,128 @@ __device__ __forceinline__ void half_angle_rotation(double tau, double &c, doubl
     s = (2.0 * tau) / den;
 }
 
+// Seed `index` of a grid descriptor g = (reference state [6], centres [4], half-spans
+// [4]) with n0..n3 points per axis (axis 3 fastest). Offsets enter as rotations by
+// 2 atan(tau): tau = v0 / (2 r0) on the seed circle, tau = v / 2 for the angles.
+__device__ __forceinline__ void seed_from_grid(const double *__restrict__ g, int n0, int n1,
+                                               int n2, int n3, int64_t index, double out[6])
+{
+    const int i3 = (int)(index % n3);
+    int64_t rest = index / n3;
+    const int i2 = (int)(rest % n2);
+    rest /= n2;
+    const int i1 = (int)(rest % n1);
+    const int i0 = (int)(rest / n1);
+    const double v0 = axis_value(g[6], g[10], n0, i0);
+    const double v1 = axis_value(g[7], g[11], n1, i1);
+    const double v2 = axis_value(g[8], g[12], n2, i2);
+    const double v3 = axis_value(g[9], g[13], n3, i3);
+    const double x0 = g[0], y0 = g[1], z0 = g[2];
+    const double px0 = g[3], py0 = g[4], pz0 = g[5];
+    const double r0 = sqrt(x0 * x0 + y0 * y0);
+    double ca, sa;
+    half_angle_rotation(v0 / (2.0 * r0), ca, sa);
+    const double pt0 = sqrt(px0 * px0 + py0 * py0);
+    const double p0 = sqrt((px0 * px0 + py0 * py0) + pz0 * pz0);
+    const double ct0 = pz0 / p0, st0 = pt0 / p0;
+    const double cp0 = px0 / pt0, sp0 = py0 / pt0;
+    double cdt, sdt, cdp, sdp;
+    half_angle_rotation(v2 * 0.5, cdt, sdt);
+    half_angle_rotation(v3 * 0.5, cdp, sdp);
+    const double ct = ct0 * cdt - st0 * sdt;
+    const double st = st0 * cdt + ct0 * sdt;
+    const double cp = cp0 * cdp - sp0 * sdp;
+    const double sp = sp0 * cdp + cp0 * sdp;
+    out[0] = x0 * ca - y0 * sa;
+    out[1] = y0 * ca + x0 * sa;
+    out[2] = z0;
+    out[3] = v1 * (st * cp);
+    out[4] = v1 * (st * sp);
+    out[5] = v1 * ct;
+}
+
+// Finer re-scan around seed b (Sec. 2.1): each axis with n > 1 is re-centred on b's
+// value and its half-span becomes one spacing, (2 half) / (n - 1). b < 0: no change.
+__device__ __forceinline__ void refine_grid_desc(double *__restrict__ g, int n0, int n1, int n2,
+                                                 int n3, int64_t b)
+{
+    if (b < 0)
+        return;
+    const int n[4] = {n0, n1, n2, n3};
+    int idx[4];
+    int64_t rest = b;
+    for (int a = 3; a >= 0; --a) {
+        idx[a] = (int)(rest % n[a]);
+        rest /= n[a];
+    }
+    for (int a = 0; a < 4; ++a) {
+        if (n[a] > 1) {
+            const double v = axis_value(g[6 + a], g[10 + a], n[a], idx[a]);
+            g[6 + a] = v;
+            g[10 + a] = (2.0 * g[10 + a]) / (double)(n[a] - 1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ selection
+// (value, index) pairs; index < 0 means "nothing yet". a beats b when b is empty,
+// or a.v < b.v, or a.v == b.v and a.i < b.i. NaN is never stored.
+struct MinLoc {
+    double v;
+    int64_t i;
+};
+
+__device__ __forceinline__ bool beats(const MinLoc &a, const MinLoc &b)
+{
+    if (a.i < 0)
+        return false;
+    if (b.i < 0)
+        return true;
+    return a.v < b.v || (a.v == b.v && a.i < b.i);
+}
+
+constexpr int kSelectThreads = 1024;
+
+// First index of the smallest of rss[0..S) (NaN never chosen, -1 if all are NaN), by
+// a block of kSelectThreads threads; the result is valid in thread 0.
+__device__ __forceinline__ int64_t block_argmin(const double *__restrict__ rss, int64_t S)
+{
+    __shared__ double sv[kSelectThreads / 64];
+    __shared__ int64_t si[kSelectThreads / 64];
+    MinLoc m{INFINITY, -1};
+    for (int64_t s = threadIdx.x; s < S; s += kSelectThreads) {
+        const double v = rss[s];
+        if (v < m.v || (m.i < 0 && v == m.v)) {
+            m.v = v;
+            m.i = s;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        MinLoc o{__shfl_xor(m.v, off), __shfl_xor(m.i, off)};
+        if (beats(o, m))
+            m = o;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sv[wave] = m.v;
+        si[wave] = m.i;
+    }
+    __syncthreads();
+    MinLoc a{INFINITY, -1};
+    if (wave == 0) {
+        if (lane < kSelectThreads / 64) {
+            a.v = sv[lane];
+            a.i = si[lane];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            MinLoc o{__shfl_xor(a.v, off), __shfl_xor(a.i, off)};
+            if (beats(o, a))
+                a = o;
+        }
+    }
+    return a.i;
+}
+
 // ------------------------------------------------------------------ RK4 step
 // Alg. 1's stepping. ODE in path length: dx/ds = p / p0, dp/ds = c (p_y, -p_x, 0)
 // with inv = 1 / p0 and c = ((kappa q) B_z) * inv (uniform field along z; p_z and the
@@ -143,35 +265,45 @@ __device__ __forceinline__ double chord_distance2(double axi, double aeta, doubl
 }
 
 // Alg. 2's local refinement from the closest recorded point k (value qk): the
-// squared DCA is min(qk, chord(k-1 -> k), chord(k -> k+1)). Point j of seed s is
-// track[(c P + j) S + s].
-__device__ __forceinline__ double refine_dca2(const double *__restrict__ track, int64_t S, int P,
-                                              int64_t s, const double f[8], int k, double qk)
+// squared DCA is min(qk, chord(k-1 -> k), chord(k -> k+1)). Point j is
+// (tx[j ld], ty[j ld], tz[j ld]).
+__device__ __forceinline__ double refine_dca2(const double *__restrict__ tx,
+                                              const double *__restrict__ ty,
+                                              const double *__restrict__ tz, int64_t ld, int P,
+                                              const double f[8], int k, double qk)
 {
-    const int64_t PS = (int64_t)P * S;
-    const double *t = track + s;
     double cxi, ceta;
-    project(f, t[(int64_t)k * S], t[PS + (int64_t)k * S], t[2 * PS + (int64_t)k * S], cxi, ceta);
+    const int64_t oc = (int64_t)k * ld;
+    project(f, tx[oc], ty[oc], tz[oc], cxi, ceta);
     double d2 = qk;
     if (k > 0) {
-        const int64_t o = (int64_t)(k - 1) * S;
+        const int64_t o = (int64_t)(k - 1) * ld;
         double xi, eta;
-        project(f, t[o], t[PS + o], t[2 * PS + o], xi, eta);
+        project(f, tx[o], ty[o], tz[o], xi, eta);
         const double q = fma(xi, xi, eta * eta);
         const double v = chord_distance2(xi, eta, q, cxi, ceta, qk);
         if (v < d2)
             d2 = v;
     }
     if (k < P - 1) {
-        const int64_t o = (int64_t)(k + 1) * S;
+        const int64_t o = (int64_t)(k + 1) * ld;
         double xi, eta;
-        project(f, t[o], t[PS + o], t[2 * PS + o], xi, eta);
+        project(f, tx[o], ty[o], tz[o], xi, eta);
         const double q = fma(xi, xi, eta * eta);
         const double v = chord_distance2(cxi, ceta, qk, xi, eta, q);
         if (v < d2)
             d2 = v;
     }
     return d2;
+}
+
+// The same with the seed-fastest track layout [3][P][S]: point j of seed s is
+// track[(c P + j) S + s].
+__device__ __forceinline__ double refine_dca2(const double *__restrict__ track, int64_t S, int P,
+                                              int64_t s, const double f[8], int k, double qk)
+{
+    const int64_t PS = (int64_t)P * S;
+    return refine_dca2(track + s, track + PS + s, track + 2 * PS + s, S, P, f, k, qk);
 }
 
 // Eq. 1 for one wire: d = min(lambda, min_j |D - r_j|).

@@ -86,6 +86,28 @@ class PartitionScanner:
         return out
 
 
+@dataclass
+class PackedEvents:
+    """Several events in one CSR: event e owns wires [event_wires[e], event_wires[e+1])."""
+    wire_ends: torch.Tensor     # f64 [W, 6]
+    wire_offsets: torch.Tensor  # i32 [W + 1], global hit offsets
+    drift: torch.Tensor         # f64 [H]
+    event_wires: torch.Tensor   # i32 [E + 1]
+
+    @classmethod
+    def from_events(cls, events, device="cuda"):
+        ends, offs, drift, ew = [], [0], [], [0]
+        for ev in events:
+            ends.append(ev.wire_ends)
+            offs.extend((offs[-1] + ev.wire_offsets[1:]).tolist())
+            drift.append(ev.drift)
+            ew.append(ew[-1] + ev.n_wires)
+        return cls(torch.as_tensor(np.ascontiguousarray(np.concatenate(ends)), device=device),
+                   torch.as_tensor(np.asarray(offs, dtype=np.int32), device=device),
+                   torch.as_tensor(np.ascontiguousarray(np.concatenate(drift)), device=device),
+                   torch.as_tensor(np.asarray(ew, dtype=np.int32), device=device))
+
+
 def grid_tensor(ref_state, scan_cfg, device="cuda") -> torch.Tensor:
     from .synth import grid_descriptor
     return torch.as_tensor(grid_descriptor(ref_state, scan_cfg), device=device)
@@ -94,3 +116,60 @@ def grid_tensor(ref_state, scan_cfg, device="cuda") -> torch.Tensor:
 def config_for(ev, scan_cfg) -> comet.Config:
     return comet.make_config(ev.bz, ev.charge, scan_cfg.step_mm, scan_cfg.n_steps,
                              scan_cfg.lambda_mm)
+
+
+class BatchRunner:
+    """All turn partitions of many events through comet_batch_scan (one call per run,
+    capturable into a HIP graph)."""
+
+    def __init__(self, events, scan_cfg, device="cuda"):
+        from .synth import grid_descriptor
+        self.events = list(events)
+        self.sc = scan_cfg
+        self.cfg = config_for(self.events[0], scan_cfg)
+        self.packed = PackedEvents.from_events(self.events, device)
+        part_event, grids = [], []
+        for e, ev in enumerate(self.events):
+            for t in range(ev.n_turns):
+                part_event.append(e)
+                grids.append(grid_descriptor(ev.ref_states[t], scan_cfg))
+        self.n_part = len(part_event)
+        self.part_event = torch.as_tensor(np.asarray(part_event, dtype=np.int32), device=device)
+        self.grids0 = torch.as_tensor(np.stack(grids), device=device)
+        self.grids = self.grids0.clone()
+        S = scan_cfg.n_seeds
+        f64 = dict(dtype=torch.float64, device=device)
+        self.rss = torch.empty(self.n_part, S, **f64)
+        self.best = torch.empty(self.n_part, dtype=torch.int64, device=device)
+        self.best_seed = torch.empty(self.n_part, 6, **f64)
+        self.best_rss = torch.empty(self.n_part, **f64)
+        self.stride = max(ev.n_hits for ev in self.events)
+        self.mask = torch.empty(self.n_part, self.stride, dtype=torch.uint8, device=device)
+        self.n_border = torch.empty(self.n_part, dtype=torch.int32, device=device)
+        self.workspace = comet.batch_workspace(int(self.packed.wire_ends.shape[0]),
+                                               scan_cfg.n_steps, device)
+        self.graph = None
+
+    @property
+    def evals_per_run(self) -> int:
+        """Seed x hit evaluations of one run (every scan of every partition)."""
+        hits = np.asarray([self.events[e].n_hits for e in self.part_event.cpu().numpy()])
+        return int(hits.sum()) * self.sc.n_seeds * (self.sc.n_refine + 1)
+
+    def run(self, max_items: int = 0) -> None:
+        comet.batch_scan(self.packed, self.part_event, self.grids, self.sc.n, self.cfg,
+                         self.sc.n_refine, self.rss, self.best, self.workspace,
+                         best_seed=self.best_seed, best_rss=self.best_rss, hit_mask=self.mask,
+                         n_borderline=self.n_border, max_items=max_items, grids_init=self.grids0)
+
+    def capture(self) -> None:
+        """Capture one run into a HIP graph (replay() then repeats it)."""
+        self.run()  # warm-up outside capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+
+    def replay(self) -> None:
+        self.graph.replay()

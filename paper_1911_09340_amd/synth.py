@@ -437,3 +437,14 @@ C2 = ScanConfig("mix-batched", (8, 16, 16, 16), (5.0, 5.0, 0.05, 0.05), 1000, 2.
 # Differentiation workload: coarse 8^4 grid (then Gauss-Newton) vs fine 32^4 grid.
 C3_COARSE = ScanConfig("mix-coarse", (8, 8, 8, 8), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)
 C3_FINE = ScanConfig("mix-fine", (32, 32, 32, 32), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)
+
+
+def event_mix_batch(seeds, workers: int = 0):
+    """event_mix for many seeds, in worker processes when workers > 1 (numpy only)."""
+    seeds = list(seeds)
+    if workers <= 1 or len(seeds) < 8:
+        return [event_mix(s) for s in seeds]
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        return pool.map(event_mix, seeds, chunksize=max(1, len(seeds) // (4 * workers)))

@@ -477,5 +477,20 @@ def pin_lm_truth(o, ev_exact, lam=1.0, K=1000, h=2.0):
     assert rss < 1e-4, rss
 
 
+def pin_topk(o):
+    """Top-k against an independent stable sort of (value, index) pairs."""
+    rng = np.random.default_rng(2)
+    for n, k in [(50, 7), (1000, 64), (5, 9)]:
+        v = np.round(rng.normal(size=n), 1)           # many exact ties
+        v[rng.integers(0, n, max(1, n // 10))] = np.nan
+        ok = np.nonzero(~np.isnan(v))[0]
+        order = ok[np.lexsort((ok, v[ok]))]
+        want = np.full(k, -1, dtype=np.int64)
+        want[:min(k, order.size)] = order[:k]
+        assert np.array_equal(o.topk(v, k), want), (n, k)
+    assert o.topk(np.array([2.0, 1.0, 1.0, 0.5]), 3).tolist() == [3, 1, 2]
+
+
 ALL_SIMPLE.append(pin_jacobian_straight)
+ALL_SIMPLE.append(pin_topk)
 ALL_EVENT.extend([pin_gradient_fd, pin_lm_truth])

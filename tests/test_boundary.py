@@ -116,9 +116,11 @@ def test_dca_rss_rejects(lib):
 def test_select_classify_rejects(lib):
     cfg = _cfg()
     best = _p()
-    # top_k other than 1 is not supported
-    assert lib.comet_select_classify(_p(), 64, None, 0, None, 0, None, None, 0, ctypes.byref(cfg),
-                                     2, best, None, None, None, None) == comet.EUNSUPPORTED
+    # top_k must be in [1, 1024]
+    for k in (0, 1025):
+        assert lib.comet_select_classify(_p(), 64, None, 0, None, 0, None, None, 0,
+                                         ctypes.byref(cfg), k, best, None, None, None,
+                                         None) == comet.EINVAL
     assert lib.comet_select_classify(None, 64, None, 0, None, 0, None, None, 0, ctypes.byref(cfg),
                                      1, best, None, None, None, None) == comet.EINVAL
     assert lib.comet_select_classify(_p(), 64, None, 0, None, 0, None, None, 0, ctypes.byref(cfg),
@@ -153,3 +155,42 @@ def test_binding_validates_tensors():
     with pytest.raises(ValueError):
         comet.extrapolate_seeds(torch.zeros(6, 64, dtype=torch.float64), cfg,
                                 torch.zeros(3, 11, 64, dtype=torch.float64))
+
+
+def test_adjoint_and_lm_reject(lib):
+    comet._bind_derivatives(lib)
+    cfg = _cfg()
+    ok = (_p(), 8, ctypes.byref(cfg), _p(), 4, _p(), _p(), 5)
+    assert lib.comet_rss_adjoint(None, *ok[1:], None, None, *([None] * 7), None) == comet.EINVAL
+    assert lib.comet_rss_adjoint(*ok, _p(), None, *([None] * 7), None) == comet.EINVAL
+    long_cfg = _cfg(n_steps=5000)
+    assert lib.comet_rss_adjoint(_p(), 8, ctypes.byref(long_cfg), _p(), 4, _p(), _p(), 5, None,
+                                 None, *([None] * 7), None) == comet.EUNSUPPORTED
+    need = lib.comet_lm_workspace_bytes(8)
+    assert need > 0 and need % 256 == 0
+    args = ok + (None, None)
+    assert lib.comet_lm_refine(*args, 4, 1e-3, _p(), None, _p(0x100000), 16, None) == comet.EWORKSPACE
+    assert lib.comet_lm_refine(*args, -1, 1e-3, _p(), None, _p(0x100000), need, None) == comet.EINVAL
+    assert lib.comet_lm_refine(*args, 4, 0.0, _p(), None, _p(0x100000), need, None) == comet.EINVAL
+    assert lib.comet_lm_refine(*args, 4, 1e-3, None, None, _p(0x100000), need, None) == comet.EINVAL
+
+
+def test_batch_topk_and_seed_rejects(lib):
+    comet._bind_batch(lib)
+    assert lib.comet_topk(None, 10, 1, 1, _p(), None) == comet.EINVAL
+    assert lib.comet_topk(_p(), 10, 1, 0, _p(), None) == comet.EINVAL
+    assert lib.comet_topk(_p(), 0, 1, 1, _p(), None) == comet.EINVAL
+    assert lib.comet_grid_seeds(_p(), 2, _n4(2, 2, 0, 2), _p(), 1, _p(), None) == comet.EINVAL
+    need = lib.comet_batch_workspace_bytes(100, 1000)
+    assert need > 0 and need % 256 == 0
+    cfg = _cfg()
+    args = [_p(), 10, _p(), _p(), 20, _p(), 2, _p(), 3, None, _p(), _n4(2, 2, 2, 2),
+            ctypes.byref(cfg), 1, _p(), _p(), None, None, None, 0, None, 0]
+    ws = lib.comet_batch_workspace_bytes(10, 10)
+    assert lib.comet_batch_scan(*args, _p(0x100000), 16, None) == comet.EWORKSPACE
+    bad = list(args)
+    bad[13] = -1  # n_refine
+    assert lib.comet_batch_scan(*bad, _p(0x100000), ws, None) == comet.EINVAL
+    bad = list(args)
+    bad[0] = None
+    assert lib.comet_batch_scan(*bad, _p(0x100000), ws, None) == comet.EINVAL

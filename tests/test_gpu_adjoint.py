@@ -1,0 +1,200 @@
+"""GPU adjoint and Levenberg-Marquardt vs the CPU reference's dual numbers.
+
+The bar (spec form 3): gradients within 1e-7 relative of the CPU forward-mode
+dual-number gradient and of central differences. D_i and the residuals come out of
+the same forward arithmetic on both sides, so they are compared exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pins
+from paper_1911_09340_amd import autograd, comet, scan, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    comet.load()
+
+
+def _seeds_near(ref, n, rel, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.stack([ref * (1 + rng.normal(0, rel, 6)) for _ in range(n)], axis=1)
+
+
+def _gpu_adjoint(ev, seeds, cfg, packed=None, seed_event=None):
+    S = seeds.shape[1]
+    dev = packed if packed is not None else scan.DeviceEvent.from_event(ev)
+    n_w = dev.wire_ends.shape[0]
+    t = lambda *sh: torch.empty(*sh, dtype=torch.float64, device="cuda")
+    out = dict(rss=t(S), grad=t(S, 6), jtj=t(S, 21), jte=t(S, 6), dca=t(S, n_w), resid=t(S, n_w),
+               jac=t(S, n_w, 6))
+    comet.rss_adjoint(torch.as_tensor(seeds, device="cuda"), cfg, dev.wire_ends,
+                      dev.wire_offsets, dev.drift,
+                      event_wires=getattr(dev, "event_wires", None) if seed_event is not None else None,
+                      seed_event=seed_event, **out)
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _compare_to_duals(orc, ev, seeds, sc, got, wire_slice=slice(None)):
+    ocfg = [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+    for s in range(seeds.shape[1]):
+        want = orc.rss_jacobian(seeds[:, s], ocfg, sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                                ev.drift)
+        D = got["dca"][s, wire_slice]
+        assert np.array_equal(D, want["D"]), s
+        r = got["resid"][s, wire_slice]
+        assert np.array_equal(np.isnan(r), np.isnan(want["resid"]))
+        assert np.array_equal(r[~np.isnan(r)], want["resid"][~np.isnan(want["resid"])])
+        assert abs(got["rss"][s] - want["rss"]) <= 1e-13 * want["rss"]
+        scale = np.max(np.abs(want["grad"]))
+        assert np.max(np.abs(got["grad"][s] - want["grad"])) <= 1e-7 * scale, (s, got["grad"][s],
+                                                                               want["grad"])
+        act = want["active"]
+        J = got["jac"][s, wire_slice]
+        jw = want["J"][act]
+        assert np.max(np.abs(J[act] - jw)) <= 1e-7 * np.max(np.abs(jw)), s
+        assert np.all(J[~act] == 0.0)
+        A = np.zeros((6, 6))
+        k = 0
+        for i in range(6):
+            for j in range(i, 6):
+                A[i, j] = A[j, i] = got["jtj"][s, k]
+                k += 1
+        Aw = jw.T @ jw
+        assert np.max(np.abs(A - Aw)) <= 1e-7 * np.max(np.abs(Aw))
+        bw = jw.T @ want["resid"][act]
+        assert np.max(np.abs(got["jte"][s] - bw)) <= 1e-7 * np.max(np.abs(bw))
+
+
+def test_adjoint_matches_duals_plain(orc, ev_plain):
+    sc = synth.C0
+    seeds = _seeds_near(ev_plain.ref_states[0], 12, 2e-3)
+    got = _gpu_adjoint(ev_plain, seeds, scan.config_for(ev_plain, sc))
+    _compare_to_duals(orc, ev_plain, seeds, sc, got)
+
+
+def test_adjoint_matches_duals_signal(orc, ev_signal):
+    sc = synth.C1
+    seeds = np.concatenate([_seeds_near(ev_signal.ref_states[t], 4, 1e-3, t) for t in range(3)],
+                           axis=1)
+    got = _gpu_adjoint(ev_signal, seeds, scan.config_for(ev_signal, sc))
+    _compare_to_duals(orc, ev_signal, seeds, sc, got)
+
+
+def test_adjoint_packed_events(orc):
+    """Seeds of three different events in one launch (event_wires / seed_event)."""
+    evs = [synth.event_mix(i) for i in range(3)]
+    sc = synth.C2
+    packed = scan.PackedEvents.from_events(evs)
+    seeds = np.concatenate([_seeds_near(ev.ref_states[0], 3, 1e-3, i) for i, ev in enumerate(evs)],
+                           axis=1)
+    se = torch.tensor(np.repeat(np.arange(3), 3), dtype=torch.int32, device="cuda")
+    got = _gpu_adjoint(None, seeds, scan.config_for(evs[0], sc), packed=packed, seed_event=se)
+    w0 = 0
+    for i, ev in enumerate(evs):
+        sub = {k: (v[3 * i:3 * i + 3] if v.ndim >= 1 else v) for k, v in got.items()}
+        _compare_to_duals(orc, ev, seeds[:, 3 * i:3 * i + 3], sc, sub, slice(w0, w0 + ev.n_wires))
+        w0 += ev.n_wires
+
+
+def test_adjoint_matches_central_differences(ev_plain):
+    """Gradient of the GPU RSS (forward path) by central differences, h = 1e-6 relative."""
+    sc = synth.C0
+    cfg = scan.config_for(ev_plain, sc)
+    o = oracle.Oracle()
+    ocfg = [ev_plain.bz, ev_plain.charge, sc.step_mm, sc.lambda_mm]
+    dev = scan.DeviceEvent.from_event(ev_plain)
+    rng = np.random.default_rng(9)
+    tested = 0
+    for _ in range(10):
+        seed = ev_plain.ref_states[0] * (1 + rng.normal(0, 2e-3, 6))
+        if not pins._kink_free(o, seed, ev_plain, ocfg, sc.n_steps):
+            continue
+        cols = [seed]
+        hs = []
+        for c in range(6):
+            h = 1e-6 * max(abs(seed[c]), 1.0)
+            hs.append(h)
+            for sgn in (1, -1):
+                sp = seed.copy()
+                sp[c] += sgn * h
+                cols.append(sp)
+        X = torch.as_tensor(np.stack(cols, axis=1), device="cuda")
+        rss = autograd.seed_rss(X, dev, cfg).cpu().numpy()
+        fd = np.array([(rss[1 + 2 * c] - rss[2 + 2 * c]) / (2 * hs[c]) for c in range(6)])
+        g = _gpu_adjoint(ev_plain, seed[:, None], cfg)["grad"][0]
+        assert np.max(np.abs(g - fd)) <= 1e-7 * np.max(np.abs(g)), (g, fd)
+        tested += 1
+        if tested == 3:
+            break
+    assert tested >= 2
+
+
+def test_autograd_function(ev_plain):
+    sc = synth.C0
+    cfg = scan.config_for(ev_plain, sc)
+    dev = scan.DeviceEvent.from_event(ev_plain)
+    seeds = torch.as_tensor(_seeds_near(ev_plain.ref_states[0], 5, 2e-3), device="cuda")
+    x = seeds.clone().requires_grad_(True)
+    rss = autograd.seed_rss(x, dev, cfg)
+    w = torch.arange(1.0, 6.0, dtype=torch.float64, device="cuda")
+    (rss * w).sum().backward()
+    got = _gpu_adjoint(ev_plain, seeds.cpu().numpy(), cfg)
+    # forward equals the scan path, backward equals w * adjoint gradient
+    track = torch.empty(3, sc.n_steps + 1, 5, dtype=torch.float64, device="cuda")
+    comet.extrapolate_seeds(seeds, cfg, track)
+    ref = torch.empty(5, dtype=torch.float64, device="cuda")
+    comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, ref,
+                  comet.dca_workspace(5, dev.n_wires))
+    assert torch.equal(rss.detach(), ref)
+    want = got["grad"] * np.arange(1.0, 6.0)[:, None]
+    assert np.array_equal(x.grad.cpu().numpy(), want.T)
+
+
+def test_lm_matches_cpu_reference(orc, ev_plain):
+    sc = synth.C0
+    cfg = scan.config_for(ev_plain, sc)
+    ocfg = [ev_plain.bz, ev_plain.charge, sc.step_mm, sc.lambda_mm]
+    dev = scan.DeviceEvent.from_event(ev_plain)
+    start = _seeds_near(ev_plain.ref_states[0], 6, 1.5e-3, 4)
+    x = torch.as_tensor(start, device="cuda").clone()
+    rss = torch.empty(6, dtype=torch.float64, device="cuda")
+    acc = torch.empty(6, dtype=torch.int32, device="cuda")
+    comet.lm_refine(x, cfg, dev.wire_ends, dev.wire_offsets, dev.drift, 8, 1e-3, rss,
+                    comet.lm_workspace(6), n_accepted=acc)
+    got = x.cpu().numpy()
+    for s in range(6):
+        ws, wrss, wacc = orc.lm_refine(start[:, s], ocfg, sc.n_steps, ev_plain.wire_ends,
+                                       ev_plain.wire_offsets, ev_plain.drift, 8, 1e-3)
+        assert np.max(np.abs(got[:, s] - ws) / np.maximum(np.abs(ws), 1.0)) < 1e-7, (s, got[:, s], ws)
+        assert abs(float(rss[s]) - wrss) <= 1e-9 * wrss
+        assert int(acc[s]) == wacc
+
+
+def test_lm_packed_equals_single(ev_plain):
+    """The batched (packed) refinement gives each seed the single-event result."""
+    evs = [synth.event_mix(i) for i in range(3)]
+    sc = synth.C2
+    cfg = scan.config_for(evs[0], sc)
+    packed = scan.PackedEvents.from_events(evs)
+    starts = [_seeds_near(ev.ref_states[0], 2, 1e-3, i) for i, ev in enumerate(evs)]
+    x = torch.as_tensor(np.concatenate(starts, axis=1), device="cuda").clone()
+    se = torch.tensor([0, 0, 1, 1, 2, 2], dtype=torch.int32, device="cuda")
+    rss = torch.empty(6, dtype=torch.float64, device="cuda")
+    comet.lm_refine(x, cfg, packed.wire_ends, packed.wire_offsets, packed.drift, 6, 1e-3, rss,
+                    comet.lm_workspace(6), event_wires=packed.event_wires, seed_event=se)
+    for i, ev in enumerate(evs):
+        dev = scan.DeviceEvent.from_event(ev)
+        y = torch.as_tensor(starts[i], device="cuda").clone()
+        r1 = torch.empty(2, dtype=torch.float64, device="cuda")
+        comet.lm_refine(y, cfg, dev.wire_ends, dev.wire_offsets, dev.drift, 6, 1e-3, r1,
+                        comet.lm_workspace(2))
+        assert torch.equal(x[:, 2 * i:2 * i + 2], y)
+        assert torch.equal(rss[2 * i:2 * i + 2], r1)

@@ -1,0 +1,209 @@
+"""Batched persistent path (many uneven events) vs the single-event path and the CPU
+reference; top-k selection; HIP-graph capture and replay."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_09340_amd import comet, refine, scan, synth
+
+pytestmark = pytest.mark.gpu
+
+SC = synth.ScanConfig("batch-test", (2, 4, 5, 7), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 2)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    comet.load()
+    yield
+    comet.set_batch_variant(0)
+
+
+@pytest.fixture(scope="module")
+def events():
+    return [synth.event_mix(i) for i in range(6)]
+
+
+def _single(ev, turn, sc):
+    cfg = scan.config_for(ev, sc)
+    r = scan.PartitionScanner(sc.n, cfg, ev.n_wires, ev.n_hits)
+    r.run(scan.DeviceEvent.from_event(ev), scan.grid_tensor(ev.ref_states[turn], sc), sc.n_refine)
+    torch.cuda.synchronize()
+    out = r.result()
+    out["rss"] = r.rss.cpu().numpy()
+    return out
+
+
+def _check_against_single(runner, events, sc):
+    rss = runner.rss.cpu().numpy()
+    best = runner.best.cpu().numpy()
+    grids = runner.grids.cpu().numpy()
+    seeds = runner.best_seed.cpu().numpy()
+    brss = runner.best_rss.cpu().numpy()
+    mask = runner.mask.cpu().numpy()
+    nb = runner.n_border.cpu().numpy()
+    p = 0
+    for ev in events:
+        for t in range(ev.n_turns):
+            want = _single(ev, t, sc)
+            assert best[p] == want["best"], p
+            assert np.array_equal(grids[p], want["grid"]), p
+            assert np.array_equal(rss[p], want["rss"]), p
+            assert np.array_equal(seeds[p], want["best_seed"]), p
+            assert brss[p] == want["best_rss"], p
+            assert np.array_equal(mask[p, :ev.n_hits], want["mask"]), p
+            assert nb[p] == want["n_borderline"], p
+            p += 1
+
+
+def test_batch_equals_single_event_path(events):
+    runner = scan.BatchRunner(events, SC)
+    assert runner.n_part == sum(ev.n_turns for ev in events) and runner.n_part > 6
+    runner.run()
+    torch.cuda.synchronize()
+    _check_against_single(runner, events, SC)
+
+
+def test_batch_every_shape_identical(events):
+    ref = None
+    for i in range(len(comet.batch_variants())):
+        comet.set_batch_variant(i)
+        runner = scan.BatchRunner(events[:3], SC)
+        runner.run()
+        got = (runner.rss.cpu().numpy(), runner.best.cpu().numpy(), runner.mask.cpu().numpy())
+        if ref is None:
+            ref = got
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(got, ref)), i
+    comet.set_batch_variant(0)
+
+
+def test_batch_matches_cpu_reference(orc, events):
+    runner = scan.BatchRunner(events[:2], SC)
+    runner.run()
+    torch.cuda.synchronize()
+    p = 0
+    for ev in events[:2]:
+        for t in range(ev.n_turns):
+            want = orc.scan_partition(synth.grid_descriptor(ev.ref_states[t], SC),
+                                      np.array(SC.n, np.int32),
+                                      [ev.bz, ev.charge, SC.step_mm, SC.lambda_mm], SC.n_steps,
+                                      SC.n_refine, ev.wire_ends, ev.wire_offsets, ev.drift)
+            assert int(runner.best[p]) == want["best"]
+            assert np.array_equal(runner.rss[p].cpu().numpy(), want["rss"])
+            assert np.array_equal(runner.best_seed[p].cpu().numpy(), want["best_seed"])
+            assert np.array_equal(runner.mask[p, :ev.n_hits].cpu().numpy(), want["mask"])
+            p += 1
+
+
+def test_graph_capture_replays_match_eager(events):
+    """Captured once, replayed several times with eager work in between."""
+    runner = scan.BatchRunner(events[:4], SC)
+    runner.run()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in (runner.rss, runner.best, runner.best_seed, runner.mask,
+                                 runner.grids)]
+    runner.capture()
+    for rep in range(3):
+        for t in (runner.rss, runner.best_seed, runner.grids):
+            t.fill_(float("nan"))
+        runner.mask.fill_(7)
+        runner.replay()
+        torch.cuda.synchronize()
+        got = (runner.rss, runner.best, runner.best_seed, runner.mask, runner.grids)
+        assert all(torch.equal(a, b) for a, b in zip(got, eager)), rep
+        _ = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+
+
+def test_max_items_scans_a_prefix(events):
+    runner = scan.BatchRunner(events[:2], replace(SC, n_refine=0))
+    runner.rss.fill_(-1.0)
+    runner.run(max_items=3)
+    torch.cuda.synchronize()
+    flat = runner.rss.cpu().numpy().ravel()
+    S = SC.n_seeds
+    tiles = (S + 63) // 64
+    done = np.zeros_like(flat, dtype=bool)
+    for item in range(3):
+        p, t = divmod(item, tiles)
+        done[p * S + t * 64:p * S + min(S, (t + 1) * 64)] = True
+    assert np.all(flat[done] >= 0) and np.all(flat[~done] == -1.0)
+
+
+def test_topk_matches_cpu_reference(orc):
+    rng = np.random.default_rng(4)
+    v = np.round(rng.normal(size=(3, 5000)), 2)
+    v[0, rng.integers(0, 5000, 300)] = np.nan
+    v[2, :] = np.nan
+    v[2, 17] = 1.0
+    out = torch.empty(3, 64, dtype=torch.int64, device="cuda")
+    comet.topk(torch.as_tensor(v, device="cuda"), 64, out)
+    for r in range(3):
+        assert np.array_equal(out[r].cpu().numpy(), orc.topk(v[r], 64)), r
+
+
+def test_select_classify_top_k(orc, ev_plain):
+    sc = synth.C0
+    g = synth.grid_descriptor(ev_plain.ref_states[0], sc)
+    cfg = scan.config_for(ev_plain, sc)
+    seeds = torch.empty(6, sc.n_seeds, dtype=torch.float64, device="cuda")
+    comet.seed_grid(torch.as_tensor(g, device="cuda"), sc.n, seeds)
+    track = torch.empty(3, sc.n_steps + 1, sc.n_seeds, dtype=torch.float64, device="cuda")
+    comet.extrapolate_seeds(seeds, cfg, track)
+    dev = scan.DeviceEvent.from_event(ev_plain)
+    rss = torch.empty(sc.n_seeds, dtype=torch.float64, device="cuda")
+    comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss,
+                  comet.dca_workspace(sc.n_seeds, dev.n_wires))
+    best = torch.empty(64, dtype=torch.int64, device="cuda")
+    mask = torch.empty(ev_plain.n_hits, dtype=torch.uint8, device="cuda")
+    comet.select_classify(rss, best, cfg, track, dev.wire_ends, dev.wire_offsets, dev.drift,
+                          hit_mask=mask, top_k=64)
+    want = orc.topk(rss.cpu().numpy(), 64)
+    assert np.array_equal(best.cpu().numpy(), want)
+    wmask, _, _ = orc.classify(orc.seed(g, np.array(sc.n, np.int32), int(want[0])),
+                               [ev_plain.bz, ev_plain.charge, sc.step_mm, sc.lambda_mm],
+                               sc.n_steps, ev_plain.wire_ends, ev_plain.wire_offsets,
+                               ev_plain.drift)
+    assert np.array_equal(mask.cpu().numpy(), wmask)
+
+
+def test_grid_seeds_match_cpu_reference(orc, events):
+    runner = scan.BatchRunner(events[:2], SC)
+    idx = torch.tensor([[0, 5, SC.n_seeds - 1, -1]] * runner.n_part, dtype=torch.int64,
+                       device="cuda")
+    out = torch.empty(6, runner.n_part * 4, dtype=torch.float64, device="cuda")
+    comet.grid_seeds(runner.grids0, SC.n, idx, out)
+    got = out.cpu().numpy()
+    g0 = runner.grids0.cpu().numpy()
+    for p in range(runner.n_part):
+        for r, i in enumerate([0, 5, SC.n_seeds - 1]):
+            assert np.array_equal(got[:, p * 4 + r], orc.seed(g0[p], np.array(SC.n, np.int32), i))
+        assert np.all(np.isnan(got[:, p * 4 + 3]))
+
+
+def test_multistart_refinement_matches_cpu_lm(orc, events):
+    """coarse_then_lm: every start's LM result equals the CPU LM from the same start."""
+    sc = synth.ScanConfig("c", (4, 4, 4, 4), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)
+    evs = events[:2]
+    out = refine.coarse_then_lm(evs, sc, top_k=3, n_iter=6)
+    final = out["refined"].cpu().numpy()
+    p = 0
+    o = oracle.Oracle()
+    for ev in evs:
+        cfg = [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+        for t in range(ev.n_turns):
+            g = synth.grid_descriptor(ev.ref_states[t], sc)
+            seeds = o.seed_grid(g, np.array(sc.n, np.int32))
+            rss, _ = o.scan(seeds, cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+            starts = o.topk(rss, 3)
+            res = [o.lm_refine(seeds[:, i], cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                               ev.drift, 6, 1e-3) for i in starts]
+            best = min(range(3), key=lambda r: (res[r][1], r))
+            ws = res[best][0]
+            assert np.max(np.abs(final[:, p] - ws) / np.maximum(np.abs(ws), 1.0)) < 1e-7, p
+            p += 1

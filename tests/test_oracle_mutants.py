@@ -47,6 +47,7 @@ MUTANTS = {
     "dual_fma_drops_c": ("r.d[i] = a.d[i] * b.v + a.v * b.d[i] + c.d[i];", "r.d[i] = a.d[i] * b.v + a.v * b.d[i];"),
     "lm_accepts_worse": ("        if (rss2 < rss) {\n            for (int r = 0; r < 6; ++r) {", "        if (rss2 > rss) {\n            for (int r = 0; r < 6; ++r) {"),
     "lm_gradient_sign": ("            rhs[r] = -b[r];", "            rhs[r] = b[r];"),
+    "topk_ties_reversed": ("    return x->i < y->i ? -1 : (x->i > y->i ? 1 : 0);", "    return x->i > y->i ? -1 : (x->i < y->i ? 1 : 0);"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
