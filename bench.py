@@ -30,7 +30,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, dense
+# MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flop x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 FLOP_PER_POINT_WIRE = 15  # 6 FMA (in-plane coordinates) + 1 MUL + 1 FMA (squared distance)
 METRIC = ("seed×hit DCA evals/s and events/s (FP64 % peak); "
@@ -273,7 +274,7 @@ def main():
         "events_per_s": args.steps / dt,
         "roofline": {
             "kernel": "dca_kernel",
-            "bound": "fp64-valu",
+            "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
