@@ -38,7 +38,7 @@ METRIC = ("seed×hit DCA evals/s and events/s (FP64 % peak); "
           "grad-refine vs fine-grid time")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dca_traffic.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1911_09340_amd", "csrc", f)
-               for f in ("comet.hip", "device_math.h")]
+               for f in ("comet.hip", "device_math.h", "dca_scan.h")]
 
 
 def log(*a):
@@ -54,14 +54,17 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
-    """HBM bytes per DCA launch from the committed counter runs, if still current."""
+def stored_traffic(shape: dict):
+    """HBM bytes per DCA launch from the committed counter runs, if they were taken with
+    the current kernel sources and the same kernel shape."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_hash():
+    name = "dca_kernel<%d, %d, %d, %s>" % (shape["w"], shape["nwv"], shape["chunk"],
+                                          "true" if shape["chunk_argmin"] else "false")
+    if t.get("kernel_sha") != kernel_hash() or t.get("kernel") != name:
         return None
     return t.get("bytes_per_launch")
 
@@ -107,7 +110,17 @@ def bench_batch(events, sc, reps: int = 2):
     """Every partition of `events` through the batched path, captured in a HIP graph."""
     import torch
     from paper_1911_09340_amd import comet, scan
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    packed = scan.PackedEvents.from_events(events)   # host CSR pack + copy to the device
+    torch.cuda.synchronize()
+    pack_s = time.perf_counter() - t0
+    del packed
     runner = scan.BatchRunner(events, sc)
+    tune = runner.autotune()
+    log("  batched kernel shape %d %s; ms per scan of %d items: %s"
+        % (tune["variant"], tune["shape"], tune["items"],
+           ", ".join("%.2f" % m for m in tune["ms_per_scan"])))
     runner.capture()
     runner.replay()
     torch.cuda.synchronize()
@@ -133,12 +146,14 @@ def bench_batch(events, sc, reps: int = 2):
             "scans_per_partition": scans, "rk4_steps": sc.n_steps,
             "hits_min_mean_max": [min(hits), float(np.mean(hits)), max(hits)],
             "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "host_pack_and_copy_s": pack_s,
             "evals_per_s": runner.evals_per_run / dt,
             "scan_kernel_ms_per_run": scan_ms,
             "scan_fp64_tflops": flops / (scan_ms * 1e-3) / 1e12,
             "scan_fp64_frac": flops / (scan_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "kernel_shape": tune["shape"],
             "graph": "one HIP graph per run (frames, per scan: refine, counter reset, "
-                     "persistent scan, argmin; classification)"}
+                     "persistent scan with in-kernel selection; classification)"}
 
 
 def main():
@@ -244,7 +259,7 @@ def main():
     achieved = flops / dca_s / 1e12
     ms_trk, n_trk = prof["track"]
     trk_bytes = 8 * 3 * P * sc.n_seeds + 8 * 6 * sc.n_seeds
-    traffic = stored_traffic()
+    traffic = stored_traffic(variants[variant])
 
     out = {
         "metric": METRIC,

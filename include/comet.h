@@ -206,9 +206,11 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
  * from an atomic counter, build the seeds from the descriptor, record their RK4
  * tracks into per-block scratch (no track array in HBM) and scan the partition's
  * event wires; per-seed RSS are summed in wire order and equal those of
- * comet_dca_rss bit for bit. The calls on `stream` are: a wire-frame kernel, then per
- * scan [refine (not before the first), counter reset, scan, per-partition argmin],
- * then classification. No host synchronisation and no allocation: capturable.
+ * comet_dca_rss bit for bit. A per-partition completion counter lets the block that
+ * finishes a partition's last tile select its best seed inside the same launch. The
+ * calls on `stream` are: a wire-frame kernel, then per scan [refine (not before the
+ * first), counter reset, persistent scan], then classification. No host
+ * synchronisation and no allocation: capturable.
  *   wire_ends, wire_offsets, drift   packed events, device (n_wires >= 1)
  *   event_wires  device int32[n_events + 1]; part_event device int32[n_partitions]
  *   grids_init   device double[n_partitions][14] or NULL: copied into grids first (by
@@ -226,8 +228,9 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
  *   n_borderline device int32[n_partitions] or NULL
  *   max_items    > 0: scan only the first max_items (partition, tile) items of every
  *                scan (for timing shapes; the other RSS are not written)
- *   workspace    >= comet_batch_workspace_bytes(n_wires, n_steps), 256-byte aligned */
-size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps);
+ *   workspace    >= comet_batch_workspace_bytes(n_wires, n_steps, n_partitions),
+ *                256-byte aligned */
+size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps, int32_t n_partitions);
 int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
                      const double *drift, int32_t n_hits, const int32_t *event_wires,
                      int32_t n_events, const int32_t *part_event, int32_t n_partitions,
@@ -276,10 +279,11 @@ int comet_profile_end(double ms[COMET_PROFILE_KINDS], int64_t launches[COMET_PRO
  *
  * comet_dca_autotune() takes the arguments of comet_dca_rss (same checks, same
  * result in rss) plus: reps (1..1000) timed launches per shape, best_id (host, may be
- * NULL) receiving the fastest shape, ms (host, may be NULL, comet_dca_variant_count()
- * entries) receiving each shape's mean kernel time. It records the fastest shape for
- * this (n_seeds, n_points, n_wires) and later comet_dca_rss calls of that shape use
- * it. Unlike the other calls it creates two HIP events and synchronises `stream`: it
+ * NULL) receiving the chosen shape, ms (host, may be NULL, comet_dca_variant_count()
+ * entries) receiving each shape's mean kernel time. It chooses, among the shapes
+ * within 1 % of the fastest, the one with the fewest wire groups (each group reads
+ * the seed tile's track once more), records it for this (n_seeds, n_points, n_wires),
+ * and later comet_dca_rss calls of that size use it. Unlike the other calls it creates two HIP events and synchronises `stream`: it
  * is a set-up call, not one for a timed loop.
  *
  * comet_dca_set_variant(id) forces shape id for every call (-1 removes the override);

@@ -191,7 +191,7 @@ def select_classify(rss: torch.Tensor, best: torch.Tensor, cfg: Config, track=No
         _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6), optional=True), n_w,
         _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,), optional=True),
         _ptr(drift, torch.float64, "drift", (n_h,), optional=True), n_h, ctypes.byref(cfg),
-        int(top_k), _ptr(best, torch.int64, "best", (1,)),
+        int(top_k), _ptr(best, torch.int64, "best", (int(top_k),)),
         _ptr(hit_mask, torch.uint8, "hit_mask", (n_h,), optional=True),
         _ptr(n_borderline, torch.int32, "n_borderline", (1,), optional=True),
         _ptr(dca_best, torch.float64, "dca_best", (n_w,), optional=True), _stream()),
@@ -330,7 +330,7 @@ def _bind_batch(lib):
     if getattr(lib, "_batch_bound", False):
         return lib
     I4 = ctypes.POINTER(ctypes.c_int32)
-    lib.comet_batch_workspace_bytes.argtypes = [_i32, _i32]
+    lib.comet_batch_workspace_bytes.argtypes = [_i32, _i32, _i32]
     lib.comet_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.comet_batch_scan.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp, I4,
                                      ctypes.POINTER(Config), _i32, _vp, _vp, _vp, _vp, _vp, _i64,
@@ -349,8 +349,9 @@ def _bind_batch(lib):
     return lib
 
 
-def batch_workspace(n_wires: int, n_steps: int, device=None) -> torch.Tensor:
-    nbytes = int(_bind_batch(load()).comet_batch_workspace_bytes(int(n_wires), int(n_steps)))
+def batch_workspace(n_wires: int, n_steps: int, n_partitions: int, device=None) -> torch.Tensor:
+    nbytes = int(_bind_batch(load()).comet_batch_workspace_bytes(int(n_wires), int(n_steps),
+                                                                 int(n_partitions)))
     return torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=device or "cuda")
 
 

@@ -46,18 +46,24 @@ struct BatchArgs {
     double bz, charge, h, lambda;
     int K;
     double *scratch;          // [blocks][3][P][64]
-    int *counter;
+    int *counter;             // work queue
+    int *done;                // [NP] tiles finished per partition
     double *rss;              // [NP][S]
+    int64_t *best;            // [NP]
 };
 
-template <int W, int NWV, int C>
-__global__ __launch_bounds__(64 * NWV) void batch_scan_kernel(BatchArgs a)
+// WPE: waves per SIMD the register allocation must allow (2 blocks of 8 waves per CU
+// need 4), so that one block's track recording overlaps another block's scan.
+template <int W, int NWV, int C, int WPE>
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
+batch_scan_kernel(BatchArgs a)
 {
     using Scan = TileScan<W, NWV, C, true>;
     constexpr int G = W * NWV;  // wires per group
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];
     __shared__ double dd[G * 64];
-    __shared__ int64_t item_s;
+    __shared__ int item_s;
+    __shared__ int last_s;
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -66,11 +72,17 @@ __global__ __launch_bounds__(64 * NWV) void batch_scan_kernel(BatchArgs a)
     double *sx = a.scratch + (int64_t)blockIdx.x * 3 * row;
     double *sy = sx + row, *sz = sy + row;
 
+    // Control flow around the barriers stays wave-uniform: counters are bumped by a
+    // whole wave (lane 0 adds 1, the others 0) and results are broadcast with
+    // readfirstlane, never by a region that only thread 0 enters (the compiler may
+    // move such a region across the loop's back edge, apart from its wave's barriers).
     for (;;) {
-        if (threadIdx.x == 0)
-            item_s = atomicAdd(a.counter, 1);
+        if (wave == 0) {
+            const int old = atomicAdd(a.counter, lane == 0 ? 1 : 0);
+            item_s = __builtin_amdgcn_readfirstlane(old);
+        }
         __syncthreads();
-        const int64_t item = item_s;
+        const int64_t item = __builtin_amdgcn_readfirstlane(item_s);
         __syncthreads();
         if (item >= a.n_items)
             break;
@@ -107,7 +119,12 @@ __global__ __launch_bounds__(64 * NWV) void batch_scan_kernel(BatchArgs a)
             for (int w = 0; w < W; ++w)
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    f[w][j] = a.frames[8 * (int64_t)(wbase + w) + j];
+                {
+                    // wave-uniform: keep the frames in scalar registers
+                    const double v = a.frames[8 * (int64_t)(wbase + w) + j];
+                    f[w][j] = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                                               __builtin_amdgcn_readfirstlane(__double2loint(v)));
+                }
             double d2[W];
             Scan::run(sx, sy, sz, 64, P, n_valid, true, f, nw, a.offsets + (nw > 0 ? wbase : 0),
                       a.drift, a.lambda, lds, d2);
@@ -124,17 +141,25 @@ __global__ __launch_bounds__(64 * NWV) void batch_scan_kernel(BatchArgs a)
         }
         if (wave == 0 && lane < n_valid)
             a.rss[(int64_t)p * a.S + s0 + lane] = acc;
-    }
-}
 
-// One block per partition: argmin of its RSS (first index of the smallest, NaN never).
-__global__ __launch_bounds__(kSelectThreads) void batch_argmin_kernel(const double *__restrict__ rss,
-                                                                      int64_t S,
-                                                                      int64_t *__restrict__ best)
-{
-    const int64_t b = block_argmin(rss + (int64_t)blockIdx.x * S, S);
-    if (threadIdx.x == 0)
-        best[blockIdx.x] = b;
+        // Completion counter of partition p: the tile's RSS are made visible device-wide
+        // before the count; the block that finishes the partition's last tile selects its
+        // best seed (Sec. 2.1) while other blocks keep scanning.
+        __threadfence();
+        __syncthreads();
+        if (wave == 0) {
+            const int old = atomicAdd(a.done + p, lane == 0 ? 1 : 0);
+            last_s = __builtin_amdgcn_readfirstlane(old) == a.tiles - 1;
+        }
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(last_s)) {
+            __threadfence();
+            const int64_t b = block_argmin_n<64 * NWV>(a.rss + (int64_t)p * a.S, a.S);
+            if (wave == 0)  // every lane of wave 0 holds the result
+                a.best[p] = b;
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void batch_refine_kernel(int n_part, double *__restrict__ grids, int n0, int n1, int n2,
@@ -336,7 +361,17 @@ __global__ void batch_frames_kernel(const double *__restrict__ ends, int n_w, in
         frames[8 * (int64_t)w + j] = f[j];
 }
 
-__global__ void zero_counter_kernel(int *c) { *c = 0; }
+// Start of a scan: empty work queue, no tile finished, no partition selected yet.
+__global__ void reset_scan_kernel(int *counter, int *done, int64_t *best, int n_part)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0)
+        *counter = 0;
+    if (p < n_part) {
+        done[p] = 0;
+        best[p] = -1;
+    }
+}
 
 __global__ void copy_kernel(const double *__restrict__ src, double *__restrict__ dst, int64_t n)
 {
@@ -352,12 +387,13 @@ struct BatchVariant {
 };
 
 const BatchVariant kBatchVariants[] = {
-    {5, 8, 16, batch_scan_kernel<5, 8, 16>},
-    {6, 8, 16, batch_scan_kernel<6, 8, 16>},
-    {4, 8, 16, batch_scan_kernel<4, 8, 16>},
-    {4, 8, 32, batch_scan_kernel<4, 8, 32>},
-    {4, 12, 16, batch_scan_kernel<4, 12, 16>},
-    {3, 8, 32, batch_scan_kernel<3, 8, 32>},
+    {4, 8, 16, batch_scan_kernel<4, 8, 16, 4>},
+    {3, 8, 16, batch_scan_kernel<3, 8, 16, 4>},
+    {2, 8, 16, batch_scan_kernel<2, 8, 16, 4>},
+    {4, 8, 16, batch_scan_kernel<4, 8, 16, 1>},
+    {5, 8, 16, batch_scan_kernel<5, 8, 16, 1>},
+    {4, 12, 16, batch_scan_kernel<4, 12, 16, 1>},
+    {3, 8, 32, batch_scan_kernel<3, 8, 32, 1>},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 constexpr int kBatchWirePad = 64;  // >= the largest W * NWV above
@@ -394,10 +430,11 @@ int frames_pad(int n_w) { return ((n_w + 63) / 64) * 64 + kBatchWirePad; }
 struct BatchLayout {
     double *frames;
     int *counter;
+    int *done;
     double *scratch;
 };
 
-BatchLayout batch_layout(void *ws, int n_wires)
+BatchLayout batch_layout(void *ws, int n_wires, int n_partitions)
 {
     char *p = (char *)ws;
     BatchLayout l;
@@ -405,6 +442,8 @@ BatchLayout batch_layout(void *ws, int n_wires)
     p += align256(sizeof(double) * 8 * (size_t)frames_pad(n_wires));
     l.counter = (int *)p;
     p += 256;
+    l.done = (int *)p;
+    p += align256(sizeof(int) * (size_t)n_partitions);
     l.scratch = (double *)p;
     return l;
 }
@@ -413,11 +452,12 @@ BatchLayout batch_layout(void *ws, int n_wires)
 
 extern "C" {
 
-size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps)
+size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps, int32_t n_partitions)
 {
-    if (n_wires < 0 || n_steps < 1)
+    if (n_wires < 0 || n_steps < 1 || n_partitions < 0)
         return 0;
     return align256(sizeof(double) * 8 * (size_t)frames_pad(n_wires)) + 256 +
+           align256(sizeof(int) * (size_t)n_partitions) +
            (size_t)kMaxBatchBlocks * batch_scratch_bytes(n_steps);
 }
 
@@ -454,7 +494,7 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
         return fail(COMET_EUNSUPPORTED, "comet_batch_scan: n_steps %d > 2400", cfg->n_steps);
     if (hit_mask && mask_stride < 1)
         return fail(COMET_EINVAL, "comet_batch_scan: mask_stride must be >= 1");
-    const size_t need = comet_batch_workspace_bytes(n_wires, cfg->n_steps);
+    const size_t need = comet_batch_workspace_bytes(n_wires, cfg->n_steps, n_partitions);
     if (!workspace || workspace_bytes < need)
         return fail(COMET_EWORKSPACE, "comet_batch_scan: workspace %zu < %zu bytes",
                     workspace_bytes, need);
@@ -464,7 +504,7 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
     if (st)
         return st;
     hipStream_t hs = (hipStream_t)stream;
-    const BatchLayout l = batch_layout(workspace, n_wires);
+    const BatchLayout l = batch_layout(workspace, n_wires, n_partitions);
     if (grids_init) {
         const int64_t nd = 14 * (int64_t)n_partitions;
         hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, hs,
@@ -494,7 +534,7 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
         items = max_items;
     BatchArgs args{l.frames, wire_offsets, drift, event_wires, part_event, grids, n[0], n[1],
                    n[2], n[3], S, tiles, items, cfg->bz_tesla, cfg->charge_e, cfg->step_mm,
-                   cfg->lambda_mm, cfg->n_steps, l.scratch, l.counter, rss};
+                   cfg->lambda_mm, cfg->n_steps, l.scratch, l.counter, l.done, rss, best};
     for (int it = 0; it <= n_refine && st == COMET_OK; ++it) {
         if (it) {
             hipLaunchKernelGGL(batch_refine_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0,
@@ -504,21 +544,14 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
             if (st)
                 break;
         }
-        hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, hs, l.counter);
-        st = launched("zero_counter_kernel");
+        hipLaunchKernelGGL(reset_scan_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0, hs,
+                           l.counter, l.done, best, n_partitions);
+        st = launched("reset_scan_kernel");
         if (st)
             break;
-        {
-            ProfScope prof(kProfDca, hs);
-            hipLaunchKernelGGL(v.kernel, dim3(blocks), dim3(64 * v.nwv), 0, hs, args);
-            st = launched("batch_scan_kernel");
-        }
-        if (st)
-            break;
-        ProfScope prof(kProfSelect, hs);
-        hipLaunchKernelGGL(batch_argmin_kernel, dim3(n_partitions), dim3(kSelectThreads), 0, hs,
-                           (const double *)rss, S, best);
-        st = launched("batch_argmin_kernel");
+        ProfScope prof(kProfDca, hs);
+        hipLaunchKernelGGL(v.kernel, dim3(blocks), dim3(64 * v.nwv), 0, hs, args);
+        st = launched("batch_scan_kernel");
     }
     if (st)
         return st;

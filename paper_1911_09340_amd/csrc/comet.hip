@@ -569,6 +569,7 @@ int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_point
     }
     int best = -1;
     float best_ms = 0.0f;
+    float times[kNumDcaVariants];
     for (int id = 0; id < kNumDcaVariants && st == COMET_OK; ++id) {
         st = launch_dca(id, track_xyz, n_seeds, n_points, n_wires, wire_offsets, drift,
                         cfg->lambda_mm, workspace, hs);  // warm-up
@@ -584,6 +585,7 @@ int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_point
         if (e != hipSuccess && st == COMET_OK)
             st = fail(COMET_EHIP, "comet_dca_autotune: %s", hipGetErrorString(e));
         t /= (float)reps;
+        times[id] = t;
         if (ms)
             ms[id] = t;
         if (st == COMET_OK && (best < 0 || t < best_ms)) {
@@ -595,6 +597,21 @@ int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_point
     (void)hipEventDestroy(e1);
     if (st)
         return st;
+    // Within 1 % of the fastest, prefer fewer wire groups: each group reads the seed
+    // tile's track again, so fewer groups means less memory traffic at equal speed.
+    {
+        auto groups = [&](int id) {
+            const int g = kDcaVariants[id].w * kDcaVariants[id].nwv;
+            return (n_wires + g - 1) / g;
+        };
+        int pick = best;
+        for (int id = 0; id < kNumDcaVariants; ++id) {
+            if (times[id] <= 1.01f * best_ms &&
+                (groups(id) < groups(pick) || (groups(id) == groups(pick) && times[id] < times[pick])))
+                pick = id;
+        }
+        best = pick;
+    }
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tuned[ShapeKey{n_seeds, n_points, n_wires}] = best;

@@ -7,15 +7,18 @@
 // Layout: coordinate c of track point k for tile lane l sits at base_c[k * ld + l]
 // (base_x, base_y, base_z; lanes l < n_valid hold seeds). Each of the block's NWV
 // waves owns W wires whose frames are in registers (`f`). The tile's track streams
-// through LDS in chunks of C points, loaded once per block and read by every wave;
-// the next chunk's loads are issued before the current chunk is scanned. Every lane
-// keeps, per wire, the smallest q = xi^2 + eta^2 seen so far and the first index
-// reaching it (Alg. 2: the recorded state closest to the wire); the index is either
-// tracked per point (CHUNK_ARGMIN = false) or per chunk (true: a running min per
-// point, the chunk holding the first minimum recorded, and that chunk rescanned from
-// memory at the end with the same arithmetic, so equality finds the first index).
-// The closest point is then refined over its two chords and Eq. 1's capped residual
-// d = min(lambda, min_j |D - r_j|) is formed.
+// through LDS in chunks of C points, loaded once per block and read by every wave.
+// Two LDS buffers alternate: while the waves scan chunk n from one, chunk n + 1 is
+// stored into the other from registers, and chunk n + 2 is already being loaded
+// from memory, so one barrier per chunk suffices.
+//
+// Every lane keeps, per wire, the smallest q = xi^2 + eta^2 seen so far and the first
+// index reaching it (Alg. 2: the recorded state closest to the wire); the index is
+// either tracked per point (CHUNK_ARGMIN = false) or per chunk (true: a running min
+// per point, the chunk holding the first minimum recorded, and that chunk rescanned
+// from memory at the end with the same arithmetic, so equality finds the first
+// index). The closest point is then refined over its two chords and Eq. 1's capped
+// residual d = min(lambda, min_j |D - r_j|) is formed.
 #ifndef COMET_DCA_SCAN_H
 #define COMET_DCA_SCAN_H
 
@@ -25,12 +28,13 @@ namespace cdev {
 
 template <int W, int NWV, int C, bool CHUNK_ARGMIN>
 struct TileScan {
-    static constexpr int kLdsDoubles = 3 * C * 64;
+    static constexpr int kChunkDoubles = 3 * C * 64;
+    static constexpr int kLdsDoubles = 2 * kChunkDoubles;
 
     // Returns d^2 of (lane, wire w) in dsq[w] for lanes < n_valid and w < nw (0
     // elsewhere). nw (this wave's wire count, 0..W) must be wave-uniform; offsets
     // points at the CSR entry of the wave's first wire. Every thread of the block
-    // must call this (it synchronises the block).
+    // must call this (it synchronises the block); lds holds kLdsDoubles doubles.
     __device__ static void run(const double *__restrict__ bx, const double *__restrict__ by,
                                const double *__restrict__ bz, int64_t ld, int P, int n_valid,
                                bool pairs, const double (&f)[W][8], int nw,
@@ -45,7 +49,6 @@ struct TileScan {
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             best[w] = INFINITY;
-            cmin[w] = INFINITY;
             kbest[w] = 0;
         }
 
@@ -53,8 +56,24 @@ struct TileScan {
         constexpr int T = 64 * NWV;
         constexpr int UNITS = 3 * C * 32;
         constexpr int PER_T = (UNITS + T - 1) / T;
+        const bool full_tile = pairs && n_valid == 64;
         double2 pre[PER_T];
         auto fetch = [&](int k0) {
+            if (full_tile && k0 + C <= P) {
+                // whole chunk in range, every lane a seed: plain 16-byte loads
+#pragma unroll
+                for (int u = 0; u < PER_T; ++u) {
+                    const int idx = threadIdx.x + u * T;
+                    if (UNITS % T == 0 || idx < UNITS) {
+                        const int c = idx / (C * 32);
+                        const int r = idx - c * (C * 32);
+                        const double *src = (c == 0 ? bx : (c == 1 ? by : bz)) +
+                                            (int64_t)(k0 + (r >> 5)) * ld + (r & 31) * 2;
+                        pre[u] = *reinterpret_cast<const double2 *>(src);
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int u = 0; u < PER_T; ++u) {
                 const int idx = threadIdx.x + u * T;
@@ -78,48 +97,52 @@ struct TileScan {
                 pre[u] = v;
             }
         };
-        auto stash = [&]() {
+        auto stash = [&](double *buf) {
 #pragma unroll
             for (int u = 0; u < PER_T; ++u) {
                 const int idx = threadIdx.x + u * T;
-                if (idx < UNITS)
-                    *reinterpret_cast<double2 *>(&lds[2 * idx]) = pre[u];
+                if (UNITS % T == 0 || idx < UNITS)
+                    *reinterpret_cast<double2 *>(&buf[2 * idx]) = pre[u];
+            }
+        };
+        auto point = [&](const double *buf, int kk, int k, bool first) {
+            const double x = buf[(0 * C + kk) * 64 + lane];
+            const double y = buf[(1 * C + kk) * 64 + lane];
+            const double z = buf[(2 * C + kk) * 64 + lane];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                double xi, eta;
+                project(f[w], x, y, z, xi, eta);
+                const double q = fma(xi, xi, eta * eta);
+                if (CHUNK_ARGMIN) {
+                    cmin[w] = first ? q : fmin(cmin[w], q);
+                } else {
+                    kbest[w] = q < best[w] ? k : kbest[w];
+                    best[w] = fmin(best[w], q);
+                }
             }
         };
 
+        // prologue: chunk 0 into buffer 0, chunk 1 in flight
         fetch(0);
-        for (int k0 = 0; k0 < P; k0 += C) {
-            __syncthreads();
-            stash();
-            __syncthreads();
-            if (k0 + C < P)
-                fetch(k0 + C);
+        __syncthreads();  // the previous caller's reads of lds are done
+        stash(lds);
+        if (C < P)
+            fetch(C);
+        __syncthreads();
+
+        for (int k0 = 0, n = 0; k0 < P; k0 += C, ++n) {
+            const double *cur = lds + (n & 1) * kChunkDoubles;
             if (active) {
-                auto body = [&](int kk) {
-                    const double x = lds[(0 * C + kk) * 64 + lane];
-                    const double y = lds[(1 * C + kk) * 64 + lane];
-                    const double z = lds[(2 * C + kk) * 64 + lane];
-#pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        double xi, eta;
-                        project(f[w], x, y, z, xi, eta);
-                        const double q = fma(xi, xi, eta * eta);
-                        if (CHUNK_ARGMIN) {
-                            cmin[w] = fmin(cmin[w], q);
-                        } else {
-                            kbest[w] = q < best[w] ? k0 + kk : kbest[w];
-                            best[w] = fmin(best[w], q);
-                        }
-                    }
-                };
                 const int kn = min(C, P - k0);
                 if (kn == C) {
-#pragma unroll 4
+#pragma unroll
                     for (int kk = 0; kk < C; ++kk)
-                        body(kk);
+                        point(cur, kk, k0 + kk, kk == 0);
                 } else {
-                    for (int kk = 0; kk < kn; ++kk)
-                        body(kk);
+                    point(cur, 0, k0, true);
+                    for (int kk = 1; kk < kn; ++kk)
+                        point(cur, kk, k0 + kk, false);
                 }
                 if (CHUNK_ARGMIN) {
 #pragma unroll
@@ -128,10 +151,17 @@ struct TileScan {
                             best[w] = cmin[w];
                             kbest[w] = k0;
                         }
-                        cmin[w] = INFINITY;
                     }
                 }
             }
+            if (k0 + C < P) {
+                // chunk n + 1 goes to the other buffer, whose chunk n - 1 every wave
+                // finished before the previous barrier
+                stash(lds + ((n + 1) & 1) * kChunkDoubles);
+                if (k0 + 2 * C < P)
+                    fetch(k0 + 2 * C);
+            }
+            __syncthreads();
         }
 
 #pragma unroll

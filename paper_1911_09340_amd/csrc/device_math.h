@@ -120,13 +120,16 @@ __device__ __forceinline__ bool beats(const MinLoc &a, const MinLoc &b)
 constexpr int kSelectThreads = 1024;
 
 // First index of the smallest of rss[0..S) (NaN never chosen, -1 if all are NaN), by
-// a block of kSelectThreads threads; the result is valid in thread 0.
-__device__ __forceinline__ int64_t block_argmin(const double *__restrict__ rss, int64_t S)
+// a block of NT threads (a multiple of 64, at most 4096); the result is valid in
+// thread 0. Every thread of the block must call it.
+template <int NT>
+__device__ __forceinline__ int64_t block_argmin_n(const double *__restrict__ rss, int64_t S)
 {
-    __shared__ double sv[kSelectThreads / 64];
-    __shared__ int64_t si[kSelectThreads / 64];
+    static_assert(NT % 64 == 0 && NT <= 4096, "block size");
+    __shared__ double sv[NT / 64];
+    __shared__ int64_t si[NT / 64];
     MinLoc m{INFINITY, -1};
-    for (int64_t s = threadIdx.x; s < S; s += kSelectThreads) {
+    for (int64_t s = threadIdx.x; s < S; s += NT) {
         const double v = rss[s];
         if (v < m.v || (m.i < 0 && v == m.v)) {
             m.v = v;
@@ -146,7 +149,7 @@ __device__ __forceinline__ int64_t block_argmin(const double *__restrict__ rss, 
     __syncthreads();
     MinLoc a{INFINITY, -1};
     if (wave == 0) {
-        if (lane < kSelectThreads / 64) {
+        if (lane < NT / 64) {
             a.v = sv[lane];
             a.i = si[lane];
         }
@@ -157,6 +160,11 @@ __device__ __forceinline__ int64_t block_argmin(const double *__restrict__ rss, 
         }
     }
     return a.i;
+}
+
+__device__ __forceinline__ int64_t block_argmin(const double *__restrict__ rss, int64_t S)
+{
+    return block_argmin_n<kSelectThreads>(rss, S);
 }
 
 // ------------------------------------------------------------------ RK4 step

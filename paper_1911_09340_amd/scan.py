@@ -144,10 +144,11 @@ class BatchRunner:
         self.best_seed = torch.empty(self.n_part, 6, **f64)
         self.best_rss = torch.empty(self.n_part, **f64)
         self.stride = max(ev.n_hits for ev in self.events)
-        self.mask = torch.empty(self.n_part, self.stride, dtype=torch.uint8, device=device)
+        # entries past a partition's own hits are never written: start them at 0
+        self.mask = torch.zeros(self.n_part, self.stride, dtype=torch.uint8, device=device)
         self.n_border = torch.empty(self.n_part, dtype=torch.int32, device=device)
         self.workspace = comet.batch_workspace(int(self.packed.wire_ends.shape[0]),
-                                               scan_cfg.n_steps, device)
+                                               scan_cfg.n_steps, self.n_part, device)
         self.graph = None
 
     @property
@@ -161,6 +162,28 @@ class BatchRunner:
                          self.sc.n_refine, self.rss, self.best, self.workspace,
                          best_seed=self.best_seed, best_rss=self.best_rss, hit_mask=self.mask,
                          n_borderline=self.n_border, max_items=max_items, grids_init=self.grids0)
+
+    def autotune(self, max_items: int = 0, reps: int = 2) -> dict:
+        """Time every shape of the batched scan kernel on a prefix of this run's work
+        queue (max_items items per scan; default four items per persistent block) and
+        keep the fastest. Every shape gives identical results."""
+        variants = comet.batch_variants()
+        if max_items <= 0:
+            max_items = 4 * max(v["blocks"] for v in variants)
+        times = []
+        for i in range(len(variants)):
+            comet.set_batch_variant(i)
+            self.run(max_items)
+            torch.cuda.synchronize()
+            comet.profile_begin()
+            for _ in range(reps):
+                self.run(max_items)
+            ms, n = comet.profile_end()["dca"]
+            times.append(ms / max(n, 1))
+        best = int(np.argmin(times))
+        comet.set_batch_variant(best)
+        return {"variant": best, "shape": variants[best], "ms_per_scan": times,
+                "items": int(max_items)}
 
     def capture(self) -> None:
         """Capture one run into a HIP graph (replay() then repeats it)."""

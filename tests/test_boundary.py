@@ -181,12 +181,12 @@ def test_batch_topk_and_seed_rejects(lib):
     assert lib.comet_topk(_p(), 10, 1, 0, _p(), None) == comet.EINVAL
     assert lib.comet_topk(_p(), 0, 1, 1, _p(), None) == comet.EINVAL
     assert lib.comet_grid_seeds(_p(), 2, _n4(2, 2, 0, 2), _p(), 1, _p(), None) == comet.EINVAL
-    need = lib.comet_batch_workspace_bytes(100, 1000)
+    need = lib.comet_batch_workspace_bytes(100, 1000, 7)
     assert need > 0 and need % 256 == 0
     cfg = _cfg()
     args = [_p(), 10, _p(), _p(), 20, _p(), 2, _p(), 3, None, _p(), _n4(2, 2, 2, 2),
             ctypes.byref(cfg), 1, _p(), _p(), None, None, None, 0, None, 0]
-    ws = lib.comet_batch_workspace_bytes(10, 10)
+    ws = lib.comet_batch_workspace_bytes(10, 10, 3)
     assert lib.comet_batch_scan(*args, _p(0x100000), 16, None) == comet.EWORKSPACE
     bad = list(args)
     bad[13] = -1  # n_refine

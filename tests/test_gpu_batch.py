@@ -75,7 +75,12 @@ def test_batch_every_shape_identical(events):
         comet.set_batch_variant(i)
         runner = scan.BatchRunner(events[:3], SC)
         runner.run()
-        got = (runner.rss.cpu().numpy(), runner.best.cpu().numpy(), runner.mask.cpu().numpy())
+        mask = runner.mask.cpu().numpy()
+        parts = [t for ev in events[:3] for t in range(ev.n_turns)]
+        hits = [ev.n_hits for ev in events[:3] for _ in range(ev.n_turns)]
+        masks = [mask[p, :h] for p, h in enumerate(hits)]
+        assert len(parts) == runner.n_part
+        got = (runner.rss.cpu().numpy(), runner.best.cpu().numpy(), *masks)
         if ref is None:
             ref = got
         else:
@@ -109,14 +114,18 @@ def test_graph_capture_replays_match_eager(events):
     eager = [t.clone() for t in (runner.rss, runner.best, runner.best_seed, runner.mask,
                                  runner.grids)]
     runner.capture()
+    hits = [ev.n_hits for ev in events[:4] for _ in range(ev.n_turns)]
     for rep in range(3):
         for t in (runner.rss, runner.best_seed, runner.grids):
             t.fill_(float("nan"))
-        runner.mask.fill_(7)
+        runner.best.fill_(-7)
+        runner.mask.fill_(7)  # entries past a partition's own hits are not outputs
         runner.replay()
         torch.cuda.synchronize()
-        got = (runner.rss, runner.best, runner.best_seed, runner.mask, runner.grids)
-        assert all(torch.equal(a, b) for a, b in zip(got, eager)), rep
+        got = (runner.rss, runner.best, runner.best_seed, runner.grids)
+        assert all(torch.equal(a, b) for a, b in zip(got, eager[:3] + eager[4:])), rep
+        for p, h in enumerate(hits):
+            assert torch.equal(runner.mask[p, :h], eager[3][p, :h]), (rep, p)
         _ = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
 
 
