@@ -106,7 +106,7 @@ def cpu_baseline(ev, sc, target_s: float):
                       (m, ev.n_hits, ev.n_wires)}
 
 
-def bench_batch(events, sc, reps: int = 2):
+def bench_batch(events, sc, reps: int = 3):
     """Every partition of `events` through the batched path, captured in a HIP graph."""
     import torch
     from paper_1911_09340_amd import comet, scan
@@ -118,18 +118,21 @@ def bench_batch(events, sc, reps: int = 2):
     del packed
     runner = scan.BatchRunner(events, sc)
     tune = runner.autotune()
-    log("  batched kernel shape %d %s; ms per scan of %d items: %s"
-        % (tune["variant"], tune["shape"], tune["items"],
-           ", ".join("%.2f" % m for m in tune["ms_per_scan"])))
+    log("  batched kernel shape %d %s; us per tile: %s"
+        % (tune["variant"], tune["shape"], ", ".join("%.2f" % m for m in tune["us_per_tile"])))
     runner.capture()
     runner.replay()
     torch.cuda.synchronize()
+    log("  captured one run in a HIP graph")
     comet.profile_begin()
-    t0 = time.perf_counter()
-    for _ in range(reps):
+    dts = []
+    for r in range(reps):
+        t0 = time.perf_counter()
         runner.replay()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - t0)
+        log("  graph replay %d: %.3f s" % (r, dts[-1]))
+    dt = float(np.median(dts))
     prof = comet.profile_end()  # graph replays record no events; eager run below
     comet.profile_begin()
     runner.run()
@@ -156,6 +159,37 @@ def bench_batch(events, sc, reps: int = 2):
                      "persistent scan with in-kernel selection; classification)"}
 
 
+def bench_stress(events, sc, top_k: int = 64, n_iter: int = 8):
+    """The stress mix: one batched scan of every partition, then Levenberg-Marquardt
+    from the top_k lowest-RSS seeds of each partition (device time per phase)."""
+    import torch
+    from paper_1911_09340_amd import comet, refine
+    refine.coarse_then_lm(events[:2], sc, top_k=top_k, n_iter=1)  # warm-up
+    torch.cuda.synchronize()
+    comet.profile_begin()
+    t0 = time.perf_counter()
+    out = refine.coarse_then_lm(events, sc, top_k=top_k, n_iter=n_iter)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = comet.profile_end()
+    hits = [ev.n_hits for ev in events]
+    pw = sum(ev.n_turns * ev.n_wires for ev in events)
+    ph = sum(ev.n_turns * ev.n_hits for ev in events)
+    flops = FLOP_PER_POINT_WIRE * sc.n_seeds * (sc.n_steps + 1) * pw
+    scan_ms = prof["dca"][0]
+    res = refine.summary(refine.momentum_residuals(out["refined"], events))
+    return {"events": len(events), "partitions": out["partitions"],
+            "seeds_per_partition": sc.n_seeds, "rk4_steps": sc.n_steps, "step_mm": sc.step_mm,
+            "hits_min_mean_max": [min(hits), float(np.mean(hits)), max(hits)],
+            "lm_starts_per_partition": top_k, "lm_iterations": n_iter,
+            "seconds": dt, "events_per_s": len(events) / dt,
+            "evals_per_s": ph * sc.n_seeds / dt,
+            "scan_kernel_ms": scan_ms, "scan_fp64_frac":
+                flops / (scan_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "momentum_residual": res,
+            "timing": "wall time of the whole call: host pack, batched scan, top-k, LM"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +206,13 @@ def main():
     ap.add_argument("--grad-events", type=int, default=32,
                     help="events of the batched mix for the coarse+LM vs fine-grid comparison "
                          "(0 = skip; 256 = the full differentiation workload)")
+    ap.add_argument("--grad-topk", type=int, default=16,
+                    help="LM starts per partition (the lowest-RSS coarse seeds)")
+    ap.add_argument("--grad-iters", type=int, default=32, help="LM iterations")
+    ap.add_argument("--stress-events", type=int, default=0,
+                    help="events of the stress mix (1-6 turns, 200-1200 hits, 30%% noise, "
+                         "131072 seeds, 2000 x 1.5 mm) through the batched scan and LM from "
+                         "the 64 lowest-RSS seeds per partition (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -183,14 +224,21 @@ def main():
 
     # events for the gradient comparison are drawn before the GPU is touched, so that
     # worker processes can be forked safely
-    grad_events, batch_events = [], []
+    grad_events, batch_events, stress_events = [], [], []
     n_mix = max(args.grad_events, args.batch_events)
-    if n_mix > 0 and not args.calibrate_copy:
+    if not args.calibrate_copy:
         from paper_1911_09340_amd import synth as _synth
-        t0 = time.perf_counter()
-        mix = _synth.event_mix_batch(range(n_mix), workers=min(16, os.cpu_count() or 1))
-        grad_events, batch_events = mix[:args.grad_events], mix[:args.batch_events]
-        log("drew %d mix events in %.1f s" % (len(mix), time.perf_counter() - t0))
+        workers = min(16, os.cpu_count() or 1)
+        if n_mix > 0:
+            t0 = time.perf_counter()
+            mix = _synth.event_mix_batch(range(n_mix), workers=workers)
+            grad_events, batch_events = mix[:args.grad_events], mix[:args.batch_events]
+            log("drew %d mix events in %.1f s" % (len(mix), time.perf_counter() - t0))
+        if args.stress_events > 0:
+            t0 = time.perf_counter()
+            stress_events = _synth.event_mix_batch(range(args.stress_events), workers=workers,
+                                                   kind="stress")
+            log("drew %d stress events in %.1f s" % (len(stress_events), time.perf_counter() - t0))
 
     import torch
     from paper_1911_09340_amd import comet, scan, synth
@@ -320,12 +368,19 @@ def main():
     if grad_events:
         from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))
-        out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE)
+        out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE,
+                                            top_k=args.grad_topk, n_iter=args.grad_iters)
         g = out["grad_refine"]
         log("  coarse+LM %.2f s, |p| residual rms %.3f core %.3f MeV/c; fine grid %.2f s, rms %.3f "
             "core %.3f" % (g["coarse_lm"]["seconds"], g["coarse_lm"]["rms"],
                            g["coarse_lm"]["core_sigma"], g["fine_grid"]["seconds"],
                            g["fine_grid"]["rms"], g["fine_grid"]["core_sigma"]))
+    if stress_events:
+        log("stress mix: %d events, batched scan + LM from the top 64 seeds ..." % len(stress_events))
+        out["stress"] = bench_stress(stress_events, synth.C4)
+        log("  %.2f events/s, %.3g seed x hit evals/s, scan kernel %.1f %% of FP64 peak"
+            % (out["stress"]["events_per_s"], out["stress"]["evals_per_s"],
+               100 * out["stress"]["scan_fp64_frac"]))
     if not args.no_cpu_baseline:
         log("CPU reference baseline (~%.0f s) ..." % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(ev, sc, args.cpu_seconds)

@@ -202,10 +202,11 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
  * event part_event[p] and starts from the grid descriptor grids[p] (layout as in
  * comet_seed_grid; every partition uses the same n, so S = n0 n1 n2 n3 seeds).
  *
- * Each scan is one persistent launch: blocks take (partition, 64-seed tile) items
- * from an atomic counter, build the seeds from the descriptor, record their RK4
- * tracks into per-block scratch (no track array in HBM) and scan the partition's
- * event wires; per-seed RSS are summed in wire order and equal those of
+ * Each scan is one persistent launch: blocks take work items (a partition and a run
+ * of consecutive 64-seed tiles) from an atomic counter, build the seeds from the
+ * descriptor, record their RK4 tracks into per-block scratch (no track array in HBM)
+ * and scan the partition's event wires; per-seed RSS are summed in wire order and
+ * equal those of
  * comet_dca_rss bit for bit. A per-partition completion counter lets the block that
  * finishes a partition's last tile select its best seed inside the same launch. The
  * calls on `stream` are: a wire-frame kernel, then per scan [refine (not before the
@@ -226,8 +227,9 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
  *                hit - wire_offsets[event_wires[e]]; mask_stride >= the most hits of an
  *                event
  *   n_borderline device int32[n_partitions] or NULL
- *   max_items    > 0: scan only the first max_items (partition, tile) items of every
- *                scan (for timing shapes; the other RSS are not written)
+ *   max_items    > 0: scan only the first max_items 64-seed tiles (partition-major) of
+ *                every scan (for timing shapes; the other RSS are not written, and a
+ *                partition not scanned in full keeps best = -1)
  *   workspace    >= comet_batch_workspace_bytes(n_wires, n_steps, n_partitions),
  *                256-byte aligned */
 size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps, int32_t n_partitions);

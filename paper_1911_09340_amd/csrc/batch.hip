@@ -6,13 +6,14 @@
 //
 // Events are packed in one CSR (event -> wires -> hits); partition p belongs to event
 // part_event[p] and scans the grid descriptor grids[p] (the same n per axis for all
-// partitions, S seeds). The scan kernel is persistent: each block takes (partition,
-// 64-seed tile) items from an atomic work counter until none are left, builds the
-// tile's seeds from the partition's descriptor, records their RK4 track into the
-// block's own scratch rows, and scans the partition's event wires group by group
-// with the same tile scan as the single-event kernel (cdev::TileScan). Each wire
-// group's d^2 values go to LDS and one wave adds them to the per-seed RSS in wire
-// order, so every RSS equals the single-event path's bit for bit.
+// partitions, S seeds). The scan kernel is persistent: each block takes work items
+// (a partition and up to one tile of 64 seeds per wave) from an atomic work counter
+// until none are left. Every wave builds its tile's seeds from the partition's
+// descriptor and records their RK4 tracks into the block's own scratch rows; then the
+// block scans the tiles one by one against the partition's event wires, group by
+// group, with the same tile scan as the single-event kernel (cdev::TileScan). Each
+// wire group's d^2 values go to LDS and one wave adds them to the per-seed RSS in
+// wire order, so every RSS equals the single-event path's bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -30,7 +31,9 @@ namespace {
 using namespace cdev;
 using namespace chost;
 
-constexpr int kMaxBatchBlocks = 2048;  // persistent blocks (scratch rows) at most
+constexpr int kMaxBatchBlocks = 512;  // persistent blocks at most (2 per CU on gfx950)
+constexpr int kMaxBatchNwv = 8;       // waves per block at most = tiles per work item
+constexpr int kBatchWirePad = 64;     // frames padding: at least one wire group W * NWV
 
 struct BatchArgs {
     const double *frames;     // [W_pad][8]
@@ -41,11 +44,13 @@ struct BatchArgs {
     const double *grids;      // [NP][14]
     int n0, n1, n2, n3;
     int64_t S;
-    int tiles;                // tiles per partition
-    int64_t n_items;
+    int tiles;                // 64-seed tiles per partition
+    int supers;               // work items (super-tiles of NWV tiles) per partition
+    int64_t n_items;          // partitions x supers
+    int64_t max_tiles;        // tiles (partition-major) scanned, at most partitions x tiles
     double bz, charge, h, lambda;
     int K;
-    double *scratch;          // [blocks][3][P][64]
+    double *scratch;          // [blocks][NWV][3][P][64]
     int *counter;             // work queue
     int *done;                // [NP] tiles finished per partition
     double *rss;              // [NP][S]
@@ -53,13 +58,16 @@ struct BatchArgs {
 };
 
 // WPE: waves per SIMD the register allocation must allow (2 blocks of 8 waves per CU
-// need 4), so that one block's track recording overlaps another block's scan.
+// need 4). A work item is a super-tile of up to NWV consecutive 64-seed tiles of one
+// partition: every wave records one tile's tracks (RK4 runs on all waves at once),
+// then the block scans the tiles one after the other against the event's wires.
 template <int W, int NWV, int C, int WPE>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_scan_kernel(BatchArgs a)
 {
     using Scan = TileScan<W, NWV, C, true>;
     constexpr int G = W * NWV;  // wires per group
+    static_assert(NWV <= kMaxBatchNwv && G <= kBatchWirePad, "shape exceeds the workspace");
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];
     __shared__ double dd[G * 64];
     __shared__ int item_s;
@@ -68,12 +76,11 @@ batch_scan_kernel(BatchArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int P = a.K + 1;
-    const int64_t row = (int64_t)P * 64;
-    double *sx = a.scratch + (int64_t)blockIdx.x * 3 * row;
-    double *sy = sx + row, *sz = sy + row;
+    const int64_t row = (int64_t)P * 64;                 // one coordinate of one tile
+    double *const block_scratch = a.scratch + (int64_t)blockIdx.x * NWV * 3 * row;
 
     // Control flow around the barriers stays wave-uniform: counters are bumped by a
-    // whole wave (lane 0 adds 1, the others 0) and results are broadcast with
+    // whole wave (lane 0 adds its count, the others 0) and results are broadcast with
     // readfirstlane, never by a region that only thread 0 enters (the compiler may
     // move such a region across the loop's back edge, apart from its wave's barriers).
     for (;;) {
@@ -86,70 +93,86 @@ batch_scan_kernel(BatchArgs a)
         __syncthreads();
         if (item >= a.n_items)
             break;
-        const int p = (int)(item / a.tiles);
-        const int64_t s0 = (item - (int64_t)p * a.tiles) * 64;
-        const int n_valid = (int)min((int64_t)64, a.S - s0);
+        const int p = (int)(item / a.supers);
+        const int t0 = (int)(item - (int64_t)p * a.supers) * NWV;  // first tile
+        // tiles of this item that exist and lie within the max_tiles prefix
+        const int64_t first_global = (int64_t)p * a.tiles + t0;
+        const int n_sub = (int)max((int64_t)0, min(min((int64_t)NWV, (int64_t)(a.tiles - t0)),
+                                                   a.max_tiles - first_global));
         const int e = a.part_event[p];
         const int w0 = a.ev_wires[e], w1 = a.ev_wires[e + 1];
 
-        // seeds of the tile and their tracks (one wave, one seed per lane)
-        if (wave == 0 && lane < n_valid) {
-            double st[6];
-            seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, s0 + lane, st);
-            double x = st[0], y = st[1], z = st[2], px = st[3], py = st[4];
-            const StepConsts kc = step_consts(px, py, st[5], a.bz, a.charge, a.h);
-            for (int k = 0; k < a.K; ++k) {
-                sx[(int64_t)k * 64 + lane] = x;
-                sy[(int64_t)k * 64 + lane] = y;
-                sz[(int64_t)k * 64 + lane] = z;
-                rk4_step(kc, x, y, z, px, py);
+        // seeds and tracks: wave w records tile t0 + w (one seed per lane)
+        if (wave < n_sub) {
+            const int64_t s0 = (int64_t)(t0 + wave) * 64;
+            const int n_valid = (int)min((int64_t)64, a.S - s0);
+            double *sx = block_scratch + (int64_t)wave * 3 * row;
+            double *sy = sx + row, *sz = sy + row;
+            if (lane < n_valid) {
+                double st[6];
+                seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, s0 + lane,
+                               st);
+                double x = st[0], y = st[1], z = st[2], px = st[3], py = st[4];
+                const StepConsts kc = step_consts(px, py, st[5], a.bz, a.charge, a.h);
+                for (int k = 0; k < a.K; ++k) {
+                    sx[(int64_t)k * 64 + lane] = x;
+                    sy[(int64_t)k * 64 + lane] = y;
+                    sz[(int64_t)k * 64 + lane] = z;
+                    rk4_step(kc, x, y, z, px, py);
+                }
+                sx[(int64_t)a.K * 64 + lane] = x;
+                sy[(int64_t)a.K * 64 + lane] = y;
+                sz[(int64_t)a.K * 64 + lane] = z;
             }
-            sx[(int64_t)a.K * 64 + lane] = x;
-            sy[(int64_t)a.K * 64 + lane] = y;
-            sz[(int64_t)a.K * 64 + lane] = z;
         }
         __syncthreads();
 
-        double acc = 0.0;  // RSS of this lane's seed (wave 0)
-        for (int g0 = w0; g0 < w1; g0 += G) {
-            const int wbase = g0 + wave * W;
-            const int nw = max(0, min(W, w1 - wbase));
-            double f[W][8];
+        for (int t = 0; t < n_sub; ++t) {
+            const int64_t s0 = (int64_t)(t0 + t) * 64;
+            const int n_valid = (int)min((int64_t)64, a.S - s0);
+            const double *sx = block_scratch + (int64_t)t * 3 * row;
+            const double *sy = sx + row, *sz = sy + row;
+            double acc = 0.0;  // RSS of this lane's seed (wave 0)
+            for (int g0 = w0; g0 < w1; g0 += G) {
+                const int wbase = g0 + wave * W;
+                const int nw = max(0, min(W, w1 - wbase));
+                double f[W][8];
 #pragma unroll
-            for (int w = 0; w < W; ++w)
+                for (int w = 0; w < W; ++w)
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                {
-                    // wave-uniform: keep the frames in scalar registers
-                    const double v = a.frames[8 * (int64_t)(wbase + w) + j];
-                    f[w][j] = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
-                                               __builtin_amdgcn_readfirstlane(__double2loint(v)));
+                    for (int j = 0; j < 8; ++j) {
+                        // wave-uniform: keep the frames in scalar registers
+                        const double v = a.frames[8 * (int64_t)(wbase + w) + j];
+                        f[w][j] = __hiloint2double(
+                            __builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+                    }
+                double d2[W];
+                Scan::run(sx, sy, sz, 64, P, n_valid, true, f, nw,
+                          a.offsets + (nw > 0 ? wbase : 0), a.drift, a.lambda, lds, d2);
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    dd[(wave * W + w) * 64 + lane] = d2[w];
+                __syncthreads();
+                if (wave == 0) {
+                    const int ng = min(G, w1 - g0);
+                    for (int j = 0; j < ng; ++j)
+                        acc = acc + dd[j * 64 + lane];
                 }
-            double d2[W];
-            Scan::run(sx, sy, sz, 64, P, n_valid, true, f, nw, a.offsets + (nw > 0 ? wbase : 0),
-                      a.drift, a.lambda, lds, d2);
-#pragma unroll
-            for (int w = 0; w < W; ++w)
-                dd[(wave * W + w) * 64 + lane] = d2[w];
-            __syncthreads();
-            if (wave == 0) {
-                const int ng = min(G, w1 - g0);
-                for (int j = 0; j < ng; ++j)
-                    acc = acc + dd[j * 64 + lane];
+                __syncthreads();
             }
-            __syncthreads();
+            if (wave == 0 && lane < n_valid)
+                a.rss[(int64_t)p * a.S + s0 + lane] = acc;
         }
-        if (wave == 0 && lane < n_valid)
-            a.rss[(int64_t)p * a.S + s0 + lane] = acc;
 
-        // Completion counter of partition p: the tile's RSS are made visible device-wide
-        // before the count; the block that finishes the partition's last tile selects its
-        // best seed (Sec. 2.1) while other blocks keep scanning.
+        // Completion counter of partition p: the item's RSS are made visible
+        // device-wide before the count; the block that finishes the partition's last
+        // tile selects its best seed (Sec. 2.1) while other blocks keep scanning.
         __threadfence();
         __syncthreads();
         if (wave == 0) {
-            const int old = atomicAdd(a.done + p, lane == 0 ? 1 : 0);
-            last_s = __builtin_amdgcn_readfirstlane(old) == a.tiles - 1;
+            const int old = atomicAdd(a.done + p, lane == 0 ? n_sub : 0);
+            last_s = n_sub > 0 && __builtin_amdgcn_readfirstlane(old) + n_sub == a.tiles;
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(last_s)) {
@@ -392,11 +415,10 @@ const BatchVariant kBatchVariants[] = {
     {2, 8, 16, batch_scan_kernel<2, 8, 16, 4>},
     {4, 8, 16, batch_scan_kernel<4, 8, 16, 1>},
     {5, 8, 16, batch_scan_kernel<5, 8, 16, 1>},
-    {4, 12, 16, batch_scan_kernel<4, 12, 16, 1>},
-    {3, 8, 32, batch_scan_kernel<3, 8, 32, 1>},
+    {6, 8, 16, batch_scan_kernel<6, 8, 16, 1>},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
-constexpr int kBatchWirePad = 64;  // >= the largest W * NWV above
+
 
 std::mutex g_batch_mu;
 int g_batch_variant = 0;
@@ -423,7 +445,11 @@ int batch_blocks(int id)
     return nb;
 }
 
-size_t batch_scratch_bytes(int K) { return sizeof(double) * 3 * (size_t)(K + 1) * 64; }
+// Track scratch of one persistent block: kMaxBatchNwv tiles of 64 seeds.
+size_t batch_scratch_bytes(int K)
+{
+    return sizeof(double) * 3 * (size_t)(K + 1) * 64 * kMaxBatchNwv;
+}
 
 int frames_pad(int n_w) { return ((n_w + 63) / 64) * 64 + kBatchWirePad; }
 
@@ -485,7 +511,8 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
         S *= n[a];
     }
     if (S > ((int64_t)1 << 31) ||
-        (int64_t)n_partitions * ((S + 63) / 64) + kMaxBatchBlocks > ((int64_t)1 << 31) - 1)
+        (int64_t)n_partitions * ((S + 63) / 64) + kMaxBatchBlocks > ((int64_t)1 << 31) - 1 ||
+        (int64_t)n_partitions * ((S + 63) / 64) > ((int64_t)1 << 31) - 1)
         return fail(COMET_EINVAL, "comet_batch_scan: too many work items for one launch");
     int st = check_config(cfg);
     if (st)
@@ -529,12 +556,17 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
     if (blocks < 1)
         return fail(COMET_EHIP, "comet_batch_scan: occupancy query failed");
     const int tiles = (int)((S + 63) / 64);
-    int64_t items = (int64_t)n_partitions * tiles;
-    if (max_items > 0 && max_items < items)
-        items = max_items;
+    const int supers = (tiles + v.nwv - 1) / v.nwv;
+    int64_t max_tiles = (int64_t)n_partitions * tiles;
+    if (max_items > 0 && max_items < max_tiles)
+        max_tiles = max_items;
+    // work items: the super-tiles that hold at least one of the first max_tiles tiles
+    const int64_t full = max_tiles / tiles, rest = max_tiles - full * tiles;
+    const int64_t items = full * supers + (rest + v.nwv - 1) / v.nwv;
     BatchArgs args{l.frames, wire_offsets, drift, event_wires, part_event, grids, n[0], n[1],
-                   n[2], n[3], S, tiles, items, cfg->bz_tesla, cfg->charge_e, cfg->step_mm,
-                   cfg->lambda_mm, cfg->n_steps, l.scratch, l.counter, l.done, rss, best};
+                   n[2], n[3], S, tiles, supers, items, max_tiles, cfg->bz_tesla,
+                   cfg->charge_e, cfg->step_mm, cfg->lambda_mm, cfg->n_steps, l.scratch,
+                   l.counter, l.done, rss, best};
     for (int it = 0; it <= n_refine && st == COMET_OK; ++it) {
         if (it) {
             hipLaunchKernelGGL(batch_refine_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0,

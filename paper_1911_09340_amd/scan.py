@@ -163,27 +163,30 @@ class BatchRunner:
                          best_seed=self.best_seed, best_rss=self.best_rss, hit_mask=self.mask,
                          n_borderline=self.n_border, max_items=max_items, grids_init=self.grids0)
 
-    def autotune(self, max_items: int = 0, reps: int = 2) -> dict:
+    def autotune(self, items_per_block: int = 4, reps: int = 2) -> dict:
         """Time every shape of the batched scan kernel on a prefix of this run's work
-        queue (max_items items per scan; default four items per persistent block) and
-        keep the fastest. Every shape gives identical results."""
+        queue and keep the fastest per tile. A shape's prefix holds items_per_block work
+        items for each of its persistent blocks (a work item is up to one 64-seed tile
+        per wave), so that every block stays busy as in a full run. Every shape gives
+        identical results."""
         variants = comet.batch_variants()
-        if max_items <= 0:
-            max_items = 4 * max(v["blocks"] for v in variants)
-        times = []
-        for i in range(len(variants)):
+        total = self.n_part * ((self.sc.n_seeds + 63) // 64)
+        us_per_tile, tiles = [], []
+        for i, v in enumerate(variants):
             comet.set_batch_variant(i)
-            self.run(max_items)
+            n_tiles = min(total, items_per_block * v["blocks"] * v["nwv"])
+            self.run(n_tiles)
             torch.cuda.synchronize()
             comet.profile_begin()
             for _ in range(reps):
-                self.run(max_items)
+                self.run(n_tiles)
             ms, n = comet.profile_end()["dca"]
-            times.append(ms / max(n, 1))
-        best = int(np.argmin(times))
+            us_per_tile.append(1e3 * ms / max(n, 1) / n_tiles)
+            tiles.append(n_tiles)
+        best = int(np.argmin(us_per_tile))
         comet.set_batch_variant(best)
-        return {"variant": best, "shape": variants[best], "ms_per_scan": times,
-                "items": int(max_items)}
+        return {"variant": best, "shape": variants[best], "us_per_tile": us_per_tile,
+                "tiles": tiles}
 
     def capture(self) -> None:
         """Capture one run into a HIP graph (replay() then repeats it)."""

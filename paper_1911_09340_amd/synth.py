@@ -439,12 +439,24 @@ C3_COARSE = ScanConfig("mix-coarse", (8, 8, 8, 8), (5.0, 5.0, 0.05, 0.05), 1000,
 C3_FINE = ScanConfig("mix-fine", (32, 32, 32, 32), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)
 
 
-def event_mix_batch(seeds, workers: int = 0):
+# Stress workload: up to 6 turns, 200-1200 hits with 30 % noise, 131072 seeds per
+# partition (8 x 16 x 32 x 32), RK4 2000 x 1.5 mm; refinement by Levenberg-Marquardt
+# from the 64 lowest-RSS seeds of each partition instead of finer grids.
+C4 = ScanConfig("stress", (8, 16, 32, 32), (5.0, 5.0, 0.05, 0.05), 2000, 1.5, 0.8, 0)
+
+
+def event_stress(seed: int) -> Event:
+    """One event of the stress mix (event_mix with 1-6 turns, 200-1200 hits, 30 % noise)."""
+    return event_mix(seed, noise_frac=0.30, turns=(1, 6), hits=(200, 1200))
+
+
+def event_mix_batch(seeds, workers: int = 0, kind: str = "mix"):
     """event_mix for many seeds, in worker processes when workers > 1 (numpy only)."""
     seeds = list(seeds)
+    fn = {"mix": event_mix, "stress": event_stress}[kind]
     if workers <= 1 or len(seeds) < 8:
-        return [event_mix(s) for s in seeds]
+        return [fn(s) for s in seeds]
     import multiprocessing as mp
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
-        return pool.map(event_mix, seeds, chunksize=max(1, len(seeds) // (4 * workers)))
+        return pool.map(fn, seeds, chunksize=max(1, len(seeds) // (4 * workers)))

@@ -61,12 +61,26 @@ def _check_against_single(runner, events, sc):
             p += 1
 
 
+# 26 tiles per partition (the last one half full): several work items per partition
+SC_WIDE = synth.ScanConfig("batch-wide", (3, 4, 8, 17), (5.0, 5.0, 0.05, 0.05), 700, 2.0, 0.8, 1)
+
+
 def test_batch_equals_single_event_path(events):
     runner = scan.BatchRunner(events, SC)
     assert runner.n_part == sum(ev.n_turns for ev in events) and runner.n_part > 6
     runner.run()
     torch.cuda.synchronize()
     _check_against_single(runner, events, SC)
+
+
+def test_batch_many_tiles_per_partition(events):
+    for i in range(len(comet.batch_variants())):
+        comet.set_batch_variant(i)
+        runner = scan.BatchRunner(events[:3], SC_WIDE)
+        runner.run()
+        torch.cuda.synchronize()
+        _check_against_single(runner, events[:3], SC_WIDE)
+    comet.set_batch_variant(0)
 
 
 def test_batch_every_shape_identical(events):
@@ -129,19 +143,25 @@ def test_graph_capture_replays_match_eager(events):
         _ = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
 
 
-def test_max_items_scans_a_prefix(events):
-    runner = scan.BatchRunner(events[:2], replace(SC, n_refine=0))
+@pytest.mark.parametrize("sc,max_items", [(SC, 3), (SC_WIDE, 37)])
+def test_max_items_scans_a_prefix(events, sc, max_items):
+    runner = scan.BatchRunner(events[:2], replace(sc, n_refine=0))
     runner.rss.fill_(-1.0)
-    runner.run(max_items=3)
+    runner.run(max_items=max_items)
     torch.cuda.synchronize()
     flat = runner.rss.cpu().numpy().ravel()
-    S = SC.n_seeds
+    S = sc.n_seeds
     tiles = (S + 63) // 64
     done = np.zeros_like(flat, dtype=bool)
-    for item in range(3):
+    for item in range(max_items):
         p, t = divmod(item, tiles)
         done[p * S + t * 64:p * S + min(S, (t + 1) * 64)] = True
     assert np.all(flat[done] >= 0) and np.all(flat[~done] == -1.0)
+    # partitions scanned in full select their best seed; the others keep -1
+    best = runner.best.cpu().numpy()
+    for p in range(runner.n_part):
+        full = (p + 1) * tiles <= max_items
+        assert (best[p] >= 0) == full, (p, best[p])
 
 
 def test_topk_matches_cpu_reference(orc):
