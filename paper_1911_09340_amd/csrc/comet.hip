@@ -117,8 +117,12 @@ __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad
 // with xcd_remap the wire groups of one seed tile become consecutive within one
 // XCD so that they can read the tile's track through the same L2 (without it,
 // consecutive block indices take consecutive groups).
+//
+// Registers are capped for 4 waves per SIMD (two 8-wave blocks or one 16-wave block
+// per CU); the frames live in scalar registers, so only the running minima, the
+// staged point and the prefetch buffer occupy vector registers.
 template <int W, int NWV, int C, bool CHUNK_ARGMIN>
-__global__ __launch_bounds__(64 * NWV) void dca_kernel(
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) void dca_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames,
     int n_w, const int32_t *__restrict__ offsets, const double *__restrict__ drift,
     double lambda, double *__restrict__ dsq, int n_groups, int n_blocks, int xcd_remap)
@@ -297,8 +301,8 @@ const DcaVariant kDcaVariants[] = {
     {4, 8, 16, 1, 1, dca_kernel<4, 8, 16, true>},
     {5, 8, 16, 1, 1, dca_kernel<5, 8, 16, true>},
     {3, 8, 32, 1, 1, dca_kernel<3, 8, 32, true>},
-    {2, 8, 32, 1, 1, dca_kernel<2, 8, 32, true>},
-    {4, 4, 32, 1, 1, dca_kernel<4, 4, 32, true>},
+    {4, 16, 32, 1, 1, dca_kernel<4, 16, 32, true>},
+    {3, 16, 32, 1, 1, dca_kernel<3, 16, 32, true>},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
 constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above
