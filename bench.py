@@ -64,9 +64,9 @@ def stored_traffic(shape: dict):
         return None
     name = "dca_kernel<%d, %d, %d, %s>" % (shape["w"], shape["nwv"], shape["chunk"],
                                           "true" if shape["chunk_argmin"] else "false")
-    if t.get("kernel_sha") != kernel_hash() or t.get("kernel") != name:
+    if t.get("kernel_sha") != kernel_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("shapes", {}).get(name, {}).get("bytes_per_launch")
 
 
 def calibrate_copy():
