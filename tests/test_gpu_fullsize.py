@@ -1,0 +1,106 @@
+"""Full-size workloads in the launch configuration the bench times, checked on sampled
+seeds against the CPU reference (which computes each seed on its own):
+
+- the batched mix: 32768 seeds per partition (8 x 16 x 16 x 16), 1000 x 2 mm, two
+  finer re-scans, graph-free eager run of the persistent kernel;
+- the stress mix: 131072 seeds per partition (8 x 16 x 32 x 32), 2000 x 1.5 mm;
+- the fine grid of the differentiation workload: 32^4 = 1048576 seeds;
+- Levenberg-Marquardt on stress-size tracks (2000 steps) vs the CPU LM.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_09340_amd import comet, refine, scan, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    comet.load()
+    comet.set_batch_variant(0)
+
+
+def _cfg(ev, sc):
+    return [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+
+
+def _check_partitions(orc, runner, events, sc, n_sample, seed):
+    """Sampled RSS of the last grid bit for bit, the argmin against the full RSS row,
+    and the classification of the chosen seed."""
+    rss = runner.rss.cpu().numpy()
+    best = runner.best.cpu().numpy()
+    grids = runner.grids.cpu().numpy()
+    mask = runner.mask.cpu().numpy()
+    n = np.array(sc.n, np.int32)
+    rng = np.random.default_rng(seed)
+    p = 0
+    for ev in events:
+        for _ in range(ev.n_turns):
+            row = rss[p]
+            assert best[p] == int(np.argmin(row)), p      # first index of the minimum
+            idx = np.unique(np.concatenate([rng.integers(0, sc.n_seeds, n_sample),
+                                            [0, sc.n_seeds - 1, best[p]]]))
+            seeds = np.stack([orc.seed(grids[p], n, int(i)) for i in idx], axis=1)
+            want, _ = orc.scan(seeds, _cfg(ev, sc), sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                               ev.drift)
+            assert np.array_equal(row[idx], want), p
+            wmask, _, _ = orc.classify(orc.seed(grids[p], n, int(best[p])), _cfg(ev, sc),
+                                       sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+            assert np.array_equal(mask[p, :ev.n_hits], wmask), p
+            p += 1
+
+
+def test_batched_mix_full_size_sampled(orc):
+    events = [synth.event_mix(i) for i in (3, 11)]
+    sc = synth.C2
+    runner = scan.BatchRunner(events, sc)
+    runner.run()
+    torch.cuda.synchronize()
+    _check_partitions(orc, runner, events, sc, 24, 1)
+
+
+def test_stress_full_size_sampled(orc):
+    events = [synth.event_stress(5)]
+    sc = synth.C4
+    runner = scan.BatchRunner(events, sc)
+    runner.run()
+    torch.cuda.synchronize()
+    _check_partitions(orc, runner, events, sc, 12, 2)
+
+
+def test_fine_grid_full_size_sampled(orc):
+    events = [synth.event_mix(7)]
+    sc = synth.C3_FINE
+    runner = scan.BatchRunner(events, sc)
+    runner.run()
+    torch.cuda.synchronize()
+    _check_partitions(orc, runner, events, sc, 12, 3)
+
+
+def test_lm_stress_size_matches_cpu(orc):
+    """Two starts on a stress event (2000 x 1.5 mm): device LM = CPU LM to 1e-7."""
+    ev = synth.event_stress(9)
+    sc = synth.C4
+    cfg = scan.config_for(ev, sc)
+    starts = []
+    for t in range(min(2, ev.n_turns)):
+        s = ev.ref_states[t] * np.array([1.0, 1.0, 1.0, 1.003, 0.997, 1.002])
+        starts.append(s)
+    seeds = torch.as_tensor(np.ascontiguousarray(np.stack(starts, axis=1)), device="cuda")
+    dev = scan.DeviceEvent.from_event(ev)
+    rss = torch.empty(seeds.shape[1], dtype=torch.float64, device="cuda")
+    acc = torch.empty(seeds.shape[1], dtype=torch.int32, device="cuda")
+    comet.lm_refine(seeds, cfg, dev.wire_ends, dev.wire_offsets, dev.drift, 6, 1e-3, rss,
+                    comet.lm_workspace(seeds.shape[1], "cuda"), n_accepted=acc)
+    got = seeds.cpu().numpy()
+    for r, s0 in enumerate(starts):
+        ws, wrss, wacc = orc.lm_refine(s0, _cfg(ev, sc), sc.n_steps, ev.wire_ends,
+                                       ev.wire_offsets, ev.drift, 6, 1e-3)
+        assert int(acc[r]) == wacc, r
+        assert np.max(np.abs(got[:, r] - ws) / np.maximum(np.abs(ws), 1.0)) < 1e-7, r
+        assert abs(float(rss[r]) - wrss) <= 1e-7 * max(wrss, 1.0), r
