@@ -106,6 +106,9 @@ def _ptr(t, dtype, name, shape=None, optional=False):
         raise ValueError("%s is required" % name)
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise ValueError("%s must be a tensor on the GPU" % name)
+    if t.device.index is not None and t.device.index != torch.cuda.current_device():
+        raise ValueError("%s is on %s but the current device is cuda:%d (the library works "
+                         "on the current device)" % (name, t.device, torch.cuda.current_device()))
     if t.dtype != dtype:
         raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
     if not t.is_contiguous():
