@@ -165,18 +165,21 @@ batch_scan_kernel(BatchArgs a)
                 a.rss[(int64_t)p * a.S + s0 + lane] = acc;
         }
 
-        // Completion counter of partition p: the item's RSS are made visible
-        // device-wide before the count; the block that finishes the partition's last
-        // tile selects its best seed (Sec. 2.1) while other blocks keep scanning.
-        __threadfence();
-        __syncthreads();
+        // Completion counter of partition p; the block that finishes the partition's
+        // last tile selects its best seed (Sec. 2.1) while other blocks keep scanning.
+        // Wave 0 wrote this item's RSS: its release fence (device scope: the 8 XCDs'
+        // L2 caches are not coherent with each other) orders them before its count.
+        // The selecting block's acquire fence orders the count before its reads of
+        // every tile's RSS. Release fences only write back; the L2 invalidation of
+        // an acquire happens once per partition, not once per item.
         if (wave == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const int old = atomicAdd(a.done + p, lane == 0 ? n_sub : 0);
             last_s = n_sub > 0 && __builtin_amdgcn_readfirstlane(old) + n_sub == a.tiles;
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(last_s)) {
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int64_t b = block_argmin_n<64 * NWV>(a.rss + (int64_t)p * a.S, a.S);
             if (wave == 0)  // every lane of wave 0 holds the result
                 a.best[p] = b;
