@@ -74,6 +74,9 @@ def _bind(lib):
                                         _d, _d, _u8, _d]
     lib.oracle_topk.restype = None
     lib.oracle_topk.argtypes = [_d, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_sparse_select.restype = ctypes.c_int32
+    lib.oracle_sparse_select.argtypes = [_d, _d, ctypes.c_int32, _i32, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int64), _d, _d]
     lib.oracle_lm_refine.restype = ctypes.c_double
     lib.oracle_lm_refine.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d,
                                      ctypes.c_int32, ctypes.c_double, _i32]
@@ -221,6 +224,19 @@ class Oracle:
                                         _p(_i32a(offsets), _i32), _p(_f64(drift)), n_iter,
                                         float(mu0), _p(acc, _i32))
         return s, rss, int(acc[0])
+
+    def sparse_select(self, grids, rss, n, n_ref):
+        """Sparse reference seeds of one group of sub-grids: (idx, rss, new_grids, taken)."""
+        grids = _f64(grids).reshape(-1, 14)
+        rss = _f64(rss).ravel()
+        idx = np.empty(n_ref, dtype=np.int64)
+        rr = np.empty(n_ref)
+        ng = np.empty((n_ref, 14))
+        taken = self.lib.oracle_sparse_select(_p(grids), _p(rss), grids.shape[0],
+                                              _p(_i32a(n), _i32), n_ref,
+                                              idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                              _p(rr), _p(ng))
+        return idx, rr, ng, int(taken)
 
     def topk(self, values, k):
         v = _f64(values)

@@ -844,3 +844,99 @@ void oracle_topk(const double *values, int64_t n, int32_t k, int64_t *out)
         out[r] = r < m ? p[r].i : -1;
     free(p);
 }
+
+/* ------------------------------------------------------------ several references
+ * Sec. 2.1: several of the lowest-RSS seeds become the reference points of the
+ * next, finer scan, and they are chosen sparse enough that the new seed sets around
+ * them do not overlap.
+ *
+ * Candidates: every seed of a group's n_sub grids (grids[u]: same n, S seeds each;
+ * candidate index u * S + i). The new seed set around candidate (u, i) is, per axis
+ * a, the interval centred on its axis value with the refined half-span
+ * 2 half_a / (n_a - 1) (for n_a = 1 the grid's own centre and half-span). Two such
+ * boxes overlap when, in every axis, their centres are equal or lie less than the
+ * sum of their half-spans apart: fabs(c1 - c2) < 0.999999999 * (h1 + h2). The factor
+ * makes boxes that only touch (centres two spacings apart on one grid) count as
+ * disjoint whatever the rounding of the centres.
+ *
+ * Greedy in increasing (rss, candidate index): a candidate is taken when its box
+ * overlaps none taken before, until n_ref are taken; NaN is never taken. Per taken
+ * reference r: ref_idx[r], ref_rss[r], and new_grids[r] = its grid refined around it
+ * (as oracle_refine_grid). Past the last one taken: -1, NaN, and a copy of
+ * new_grids[0] (of grids[0] if none was taken). Returns the number taken. */
+static void candidate_box(const double grid[14], const int32_t n[4], int64_t i, double c[4],
+                          double h[4])
+{
+    int32_t idx[4];
+    int64_t rest = i;
+    for (int a = 3; a >= 0; --a) {
+        idx[a] = (int32_t)(rest % n[a]);
+        rest /= n[a];
+    }
+    for (int a = 0; a < 4; ++a) {
+        if (n[a] > 1) {
+            c[a] = oracle_axis_value(grid[6 + a], grid[10 + a], n[a], idx[a]);
+            h[a] = (2.0 * grid[10 + a]) / (double)(n[a] - 1);
+        } else {
+            c[a] = grid[6 + a];
+            h[a] = grid[10 + a];
+        }
+    }
+}
+
+static int boxes_overlap(const double c1[4], const double h1[4], const double c2[4],
+                         const double h2[4])
+{
+    for (int a = 0; a < 4; ++a)
+        if (!(c1[a] == c2[a] || fabs(c1[a] - c2[a]) < 0.999999999 * (h1[a] + h2[a])))
+            return 0;
+    return 1;
+}
+
+int32_t oracle_sparse_select(const double *grids, const double *rss, int32_t n_sub,
+                             const int32_t n[4], int32_t n_ref, int64_t *ref_idx,
+                             double *ref_rss, double *new_grids)
+{
+    const int64_t S = (int64_t)n[0] * n[1] * n[2] * n[3];
+    const int64_t total = S * n_sub;
+    oracle_pair *p = (oracle_pair *)malloc(sizeof(oracle_pair) * (size_t)(total > 0 ? total : 1));
+    double *tc = (double *)malloc(sizeof(double) * 4 * (size_t)(n_ref > 0 ? n_ref : 1));
+    double *th = (double *)malloc(sizeof(double) * 4 * (size_t)(n_ref > 0 ? n_ref : 1));
+    int64_t m = 0;
+    for (int64_t j = 0; j < total; ++j)
+        if (!isnan(rss[j])) {
+            p[m].v = rss[j];
+            p[m].i = j;
+            ++m;
+        }
+    qsort(p, (size_t)m, sizeof(oracle_pair), pair_cmp);
+    int32_t taken = 0;
+    for (int64_t q = 0; q < m && taken < n_ref; ++q) {
+        const int64_t j = p[q].i;
+        const double *g = grids + 14 * (j / S);
+        double c[4], h[4];
+        candidate_box(g, n, j % S, c, h);
+        int free_box = 1;
+        for (int32_t r = 0; r < taken && free_box; ++r)
+            if (boxes_overlap(c, h, tc + 4 * r, th + 4 * r))
+                free_box = 0;
+        if (!free_box)
+            continue;
+        memcpy(tc + 4 * taken, c, sizeof c);
+        memcpy(th + 4 * taken, h, sizeof h);
+        ref_idx[taken] = j;
+        ref_rss[taken] = p[q].v;
+        memcpy(new_grids + 14 * taken, g, 14 * sizeof(double));
+        oracle_refine_grid(new_grids + 14 * taken, n, j % S);
+        ++taken;
+    }
+    for (int32_t r = taken; r < n_ref; ++r) {
+        ref_idx[r] = -1;
+        ref_rss[r] = NAN;
+        memcpy(new_grids + 14 * r, taken > 0 ? new_grids : grids, 14 * sizeof(double));
+    }
+    free(p);
+    free(tc);
+    free(th);
+    return taken;
+}

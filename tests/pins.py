@@ -494,3 +494,56 @@ def pin_topk(o):
 ALL_SIMPLE.append(pin_jacobian_straight)
 ALL_SIMPLE.append(pin_topk)
 ALL_EVENT.extend([pin_gradient_fd, pin_lm_truth])
+
+
+# ------------------------------------------------------------------ several references
+def pin_sparse_select_hand(o):
+    """One axis of 5 points (spacing 1, refined half-span 1): boxes of neighbours
+    overlap, boxes two points apart only touch. RSS [5, 1, 2, 3, 4] takes points 1
+    and 3; a NaN is never taken; equal RSS go to the lower candidate index."""
+    g = np.zeros(14)
+    g[3:6] = [50.0, 0.0, 20.0]
+    g[6:10] = [0.0, 100.0, 0.0, 0.0]
+    g[10:14] = [0.0, 0.0, 0.0, 2.0]
+    n = np.array([1, 1, 1, 5], np.int32)
+    idx, rr, ng, t = o.sparse_select(g[None, :], np.array([5.0, 1.0, 2.0, 3.0, 4.0]), n, 3)
+    assert t == 2 and idx.tolist() == [1, 3, -1], (idx, t)
+    assert rr[0] == 1.0 and rr[1] == 3.0 and np.isnan(rr[2])
+    assert ng[0, 9] == -1.0 and ng[0, 13] == 1.0 and ng[1, 9] == 1.0 and ng[1, 13] == 1.0
+    assert np.array_equal(ng[2], ng[0]) and np.array_equal(ng[0, :9], g[:9])
+    idx, _, _, t = o.sparse_select(g[None, :], np.array([np.nan, 2.0, 9.0, 2.0, 2.0]), n, 5)
+    assert idx.tolist() == [1, 3, -1, -1, -1] and t == 2, idx
+    # two sub-grids whose refined boxes coincide: the second copy is never taken
+    idx, _, _, t = o.sparse_select(np.stack([g, g]), np.array([5.0, 1.0, 9, 9, 9, 5.0, 1.0, 9, 9, 9]),
+                                   n, 4)
+    assert idx[0] == 1 and 6 not in idx.tolist(), idx
+
+
+def pin_sparse_select_chebyshev(o):
+    """On one grid the refined box of a seed spans one spacing each way, so two seeds'
+    boxes overlap exactly when their grid indices differ by at most 1 on every axis
+    (Chebyshev distance 1). Greedy on that index rule, written independently, must
+    give the same references on random RSS with many ties."""
+    rng = np.random.default_rng(11)
+    n = np.array([3, 4, 5, 6], np.int32)
+    g = np.zeros(14)
+    g[0:6] = [500.0, 0.0, 10.0, 0.0, 80.0, 30.0]
+    g[6:10] = [0.0, 86.0, 0.0, 0.0]
+    g[10:14] = [5.0, 5.0, 0.05, 0.05]
+    S = int(np.prod(n))
+    coords = np.stack(np.unravel_index(np.arange(S), tuple(n)), axis=1)
+    for trial in range(4):
+        rss = np.round(rng.uniform(0, 10, S), 1)
+        rss[rng.integers(0, S, 20)] = np.nan
+        order = sorted((v, i) for i, v in enumerate(rss) if not np.isnan(v))
+        want = []
+        for v, i in order:
+            if all(np.max(np.abs(coords[i] - coords[j])) > 1 for j in want):
+                want.append(i)
+            if len(want) == 12:
+                break
+        idx, _, _, t = o.sparse_select(g[None, :], rss, n, 12)
+        assert idx[:t].tolist() == want, (trial, idx, want)
+
+
+ALL_SIMPLE.extend([pin_sparse_select_hand, pin_sparse_select_chebyshev])

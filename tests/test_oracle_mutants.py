@@ -48,6 +48,12 @@ MUTANTS = {
     "lm_accepts_worse": ("        if (rss2 < rss) {\n            for (int r = 0; r < 6; ++r) {", "        if (rss2 > rss) {\n            for (int r = 0; r < 6; ++r) {"),
     "lm_gradient_sign": ("            rhs[r] = -b[r];", "            rhs[r] = b[r];"),
     "topk_ties_reversed": ("    return x->i < y->i ? -1 : (x->i > y->i ? 1 : 0);", "    return x->i > y->i ? -1 : (x->i < y->i ? 1 : 0);"),
+    "sparse_any_axis_overlaps": ("        if (!(c1[a] == c2[a] || fabs(c1[a] - c2[a]) < 0.999999999 * (h1[a] + h2[a])))\n            return 0;\n    return 1;",
+                                 "        if ((c1[a] == c2[a] || fabs(c1[a] - c2[a]) < 0.999999999 * (h1[a] + h2[a])))\n            return 1;\n    return 0;"),
+    "sparse_unrefined_half": ("            h[a] = (2.0 * grid[10 + a]) / (double)(n[a] - 1);\n        } else {",
+                              "            h[a] = grid[10 + a];\n        } else {"),
+    "sparse_keeps_overlaps": ("            if (boxes_overlap(c, h, tc + 4 * r, th + 4 * r))\n                free_box = 0;",
+                              "            if (boxes_overlap(c, h, tc + 4 * r, th + 4 * r))\n                free_box = 1;"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
