@@ -109,7 +109,7 @@ def cpu_baseline(ev, sc, target_s: float):
 def bench_batch(events, sc, reps: int = 3):
     """Every partition of `events` through the batched path, captured in a HIP graph."""
     import torch
-    from paper_1911_09340_amd import comet, scan
+    from paper_1911_09340_amd import comet, quality, refine, scan
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     packed = scan.PackedEvents.from_events(events)   # host CSR pack + copy to the device
@@ -156,7 +156,51 @@ def bench_batch(events, sc, reps: int = 3):
             "scan_fp64_frac": flops / (scan_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
             "kernel_shape": tune["shape"],
             "graph": "one HIP graph per run (frames, per scan: refine, counter reset, "
-                     "persistent scan with in-kernel selection; classification)"}
+                     "persistent scan with in-kernel selection; classification)",
+            "momentum_residual": refine.summary(
+                refine.momentum_residuals(runner.best_seed.t().contiguous(), events)),
+            "classification": quality.classification(runner.mask.cpu().numpy(), events)}
+
+
+def bench_multiref(events, sc, n_ref: int = 10, n_iter: int = 2, n_fine=(4, 8, 8, 8),
+                   n_final: int = 10, reps: int = 3):
+    """The iterative re-scan around several sparse references (first scan on the full
+    grid, n_iter re-scans of n_ref finer grids per partition, n_final final seeds and
+    their classifications), captured in one HIP graph per run."""
+    import torch
+    from paper_1911_09340_amd import comet, multiref, quality, refine
+    run = multiref.MultiRefRunner(events, sc, n_ref=n_ref, n_iter=n_iter, n_fine=n_fine,
+                                  n_final=n_final)
+    run.capture()
+    run.replay()
+    torch.cuda.synchronize()
+    dts = []
+    for r in range(reps):
+        t0 = time.perf_counter()
+        run.replay()
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - t0)
+        log("  graph replay %d: %.3f s" % (r, dts[-1]))
+    dt = float(np.median(dts))
+    comet.profile_begin()
+    run.run()
+    torch.cuda.synchronize()
+    prof = comet.profile_end()
+    S0, S1 = int(np.prod(sc.n)), int(np.prod(n_fine))
+    masks = run.mask.cpu().numpy().reshape(run.n_part, n_final, -1)
+    frss = run.final_rss.cpu().numpy()
+    return {"events": len(events), "partitions": run.n_part,
+            "first_grid": "x".join(map(str, sc.n)), "references": n_ref,
+            "rescans": n_iter, "rescan_grid": "x".join(map(str, n_fine)),
+            "final_seeds": n_final,
+            "seeds_per_partition": S0 + n_iter * n_ref * S1,
+            "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "evals_per_s": run.evals_per_run / dt,
+            "scan_kernel_ms_per_run": prof["dca"][0],
+            "final_refs_taken_mean": float(np.mean(np.sum(~np.isnan(frss), axis=1))),
+            "momentum_residual": refine.summary(refine.momentum_residuals(run.best_seeds(),
+                                                                          events)),
+            "classification": quality.classification(masks[:, 0, :], events)}
 
 
 def bench_stress(events, sc, top_k: int = 64, n_iter: int = 8):
@@ -209,6 +253,8 @@ def main():
     ap.add_argument("--grad-topk", type=int, default=16,
                     help="LM starts per partition (the lowest-RSS coarse seeds)")
     ap.add_argument("--grad-iters", type=int, default=32, help="LM iterations")
+    ap.add_argument("--no-multiref", dest="multiref", action="store_false",
+                    help="skip the several-reference re-scan on the batched mix")
     ap.add_argument("--stress-events", type=int, default=0,
                     help="events of the stress mix (1-6 turns, 200-1200 hits, 30%% noise, "
                          "131072 seeds, 2000 x 1.5 mm) through the batched scan and LM from "
@@ -365,8 +411,19 @@ def main():
         log("  %.1f events/s, %.3g seed x hit evals/s, scan kernel %.1f %% of FP64 peak"
             % (out["batch"]["events_per_s"], out["batch"]["evals_per_s"],
                100 * out["batch"]["scan_fp64_frac"]))
+    if batch_events and args.multiref:
+        log("several references: %d events, 10 references, 2 re-scans of 4x8x8x8 ..."
+            % len(batch_events))
+        out["multiref"] = bench_multiref(batch_events, synth.C2)
+        m = out["multiref"]
+        log("  %.1f events/s; |p| residual core %.3f MeV/c (single reference %.3f); "
+            "efficiency %.3f purity %.3f (single reference %.3f %.3f)"
+            % (m["events_per_s"], m["momentum_residual"]["core_sigma"],
+               out["batch"]["momentum_residual"]["core_sigma"],
+               m["classification"]["efficiency_mean"], m["classification"]["purity_mean"],
+               out["batch"]["classification"]["efficiency_mean"],
+               out["batch"]["classification"]["purity_mean"]))
     if grad_events:
-        from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))
         out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE,
                                             top_k=args.grad_topk, n_iter=args.grad_iters)

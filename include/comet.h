@@ -210,7 +210,8 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
  * comet_dca_rss bit for bit. A per-partition completion counter lets the block that
  * finishes a partition's last tile select its best seed inside the same launch. The
  * calls on `stream` are: a wire-frame kernel, then per scan [refine (not before the
- * first), counter reset, persistent scan], then classification. No host
+ * first), counter reset, persistent scan], then classification (skipped when
+ * best_seed, best_rss, hit_mask and n_borderline are all NULL). No host
  * synchronisation and no allocation: capturable.
  *   wire_ends, wire_offsets, drift   packed events, device (n_wires >= 1)
  *   event_wires  device int32[n_events + 1]; part_event device int32[n_partitions]
@@ -252,6 +253,40 @@ int comet_topk(const double *values, int64_t n, int32_t n_segments, int32_t k, i
                void *stream);
 int comet_grid_seeds(const double *grids, int32_t n_partitions, const int32_t n[4],
                      const int64_t *idx, int32_t k, double *seeds6, void *stream);
+
+/* Sparse reference seeds (Sec. 2.1: several low-RSS seeds, far enough apart that the
+ * finer seed sets fetched around them do not overlap, seed the next scan). Group g
+ * has n_sub grids grids[g][u][14] (same n for all, S = n0 n1 n2 n3) and their RSS
+ * rss[g][u][S]; candidate j = u S + i is seed i of grid u. A candidate's box has the
+ * centre of its axis values and, per axis, the refined half-span 2 half / (n - 1) (the
+ * grid's centre and half-span where n = 1). Two boxes overlap when on every axis the
+ * centres are equal or differ by less than 0.999999999 (h1 + h2). Greedy in increasing
+ * (rss, j): a candidate is taken when its box overlaps none taken before; NaN is never
+ * taken. For the r-th reference of group g (output row g n_ref + r):
+ *   ref_idx    device int64[n_groups][n_ref]: j (-1 past the last one taken)
+ *   ref_rss    device double[n_groups][n_ref] or NULL: its RSS (NaN past the last)
+ *   new_grids  device double[n_groups][n_ref][14]: grid u refined around seed i (as
+ *              comet_refine_grid); past the last taken, a copy of reference 0's (of
+ *              grids[g][0] when none was taken)
+ *   ref_grids  device double[n_groups][n_ref][14] or NULL: grid u itself (same filling)
+ *   ref_local  device int64[n_groups][n_ref] or NULL: i = j mod S (-1 past the last)
+ * n_ref 1..64, n_sub S < 2^31. One block per group, on `stream`; no allocation. */
+int comet_sparse_select(const double *grids, const double *rss, int32_t n_groups, int32_t n_sub,
+                        const int32_t n[4], int32_t n_ref, int64_t *ref_idx, double *ref_rss,
+                        double *new_grids, double *ref_grids, int64_t *ref_local, void *stream);
+
+/* The classification step of comet_batch_scan on its own (Sec. 2.1, hit classification
+ * of the chosen seed): for partition p, seed best[p] of grids[p] (best[p] < 0: NaN seed,
+ * empty mask) is extrapolated and its hits classified as comet_select_classify does.
+ * Arguments as in comet_batch_scan; rss (device double[n_partitions][S]) may be NULL
+ * only when best_rss is NULL. Launches one kernel on `stream`. */
+int comet_batch_classify(const double *grids, int32_t n_partitions, const int32_t n[4],
+                         const int64_t *best, const double *rss, const double *wire_ends,
+                         int32_t n_wires, const int32_t *wire_offsets, const double *drift,
+                         int32_t n_hits, const int32_t *event_wires, int32_t n_events,
+                         const int32_t *part_event, const comet_config *cfg, double *best_seed,
+                         double *best_rss, uint8_t *hit_mask, int64_t mask_stride,
+                         int32_t *n_borderline, void *stream);
 
 /* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
  * per LDS chunk, the persistent block count on the current device); every shape

@@ -348,6 +348,13 @@ def _bind_batch(lib):
     lib.comet_topk.restype = ctypes.c_int
     lib.comet_grid_seeds.argtypes = [_vp, _i32, I4, _vp, _i32, _vp, _vp]
     lib.comet_grid_seeds.restype = ctypes.c_int
+    lib.comet_sparse_select.argtypes = [_vp, _vp, _i32, _i32, I4, _i32, _vp, _vp, _vp, _vp, _vp,
+                                        _vp]
+    lib.comet_sparse_select.restype = ctypes.c_int
+    lib.comet_batch_classify.argtypes = [_vp, _i32, I4, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp,
+                                         _i32, _vp, ctypes.POINTER(Config), _vp, _vp, _vp, _i64,
+                                         _vp, _vp]
+    lib.comet_batch_classify.restype = ctypes.c_int
     lib._batch_bound = True
     return lib
 
@@ -417,3 +424,49 @@ def grid_seeds(grids: torch.Tensor, n, idx: torch.Tensor, out: torch.Tensor) -> 
                                 _ptr(idx, torch.int64, "idx", (NP, k)), k,
                                 _ptr(out, torch.float64, "out", (6, NP * k)), _stream()),
            "comet_grid_seeds")
+
+
+def sparse_select(grids: torch.Tensor, rss: torch.Tensor, n, n_ref: int, ref_idx: torch.Tensor,
+                  new_grids: torch.Tensor, ref_rss=None, ref_grids=None, ref_local=None) -> None:
+    """comet_sparse_select: grids [G, n_sub, 14], rss [G, n_sub, S] -> ref_idx [G, n_ref],
+    new_grids [G, n_ref, 14] (optional ref_rss [G, n_ref], ref_grids [G, n_ref, 14],
+    ref_local [G, n_ref])."""
+    lib = _bind_batch(load())
+    G, n_sub = int(grids.shape[0]), int(grids.shape[1])
+    S = int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
+    R = int(n_ref)
+    _check(lib.comet_sparse_select(
+        _ptr(grids, torch.float64, "grids", (G, n_sub, 14)),
+        _ptr(rss, torch.float64, "rss", (G, n_sub, S)), G, n_sub, _n4(n), R,
+        _ptr(ref_idx, torch.int64, "ref_idx", (G, R)),
+        _ptr(ref_rss, torch.float64, "ref_rss", (G, R), optional=True),
+        _ptr(new_grids, torch.float64, "new_grids", (G, R, 14)),
+        _ptr(ref_grids, torch.float64, "ref_grids", (G, R, 14), optional=True),
+        _ptr(ref_local, torch.int64, "ref_local", (G, R), optional=True), _stream()),
+        "comet_sparse_select")
+
+
+def batch_classify(packed, part_event: torch.Tensor, grids: torch.Tensor, n, cfg: Config,
+                   best: torch.Tensor, rss=None, best_seed=None, best_rss=None, hit_mask=None,
+                   n_borderline=None) -> None:
+    """comet_batch_classify: classify seed best[p] of grids[p] for every partition p."""
+    lib = _bind_batch(load())
+    NP = int(part_event.shape[0])
+    S = int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
+    n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
+    n_e = int(packed.event_wires.shape[0]) - 1
+    stride = int(hit_mask.shape[1]) if hit_mask is not None else 0
+    _check(lib.comet_batch_classify(
+        _ptr(grids, torch.float64, "grids", (NP, 14)), NP, _n4(n),
+        _ptr(best, torch.int64, "best", (NP,)),
+        _ptr(rss, torch.float64, "rss", (NP, S), optional=True),
+        _ptr(packed.wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(packed.drift, torch.float64, "drift", (n_h,)), n_h,
+        _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e,
+        _ptr(part_event, torch.int32, "part_event", (NP,)), ctypes.byref(cfg),
+        _ptr(best_seed, torch.float64, "best_seed", (NP, 6), optional=True),
+        _ptr(best_rss, torch.float64, "best_rss", (NP,), optional=True),
+        _ptr(hit_mask, torch.uint8, "hit_mask", (NP, stride), optional=True), stride,
+        _ptr(n_borderline, torch.int32, "n_borderline", (NP,), optional=True), _stream()),
+        "comet_batch_classify")

@@ -356,6 +356,160 @@ __global__ __launch_bounds__(kSelectThreads) void topk_kernel(const double *__re
     }
 }
 
+// ------------------------------------------------------------------ several references
+// Sec. 2.1: several low-RSS seeds become reference points of the next, finer scan,
+// sparse enough that the new seed sets around them do not overlap. A candidate is a
+// seed (u, i) of one of a group's n_sub grids; its new seed set is the box centred on
+// its axis values with the refined half-spans 2 half / (n - 1) (the grid's own centre
+// and half-span on an axis with n = 1). Boxes overlap when on every axis the centres
+// are equal or fabs(c1 - c2) < 0.999999999 * (h1 + h2) (the factor keeps boxes that
+// only touch apart whatever the rounding). Greedy in increasing (rss, candidate
+// index): a candidate is taken when its box overlaps none taken before.
+constexpr int kMaxRefs = 64;
+
+__device__ __forceinline__ void candidate_box(const double *__restrict__ g, const int (&n)[4],
+                                              int64_t i, double (&c)[4], double (&h)[4])
+{
+    int idx[4];
+    int64_t rest = i;
+    for (int a = 3; a >= 0; --a) {
+        idx[a] = (int)(rest % n[a]);
+        rest /= n[a];
+    }
+    for (int a = 0; a < 4; ++a) {
+        if (n[a] > 1) {
+            c[a] = axis_value(g[6 + a], g[10 + a], n[a], idx[a]);
+            h[a] = (2.0 * g[10 + a]) / (double)(n[a] - 1);
+        } else {
+            c[a] = g[6 + a];
+            h[a] = g[10 + a];
+        }
+    }
+}
+
+__device__ __forceinline__ bool boxes_overlap(const double (&c1)[4], const double (&h1)[4],
+                                              const double *c2, const double *h2)
+{
+    for (int a = 0; a < 4; ++a)
+        if (!(c1[a] == c2[a] || fabs(c1[a] - c2[a]) < 0.999999999 * (h1[a] + h2[a])))
+            return false;
+    return true;
+}
+
+// One block per group. Each round, every thread finds its lowest (rss, index)
+// candidate whose box is free, the block reduces to the winner and wave 0 records it.
+// Control flow around the barriers is block-uniform (the winner comes from LDS).
+__global__ __launch_bounds__(kSelectThreads) void sparse_select_kernel(
+    const double *__restrict__ grids, const double *__restrict__ rss, int n_sub, int n0, int n1,
+    int n2, int n3, int64_t S, int n_ref, int64_t *__restrict__ ref_idx,
+    double *__restrict__ ref_rss, double *__restrict__ new_grids, double *__restrict__ ref_grids,
+    int64_t *__restrict__ ref_local)
+{
+    __shared__ double tc[kMaxRefs][4], th[kMaxRefs][4];
+    __shared__ double wv[kSelectThreads / 64];
+    __shared__ int64_t wi[kSelectThreads / 64];
+    __shared__ double win_v;
+    __shared__ int64_t win_i;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n[4] = {n0, n1, n2, n3};
+    const int64_t grp = blockIdx.x;
+    const double *gg = grids + 14 * grp * n_sub;
+    const double *rr = rss + grp * n_sub * S;
+    const int64_t total = S * n_sub;
+    const int64_t out0 = grp * n_ref;
+    int taken = 0;
+    for (int r = 0; r < n_ref; ++r) {
+        MinLoc m{INFINITY, -1};
+        for (int64_t j = threadIdx.x; j < total; j += kSelectThreads) {
+            const double v = rr[j];
+            if (!(v < m.v || (m.i < 0 && v == m.v)))
+                continue;  // not better than this thread's best so far (NaN never is)
+            double c[4], h[4];
+            candidate_box(gg + 14 * (j / S), n, j % S, c, h);
+            bool free_box = true;
+            for (int t = 0; t < taken && free_box; ++t)
+                if (boxes_overlap(c, h, tc[t], th[t]))
+                    free_box = false;
+            if (free_box) {
+                m.v = v;
+                m.i = j;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            MinLoc o{__shfl_xor(m.v, off), __shfl_xor(m.i, off)};
+            if (beats(o, m))
+                m = o;
+        }
+        if (lane == 0) {
+            wv[wave] = m.v;
+            wi[wave] = m.i;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            MinLoc a{INFINITY, -1};
+            if (lane < kSelectThreads / 64) {
+                a.v = wv[lane];
+                a.i = wi[lane];
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                MinLoc o{__shfl_xor(a.v, off), __shfl_xor(a.i, off)};
+                if (beats(o, a))
+                    a = o;
+            }
+            if (lane == 0) {
+                win_v = a.v;
+                win_i = a.i;
+            }
+        }
+        __syncthreads();
+        const int64_t j = __builtin_amdgcn_readfirstlane((int)win_i);  // < 2^31 (host check)
+        if (j < 0)
+            break;
+        if (wave == 0 && lane == 0) {
+            const double *g = gg + 14 * (j / S);
+            double c[4], h[4];
+            candidate_box(g, n, j % S, c, h);
+            for (int a = 0; a < 4; ++a) {
+                tc[taken][a] = c[a];
+                th[taken][a] = h[a];
+            }
+            ref_idx[out0 + r] = j;
+            if (ref_rss)
+                ref_rss[out0 + r] = win_v;
+            if (ref_local)
+                ref_local[out0 + r] = j % S;
+            double d[14];
+            for (int q = 0; q < 14; ++q)
+                d[q] = g[q];
+            if (ref_grids)
+                for (int q = 0; q < 14; ++q)
+                    ref_grids[14 * (out0 + r) + q] = d[q];
+            refine_grid_desc(d, n0, n1, n2, n3, j % S);
+            for (int q = 0; q < 14; ++q)
+                new_grids[14 * (out0 + r) + q] = d[q];
+        }
+        __syncthreads();
+        ++taken;
+    }
+    // past the last reference: -1, NaN and copies of reference 0 (of grid 0 if none)
+    for (int r = taken; r < n_ref; ++r) {
+        if (threadIdx.x == 0) {
+            ref_idx[out0 + r] = -1;
+            if (ref_rss)
+                ref_rss[out0 + r] = NAN;
+            if (ref_local)
+                ref_local[out0 + r] = -1;
+        }
+        if (threadIdx.x < 14) {
+            const int q = threadIdx.x;
+            new_grids[14 * (out0 + r) + q] = taken > 0 ? new_grids[14 * out0 + q] : gg[q];
+            if (ref_grids)
+                ref_grids[14 * (out0 + r) + q] = taken > 0 ? ref_grids[14 * out0 + q] : gg[q];
+        }
+    }
+}
+
 // Seeds at chosen grid indices: out[:, p k + r] = seed idx[p k + r] of grids[p]
 // (NaN for idx < 0). One thread per (partition, rank).
 __global__ void grid_seeds_kernel(const double *__restrict__ grids, int n0, int n1, int n2, int n3,
@@ -477,6 +631,23 @@ BatchLayout batch_layout(void *ws, int n_wires, int n_partitions)
     return l;
 }
 
+int launch_batch_classify(const double *grids, int n_partitions, const int32_t n[4], int64_t S,
+                          const int64_t *best, const double *rss, const double *wire_ends,
+                          const int32_t *wire_offsets, const double *drift,
+                          const int32_t *event_wires, const int32_t *part_event,
+                          const comet_config *cfg, double *best_seed, double *best_rss,
+                          uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
+                          hipStream_t hs)
+{
+    const size_t lds = sizeof(double) * 3 * (size_t)(cfg->n_steps + 1);
+    hipLaunchKernelGGL(batch_classify_kernel, dim3(n_partitions), dim3(kBatchClassifyThreads), lds,
+                       hs, grids, n[0], n[1], n[2], n[3], S, best, rss, wire_ends, wire_offsets,
+                       drift, event_wires, part_event, cfg->bz_tesla, cfg->charge_e,
+                       cfg->step_mm, cfg->n_steps, cfg->lambda_mm, best_seed, best_rss, hit_mask,
+                       mask_stride, n_borderline);
+    return launched("batch_classify_kernel");
+}
+
 }  // namespace
 
 extern "C" {
@@ -590,14 +761,74 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
     }
     if (st)
         return st;
-    const size_t lds = sizeof(double) * 3 * (size_t)(cfg->n_steps + 1);
-    hipLaunchKernelGGL(batch_classify_kernel, dim3(n_partitions), dim3(kBatchClassifyThreads), lds,
-                       hs, (const double *)grids, n[0], n[1], n[2], n[3], S,
-                       (const int64_t *)best, (const double *)rss, wire_ends, wire_offsets, drift,
-                       event_wires, part_event, cfg->bz_tesla, cfg->charge_e, cfg->step_mm,
-                       cfg->n_steps, cfg->lambda_mm, best_seed, best_rss, hit_mask, mask_stride,
-                       n_borderline);
-    return launched("batch_classify_kernel");
+    if (!best_seed && !best_rss && !hit_mask && !n_borderline)
+        return COMET_OK;  // no classification output asked for
+    return launch_batch_classify(grids, n_partitions, n, S, best, rss, wire_ends, wire_offsets,
+                                 drift, event_wires, part_event, cfg, best_seed, best_rss,
+                                 hit_mask, mask_stride, n_borderline, hs);
+}
+
+int comet_batch_classify(const double *grids, int32_t n_partitions, const int32_t n[4],
+                         const int64_t *best, const double *rss, const double *wire_ends,
+                         int32_t n_wires, const int32_t *wire_offsets, const double *drift,
+                         int32_t n_hits, const int32_t *event_wires, int32_t n_events,
+                         const int32_t *part_event, const comet_config *cfg, double *best_seed,
+                         double *best_rss, uint8_t *hit_mask, int64_t mask_stride,
+                         int32_t *n_borderline, void *stream)
+{
+    clear_error();
+    if (!grids || !n || !best || !wire_ends || !wire_offsets || !event_wires || !part_event)
+        return fail(COMET_EINVAL, "comet_batch_classify: NULL pointer");
+    if (n_partitions < 1 || n_wires < 1 || n_hits < 0 || (n_hits > 0 && !drift) || n_events < 1)
+        return fail(COMET_EINVAL, "comet_batch_classify: bad sizes");
+    if (best_rss && !rss)
+        return fail(COMET_EINVAL, "comet_batch_classify: best_rss needs rss");
+    if (hit_mask && mask_stride < 1)
+        return fail(COMET_EINVAL, "comet_batch_classify: mask_stride must be >= 1");
+    int64_t S = 1;
+    for (int a = 0; a < 4; ++a) {
+        if (n[a] < 1)
+            return fail(COMET_EINVAL, "comet_batch_classify: n[%d] < 1", a);
+        S *= n[a];
+    }
+    int st = check_config(cfg);
+    if (st)
+        return st;
+    if (cfg->n_steps > 2400)
+        return fail(COMET_EUNSUPPORTED, "comet_batch_classify: n_steps %d > 2400", cfg->n_steps);
+    st = check_device();
+    if (st)
+        return st;
+    return launch_batch_classify(grids, n_partitions, n, S, best, rss, wire_ends, wire_offsets,
+                                 drift, event_wires, part_event, cfg, best_seed, best_rss,
+                                 hit_mask, mask_stride, n_borderline, (hipStream_t)stream);
+}
+
+int comet_sparse_select(const double *grids, const double *rss, int32_t n_groups, int32_t n_sub,
+                        const int32_t n[4], int32_t n_ref, int64_t *ref_idx, double *ref_rss,
+                        double *new_grids, double *ref_grids, int64_t *ref_local, void *stream)
+{
+    clear_error();
+    if (!grids || !rss || !n || !ref_idx || !new_grids)
+        return fail(COMET_EINVAL, "comet_sparse_select: NULL pointer");
+    if (n_groups < 1 || n_sub < 1 || n_ref < 1 || n_ref > kMaxRefs)
+        return fail(COMET_EINVAL, "comet_sparse_select: need n_groups, n_sub >= 1 and "
+                                  "1 <= n_ref <= %d", kMaxRefs);
+    int64_t S = 1;
+    for (int a = 0; a < 4; ++a) {
+        if (n[a] < 1)
+            return fail(COMET_EINVAL, "comet_sparse_select: n[%d] < 1", a);
+        S *= n[a];
+    }
+    if (S * n_sub > ((int64_t)1 << 31) - 1)
+        return fail(COMET_EINVAL, "comet_sparse_select: more than 2^31 - 1 candidates a group");
+    const int st = check_device();
+    if (st)
+        return st;
+    hipLaunchKernelGGL(sparse_select_kernel, dim3(n_groups), dim3(kSelectThreads), 0,
+                       (hipStream_t)stream, grids, rss, n_sub, n[0], n[1], n[2], n[3], S, n_ref,
+                       ref_idx, ref_rss, new_grids, ref_grids, ref_local);
+    return launched("sparse_select_kernel");
 }
 
 int comet_topk(const double *values, int64_t n, int32_t n_segments, int32_t k, int64_t *idx,

@@ -194,3 +194,48 @@ def test_batch_topk_and_seed_rejects(lib):
     bad = list(args)
     bad[0] = None
     assert lib.comet_batch_scan(*bad, _p(0x100000), ws, None) == comet.EINVAL
+
+
+def test_sparse_select_and_classify_reject(lib):
+    comet._bind_batch(lib)
+    n = _n4(2, 3, 1, 4)
+    ok = [_p(), _p(), 3, 2, n, 10, _p(), None, _p(), None, None, None]
+
+    def call(**kw):
+        a = list(ok)
+        names = ["grids", "rss", "n_groups", "n_sub", "n", "n_ref", "ref_idx", "ref_rss",
+                 "new_grids", "ref_grids", "ref_local", "stream"]
+        for k, v in kw.items():
+            a[names.index(k)] = v
+        return lib.comet_sparse_select(*a)
+
+    assert call(grids=None) == comet.EINVAL
+    assert call(rss=None) == comet.EINVAL
+    assert call(ref_idx=None) == comet.EINVAL
+    assert call(new_grids=None) == comet.EINVAL
+    assert call(n_groups=0) == comet.EINVAL
+    assert call(n_sub=0) == comet.EINVAL
+    assert call(n_ref=0) == comet.EINVAL
+    assert call(n_ref=65) == comet.EINVAL
+    assert call(n=_n4(2, 0, 1, 4)) == comet.EINVAL
+    assert call(n=_n4(1024, 1024, 1024, 2), n_sub=1) == comet.EINVAL   # 2^31 candidates
+    cfg = _cfg()
+    args = [_p(), 3, n, _p(), _p(), _p(), 10, _p(), _p(), 20, _p(), 2, _p(), ctypes.byref(cfg),
+            None, None, None, 0, None, None]
+    for i in (0, 3, 5, 7, 10, 12):                        # required pointers
+        bad = list(args)
+        bad[i] = None
+        assert lib.comet_batch_classify(*bad) == comet.EINVAL, i
+    bad = list(args)
+    bad[4], bad[15] = None, _p()                          # best_rss needs rss
+    assert lib.comet_batch_classify(*bad) == comet.EINVAL
+    bad = list(args)
+    bad[16], bad[17] = _p(), 0                            # mask without a stride
+    assert lib.comet_batch_classify(*bad) == comet.EINVAL
+    bad = list(args)
+    bad[1] = 0
+    assert lib.comet_batch_classify(*bad) == comet.EINVAL
+    long_cfg = _cfg(n_steps=5000)
+    bad = list(args)
+    bad[13] = ctypes.byref(long_cfg)
+    assert lib.comet_batch_classify(*bad) == comet.EUNSUPPORTED

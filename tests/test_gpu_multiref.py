@@ -1,0 +1,222 @@
+"""Several sparse reference seeds (Sec. 2.1) on the GPU vs the CPU reference:
+comet_sparse_select on its own (ties, NaN, infinities, one-point axes, several groups
+and sub-grids, up to 64 references), comet_batch_classify against the batched scan's
+own classification, and the whole iterative re-scan chain, every intermediate bit for
+bit."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_09340_amd import comet, multiref, scan, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    comet.load()
+    comet.set_batch_variant(0)
+
+
+def _groups(rng, G, n_sub, n, ties):
+    """G groups of n_sub sub-grids around one event's seed point, shifted by fractions
+    of a spacing so that boxes of different sub-grids overlap, and their RSS (a few
+    distinct values when ties, with NaN and infinity sprinkled in)."""
+    ev = synth.event_mix(int(rng.integers(0, 1000)))
+    sc = synth.ScanConfig("sel", tuple(n), (5.0, 5.0, 0.05, 0.05), 10, 2.0, 0.8)
+    base = synth.grid_descriptor(ev.ref_states[0], sc)
+    S = int(np.prod(n))
+    grids = np.repeat(base[None, None, :], G * n_sub, axis=0).reshape(G, n_sub, 14).copy()
+    half = base[10:14]
+    grids[..., 6:10] += rng.uniform(-0.6, 0.6, (G, n_sub, 4)) * half
+    grids[..., 10:14] *= rng.uniform(0.5, 1.5, (G, n_sub, 4))
+    if ties:
+        rss = rng.integers(0, 6, (G, n_sub, S)).astype(np.float64)
+    else:
+        rss = rng.uniform(0.0, 100.0, (G, n_sub, S))
+    rss[rng.random((G, n_sub, S)) < 0.05] = np.nan
+    rss[rng.random((G, n_sub, S)) < 0.02] = np.inf
+    return grids, rss
+
+
+def _select_gpu(grids, rss, n, R):
+    G = grids.shape[0]
+    d = dict(device="cuda")
+    idx = torch.empty(G, R, dtype=torch.int64, **d)
+    rr = torch.empty(G, R, dtype=torch.float64, **d)
+    ng = torch.empty(G, R, 14, dtype=torch.float64, **d)
+    rg = torch.empty(G, R, 14, dtype=torch.float64, **d)
+    loc = torch.empty(G, R, dtype=torch.int64, **d)
+    comet.sparse_select(torch.as_tensor(grids, **d), torch.as_tensor(rss, **d), n, R, idx, ng,
+                        ref_rss=rr, ref_grids=rg, ref_local=loc)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in (idx, rr, ng, rg, loc)]
+
+
+def _check_select(orc, grids, rss, n, R):
+    idx, rr, ng, rg, loc = _select_gpu(grids, rss, n, R)
+    S = int(np.prod(n))
+    for g in range(grids.shape[0]):
+        widx, wrss, wng, taken = orc.sparse_select(grids[g], rss[g], n, R)
+        assert np.array_equal(idx[g], widx), g
+        assert np.array_equal(rr[g], wrss, equal_nan=True), g
+        assert np.array_equal(ng[g], wng), g
+        for r in range(R):
+            if r < taken:
+                assert loc[g, r] == widx[r] % S
+                assert np.array_equal(rg[g, r], grids[g, widx[r] // S])
+            else:
+                assert loc[g, r] == -1
+                src = rg[g, 0] if taken else grids[g, 0]
+                assert np.array_equal(rg[g, r], src)
+    return idx
+
+
+@pytest.mark.parametrize("n,n_sub,R,ties", [
+    ((2, 3, 4, 5), 1, 10, False),
+    ((2, 3, 4, 5), 3, 10, True),
+    ((1, 4, 1, 6), 2, 5, True),     # one-point axes: the grid's own half-span
+    ((3, 3, 3, 3), 4, 64, True),    # more references than free boxes
+    ((4, 8, 8, 8), 10, 10, False),  # the re-scan shape: 20480 candidates
+    ((8, 16, 16, 16), 1, 1, False), # one reference of a full first scan
+])
+def test_sparse_select_matches_cpu(orc, n, n_sub, R, ties):
+    rng = np.random.default_rng([*n, n_sub, R, int(ties)])
+    grids, rss = _groups(rng, 5, n_sub, n, ties)
+    _check_select(orc, grids, rss, n, R)
+
+
+def test_sparse_select_all_nan_and_single_candidate(orc):
+    rng = np.random.default_rng(7)
+    n = (1, 1, 1, 1)
+    grids, rss = _groups(rng, 3, 1, n, False)
+    rss[0] = np.nan                     # nothing to take: -1, NaN, copies of grid 0
+    rss[1] = np.inf                     # infinity is a value, NaN is not
+    idx = _check_select(orc, grids, rss, n, 4)
+    assert idx[0, 0] == -1 and idx[1, 0] == 0 and idx[2, 0] == 0
+    assert (idx[:, 1:] == -1).all()
+
+
+def test_batch_classify_equals_batch_scan_classification():
+    events = [synth.event_mix(i) for i in range(4)]
+    sc = synth.ScanConfig("cls", (2, 4, 5, 7), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 1)
+    runner = scan.BatchRunner(events, sc)
+    runner.run()
+    NP = runner.n_part
+    seed = torch.empty(NP, 6, dtype=torch.float64, device="cuda")
+    brss = torch.empty(NP, dtype=torch.float64, device="cuda")
+    mask = torch.zeros_like(runner.mask)
+    nb = torch.empty(NP, dtype=torch.int32, device="cuda")
+    best = runner.best.clone()
+    best[1] = -1                        # no seed: NaN seed and RSS, empty mask
+    comet.batch_classify(runner.packed, runner.part_event, runner.grids, sc.n, runner.cfg, best,
+                         rss=runner.rss, best_seed=seed, best_rss=brss, hit_mask=mask,
+                         n_borderline=nb)
+    torch.cuda.synchronize()
+    keep = [p for p in range(NP) if p != 1]
+    assert torch.equal(seed[keep], runner.best_seed[keep])
+    assert torch.equal(brss[keep], runner.best_rss[keep])
+    assert torch.equal(mask[keep], runner.mask[keep])
+    assert torch.equal(nb[keep], runner.n_border[keep])
+    assert torch.isnan(seed[1]).all() and torch.isnan(brss[1])
+    assert int(mask[1].sum()) == 0 and int(nb[1]) == 0
+
+
+def _cfg(ev, sc):
+    return [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+
+
+def _oracle_chain(orc, ev, grid0, sc, n0, n_fine, R, n_iter, F):
+    """The same chain on the CPU for one partition: scans of every grid, selections."""
+    def scan_grids(grids, n):
+        out = []
+        for g in grids:
+            s = orc.seed_grid(g, np.asarray(n, np.int32))
+            r, _ = orc.scan(s, _cfg(ev, sc), sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+            out.append(r)
+        return np.stack(out)
+
+    steps = []
+    grids, n = grid0[None, :], n0
+    rss = scan_grids(grids, n)
+    steps.append((grids, rss))
+    for _ in range(n_iter):
+        _, _, ng, _ = orc.sparse_select(grids, rss, n, R)
+        grids, n = ng, n_fine
+        rss = scan_grids(grids, n)
+        steps.append((grids, rss))
+    idx, frss, _, taken = orc.sparse_select(grids, rss, n, F)
+    S = int(np.prod(n))
+    seeds, masks = [], []
+    for r in range(F):
+        if idx[r] < 0:
+            seeds.append(None)
+            masks.append(None)
+            continue
+        s = orc.seed(grids[idx[r] // S], np.asarray(n, np.int32), int(idx[r] % S))
+        m, _, _ = orc.classify(s, _cfg(ev, sc), sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                               ev.drift)
+        seeds.append(s)
+        masks.append(m)
+    return steps, idx, frss, seeds, masks
+
+
+@pytest.mark.parametrize("n_iter", [0, 2])
+def test_multiref_chain_matches_cpu(orc, n_iter):
+    events = [synth.event_mix(i) for i in (2, 5)]
+    sc = synth.ScanConfig("mref", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 800, 2.0, 0.8, 0)
+    n_fine, R, F = (2, 3, 3, 4), 4, 6
+    run = multiref.MultiRefRunner(events, sc, n_ref=R, n_iter=n_iter, n_fine=n_fine, n_final=F)
+    run.run()
+    torch.cuda.synchronize()
+    rss0 = run.rss0.cpu().numpy()
+    grids = [g.cpu().numpy() for g in run.grids]
+    rss = [r.cpu().numpy() for r in run.rss]
+    fidx = run.final_idx.cpu().numpy()
+    frss = run.final_rss.cpu().numpy()
+    fseed = run.final_seed.cpu().numpy().reshape(run.n_part, F, 6)
+    mask = run.mask.cpu().numpy().reshape(run.n_part, F, -1)
+    g0 = run.grids0.cpu().numpy()
+    p = 0
+    for ev in events:
+        for _ in range(ev.n_turns):
+            steps, widx, wrss, wseeds, wmasks = _oracle_chain(orc, ev, g0[p], sc, sc.n, n_fine,
+                                                              R, n_iter, F)
+            assert np.array_equal(rss0[p], steps[0][1][0]), p
+            for k in range(n_iter):
+                assert np.array_equal(grids[k][p], steps[k + 1][0]), (p, k)
+                assert np.array_equal(rss[k][p], steps[k + 1][1]), (p, k)
+            assert np.array_equal(fidx[p], widx), p
+            assert np.array_equal(frss[p], wrss, equal_nan=True), p
+            for r in range(F):
+                if wseeds[r] is None:
+                    assert np.isnan(fseed[p, r]).all()
+                    assert not mask[p, r].any()
+                else:
+                    assert np.array_equal(fseed[p, r], wseeds[r]), (p, r)
+                    assert np.array_equal(mask[p, r, :ev.n_hits], wmasks[r]), (p, r)
+            p += 1
+
+
+def test_multiref_graph_replays_match_eager():
+    events = [synth.event_mix(i) for i in (1, 4, 9)]
+    sc = synth.ScanConfig("mref-g", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 600, 2.0, 0.8, 0)
+    run = multiref.MultiRefRunner(events, sc, n_ref=3, n_iter=2, n_fine=(2, 2, 3, 3), n_final=5)
+    run.run()
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (run.rss[-1], run.final_idx, run.final_seed, run.mask)]
+    run.capture()
+    for rep in range(3):
+        for t in (run.rss[-1], run.final_seed):
+            t.fill_(-7.0)
+        run.mask.fill_(0)
+        run.replay()
+        torch.cuda.synchronize()
+        got = (run.rss[-1], run.final_idx, run.final_seed, run.mask)
+        for a, b in zip(got, want):
+            if a.is_floating_point():
+                a, b = a.nan_to_num(123.0), b.nan_to_num(123.0)
+            assert torch.equal(a, b), rep
