@@ -74,6 +74,11 @@ def _bind(lib):
                                         _d, _d, _u8, _d]
     lib.oracle_topk.restype = None
     lib.oracle_topk.argtypes = [_d, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_layer_veto.restype = ctypes.c_int32
+    lib.oracle_layer_veto.argtypes = [ctypes.POINTER(ctypes.c_uint8), _i32, ctypes.c_int32, _i32,
+                                      ctypes.c_int32]
+    lib.oracle_merge_halves.restype = ctypes.c_int32
+    lib.oracle_merge_halves.argtypes = [_d, _i32, _d, _i32, ctypes.c_int32, _i32, _d]
     lib.oracle_sparse_select.restype = ctypes.c_int32
     lib.oracle_sparse_select.argtypes = [_d, _d, ctypes.c_int32, _i32, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int64), _d, _d]
@@ -237,6 +242,28 @@ class Oracle:
                                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                               _p(rr), _p(ng))
         return idx, rr, ng, int(taken)
+
+    def layer_veto(self, mask, wire_offsets, wire_layer, n_layers):
+        """1 vetoed, 0 kept, -1 a layer out of range (one classified seed of a half)."""
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if m.size == 0:
+            m = np.zeros(1, np.uint8)
+        off = _i32a(wire_offsets)
+        lay = _i32a(wire_layer)
+        return int(self.lib.oracle_layer_veto(m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                              _p(off, _i32), off.size - 1, _p(lay, _i32),
+                                              int(n_layers)))
+
+    def merge_halves(self, rss_a, veto_a, rss_b, veto_b):
+        """Ranked complete sets of two half sets: (pair, pair_rss, count)."""
+        ra, rb = _f64(rss_a).ravel(), _f64(rss_b).ravel()
+        va, vb = _i32a(veto_a), _i32a(veto_b)
+        F = ra.size
+        pair = np.empty(F * F, np.int32)
+        prss = np.empty(F * F)
+        n = self.lib.oracle_merge_halves(_p(ra), _p(va, _i32), _p(rb), _p(vb, _i32), F,
+                                         _p(pair, _i32), _p(prss))
+        return pair, prss, int(n)
 
     def topk(self, values, k):
         v = _f64(values)

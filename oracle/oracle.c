@@ -940,3 +940,83 @@ int32_t oracle_sparse_select(const double *grids, const double *rss, int32_t n_s
     free(th);
     return taken;
 }
+
+/* ------------------------------------------------------------ half tracks (Sec. 3.1)
+ * Missing-layer veto. A finally selected seed of a half track comes with its half set
+ * of classified hits (bit 0 of mask, indexed by the half's hits); a seed whose set
+ * leaves some layer without a hit is excluded. The half track starts in front of the
+ * first layer and runs out to its outermost classified layer L, so every layer
+ * 0..L must hold a classified hit. Returns 1 (vetoed) when one is missing or no hit
+ * is classified, 0 when none is missing, -1 when a wire's layer lies outside
+ * [0, n_layers). Wire i owns hits [wire_offsets[i] - wire_offsets[0],
+ * wire_offsets[i + 1] - wire_offsets[0]) of the mask. */
+int32_t oracle_layer_veto(const uint8_t *mask, const int32_t *wire_offsets, int32_t n_wires,
+                          const int32_t *wire_layer, int32_t n_layers)
+{
+    int has[256];
+    if (n_layers < 1 || n_layers > 256)
+        return -1;
+    for (int32_t l = 0; l < n_layers; ++l)
+        has[l] = 0;
+    for (int32_t i = 0; i < n_wires; ++i) {
+        if (wire_layer[i] < 0 || wire_layer[i] >= n_layers)
+            return -1;
+        for (int32_t j = wire_offsets[i]; j < wire_offsets[i + 1]; ++j)
+            if (mask[j - wire_offsets[0]] & 1)
+                has[wire_layer[i]] = 1;
+    }
+    int32_t outer = -1;
+    for (int32_t l = 0; l < n_layers; ++l)
+        if (has[l])
+            outer = l;
+    if (outer < 0)
+        return 1;
+    for (int32_t l = 0; l <= outer; ++l)
+        if (!has[l])
+            return 1;
+    return 0;
+}
+
+/* Combinatorial merge of two half sets (Sec. 3.1): every entrance seed i and exit
+ * seed j (F each) form a complete set when neither is vetoed (veto == 0) and neither
+ * RSS is NaN. With no fit, complete sets are ranked by their combined RSS
+ * rss_a[i] + rss_b[j] (each half's RSS over its own wires; the halves share no
+ * wire), ascending, ties by the pair index i F + j. pair[k] = i F + j of rank k and
+ * pair_rss[k] its combined RSS; -1 and NaN past the last. Returns the number of
+ * complete sets. */
+typedef struct {
+    double v;
+    int32_t k;
+} oracle_rank;
+
+static int rank_cmp(const void *x, const void *y)
+{
+    const oracle_rank *a = (const oracle_rank *)x, *b = (const oracle_rank *)y;
+    if (a->v < b->v)
+        return -1;
+    if (a->v > b->v)
+        return 1;
+    return (a->k > b->k) - (a->k < b->k);
+}
+
+int32_t oracle_merge_halves(const double *rss_a, const int32_t *veto_a, const double *rss_b,
+                            const int32_t *veto_b, int32_t F, int32_t *pair, double *pair_rss)
+{
+    oracle_rank *r = (oracle_rank *)malloc(sizeof(oracle_rank) * (size_t)(F > 0 ? F * F : 1));
+    int32_t m = 0;
+    for (int32_t i = 0; i < F; ++i)
+        for (int32_t j = 0; j < F; ++j) {
+            if (veto_a[i] != 0 || veto_b[j] != 0 || isnan(rss_a[i]) || isnan(rss_b[j]))
+                continue;
+            r[m].v = rss_a[i] + rss_b[j];
+            r[m].k = i * F + j;
+            ++m;
+        }
+    qsort(r, (size_t)m, sizeof(oracle_rank), rank_cmp);
+    for (int32_t k = 0; k < F * F; ++k) {
+        pair[k] = k < m ? r[k].k : -1;
+        pair_rss[k] = k < m ? r[k].v : NAN;
+    }
+    free(r);
+    return m;
+}

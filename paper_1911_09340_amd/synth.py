@@ -131,6 +131,25 @@ def _outward_crossing(state0, charge, bz, s_len, radius=SEED_RADIUS, ds=0.5):
     return 0.5 * (lo + hi)
 
 
+def _inward_crossing(state0, charge, bz, s_lo, s_hi, radius=SEED_RADIUS, ds=0.5):
+    """First arc length in [s_lo, s_hi] where the helix crosses `radius` inward (None if none)."""
+    s = np.arange(s_lo, s_hi + ds, ds)
+    st = helix_state(state0, charge, bz, s)
+    r = np.hypot(st[:, 0], st[:, 1])
+    down = np.nonzero((r[:-1] >= radius) & (r[1:] < radius))[0]
+    if down.size == 0:
+        return None
+    lo, hi = s[down[0]], s[down[0] + 1]
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        st_m = helix_state(state0, charge, bz, mid)
+        if np.hypot(st_m[0], st_m[1]) >= radius:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
 def helix_hits(state0, charge: float, bz: float, s_len: float, ds: float = 0.5):
     """Truth hits of one helix segment: (wire_id, dca, s_pca, z_pca) arrays.
 
@@ -224,7 +243,9 @@ class Event:
     wire_ids [n_w] (sorted), wire_ends [n_w, 6], wire_offsets [n_w + 1] (every wire
     holds at least one hit), drift [n_h]; truth: hit_turn [n_h] (-1 = noise),
     true_dca [n_h] (nan for noise); ref_states [n_turns, 6] = the true state at each
-    turn's first outward crossing of r = 500 mm (the seed-grid centre).
+    turn's first outward crossing of r = 500 mm (the seed-grid centre); exit_states
+    [n_turns, 6] = the true state where that turn crosses r = 500 mm inward again (NaN
+    if it does not within the turn).
     """
     wire_ids: np.ndarray
     wire_ends: np.ndarray
@@ -236,6 +257,7 @@ class Event:
     charge: float = -1.0
     bz: float = 1.0
     meta: dict = field(default_factory=dict)
+    exit_states: np.ndarray = None
 
     @property
     def n_wires(self) -> int:
@@ -275,7 +297,7 @@ def make_event(state0, n_turns: int, rng: np.random.Generator, *, charge: float 
     wires = _wires()
     st = np.array(state0, dtype=np.float64)
     hit_w, hit_d, hit_t = [], [], []
-    refs = []
+    refs, exits = [], []
     for t in range(n_turns):
         L = turn_length(st, charge, bz)
         w, dca, _, _ = helix_hits(st, charge, bz, L)
@@ -283,6 +305,8 @@ def make_event(state0, n_turns: int, rng: np.random.Generator, *, charge: float 
         if s_ref is None:
             raise ValueError("turn %d never crosses r = %.0f mm outward" % (t, SEED_RADIUS))
         refs.append(helix_state(st, charge, bz, s_ref))
+        s_exit = _inward_crossing(st, charge, bz, s_ref, L)
+        exits.append(np.full(6, np.nan) if s_exit is None else helix_state(st, charge, bz, s_exit))
         hit_w.append(w)
         hit_d.append(dca)
         hit_t.append(np.full(w.size, t, dtype=np.int32))
@@ -311,7 +335,8 @@ def make_event(state0, n_turns: int, rng: np.random.Generator, *, charge: float 
                  wire_offsets=offsets, drift=np.ascontiguousarray(drift, dtype=np.float64),
                  hit_turn=turn.astype(np.int32), true_dca=true,
                  ref_states=np.ascontiguousarray(np.stack(refs)), charge=charge, bz=bz,
-                 meta={"n_signal": int(np.sum(turn >= 0)), "n_noise": int(noise)})
+                 meta={"n_signal": int(np.sum(turn >= 0)), "n_noise": int(noise)},
+                 exit_states=np.ascontiguousarray(np.stack(exits)))
 
 
 def vertex_state(p: float, polar: float, azimuth: float, vertex=(0.0, 0.0, 0.0)) -> np.ndarray:
@@ -460,3 +485,57 @@ def event_mix_batch(seeds, workers: int = 0, kind: str = "mix"):
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         return pool.map(fn, seeds, chunksize=max(1, len(seeds) // (4 * workers)))
+
+
+# ---------------------------------------------------------------- half tracks
+def circle_centre(state, charge: float, bz: float) -> np.ndarray:
+    """Transverse centre of the helix through `state` (x, y)."""
+    xt = complex(state[0], state[1])
+    pt = complex(state[3], state[4])
+    c = xt - 1j * pt / (KAPPA * charge * bz)
+    return np.array([c.real, c.imag])
+
+
+def wire_layers(wire_ids) -> np.ndarray:
+    return (np.asarray(wire_ids, dtype=np.int32) // WIRES_PER_LAYER).astype(np.int32)
+
+
+def _sub_event(ev: Event, wire_sel: np.ndarray, state, charge: float, meta: dict) -> Event:
+    wsel = np.nonzero(wire_sel)[0]
+    counts = np.diff(ev.wire_offsets)[wsel]
+    offsets = np.zeros(wsel.size + 1, dtype=np.int32)
+    offsets[1:] = np.cumsum(counts)
+    hits = (np.concatenate([np.arange(ev.wire_offsets[i], ev.wire_offsets[i + 1])
+                            for i in wsel]) if wsel.size else np.zeros(0, np.int64))
+    hits = hits.astype(np.int64)
+    return Event(wire_ids=ev.wire_ids[wsel].copy(),
+                 wire_ends=np.ascontiguousarray(ev.wire_ends[wsel]).reshape(-1, 6),
+                 wire_offsets=offsets, drift=np.ascontiguousarray(ev.drift[hits]),
+                 hit_turn=ev.hit_turn[hits].copy(), true_dca=ev.true_dca[hits].copy(),
+                 ref_states=np.ascontiguousarray(np.asarray(state, np.float64)[None, :]),
+                 charge=charge, bz=ev.bz, meta=dict(meta, hits=hits))
+
+
+def half_events(ev: Event, turn: int):
+    """The two half tracks of one turn partition (Sec. 3.1) as one-turn pseudo-events.
+
+    Entrance half: the event's wires on the entrance side, seeded at the turn's outward
+    crossing of r = 500 mm. Exit half: the wires on the other side, seeded at the
+    inward crossing with momentum and charge flipped, so that its tracks run backwards
+    from the exit. The two sides are split by the line through the chamber axis and the
+    turn's true circle centre (the entrance and exit points are mirror images across
+    it), taking each wire at its midpoint (z = 0); a wire exactly on the line goes to the
+    entrance side. The true circle stands in for the paper's Hough-transform circle.
+    meta["hits"] maps each half's hits to the event's hit indices.
+    """
+    ref = ev.ref_states[turn]
+    ext = ev.exit_states[turn]
+    c = circle_centre(ref, ev.charge, ev.bz)
+    mid = 0.5 * (ev.wire_ends[:, :2] + ev.wire_ends[:, 3:5])
+    side = c[0] * mid[:, 1] - c[1] * mid[:, 0]
+    s_in = c[0] * ref[1] - c[1] * ref[0]
+    entrance = (side == 0.0) | (np.sign(side) == np.sign(s_in))
+    flipped = np.concatenate([ext[:3], -ext[3:]])
+    a = _sub_event(ev, entrance, ref, ev.charge, {"turn": turn, "side": "entrance"})
+    b = _sub_event(ev, ~entrance, flipped, -ev.charge, {"turn": turn, "side": "exit"})
+    return a, b

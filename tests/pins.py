@@ -547,3 +547,76 @@ def pin_sparse_select_chebyshev(o):
 
 
 ALL_SIMPLE.extend([pin_sparse_select_hand, pin_sparse_select_chebyshev])
+
+
+# ------------------------------------------------------------------ half tracks
+def pin_layer_veto_hand(o):
+    """Wires on layers [0, 0, 1, 2, 3] with 1, 2, 1, 1, 1 hits. A half set must hold a
+    classified hit on every layer from the first out to its outermost one."""
+    off = np.array([0, 1, 3, 4, 5, 6], np.int32)
+    lay = np.array([0, 0, 1, 2, 3], np.int32)
+    cases = [
+        ([1, 0, 0, 1, 1, 1], 0),   # layers 0..3 all present
+        ([0, 0, 1, 1, 1, 0], 0),   # 0, 1, 2: the outermost classified layer is 2
+        ([1, 0, 0, 0, 1, 1], 1),   # layer 1 missing
+        ([0, 0, 0, 1, 1, 1], 1),   # layer 0 missing
+        ([0, 0, 0, 0, 0, 0], 1),   # nothing classified
+        ([2, 2, 2, 2, 2, 2], 1),   # borderline bits alone are not classifications
+        ([3, 0, 0, 0, 0, 0], 0),   # layer 0 alone
+    ]
+    for mask, want in cases:
+        got = o.layer_veto(np.array(mask, np.uint8), off, lay, 18)
+        assert got == want, (mask, got, want)
+    # offsets need not start at zero: the mask is indexed from the first wire's hits
+    assert o.layer_veto(np.array([1, 0, 0, 1, 1, 1], np.uint8), off + 7, lay, 18) == 0
+    assert o.layer_veto(np.array([1, 0, 0, 1, 1, 1], np.uint8), off, lay, 3) == -1
+
+
+def pin_layer_veto_sets(o):
+    """Random layouts against the definition written with Python sets."""
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        n_w = int(rng.integers(1, 12))
+        lay = np.sort(rng.integers(0, 6, n_w)).astype(np.int32)
+        counts = rng.integers(1, 4, n_w)
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        mask = (rng.random(off[-1]) < 0.6).astype(np.uint8) * rng.integers(1, 4, off[-1]).astype(np.uint8)
+        held = {int(lay[i]) for i in range(n_w) if any(mask[off[i]:off[i + 1]] & 1)}
+        want = 1 if not held or set(range(max(held) + 1)) - held else 0
+        assert o.layer_veto(mask, off, lay, 6) == want, trial
+
+
+def pin_merge_hand(o):
+    """F = 3: entrance RSS [1, NaN, 0.5], exit RSS [2, 1, 1] with exit seed 1 vetoed.
+    Complete sets (i, j): (2,2) 1.5, (0,2) 2, (2,0) 2.5, (0,0) 3."""
+    pair, prss, m = o.merge_halves([1.0, np.nan, 0.5], [0, 0, 0], [2.0, 1.0, 1.0], [0, 1, 0])
+    assert m == 4 and pair.tolist() == [8, 2, 6, 0, -1, -1, -1, -1, -1], pair
+    assert prss[:4].tolist() == [1.5, 2.0, 2.5, 3.0] and np.isnan(prss[4:]).all()
+    # equal sums rank by pair index; a vetoed entrance seed removes its row
+    pair, _, m = o.merge_halves([1.0, 1.0], [0, 0], [1.0, 1.0], [0, 0])
+    assert m == 4 and pair.tolist() == [0, 1, 2, 3]
+    pair, _, m = o.merge_halves([1.0, 1.0], [1, 0], [1.0, 1.0], [0, 0])
+    assert m == 2 and pair.tolist() == [2, 3, -1, -1]
+    pair, _, m = o.merge_halves([1.0, 1.0], [1, 1], [1.0, 1.0], [0, 0])
+    assert m == 0 and (pair == -1).all()
+
+
+def pin_merge_sorted(o):
+    """Random halves against Python's sort of (sum, i, j) tuples."""
+    rng = np.random.default_rng(9)
+    for trial in range(50):
+        F = int(rng.integers(1, 12))
+        ra = np.round(rng.uniform(0, 5, F), 1)
+        rb = np.round(rng.uniform(0, 5, F), 1)
+        ra[rng.random(F) < 0.1] = np.nan
+        va = (rng.random(F) < 0.2).astype(np.int32)
+        vb = (rng.random(F) < 0.2).astype(np.int32)
+        want = sorted((ra[i] + rb[j], i, j) for i in range(F) for j in range(F)
+                      if not va[i] and not vb[j] and not np.isnan(ra[i]) and not np.isnan(rb[j]))
+        pair, prss, m = o.merge_halves(ra, va, rb, vb)
+        assert m == len(want), trial
+        assert pair[:m].tolist() == [i * F + j for _, i, j in want], trial
+        assert prss[:m].tolist() == [v for v, _, _ in want], trial
+
+
+ALL_SIMPLE.extend([pin_layer_veto_hand, pin_layer_veto_sets, pin_merge_hand, pin_merge_sorted])

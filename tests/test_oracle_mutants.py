@@ -54,6 +54,12 @@ MUTANTS = {
                               "            h[a] = grid[10 + a];\n        } else {"),
     "sparse_keeps_overlaps": ("            if (boxes_overlap(c, h, tc + 4 * r, th + 4 * r))\n                free_box = 0;",
                               "            if (boxes_overlap(c, h, tc + 4 * r, th + 4 * r))\n                free_box = 1;"),
+    "veto_skips_layer0": ("    for (int32_t l = 0; l <= outer; ++l)\n        if (!has[l])", "    for (int32_t l = 1; l <= outer; ++l)\n        if (!has[l])"),
+    "veto_keeps_empty": ("    if (outer < 0)\n        return 1;", "    if (outer < 0)\n        return 0;"),
+    "veto_any_bit": ("            if (mask[j - wire_offsets[0]] & 1)", "            if (mask[j - wire_offsets[0]])"),
+    "merge_ignores_exit_veto": ("if (veto_a[i] != 0 || veto_b[j] != 0 ||", "if (veto_a[i] != 0 ||"),
+    "merge_ties_reversed": ("    return (a->k > b->k) - (a->k < b->k);", "    return (a->k < b->k) - (a->k > b->k);"),
+    "merge_transposed_pair": ("            r[m].k = i * F + j;", "            r[m].k = j * F + i;"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 

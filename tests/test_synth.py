@@ -72,3 +72,35 @@ def test_grid_descriptor_layout():
     assert np.array_equal(g[10:], [5.0, 5.0, 0.05, 0.05])
     assert synth.C1.n_seeds == 65536 and synth.C2.n_seeds == 32768
     assert synth.C3_FINE.n_seeds == 32 ** 4 and synth.C3_COARSE.n_seeds == 8 ** 4
+
+
+def test_exit_states_and_half_split():
+    """The exit seed sits on r = 500 mm moving inward, mirrors the entrance point across
+    the line through the axis and the circle centre, and the two halves partition the
+    event's wires and hits."""
+    for seed in range(4):
+        ev = synth.event_mix(seed)
+        for t in range(ev.n_turns):
+            ref, ext = ev.ref_states[t], ev.exit_states[t]
+            assert abs(np.hypot(ext[0], ext[1]) - synth.SEED_RADIUS) < 1e-6
+            assert ext[0] * ext[3] + ext[1] * ext[4] < 0          # inward
+            assert ref[0] * ref[3] + ref[1] * ref[4] > 0          # outward
+            c = synth.circle_centre(ref, ev.charge, ev.bz)
+            cx = synth.circle_centre(ext, ev.charge, ev.bz)
+            assert np.allclose(c, cx, atol=1e-6)                  # same circle
+            u = c / np.linalg.norm(c)
+            mirror = 2.0 * np.dot(ref[:2], u) * u - ref[:2]
+            assert np.allclose(mirror, ext[:2], atol=1e-6)
+            a, b = synth.half_events(ev, t)
+            assert a.n_wires + b.n_wires == ev.n_wires
+            assert sorted(np.concatenate([a.wire_ids, b.wire_ids]).tolist()) == ev.wire_ids.tolist()
+            hits = np.concatenate([a.meta["hits"], b.meta["hits"]])
+            assert sorted(hits.tolist()) == list(range(ev.n_hits))
+            assert np.array_equal(a.drift, ev.drift[a.meta["hits"]])
+            assert np.array_equal(b.ref_states[0], np.concatenate([ext[:3], -ext[3:]]))
+            assert b.charge == -ev.charge and a.charge == ev.charge
+            # the flipped exit seed retraces the turn backwards: same circle centre
+            assert np.allclose(synth.circle_centre(b.ref_states[0], b.charge, b.bz), c, atol=1e-6)
+            # each half holds a good share of the turn's own hits
+            own = np.sum(ev.hit_turn == t)
+            assert np.sum(a.hit_turn == t) > 0.25 * own and np.sum(b.hit_turn == t) > 0.25 * own
