@@ -203,6 +203,43 @@ def bench_multiref(events, sc, n_ref: int = 10, n_iter: int = 2, n_fine=(4, 8, 8
             "classification": quality.classification(masks[:, 0, :], events)}
 
 
+def bench_halves(events, sc, n_ref: int = 10, n_iter: int = 2, n_fine=(4, 8, 8, 8),
+                 n_final: int = 10, reps: int = 3):
+    """Both half tracks of every partition through the several-reference scan (half the
+    RK4 steps each), the missing-layer veto and the ranked merge of half sets, captured
+    in one HIP graph per run."""
+    import torch
+    from paper_1911_09340_amd import halves, quality, refine
+    run = halves.HalfTrackRunner(events, sc, n_ref=n_ref, n_iter=n_iter, n_fine=n_fine,
+                                 n_final=n_final)
+    run.capture()
+    run.replay()
+    torch.cuda.synchronize()
+    dts = []
+    for r in range(reps):
+        t0 = time.perf_counter()
+        run.replay()
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - t0)
+        log("  graph replay %d: %.3f s" % (r, dts[-1]))
+    dt = float(np.median(dts))
+    nc = run.n_complete.cpu().numpy()
+    seeds = run.best_complete_seeds()
+    have = ~np.isnan(seeds[:, 0, 0])
+    p_true = refine.true_momenta(events)
+    res = np.linalg.norm(seeds[have, 0, 3:], axis=1) - p_true[have]
+    vetoed = [float(np.mean(v.cpu().numpy() != 0)) for v in run.veto]
+    return {"events": len(events), "partitions": run.n_part, "rk4_steps_per_half": run.sc_half.n_steps,
+            "first_grid": "x".join(map(str, sc.n)), "references": n_ref, "rescans": n_iter,
+            "rescan_grid": "x".join(map(str, n_fine)), "final_seeds_per_side": n_final,
+            "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "evals_per_s": run.evals_per_run / dt,
+            "vetoed_fraction_entrance_exit": vetoed,
+            "partitions_with_complete_set": float(np.mean(nc > 0)),
+            "momentum_residual_entrance": refine.summary(res) if res.size else None,
+            "classification": quality.classification(run.best_complete_masks(), events)}
+
+
 def bench_stress(events, sc, top_k: int = 64, n_iter: int = 8):
     """The stress mix: one batched scan of every partition, then Levenberg-Marquardt
     from the top_k lowest-RSS seeds of each partition (device time per phase)."""
@@ -255,6 +292,8 @@ def main():
     ap.add_argument("--grad-iters", type=int, default=32, help="LM iterations")
     ap.add_argument("--no-multiref", dest="multiref", action="store_false",
                     help="skip the several-reference re-scan on the batched mix")
+    ap.add_argument("--no-halves", dest="halves", action="store_false",
+                    help="skip the half-track scans and merge on the batched mix")
     ap.add_argument("--stress-events", type=int, default=0,
                     help="events of the stress mix (1-6 turns, 200-1200 hits, 30%% noise, "
                          "131072 seeds, 2000 x 1.5 mm) through the batched scan and LM from "
@@ -423,6 +462,14 @@ def main():
                m["classification"]["efficiency_mean"], m["classification"]["purity_mean"],
                out["batch"]["classification"]["efficiency_mean"],
                out["batch"]["classification"]["purity_mean"]))
+    if batch_events and args.halves:
+        log("half tracks: %d events, both halves with several references, veto, merge ..."
+            % len(batch_events))
+        out["halves"] = bench_halves(batch_events, synth.C2)
+        h = out["halves"]
+        log("  %.1f events/s; complete sets in %.3f of partitions; efficiency %.3f purity %.3f"
+            % (h["events_per_s"], h["partitions_with_complete_set"],
+               h["classification"]["efficiency_mean"], h["classification"]["purity_mean"]))
     if grad_events:
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))
         out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE,

@@ -288,6 +288,38 @@ int comet_batch_classify(const double *grids, int32_t n_partitions, const int32_
                          double *best_rss, uint8_t *hit_mask, int64_t mask_stride,
                          int32_t *n_borderline, void *stream);
 
+/* Half tracks (Sec. 3.1): a turn partition is scanned as two half tracks, entrance and
+ * exit, each with its own hits; each side ends with its finally selected seeds and
+ * their half sets of classified hits.
+ *
+ * comet_layer_veto: a seed whose half set leaves a layer without a hit is excluded.
+ * Row r is one classified seed of packed event row_event[r] (event CSR as in
+ * comet_batch_scan; hit_mask[r] indexed by hit - wire_offsets[event_wires[e]], bit 0 =
+ * classified). Its half track runs from in front of the first layer out to its
+ * outermost classified layer L, so layers 0..L must each hold a classified hit.
+ *   veto   device int32[n_rows]: 1 vetoed (a layer missing, or nothing classified),
+ *          0 kept, -1 invalid row (a wire_layer outside [0, n_layers) or a hit index
+ *          past mask_stride)
+ *   wire_layer  device int32[n_wires]; n_layers 1..256. One block per row.
+ *
+ * comet_merge_halves: complete sets are formed by merging one half set of each side.
+ * For partition p, entrance seed i and exit seed j (n_seeds = F each, F 1..32) form a
+ * complete set when veto_a[p][i] == 0, veto_b[p][j] == 0 and neither RSS is NaN; with
+ * no track fit to rank them, complete sets are ranked by the combined RSS
+ * rss_a[p][i] + rss_b[p][j] (the two sides' wires are disjoint), ascending, ties by
+ * the pair index i F + j.
+ *   pair       device int32[n_partitions][F F]: i F + j of rank k (-1 past the last)
+ *   pair_rss   device double[n_partitions][F F]: its combined RSS (NaN past the last)
+ *   n_complete device int32[n_partitions] or NULL: the number of complete sets
+ * One block per partition; no allocation. */
+int comet_layer_veto(const uint8_t *hit_mask, int64_t mask_stride, int32_t n_rows,
+                     const int32_t *row_event, const int32_t *event_wires, int32_t n_events,
+                     const int32_t *wire_offsets, const int32_t *wire_layer, int32_t n_wires,
+                     int32_t n_layers, int32_t *veto, void *stream);
+int comet_merge_halves(const double *rss_a, const int32_t *veto_a, const double *rss_b,
+                       const int32_t *veto_b, int32_t n_partitions, int32_t n_seeds,
+                       int32_t *pair, double *pair_rss, int32_t *n_complete, void *stream);
+
 /* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
  * per LDS chunk, the persistent block count on the current device); every shape
  * gives the same results. comet_batch_set_variant selects the shape (default 0). */

@@ -355,6 +355,11 @@ def _bind_batch(lib):
                                          _i32, _vp, ctypes.POINTER(Config), _vp, _vp, _vp, _i64,
                                          _vp, _vp]
     lib.comet_batch_classify.restype = ctypes.c_int
+    lib.comet_layer_veto.argtypes = [_vp, _i64, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp,
+                                     _vp]
+    lib.comet_layer_veto.restype = ctypes.c_int
+    lib.comet_merge_halves.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]
+    lib.comet_merge_halves.restype = ctypes.c_int
     lib._batch_bound = True
     return lib
 
@@ -470,3 +475,34 @@ def batch_classify(packed, part_event: torch.Tensor, grids: torch.Tensor, n, cfg
         _ptr(hit_mask, torch.uint8, "hit_mask", (NP, stride), optional=True), stride,
         _ptr(n_borderline, torch.int32, "n_borderline", (NP,), optional=True), _stream()),
         "comet_batch_classify")
+
+
+def layer_veto(hit_mask: torch.Tensor, row_event: torch.Tensor, packed, wire_layer: torch.Tensor,
+               n_layers: int, veto: torch.Tensor) -> None:
+    """comet_layer_veto: hit_mask [rows, stride] (uint8), row_event [rows] -> veto [rows]."""
+    lib = _bind_batch(load())
+    rows, stride = int(hit_mask.shape[0]), int(hit_mask.shape[1])
+    n_w = int(packed.wire_ends.shape[0])
+    n_e = int(packed.event_wires.shape[0]) - 1
+    _check(lib.comet_layer_veto(
+        _ptr(hit_mask, torch.uint8, "hit_mask", (rows, stride)), stride, rows,
+        _ptr(row_event, torch.int32, "row_event", (rows,)),
+        _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e,
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(wire_layer, torch.int32, "wire_layer", (n_w,)), n_w, int(n_layers),
+        _ptr(veto, torch.int32, "veto", (rows,)), _stream()), "comet_layer_veto")
+
+
+def merge_halves(rss_a: torch.Tensor, veto_a: torch.Tensor, rss_b: torch.Tensor,
+                 veto_b: torch.Tensor, pair: torch.Tensor, pair_rss: torch.Tensor,
+                 n_complete=None) -> None:
+    """comet_merge_halves: [P, F] per side -> pair / pair_rss [P, F * F]."""
+    lib = _bind_batch(load())
+    P, F = int(rss_a.shape[0]), int(rss_a.shape[1])
+    _check(lib.comet_merge_halves(
+        _ptr(rss_a, torch.float64, "rss_a", (P, F)), _ptr(veto_a, torch.int32, "veto_a", (P, F)),
+        _ptr(rss_b, torch.float64, "rss_b", (P, F)), _ptr(veto_b, torch.int32, "veto_b", (P, F)),
+        P, F, _ptr(pair, torch.int32, "pair", (P, F * F)),
+        _ptr(pair_rss, torch.float64, "pair_rss", (P, F * F)),
+        _ptr(n_complete, torch.int32, "n_complete", (P,), optional=True), _stream()),
+        "comet_merge_halves")

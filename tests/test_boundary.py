@@ -239,3 +239,25 @@ def test_sparse_select_and_classify_reject(lib):
     bad = list(args)
     bad[13] = ctypes.byref(long_cfg)
     assert lib.comet_batch_classify(*bad) == comet.EUNSUPPORTED
+
+
+def test_layer_veto_and_merge_reject(lib):
+    comet._bind_batch(lib)
+    ok = [_p(), 16, 4, _p(), _p(), 2, _p(), _p(), 30, 18, _p(), None]
+    for i in (0, 3, 4, 6, 7, 10):
+        bad = list(ok)
+        bad[i] = None
+        assert lib.comet_layer_veto(*bad) == comet.EINVAL, i
+    for i, v in ((1, 0), (2, 0), (5, 0), (9, 0), (9, 257)):
+        bad = list(ok)
+        bad[i] = v
+        assert lib.comet_layer_veto(*bad) == comet.EINVAL, (i, v)
+    ok = [_p(), _p(), _p(), _p(), 5, 10, _p(), _p(), None, None]
+    for i in (0, 1, 2, 3, 6, 7):
+        bad = list(ok)
+        bad[i] = None
+        assert lib.comet_merge_halves(*bad) == comet.EINVAL, i
+    for i, v in ((4, 0), (5, 0), (5, 33)):
+        bad = list(ok)
+        bad[i] = v
+        assert lib.comet_merge_halves(*bad) == comet.EINVAL, (i, v)

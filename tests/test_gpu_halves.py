@@ -1,0 +1,165 @@
+"""Half tracks (Sec. 3.1) on the GPU vs the CPU reference: the missing-layer veto, the
+combinatorial merge of half sets, and the whole two-sided chain (several-reference
+scans of both halves, vetoes, ranked complete sets), every intermediate bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_09340_amd import comet, halves, scan, synth
+from test_gpu_multiref import _oracle_chain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    comet.load()
+    comet.set_batch_variant(0)
+
+
+def test_layer_veto_matches_cpu(orc):
+    """Random masks over the half events of real events (plus all-zero, all-one,
+    borderline-only and true-turn rows), one row per (half event, draw)."""
+    rng = np.random.default_rng(3)
+    evs = []
+    turn_of = []
+    for i in range(3):
+        ev = synth.event_mix(i)
+        for t in range(ev.n_turns):
+            evs.extend(synth.half_events(ev, t))
+            turn_of.extend([t, t])
+    packed = scan.PackedEvents.from_events(evs)
+    layers = torch.as_tensor(np.concatenate([synth.wire_layers(e.wire_ids) for e in evs]),
+                             device="cuda")
+    stride = max(e.n_hits for e in evs)
+    rows, row_event = [], []
+    for e, ev in enumerate(evs):
+        for kind in range(7):
+            if kind == 6:     # the half's own true hits: layers 0..apex, no gap
+                m = (ev.hit_turn == turn_of[e]).astype(np.uint8)
+            elif kind == 0:
+                m = np.zeros(ev.n_hits, np.uint8)
+            elif kind == 1:
+                m = np.ones(ev.n_hits, np.uint8)
+            elif kind == 2:
+                m = np.full(ev.n_hits, 2, np.uint8)
+            else:
+                m = (rng.random(ev.n_hits) < [0.3, 0.7, 0.95][kind - 3]).astype(np.uint8)
+            row = np.zeros(stride, np.uint8)
+            row[:ev.n_hits] = m
+            rows.append(row)
+            row_event.append(e)
+    mask = torch.as_tensor(np.stack(rows), device="cuda")
+    rev = torch.as_tensor(np.asarray(row_event, np.int32), device="cuda")
+    veto = torch.empty(len(rows), dtype=torch.int32, device="cuda")
+    comet.layer_veto(mask, rev, packed, layers, synth.N_LAYERS, veto)
+    torch.cuda.synchronize()
+    got = veto.cpu().numpy()
+    for r, e in enumerate(row_event):
+        ev = evs[e]
+        want = orc.layer_veto(rows[r][:ev.n_hits], ev.wire_offsets,
+                              synth.wire_layers(ev.wire_ids), synth.N_LAYERS)
+        assert got[r] == want, (r, e)
+    assert set(got.tolist()) >= {0, 1}
+    assert (got[6::7] == 0).sum() > len(evs) // 2      # true half sets are mostly kept
+
+
+@pytest.mark.parametrize("F", [1, 3, 10, 32])
+def test_merge_halves_matches_cpu(orc, F):
+    rng = np.random.default_rng(F)
+    P = 7
+    ra = np.round(rng.uniform(0, 4, (P, F)), 1)     # many equal sums
+    rb = np.round(rng.uniform(0, 4, (P, F)), 1)
+    ra[rng.random((P, F)) < 0.1] = np.nan
+    va = (rng.random((P, F)) < 0.25).astype(np.int32)
+    vb = (rng.random((P, F)) < 0.25).astype(np.int32)
+    va[0] = 1                                        # partition 0: no complete set
+    vb[1, :] = -1                                    # invalid rows count as excluded
+    d = dict(device="cuda")
+    pair = torch.empty(P, F * F, dtype=torch.int32, **d)
+    prss = torch.empty(P, F * F, dtype=torch.float64, **d)
+    nc = torch.empty(P, dtype=torch.int32, **d)
+    comet.merge_halves(torch.as_tensor(ra, **d), torch.as_tensor(va, **d),
+                       torch.as_tensor(rb, **d), torch.as_tensor(vb, **d), pair, prss, nc)
+    torch.cuda.synchronize()
+    pair, prss, nc = pair.cpu().numpy(), prss.cpu().numpy(), nc.cpu().numpy()
+    for p in range(P):
+        wp, wr, wn = orc.merge_halves(ra[p], va[p], rb[p], vb[p])
+        assert nc[p] == wn, p
+        assert np.array_equal(pair[p], wp), p
+        assert np.array_equal(prss[p], wr, equal_nan=True), p
+    assert nc[0] == 0 and nc[1] == 0
+
+
+def _check_side(orc, side, evs, sc, n_fine, R, n_iter, F):
+    fidx = side.final_idx.cpu().numpy()
+    frss = side.final_rss.cpu().numpy()
+    mask = side.mask.cpu().numpy().reshape(side.n_part, F, -1)
+    g0 = side.grids0.cpu().numpy()
+    wrss, wmasks = [], []
+    for p, ev in enumerate(evs):
+        steps, widx, wr, wseeds, wm = _oracle_chain(orc, ev, g0[p], sc, sc.n, n_fine, R,
+                                                    n_iter, F)
+        assert np.array_equal(fidx[p], widx), p
+        assert np.array_equal(frss[p], wr, equal_nan=True), p
+        for r in range(F):
+            if wm[r] is not None:
+                assert np.array_equal(mask[p, r, :ev.n_hits], wm[r]), (p, r)
+        wrss.append(wr)
+        wmasks.append(wm)
+    return np.asarray(wrss), wmasks
+
+
+def test_half_track_chain_matches_cpu(orc):
+    events = [synth.event_mix(i) for i in (4, 8)]
+    sc = synth.ScanConfig("half", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 800, 2.0, 0.8, 0)
+    n_fine, R, n_iter, F = (2, 3, 3, 4), 4, 1, 5
+    run = halves.HalfTrackRunner(events, sc, n_ref=R, n_iter=n_iter, n_fine=n_fine, n_final=F)
+    assert run.sc_half.n_steps == 400
+    run.run()
+    torch.cuda.synchronize()
+    vetoes = [v.cpu().numpy().reshape(run.n_part, F) for v in run.veto]
+    wrss, wveto = [], []
+    for s in range(2):
+        evs = run.half_events[s]
+        r, masks = _check_side(orc, run.sides[s], evs, run.sc_half, n_fine, R, n_iter, F)
+        wrss.append(r)
+        wv = np.ones((run.n_part, F), np.int32)
+        for p, ev in enumerate(evs):
+            for k in range(F):
+                if masks[p][k] is not None:
+                    wv[p, k] = orc.layer_veto(masks[p][k], ev.wire_offsets,
+                                              synth.wire_layers(ev.wire_ids), synth.N_LAYERS)
+                else:   # no seed: an empty mask, nothing classified
+                    wv[p, k] = 1
+        assert np.array_equal(vetoes[s], wv), s
+        wveto.append(wv)
+    pair = run.pair.cpu().numpy()
+    prss = run.pair_rss.cpu().numpy()
+    nc = run.n_complete.cpu().numpy()
+    for p in range(run.n_part):
+        wp, wr, wn = orc.merge_halves(wrss[0][p], wveto[0][p], wrss[1][p], wveto[1][p])
+        assert nc[p] == wn and np.array_equal(pair[p], wp), p
+        assert np.array_equal(prss[p], wr, equal_nan=True), p
+
+
+def test_half_track_graph_replays_match_eager():
+    events = [synth.event_mix(i) for i in (6, 10)]
+    sc = synth.ScanConfig("half-g", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 600, 2.0, 0.8, 0)
+    run = halves.HalfTrackRunner(events, sc, n_ref=3, n_iter=1, n_fine=(2, 2, 3, 3), n_final=4)
+    run.run()
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (run.pair, run.n_complete, run.veto[0], run.veto[1])]
+    want_rss = run.pair_rss.clone().nan_to_num(123.0)
+    run.capture()
+    for rep in range(3):
+        run.pair.fill_(-5)
+        run.veto[0].fill_(7)
+        run.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((run.pair, run.n_complete, run.veto[0], run.veto[1]), want):
+            assert torch.equal(a, b), rep
+        assert torch.equal(run.pair_rss.nan_to_num(123.0), want_rss), rep
