@@ -10,8 +10,10 @@ device memory when the timed region starts.
 
 Prints one JSON line. `value` = seed x hit DCA evaluations per second (sum over
 scans of seeds x hits, divided by wall time of the timed steps). `roofline` covers
-the dominant kernel (the DCA scan): algorithmic FP64 flops per launch / its average
-device time from HIP events recorded on its stream. `cpu_baseline` times the CPU
+the dominant kernel (the DCA scan): FP64 flops of the distance evaluations it
+performs per launch (15 per (seed, wire, point) evaluated, counted by the kernel;
+the scan skips points that a distance bound rules out, with the results of the
+full scan) / its average device time from HIP events recorded on its stream. `cpu_baseline` times the CPU
 reference (oracle/) on a bounded sample of the same workload on the host cores.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -143,7 +145,8 @@ def bench_batch(events, sc, reps: int = 3):
     for e, ev in enumerate(events):
         pw += ev.n_turns * ev.n_wires
     scans = sc.n_refine + 1
-    flops = FLOP_PER_POINT_WIRE * sc.n_seeds * (sc.n_steps + 1) * pw * scans
+    brute = FLOP_PER_POINT_WIRE * sc.n_seeds * (sc.n_steps + 1) * pw * scans
+    flops = FLOP_PER_POINT_WIRE * prof["scan_points"]   # distance evaluations performed
     scan_ms = prof["dca"][0]
     return {"events": len(events), "partitions": runner.n_part, "seeds_per_partition": sc.n_seeds,
             "scans_per_partition": scans, "rk4_steps": sc.n_steps,
@@ -154,6 +157,7 @@ def bench_batch(events, sc, reps: int = 3):
             "scan_kernel_ms_per_run": scan_ms,
             "scan_fp64_tflops": flops / (scan_ms * 1e-3) / 1e12,
             "scan_fp64_frac": flops / (scan_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "scan_points_evaluated_frac": flops / brute,
             "kernel_shape": tune["shape"],
             "graph": "one HIP graph per run (frames, per scan: refine, counter reset, "
                      "persistent scan with in-kernel selection; classification)",
@@ -256,7 +260,8 @@ def bench_stress(events, sc, top_k: int = 64, n_iter: int = 8):
     hits = [ev.n_hits for ev in events]
     pw = sum(ev.n_turns * ev.n_wires for ev in events)
     ph = sum(ev.n_turns * ev.n_hits for ev in events)
-    flops = FLOP_PER_POINT_WIRE * sc.n_seeds * (sc.n_steps + 1) * pw
+    brute = FLOP_PER_POINT_WIRE * sc.n_seeds * (sc.n_steps + 1) * pw
+    flops = FLOP_PER_POINT_WIRE * prof["scan_points"]
     scan_ms = prof["dca"][0]
     res = refine.summary(refine.momentum_residuals(out["refined"], events))
     return {"events": len(events), "partitions": out["partitions"],
@@ -267,6 +272,7 @@ def bench_stress(events, sc, top_k: int = 64, n_iter: int = 8):
             "evals_per_s": ph * sc.n_seeds / dt,
             "scan_kernel_ms": scan_ms, "scan_fp64_frac":
                 flops / (scan_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "scan_points_evaluated_frac": flops / brute,
             "momentum_residual": res,
             "timing": "wall time of the whole call: host pack, batched scan, top-k, LM"}
 
@@ -376,7 +382,7 @@ def main():
             comet.set_dca_variant(i)
             dt, prof = timed(max(2, args.steps // 2), 1)
             ms, n = prof["dca"]
-            tfl = FLOP_PER_POINT_WIRE * sc.n_seeds * ev.n_wires * P / (ms / n * 1e-3) / 1e12
+            tfl = FLOP_PER_POINT_WIRE * prof["scan_points"] / n / (ms / n * 1e-3) / 1e12
             log("variant %d %s: %.3f ms/step, dca %.3f ms/launch, %.1f TFLOP/s (%.1f %% of FP64 peak)"
                 % (i, v, dt / max(2, args.steps // 2) * 1e3, ms / n, tfl, 100 * tfl / PEAK_FP64_TFLOPS))
     comet.set_dca_variant(-1 if args.variant is None else args.variant)
@@ -388,7 +394,8 @@ def main():
     log("timed region %.3f s" % dt)
     ms_dca, n_dca = prof["dca"]
     dca_s = ms_dca / n_dca * 1e-3
-    flops = FLOP_PER_POINT_WIRE * sc.n_seeds * ev.n_wires * P
+    brute = FLOP_PER_POINT_WIRE * sc.n_seeds * ev.n_wires * P
+    flops = FLOP_PER_POINT_WIRE * prof["scan_points"] / n_dca   # per launch, performed
     achieved = flops / dca_s / 1e12
     ms_trk, n_trk = prof["track"]
     trk_bytes = 8 * 3 * P * sc.n_seeds + 8 * 6 * sc.n_seeds
@@ -431,7 +438,10 @@ def main():
             "avg_launch_ms": dca_s * 1e3,
             "launches": n_dca,
             "flop_per_launch": flops,
-            "flop_unit": "%d FP64 flop per (seed, wire, track point)" % FLOP_PER_POINT_WIRE,
+            "flop_unit": "%d FP64 flop per (seed, wire, track point) distance evaluated; the "
+                         "scan skips points a distance bound rules out" % FLOP_PER_POINT_WIRE,
+            "points_evaluated_frac": flops / brute,
+            "full_scan_equivalent_tflops": brute / dca_s / 1e12,
         },
         "track_recording": {
             "kernel": "rk4_record_kernel",
@@ -442,7 +452,8 @@ def main():
             "frac": trk_bytes / (ms_trk / n_trk * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "avg_launch_ms": ms_trk / n_trk,
         },
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()
+                               if k in comet.PROFILE_KINDS},
     }
     if batch_events:
         log("batched mix: %d events, persistent scans, HIP graph ..." % len(batch_events))

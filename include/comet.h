@@ -91,14 +91,18 @@ int comet_refine_grid(double *grid, const int32_t n[4], const int64_t *best, voi
 int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
                             double *track_xyz, void *stream);
 
-/* Bytes of workspace comet_dca_rss needs for n_seeds seeds and n_wires wires. */
-size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_wires);
+/* Bytes of workspace comet_dca_rss needs for n_seeds seeds of n_points recorded points
+ * and n_wires wires (0 for invalid sizes). */
+size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_points, int32_t n_wires);
 
 /* Distance of closest approach and Eq. 1 (Sec. 2.1, Sec. 2.2.2, Alg. 2).
  * For every seed and wire: the recorded point closest to the wire line (first
  * index on ties) is refined over its two adjacent chords to the DCA D; the wire
  * contributes d^2 with d = min(lambda, min_j |D - r_j|) over its hits j (lambda for
- * a wire without hits); rss[s] is the sum over wires in wire order.
+ * a wire without hits); rss[s] is the sum over wires in wire order. The scan skips
+ * runs of points that a distance bound proves cannot hold or tie a wire's closest
+ * point (the radii of 16-point windows of each track go to the workspace first); the
+ * results are those of the full scan for any track.
  *   track_xyz    device double[3][n_points][n_seeds] from comet_extrapolate_seeds
  *   n_points     must equal cfg->n_steps + 1
  *   wire_ends    device double[n_wires][6]: both endpoints of each wire (the wire is
@@ -108,7 +112,7 @@ size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_wires);
  *                non-decreasing, wire_offsets[n_wires] = n_hits
  *   drift        device double[n_hits]: drift distances r_j (finite)
  *   rss          device double[n_seeds], written
- *   workspace    device, >= comet_dca_workspace_bytes(n_seeds, n_wires) bytes,
+ *   workspace    device, >= comet_dca_workspace_bytes(n_seeds, n_points, n_wires) bytes,
  *                256-byte aligned; contents on entry are ignored */
 int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
                   const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
@@ -338,6 +342,11 @@ int comet_batch_set_variant(int id);
 #define COMET_PROFILE_KINDS 4
 int comet_profile_begin(void);
 int comet_profile_end(double ms[COMET_PROFILE_KINDS], int64_t launches[COMET_PROFILE_KINDS]);
+/* The number of (seed, wire, track point) distance evaluations the DCA scans (single
+ * event and batched) performed on the device current at comet_profile_begin, between
+ * it and the last comet_profile_end (the scans skip points a distance bound rules
+ * out, so this is at most seeds x wires x points per scan). COMET_EINVAL for NULL. */
+int comet_profile_scan_points(int64_t *points);
 
 /* ------------------------------------------------------------ tuning
  * The DCA kernel exists in several shapes: W wires per wave, NWV waves per block,

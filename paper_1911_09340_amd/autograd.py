@@ -24,7 +24,8 @@ class SeedRSS(torch.autograd.Function):
         comet.extrapolate_seeds(seeds_c, cfg, track)
         rss = torch.empty(S, dtype=torch.float64, device=seeds.device)
         comet.dca_rss(track, wire_ends, wire_offsets, drift, cfg, rss,
-                      comet.dca_workspace(S, int(wire_ends.shape[0]), seeds.device))
+                      comet.dca_workspace(S, cfg.n_steps + 1, int(wire_ends.shape[0]),
+                                          seeds.device))
         ctx.save_for_backward(seeds_c, wire_ends, wire_offsets, drift)
         ctx.cfg = cfg
         return rss

@@ -53,7 +53,7 @@ def load(path: str = LIB_PATH):
     lib.comet_seed_grid.argtypes = [_vp, I4, _vp, _i64, _vp]
     lib.comet_refine_grid.argtypes = [_vp, I4, _vp, _vp]
     lib.comet_extrapolate_seeds.argtypes = [_vp, _i64, ctypes.POINTER(Config), _vp, _vp]
-    lib.comet_dca_workspace_bytes.argtypes = [_i64, _i32]
+    lib.comet_dca_workspace_bytes.argtypes = [_i64, _i32, _i32]
     lib.comet_dca_workspace_bytes.restype = ctypes.c_size_t
     lib.comet_dca_rss.argtypes = [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _i32,
                                   ctypes.POINTER(Config), _vp, _vp, ctypes.c_size_t, _vp]
@@ -73,6 +73,8 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_double), _vp]
     lib.comet_dca_autotune.restype = ctypes.c_int
+    lib.comet_profile_scan_points.argtypes = [ctypes.POINTER(ctypes.c_int64)]
+    lib.comet_profile_scan_points.restype = ctypes.c_int
     lib.comet_profile_begin.restype = ctypes.c_int
     lib.comet_profile_end.restype = ctypes.c_int
     lib.comet_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double),
@@ -152,13 +154,13 @@ def extrapolate_seeds(seeds: torch.Tensor, cfg: Config, track: torch.Tensor) -> 
         "comet_extrapolate_seeds")
 
 
-def dca_workspace_bytes(n_seeds: int, n_wires: int) -> int:
-    return int(load().comet_dca_workspace_bytes(int(n_seeds), int(n_wires)))
+def dca_workspace_bytes(n_seeds: int, n_points: int, n_wires: int) -> int:
+    return int(load().comet_dca_workspace_bytes(int(n_seeds), int(n_points), int(n_wires)))
 
 
-def dca_workspace(n_seeds: int, n_wires: int, device=None) -> torch.Tensor:
+def dca_workspace(n_seeds: int, n_points: int, n_wires: int, device=None) -> torch.Tensor:
     """A workspace tensor large enough for comet_dca_rss (256-byte aligned)."""
-    nbytes = max(dca_workspace_bytes(n_seeds, n_wires), 8)
+    nbytes = max(dca_workspace_bytes(n_seeds, n_points, n_wires), 8)
     return torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device or "cuda")
 
 
@@ -253,11 +255,17 @@ def profile_begin() -> None:
 
 
 def profile_end() -> dict:
-    """{kind: (total_ms, launches)} since profile_begin (waits for the events)."""
+    """{kind: (total_ms, launches)} since profile_begin (waits for the events), plus
+    "scan_points": the (seed, wire, point) distance evaluations the DCA scans made."""
+    lib = load()
     ms = (ctypes.c_double * 4)()
     n = (ctypes.c_int64 * 4)()
-    _check(load().comet_profile_end(ms, n), "comet_profile_end")
-    return {k: (ms[i], n[i]) for i, k in enumerate(PROFILE_KINDS)}
+    _check(lib.comet_profile_end(ms, n), "comet_profile_end")
+    out = {k: (ms[i], n[i]) for i, k in enumerate(PROFILE_KINDS)}
+    pts = ctypes.c_int64()
+    _check(lib.comet_profile_scan_points(ctypes.byref(pts)), "comet_profile_scan_points")
+    out["scan_points"] = pts.value
+    return out
 
 
 # ------------------------------------------------------------------ derivatives

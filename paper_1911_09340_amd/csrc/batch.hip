@@ -50,11 +50,12 @@ struct BatchArgs {
     int64_t max_tiles;        // tiles (partition-major) scanned, at most partitions x tiles
     double bz, charge, h, lambda;
     int K;
-    double *scratch;          // [blocks][NWV][3][P][64]
+    double *scratch;          // [blocks][NWV] x ([3][P][64] tracks, [P/16][64] chunk radii)
     int *counter;             // work queue
     int *done;                // [NP] tiles finished per partition
     double *rss;              // [NP][S]
     int64_t *best;            // [NP]
+    unsigned long long *evals;  // profiling: distance evaluations, or null
 };
 
 // WPE: waves per SIMD the register allocation must allow (2 blocks of 8 waves per CU
@@ -77,7 +78,9 @@ batch_scan_kernel(BatchArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int P = a.K + 1;
     const int64_t row = (int64_t)P * 64;                 // one coordinate of one tile
-    double *const block_scratch = a.scratch + (int64_t)blockIdx.x * NWV * 3 * row;
+    const int64_t rrow = (int64_t)radius_chunks(P) * 64;  // chunk radii of one tile
+    double *const block_scratch = a.scratch + (int64_t)blockIdx.x * NWV * (3 * row + rrow);
+    double *const block_rho = block_scratch + (int64_t)NWV * 3 * row;
 
     // Control flow around the barriers stays wave-uniform: counters are bumped by a
     // whole wave (lane 0 adds its count, the others 0) and results are broadcast with
@@ -108,7 +111,9 @@ batch_scan_kernel(BatchArgs a)
             const int n_valid = (int)min((int64_t)64, a.S - s0);
             double *sx = block_scratch + (int64_t)wave * 3 * row;
             double *sy = sx + row, *sz = sy + row;
+            double *rho = block_rho + (int64_t)wave * rrow + lane;
             if (lane < n_valid) {
+                ChunkRadius rad;
                 double st[6];
                 seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, s0 + lane,
                                st);
@@ -118,11 +123,13 @@ batch_scan_kernel(BatchArgs a)
                     sx[(int64_t)k * 64 + lane] = x;
                     sy[(int64_t)k * 64 + lane] = y;
                     sz[(int64_t)k * 64 + lane] = z;
+                    rad.add(k, P, x, y, z, rho, 64);
                     rk4_step(kc, x, y, z, px, py);
                 }
                 sx[(int64_t)a.K * 64 + lane] = x;
                 sy[(int64_t)a.K * 64 + lane] = y;
                 sz[(int64_t)a.K * 64 + lane] = z;
+                rad.add(a.K, P, x, y, z, rho, 64);
             }
         }
         __syncthreads();
@@ -149,7 +156,8 @@ batch_scan_kernel(BatchArgs a)
                     }
                 double d2[W];
                 Scan::run(sx, sy, sz, 64, P, n_valid, true, f, nw,
-                          a.offsets + (nw > 0 ? wbase : 0), a.drift, a.lambda, lds, d2);
+                          a.offsets + (nw > 0 ? wbase : 0), a.drift, a.lambda,
+                          block_rho + (int64_t)t * rrow, 64, a.evals, lds, d2);
 #pragma unroll
                 for (int w = 0; w < W; ++w)
                     dd[(wave * W + w) * 64 + lane] = d2[w];
@@ -602,10 +610,12 @@ int batch_blocks(int id)
     return nb;
 }
 
-// Track scratch of one persistent block: kMaxBatchNwv tiles of 64 seeds.
+// Scratch of one persistent block: the tracks and chunk radii of kMaxBatchNwv tiles of
+// 64 seeds.
 size_t batch_scratch_bytes(int K)
 {
-    return sizeof(double) * 3 * (size_t)(K + 1) * 64 * kMaxBatchNwv;
+    return sizeof(double) * (3 * (size_t)(K + 1) + (size_t)radius_chunks(K + 1)) * 64 *
+           kMaxBatchNwv;
 }
 
 int frames_pad(int n_w) { return ((n_w + 63) / 64) * 64 + kBatchWirePad; }
@@ -740,7 +750,7 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
     BatchArgs args{l.frames, wire_offsets, drift, event_wires, part_event, grids, n[0], n[1],
                    n[2], n[3], S, tiles, supers, items, max_tiles, cfg->bz_tesla,
                    cfg->charge_e, cfg->step_mm, cfg->lambda_mm, cfg->n_steps, l.scratch,
-                   l.counter, l.done, rss, best};
+                   l.counter, l.done, rss, best, scan_counter()};
     for (int it = 0; it <= n_refine && st == COMET_OK; ++it) {
         if (it) {
             hipLaunchKernelGGL(batch_refine_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0,

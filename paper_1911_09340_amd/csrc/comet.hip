@@ -94,6 +94,22 @@ __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restric
     tz[(int64_t)K * S] = z;
 }
 
+// Chunk radii of every seed's track (ChunkRadius): rho[n][s], one thread per seed.
+__global__ __launch_bounds__(256) void chunk_radius_kernel(const double *__restrict__ track,
+                                                           int64_t S, int P,
+                                                           double *__restrict__ rho)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S)
+        return;
+    const int64_t PS = (int64_t)P * S;
+    cdev::ChunkRadius acc;
+    for (int k = 0; k < P; ++k) {
+        const int64_t o = (int64_t)k * S + s;
+        acc.add(k, P, track[o], track[PS + o], track[2 * PS + o], rho + s, S);
+    }
+}
+
 // ------------------------------------------------------------------ wire frames
 // frames[w] for w < n_w; zero frames pad the array to n_pad entries.
 __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad,
@@ -125,7 +141,8 @@ template <int W, int NWV, int C, bool CHUNK_ARGMIN>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) void dca_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames,
     int n_w, const int32_t *__restrict__ offsets, const double *__restrict__ drift,
-    double lambda, double *__restrict__ dsq, int n_groups, int n_blocks, int xcd_remap)
+    double lambda, const double *__restrict__ rho, double *__restrict__ dsq, int n_groups,
+    int n_blocks, int xcd_remap, unsigned long long *counter)
 {
     using Scan = TileScan<W, NWV, C, CHUNK_ARGMIN>;
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];
@@ -156,7 +173,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) v
     const bool pairs = (S & 1) == 0 && ((uintptr_t)track & 15) == 0;
     double d2[W];
     Scan::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid, pairs, f, nw,
-              offsets + (nw > 0 ? wbase : 0), drift, lambda, lds, d2);
+              offsets + (nw > 0 ? wbase : 0), drift, lambda, rho + s0, S, counter, lds, d2);
     if (lane < n_valid)
 #pragma unroll
         for (int w = 0; w < W; ++w)
@@ -287,7 +304,8 @@ __global__ void fill_kernel(double *__restrict__ out, int64_t n, double v)
 struct DcaVariant {
     int w, nwv, c, chunk_argmin, xcd_remap;
     void (*kernel)(const double *, int64_t, int, const double *, int, const int32_t *,
-                   const double *, double, double *, int, int, int);
+                   const double *, double, const double *, double *, int, int, int,
+                   unsigned long long *);
 };
 
 const DcaVariant kDcaVariants[] = {
@@ -419,12 +437,13 @@ int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_c
     return launched("rk4_record_kernel");
 }
 
-size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_wires)
+size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_points, int32_t n_wires)
 {
-    if (n_seeds < 1 || n_wires < 0)
+    if (n_seeds < 1 || n_points < 1 || n_wires < 0)
         return 0;
     return align256(sizeof(double) * 8 * (size_t)wire_pad(n_wires)) +
-           align256(sizeof(double) * (size_t)n_wires * (size_t)n_seeds);
+           align256(sizeof(double) * (size_t)n_wires * (size_t)n_seeds) +
+           align256(sizeof(double) * (size_t)cdev::radius_chunks(n_points) * (size_t)n_seeds);
 }
 
 }  // extern "C"
@@ -453,7 +472,7 @@ int check_dca_args(const char *who, const double *track_xyz, int64_t n_seeds, in
     if ((int64_t)(n_seeds + 63) / 64 * (int64_t)((n_wires + 15) / 16) > (int64_t)1 << 30)
         return fail(COMET_EINVAL, "%s: problem too large for one launch", who);
     if (n_wires > 0) {
-        const size_t need = comet_dca_workspace_bytes(n_seeds, n_wires);
+        const size_t need = comet_dca_workspace_bytes(n_seeds, n_points, n_wires);
         if (!workspace || workspace_bytes < need)
             return fail(COMET_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, workspace_bytes,
                         need);
@@ -468,6 +487,20 @@ double *dca_frames(void *workspace) { return (double *)workspace; }
 double *dca_dsq(void *workspace, int n_wires)
 {
     return (double *)((char *)workspace + align256(sizeof(double) * 8 * (size_t)wire_pad(n_wires)));
+}
+
+double *dca_rho(void *workspace, int n_wires, int64_t n_seeds)
+{
+    return (double *)((char *)dca_dsq(workspace, n_wires) +
+                      align256(sizeof(double) * (size_t)n_wires * (size_t)n_seeds));
+}
+
+int launch_radius(const double *track_xyz, int64_t n_seeds, int32_t n_points, int n_wires,
+                  void *workspace, hipStream_t hs)
+{
+    hipLaunchKernelGGL(chunk_radius_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256),
+                       0, hs, track_xyz, n_seeds, n_points, dca_rho(workspace, n_wires, n_seeds));
+    return launched("chunk_radius_kernel");
 }
 
 int launch_frames(const double *wire_ends, int n_wires, void *workspace, hipStream_t hs)
@@ -489,8 +522,10 @@ int launch_dca(int id, const double *track_xyz, int64_t n_seeds, int32_t n_point
     const int64_t n_blocks = n_tiles * n_groups;
     hipLaunchKernelGGL(v.kernel, dim3((unsigned)n_blocks), dim3(64 * v.nwv), 0, hs, track_xyz,
                        n_seeds, n_points, (const double *)dca_frames(workspace), n_wires,
-                       wire_offsets, drift, lambda, dca_dsq(workspace, n_wires), n_groups,
-                       (int)n_blocks, v.xcd_remap);
+                       wire_offsets, drift, lambda,
+                       (const double *)dca_rho(workspace, n_wires, n_seeds),
+                       dca_dsq(workspace, n_wires), n_groups, (int)n_blocks, v.xcd_remap,
+                       scan_counter());
     return launched("dca_kernel");
 }
 
@@ -529,6 +564,9 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
     st = launch_frames(wire_ends, n_wires, workspace, hs);
     if (st)
         return st;
+    st = launch_radius(track_xyz, n_seeds, n_points, n_wires, workspace, hs);
+    if (st)
+        return st;
     {
         ProfScope prof(kProfDca, hs);
         st = launch_dca(choose_variant(n_seeds, n_points, n_wires), track_xyz, n_seeds, n_points,
@@ -563,6 +601,9 @@ int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_point
         return st;
     hipStream_t hs = (hipStream_t)stream;
     st = launch_frames(wire_ends, n_wires, workspace, hs);
+    if (st)
+        return st;
+    st = launch_radius(track_xyz, n_seeds, n_points, n_wires, workspace, hs);
     if (st)
         return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -19,6 +19,18 @@
 // from memory at the end with the same arithmetic, so equality finds the first
 // index). The closest point is then refined over its two chords and Eq. 1's capped
 // residual d = min(lambda, min_j |D - r_j|) is formed.
+//
+// Distance bound (exact; it only saves work). Every point of a chunk lies within rho
+// (the chunk radius, ChunkRadius in device_math.h) of the chunk's first point p0, so
+// its distance to a wire is at least dist(p0) - rho. (A) The first points of every
+// other chunk give each (lane, wire) an upper bound ub of its final minimum q. (B) A wave
+// needs a chunk unless, for every lane and every wire it owns, sqrt(q(p0)) exceeds
+// rho + sqrt(ub) (with margins far above the rounding of either side): then no point
+// of the chunk can reach or tie the final minimum. (C) Only the chunks some wave of
+// the block needs go through LDS, and each wave scans only the ones it needs. The
+// chunk holding the first minimum is always scanned, so the minimum, its first index
+// and every result are those of the full scan. Chunks are handled in segments of 256
+// (any track length).
 #ifndef COMET_DCA_SCAN_H
 #define COMET_DCA_SCAN_H
 
@@ -29,28 +41,92 @@ namespace cdev {
 template <int W, int NWV, int C, bool CHUNK_ARGMIN>
 struct TileScan {
     static constexpr int kChunkDoubles = 3 * C * 64;
-    static constexpr int kLdsDoubles = 2 * kChunkDoubles;
+    static constexpr int kSegChunks = 256;  // chunks per segment of the need pass
+    static constexpr int kSegWords = kSegChunks / 64;
+    // LDS: two chunk buffers, the need bits of every wave for one segment, then the
+    // segment's list of needed chunks, the per-wave counts and their total (ints).
+    static constexpr int kMaskOffset = 2 * kChunkDoubles;
+    static constexpr int kListOffset = kMaskOffset + NWV * kSegWords;
+    static constexpr int kLdsDoubles = kListOffset + (kSegChunks + NWV + 2) / 2 + 1;
+    static_assert(64 * NWV >= kSegChunks, "one thread per chunk of a segment");
 
     // Returns d^2 of (lane, wire w) in dsq[w] for lanes < n_valid and w < nw (0
     // elsewhere). nw (this wave's wire count, 0..W) must be wave-uniform; offsets
     // points at the CSR entry of the wave's first wire. Every thread of the block
     // must call this (it synchronises the block); lds holds kLdsDoubles doubles.
+    // rho: the tile's chunk radii, window n of lane l at rho[n * ldr + l] (lanes <
+    // n_valid are read). counter (may be null): receives the (seed, wire, point)
+    // distance evaluations performed.
     __device__ static void run(const double *__restrict__ bx, const double *__restrict__ by,
                                const double *__restrict__ bz, int64_t ld, int P, int n_valid,
                                bool pairs, const double (&f)[W][8], int nw,
                                const int32_t *__restrict__ offsets,
                                const double *__restrict__ drift, double lambda,
-                               double *__restrict__ lds, double (&dsq)[W])
+                               const double *__restrict__ rho, int64_t ldr,
+                               unsigned long long *counter, double *__restrict__ lds,
+                               double (&dsq)[W])
     {
+        static_assert(C % kRadiusChunk == 0 && C / kRadiusChunk <= 2, "chunk of 16 or 32");
         const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const bool active = nw > 0;
+        const bool seed = lane < n_valid;
+        uint64_t *const wmask = reinterpret_cast<uint64_t *>(lds + kMaskOffset);
+        int *const list = reinterpret_cast<int *>(lds + kListOffset);
+        int *const wtot = list + kSegChunks;
+        const int nch = (P + C - 1) / C;
         double best[W], cmin[W];
+        float ub[W];  // rounded to nearest: the test's margins cover it
         int kbest[W];
+        int64_t evals = 0;  // wave-uniform: distance evaluations per seed lane
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             best[w] = INFINITY;
             kbest[w] = 0;
+            ub[w] = INFINITY;
         }
+        // points k0 + i * stride (i < 4, those below P) of this lane; 0 elsewhere
+        constexpr int kGather = 2;
+        auto gather = [&](int k0, int stride, double (&x)[kGather], double (&y)[kGather],
+                          double (&z)[kGather]) {
+#pragma unroll
+            for (int i = 0; i < kGather; ++i) {
+                const int k = k0 + i * stride;
+                x[i] = y[i] = z[i] = 0.0;
+                if (seed && k < P) {
+                    const int64_t o = (int64_t)k * ld + lane;
+                    x[i] = bx[o];
+                    y[i] = by[o];
+                    z[i] = bz[o];
+                }
+            }
+        };
+        // (A) upper bounds of the final minima: every other chunk's first point
+        if (active) {
+            int n_s = 0;
+            for (int k0 = 0; k0 < P; k0 += kGather * 2 * C) {
+                double x[kGather], y[kGather], z[kGather];
+                gather(k0, 2 * C, x, y, z);
+#pragma unroll
+                for (int i = 0; i < kGather; ++i) {
+                    if (k0 + i * 2 * C < P) {
+                        ++n_s;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            double xi, eta;
+                            project(f[w], x[i], y[i], z[i], xi, eta);
+                            ub[w] = fminf(ub[w], (float)fma(xi, xi, eta * eta));
+                        }
+                    }
+                }
+            }
+            evals += (int64_t)nw * n_s;
+        }
+        // sqrt(ub) rounded up (FP32 sqrt is within 1 ulp; the factor covers it)
+        float sub[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
 
         // Each thread owns PER_T slots of two consecutive lanes (16 bytes).
         constexpr int T = 64 * NWV;
@@ -123,47 +199,136 @@ struct TileScan {
             }
         };
 
-        // prologue: chunk 0 into buffer 0, chunk 1 in flight
-        fetch(0);
-        __syncthreads();  // the previous caller's reads of lds are done
-        stash(lds);
-        if (C < P)
-            fetch(C);
-        __syncthreads();
-
-        for (int k0 = 0, n = 0; k0 < P; k0 += C, ++n) {
-            const double *cur = lds + (n & 1) * kChunkDoubles;
-            if (active) {
-                const int kn = min(C, P - k0);
-                if (kn == C) {
+        for (int s0 = 0; s0 < nch; s0 += kSegChunks) {
+            const int sn = min(kSegChunks, nch - s0);
+            // (B) this wave's need bit of every chunk of the segment: some lane and wire
+            // whose bound does not rule the chunk out (the partial last chunk always)
+#pragma unroll 1
+            for (int word = 0; word < kSegWords; ++word) {
+                uint64_t m = 0;
+                if (active) {
+#pragma unroll 1
+                    for (int b0 = 0; b0 < 64 && word * 64 + b0 < sn; b0 += kGather) {
+                        const int kb = (s0 + word * 64 + b0) * C;
+                        double x[kGather], y[kGather], z[kGather], r[kGather];
+                        gather(kb, C, x, y, z);
 #pragma unroll
-                    for (int kk = 0; kk < C; ++kk)
-                        point(cur, kk, k0 + kk, kk == 0);
-                } else {
-                    point(cur, 0, k0, true);
-                    for (int kk = 1; kk < kn; ++kk)
-                        point(cur, kk, k0 + kk, false);
-                }
-                if (CHUNK_ARGMIN) {
+                        for (int i = 0; i < kGather; ++i) {
+                            const int k0 = kb + i * C;
+                            r[i] = 0.0;
+                            if (seed && k0 + C <= P) {
+                                const int nr = k0 / kRadiusChunk;
+                                r[i] = rho[(int64_t)nr * ldr + lane];
+                                if (C == 2 * kRadiusChunk)
+                                    r[i] = r[i] + rho[(int64_t)(nr + 1) * ldr + lane];
+                            }
+                        }
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        if (cmin[w] < best[w]) {
-                            best[w] = cmin[w];
-                            kbest[w] = k0;
+                        for (int i = 0; i < kGather; ++i) {
+                            const int b = b0 + i;
+                            const int k0 = kb + i * C;
+                            if (b >= 64 || word * 64 + b >= sn)
+                                break;
+                            bool need = true;
+                            if (k0 + C <= P) {
+                                evals += nw;
+                                const float rf = (float)r[i] * 1.000001f;
+                                bool lane_need = false;
+#pragma unroll
+                                for (int w = 0; w < W; ++w) {
+                                    if (w < nw) {
+                                        double xi, eta;
+                                        project(f[w], x[i], y[i], z[i], xi, eta);
+                                        const float q0 = (float)fma(xi, xi, eta * eta);
+                                        const float B = fmaf(rf + sub[w], 1.000001f, 1e-6f);
+                                        lane_need = lane_need ||
+                                                    !(q0 * 0.999999f > (B * B) * 1.000001f);
+                                    }
+                                }
+                                need = __builtin_amdgcn_ballot_w64(lane_need && seed) != 0;
+                            }
+                            if (need)
+                                m |= 1ull << b;
                         }
                     }
                 }
-            }
-            if (k0 + C < P) {
-                // chunk n + 1 goes to the other buffer, whose chunk n - 1 every wave
-                // finished before the previous barrier
-                stash(lds + ((n + 1) & 1) * kChunkDoubles);
-                if (k0 + 2 * C < P)
-                    fetch(k0 + 2 * C);
+                if (lane == 0)
+                    wmask[wave * kSegWords + word] = m;
             }
             __syncthreads();
+            // the segment's needed chunks in order (any wave's bit), one thread per chunk
+            const int t = threadIdx.x;
+            bool flag = false;
+            if (t < sn)
+                for (int v = 0; v < NWV; ++v)
+                    flag = flag || ((wmask[v * kSegWords + (t >> 6)] >> (t & 63)) & 1);
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(flag);
+            const int below = __builtin_popcountll(bal & ((1ull << lane) - 1));
+            if (lane == 0)
+                wtot[wave] = __builtin_popcountll(bal);
+            __syncthreads();
+            int base = 0, total = 0;
+            for (int v = 0; v < NWV; ++v) {
+                const int c = wtot[v];
+                base += v < wave ? c : 0;
+                total += c;
+            }
+            total = __builtin_amdgcn_readfirstlane(total);
+            if (flag)
+                list[base + below] = t;
+            __syncthreads();
+            if (total == 0)
+                continue;
+
+            // (C) the needed chunks through LDS: chunk j scanned from one buffer while
+            // chunk j + 1 is stored into the other and chunk j + 2 is loaded
+            fetch((s0 + list[0]) * C);
+            stash(lds);
+            if (total > 1)
+                fetch((s0 + list[1]) * C);
+            __syncthreads();
+            for (int j = 0; j < total; ++j) {
+                const int n = __builtin_amdgcn_readfirstlane(list[j]);
+                const int k0 = (s0 + n) * C;
+                const double *cur = lds + (j & 1) * kChunkDoubles;
+                const bool mine =
+                    __builtin_amdgcn_readfirstlane(
+                        (int)((wmask[wave * kSegWords + (n >> 6)] >> (n & 63)) & 1)) != 0;
+                if (active && mine) {
+                    const int kn = min(C, P - k0);
+                    evals += (int64_t)nw * kn;
+                    if (kn == C) {
+#pragma unroll
+                        for (int kk = 0; kk < C; ++kk)
+                            point(cur, kk, k0 + kk, kk == 0);
+                    } else {
+                        point(cur, 0, k0, true);
+                        for (int kk = 1; kk < kn; ++kk)
+                            point(cur, kk, k0 + kk, false);
+                    }
+                    if (CHUNK_ARGMIN) {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            if (cmin[w] < best[w]) {
+                                best[w] = cmin[w];
+                                kbest[w] = k0;
+                            }
+                        }
+                    }
+                }
+                if (j + 1 < total) {
+                    // chunk j + 1 goes to the other buffer, whose chunk j - 1 every wave
+                    // finished before the previous barrier
+                    stash(lds + ((j + 1) & 1) * kChunkDoubles);
+                    if (j + 2 < total)
+                        fetch((s0 + list[j + 2]) * C);
+                }
+                __syncthreads();
+            }
         }
 
+        if (counter && lane == 0 && evals > 0)
+            atomicAdd(counter, (unsigned long long)(evals * n_valid));
 #pragma unroll
         for (int w = 0; w < W; ++w)
             dsq[w] = 0.0;

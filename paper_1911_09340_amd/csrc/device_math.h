@@ -314,6 +314,39 @@ __device__ __forceinline__ double refine_dca2(const double *__restrict__ track, 
     return refine_dca2(track + s, track + PS + s, track + 2 * PS + s, S, P, f, k, qk);
 }
 
+// Chunk radii of a recorded track, for the distance bound of the DCA scan. Window n
+// holds points 16 n ... min(16 n + 16, P - 1) (consecutive windows share their end
+// point) and rho[n] = max |p_k - p_(16 n)| over it, so that a 32-point chunk starting
+// at 16 n lies within rho[n] + rho[n + 1] of its first point. Feed every point in
+// order; NaN distances are ignored (a NaN first point makes the bound unused: its q
+// is NaN and the scan never skips such a chunk).
+constexpr int kRadiusChunk = 16;
+
+struct ChunkRadius {
+    double x0 = 0.0, y0 = 0.0, z0 = 0.0, r2 = 0.0;
+    __device__ __forceinline__ void add(int k, int P, double x, double y, double z,
+                                        double *__restrict__ rho, int64_t ld)
+    {
+        if (k > 0) {
+            const double dx = x - x0, dy = y - y0, dz = z - z0;
+            const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            r2 = d2 > r2 ? d2 : r2;
+        }
+        if (k % kRadiusChunk == 0) {
+            if (k > 0)
+                rho[(int64_t)(k / kRadiusChunk - 1) * ld] = sqrt(r2);
+            x0 = x;
+            y0 = y;
+            z0 = z;
+            r2 = 0.0;
+        }
+        if (k == P - 1)
+            rho[(int64_t)(k / kRadiusChunk) * ld] = sqrt(r2);
+    }
+};
+
+__host__ __device__ constexpr int radius_chunks(int P) { return (P - 1) / kRadiusChunk + 1; }
+
 // Eq. 1 for one wire: d = min(lambda, min_j |D - r_j|).
 __device__ __forceinline__ double capped_residual(double D, const double *__restrict__ drift,
                                                   int j0, int j1, double lambda)

@@ -28,6 +28,10 @@ size_t align256(size_t v);
 // Kernel kinds for comet_profile_end().
 enum { kProfTrack = 0, kProfDca = 1, kProfSum = 2, kProfSelect = 3 };
 
+// While profiling is on: a device counter (current device) that the DCA scans add
+// their (seed, wire, point) distance evaluations to; nullptr otherwise.
+unsigned long long *scan_counter();
+
 // Brackets the launches made during its lifetime with two HIP events on `stream`
 // when profiling is on (comet_profile_begin); does nothing otherwise.
 class ProfScope {

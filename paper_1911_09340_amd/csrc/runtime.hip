@@ -27,6 +27,9 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof_records;
 std::vector<hipEvent_t> g_prof_pool;
+unsigned long long *g_scan_counter[64] = {};  // per device, allocated on first use
+int g_scan_dev = -1;                          // device of the running count
+long long g_scan_points = 0;                  // the last finished count
 
 // An event from the pool, or a new one (caller holds g_prof_mu).
 hipEvent_t prof_event()
@@ -91,6 +94,15 @@ int launched(const char *what)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+unsigned long long *scan_counter()
+{
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    int dev = -1;
+    if (!g_prof_on || hipGetDevice(&dev) != hipSuccess || dev != g_scan_dev)
+        return nullptr;
+    return g_scan_counter[dev];
+}
+
 int check_config(const comet_config *cfg)
 {
     if (!cfg)
@@ -145,6 +157,17 @@ int comet_profile_begin(void)
         g_prof_pool.push_back(r.stop);
     }
     g_prof_records.clear();
+    g_scan_dev = -1;
+    g_scan_points = 0;
+    int dev = -1;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        if (!g_scan_counter[dev] &&
+            hipMalloc((void **)&g_scan_counter[dev], sizeof(unsigned long long)) != hipSuccess)
+            g_scan_counter[dev] = nullptr;
+        if (g_scan_counter[dev] &&
+            hipMemset(g_scan_counter[dev], 0, sizeof(unsigned long long)) == hipSuccess)
+            g_scan_dev = dev;
+    }
     g_prof_on = true;
     return COMET_OK;
 }
@@ -178,7 +201,29 @@ int comet_profile_end(double ms[COMET_PROFILE_KINDS], int64_t launches[COMET_PRO
         g_prof_pool.push_back(r.stop);
     }
     g_prof_records.clear();
+    if (g_scan_dev >= 0) {
+        unsigned long long n = 0;
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(g_scan_dev);
+        hipError_t e = hipMemcpy(&n, g_scan_counter[g_scan_dev], sizeof(n), hipMemcpyDeviceToHost);
+        (void)hipSetDevice(cur);
+        if (e != hipSuccess && status == COMET_OK)
+            status = fail(COMET_EHIP, "comet_profile_end: %s", hipGetErrorString(e));
+        g_scan_points = (long long)n;
+        g_scan_dev = -1;
+    }
     return status;
+}
+
+int comet_profile_scan_points(int64_t *points)
+{
+    using namespace chost;
+    if (!points)
+        return fail(COMET_EINVAL, "comet_profile_scan_points: NULL pointer");
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    *points = g_scan_points;
+    return COMET_OK;
 }
 
 }  // extern "C"

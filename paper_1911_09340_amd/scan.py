@@ -53,7 +53,7 @@ class PartitionScanner:
         self.track = torch.empty(3, self.P, self.S, **f64)
         self.rss = torch.empty(self.S, **f64)
         self.best = torch.empty(1, dtype=torch.int64, device=device)
-        self.workspace = comet.dca_workspace(self.S, n_wires, device)
+        self.workspace = comet.dca_workspace(self.S, self.P, n_wires, device)
         self.mask = torch.empty(n_hits, dtype=torch.uint8, device=device)
         self.n_border = torch.empty(1, dtype=torch.int32, device=device)
         self.dca_best = torch.empty(n_wires, **f64)

@@ -56,12 +56,15 @@ def _n4(*n):
 
 
 def test_workspace_bytes(lib):
-    assert lib.comet_dca_workspace_bytes(0, 10) == 0
-    assert lib.comet_dca_workspace_bytes(10, -1) == 0
-    a = lib.comet_dca_workspace_bytes(64, 10)
-    b = lib.comet_dca_workspace_bytes(128, 10)
-    assert a % 256 == 0 and b > a
-    assert a >= 8 * 64 * 10 + 8 * 8 * 10
+    assert lib.comet_dca_workspace_bytes(0, 11, 10) == 0
+    assert lib.comet_dca_workspace_bytes(10, 11, -1) == 0
+    assert lib.comet_dca_workspace_bytes(10, 0, 10) == 0
+    a = lib.comet_dca_workspace_bytes(64, 11, 10)
+    b = lib.comet_dca_workspace_bytes(128, 11, 10)
+    c = lib.comet_dca_workspace_bytes(64, 1001, 10)
+    assert a % 256 == 0 and b > a and c > a
+    # frames, d^2 per (wire, seed), one chunk radius per 16 points and seed
+    assert c >= 8 * 64 * 10 + 8 * 8 * 10 + 8 * 64 * 63
 
 
 @pytest.mark.parametrize("case", ["null_grid", "bad_n", "count_mismatch"])

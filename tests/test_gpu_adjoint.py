@@ -152,7 +152,7 @@ def test_autograd_function(ev_plain):
     comet.extrapolate_seeds(seeds, cfg, track)
     ref = torch.empty(5, dtype=torch.float64, device="cuda")
     comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, ref,
-                  comet.dca_workspace(5, dev.n_wires))
+                  comet.dca_workspace(5, sc.n_steps + 1, dev.n_wires))
     assert torch.equal(rss.detach(), ref)
     want = got["grad"] * np.arange(1.0, 6.0)[:, None]
     assert np.array_equal(x.grad.cpu().numpy(), want.T)

@@ -187,7 +187,7 @@ def test_select_classify_top_k(orc, ev_plain):
     dev = scan.DeviceEvent.from_event(ev_plain)
     rss = torch.empty(sc.n_seeds, dtype=torch.float64, device="cuda")
     comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss,
-                  comet.dca_workspace(sc.n_seeds, dev.n_wires))
+                  comet.dca_workspace(sc.n_seeds, sc.n_steps + 1, dev.n_wires))
     best = torch.empty(64, dtype=torch.int64, device="cuda")
     mask = torch.empty(ev_plain.n_hits, dtype=torch.uint8, device="cuda")
     comet.select_classify(rss, best, cfg, track, dev.wire_ends, dev.wire_offsets, dev.drift,

@@ -44,7 +44,7 @@ def gpu_rss(ev, seeds, cfg):
     dev = scan.DeviceEvent.from_event(ev)
     rss = torch.empty(S, dtype=torch.float64, device="cuda")
     comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss,
-                  comet.dca_workspace(S, dev.n_wires))
+                  comet.dca_workspace(S, cfg.n_steps + 1, dev.n_wires))
     return rss, track, dev
 
 
@@ -312,7 +312,7 @@ def test_autotune_picks_a_shape_and_keeps_results(orc, ev_plain):
     cfg = scan.config_for(ev_plain, sc)
     seeds = gpu_seeds(g, n)
     rss, track, dev = gpu_rss(ev_plain, seeds, cfg)
-    ws = comet.dca_workspace(seeds.shape[1], dev.n_wires)
+    ws = comet.dca_workspace(seeds.shape[1], cfg.n_steps + 1, dev.n_wires)
     rss2 = torch.empty_like(rss)
     best, ms = comet.dca_autotune(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss2, ws,
                                   reps=1)
@@ -323,3 +323,79 @@ def test_autotune_picks_a_shape_and_keeps_results(orc, ev_plain):
     rss3 = torch.empty_like(rss)
     comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss3, ws)
     assert torch.equal(rss, rss3)
+
+
+def _odd_tracks(ev, kind, S, P, seed):
+    """Polylines that no integrator would make: random walks with long jumps, and
+    small orbits around a wire that repeat every 16 points (exact ties between chunks,
+    where the first index must win)."""
+    rng = np.random.default_rng(seed)
+    mid = 0.5 * (ev.wire_ends[:, :3] + ev.wire_ends[:, 3:])
+    tr = np.empty((3, P, S))
+    for s in range(S):
+        c = mid[rng.integers(0, mid.shape[0])]
+        if kind == "walk":
+            steps = rng.normal(0.0, 3.0, (P, 3))
+            jump = rng.random(P) < 0.02
+            steps[jump] += rng.normal(0.0, 300.0, (int(jump.sum()), 3))
+            steps[0] = c + rng.normal(0.0, 20.0, 3)
+            tr[:, :, s] = np.cumsum(steps, axis=0).T
+        else:
+            r = rng.uniform(2.0, 15.0)
+            ph = 2.0 * np.pi * (np.arange(P) % 16) / 16.0 + rng.uniform(0, 2 * np.pi)
+            tr[0, :, s] = c[0] + r * np.cos(ph)
+            tr[1, :, s] = c[1] + r * np.sin(ph)
+            tr[2, :, s] = c[2] + 40.0 * ((np.arange(P) // 16) % 3)   # three z levels, revisited
+    return tr
+
+
+@pytest.mark.parametrize("kind", ["walk", "orbit"])
+def test_rss_arbitrary_tracks_every_variant(orc, ev_signal, kind):
+    """The distance bound that lets the scan skip chunks must never change a result,
+    whatever the track: every DCA shape vs the CPU reference on odd polylines (2 full
+    tiles and a ragged one, 401 points)."""
+    ev = ev_signal
+    S, P = 145, 401
+    tr = _odd_tracks(ev, kind, S, P, 17 if kind == "walk" else 23)
+    lam = 1.0e4   # no cap: every wire's D enters the RSS
+    cfg = comet.make_config(ev.bz, ev.charge, 2.0, P - 1, lam)
+    want = np.array([orc.rss_track(np.ascontiguousarray(tr[:, :, s].T), ev.wire_ends,
+                                   ev.wire_offsets, ev.drift, lam) for s in range(S)])
+    dev = scan.DeviceEvent.from_event(ev)
+    track = torch.as_tensor(np.ascontiguousarray(tr), device="cuda")
+    rss = torch.empty(S, dtype=torch.float64, device="cuda")
+    ws = comet.dca_workspace(S, P, dev.n_wires)
+    try:
+        for v in range(len(comet.dca_variants())):
+            comet.set_dca_variant(v)
+            rss.fill_(-1.0)
+            comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss, ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(rss.cpu().numpy(), want), (kind, v)
+    finally:
+        comet.set_dca_variant(-1)
+
+
+def test_profile_counts_the_distance_evaluations(ev_signal):
+    """While profiling, the scans count their (seed, wire, point) evaluations: at least
+    one point per chunk and wire, at most the full scan plus its sample pass; a seed far
+    from every wire lets the bound skip almost everything."""
+    ev = ev_signal
+    S, P = 200, 801
+    cfg = comet.make_config(ev.bz, ev.charge, 2.0, P - 1, 0.8)
+    dev = scan.DeviceEvent.from_event(ev)
+    ws = comet.dca_workspace(S, P, dev.n_wires)
+    rss = torch.empty(S, dtype=torch.float64, device="cuda")
+    for far in (False, True):
+        seeds = np.tile(ev.ref_states[0][:, None], (1, S))
+        if far:
+            seeds[0] += 5.0e4        # 50 m off in x: every wire line far from every point
+        track = torch.empty(3, P, S, dtype=torch.float64, device="cuda")
+        comet.extrapolate_seeds(torch.as_tensor(seeds, device="cuda"), cfg, track)
+        comet.profile_begin()
+        comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss, ws)
+        prof = comet.profile_end()
+        full = S * dev.n_wires * P
+        assert S * dev.n_wires * (P // 32) <= prof["scan_points"] <= 2 * full, far
+        if far:
+            assert prof["scan_points"] < 0.3 * full
