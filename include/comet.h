@@ -325,10 +325,12 @@ int comet_merge_halves(const double *rss_a, const int32_t *veto_a, const double 
                        int32_t *pair, double *pair_rss, int32_t *n_complete, void *stream);
 
 /* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
- * per LDS chunk, the persistent block count on the current device); every shape
- * gives the same results. comet_batch_set_variant selects the shape (default 0). */
+ * per LDS chunk, the persistent block count on the current device, and direct as for
+ * the DCA shapes; blocks and direct may be NULL); every shape gives the same results.
+ * comet_batch_set_variant selects the shape (default 0). */
 int comet_batch_variant_count(void);
-int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks);
+int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks,
+                             int32_t *direct);
 int comet_batch_set_variant(int id);
 
 /* ------------------------------------------------------------ diagnostics
@@ -351,9 +353,11 @@ int comet_profile_scan_points(int64_t *points);
 /* ------------------------------------------------------------ tuning
  * The DCA kernel exists in several shapes: W wires per wave, NWV waves per block,
  * C track points per LDS chunk, whether the first closest index is tracked per point
- * (chunk_argmin = 0) or per chunk with a final rescan (1), and whether blocks are
- * remapped so that one seed tile's wire groups share an XCD. Every shape gives the
- * same results bit for bit; only speed differs.
+ * (chunk_argmin = 0) or per chunk with a final rescan (1), whether blocks are
+ * remapped so that one seed tile's wire groups share an XCD, and whether the block's
+ * waves share the needed chunks through LDS (direct = 0) or each wave loads the
+ * chunks it needs itself, with no LDS and no barrier (direct = 1). Every shape gives
+ * the same results bit for bit; only speed differs.
  *
  * comet_dca_autotune() takes the arguments of comet_dca_rss (same checks, same
  * result in rss) plus: reps (1..1000) timed launches per shape, best_id (host, may be
@@ -369,7 +373,7 @@ int comet_profile_scan_points(int64_t *points);
  * comet_dca_variant_info() describes shape id (0 <= id < comet_dca_variant_count()). */
 int comet_dca_variant_count(void);
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
-                           int32_t *chunk_argmin, int32_t *xcd_remap);
+                           int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct);
 int comet_dca_set_variant(int id);
 int comet_dca_variant_for(int64_t n_seeds, int32_t n_points, int32_t n_wires);
 int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_points,

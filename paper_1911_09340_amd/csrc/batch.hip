@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "comet.h"
 #include "dca_scan.h"
@@ -62,11 +63,11 @@ struct BatchArgs {
 // need 4). A work item is a super-tile of up to NWV consecutive 64-seed tiles of one
 // partition: every wave records one tile's tracks (RK4 runs on all waves at once),
 // then the block scans the tiles one after the other against the event's wires.
-template <int W, int NWV, int C, int WPE>
+template <int W, int NWV, int C, int WPE, bool DIRECT>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_scan_kernel(BatchArgs a)
 {
-    using Scan = TileScan<W, NWV, C, true>;
+    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, true>, TileScan<W, NWV, C, true>>;
     constexpr int G = W * NWV;  // wires per group
     static_assert(NWV <= kMaxBatchNwv && G <= kBatchWirePad, "shape exceeds the workspace");
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];
@@ -570,17 +571,21 @@ __global__ void copy_kernel(const double *__restrict__ src, double *__restrict__
 
 // ------------------------------------------------------------------ shapes
 struct BatchVariant {
-    int w, nwv, c;
+    int w, nwv, c, direct;
     void (*kernel)(BatchArgs);
 };
 
 const BatchVariant kBatchVariants[] = {
-    {4, 8, 16, batch_scan_kernel<4, 8, 16, 4>},
-    {3, 8, 16, batch_scan_kernel<3, 8, 16, 4>},
-    {2, 8, 16, batch_scan_kernel<2, 8, 16, 4>},
-    {4, 8, 16, batch_scan_kernel<4, 8, 16, 1>},
-    {5, 8, 16, batch_scan_kernel<5, 8, 16, 1>},
-    {6, 8, 16, batch_scan_kernel<6, 8, 16, 1>},
+    {4, 8, 16, 0, batch_scan_kernel<4, 8, 16, 4, false>},
+    {3, 8, 16, 0, batch_scan_kernel<3, 8, 16, 4, false>},
+    {2, 8, 16, 0, batch_scan_kernel<2, 8, 16, 4, false>},
+    {4, 8, 16, 0, batch_scan_kernel<4, 8, 16, 1, false>},
+    {5, 8, 16, 0, batch_scan_kernel<5, 8, 16, 1, false>},
+    {6, 8, 16, 0, batch_scan_kernel<6, 8, 16, 1, false>},
+    // every wave on its own (no LDS staging)
+    {4, 8, 16, 1, batch_scan_kernel<4, 8, 16, 4, true>},
+    {3, 8, 16, 1, batch_scan_kernel<3, 8, 16, 4, true>},
+    {2, 8, 16, 1, batch_scan_kernel<2, 8, 16, 4, true>},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 
@@ -882,7 +887,8 @@ int comet_grid_seeds(const double *grids, int32_t n_partitions, const int32_t n[
 
 int comet_batch_variant_count(void) { return kNumBatchVariants; }
 
-int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks)
+int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks,
+                             int32_t *direct)
 {
     if (id < 0 || id >= kNumBatchVariants || !w || !nwv || !chunk)
         return fail(COMET_EINVAL, "comet_batch_variant_info: bad id or NULL pointer");
@@ -891,6 +897,8 @@ int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, i
     *chunk = kBatchVariants[id].c;
     if (blocks)
         *blocks = batch_blocks(id);
+    if (direct)
+        *direct = kBatchVariants[id].direct;
     return COMET_OK;
 }
 

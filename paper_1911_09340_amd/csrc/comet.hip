@@ -29,6 +29,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "comet.h"
@@ -137,14 +138,15 @@ __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad
 // Registers are capped for 4 waves per SIMD (two 8-wave blocks or one 16-wave block
 // per CU); the frames live in scalar registers, so only the running minima, the
 // staged point and the prefetch buffer occupy vector registers.
-template <int W, int NWV, int C, bool CHUNK_ARGMIN>
+template <int W, int NWV, int C, bool CHUNK_ARGMIN, bool DIRECT>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) void dca_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames,
     int n_w, const int32_t *__restrict__ offsets, const double *__restrict__ drift,
     double lambda, const double *__restrict__ rho, double *__restrict__ dsq, int n_groups,
     int n_blocks, int xcd_remap, unsigned long long *counter)
 {
-    using Scan = TileScan<W, NWV, C, CHUNK_ARGMIN>;
+    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN>,
+                                    TileScan<W, NWV, C, CHUNK_ARGMIN>>;
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];
 
     const int b = blockIdx.x;
@@ -302,25 +304,32 @@ __global__ void fill_kernel(double *__restrict__ out, int64_t n, double v)
 
 // ------------------------------------------------------------------ DCA variants
 struct DcaVariant {
-    int w, nwv, c, chunk_argmin, xcd_remap;
+    int w, nwv, c, chunk_argmin, xcd_remap, direct;
     void (*kernel)(const double *, int64_t, int, const double *, int, const int32_t *,
                    const double *, double, const double *, double *, int, int, int,
                    unsigned long long *);
 };
 
 const DcaVariant kDcaVariants[] = {
-    {6, 8, 16, 1, 1, dca_kernel<6, 8, 16, true>},
-    {6, 8, 16, 1, 0, dca_kernel<6, 8, 16, true>},
-    {6, 16, 16, 1, 1, dca_kernel<6, 16, 16, true>},
-    {5, 16, 16, 1, 1, dca_kernel<5, 16, 16, true>},
-    {4, 16, 16, 1, 1, dca_kernel<4, 16, 16, true>},
-    {4, 8, 32, 0, 1, dca_kernel<4, 8, 32, false>},
-    {4, 8, 32, 1, 1, dca_kernel<4, 8, 32, true>},
-    {4, 8, 16, 1, 1, dca_kernel<4, 8, 16, true>},
-    {5, 8, 16, 1, 1, dca_kernel<5, 8, 16, true>},
-    {3, 8, 32, 1, 1, dca_kernel<3, 8, 32, true>},
-    {4, 16, 32, 1, 1, dca_kernel<4, 16, 32, true>},
-    {3, 16, 32, 1, 1, dca_kernel<3, 16, 32, true>},
+    {6, 8, 16, 1, 1, 0, dca_kernel<6, 8, 16, true, false>},
+    {6, 8, 16, 1, 0, 0, dca_kernel<6, 8, 16, true, false>},
+    {6, 16, 16, 1, 1, 0, dca_kernel<6, 16, 16, true, false>},
+    {5, 16, 16, 1, 1, 0, dca_kernel<5, 16, 16, true, false>},
+    {4, 16, 16, 1, 1, 0, dca_kernel<4, 16, 16, true, false>},
+    {4, 8, 32, 0, 1, 0, dca_kernel<4, 8, 32, false, false>},
+    {4, 8, 32, 1, 1, 0, dca_kernel<4, 8, 32, true, false>},
+    {4, 8, 16, 1, 1, 0, dca_kernel<4, 8, 16, true, false>},
+    {5, 8, 16, 1, 1, 0, dca_kernel<5, 8, 16, true, false>},
+    {3, 8, 32, 1, 1, 0, dca_kernel<3, 8, 32, true, false>},
+    {4, 16, 32, 1, 1, 0, dca_kernel<4, 16, 32, true, false>},
+    {3, 16, 32, 1, 1, 0, dca_kernel<3, 16, 32, true, false>},
+    // every wave on its own (no LDS staging)
+    {4, 8, 16, 1, 1, 1, dca_kernel<4, 8, 16, true, true>},
+    {3, 8, 16, 1, 1, 1, dca_kernel<3, 8, 16, true, true>},
+    {2, 8, 16, 1, 1, 1, dca_kernel<2, 8, 16, true, true>},
+    {4, 4, 16, 1, 1, 1, dca_kernel<4, 4, 16, true, true>},
+    {3, 4, 16, 1, 1, 1, dca_kernel<3, 4, 16, true, true>},
+    {4, 8, 32, 1, 1, 1, dca_kernel<4, 8, 32, true, true>},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
 constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above
@@ -725,7 +734,7 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
 int comet_dca_variant_count(void) { return kNumDcaVariants; }
 
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
-                           int32_t *chunk_argmin, int32_t *xcd_remap)
+                           int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct)
 {
     if (id < 0 || id >= kNumDcaVariants || !w || !nwv || !chunk || !chunk_argmin || !xcd_remap)
         return fail(COMET_EINVAL, "comet_dca_variant_info: bad id or NULL pointer");
@@ -734,6 +743,8 @@ int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
     *chunk = kDcaVariants[id].c;
     *chunk_argmin = kDcaVariants[id].chunk_argmin;
     *xcd_remap = kDcaVariants[id].xcd_remap;
+    if (direct)
+        *direct = kDcaVariants[id].direct;
     return COMET_OK;
 }
 

@@ -38,6 +38,55 @@
 
 namespace cdev {
 
+// The end of a tile scan (both forms below): the evaluation count, then per (lane,
+// wire) the first index of the minimum (per chunk: rescan the chunk that holds it),
+// its chord refinement, D and Eq. 1's capped residual.
+template <int W, int C, bool CHUNK_ARGMIN>
+__device__ __forceinline__ void scan_finish(const double *__restrict__ bx,
+                                            const double *__restrict__ by,
+                                            const double *__restrict__ bz, int64_t ld, int P,
+                                            int n_valid, const double (&f)[W][8], int nw,
+                                            const int32_t *__restrict__ offsets,
+                                            const double *__restrict__ drift, double lambda,
+                                            unsigned long long *counter, int64_t evals,
+                                            const double (&best)[W], const int (&kbest)[W],
+                                            double (&dsq)[W])
+{
+    const int lane = threadIdx.x & 63;
+    if (counter && lane == 0 && evals > 0)
+        atomicAdd(counter, (unsigned long long)(evals * n_valid));
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        dsq[w] = 0.0;
+    if (nw <= 0 || lane >= n_valid)
+        return;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        if (w < nw) {
+            int k = kbest[w];
+            if (CHUNK_ARGMIN) {
+                const int kend = min(k + C, P);
+                int kf = k;
+                for (int j = k; j < kend; ++j) {
+                    const int64_t o = (int64_t)j * ld + lane;
+                    double xi, eta;
+                    project(f[w], bx[o], by[o], bz[o], xi, eta);
+                    if (fma(xi, xi, eta * eta) == best[w]) {
+                        kf = j;
+                        break;
+                    }
+                }
+                k = kf;
+            }
+            const double d2 =
+                refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f[w], k, best[w]);
+            const double D = sqrt(d2);
+            const double d = capped_residual(D, drift, offsets[w], offsets[w + 1], lambda);
+            dsq[w] = d * d;
+        }
+    }
+}
+
 template <int W, int NWV, int C, bool CHUNK_ARGMIN>
 struct TileScan {
     static constexpr int kChunkDoubles = 3 * C * 64;
@@ -327,38 +376,151 @@ struct TileScan {
             }
         }
 
-        if (counter && lane == 0 && evals > 0)
-            atomicAdd(counter, (unsigned long long)(evals * n_valid));
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-            dsq[w] = 0.0;
-        if (!active || lane >= n_valid)
-            return;
+        scan_finish<W, C, CHUNK_ARGMIN>(bx, by, bz, ld, P, n_valid, f, nw, offsets, drift, lambda,
+                                        counter, evals, best, kbest, dsq);
+    }
+};
+
+// The same scan with every wave on its own: no LDS and no block barrier. A wave tests
+// each chunk as it comes (against min(ub, its running minimum), which only tightens
+// the bound) and loads the points of the chunks it needs straight from memory; waves
+// of a block that need the same chunk share it through the caches.
+template <int W, int C, bool CHUNK_ARGMIN>
+struct TileScanDirect {
+    static constexpr int kLdsDoubles = 1;
+
+    // Arguments as TileScan::run (pairs and lds are unused; no synchronisation).
+    __device__ static void run(const double *__restrict__ bx, const double *__restrict__ by,
+                               const double *__restrict__ bz, int64_t ld, int P, int n_valid,
+                               bool, const double (&f)[W][8], int nw,
+                               const int32_t *__restrict__ offsets,
+                               const double *__restrict__ drift, double lambda,
+                               const double *__restrict__ rho, int64_t ldr,
+                               unsigned long long *counter, double *, double (&dsq)[W])
+    {
+        static_assert(C % kRadiusChunk == 0 && C / kRadiusChunk <= 2, "chunk of 16 or 32");
+        const int lane = threadIdx.x & 63;
+        const bool active = nw > 0;
+        const bool seed = lane < n_valid;
+        const int64_t col = seed ? lane : 0;  // lanes without a seed read lane 0's column
+        double best[W], cmin[W];
+        float ub[W], sub[W];
+        int kbest[W];
+        int64_t evals = 0;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            if (w < nw) {
-                int k = kbest[w];
-                if (CHUNK_ARGMIN) {
-                    const int kend = min(k + C, P);
-                    int kf = k;
-                    for (int j = k; j < kend; ++j) {
-                        const int64_t o = (int64_t)j * ld + lane;
-                        double xi, eta;
-                        project(f[w], bx[o], by[o], bz[o], xi, eta);
-                        if (fma(xi, xi, eta * eta) == best[w]) {
-                            kf = j;
-                            break;
+            best[w] = INFINITY;
+            kbest[w] = 0;
+            ub[w] = INFINITY;
+        }
+        auto load = [&](int k, double &x, double &y, double &z) {
+            const int64_t o = (int64_t)k * ld + col;
+            x = bx[o];
+            y = by[o];
+            z = bz[o];
+        };
+        if (active) {
+            // (A) upper bounds of the final minima: every other chunk's first point
+            int n_s = 0;
+            for (int k0 = 0; k0 < P; k0 += 4 * C) {
+                double x0, y0, z0, x1 = 0.0, y1 = 0.0, z1 = 0.0;
+                load(k0, x0, y0, z0);
+                const bool two = k0 + 2 * C < P;
+                if (two)
+                    load(k0 + 2 * C, x1, y1, z1);
+                n_s += two ? 2 : 1;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    double xi, eta;
+                    project(f[w], x0, y0, z0, xi, eta);
+                    ub[w] = fminf(ub[w], (float)fma(xi, xi, eta * eta));
+                    if (two) {
+                        project(f[w], x1, y1, z1, xi, eta);
+                        ub[w] = fminf(ub[w], (float)fma(xi, xi, eta * eta));
+                    }
+                }
+            }
+            evals += (int64_t)nw * n_s;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
+
+            for (int k0 = 0; k0 < P; k0 += C) {
+                const int kn = min(C, P - k0);
+                double x, y, z, q0[W];
+                load(k0, x, y, z);
+                double r = 0.0;
+                if (kn == C) {
+                    const int nr = k0 / kRadiusChunk;
+                    r = rho[(int64_t)nr * ldr + col];
+                    if (C == 2 * kRadiusChunk)
+                        r = r + rho[(int64_t)(nr + 1) * ldr + col];
+                }
+                const float rf = (float)r * 1.000001f;
+                bool lane_need = false;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    double xi, eta;
+                    project(f[w], x, y, z, xi, eta);
+                    q0[w] = fma(xi, xi, eta * eta);
+                    if (w < nw) {
+                        const float B = fmaf(rf + sub[w], 1.000001f, 1e-6f);
+                        lane_need = lane_need ||
+                                    !((float)q0[w] * 0.999999f > (B * B) * 1.000001f);
+                    }
+                }
+                evals += nw;
+                // the partial last chunk is always scanned
+                if (kn < C || __builtin_amdgcn_ballot_w64(lane_need && seed) != 0) {
+                    evals += (int64_t)nw * (kn - 1);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        if (CHUNK_ARGMIN) {
+                            cmin[w] = q0[w];
+                        } else {
+                            kbest[w] = q0[w] < best[w] ? k0 : kbest[w];
+                            best[w] = fmin(best[w], q0[w]);
                         }
                     }
-                    k = kf;
+                    auto pt = [&](int k) {
+                        double px, py, pz;
+                        load(k, px, py, pz);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            double xi, eta;
+                            project(f[w], px, py, pz, xi, eta);
+                            const double q = fma(xi, xi, eta * eta);
+                            if (CHUNK_ARGMIN) {
+                                cmin[w] = fmin(cmin[w], q);
+                            } else {
+                                kbest[w] = q < best[w] ? k : kbest[w];
+                                best[w] = fmin(best[w], q);
+                            }
+                        }
+                    };
+                    if (kn == C) {
+#pragma unroll
+                        for (int kk = 1; kk < C; ++kk)
+                            pt(k0 + kk);
+                    } else {
+                        for (int kk = 1; kk < kn; ++kk)
+                            pt(k0 + kk);
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        if (CHUNK_ARGMIN && cmin[w] < best[w]) {
+                            best[w] = cmin[w];
+                            kbest[w] = k0;
+                        }
+                        // the running minimum bounds the final one as well
+                        sub[w] = fminf(sub[w],
+                                       __builtin_amdgcn_sqrtf((float)best[w]) * 1.000001f);
+                    }
                 }
-                const double d2 = refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f[w], k,
-                                              best[w]);
-                const double D = sqrt(d2);
-                const double d = capped_residual(D, drift, offsets[w], offsets[w + 1], lambda);
-                dsq[w] = d * d;
             }
         }
+        scan_finish<W, C, CHUNK_ARGMIN>(bx, by, bz, ld, P, n_valid, f, nw, offsets, drift, lambda,
+                                        counter, evals, best, kbest, dsq);
     }
 };
 
