@@ -483,6 +483,7 @@ def main():
             % (h["events_per_s"], h["partitions_with_complete_set"],
                h["classification"]["efficiency_mean"], h["classification"]["purity_mean"]))
     if grad_events:
+        from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))
         out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE,
                                             top_k=args.grad_topk, n_iter=args.grad_iters)

@@ -67,7 +67,8 @@ template <int W, int NWV, int C, int WPE, bool DIRECT>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_scan_kernel(BatchArgs a)
 {
-    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, true>, TileScan<W, NWV, C, true>>;
+    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, true, true>,
+                                    TileScan<W, NWV, C, true>>;
     constexpr int G = W * NWV;  // wires per group
     static_assert(NWV <= kMaxBatchNwv && G <= kBatchWirePad, "shape exceeds the workspace");
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];

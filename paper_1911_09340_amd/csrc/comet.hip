@@ -27,6 +27,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -95,7 +96,10 @@ __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restric
     tz[(int64_t)K * S] = z;
 }
 
-// Chunk radii of every seed's track (ChunkRadius): rho[n][s], one thread per seed.
+// Chunk radii of every seed's track (ChunkRadius: window n holds points 16 n ...
+// min(16 n + 16, P - 1), rho = the largest distance from its first point): one thread
+// per (seed, window), consecutive threads on consecutive seeds, so that every load
+// of a block reads one contiguous row segment.
 __global__ __launch_bounds__(256) void chunk_radius_kernel(const double *__restrict__ track,
                                                            int64_t S, int P,
                                                            double *__restrict__ rho)
@@ -104,10 +108,22 @@ __global__ __launch_bounds__(256) void chunk_radius_kernel(const double *__restr
     if (s >= S)
         return;
     const int64_t PS = (int64_t)P * S;
-    cdev::ChunkRadius acc;
-    for (int k = 0; k < P; ++k) {
-        const int64_t o = (int64_t)k * S + s;
-        acc.add(k, P, track[o], track[PS + o], track[2 * PS + o], rho + s, S);
+    const int nch = cdev::radius_chunks(P);
+    for (int n = blockIdx.y; n < nch; n += gridDim.y) {
+        const int k0 = n * cdev::kRadiusChunk;
+        const int k1 = min(k0 + cdev::kRadiusChunk, P - 1);
+        const int64_t o0 = (int64_t)k0 * S + s;
+        const double x0 = track[o0], y0 = track[PS + o0], z0 = track[2 * PS + o0];
+        double r2 = 0.0;
+#pragma unroll 4
+        for (int k = k0 + 1; k <= k1; ++k) {
+            const int64_t o = (int64_t)k * S + s;
+            const double dx = track[o] - x0, dy = track[PS + o] - y0,
+                         dz = track[2 * PS + o] - z0;
+            const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            r2 = d2 > r2 ? d2 : r2;
+        }
+        rho[(int64_t)n * S + s] = sqrt(r2);
     }
 }
 
@@ -145,15 +161,17 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) v
     double lambda, const double *__restrict__ rho, double *__restrict__ dsq, int n_groups,
     int n_blocks, int xcd_remap, unsigned long long *counter)
 {
-    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN>,
+    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN, true>,
                                     TileScan<W, NWV, C, CHUNK_ARGMIN>>;
+    using ScanFar = std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN, false>, Scan>;
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];
 
     const int b = blockIdx.x;
     const int q8 = n_blocks >> 3, r8 = n_blocks & 7;
     const int xcd = b & 7;
     const int L = xcd_remap ? xcd * q8 + min(xcd, r8) + (b >> 3) : b;
-    const int tile = L / n_groups;
+    // wave-uniform (the division runs on the vector unit; keep the result scalar)
+    const int tile = __builtin_amdgcn_readfirstlane(L / n_groups);
     const int group = L - tile * n_groups;
 
     const int lane = threadIdx.x & 63;
@@ -174,8 +192,14 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) v
     // 16-byte loads when every row start is 16-byte aligned (even S, aligned base)
     const bool pairs = (S & 1) == 0 && ((uintptr_t)track & 15) == 0;
     double d2[W];
-    Scan::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid, pairs, f, nw,
-              offsets + (nw > 0 ? wbase : 0), drift, lambda, rho + s0, S, counter, lds, d2);
+    // 32-bit buffer offsets reach every point of the tile when P S doubles span < 4 GiB
+    if (!DIRECT || (int64_t)P * S < ((int64_t)1 << 29) - 64)
+        Scan::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid, pairs, f, nw,
+                  offsets + (nw > 0 ? wbase : 0), drift, lambda, rho + s0, S, counter, lds, d2);
+    else
+        ScanFar::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid, pairs, f,
+                     nw, offsets + (nw > 0 ? wbase : 0), drift, lambda, rho + s0, S, counter, lds,
+                     d2);
     if (lane < n_valid)
 #pragma unroll
         for (int w = 0; w < W; ++w)
@@ -507,8 +531,11 @@ double *dca_rho(void *workspace, int n_wires, int64_t n_seeds)
 int launch_radius(const double *track_xyz, int64_t n_seeds, int32_t n_points, int n_wires,
                   void *workspace, hipStream_t hs)
 {
-    hipLaunchKernelGGL(chunk_radius_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256),
-                       0, hs, track_xyz, n_seeds, n_points, dca_rho(workspace, n_wires, n_seeds));
+    hipLaunchKernelGGL(chunk_radius_kernel,
+                       dim3((unsigned)((n_seeds + 255) / 256),
+                            (unsigned)std::min(cdev::radius_chunks(n_points), 65535)),
+                       dim3(256), 0, hs, track_xyz, n_seeds, n_points,
+                       dca_rho(workspace, n_wires, n_seeds));
     return launched("chunk_radius_kernel");
 }
 

@@ -384,8 +384,11 @@ struct TileScan {
 // The same scan with every wave on its own: no LDS and no block barrier. A wave tests
 // each chunk as it comes (against min(ub, its running minimum), which only tightens
 // the bound) and loads the points of the chunks it needs straight from memory; waves
-// of a block that need the same chunk share it through the caches.
-template <int W, int C, bool CHUNK_ARGMIN>
+// of a block that need the same chunk share it through the caches. With BUF (each
+// coordinate's rows, from the tile's first seed on, span less than 4 GiB) the loads
+// are buffer loads whose per-lane offset is fixed and whose row offset is a scalar,
+// so no per-point address arithmetic runs on the vector unit.
+template <int W, int C, bool CHUNK_ARGMIN, bool BUF>
 struct TileScanDirect {
     static constexpr int kLdsDoubles = 1;
 
@@ -413,11 +416,44 @@ struct TileScanDirect {
             kbest[w] = 0;
             ub[w] = INFINITY;
         }
+        // The frames sit in scalar registers; an FMA may read only one scalar pair, so
+        // the two offsets get vector copies once, not one per point.
+        double fo[W][2];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            asm("v_mov_b64 %0, %1" : "=v"(fo[w][0]) : "s"(f[w][3]));
+            asm("v_mov_b64 %0, %1" : "=v"(fo[w][1]) : "s"(f[w][7]));
+        }
+        auto proj_q = [&](int w, double x, double y, double z) {
+            const double xi = fma(f[w][0], x, fma(f[w][1], y, fma(f[w][2], z, fo[w][0])));
+            const double eta = fma(f[w][4], x, fma(f[w][5], y, fma(f[w][6], z, fo[w][1])));
+            return fma(xi, xi, eta * eta);
+        };
+        const uint32_t voff = (uint32_t)col * 8u;
+        // a raw buffer over one coordinate's rows (stride 0, no range limit); the base is
+        // the same for the whole wave, and readfirstlane tells the compiler so
+        auto rsrc = [](const double *p) {
+            const uint64_t a = (uint64_t)p;
+            const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(a >> 32))
+                                << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+            return __builtin_amdgcn_make_buffer_rsrc((void *)u, 0, -1, 0x00020000);
+        };
         auto load = [&](int k, double &x, double &y, double &z) {
-            const int64_t o = (int64_t)k * ld + col;
-            x = bx[o];
-            y = by[o];
-            z = bz[o];
+            if constexpr (BUF) {
+                const uint32_t soff = (uint32_t)k * (uint32_t)ld * 8u;  // wave-uniform
+                x = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(bx), voff, soff, 0));
+                y = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(by), voff, soff, 0));
+                z = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(bz), voff, soff, 0));
+            } else {
+                const int64_t o = (int64_t)k * ld + col;
+                x = bx[o];
+                y = by[o];
+                z = bz[o];
+            }
         };
         if (active) {
             // (A) upper bounds of the final minima: every other chunk's first point
@@ -460,9 +496,7 @@ struct TileScanDirect {
                 bool lane_need = false;
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    double xi, eta;
-                    project(f[w], x, y, z, xi, eta);
-                    q0[w] = fma(xi, xi, eta * eta);
+                    q0[w] = proj_q(w, x, y, z);
                     if (w < nw) {
                         const float B = fmaf(rf + sub[w], 1.000001f, 1e-6f);
                         lane_need = lane_need ||
@@ -482,14 +516,10 @@ struct TileScanDirect {
                             best[w] = fmin(best[w], q0[w]);
                         }
                     }
-                    auto pt = [&](int k) {
-                        double px, py, pz;
-                        load(k, px, py, pz);
+                    auto use = [&](int k, double px, double py, double pz) {
 #pragma unroll
                         for (int w = 0; w < W; ++w) {
-                            double xi, eta;
-                            project(f[w], px, py, pz, xi, eta);
-                            const double q = fma(xi, xi, eta * eta);
+                            const double q = proj_q(w, px, py, pz);
                             if (CHUNK_ARGMIN) {
                                 cmin[w] = fmin(cmin[w], q);
                             } else {
@@ -499,12 +529,39 @@ struct TileScanDirect {
                         }
                     };
                     if (kn == C) {
+                        // points 1 .. C-1 in batches of 3, the next batch loading while
+                        // the current one is used
+                        constexpr int NB = (C + 1) / 3;
+                        double cx[3], cy[3], cz[3];
+                        auto load3 = [&](int b, double (&x)[3], double (&y)[3], double (&z)[3]) {
 #pragma unroll
-                        for (int kk = 1; kk < C; ++kk)
-                            pt(k0 + kk);
+                            for (int i = 0; i < 3; ++i)
+                                if (1 + 3 * b + i < C)
+                                    load(k0 + 1 + 3 * b + i, x[i], y[i], z[i]);
+                        };
+                        load3(0, cx, cy, cz);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            double nx[3], ny[3], nz[3];
+                            if (b + 1 < NB)
+                                load3(b + 1, nx, ny, nz);
+#pragma unroll
+                            for (int i = 0; i < 3; ++i)
+                                if (1 + 3 * b + i < C)
+                                    use(k0 + 1 + 3 * b + i, cx[i], cy[i], cz[i]);
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                cx[i] = nx[i];
+                                cy[i] = ny[i];
+                                cz[i] = nz[i];
+                            }
+                        }
                     } else {
-                        for (int kk = 1; kk < kn; ++kk)
-                            pt(k0 + kk);
+                        for (int kk = 1; kk < kn; ++kk) {
+                            double px, py, pz;
+                            load(k0 + kk, px, py, pz);
+                            use(k0 + kk, px, py, pz);
+                        }
                     }
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
