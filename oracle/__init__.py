@@ -79,6 +79,14 @@ def _bind(lib):
                                       ctypes.c_int32]
     lib.oracle_merge_halves.restype = ctypes.c_int32
     lib.oracle_merge_halves.argtypes = [_d, _i32, _d, _i32, ctypes.c_int32, _i32, _d]
+    lib.oracle_backward_seed.restype = ctypes.c_int32
+    lib.oracle_backward_seed.argtypes = [_d, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int32, _d]
+    lib.oracle_stage_grid.restype = None
+    lib.oracle_stage_grid.argtypes = [_d, _d, _d, _d]
+    lib.oracle_exclude_hits.restype = ctypes.c_int32
+    lib.oracle_exclude_hits.argtypes = [ctypes.c_int32, _i32, _d, _d, ctypes.POINTER(ctypes.c_uint8),
+                                        _i32, _d, _d, _i32, _i32]
     lib.oracle_sparse_select.restype = ctypes.c_int32
     lib.oracle_sparse_select.argtypes = [_d, _d, ctypes.c_int32, _i32, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int64), _d, _d]
@@ -264,6 +272,38 @@ class Oracle:
         n = self.lib.oracle_merge_halves(_p(ra), _p(va, _i32), _p(rb), _p(vb, _i32), F,
                                          _p(pair, _i32), _p(prss))
         return pair, prss, int(n)
+
+    def backward_seed(self, seed6, bz, charge, h, radius, max_steps):
+        """State at the previous turn's entry through r = radius: (out6, steps)."""
+        out = np.empty(6)
+        k = self.lib.oracle_backward_seed(_p(_f64(seed6)), bz, charge, h, radius, max_steps,
+                                          _p(out))
+        return out, int(k)
+
+    def stage_grid(self, transverse6, ext6, half):
+        g = np.empty(14)
+        self.lib.oracle_stage_grid(_p(_f64(transverse6)), _p(_f64(ext6)), _p(_f64(half)), _p(g))
+        return g
+
+    def exclude_hits(self, offsets, drift, ends, exclude):
+        """(offsets, drift, ends, wire_map, hit_map) without the excluded hits."""
+        off = _i32a(offsets)
+        nw = off.size - 1
+        nh = int(off[-1])
+        ex = np.ascontiguousarray(exclude, dtype=np.uint8)
+        if ex.size == 0:
+            ex = np.zeros(1, np.uint8)
+        o2 = np.empty(nw + 1, np.int32)
+        d2 = np.empty(max(nh, 1))
+        e2 = np.empty((max(nw, 1), 6))
+        wm = np.empty(max(nw, 1), np.int32)
+        hm = np.empty(max(nh, 1), np.int32)
+        n = self.lib.oracle_exclude_hits(nw, _p(off, _i32), _p(_f64(drift) if nh else np.zeros(1)),
+                                         _p(_f64(ends).reshape(-1) if nw else np.zeros(6)),
+                                         ex.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                         _p(o2, _i32), _p(d2), _p(e2), _p(wm, _i32), _p(hm, _i32))
+        n_h = int(o2[n])
+        return o2[:n + 1].copy(), d2[:n_h].copy(), e2[:n].copy(), wm[:n].copy(), hm[:n_h].copy()
 
     def topk(self, values, k):
         v = _f64(values)

@@ -152,45 +152,64 @@ void oracle_refine_grid(double grid[14], const int32_t n[4], int64_t best)
  *   y <- y + h/6 (((k1 + 2 k2) + 2 k3) + k4).
  * pts: AoS [K+1][3].
  */
+typedef struct {
+    double inv, c, h, hh, h6, vz;
+} rk4_consts;
+
+static rk4_consts rk4_setup(double px, double py, double pz, double bz, double charge, double h)
+{
+    rk4_consts k;
+    double p0 = sqrt((px * px + py * py) + pz * pz);
+    k.inv = 1.0 / p0;
+    k.c = ((ORACLE_KAPPA * charge) * bz) * k.inv;
+    k.h = h;
+    k.hh = 0.5 * h;
+    k.h6 = h / 6.0;
+    k.vz = pz * k.inv; /* z velocity: the same at every stage */
+    return k;
+}
+
+/* one RK4 step of (x, y, z, px, py); p_z is constant */
+static void rk4_step(const rk4_consts *k, double *x, double *y, double *z, double *px,
+                     double *py)
+{
+    const double inv = k->inv, c = k->c, h = k->h, hh = k->hh, h6 = k->h6, vz = k->vz;
+    /* stage 1 at p */
+    double v1x = *px * inv, v1y = *py * inv;
+    double f1x = c * *py, f1y = -(c * *px);
+    /* stage 2 at p + h/2 f1 */
+    double qx = *px + hh * f1x, qy = *py + hh * f1y;
+    double v2x = qx * inv, v2y = qy * inv;
+    double f2x = c * qy, f2y = -(c * qx);
+    /* stage 3 at p + h/2 f2 */
+    qx = *px + hh * f2x;
+    qy = *py + hh * f2y;
+    double v3x = qx * inv, v3y = qy * inv;
+    double f3x = c * qy, f3y = -(c * qx);
+    /* stage 4 at p + h f3 */
+    qx = *px + h * f3x;
+    qy = *py + h * f3y;
+    double v4x = qx * inv, v4y = qy * inv;
+    double f4x = c * qy, f4y = -(c * qx);
+
+    *x = *x + h6 * (((v1x + 2.0 * v2x) + 2.0 * v3x) + v4x);
+    *y = *y + h6 * (((v1y + 2.0 * v2y) + 2.0 * v3y) + v4y);
+    *z = *z + h6 * (((vz + 2.0 * vz) + 2.0 * vz) + vz);
+    *px = *px + h6 * (((f1x + 2.0 * f2x) + 2.0 * f3x) + f4x);
+    *py = *py + h6 * (((f1y + 2.0 * f2y) + 2.0 * f3y) + f4y);
+}
+
 void oracle_track(const double seed[6], double bz, double charge, double h, int32_t K,
                   double *pts)
 {
     double x = seed[0], y = seed[1], z = seed[2];
-    double px = seed[3], py = seed[4], pz = seed[5];
-    double p0 = sqrt((px * px + py * py) + pz * pz);
-    double inv = 1.0 / p0;
-    double c = ((ORACLE_KAPPA * charge) * bz) * inv;
-    double hh = 0.5 * h;
-    double h6 = h / 6.0;
-    double vz = pz * inv; /* z velocity: the same at every stage */
-
-    for (int32_t k = 0; k < K; ++k) {
-        pts[3 * k + 0] = x;
-        pts[3 * k + 1] = y;
-        pts[3 * k + 2] = z;
-        /* stage 1 at p */
-        double v1x = px * inv, v1y = py * inv;
-        double f1x = c * py, f1y = -(c * px);
-        /* stage 2 at p + h/2 f1 */
-        double qx = px + hh * f1x, qy = py + hh * f1y;
-        double v2x = qx * inv, v2y = qy * inv;
-        double f2x = c * qy, f2y = -(c * qx);
-        /* stage 3 at p + h/2 f2 */
-        qx = px + hh * f2x;
-        qy = py + hh * f2y;
-        double v3x = qx * inv, v3y = qy * inv;
-        double f3x = c * qy, f3y = -(c * qx);
-        /* stage 4 at p + h f3 */
-        qx = px + h * f3x;
-        qy = py + h * f3y;
-        double v4x = qx * inv, v4y = qy * inv;
-        double f4x = c * qy, f4y = -(c * qx);
-
-        x = x + h6 * (((v1x + 2.0 * v2x) + 2.0 * v3x) + v4x);
-        y = y + h6 * (((v1y + 2.0 * v2y) + 2.0 * v3y) + v4y);
-        z = z + h6 * (((vz + 2.0 * vz) + 2.0 * vz) + vz);
-        px = px + h6 * (((f1x + 2.0 * f2x) + 2.0 * f3x) + f4x);
-        py = py + h6 * (((f1y + 2.0 * f2y) + 2.0 * f3y) + f4y);
+    double px = seed[3], py = seed[4];
+    const rk4_consts k = rk4_setup(px, py, seed[5], bz, charge, h);
+    for (int32_t j = 0; j < K; ++j) {
+        pts[3 * j + 0] = x;
+        pts[3 * j + 1] = y;
+        pts[3 * j + 2] = z;
+        rk4_step(&k, &x, &y, &z, &px, &py);
     }
     pts[3 * K + 0] = x;
     pts[3 * K + 1] = y;
@@ -1019,4 +1038,99 @@ int32_t oracle_merge_halves(const double *rss_a, const int32_t *veto_a, const do
     }
     free(r);
     return m;
+}
+
+/* ------------------------------------------------------------ stage loop (Sec. 3.1)
+ * Backward extrapolation to the previous turn partition: the fitted track of a stage
+ * is extrapolated backwards to the seed region of the previous turn, which gives the
+ * longitudinal seed (z, p_z) of the next stage. From seed6 (x, p) at the current
+ * turn's outward crossing of r = radius, the track runs backwards (momentum and
+ * charge flipped) with the RK4 step of oracle_track, each step's full state kept.
+ * Backwards, the track first heads inwards, comes out again through r = radius (the
+ * previous turn's exit) and goes back in through it (the previous turn's entry): the
+ * answer is the first inward crossing after an outward one. Between the states a and
+ * b of the step that crosses, with d = r^2 - radius^2 (r^2 = x x + y y) >= 0 at a and
+ * < 0 at b, f = d_a / (d_a - d_b) and every component is fma(f, b - a, a); the
+ * momentum is flipped back. out6 is NaN when no such crossing comes within
+ * max_steps. Returns the step count at the crossing (-1 if none). */
+int32_t oracle_backward_seed(const double seed6[6], double bz, double charge, double h,
+                             double radius, int32_t max_steps, double out6[6])
+{
+    double s[6] = {seed6[0], seed6[1], seed6[2], -seed6[3], -seed6[4], -seed6[5]};
+    const rk4_consts kc = rk4_setup(s[3], s[4], s[5], bz, -charge, h);
+    const double R2 = radius * radius;
+    int out_seen = 0;
+    for (int32_t k = 0; k < 6; ++k)
+        out6[k] = NAN;
+    for (int32_t k = 1; k <= max_steps; ++k) {
+        double a[6];
+        for (int j = 0; j < 6; ++j)
+            a[j] = s[j];
+        rk4_step(&kc, &s[0], &s[1], &s[2], &s[3], &s[4]);
+        const double da = (a[0] * a[0] + a[1] * a[1]) - R2;
+        const double db = (s[0] * s[0] + s[1] * s[1]) - R2;
+        if (da < 0.0 && db >= 0.0)
+            out_seen = 1;
+        else if (out_seen && da >= 0.0 && db < 0.0) {
+            const double f = da / (da - db);
+            for (int j = 0; j < 6; ++j)
+                out6[j] = fma(f, s[j] - a[j], a[j]);
+            out6[3] = -out6[3];
+            out6[4] = -out6[4];
+            out6[5] = -out6[5];
+            return k;
+        }
+    }
+    return -1;
+}
+
+/* The next stage's grid descriptor: the transverse seed (x, y, p_x, p_y) of the turn
+ * (the Hough-transform seed of Sec. 3.1) with (z, p_z) from the backward
+ * extrapolation; axis centres (0, |p|, 0, 0) with |p| = sqrt((px px + py py) + pz pz)
+ * and the given half-spans. */
+void oracle_stage_grid(const double transverse6[6], const double ext6[6], const double half[4],
+                       double grid[14])
+{
+    for (int j = 0; j < 6; ++j)
+        grid[j] = transverse6[j];
+    grid[2] = ext6[2];
+    grid[5] = ext6[5];
+    grid[6] = 0.0;
+    grid[7] = sqrt((grid[3] * grid[3] + grid[4] * grid[4]) + grid[5] * grid[5]);
+    grid[8] = 0.0;
+    grid[9] = 0.0;
+    for (int a = 0; a < 4; ++a)
+        grid[10 + a] = half[a];
+}
+
+/* Exclusion of classified hits (Sec. 3.1: hits classified at earlier stages are left
+ * out of later scans, so the wire count shrinks). One event in CSR (wire i owns hits
+ * [offsets[i], offsets[i+1]), offsets[0] = 0): hits with exclude[j] != 0 are dropped,
+ * then wires left without hits; the order of what remains is kept. Writes the new
+ * CSR (offsets_out[n_out + 1], drift_out, ends_out[n_out][6]), wire_map[i'] = old wire
+ * and hit_map[j'] = old hit; returns n_out. */
+int32_t oracle_exclude_hits(int32_t n_wires, const int32_t *offsets, const double *drift,
+                            const double *ends, const uint8_t *exclude, int32_t *offsets_out,
+                            double *drift_out, double *ends_out, int32_t *wire_map,
+                            int32_t *hit_map)
+{
+    int32_t nw = 0, nh = 0;
+    offsets_out[0] = 0;
+    for (int32_t i = 0; i < n_wires; ++i) {
+        const int32_t h0 = nh;
+        for (int32_t j = offsets[i]; j < offsets[i + 1]; ++j)
+            if (!exclude[j]) {
+                drift_out[nh] = drift[j];
+                hit_map[nh] = j;
+                ++nh;
+            }
+        if (nh > h0) {
+            for (int c = 0; c < 6; ++c)
+                ends_out[6 * nw + c] = ends[6 * i + c];
+            wire_map[nw] = i;
+            ++nw;
+            offsets_out[nw] = nh;
+        }
+    }
+    return nw;
 }

@@ -620,3 +620,69 @@ def pin_merge_sorted(o):
 
 
 ALL_SIMPLE.extend([pin_layer_veto_hand, pin_layer_veto_sets, pin_merge_hand, pin_merge_sorted])
+
+
+# ------------------------------------------------------------------ stage loop
+def pin_backward_seed_helix(o):
+    """In a uniform field a turn's entry through r = R repeats exactly one revolution
+    later, so the previous entry is (x, y, z - L p_z / |p|, p) with L the path length of
+    one revolution: the backward extrapolation lands there within the RK4 step error
+    and the chord interpolation (< 0.01 mm), with p_z exact."""
+    from paper_1911_09340_amd import synth
+    for p, pol, az in ((100.0, 1.2, 0.3), (80.0, 1.35, 2.0), (104.0, 1.4, 4.0)):
+        st0 = synth.vertex_state(p, pol, az)
+        L = synth.turn_length(st0, -1.0, 1.0)
+        s_in = synth._outward_crossing(st0, -1.0, 1.0, L + 1.0)
+        s_in2 = synth._outward_crossing(synth.helix_state(st0, -1.0, 1.0, s_in + 1.0), -1.0, 1.0,
+                                        L + 1.0)
+        assert s_in is not None and s_in2 is not None
+        now = synth.helix_state(st0, -1.0, 1.0, s_in + 1.0 + s_in2)   # second turn's entry
+        prev = synth.helix_state(st0, -1.0, 1.0, s_in)                # first turn's entry
+        out, k = o.backward_seed(now, 1.0, -1.0, 2.0, synth.SEED_RADIUS, 5000)
+        assert k > 0, (p, pol)
+        assert np.max(np.abs(out[:3] - prev[:3])) < 0.01, (out, prev)
+        assert np.max(np.abs(out[3:5] - prev[3:5])) < 1e-3, (out, prev)
+        assert out[5] == now[5]
+        # a start just outside r = R: the first inward crossing is the current turn's own
+        # entry, not the previous one, and must be passed over
+        after = synth.helix_state(st0, -1.0, 1.0, s_in + 1.0 + s_in2 + 0.7)
+        out2, k2 = o.backward_seed(after, 1.0, -1.0, 2.0, synth.SEED_RADIUS, 5000)
+        assert k2 > 1 and np.max(np.abs(out2[:3] - prev[:3])) < 0.01, (out2, prev)
+    # too few steps: no crossing, NaN
+    out, k = o.backward_seed(now, 1.0, -1.0, 2.0, synth.SEED_RADIUS, 10)
+    assert k == -1 and np.isnan(out).all()
+
+
+def pin_stage_grid(o):
+    t = np.array([1.0, 2.0, 3.0, 3.0, 4.0, 6.0])
+    e = np.array([9.0, 9.0, -7.0, 9.0, 9.0, 12.0])
+    g = o.stage_grid(t, e, [0.5, 1.5, 0.01, 0.02])
+    assert g.tolist() == [1.0, 2.0, -7.0, 3.0, 4.0, 12.0, 0.0, 13.0, 0.0, 0.0,
+                          0.5, 1.5, 0.01, 0.02]
+
+
+def pin_exclude_hits(o):
+    """Wires with 2, 1, 3 hits; dropping hit 0, both hits of wire 1 (hit 2) and hit 4
+    leaves wires 0 (hit 1) and 2 (hits 3, 5), in order."""
+    off = np.array([0, 2, 3, 6], np.int32)
+    drift = np.arange(6) * 1.5
+    ends = np.arange(18, dtype=np.float64).reshape(3, 6)
+    ex = np.array([1, 0, 1, 0, 1, 0], np.uint8)
+    o2, d2, e2, wm, hm = o.exclude_hits(off, drift, ends, ex)
+    assert o2.tolist() == [0, 1, 3] and wm.tolist() == [0, 2] and hm.tolist() == [1, 3, 5]
+    assert d2.tolist() == [1.5, 4.5, 7.5] and np.array_equal(e2, ends[[0, 2]])
+    rng = np.random.default_rng(4)
+    for trial in range(50):
+        n_w = int(rng.integers(0, 9))
+        counts = rng.integers(1, 4, n_w)
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        nh = int(off[-1])
+        ex = (rng.random(nh) < 0.5).astype(np.uint8)
+        o2, d2, e2, wm, hm = o.exclude_hits(off, rng.random(nh), rng.random((n_w, 6)), ex)
+        keep = [j for j in range(nh) if not ex[j]]
+        assert hm.tolist() == keep, trial
+        wires = sorted({int(np.searchsorted(off, j, side="right") - 1) for j in keep})
+        assert wm.tolist() == wires and o2[-1] == len(keep), trial
+
+
+ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_exclude_hits])

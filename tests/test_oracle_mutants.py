@@ -16,11 +16,11 @@ import pins
 from paper_1911_09340_amd import synth
 
 MUTANTS = {
-    "rk4_drop_factor2": ("x = x + h6 * (((v1x + 2.0 * v2x)", "x = x + h6 * (((v1x + v2x)"),
-    "rk4_full_half_step": ("double hh = 0.5 * h;", "double hh = h;"),
-    "rk4_force_sign": ("double f1x = c * py, f1y = -(c * px);", "double f1x = c * py, f1y = (c * px);"),
-    "rk4_stage4_uses_f2": ("qx = px + h * f3x;", "qx = px + h * f2x;"),
-    "rk4_h6": ("double h6 = h / 6.0;", "double h6 = h / 5.0;"),
+    "rk4_drop_factor2": ("*x = *x + h6 * (((v1x + 2.0 * v2x)", "*x = *x + h6 * (((v1x + v2x)"),
+    "rk4_full_half_step": ("k.hh = 0.5 * h;", "k.hh = h;"),
+    "rk4_force_sign": ("double f1x = c * *py, f1y = -(c * *px);", "double f1x = c * *py, f1y = (c * *px);"),
+    "rk4_stage4_uses_f2": ("qx = *px + h * f3x;", "qx = *px + h * f2x;"),
+    "rk4_h6": ("k.h6 = h / 6.0;", "k.h6 = h / 5.0;"),
     "grid_half_angle_sin": ("*s = (2.0 * tau) / den;", "*s = (tau) / den;"),
     "grid_py_uses_cp": ("out[4] = v1 * (st * sp);", "out[4] = v1 * (st * cp);"),
     "grid_axis_order": ("int32_t i3 = (int32_t)(index % n[3]);", "int32_t i3 = (int32_t)(index % n[2]);"),
@@ -60,6 +60,12 @@ MUTANTS = {
     "merge_ignores_exit_veto": ("if (veto_a[i] != 0 || veto_b[j] != 0 ||", "if (veto_a[i] != 0 ||"),
     "merge_ties_reversed": ("    return (a->k > b->k) - (a->k < b->k);", "    return (a->k < b->k) - (a->k > b->k);"),
     "merge_transposed_pair": ("            r[m].k = i * F + j;", "            r[m].k = j * F + i;"),
+    "backward_first_inward": ("        else if (out_seen && da >= 0.0 && db < 0.0) {", "        else if (da >= 0.0 && db < 0.0) {"),
+    "backward_no_flip_back": ("            out6[3] = -out6[3];\n            out6[4] = -out6[4];", "            out6[3] = out6[3];\n            out6[4] = out6[4];"),
+    "backward_charge_kept": ("rk4_setup(s[3], s[4], s[5], bz, -charge, h)", "rk4_setup(s[3], s[4], s[5], bz, charge, h)"),
+    "backward_interp_reversed": ("            const double f = da / (da - db);", "            const double f = db / (db - da);"),
+    "stage_grid_keeps_truth_z": ("    grid[2] = ext6[2];\n    grid[5] = ext6[5];", "    grid[5] = ext6[5];"),
+    "exclude_keeps_empty_wires": ("        if (nh > h0) {\n            for (int c = 0; c < 6; ++c)", "        if (nh >= h0) {\n            for (int c = 0; c < 6; ++c)"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
