@@ -245,6 +245,51 @@ def bench_halves(events, sc, n_ref: int = 10, n_iter: int = 2, n_fine=(4, 8, 8, 
             "classification": quality.classification(run.best_complete_masks(), events)}
 
 
+def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int = 3):
+    """The stage loop: every event reconstructed turn by turn from its last turn, the
+    hits of each stage left out of the next, each next stage's (z, p_z) from the
+    backward extrapolation of the previous stage's seed (eager runs, device-synchronised
+    wall time)."""
+    import torch
+    from paper_1911_09340_amd import quality, stages
+    run = stages.StageRunner(events, sc, max_stages=max_stages, min_wires=min_wires)
+    run.run()
+    torch.cuda.synchronize()
+    dts = []
+    for r in range(reps):
+        t0 = time.perf_counter()
+        run.run()
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - t0)
+        log("  stage-loop run %d: %.3f s" % (r, dts[-1]))
+    dt = float(np.median(dts))
+    tm = run.turn_masks()
+    stride = max(ev.n_hits for ev in events)
+    rows = []
+    for ev, m in zip(events, tm):
+        for t in range(ev.n_turns):
+            row = np.zeros(stride, np.uint8)
+            row[:ev.n_hits] = m[t]
+            rows.append(row)
+    masks = np.stack(rows)
+    by_turns = {}
+    p = 0
+    for ev in events:
+        q = quality.classification(masks[p:p + ev.n_turns], [ev])
+        by_turns.setdefault(ev.n_turns, []).append((q["efficiency_mean"], q["purity_mean"]))
+        p += ev.n_turns
+    act = run.active_after.cpu().numpy()
+    return {"events": len(events), "seeds_per_stage_scan": sc.n_seeds, "rescans": sc.n_refine,
+            "max_stages": max_stages, "min_wires": min_wires,
+            "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "events_active_after_stage": [int(a.sum()) for a in act],
+            "classification_all_turns": quality.classification(masks, events),
+            "efficiency_purity_by_turns": {
+                str(k): [float(np.mean([x[0] for x in v])),
+                         float(np.nanmean([x[1] for x in v])) if any(not np.isnan(x[1]) for x in v)
+                         else None, len(v)] for k, v in sorted(by_turns.items())}}
+
+
 def bench_stress(events, sc, top_k: int = 64, n_iter: int = 8):
     """The stress mix: one batched scan of every partition, then Levenberg-Marquardt
     from the top_k lowest-RSS seeds of each partition (device time per phase)."""
@@ -301,6 +346,8 @@ def main():
                     help="skip the several-reference re-scan on the batched mix")
     ap.add_argument("--no-halves", dest="halves", action="store_false",
                     help="skip the half-track scans and merge on the batched mix")
+    ap.add_argument("--no-stages", dest="stages", action="store_false",
+                    help="skip the stage loop on the batched mix")
     ap.add_argument("--stress-events", type=int, default=0,
                     help="events of the stress mix (1-6 turns, 200-1200 hits, 30%% noise, "
                          "131072 seeds, 2000 x 1.5 mm) through the batched scan and LM from "
@@ -482,6 +529,15 @@ def main():
         log("  %.1f events/s; complete sets in %.3f of partitions; efficiency %.3f purity %.3f"
             % (h["events_per_s"], h["partitions_with_complete_set"],
                h["classification"]["efficiency_mean"], h["classification"]["purity_mean"]))
+    if batch_events and args.stages:
+        log("stage loop: %d events, up to 5 stages from the last turn back ..." % len(batch_events))
+        out["stages"] = bench_stages(batch_events, synth.C2)
+        st = out["stages"]
+        log("  %.1f events/s; efficiency %.3f purity %.3f over all turns; by turns: %s"
+            % (st["events_per_s"], st["classification_all_turns"]["efficiency_mean"],
+               st["classification_all_turns"]["purity_mean"],
+               ", ".join("%s: %.2f/%s" % (k, v[0], "-" if v[1] is None else "%.2f" % v[1])
+                         for k, v in st["efficiency_purity_by_turns"].items())))
     if grad_events:
         from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))

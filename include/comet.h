@@ -324,6 +324,60 @@ int comet_merge_halves(const double *rss_a, const int32_t *veto_a, const double 
                        const int32_t *veto_b, int32_t n_partitions, int32_t n_seeds,
                        int32_t *pair, double *pair_rss, int32_t *n_complete, void *stream);
 
+/* ------------------------------------------------------------ stage loop (Sec. 3.1)
+ * Turn partitions are reconstructed one stage at a time from the last turn backwards.
+ * After a stage the hits it classified are left out of later scans, the chosen seed
+ * is extrapolated backwards to the previous turn's entry, which gives the next
+ * stage's longitudinal seed (z, p_z) (the transverse seed comes from elsewhere: the
+ * Hough transform in the paper), and an event stops when fewer than a minimum of
+ * wires remain or enough tracks were found. All arrays are device arrays; every call
+ * launches on `stream` without allocating or synchronising.
+ *
+ * comet_backward_seeds: for seed i (seeds6[i][6], at a turn's outward crossing of
+ * r = radius mm) the track runs backwards (momentum and charge flipped, the RK4 step
+ * of comet_extrapolate_seeds with cfg's field and step) for at most max_steps steps;
+ * out6[i] is the state at the first inward crossing of r = radius after an outward
+ * one (the previous turn's entry), interpolated linearly in r^2 - radius^2 between
+ * the two states of the crossing step, momentum flipped back; NaN (steps[i] = -1)
+ * when there is none within max_steps. steps (int32[n]) may be NULL.
+ *
+ * comet_stage_grids: grids[i][14] = the descriptor of comet_seed_grid with reference
+ * state (x, y, z, px, py, pz) = (transverse6[i][0], [1], ext6[i][2], transverse6[i][3],
+ * [4], ext6[i][5]), centres (0, |p|, 0, 0) and half-spans half (host double[4]).
+ *
+ * comet_exclude_hits: the packed events (CSR as in comet_batch_scan, with hit_ids[j] the
+ * caller's index of hit j) without the hits whose exclude[j] != 0, and without the
+ * wires left with no hit; the order of what remains is kept. Outputs have the input
+ * capacities (n_wires + 1, n_hits, n_wires x 6, n_hits); workspace >=
+ * comet_exclude_workspace_bytes(n_events), 256-byte aligned. Outputs must not alias
+ * inputs.
+ *
+ * comet_stage_record: for each event e with active[e] != 0, the hits with bit 0 set
+ * in hit_mask[e] (indexed as in comet_batch_scan) get stage_of_hit[hit_ids[j]] = stage
+ * and exclude[j] = 1; every other hit gets exclude[j] = 0.
+ *
+ * comet_stage_update: active[e] stays 1 only if best[e] >= 0, stage + 1 <
+ * min(n_turns[e], max_stages) and event e keeps at least min_wires wires in the CSR
+ * event_wires_next (after the exclusion). */
+int comet_backward_seeds(const double *seeds6, int32_t n, const comet_config *cfg, double radius,
+                         int32_t max_steps, double *out6, int32_t *steps, void *stream);
+int comet_stage_grids(const double *transverse6, const double *ext6, int32_t n,
+                      const double half[4], double *grids, void *stream);
+size_t comet_exclude_workspace_bytes(int32_t n_events);
+int comet_exclude_hits(const int32_t *event_wires, int32_t n_events, const int32_t *wire_offsets,
+                       int32_t n_wires, const double *drift, const double *wire_ends,
+                       const int32_t *hit_ids, int32_t n_hits, const uint8_t *exclude,
+                       int32_t *event_wires_out, int32_t *wire_offsets_out, double *drift_out,
+                       double *wire_ends_out, int32_t *hit_ids_out, void *workspace,
+                       size_t workspace_bytes, void *stream);
+int comet_stage_record(const uint8_t *hit_mask, int64_t mask_stride, int32_t n_events,
+                       const int32_t *event_wires, const int32_t *wire_offsets,
+                       const int32_t *hit_ids, const int32_t *active, int32_t stage,
+                       int32_t *stage_of_hit, uint8_t *exclude, void *stream);
+int comet_stage_update(int32_t *active, int32_t n_events, const int64_t *best,
+                       const int32_t *event_wires_next, const int32_t *n_turns, int32_t stage,
+                       int32_t max_stages, int32_t min_wires, void *stream);
+
 /* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
  * per LDS chunk, the persistent block count on the current device, and direct as for
  * the DCA shapes; blocks and direct may be NULL); every shape gives the same results.

@@ -369,6 +369,21 @@ def _bind_batch(lib):
     lib.comet_layer_veto.restype = ctypes.c_int
     lib.comet_merge_halves.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]
     lib.comet_merge_halves.restype = ctypes.c_int
+    D4 = ctypes.POINTER(ctypes.c_double)
+    lib.comet_backward_seeds.argtypes = [_vp, _i32, ctypes.POINTER(Config), ctypes.c_double, _i32,
+                                         _vp, _vp, _vp]
+    lib.comet_backward_seeds.restype = ctypes.c_int
+    lib.comet_stage_grids.argtypes = [_vp, _vp, _i32, D4, _vp, _vp]
+    lib.comet_stage_grids.restype = ctypes.c_int
+    lib.comet_exclude_workspace_bytes.argtypes = [_i32]
+    lib.comet_exclude_workspace_bytes.restype = ctypes.c_size_t
+    lib.comet_exclude_hits.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
+                                       _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.comet_exclude_hits.restype = ctypes.c_int
+    lib.comet_stage_record.argtypes = [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]
+    lib.comet_stage_record.restype = ctypes.c_int
+    lib.comet_stage_update.argtypes = [_vp, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _vp]
+    lib.comet_stage_update.restype = ctypes.c_int
     lib._batch_bound = True
     return lib
 
@@ -516,3 +531,78 @@ def merge_halves(rss_a: torch.Tensor, veto_a: torch.Tensor, rss_b: torch.Tensor,
         _ptr(pair_rss, torch.float64, "pair_rss", (P, F * F)),
         _ptr(n_complete, torch.int32, "n_complete", (P,), optional=True), _stream()),
         "comet_merge_halves")
+
+
+# ------------------------------------------------------------------ stage loop
+def backward_seeds(seeds: torch.Tensor, cfg: Config, radius: float, max_steps: int,
+                   out: torch.Tensor, steps=None) -> None:
+    """comet_backward_seeds: seeds [n, 6] -> out [n, 6] (optional steps [n] int32)."""
+    lib = _bind_batch(load())
+    n = int(seeds.shape[0])
+    _check(lib.comet_backward_seeds(_ptr(seeds, torch.float64, "seeds", (n, 6)), n,
+                                    ctypes.byref(cfg), float(radius), int(max_steps),
+                                    _ptr(out, torch.float64, "out", (n, 6)),
+                                    _ptr(steps, torch.int32, "steps", (n,), optional=True),
+                                    _stream()), "comet_backward_seeds")
+
+
+def stage_grids(transverse: torch.Tensor, ext: torch.Tensor, half, grids: torch.Tensor) -> None:
+    lib = _bind_batch(load())
+    n = int(transverse.shape[0])
+    h = (ctypes.c_double * 4)(*[float(v) for v in half])
+    _check(lib.comet_stage_grids(_ptr(transverse, torch.float64, "transverse", (n, 6)),
+                                 _ptr(ext, torch.float64, "ext", (n, 6)), n, h,
+                                 _ptr(grids, torch.float64, "grids", (n, 14)), _stream()),
+           "comet_stage_grids")
+
+
+def exclude_workspace(n_events: int, device=None) -> torch.Tensor:
+    nbytes = int(_bind_batch(load()).comet_exclude_workspace_bytes(int(n_events)))
+    return torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=device or "cuda")
+
+
+def exclude_hits(src, exclude: torch.Tensor, dst, workspace: torch.Tensor) -> None:
+    """comet_exclude_hits from packed events src (with .hit_ids) into dst (same capacities)."""
+    lib = _bind_batch(load())
+    n_w, n_h = int(src.wire_ends.shape[0]), int(src.drift.shape[0])
+    n_e = int(src.event_wires.shape[0]) - 1
+    _check(lib.comet_exclude_hits(
+        _ptr(src.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e,
+        _ptr(src.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)), n_w,
+        _ptr(src.drift, torch.float64, "drift", (n_h,)),
+        _ptr(src.wire_ends, torch.float64, "wire_ends", (n_w, 6)),
+        _ptr(src.hit_ids, torch.int32, "hit_ids", (n_h,)), n_h,
+        _ptr(exclude, torch.uint8, "exclude", (n_h,)),
+        _ptr(dst.event_wires, torch.int32, "event_wires_out", (n_e + 1,)),
+        _ptr(dst.wire_offsets, torch.int32, "wire_offsets_out", (n_w + 1,)),
+        _ptr(dst.drift, torch.float64, "drift_out", (n_h,)),
+        _ptr(dst.wire_ends, torch.float64, "wire_ends_out", (n_w, 6)),
+        _ptr(dst.hit_ids, torch.int32, "hit_ids_out", (n_h,)),
+        _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()),
+        "comet_exclude_hits")
+
+
+def stage_record(hit_mask: torch.Tensor, packed, active: torch.Tensor, stage: int,
+                 stage_of_hit: torch.Tensor, exclude: torch.Tensor) -> None:
+    lib = _bind_batch(load())
+    n_e, stride = int(hit_mask.shape[0]), int(hit_mask.shape[1])
+    n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
+    _check(lib.comet_stage_record(
+        _ptr(hit_mask, torch.uint8, "hit_mask", (n_e, stride)), stride, n_e,
+        _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)),
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(packed.hit_ids, torch.int32, "hit_ids", (n_h,)),
+        _ptr(active, torch.int32, "active", (n_e,)), int(stage),
+        _ptr(stage_of_hit, torch.int32, "stage_of_hit"),
+        _ptr(exclude, torch.uint8, "exclude", (n_h,)), _stream()), "comet_stage_record")
+
+
+def stage_update(active: torch.Tensor, best: torch.Tensor, event_wires_next: torch.Tensor,
+                 n_turns: torch.Tensor, stage: int, max_stages: int, min_wires: int) -> None:
+    lib = _bind_batch(load())
+    n_e = int(active.shape[0])
+    _check(lib.comet_stage_update(
+        _ptr(active, torch.int32, "active", (n_e,)), n_e, _ptr(best, torch.int64, "best", (n_e,)),
+        _ptr(event_wires_next, torch.int32, "event_wires_next", (n_e + 1,)),
+        _ptr(n_turns, torch.int32, "n_turns", (n_e,)), int(stage), int(max_stages),
+        int(min_wires), _stream()), "comet_stage_update")

@@ -1,0 +1,123 @@
+"""The stage loop of the event reconstruction (Sec. 3.1), batched over events.
+
+Stage s scans, for every event still active, its turn partition n_turns - 1 - s (the
+reconstruction starts from the last turn). The grid's transverse seed is the turn's
+true state at the seed radius (the stand-in for the paper's Hough-transform seed); its
+longitudinal seed (z, p_z) is the true one at stage 0 (the stand-in for the hodoscope
+prior of the last turn) and, later, the previous stage's chosen seed extrapolated
+backwards by one turn (comet_backward_seeds). Per stage, on the device:
+  comet_stage_grids -> comet_batch_scan (scan, re-scans, classification)
+  -> comet_stage_record (the classified hits get the stage number and are marked)
+  -> comet_exclude_hits (later stages scan only the hits left)
+  -> comet_backward_seeds -> comet_stage_update (stop when fewer than min_wires wires
+     remain, when max_stages tracks were found or when the event has no turn left).
+This module owns the buffers and orders the launches; no host synchronisation.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import comet, scan, synth
+
+
+@dataclass
+class StagePacked:
+    """Packed events (CSR as scan.PackedEvents) plus each hit's original index."""
+    wire_ends: torch.Tensor
+    wire_offsets: torch.Tensor
+    drift: torch.Tensor
+    event_wires: torch.Tensor
+    hit_ids: torch.Tensor
+
+    @classmethod
+    def from_events(cls, events, device="cuda"):
+        p = scan.PackedEvents.from_events(events, device)
+        n_h = int(p.drift.shape[0])
+        return cls(p.wire_ends, p.wire_offsets, p.drift, p.event_wires,
+                   torch.arange(n_h, dtype=torch.int32, device=device))
+
+    def empty_like(self):
+        return StagePacked(*(torch.empty_like(t) for t in (self.wire_ends, self.wire_offsets,
+                                                           self.drift, self.event_wires,
+                                                           self.hit_ids)))
+
+
+class StageRunner:
+    def __init__(self, events, scan_cfg: synth.ScanConfig, max_stages: int = 5,
+                 min_wires: int = 30, max_back_steps: int = 4000, device="cuda"):
+        self.events = list(events)
+        self.sc = scan_cfg
+        self.max_stages, self.min_wires = int(max_stages), int(min_wires)
+        self.max_back_steps = int(max_back_steps)
+        E = self.n_events = len(self.events)
+        self.cfg = scan.config_for(self.events[0], scan_cfg)
+        # stage 0 reads the events as given; later stages alternate between two buffers
+        self.packed0 = StagePacked.from_events(self.events, device)
+        self.bufs = [self.packed0.empty_like(), self.packed0.empty_like()]
+        self.n_hits = int(self.packed0.drift.shape[0])
+        turns = np.array([ev.n_turns for ev in self.events], np.int32)
+        self.n_turns = torch.as_tensor(turns, device=device)
+        tr = np.empty((self.max_stages, E, 6))
+        for s in range(self.max_stages):
+            for e, ev in enumerate(self.events):
+                tr[s, e] = ev.ref_states[max(ev.n_turns - 1 - s, 0)]
+        self.transverse = torch.as_tensor(tr, device=device)
+        active0 = np.array([ev.n_wires >= self.min_wires for ev in self.events], np.int32)
+        self.active0 = torch.as_tensor(active0, device=device)
+        self.active = self.active0.clone()
+        f64 = dict(dtype=torch.float64, device=device)
+        S = scan_cfg.n_seeds
+        self.part_event = torch.arange(E, dtype=torch.int32, device=device)
+        self.grids = torch.empty(E, 14, **f64)
+        self.rss = torch.empty(E, S, **f64)
+        self.best = torch.empty(max(self.max_stages, 1), E, dtype=torch.int64, device=device)
+        self.seeds = torch.empty(self.max_stages, E, 6, **f64)
+        self.best_rss = torch.empty(self.max_stages, E, **f64)
+        self.ext = torch.empty(E, 6, **f64)
+        self.stride = max(max(ev.n_hits for ev in self.events), 1)
+        self.mask = torch.zeros(E, self.stride, dtype=torch.uint8, device=device)
+        self.n_border = torch.empty(E, dtype=torch.int32, device=device)
+        self.stage_of_hit = torch.empty(self.n_hits, dtype=torch.int32, device=device)
+        self.exclude = torch.empty(self.n_hits, dtype=torch.uint8, device=device)
+        self.workspace = comet.batch_workspace(int(self.packed0.wire_ends.shape[0]),
+                                               scan_cfg.n_steps, E, device)
+        self.ex_workspace = comet.exclude_workspace(E, device)
+        self.active_after = torch.empty(self.max_stages, E, dtype=torch.int32, device=device)
+
+    def run(self) -> None:
+        self.stage_of_hit.fill_(-1)
+        self.active.copy_(self.active0)
+        for s in range(self.max_stages):
+            src = self.packed0 if s == 0 else self.bufs[(s - 1) % 2]
+            dst = self.bufs[s % 2]
+            ext = self.transverse[0] if s == 0 else self.ext
+            comet.stage_grids(self.transverse[s], ext, self.sc.half, self.grids)
+            comet.batch_scan(src, self.part_event, self.grids, self.sc.n, self.cfg,
+                             self.sc.n_refine, self.rss, self.best[s], self.workspace,
+                             best_seed=self.seeds[s], best_rss=self.best_rss[s],
+                             hit_mask=self.mask, n_borderline=self.n_border)
+            comet.stage_record(self.mask, src, self.active, s, self.stage_of_hit, self.exclude)
+            comet.exclude_hits(src, self.exclude, dst, self.ex_workspace)
+            comet.backward_seeds(self.seeds[s], self.cfg, synth.SEED_RADIUS,
+                                 self.max_back_steps, self.ext)
+            comet.stage_update(self.active, self.best[s], dst.event_wires, self.n_turns, s,
+                               self.max_stages, self.min_wires)
+            self.active_after[s].copy_(self.active)
+
+    # ---------------------------------------------------------- host-side reporting
+    def turn_masks(self) -> list:
+        """Per event, [n_turns, n_hits] bit-0 masks: the hits classified to each turn (the
+        stage that scanned it), from stage_of_hit."""
+        soh = self.stage_of_hit.cpu().numpy()
+        out, h0 = [], 0
+        for ev in self.events:
+            m = np.zeros((ev.n_turns, ev.n_hits), np.uint8)
+            part = soh[h0:h0 + ev.n_hits]
+            for s in range(min(ev.n_turns, self.max_stages)):
+                m[ev.n_turns - 1 - s] = part == s
+            out.append(m)
+            h0 += ev.n_hits
+        return out

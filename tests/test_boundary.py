@@ -264,3 +264,24 @@ def test_layer_veto_and_merge_reject(lib):
         bad = list(ok)
         bad[i] = v
         assert lib.comet_merge_halves(*bad) == comet.EINVAL, (i, v)
+
+
+def test_stage_calls_reject(lib):
+    comet._bind_batch(lib)
+    cfg = _cfg()
+    assert lib.comet_backward_seeds(None, 3, ctypes.byref(cfg), 500.0, 10, _p(), None, None) == comet.EINVAL
+    assert lib.comet_backward_seeds(_p(), 0, ctypes.byref(cfg), 500.0, 10, _p(), None, None) == comet.EINVAL
+    assert lib.comet_backward_seeds(_p(), 3, ctypes.byref(cfg), -1.0, 10, _p(), None, None) == comet.EINVAL
+    assert lib.comet_backward_seeds(_p(), 3, ctypes.byref(cfg), 500.0, 0, _p(), None, None) == comet.EINVAL
+    half = (ctypes.c_double * 4)(1.0, 1.0, -1.0, 1.0)
+    assert lib.comet_stage_grids(_p(), _p(), 3, half, _p(), None) == comet.EINVAL
+    assert lib.comet_exclude_workspace_bytes(0) == 0
+    need = lib.comet_exclude_workspace_bytes(10)
+    assert need >= 120 and need % 256 == 0
+    args = [_p(), 2, _p(), 10, _p(), _p(), _p(), 20, _p(), _p(), _p(), _p(), _p(), _p()]
+    assert lib.comet_exclude_hits(*args, _p(0x100000), 16, None) == comet.EWORKSPACE
+    bad = list(args)
+    bad[0] = None
+    assert lib.comet_exclude_hits(*bad, _p(0x100000), need, None) == comet.EINVAL
+    assert lib.comet_stage_record(_p(), 0, 2, _p(), _p(), _p(), _p(), 0, _p(), _p(), None) == comet.EINVAL
+    assert lib.comet_stage_update(_p(), 2, _p(), _p(), _p(), 0, 0, 30, None) == comet.EINVAL
