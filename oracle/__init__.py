@@ -87,6 +87,12 @@ def _bind(lib):
     lib.oracle_exclude_hits.restype = ctypes.c_int32
     lib.oracle_exclude_hits.argtypes = [ctypes.c_int32, _i32, _d, _d, ctypes.POINTER(ctypes.c_uint8),
                                         _i32, _d, _d, _i32, _i32]
+    lib.oracle_field_at.restype = None
+    lib.oracle_field_at.argtypes = [_d, _i32, _d, _d, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, _d]
+    lib.oracle_track_field.restype = None
+    lib.oracle_track_field.argtypes = [_d, _d, _i32, _d, _d, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int32, _d]
     lib.oracle_sparse_select.restype = ctypes.c_int32
     lib.oracle_sparse_select.argtypes = [_d, _d, ctypes.c_int32, _i32, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int64), _d, _d]
@@ -304,6 +310,26 @@ class Oracle:
                                          _p(o2, _i32), _p(d2), _p(e2), _p(wm, _i32), _p(hm, _i32))
         n_h = int(o2[n])
         return o2[:n + 1].copy(), d2[:n_h].copy(), e2[:n].copy(), wm[:n].copy(), hm[:n_h].copy()
+
+    def field_at(self, fmap, x, y, z):
+        """B (tesla) of a field map (b [nz, ny, nx, 3], origin [3], step [3]) at a point."""
+        b, origin, step = fmap
+        b = _f64(b)
+        n = np.array([b.shape[2], b.shape[1], b.shape[0]], np.int32)
+        out = np.empty(3)
+        self.lib.oracle_field_at(_p(b), _p(n, _i32), _p(_f64(origin)), _p(_f64(step)), x, y, z,
+                                 _p(out))
+        return out
+
+    def track_field(self, seed, fmap, charge, h, K):
+        """RK4 track in a field map: [K + 1, 3] positions."""
+        b, origin, step = fmap
+        b = _f64(b)
+        n = np.array([b.shape[2], b.shape[1], b.shape[0]], np.int32)
+        pts = np.empty((K + 1, 3))
+        self.lib.oracle_track_field(_p(_f64(seed)), _p(b), _p(n, _i32), _p(_f64(origin)),
+                                    _p(_f64(step)), charge, h, K, _p(pts))
+        return pts
 
     def topk(self, values, k):
         v = _f64(values)

@@ -1134,3 +1134,118 @@ int32_t oracle_exclude_hits(int32_t n_wires, const int32_t *offsets, const doubl
     }
     return nw;
 }
+
+/* ------------------------------------------------------------ field map (Sec. 2.2.1)
+ * The paper extrapolates tracks through the solenoid's field map. Here the map is a
+ * regular grid of B (tesla) at nodes (x0 + i dx, y0 + j dy, z0 + k dz), i < nx, j < ny,
+ * k < nz, stored b[((k ny + j) nx + i) 3 + c]. B at a point: each coordinate u = (x -
+ * x0) / dx is clamped to [0, nx - 1], i = min(floor(u), nx - 2), t = u - i, and B is
+ * interpolated trilinearly with lerp(a, b, t) = fma(t, b - a, a): first along x (four
+ * edges, in the order (j, k) = (0,0), (1,0), (0,1), (1,1)), then along y, then along z. */
+typedef struct {
+    const double *b;
+    int32_t nx, ny, nz;
+    double x0, y0, z0, dx, dy, dz;
+} oracle_field;
+
+static double lerp(double a, double b, double t) { return fma(t, b - a, a); }
+
+static void cell(double u, int32_t n, int32_t *i, double *t)
+{
+    if (!(u > 0.0))
+        u = 0.0;  /* NaN lands here too */
+    if (u > (double)(n - 1))
+        u = (double)(n - 1);
+    int32_t k = (int32_t)floor(u);
+    if (k > n - 2)
+        k = n - 2;
+    *i = k;
+    *t = u - (double)k;
+}
+
+static void field_at(const oracle_field *f, double x, double y, double z, double B[3])
+{
+    int32_t i, j, k;
+    double tu, tv, tw;
+    cell((x - f->x0) / f->dx, f->nx, &i, &tu);
+    cell((y - f->y0) / f->dy, f->ny, &j, &tv);
+    cell((z - f->z0) / f->dz, f->nz, &k, &tw);
+    for (int c = 0; c < 3; ++c) {
+#define NODE(a, b2, c2) f->b[((((int64_t)(k + (c2))) * f->ny + (j + (b2))) * f->nx + (i + (a))) * 3 + c]
+        const double c00 = lerp(NODE(0, 0, 0), NODE(1, 0, 0), tu);
+        const double c10 = lerp(NODE(0, 1, 0), NODE(1, 1, 0), tu);
+        const double c01 = lerp(NODE(0, 0, 1), NODE(1, 0, 1), tu);
+        const double c11 = lerp(NODE(0, 1, 1), NODE(1, 1, 1), tu);
+#undef NODE
+        B[c] = lerp(lerp(c00, c10, tv), lerp(c01, c11, tv), tw);
+    }
+}
+
+void oracle_field_at(const double *b, const int32_t n[3], const double origin[3],
+                     const double step[3], double x, double y, double z, double B[3])
+{
+    oracle_field f = {b, n[0], n[1], n[2], origin[0], origin[1], origin[2],
+                      step[0], step[1], step[2]};
+    field_at(&f, x, y, z, B);
+}
+
+/* RK4 in a field map. dx/ds = p / p0, dp/ds = ((KAPPA q) / p0) (p x B(x)), p0 = |p| of
+ * the seed; every stage evaluates B at its own position:
+ *   k1 at (x, p); k2 at (x + h/2 v1, p + h/2 f1); k3 at (x + h/2 v2, p + h/2 f2);
+ *   k4 at (x + h v3, p + h f3); y <- y + h/6 (((k1 + 2 k2) + 2 k3) + k4),
+ * with v = p inv, f = g (p x B) where g = (KAPPA q) inv, and the cross product
+ * (p_y B_z - p_z B_y, p_z B_x - p_x B_z, p_x B_y - p_y B_x). pts: AoS [K+1][3]. */
+static void field_force(const oracle_field *fm, double g, const double x[3], const double p[3],
+                        double f[3])
+{
+    double B[3];
+    field_at(fm, x[0], x[1], x[2], B);
+    f[0] = g * (p[1] * B[2] - p[2] * B[1]);
+    f[1] = g * (p[2] * B[0] - p[0] * B[2]);
+    f[2] = g * (p[0] * B[1] - p[1] * B[0]);
+}
+
+void oracle_track_field(const double seed[6], const double *b, const int32_t n[3],
+                        const double origin[3], const double step[3], double charge, double h,
+                        int32_t K, double *pts)
+{
+    oracle_field fm = {b, n[0], n[1], n[2], origin[0], origin[1], origin[2],
+                       step[0], step[1], step[2]};
+    double x[3] = {seed[0], seed[1], seed[2]}, p[3] = {seed[3], seed[4], seed[5]};
+    const double p0 = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+    const double inv = 1.0 / p0;
+    const double g = (ORACLE_KAPPA * charge) * inv;
+    const double hh = 0.5 * h, h6 = h / 6.0;
+    for (int32_t j = 0; j < K; ++j) {
+        for (int c = 0; c < 3; ++c)
+            pts[3 * j + c] = x[c];
+        double v1[3], f1[3], v2[3], f2[3], v3[3], f3[3], v4[3], f4[3], xs[3], ps[3];
+        for (int c = 0; c < 3; ++c)
+            v1[c] = p[c] * inv;
+        field_force(&fm, g, x, p, f1);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = x[c] + hh * v1[c];
+            ps[c] = p[c] + hh * f1[c];
+            v2[c] = ps[c] * inv;
+        }
+        field_force(&fm, g, xs, ps, f2);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = x[c] + hh * v2[c];
+            ps[c] = p[c] + hh * f2[c];
+            v3[c] = ps[c] * inv;
+        }
+        field_force(&fm, g, xs, ps, f3);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = x[c] + h * v3[c];
+            ps[c] = p[c] + h * f3[c];
+            v4[c] = ps[c] * inv;
+        }
+        field_force(&fm, g, xs, ps, f4);
+        for (int c = 0; c < 3; ++c) {
+            x[c] = x[c] + h6 * (((v1[c] + 2.0 * v2[c]) + 2.0 * v3[c]) + v4[c]);
+            p[c] = p[c] + h6 * (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]);
+        }
+    }
+    for (int c = 0; c < 3; ++c)
+        pts[3 * K + c] = x[c];
+}

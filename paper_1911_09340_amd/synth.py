@@ -539,3 +539,20 @@ def half_events(ev: Event, turn: int):
     a = _sub_event(ev, entrance, ref, ev.charge, {"turn": turn, "side": "entrance"})
     b = _sub_event(ev, ~entrance, flipped, -ev.charge, {"turn": turn, "side": "exit"})
     return a, b
+
+
+# ---------------------------------------------------------------- field map
+def solenoid_map(b0: float = 1.0, g: float = 0.1, z_scale: float = 1500.0,
+                 half_xy: float = 1000.0, half_z: float = 1500.0, step: float = 25.0):
+    """A synthetic solenoid field map (the COMET map is not available): on a regular grid,
+    B_z = b0 (1 + g (z / Z)^2), B_x = -b0 g z x / Z^2, B_y = -b0 g z y / Z^2 (tesla),
+    which has zero divergence. Returns (b [nz, ny, nx, 3], origin [3], step [3])."""
+    xs = np.arange(-half_xy, half_xy + 0.5 * step, step)
+    zs = np.arange(-half_z, half_z + 0.5 * step, step)
+    Z, Y, X = np.meshgrid(zs, xs, xs, indexing="ij")
+    b = np.empty(Z.shape + (3,))
+    b[..., 0] = -b0 * g * Z * X / z_scale ** 2
+    b[..., 1] = -b0 * g * Z * Y / z_scale ** 2
+    b[..., 2] = b0 * (1.0 + g * (Z / z_scale) ** 2)
+    return (np.ascontiguousarray(b), np.array([xs[0], xs[0], zs[0]]),
+            np.array([step, step, step]))

@@ -686,3 +686,73 @@ def pin_exclude_hits(o):
 
 
 ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_exclude_hits])
+
+
+# ------------------------------------------------------------------ field map
+def pin_field_trilinear(o):
+    """Trilinear interpolation is exact for a field linear in x, y and z (and at the
+    nodes); outside the grid the point is clamped to it."""
+    rng = np.random.default_rng(8)
+    nz, ny, nx = 4, 5, 6
+    origin, step = np.array([-10.0, 20.0, -5.0]), np.array([2.0, 3.0, 4.0])
+    A = rng.normal(0, 1, (3, 4))
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X, Y, Z = origin[0] + i * step[0], origin[1] + j * step[1], origin[2] + k * step[2]
+    b = np.stack([A[c, 0] + A[c, 1] * X + A[c, 2] * Y + A[c, 3] * Z for c in range(3)], axis=-1)
+    fm = (b, origin, step)
+    lin = lambda x, y, z: np.array([A[c, 0] + A[c, 1] * x + A[c, 2] * y + A[c, 3] * z
+                                    for c in range(3)])
+    assert np.array_equal(o.field_at(fm, X[1, 2, 3], Y[1, 2, 3], Z[1, 2, 3]), b[1, 2, 3])
+    for _ in range(50):
+        x = origin[0] + rng.uniform(0, (nx - 1) * step[0])
+        y = origin[1] + rng.uniform(0, (ny - 1) * step[1])
+        z = origin[2] + rng.uniform(0, (nz - 1) * step[2])
+        assert np.allclose(o.field_at(fm, x, y, z), lin(x, y, z), rtol=0, atol=1e-12)
+    far = o.field_at(fm, 1e4, -1e4, 0.0)
+    edge = o.field_at(fm, origin[0] + (nx - 1) * step[0], origin[1], 0.0)
+    near = o.field_at(fm, origin[0] + (nx - 0.5) * step[0], origin[1] - 0.5 * step[1], 0.0)
+    assert np.array_equal(far, edge) and np.array_equal(near, edge)
+
+
+def pin_field_uniform_helix(o):
+    """A constant map B = (0, 0, 1 T) gives the uniform-field helix: the same track as
+    the uniform stepping to rounding, and the closed form within the RK4 error."""
+    from paper_1911_09340_amd import synth
+    b = np.zeros((3, 3, 3, 3))
+    b[..., 2] = 1.0
+    fm = (b, np.array([-2000.0, -2000.0, -2000.0]), np.array([2000.0, 2000.0, 2000.0]))
+    seed = synth.vertex_state(100.0, 1.1, 0.4)
+    pts = o.track_field(seed, fm, -1.0, 2.0, 600)
+    uni = o.track(seed, 1.0, -1.0, 2.0, 600)
+    uni = uni if uni.shape[-1] == 3 else uni.T
+    assert np.max(np.abs(pts - uni)) < 1e-9
+    exact = synth.helix_state(seed, -1.0, 1.0, 2.0 * np.arange(601))[:, :3]
+    assert np.max(np.abs(pts - exact)) < 1e-4
+
+
+def pin_field_solenoid_rk4(o):
+    """In the solenoid map |p| is conserved, so every step advances the position by h
+    (to the RK4 error). In a field linear in the coordinates (so that the trilinear map
+    is exact and smooth: B_z = 1 + g z / Z, B_x = -g x / 2Z, B_y = -g y / 2Z, no
+    divergence) halving h shrinks the endpoint error ~16x: fourth order, which needs
+    every stage to read B at its own position."""
+    from paper_1911_09340_amd import synth
+    fm = synth.solenoid_map(g=0.6, z_scale=800.0)
+    seed = synth.vertex_state(90.0, 1.0, 0.7, vertex=(0.0, 0.0, -600.0))
+    pts = o.track_field(seed, fm, -1.0, 2.0, 600)
+    steps = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+    assert np.max(np.abs(steps - 2.0)) < 1e-5
+    g, Z = 0.5, 1000.0
+    xs = np.array([-1000.0, 1000.0])
+    zs = np.array([-1500.0, 1500.0])
+    K3, Y3, X3 = np.meshgrid(zs, xs, xs, indexing="ij")
+    b = np.stack([-g * X3 / (2 * Z), -g * Y3 / (2 * Z), 1.0 + g * K3 / Z], axis=-1)
+    lin = (b, np.array([-1000.0, -1000.0, -1500.0]), np.array([2000.0, 2000.0, 3000.0]))
+    L = 1200.0
+    ref = o.track_field(seed, lin, -1.0, 0.25, int(L / 0.25))[-1]
+    e = [np.linalg.norm(o.track_field(seed, lin, -1.0, h, int(L / h))[-1] - ref)
+         for h in (8.0, 4.0)]
+    assert 10.0 < e[0] / e[1] < 24.0, e
+
+
+ALL_SIMPLE.extend([pin_field_trilinear, pin_field_uniform_helix, pin_field_solenoid_rk4])

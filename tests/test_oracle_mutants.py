@@ -66,6 +66,10 @@ MUTANTS = {
     "backward_interp_reversed": ("            const double f = da / (da - db);", "            const double f = db / (db - da);"),
     "stage_grid_keeps_truth_z": ("    grid[2] = ext6[2];\n    grid[5] = ext6[5];", "    grid[5] = ext6[5];"),
     "exclude_keeps_empty_wires": ("        if (nh > h0) {\n            for (int c = 0; c < 6; ++c)", "        if (nh >= h0) {\n            for (int c = 0; c < 6; ++c)"),
+    "field_stage_at_start": ("        for (int c = 0; c < 3; ++c) {\n            xs[c] = x[c] + hh * v1[c];", "        for (int c = 0; c < 3; ++c) {\n            xs[c] = x[c] + 0.0 * v1[c];"),
+    "field_cross_sign": ("    f[1] = g * (p[2] * B[0] - p[0] * B[2]);", "    f[1] = g * (p[0] * B[2] - p[2] * B[0]);"),
+    "field_lerp_reversed": ("static double lerp(double a, double b, double t) { return fma(t, b - a, a); }", "static double lerp(double a, double b, double t) { return fma(t, a - b, b); }"),
+    "field_no_clamp": ("    if (u > (double)(n - 1))\n        u = (double)(n - 1);", "    if (u > (double)(n + 5))\n        u = (double)(n - 1);"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
