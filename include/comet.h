@@ -91,6 +91,25 @@ int comet_refine_grid(double *grid, const int32_t n[4], const int64_t *best, voi
 int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
                             double *track_xyz, void *stream);
 
+/* Track recording in a field map (Sec. 2.2.1 extrapolates through the solenoid's
+ * field map). The map is B (tesla) on a regular grid: b device double[nz][ny][nx][3]
+ * at nodes (x0 + i dx, y0 + j dy, z0 + k dz) mm; B at a point is the trilinear
+ * interpolation of its cell (each coordinate clamped to the grid). The ODE is
+ * dx/ds = p / |p_seed|, dp/ds = (kappa q / |p_seed|) (p x B(x)), stepped with
+ * classical RK4 (every stage reads B at its own position), step cfg->step_mm,
+ * cfg->n_steps steps; cfg->bz_tesla is not used. The output is as for
+ * comet_extrapolate_seeds, so comet_dca_rss and comet_select_classify take it
+ * unchanged. nx, ny, nz >= 2, reserved 0, spacings > 0. The caller owns the map. */
+typedef struct comet_field {
+    const double *b;
+    int32_t nx, ny, nz;
+    int32_t reserved; /* must be 0 */
+    double x0, y0, z0;
+    double dx, dy, dz;
+} comet_field;
+int comet_extrapolate_seeds_field(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                                  const comet_field *field, double *track_xyz, void *stream);
+
 /* Bytes of workspace comet_dca_rss needs for n_seeds seeds of n_points recorded points
  * and n_wires wires (0 for invalid sizes). */
 size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_points, int32_t n_wires);

@@ -129,6 +129,28 @@ def make_config(bz: float, charge: float, step_mm: float, n_steps: int, lambda_m
     return Config(float(bz), float(charge), float(step_mm), int(n_steps), 0, float(lambda_mm))
 
 
+class Field(ctypes.Structure):
+    """comet_field (host struct; b is a device pointer)."""
+    _fields_ = [("b", _vp), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class FieldMap:
+    """A field map on the device: b [nz, ny, nx, 3] (tesla), origin and spacing (mm);
+    keeps the tensor alive for the struct's pointer."""
+
+    def __init__(self, b, origin, step, device="cuda"):
+        self.b = torch.as_tensor(b, dtype=torch.float64, device=device).contiguous()
+        if self.b.dim() != 4 or self.b.shape[3] != 3:
+            raise ValueError("b must have shape [nz, ny, nx, 3]")
+        nz, ny, nx = (int(v) for v in self.b.shape[:3])
+        self.struct = Field(_vp(self.b.data_ptr()), nx, ny, nz, 0, float(origin[0]),
+                            float(origin[1]), float(origin[2]), float(step[0]), float(step[1]),
+                            float(step[2]))
+
+
 # ------------------------------------------------------------------ entry points
 def seed_grid(grid: torch.Tensor, n, seeds: torch.Tensor) -> None:
     """comet_seed_grid: grid f64[14] -> seeds f64[6, S], S = prod(n)."""
@@ -152,6 +174,22 @@ def extrapolate_seeds(seeds: torch.Tensor, cfg: Config, track: torch.Tensor) -> 
         _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
         _ptr(track, torch.float64, "track", (3, cfg.n_steps + 1, S)), _stream()),
         "comet_extrapolate_seeds")
+
+
+def extrapolate_seeds_field(seeds: torch.Tensor, cfg: Config, field: FieldMap,
+                            track: torch.Tensor) -> None:
+    """comet_extrapolate_seeds_field: RK4 in the field map; seeds f64[6, S] -> track."""
+    lib = load()
+    S = int(seeds.shape[1])
+    lib.comet_extrapolate_seeds_field.argtypes = [_vp, _i64, ctypes.POINTER(Config),
+                                                  ctypes.POINTER(Field), _vp, _vp]
+    lib.comet_extrapolate_seeds_field.restype = ctypes.c_int
+    _ptr(field.b, torch.float64, "field.b")
+    _check(lib.comet_extrapolate_seeds_field(
+        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
+        ctypes.byref(field.struct),
+        _ptr(track, torch.float64, "track", (3, cfg.n_steps + 1, S)), _stream()),
+        "comet_extrapolate_seeds_field")
 
 
 def dca_workspace_bytes(n_seeds: int, n_points: int, n_wires: int) -> int:

@@ -42,7 +42,10 @@ class DeviceEvent:
 class PartitionScanner:
     """Buffers sized for one grid shape, step count and event size."""
 
-    def __init__(self, n, cfg: comet.Config, n_wires: int, n_hits: int, device="cuda"):
+    def __init__(self, n, cfg: comet.Config, n_wires: int, n_hits: int, device="cuda",
+                 field=None):
+        """field: a comet.FieldMap to record tracks in (None: the uniform field of cfg)."""
+        self.field = field
         self.n = tuple(int(v) for v in n)
         self.S = int(np.prod(self.n))
         self.cfg = cfg
@@ -65,7 +68,10 @@ class PartitionScanner:
             if it:
                 comet.refine_grid(self.grid, self.n, self.best)
             comet.seed_grid(self.grid, self.n, self.seeds)
-            comet.extrapolate_seeds(self.seeds, self.cfg, self.track)
+            if self.field is None:
+                comet.extrapolate_seeds(self.seeds, self.cfg, self.track)
+            else:
+                comet.extrapolate_seeds_field(self.seeds, self.cfg, self.field, self.track)
             comet.dca_rss(self.track, ev.wire_ends, ev.wire_offsets, ev.drift, self.cfg,
                           self.rss, self.workspace)
             last = it == n_refine

@@ -285,3 +285,19 @@ def test_stage_calls_reject(lib):
     assert lib.comet_exclude_hits(*bad, _p(0x100000), need, None) == comet.EINVAL
     assert lib.comet_stage_record(_p(), 0, 2, _p(), _p(), _p(), _p(), 0, _p(), _p(), None) == comet.EINVAL
     assert lib.comet_stage_update(_p(), 2, _p(), _p(), _p(), 0, 0, 30, None) == comet.EINVAL
+
+
+def test_field_call_rejects(lib):
+    lib.comet_extrapolate_seeds_field.argtypes = [ctypes.c_void_p, ctypes.c_int64,
+                                                  ctypes.POINTER(comet.Config),
+                                                  ctypes.POINTER(comet.Field), ctypes.c_void_p,
+                                                  ctypes.c_void_p]
+    cfg = _cfg()
+    good = comet.Field(_p(), 3, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    assert lib.comet_extrapolate_seeds_field(None, 4, ctypes.byref(cfg), ctypes.byref(good), _p(), None) == comet.EINVAL
+    for field in (comet.Field(None, 3, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0),
+                  comet.Field(_p(), 1, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0),
+                  comet.Field(_p(), 3, 3, 3, 1, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0),
+                  comet.Field(_p(), 3, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 0.0, 1.0)):
+        assert lib.comet_extrapolate_seeds_field(_p(), 4, ctypes.byref(cfg), ctypes.byref(field),
+                                                 _p(), None) == comet.EINVAL
