@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("runtime.hip", "comet.hip", "adjoint.hip", "batch.hip", "halves.hip", "stages.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("runtime.hip", "comet.hip", "adjoint.hip", "batch.hip",
+                                             "halves.hip", "stages.hip", "field.hip")]
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcomet.so")
 

@@ -96,36 +96,6 @@ __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restric
     tz[(int64_t)K * S] = z;
 }
 
-// Track recording in a field map (one thread per seed), as rk4_record_kernel with
-// the map's RK4 step.
-__global__ __launch_bounds__(256) void rk4_field_record_kernel(const double *__restrict__ seeds,
-                                                               int64_t S, cdev::FieldMap m,
-                                                               double charge, double h, int K,
-                                                               double *__restrict__ track)
-{
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S)
-        return;
-    double x[3] = {seeds[0 * S + s], seeds[1 * S + s], seeds[2 * S + s]};
-    double p[3] = {seeds[3 * S + s], seeds[4 * S + s], seeds[5 * S + s]};
-    const double p0 = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
-    const double inv = 1.0 / p0;
-    const double g = (cdev::kKappa * charge) * inv;
-    const int64_t P = (int64_t)K + 1;
-    double *tx = track + s;
-    double *ty = track + P * S + s;
-    double *tz = track + 2 * P * S + s;
-    for (int j = 0; j < K; ++j) {
-        tx[(int64_t)j * S] = x[0];
-        ty[(int64_t)j * S] = x[1];
-        tz[(int64_t)j * S] = x[2];
-        cdev::rk4_field_step(m, inv, g, h, x, p);
-    }
-    tx[(int64_t)K * S] = x[0];
-    ty[(int64_t)K * S] = x[1];
-    tz[(int64_t)K * S] = x[2];
-}
-
 // Chunk radii of every seed's track (ChunkRadius: window n holds points 16 n ...
 // min(16 n + 16, P - 1), rho = the largest distance from its first point): one thread
 // per (seed, window), consecutive threads on consecutive seeds, so that every load
@@ -498,37 +468,6 @@ int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_c
                        dim3(threads), 0, (hipStream_t)stream, seeds6, n_seeds, cfg->bz_tesla,
                        cfg->charge_e, cfg->step_mm, cfg->n_steps, track_xyz);
     return launched("rk4_record_kernel");
-}
-
-int comet_extrapolate_seeds_field(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
-                                  const comet_field *field, double *track_xyz, void *stream)
-{
-    clear_error();
-    if (!seeds6 || !track_xyz || !field || !field->b)
-        return fail(COMET_EINVAL, "comet_extrapolate_seeds_field: NULL pointer");
-    if (n_seeds < 1 || n_seeds > ((int64_t)1 << 40))
-        return fail(COMET_EINVAL, "comet_extrapolate_seeds_field: n_seeds = %lld",
-                    (long long)n_seeds);
-    if (field->nx < 2 || field->ny < 2 || field->nz < 2 || field->reserved != 0 ||
-        !finite_pos(field->dx) || !finite_pos(field->dy) || !finite_pos(field->dz) ||
-        !isfinite(field->x0) || !isfinite(field->y0) || !isfinite(field->z0))
-        return fail(COMET_EINVAL, "comet_extrapolate_seeds_field: need nx, ny, nz >= 2, "
-                                  "reserved 0, finite origin, spacings > 0");
-    int st = check_config(cfg);
-    if (st)
-        return st;
-    st = check_device();
-    if (st)
-        return st;
-    const cdev::FieldMap m{field->b, field->nx, field->ny, field->nz, field->x0, field->y0,
-                           field->z0, field->dx, field->dy, field->dz};
-    const int threads = 256;
-    ProfScope prof(kProfTrack, (hipStream_t)stream);
-    hipLaunchKernelGGL(rk4_field_record_kernel,
-                       dim3((unsigned)((n_seeds + threads - 1) / threads)), dim3(threads), 0,
-                       (hipStream_t)stream, seeds6, n_seeds, m, cfg->charge_e, cfg->step_mm,
-                       cfg->n_steps, track_xyz);
-    return launched("rk4_field_record_kernel");
 }
 
 size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_points, int32_t n_wires)

@@ -216,104 +216,6 @@ __device__ __forceinline__ void rk4_step(const StepConsts &k, double &x, double 
     py = py + k.h6 * (((f1y + 2.0 * f2y) + 2.0 * f3y) + f4y);
 }
 
-// ------------------------------------------------------------------ field map
-// B on a regular grid, b[((k ny + j) nx + i) 3 + c] at node (x0 + i dx, y0 + j dy,
-// z0 + k dz). A coordinate u = (x - x0) / dx is clamped to [0, n - 1] (NaN to 0),
-// i = min(floor(u), n - 2), t = u - i; B is interpolated trilinearly with
-// lerp(a, b, t) = fma(t, b - a, a): along x on the four edges (j, k) = (0,0), (1,0),
-// (0,1), (1,1), then along y, then along z.
-struct FieldMap {
-    const double *b;
-    int nx, ny, nz;
-    double x0, y0, z0, dx, dy, dz;
-};
-
-__device__ __forceinline__ double lerp(double a, double b, double t) { return fma(t, b - a, a); }
-
-__device__ __forceinline__ void field_cell(double u, int n, int &i, double &t)
-{
-    if (!(u > 0.0))
-        u = 0.0;
-    if (u > (double)(n - 1))
-        u = (double)(n - 1);
-    int k = (int)floor(u);
-    if (k > n - 2)
-        k = n - 2;
-    i = k;
-    t = u - (double)k;
-}
-
-__device__ __forceinline__ void field_at(const FieldMap &m, double x, double y, double z,
-                                         double (&B)[3])
-{
-    int i, j, k;
-    double tu, tv, tw;
-    field_cell((x - m.x0) / m.dx, m.nx, i, tu);
-    field_cell((y - m.y0) / m.dy, m.ny, j, tv);
-    field_cell((z - m.z0) / m.dz, m.nz, k, tw);
-    const int64_t sx = 3, sy = 3 * (int64_t)m.nx, sz = 3 * (int64_t)m.nx * m.ny;
-    const double *n000 = m.b + k * sz + j * sy + i * sx;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double c00 = lerp(n000[c], n000[sx + c], tu);
-        const double c10 = lerp(n000[sy + c], n000[sy + sx + c], tu);
-        const double c01 = lerp(n000[sz + c], n000[sz + sx + c], tu);
-        const double c11 = lerp(n000[sz + sy + c], n000[sz + sy + sx + c], tu);
-        B[c] = lerp(lerp(c00, c10, tv), lerp(c01, c11, tv), tw);
-    }
-}
-
-// RK4 in the map: dx/ds = p inv, dp/ds = g (p x B(x)), inv = 1 / |p of the seed|,
-// g = (kappa q) inv; every stage reads B at its own position (x, x + h/2 v1,
-// x + h/2 v2, x + h v3); cross product (p_y B_z - p_z B_y, p_z B_x - p_x B_z,
-// p_x B_y - p_y B_x); y <- y + h/6 (((k1 + 2 k2) + 2 k3) + k4).
-__device__ __forceinline__ void field_force(const FieldMap &m, double g, const double (&x)[3],
-                                            const double (&p)[3], double (&f)[3])
-{
-    double B[3];
-    field_at(m, x[0], x[1], x[2], B);
-    f[0] = g * (p[1] * B[2] - p[2] * B[1]);
-    f[1] = g * (p[2] * B[0] - p[0] * B[2]);
-    f[2] = g * (p[0] * B[1] - p[1] * B[0]);
-}
-
-__device__ __forceinline__ void rk4_field_step(const FieldMap &m, double inv, double g, double h,
-                                               double (&x)[3], double (&p)[3])
-{
-    const double hh = 0.5 * h, h6 = h / 6.0;
-    double v1[3], f1[3], v2[3], f2[3], v3[3], f3[3], v4[3], f4[3], xs[3], ps[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        v1[c] = p[c] * inv;
-    field_force(m, g, x, p, f1);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        xs[c] = x[c] + hh * v1[c];
-        ps[c] = p[c] + hh * f1[c];
-        v2[c] = ps[c] * inv;
-    }
-    field_force(m, g, xs, ps, f2);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        xs[c] = x[c] + hh * v2[c];
-        ps[c] = p[c] + hh * f2[c];
-        v3[c] = ps[c] * inv;
-    }
-    field_force(m, g, xs, ps, f3);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        xs[c] = x[c] + h * v3[c];
-        ps[c] = p[c] + h * f3[c];
-        v4[c] = ps[c] * inv;
-    }
-    field_force(m, g, xs, ps, f4);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        x[c] = x[c] + h6 * (((v1[c] + 2.0 * v2[c]) + 2.0 * v3[c]) + v4[c]);
-        p[c] = p[c] + h6 * (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]);
-    }
-}
-
 // ------------------------------------------------------------------ wire frames
 // The distance of a point to a wire is the length of its offset from the wire
 // projected on the plane normal to the unit direction n; (e1, e2) spans that plane
