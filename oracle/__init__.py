@@ -87,6 +87,9 @@ def _bind(lib):
     lib.oracle_exclude_hits.restype = ctypes.c_int32
     lib.oracle_exclude_hits.argtypes = [ctypes.c_int32, _i32, _d, _d, ctypes.POINTER(ctypes.c_uint8),
                                         _i32, _d, _d, _i32, _i32]
+    lib.oracle_self_refine.restype = ctypes.c_int32
+    lib.oracle_self_refine.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _u8,
+                                       ctypes.c_double, _u8]
     lib.oracle_field_at.restype = None
     lib.oracle_field_at.argtypes = [_d, _i32, _d, _d, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, _d]
@@ -310,6 +313,20 @@ class Oracle:
                                          _p(o2, _i32), _p(d2), _p(e2), _p(wm, _i32), _p(hm, _i32))
         n_h = int(o2[n])
         return o2[:n + 1].copy(), d2[:n_h].copy(), e2[:n].copy(), wm[:n].copy(), hm[:n_h].copy()
+
+    def self_refine(self, seed_fit, cfg, K, wire_ends, offsets, drift, mask_in, eta):
+        """Classified hits after the self-refining at the fitted seed: (mask, n)."""
+        ends = _f64(wire_ends).reshape(-1, 6)
+        drift = _f64(drift)
+        m_in = np.ascontiguousarray(mask_in, dtype=np.uint8)
+        out = np.zeros(max(drift.size, 1), dtype=np.uint8)
+        if m_in.size == 0:
+            m_in = np.zeros(1, np.uint8)
+        n = self.lib.oracle_self_refine(_p(_f64(seed_fit)), _p(_f64(cfg)), K, _p(ends),
+                                        ends.shape[0], _p(_i32a(offsets), _i32),
+                                        _p(drift if drift.size else np.zeros(1)), _p(m_in, _u8),
+                                        float(eta), _p(out, _u8))
+        return out[:drift.size].copy(), int(n)
 
     def field_at(self, fmap, x, y, z):
         """B (tesla) of a field map (b [nz, ny, nx, 3], origin [3], step [3]) at a point."""

@@ -1135,6 +1135,68 @@ int32_t oracle_exclude_hits(int32_t n_wires, const int32_t *offsets, const doubl
     return nw;
 }
 
+/* Self-refining of a stage's classified hits (Sec. 3.1). The paper re-fits the best
+ * complete set with the deterministic annealing filter, drops the hits that the fit
+ * weights down, and on wires left with hits none of which is classified re-examines
+ * those hits against the fitted track with a second cutoff eta. Without that filter
+ * the fitted track is the track of seed_fit (the stage's chosen seed after a
+ * Levenberg-Marquardt minimisation of Eq. 1), and with D the wire's DCA to it:
+ *   (1) a hit classified in mask_in (bit 0) stays classified iff |D - r_j| < lambda;
+ *   (2) on a wire where no hit stays classified, the hit with the smallest |D - r_j|
+ *       (lowest index on ties) is classified iff that residual is below eta.
+ * mask_out[j] = 1 for a classified hit, else 0 (mask_out may be mask_in). A seed
+ * with a NaN component (no fit) keeps bit 0 of mask_in. Returns the number of hits
+ * classified. */
+int32_t oracle_self_refine(const double seed_fit[6], const double cfg[4], int32_t K,
+                           const double *wire_ends, int32_t n_wires, const int32_t *offsets,
+                           const double *drift, const uint8_t *mask_in, double eta,
+                           uint8_t *mask_out)
+{
+    int fitted = 1;
+    for (int c = 0; c < 6; ++c)
+        if (isnan(seed_fit[c]))
+            fitted = 0;
+    int32_t n_cls = 0;
+    if (!fitted) {
+        for (int32_t j = offsets[0]; j < offsets[n_wires]; ++j) {
+            mask_out[j] = mask_in[j] & 1;
+            n_cls += mask_out[j];
+        }
+        return n_cls;
+    }
+    double *pts = (double *)malloc(sizeof(double) * 3 * (size_t)(K + 1));
+    oracle_track(seed_fit, cfg[0], cfg[1], cfg[2], K, pts);
+    for (int32_t i = 0; i < n_wires; ++i) {
+        double frame[8];
+        oracle_wire_frame(wire_ends + 6 * i, frame);
+        const double D = sqrt(oracle_dca2(pts, K + 1, frame, NULL));
+        int32_t kept = 0;
+        for (int32_t j = offsets[i]; j < offsets[i + 1]; ++j) {
+            const uint8_t was = mask_in[j] & 1;
+            mask_out[j] = (was && fabs(D - drift[j]) < cfg[3]) ? 1 : 0;
+            kept += mask_out[j];
+        }
+        if (kept == 0) {
+            int32_t jb = -1;
+            double eb = INFINITY;
+            for (int32_t j = offsets[i]; j < offsets[i + 1]; ++j) {
+                const double e = fabs(D - drift[j]);
+                if (e < eb) {
+                    eb = e;
+                    jb = j;
+                }
+            }
+            if (jb >= 0 && eb < eta) {
+                mask_out[jb] = 1;
+                kept = 1;
+            }
+        }
+        n_cls += kept;
+    }
+    free(pts);
+    return n_cls;
+}
+
 /* ------------------------------------------------------------ field map (Sec. 2.2.1)
  * The paper extrapolates tracks through the solenoid's field map. Here the map is a
  * regular grid of B (tesla) at nodes (x0 + i dx, y0 + j dy, z0 + k dz), i < nx, j < ny,

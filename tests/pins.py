@@ -685,7 +685,57 @@ def pin_exclude_hits(o):
         assert wm.tolist() == wires and o2[-1] == len(keep), trial
 
 
-ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_exclude_hits])
+def pin_self_refine_hand(o):
+    """With no field the track of a seed at (0, -50, 0) moving along +y is the y axis
+    through the origin, so a wire parallel to z through (X, 0) has D = X exactly up to
+    rounding. Residuals are then set by hand (lambda 0.8, eta 0.3), each far from a cutoff:
+    a kept hit; a removed hit with a re-admitted neighbour; an unclassified wire admitted
+    and one left; the closer of two hits admitted; a kept hit that is not swapped for a
+    closer one; a removed hit with nothing to re-admit; a borderline-only bit ignored;
+    two hits at the same residual."""
+    cfg = np.array([0.0, -1.0, 2.0, 0.8])
+    seed = np.array([0.0, -50.0, 0.0, 0.0, 100.0, 0.0])
+    X = [10.0, 20.0, 30.0, 40.0, 50.0, 60.0, 70.0, 80.0, 90.0, 100.0]
+    ends = np.array([[x, 0.0, -750.0, x, 0.0, 750.0] for x in X])
+    hits = [[(9.5, 1)],                         # |e| 0.5 < lambda: kept
+            [(21.0, 1), (19.8, 0)],             # 1.0 removed; 0.2 < eta re-admitted
+            [(29.75, 0)],                       # 0.25 < eta: admitted
+            [(40.35, 0)],                       # 0.35 >= eta: left out
+            [(50.2, 0), (49.9, 0)],             # the closer (0.1) admitted
+            [(59.9, 0), (59.5, 1)],             # 0.5 kept; 0.1 not added
+            [(71.2, 1)],                        # 1.2 removed, nothing below eta
+            [(80.9, 1), (80.25, 0)],            # 0.9 removed; 0.25 re-admitted
+            [(90.1, 2)],                        # bit 1 only: unclassified; 0.1 admitted
+            [(100.2, 0), (100.2, 0)]]           # a tie: the first admitted
+    off = np.concatenate([[0], np.cumsum([len(h) for h in hits])]).astype(np.int32)
+    drift = np.array([r for h in hits for r, _ in h])
+    m_in = np.array([m for h in hits for _, m in h], np.uint8)
+    want = [1, 0, 1, 1, 0, 0, 1, 0, 1, 0, 0, 1, 1, 1, 0]
+    out, n = o.self_refine(seed, cfg, 50, ends, off, drift, m_in, 0.3)
+    assert out.tolist() == want and n == sum(want)
+    same, _ = o.self_refine(seed, cfg, 50, ends, off, drift, m_in, 0.0)
+    assert same.tolist() == [1, 0, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0]
+    nan = seed.copy()
+    nan[4] = np.nan                             # no fit: the classified bits stay
+    keep, n = o.self_refine(nan, cfg, 50, ends, off, drift, m_in, 0.3)
+    assert keep.tolist() == (m_in & 1).tolist() and n == int((m_in & 1).sum())
+
+
+def pin_self_refine_at_scan_seed(o):
+    """At the seed the hits were classified with, the self-refining with eta = 0 keeps
+    exactly the classified hits (every one is below lambda there, and eta admits none)."""
+    ev = synth.event_mix(3)
+    cfg = [ev.bz, ev.charge, 2.0, 0.8]
+    s = ev.ref_states[0].copy()
+    s[3:] *= 1.002
+    mask, _, _ = o.classify(s, cfg, 800, ev.wire_ends, ev.wire_offsets, ev.drift)
+    out, n = o.self_refine(s, cfg, 800, ev.wire_ends, ev.wire_offsets, ev.drift, mask, 0.0)
+    assert (mask & 1).any() and np.array_equal(out, mask & 1) and n == int((mask & 1).sum())
+
+
+ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_exclude_hits,
+                   pin_self_refine_hand])
+ALL_EVENT.append(pin_self_refine_at_scan_seed)
 
 
 # ------------------------------------------------------------------ field map

@@ -70,6 +70,12 @@ MUTANTS = {
     "field_cross_sign": ("    f[1] = g * (p[2] * B[0] - p[0] * B[2]);", "    f[1] = g * (p[0] * B[2] - p[2] * B[0]);"),
     "field_lerp_reversed": ("static double lerp(double a, double b, double t) { return fma(t, b - a, a); }", "static double lerp(double a, double b, double t) { return fma(t, a - b, b); }"),
     "field_no_clamp": ("    if (u > (double)(n - 1))\n        u = (double)(n - 1);", "    if (u > (double)(n + 5))\n        u = (double)(n - 1);"),
+    "refine_keep_uses_eta": ("            mask_out[j] = (was && fabs(D - drift[j]) < cfg[3]) ? 1 : 0;", "            mask_out[j] = (was && fabs(D - drift[j]) < eta) ? 1 : 0;"),
+    "refine_keeps_without_test": ("            mask_out[j] = (was && fabs(D - drift[j]) < cfg[3]) ? 1 : 0;", "            mask_out[j] = was ? 1 : 0;"),
+    "refine_readmit_uses_lambda": ("            if (jb >= 0 && eb < eta) {", "            if (jb >= 0 && eb < cfg[3]) {"),
+    "refine_readmit_every_wire": ("        if (kept == 0) {\n            int32_t jb = -1;", "        if (1) {\n            int32_t jb = -1;"),
+    "refine_bit1_counts": ("            const uint8_t was = mask_in[j] & 1;", "            const uint8_t was = mask_in[j] != 0;"),
+    "refine_readmit_last_tie": ("                if (e < eb) {\n                    eb = e;\n                    jb = j;\n                }\n            }\n            if (jb >= 0 && eb < eta)", "                if (e <= eb) {\n                    eb = e;\n                    jb = j;\n                }\n            }\n            if (jb >= 0 && eb < eta)"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
