@@ -245,14 +245,17 @@ def bench_halves(events, sc, n_ref: int = 10, n_iter: int = 2, n_fine=(4, 8, 8, 
             "classification": quality.classification(run.best_complete_masks(), events)}
 
 
-def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int = 3):
+def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int = 3,
+                 fit_iters: int = 0, eta: float = 0.3):
     """The stage loop: every event reconstructed turn by turn from its last turn, the
     hits of each stage left out of the next, each next stage's (z, p_z) from the
     backward extrapolation of the previous stage's seed (eager runs, device-synchronised
-    wall time)."""
+    wall time). With fit_iters > 0 each stage's seed is refined by Levenberg-Marquardt
+    and its hits self-refined (lambda at the fitted track, eta re-admission)."""
     import torch
     from paper_1911_09340_amd import quality, stages
-    run = stages.StageRunner(events, sc, max_stages=max_stages, min_wires=min_wires)
+    run = stages.StageRunner(events, sc, max_stages=max_stages, min_wires=min_wires,
+                             fit_iters=fit_iters, eta=eta)
     run.run()
     torch.cuda.synchronize()
     dts = []
@@ -280,7 +283,8 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
         p += ev.n_turns
     act = run.active_after.cpu().numpy()
     return {"events": len(events), "seeds_per_stage_scan": sc.n_seeds, "rescans": sc.n_refine,
-            "max_stages": max_stages, "min_wires": min_wires,
+            "max_stages": max_stages, "min_wires": min_wires, "fit_iters": fit_iters,
+            "eta_mm": eta if fit_iters > 0 else None,
             "seconds_per_run": dt, "events_per_s": len(events) / dt,
             "events_active_after_stage": [int(a.sum()) for a in act],
             "classification_all_turns": quality.classification(masks, events),
@@ -576,12 +580,15 @@ def main():
     if batch_events and args.stages:
         log("stage loop: %d events, up to 5 stages from the last turn back ..." % len(batch_events))
         out["stages"] = bench_stages(batch_events, synth.C2)
-        st = out["stages"]
-        log("  %.1f events/s; efficiency %.3f purity %.3f over all turns; by turns: %s"
-            % (st["events_per_s"], st["classification_all_turns"]["efficiency_mean"],
-               st["classification_all_turns"]["purity_mean"],
-               ", ".join("%s: %.2f/%s" % (k, v[0], "-" if v[1] is None else "%.2f" % v[1])
-                         for k, v in st["efficiency_purity_by_turns"].items())))
+        log("stage loop with self-refining (8 LM iterations, eta 0.3 mm) ...")
+        out["stages_self_refined"] = bench_stages(batch_events, synth.C2, fit_iters=8)
+        for key in ("stages", "stages_self_refined"):
+            st = out[key]
+            log("  %s: %.1f events/s; efficiency %.3f purity %.3f over all turns; by turns: %s"
+                % (key, st["events_per_s"], st["classification_all_turns"]["efficiency_mean"],
+                   st["classification_all_turns"]["purity_mean"],
+                   ", ".join("%s: %.2f/%s" % (k, v[0], "-" if v[1] is None else "%.2f" % v[1])
+                             for k, v in st["efficiency_purity_by_turns"].items())))
     if grad_events:
         from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))

@@ -377,7 +377,25 @@ int comet_merge_halves(const double *rss_a, const int32_t *veto_a, const double 
  *
  * comet_stage_update: active[e] stays 1 only if best[e] >= 0, stage + 1 <
  * min(n_turns[e], max_stages) and event e keeps at least min_wires wires in the CSR
- * event_wires_next (after the exclusion). */
+ * event_wires_next (after the exclusion).
+ *
+ * comet_self_refine: the self-refining of a stage's classified hits (Sec. 3.1). The
+ * paper re-fits the best complete set with a Kalman-type filter, drops hits the fit
+ * weights down, and re-examines the hits of wires left without a classified hit
+ * against the fitted track with a second cutoff eta (0.3 mm in the paper). Here the
+ * fitted track is the track of seeds6[r] (row r's fitted seed, e.g. the chosen seed
+ * after comet_lm_refine; host-side layout double[n_rows][6], device memory), extrapolated
+ * as comet_extrapolate_seeds does with cfg's field, step and n_steps (<= 2400). For
+ * every wire of event row_event[r] (CSR as in comet_batch_scan), with D its DCA to
+ * that track:
+ *   - a hit with bit 0 set in mask_in[r] stays classified iff |D - r_j| < lambda;
+ *   - on a wire where none stays, the hit with the smallest |D - r_j| (first on
+ *     ties) is classified iff that residual is below eta.
+ * mask_out[r][j - first hit of the event] = 1 for a classified hit, else 0; masks are
+ * uint8 [n_rows][mask_stride] and hits past mask_stride are left alone; mask_out may
+ * equal mask_in. A seed with a NaN component keeps bit 0 of mask_in. A row whose
+ * row_event is outside [0, n_events) is skipped. eta must be finite and >= 0
+ * (0: no re-admission). One block per row; no allocation. */
 int comet_backward_seeds(const double *seeds6, int32_t n, const comet_config *cfg, double radius,
                          int32_t max_steps, double *out6, int32_t *steps, void *stream);
 int comet_stage_grids(const double *transverse6, const double *ext6, int32_t n,
@@ -393,6 +411,12 @@ int comet_stage_record(const uint8_t *hit_mask, int64_t mask_stride, int32_t n_e
                        const int32_t *event_wires, const int32_t *wire_offsets,
                        const int32_t *hit_ids, const int32_t *active, int32_t stage,
                        int32_t *stage_of_hit, uint8_t *exclude, void *stream);
+int comet_self_refine(const double *seeds6, int32_t n_rows, const int32_t *row_event,
+                      const comet_config *cfg, const double *wire_ends, int32_t n_wires,
+                      const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                      const int32_t *event_wires, int32_t n_events, double eta,
+                      const uint8_t *mask_in, uint8_t *mask_out, int64_t mask_stride,
+                      void *stream);
 int comet_stage_update(int32_t *active, int32_t n_events, const int64_t *best,
                        const int32_t *event_wires_next, const int32_t *n_turns, int32_t stage,
                        int32_t max_stages, int32_t min_wires, void *stream);

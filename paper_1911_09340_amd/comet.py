@@ -422,6 +422,9 @@ def _bind_batch(lib):
     lib.comet_stage_record.restype = ctypes.c_int
     lib.comet_stage_update.argtypes = [_vp, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _vp]
     lib.comet_stage_update.restype = ctypes.c_int
+    lib.comet_self_refine.argtypes = [_vp, _i32, _vp, ctypes.POINTER(Config), _vp, _i32, _vp,
+                                      _vp, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _i64, _vp]
+    lib.comet_self_refine.restype = ctypes.c_int
     lib._batch_bound = True
     return lib
 
@@ -633,6 +636,26 @@ def stage_record(hit_mask: torch.Tensor, packed, active: torch.Tensor, stage: in
         _ptr(active, torch.int32, "active", (n_e,)), int(stage),
         _ptr(stage_of_hit, torch.int32, "stage_of_hit"),
         _ptr(exclude, torch.uint8, "exclude", (n_h,)), _stream()), "comet_stage_record")
+
+
+def self_refine(seeds: torch.Tensor, row_event: torch.Tensor, cfg: Config, packed, eta: float,
+                mask_in: torch.Tensor, mask_out: torch.Tensor) -> None:
+    """comet_self_refine: re-classify row r's hits at the fitted seed seeds[r] (double
+    [n_rows, 6]) with lambda for the classified hits and eta for wires left without one."""
+    lib = _bind_batch(load())
+    n_r, stride = int(mask_in.shape[0]), int(mask_in.shape[1])
+    n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
+    n_e = int(packed.event_wires.shape[0]) - 1
+    _check(lib.comet_self_refine(
+        _ptr(seeds, torch.float64, "seeds", (n_r, 6)), n_r,
+        _ptr(row_event, torch.int32, "row_event", (n_r,)), ctypes.byref(cfg),
+        _ptr(packed.wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(packed.drift, torch.float64, "drift", (n_h,)), n_h,
+        _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e, float(eta),
+        _ptr(mask_in, torch.uint8, "mask_in", (n_r, stride)),
+        _ptr(mask_out, torch.uint8, "mask_out", (n_r, stride)), stride, _stream()),
+        "comet_self_refine")
 
 
 def stage_update(active: torch.Tensor, best: torch.Tensor, event_wires_next: torch.Tensor,

@@ -248,6 +248,95 @@ __global__ __launch_bounds__(256) void stage_update_kernel(
     active[e] = active[e] != 0 && best[e] >= 0 && stage + 1 < stages && wires >= min_wires;
 }
 
+// Self-refining of a stage's classified hits (Sec. 3.1), one block per row: the row's
+// fitted seed is extrapolated into LDS (thread 0, the RK4 of comet_extrapolate_seeds);
+// then one thread per wire of the row's event takes the wire's DCA D to that track,
+// keeps a classified hit only while |D - r_j| < lambda, and on a wire left with no
+// classified hit classifies the closest hit (first on ties) when its residual is below
+// eta. A seed with a NaN component keeps bit 0 of the input mask. Each thread reads
+// and writes only its own wire's hits, so mask_out may be mask_in.
+constexpr int kRefineThreads = 256;
+
+__global__ __launch_bounds__(kRefineThreads) void self_refine_kernel(
+    const double *__restrict__ seeds6, const int32_t *__restrict__ row_event, int n_events,
+    double bz, double charge, double h, int K, double lambda, double eta,
+    const double *__restrict__ ends, const int32_t *__restrict__ offsets,
+    const double *__restrict__ drift, const int32_t *__restrict__ ev_wires,
+    const uint8_t *mask_in, uint8_t *mask_out, int64_t mask_stride)
+{
+    extern __shared__ double pts[];  // [3][K + 1]
+    const int r = blockIdx.x;
+    const int e = row_event[r];
+    if (e < 0 || e >= n_events)
+        return;
+    const int P = K + 1;
+    const int w0 = ev_wires[e], w1 = ev_wires[e + 1];
+    const int h0 = offsets[w0];
+    const double *sd = seeds6 + 6 * (int64_t)r;
+    bool fitted = true;
+    for (int c = 0; c < 6; ++c)
+        fitted = fitted && !isnan(sd[c]);
+    if (fitted && threadIdx.x == 0) {
+        double x = sd[0], y = sd[1], z = sd[2], px = sd[3], py = sd[4];
+        const StepConsts kc = step_consts(px, py, sd[5], bz, charge, h);
+        for (int k = 0; k < K; ++k) {
+            pts[k] = x;
+            pts[P + k] = y;
+            pts[2 * P + k] = z;
+            rk4_step(kc, x, y, z, px, py);
+        }
+        pts[K] = x;
+        pts[P + K] = y;
+        pts[2 * P + K] = z;
+    }
+    __syncthreads();
+    const uint8_t *mi = mask_in + (int64_t)r * mask_stride - h0;
+    uint8_t *mout = mask_out + (int64_t)r * mask_stride - h0;
+    const int64_t j_end = (int64_t)h0 + mask_stride;  // hits past the row's stride are left alone
+    for (int wi = w0 + threadIdx.x; wi < w1; wi += kRefineThreads) {
+        const int j0 = offsets[wi];
+        const int j1 = (int)min((int64_t)offsets[wi + 1], j_end);
+        if (!fitted) {
+            for (int j = j0; j < j1; ++j)
+                mout[j] = mi[j] & 1;
+            continue;
+        }
+        double f[8];
+        wire_frame(ends + 6 * (int64_t)wi, f);
+        double qb = INFINITY;
+        int kb = 0;
+        for (int k = 0; k < P; ++k) {
+            double xi, et;
+            project(f, pts[k], pts[P + k], pts[2 * P + k], xi, et);
+            const double q = fma(xi, xi, et * et);
+            if (q < qb) {
+                qb = q;
+                kb = k;
+            }
+        }
+        const double D = sqrt(refine_dca2(pts, pts + P, pts + 2 * P, 1, P, f, kb, qb));
+        int kept = 0;
+        for (int j = j0; j < j1; ++j) {
+            const bool keep = (mi[j] & 1) && fabs(D - drift[j]) < lambda;
+            mout[j] = keep ? 1 : 0;
+            kept += keep;
+        }
+        if (kept == 0) {
+            int jb = -1;
+            double eb = INFINITY;
+            for (int j = j0; j < j1; ++j) {
+                const double res = fabs(D - drift[j]);
+                if (res < eb) {
+                    eb = res;
+                    jb = j;
+                }
+            }
+            if (jb >= 0 && eb < eta)
+                mout[jb] = 1;
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -357,6 +446,37 @@ int comet_stage_record(const uint8_t *hit_mask, int64_t mask_stride, int32_t n_e
                        (hipStream_t)stream, hit_mask, mask_stride, event_wires, wire_offsets,
                        hit_ids, active, stage, stage_of_hit, exclude);
     return launched("stage_record_kernel");
+}
+
+int comet_self_refine(const double *seeds6, int32_t n_rows, const int32_t *row_event,
+                      const comet_config *cfg, const double *wire_ends, int32_t n_wires,
+                      const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                      const int32_t *event_wires, int32_t n_events, double eta,
+                      const uint8_t *mask_in, uint8_t *mask_out, int64_t mask_stride,
+                      void *stream)
+{
+    clear_error();
+    if (!seeds6 || !row_event || !wire_ends || !wire_offsets || !drift || !event_wires ||
+        !mask_in || !mask_out)
+        return fail(COMET_EINVAL, "comet_self_refine: NULL pointer");
+    if (n_rows < 1 || n_events < 1 || n_wires < 0 || n_hits < 0 || mask_stride < 1)
+        return fail(COMET_EINVAL, "comet_self_refine: bad sizes");
+    if (!(eta >= 0.0) || !isfinite(eta))
+        return fail(COMET_EINVAL, "comet_self_refine: eta must be finite and >= 0");
+    int st = check_config(cfg);
+    if (st)
+        return st;
+    if (cfg->n_steps > 2400)
+        return fail(COMET_EUNSUPPORTED, "comet_self_refine: n_steps %d > 2400", cfg->n_steps);
+    st = check_device();
+    if (st)
+        return st;
+    const size_t lds = sizeof(double) * 3 * (size_t)(cfg->n_steps + 1);
+    hipLaunchKernelGGL(self_refine_kernel, dim3(n_rows), dim3(kRefineThreads), lds,
+                       (hipStream_t)stream, seeds6, row_event, n_events, cfg->bz_tesla,
+                       cfg->charge_e, cfg->step_mm, cfg->n_steps, cfg->lambda_mm, eta, wire_ends,
+                       wire_offsets, drift, event_wires, mask_in, mask_out, mask_stride);
+    return launched("self_refine_kernel");
 }
 
 int comet_stage_update(int32_t *active, int32_t n_events, const int64_t *best,

@@ -7,9 +7,13 @@ longitudinal seed (z, p_z) is the true one at stage 0 (the stand-in for the hodo
 prior of the last turn) and, later, the previous stage's chosen seed extrapolated
 backwards by one turn (comet_backward_seeds). Per stage, on the device:
   comet_stage_grids -> comet_batch_scan (scan, re-scans, classification)
+  [-> with fit_iters > 0: comet_lm_refine from the chosen seed (the fitted track) and
+     comet_self_refine (classified hits re-tested with lambda at the fitted track, wires
+     left without one re-admit their closest hit below eta)]
   -> comet_stage_record (the classified hits get the stage number and are marked)
   -> comet_exclude_hits (later stages scan only the hits left)
-  -> comet_backward_seeds -> comet_stage_update (stop when fewer than min_wires wires
+  -> comet_backward_seeds (from the fitted seed when there is a fit)
+  -> comet_stage_update (stop when fewer than min_wires wires
      remain, when max_stages tracks were found or when the event has no turn left).
 This module owns the buffers and orders the launches; no host synchronisation.
 """
@@ -47,11 +51,13 @@ class StagePacked:
 
 class StageRunner:
     def __init__(self, events, scan_cfg: synth.ScanConfig, max_stages: int = 5,
-                 min_wires: int = 30, max_back_steps: int = 4000, device="cuda"):
+                 min_wires: int = 30, max_back_steps: int = 4000, fit_iters: int = 0,
+                 eta: float = 0.3, mu0: float = 1e-3, device="cuda"):
         self.events = list(events)
         self.sc = scan_cfg
         self.max_stages, self.min_wires = int(max_stages), int(min_wires)
         self.max_back_steps = int(max_back_steps)
+        self.fit_iters, self.eta, self.mu0 = int(fit_iters), float(eta), float(mu0)
         E = self.n_events = len(self.events)
         self.cfg = scan.config_for(self.events[0], scan_cfg)
         # stage 0 reads the events as given; later stages alternate between two buffers
@@ -86,6 +92,12 @@ class StageRunner:
                                                scan_cfg.n_steps, E, device)
         self.ex_workspace = comet.exclude_workspace(E, device)
         self.active_after = torch.empty(self.max_stages, E, dtype=torch.int32, device=device)
+        # the fitted seed of every stage (the chosen seed itself without a fit)
+        self.fitted = torch.empty(self.max_stages, E, 6, **f64)
+        if self.fit_iters > 0:
+            self.fit_soa = torch.empty(6, E, **f64)
+            self.fit_rss = torch.empty(E, **f64)
+            self.lm_ws = comet.lm_workspace(E, device)
 
     def run(self) -> None:
         self.stage_of_hit.fill_(-1)
@@ -99,9 +111,19 @@ class StageRunner:
                              self.sc.n_refine, self.rss, self.best[s], self.workspace,
                              best_seed=self.seeds[s], best_rss=self.best_rss[s],
                              hit_mask=self.mask, n_borderline=self.n_border)
+            if self.fit_iters > 0:
+                self.fit_soa.copy_(self.seeds[s].t())
+                comet.lm_refine(self.fit_soa, self.cfg, src.wire_ends, src.wire_offsets,
+                                src.drift, self.fit_iters, self.mu0, self.fit_rss, self.lm_ws,
+                                event_wires=src.event_wires, seed_event=self.part_event)
+                self.fitted[s].copy_(self.fit_soa.t())
+                comet.self_refine(self.fitted[s], self.part_event, self.cfg, src, self.eta,
+                                  self.mask, self.mask)
+            else:
+                self.fitted[s].copy_(self.seeds[s])
             comet.stage_record(self.mask, src, self.active, s, self.stage_of_hit, self.exclude)
             comet.exclude_hits(src, self.exclude, dst, self.ex_workspace)
-            comet.backward_seeds(self.seeds[s], self.cfg, synth.SEED_RADIUS,
+            comet.backward_seeds(self.fitted[s], self.cfg, synth.SEED_RADIUS,
                                  self.max_back_steps, self.ext)
             comet.stage_update(self.active, self.best[s], dst.event_wires, self.n_turns, s,
                                self.max_stages, self.min_wires)

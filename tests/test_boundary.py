@@ -285,6 +285,20 @@ def test_stage_calls_reject(lib):
     assert lib.comet_exclude_hits(*bad, _p(0x100000), need, None) == comet.EINVAL
     assert lib.comet_stage_record(_p(), 0, 2, _p(), _p(), _p(), _p(), 0, _p(), _p(), None) == comet.EINVAL
     assert lib.comet_stage_update(_p(), 2, _p(), _p(), _p(), 0, 0, 30, None) == comet.EINVAL
+    ok = [_p(), 4, _p(), ctypes.byref(cfg), _p(), 10, _p(), _p(), 20, _p(), 4, 0.3, _p(), _p(),
+          32, None]
+    for i in (0, 2, 4, 6, 7, 9, 12, 13):
+        bad = list(ok)
+        bad[i] = None
+        assert lib.comet_self_refine(*bad) == comet.EINVAL, i
+    for i, v in ((1, 0), (10, 0), (14, 0), (11, -0.1), (11, float("nan")), (11, float("inf"))):
+        bad = list(ok)
+        bad[i] = v
+        assert lib.comet_self_refine(*bad) == comet.EINVAL, (i, v)
+    long_cfg = comet.make_config(1.0, -1.0, 1.0, 2401, 0.8)
+    bad = list(ok)
+    bad[3] = ctypes.byref(long_cfg)
+    assert lib.comet_self_refine(*bad) == comet.EUNSUPPORTED
 
 
 def test_field_call_rejects(lib):

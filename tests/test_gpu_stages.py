@@ -100,11 +100,66 @@ def test_exclude_hits_match_cpu(orc):
     assert ew[3] == ew[2]                        # the emptied event keeps no wire
 
 
+def test_self_refine_matches_cpu(orc):
+    """Fitted seeds near the truth, input masks from the CPU classification at another
+    seed and random bits; a NaN seed keeps its classified bits, a row of an event out of
+    range is left alone; in place and out of place."""
+    rng = np.random.default_rng(5)
+    evs = [synth.event_mix(i) for i in (1, 4, 6)]
+    packed = stages.StagePacked.from_events(evs)
+    cfg = comet.make_config(evs[0].bz, evs[0].charge, 2.0, 900, 0.8)
+    ocfg = [evs[0].bz, evs[0].charge, 2.0, 0.8]
+    rows, seeds, masks = [], [], []
+    stride = max(ev.n_hits for ev in evs)
+    for e, ev in enumerate(evs):
+        for t in range(ev.n_turns):
+            fit = ev.ref_states[t].copy()
+            fit[3:] *= 1.0 + rng.normal(0.0, 0.002, 3)
+            scan_seed = ev.ref_states[t].copy()
+            scan_seed[3:] *= 1.0 + rng.normal(0.0, 0.004, 3)
+            m, _, _ = orc.classify(scan_seed, ocfg, 900, ev.wire_ends, ev.wire_offsets, ev.drift)
+            for mask in (m, rng.integers(0, 4, ev.n_hits).astype(np.uint8)):
+                rows.append(e)
+                seeds.append(fit)
+                masks.append(np.pad(mask, (0, stride - ev.n_hits)))
+    seeds.append(np.full(6, np.nan))
+    rows.append(2)
+    masks.append(np.pad(rng.integers(0, 4, evs[2].n_hits).astype(np.uint8),
+                        (0, stride - evs[2].n_hits)))
+    seeds.append(evs[0].ref_states[0])
+    rows.append(-1)                                          # skipped row
+    masks.append(np.full(stride, 7, np.uint8))
+    m_in = np.stack(masks)
+    d = dict(device="cuda")
+    t_seeds = torch.as_tensor(np.stack(seeds), **d)
+    t_rows = torch.as_tensor(np.array(rows, np.int32), **d)
+    out = torch.full(m_in.shape, 9, dtype=torch.uint8, **d)
+    t_in = torch.as_tensor(m_in, **d)
+    comet.self_refine(t_seeds, t_rows, cfg, packed, 0.3, t_in, out)
+    comet.self_refine(t_seeds, t_rows, cfg, packed, 0.3, t_in, t_in)     # in place
+    torch.cuda.synchronize()
+    got, got_in = out.cpu().numpy(), t_in.cpu().numpy()
+    n_changed = 0
+    for r, e in enumerate(rows):
+        if e < 0:
+            assert (got[r] == 9).all() and (got_in[r] == 7).all()
+            continue
+        ev = evs[e]
+        want, _ = orc.self_refine(seeds[r], ocfg, 900, ev.wire_ends, ev.wire_offsets, ev.drift,
+                                  m_in[r, :ev.n_hits], 0.3)
+        assert np.array_equal(got[r, :ev.n_hits], want), r
+        assert np.array_equal(got_in[r, :ev.n_hits], want), r
+        assert (got[r, ev.n_hits:] == 9).all(), r
+        n_changed += int((want != (m_in[r, :ev.n_hits] & 1)).sum())
+    assert n_changed > 0
+
+
 def _cfg(ev, sc):
     return [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
 
 
-def _oracle_stages(orc, ev, sc, max_stages, min_wires, max_back):
+def _oracle_stages(orc, ev, sc, max_stages, min_wires, max_back, fit_iters=0, eta=0.3,
+                   mu0=1e-3):
     soh = np.full(ev.n_hits, -1, np.int32)
     off, drift, ends = ev.wire_offsets, ev.drift, ev.wire_ends
     ids = np.arange(ev.n_hits)
@@ -118,13 +173,18 @@ def _oracle_stages(orc, ev, sc, max_stages, min_wires, max_back):
         g = orc.stage_grid(ev.ref_states[t], ext, sc.half)
         r = orc.scan_partition(g, np.array(sc.n, np.int32), _cfg(ev, sc), sc.n_steps,
                                sc.n_refine, ends, off, drift)
-        cls = (r["mask"] & 1).astype(bool)
+        mask, fit = r["mask"] & 1, r["best_seed"]
+        if fit_iters > 0:
+            fit, _, _ = orc.lm_refine(fit, _cfg(ev, sc), sc.n_steps, ends, off, drift,
+                                      fit_iters, mu0)
+            mask, _ = orc.self_refine(fit, _cfg(ev, sc), sc.n_steps, ends, off, drift, mask, eta)
+        cls = mask.astype(bool)
         soh[ids[cls]] = s
         off, drift, ends, _, hm = orc.exclude_hits(off, drift, ends, cls.astype(np.uint8))
         ids = ids[hm]
-        ext, _ = orc.backward_seed(r["best_seed"], ev.bz, ev.charge, sc.step_mm,
-                                   synth.SEED_RADIUS, max_back)
-        out.append((r["best"], r["best_seed"]))
+        ext, _ = orc.backward_seed(fit, ev.bz, ev.charge, sc.step_mm, synth.SEED_RADIUS,
+                                   max_back)
+        out.append((r["best"], r["best_seed"], fit))
         active = (r["best"] >= 0 and s + 1 < min(ev.n_turns, max_stages)
                   and len(off) - 1 >= min_wires)
     return soh, out
@@ -148,9 +208,37 @@ def test_stage_loop_matches_cpu(orc):
     for e, ev in enumerate(events):
         want, per_stage = _oracle_stages(orc, ev, sc, 5, 30, 3000)
         assert np.array_equal(soh[h0:h0 + ev.n_hits], want), e
-        for s, (b, seed) in enumerate(per_stage):
+        for s, (b, seed, _) in enumerate(per_stage):
             assert best[s, e] == b, (e, s)
             assert np.array_equal(seeds[s, e], seed), (e, s)
         n_stages += len(per_stage)
         h0 += ev.n_hits
     assert n_stages > len(events)                # the loop went past the first stage
+
+
+def test_stage_loop_with_fit_matches_cpu(orc):
+    """The loop with the self-refining: every stage's chosen seed is refined by
+    Levenberg-Marquardt (the fitted track), the hits are re-tested at it with lambda and
+    eta, and the next stage starts from the fitted seed. Fitted seeds agree to the LM bar
+    (1e-7 relative); the chosen grid indices and the stage of every hit exactly."""
+    events = [synth.event_mix(i) for i in (2, 3, 5, 8)]
+    sc = synth.ScanConfig("stages", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 800, 2.0, 0.8, 1)
+    run = stages.StageRunner(events, sc, max_stages=5, min_wires=30, max_back_steps=3000,
+                             fit_iters=4, eta=0.3)
+    run.run()
+    torch.cuda.synchronize()
+    soh = run.stage_of_hit.cpu().numpy()
+    best = run.best.cpu().numpy()
+    seeds, fitted = run.seeds.cpu().numpy(), run.fitted.cpu().numpy()
+    h0, n_stages, n_moved = 0, 0, 0
+    for e, ev in enumerate(events):
+        want, per_stage = _oracle_stages(orc, ev, sc, 5, 30, 3000, fit_iters=4, eta=0.3)
+        assert np.array_equal(soh[h0:h0 + ev.n_hits], want), e
+        for s, (b, seed, fit) in enumerate(per_stage):
+            assert best[s, e] == b, (e, s)
+            np.testing.assert_allclose(seeds[s, e], seed, rtol=1e-7, atol=1e-9)
+            np.testing.assert_allclose(fitted[s, e], fit, rtol=1e-7, atol=1e-9)
+            n_moved += int(not np.array_equal(fit, seed))
+        n_stages += len(per_stage)
+        h0 += ev.n_hits
+    assert n_stages > len(events) and n_moved > 0
