@@ -87,6 +87,10 @@ def _bind(lib):
     lib.oracle_exclude_hits.restype = ctypes.c_int32
     lib.oracle_exclude_hits.argtypes = [ctypes.c_int32, _i32, _d, _d, ctypes.POINTER(ctypes.c_uint8),
                                         _i32, _d, _d, _i32, _i32]
+    lib.oracle_rss_jacobian_field.restype = ctypes.c_double
+    lib.oracle_rss_jacobian_field.argtypes = [_d, _d, _i32, _d, _d, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                              _d, ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _d]
     lib.oracle_self_refine.restype = ctypes.c_int32
     lib.oracle_self_refine.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _u8,
                                        ctypes.c_double, _u8]
@@ -235,6 +239,22 @@ class Oracle:
         rss = self.lib.oracle_rss_jacobian(_p(_f64(seed)), _p(_f64(cfg)), K, _p(ends), n_w,
                                            _p(_i32a(offsets), _i32), _p(_f64(drift)), _p(D),
                                            _p(J), _p(e), _p(act, _u8), _p(grad))
+        return {"rss": rss, "grad": grad, "D": D, "J": J, "resid": e, "active": act.astype(bool)}
+
+    def rss_jacobian_field(self, seed, fmap, charge, h, K, lam, wire_ends, offsets, drift):
+        """rss_jacobian for the track in a field map (b [nz, ny, nx, 3], origin, step)."""
+        b, origin, step = fmap
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        n = np.array([b.shape[2], b.shape[1], b.shape[0]], np.int32)
+        ends = _f64(wire_ends).reshape(-1, 6)
+        n_w = ends.shape[0]
+        D, J, e = np.empty(n_w), np.empty((n_w, 6)), np.empty(n_w)
+        act = np.zeros(n_w, dtype=np.uint8)
+        grad = np.empty(6)
+        rss = self.lib.oracle_rss_jacobian_field(
+            _p(_f64(seed)), _p(b), _p(n, _i32), _p(_f64(origin)), _p(_f64(step)), float(charge),
+            float(h), int(K), float(lam), _p(ends), n_w, _p(_i32a(offsets), _i32),
+            _p(_f64(drift)), _p(D), _p(J), _p(e), _p(act, _u8), _p(grad))
         return {"rss": rss, "grad": grad, "D": D, "J": J, "resid": e, "active": act.astype(bool)}
 
     def lm_refine(self, seed, cfg, K, wire_ends, offsets, drift, n_iter, mu0):

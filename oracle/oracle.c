@@ -671,14 +671,11 @@ static dual dual_dca2(const dual *pts, int32_t P, const double frame[8])
  * e_i = D_i - r_j of the wire's closest hit (NaN without hits) and whether it is
  * active (|e_i| < lambda). Returns the RSS of Eq. 1 and writes its gradient
  * sum over active wires of 2 e_i J_i to grad[6]. Any output pointer may be NULL. */
-double oracle_rss_jacobian(const double seed[6], const double cfg[4], int32_t K,
-                           const double *wire_ends, int32_t n_wires, const int32_t *offsets,
-                           const double *drift, double *D, double *J, double *resid,
-                           uint8_t *active, double grad[6])
+static double rss_of_dual_track(const dual *pts, int32_t K, double lambda,
+                                const double *wire_ends, int32_t n_wires,
+                                const int32_t *offsets, const double *drift, double *D,
+                                double *J, double *resid, uint8_t *active, double grad[6])
 {
-    dual *pts = (dual *)malloc(sizeof(dual) * 3 * (size_t)(K + 1));
-    dual_track(seed, cfg[0], cfg[1], cfg[2], K, pts);
-    double lambda = cfg[3];
     double rss = 0.0;
     double g[6] = {0, 0, 0, 0, 0, 0};
     for (int32_t i = 0; i < n_wires; ++i) {
@@ -712,6 +709,18 @@ double oracle_rss_jacobian(const double seed[6], const double cfg[4], int32_t K,
     if (grad)
         for (int c = 0; c < 6; ++c)
             grad[c] = g[c];
+    return rss;
+}
+
+double oracle_rss_jacobian(const double seed[6], const double cfg[4], int32_t K,
+                           const double *wire_ends, int32_t n_wires, const int32_t *offsets,
+                           const double *drift, double *D, double *J, double *resid,
+                           uint8_t *active, double grad[6])
+{
+    dual *pts = (dual *)malloc(sizeof(dual) * 3 * (size_t)(K + 1));
+    dual_track(seed, cfg[0], cfg[1], cfg[2], K, pts);
+    double rss = rss_of_dual_track(pts, K, cfg[3], wire_ends, n_wires, offsets, drift, D, J,
+                                   resid, active, grad);
     free(pts);
     return rss;
 }
@@ -1310,4 +1319,115 @@ void oracle_track_field(const double seed[6], const double *b, const int32_t n[3
     }
     for (int c = 0; c < 3; ++c)
         pts[3 * K + c] = x[c];
+}
+
+/* Derivatives in a field map: the same per-wire outputs as oracle_rss_jacobian for the
+ * track of oracle_track_field, in dual numbers. B(x) enters the chain through the
+ * trilinear interpolation: the fractions t of a cell are duals, so each stage's force
+ * carries dB/dx (piecewise constant in each cell's t, as the interpolation is); a
+ * coordinate clamped to the grid is a constant there, as the plain function's value is.
+ * The values are computed with the operations of oracle_track_field. */
+static dual dual_lerp(dual a, dual b, dual t) { return dfma(t, dsub(b, a), a); }
+
+static void dual_cell(dual u, int32_t n, int32_t *i, dual *t)
+{
+    if (!(u.v > 0.0))
+        u = dc(0.0);
+    if (u.v > (double)(n - 1))
+        u = dc((double)(n - 1));
+    int32_t k = (int32_t)floor(u.v);
+    if (k > n - 2)
+        k = n - 2;
+    *i = k;
+    *t = dsub(u, dc((double)k));
+}
+
+static void dual_field_at(const oracle_field *f, const dual x[3], dual B[3])
+{
+    int32_t i, j, k;
+    dual tu, tv, tw;
+    dual_cell(ddiv(dsub(x[0], dc(f->x0)), dc(f->dx)), f->nx, &i, &tu);
+    dual_cell(ddiv(dsub(x[1], dc(f->y0)), dc(f->dy)), f->ny, &j, &tv);
+    dual_cell(ddiv(dsub(x[2], dc(f->z0)), dc(f->dz)), f->nz, &k, &tw);
+    for (int c = 0; c < 3; ++c) {
+#define NODE(a, b2, c2) dc(f->b[((((int64_t)(k + (c2))) * f->ny + (j + (b2))) * f->nx + (i + (a))) * 3 + c])
+        const dual c00 = dual_lerp(NODE(0, 0, 0), NODE(1, 0, 0), tu);
+        const dual c10 = dual_lerp(NODE(0, 1, 0), NODE(1, 1, 0), tu);
+        const dual c01 = dual_lerp(NODE(0, 0, 1), NODE(1, 0, 1), tu);
+        const dual c11 = dual_lerp(NODE(0, 1, 1), NODE(1, 1, 1), tu);
+#undef NODE
+        B[c] = dual_lerp(dual_lerp(c00, c10, tv), dual_lerp(c01, c11, tv), tw);
+    }
+}
+
+static void dual_field_force(const oracle_field *fm, dual g, const dual x[3], const dual p[3],
+                             dual f[3])
+{
+    dual B[3];
+    dual_field_at(fm, x, B);
+    f[0] = dmul(g, dsub(dmul(p[1], B[2]), dmul(p[2], B[1])));
+    f[1] = dmul(g, dsub(dmul(p[2], B[0]), dmul(p[0], B[2])));
+    f[2] = dmul(g, dsub(dmul(p[0], B[1]), dmul(p[1], B[0])));
+}
+
+static void dual_track_field(const double seed[6], const oracle_field *fm, double charge,
+                             double h, int32_t K, dual *pts)
+{
+    dual x[3] = {dvar(seed[0], 0), dvar(seed[1], 1), dvar(seed[2], 2)};
+    dual p[3] = {dvar(seed[3], 3), dvar(seed[4], 4), dvar(seed[5], 5)};
+    const dual p0 = dsqrt(dadd(dadd(dmul(p[0], p[0]), dmul(p[1], p[1])), dmul(p[2], p[2])));
+    const dual inv = ddiv(dc(1.0), p0);
+    const dual g = dmul(dc(ORACLE_KAPPA * charge), inv);
+    const dual hh = dc(0.5 * h), hd = dc(h), h6 = dc(h / 6.0), two = dc(2.0);
+    for (int32_t j = 0; j < K; ++j) {
+        for (int c = 0; c < 3; ++c)
+            pts[3 * j + c] = x[c];
+        dual v1[3], f1[3], v2[3], f2[3], v3[3], f3[3], v4[3], f4[3], xs[3], ps[3];
+        for (int c = 0; c < 3; ++c)
+            v1[c] = dmul(p[c], inv);
+        dual_field_force(fm, g, x, p, f1);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = dadd(x[c], dmul(hh, v1[c]));
+            ps[c] = dadd(p[c], dmul(hh, f1[c]));
+            v2[c] = dmul(ps[c], inv);
+        }
+        dual_field_force(fm, g, xs, ps, f2);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = dadd(x[c], dmul(hh, v2[c]));
+            ps[c] = dadd(p[c], dmul(hh, f2[c]));
+            v3[c] = dmul(ps[c], inv);
+        }
+        dual_field_force(fm, g, xs, ps, f3);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = dadd(x[c], dmul(hd, v3[c]));
+            ps[c] = dadd(p[c], dmul(hd, f3[c]));
+            v4[c] = dmul(ps[c], inv);
+        }
+        dual_field_force(fm, g, xs, ps, f4);
+        for (int c = 0; c < 3; ++c) {
+            x[c] = dadd(x[c], dmul(h6, dadd(dadd(dadd(v1[c], dmul(two, v2[c])), dmul(two, v3[c])),
+                                            v4[c])));
+            p[c] = dadd(p[c], dmul(h6, dadd(dadd(dadd(f1[c], dmul(two, f2[c])), dmul(two, f3[c])),
+                                            f4[c])));
+        }
+    }
+    for (int c = 0; c < 3; ++c)
+        pts[3 * K + c] = x[c];
+}
+
+double oracle_rss_jacobian_field(const double seed[6], const double *b, const int32_t n[3],
+                                 const double origin[3], const double step[3], double charge,
+                                 double h, int32_t K, double lambda, const double *wire_ends,
+                                 int32_t n_wires, const int32_t *offsets, const double *drift,
+                                 double *D, double *J, double *resid, uint8_t *active,
+                                 double grad[6])
+{
+    oracle_field fm = {b, n[0], n[1], n[2], origin[0], origin[1], origin[2],
+                       step[0], step[1], step[2]};
+    dual *pts = (dual *)malloc(sizeof(dual) * 3 * (size_t)(K + 1));
+    dual_track_field(seed, &fm, charge, h, K, pts);
+    double rss = rss_of_dual_track(pts, K, lambda, wire_ends, n_wires, offsets, drift, D, J,
+                                   resid, active, grad);
+    free(pts);
+    return rss;
 }

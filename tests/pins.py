@@ -734,8 +734,7 @@ def pin_self_refine_at_scan_seed(o):
 
 
 ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_exclude_hits,
-                   pin_self_refine_hand])
-ALL_EVENT.append(pin_self_refine_at_scan_seed)
+                   pin_self_refine_hand, pin_self_refine_at_scan_seed])
 
 
 # ------------------------------------------------------------------ field map
@@ -806,3 +805,71 @@ def pin_field_solenoid_rk4(o):
 
 
 ALL_SIMPLE.extend([pin_field_trilinear, pin_field_uniform_helix, pin_field_solenoid_rk4])
+
+
+def _linear_map(bz, gx, gz):
+    """A field linear in the coordinates on a 3 x 3 x 3 grid (the trilinear map is exact
+    and smooth): B_x = gx z, B_y = -gx z, B_z = bz (1 + gz x - gz y / 2)."""
+    xs, zs = np.array([-1500.0, 0.0, 1500.0]), np.array([-2000.0, 0.0, 2000.0])
+    K3, Y3, X3 = np.meshgrid(zs, xs, xs, indexing="ij")
+    b = np.stack([gx * K3, -gx * K3, bz * (1.0 + gz * X3 - 0.5 * gz * Y3)], axis=-1)
+    return b, np.array([-1500.0, -1500.0, -2000.0]), np.array([1500.0, 1500.0, 2000.0])
+
+
+def pin_field_jacobian_uniform(o):
+    """In a constant map B = (0, 0, B_z) the derivatives through the map equal those of
+    the uniform-field stepping (the tracks agree to rounding)."""
+    ev = synth.event_plain(0)
+    b = np.zeros((2, 2, 2, 3))
+    b[..., 2] = ev.bz
+    fm = (b, np.array([-2000.0, -2000.0, -2000.0]), np.array([4000.0, 4000.0, 4000.0]))
+    seed = ev.ref_states[0] * (1 + np.array([1e-3, -1e-3, 2e-3, 1e-3, -2e-3, 1e-3]))
+    u = o.rss_jacobian(seed, [ev.bz, ev.charge, 2.0, 1.0], 800, ev.wire_ends, ev.wire_offsets,
+                       ev.drift)
+    f = o.rss_jacobian_field(seed, fm, ev.charge, 2.0, 800, 1.0, ev.wire_ends, ev.wire_offsets,
+                             ev.drift)
+    assert np.array_equal(u["active"], f["active"]) and u["active"].sum() >= 10
+    assert np.max(np.abs(f["D"] - u["D"])) < 1e-9
+    assert np.max(np.abs(f["J"] - u["J"])) < 1e-9 * np.max(np.abs(u["J"]))
+    assert abs(f["rss"] - u["rss"]) < 1e-9 * u["rss"]
+
+
+def pin_field_jacobian_fd(o):
+    """In a field with gradients (so dB/dx matters: B_z changes by 0.2 % per 100 mm in x
+    and by -0.1 % in y, B_x and B_y grow with z) the dual-number rows dD_i/d(seed) and the RSS gradient
+    agree with central differences of the plain map tracking (1e-6 relative)."""
+    ev = synth.event_plain(0)
+    fm = _linear_map(ev.bz, 2e-5, 2e-5)
+    lam, K, h = 1.5, 800, 2.0
+    rng = np.random.default_rng(11)
+    tested = 0
+    for _ in range(10):
+        seed = ev.ref_states[0] * (1 + rng.normal(0, 1e-3, 6))
+        r = o.rss_jacobian_field(seed, fm, ev.charge, h, K, lam, ev.wire_ends, ev.wire_offsets,
+                                 ev.drift)
+        kink = False
+        for i in range(ev.n_wires):
+            j0, j1 = ev.wire_offsets[i], ev.wire_offsets[i + 1]
+            e = np.sort(np.abs(r["D"][i] - ev.drift[j0:j1]))
+            kink |= abs(e[0] - lam) < 2e-3 or (len(e) > 1 and e[1] - e[0] < 2e-3)
+        if kink or r["active"].sum() < 5:
+            continue
+
+        def track(s):
+            return o.track_field(s, fm, ev.charge, h, K)
+
+        def rss(s):
+            return o.rss_track(track(s), ev.wire_ends, ev.wire_offsets, ev.drift, lam)
+        fd = _fd(rss, seed)
+        assert np.max(np.abs(r["grad"] - fd)) < 1e-6 * np.max(np.abs(r["grad"])), (r["grad"], fd)
+        for i in np.nonzero(r["D"] < 9.0)[0][:6]:
+            fr = o.wire_frame(ev.wire_ends[i])
+            fdi = _fd(lambda s: np.sqrt(o.dca2(track(s), fr)[0]), seed)
+            assert np.max(np.abs(r["J"][i] - fdi)) < 1e-6 * np.max(np.abs(r["J"][i])), i
+        tested += 1
+        if tested == 2:
+            break
+    assert tested == 2, "too few kink-free test points"
+
+
+ALL_SIMPLE.extend([pin_field_jacobian_uniform, pin_field_jacobian_fd])

@@ -76,6 +76,10 @@ MUTANTS = {
     "refine_readmit_every_wire": ("        if (kept == 0) {\n            int32_t jb = -1;", "        if (1) {\n            int32_t jb = -1;"),
     "refine_bit1_counts": ("            const uint8_t was = mask_in[j] & 1;", "            const uint8_t was = mask_in[j] != 0;"),
     "refine_readmit_last_tie": ("                if (e < eb) {\n                    eb = e;\n                    jb = j;\n                }\n            }\n            if (jb >= 0 && eb < eta)", "                if (e <= eb) {\n                    eb = e;\n                    jb = j;\n                }\n            }\n            if (jb >= 0 && eb < eta)"),
+    "field_dual_no_dbdx": ("    *t = dsub(u, dc((double)k));", "    *t = dc(u.v - (double)k);"),
+    "field_dual_cross_sign": ("    f[1] = dmul(g, dsub(dmul(p[2], B[0]), dmul(p[0], B[2])));", "    f[1] = dmul(g, dsub(dmul(p[0], B[2]), dmul(p[2], B[0])));"),
+    "field_dual_stage3_uses_v1": ("            xs[c] = dadd(x[c], dmul(hh, v2[c]));", "            xs[c] = dadd(x[c], dmul(hh, v1[c]));"),
+    "field_dual_y_cell_from_x": ("    dual_cell(ddiv(dsub(x[1], dc(f->y0)), dc(f->dy)), f->ny, &j, &tv);", "    dual_cell(ddiv(dsub(x[0], dc(f->y0)), dc(f->dy)), f->ny, &j, &tv);"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
