@@ -91,6 +91,10 @@ def _bind(lib):
     lib.oracle_rss_jacobian_field.argtypes = [_d, _d, _i32, _d, _d, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                               _d, ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _d]
+    lib.oracle_lm_refine_field.restype = ctypes.c_double
+    lib.oracle_lm_refine_field.argtypes = [_d, _d, _i32, _d, _d, _d, ctypes.c_int32, _d,
+                                           ctypes.c_int32, _i32, _d, ctypes.c_int32,
+                                           ctypes.c_double, _i32]
     lib.oracle_self_refine.restype = ctypes.c_int32
     lib.oracle_self_refine.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _u8,
                                        ctypes.c_double, _u8]
@@ -256,6 +260,21 @@ class Oracle:
             float(h), int(K), float(lam), _p(ends), n_w, _p(_i32a(offsets), _i32),
             _p(_f64(drift)), _p(D), _p(J), _p(e), _p(act, _u8), _p(grad))
         return {"rss": rss, "grad": grad, "D": D, "J": J, "resid": e, "active": act.astype(bool)}
+
+    def lm_refine_field(self, seed, fmap, cfg, K, wire_ends, offsets, drift, n_iter, mu0):
+        """lm_refine with tracks in a field map (cfg = [unused, charge, h, lambda])."""
+        b, origin, step = fmap
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        n = np.array([b.shape[2], b.shape[1], b.shape[0]], np.int32)
+        s = _f64(seed).copy()
+        ends = _f64(wire_ends).reshape(-1, 6)
+        acc = np.zeros(1, dtype=np.int32)
+        rss = self.lib.oracle_lm_refine_field(_p(s), _p(b), _p(n, _i32), _p(_f64(origin)),
+                                              _p(_f64(step)), _p(_f64(cfg)), int(K), _p(ends),
+                                              ends.shape[0], _p(_i32a(offsets), _i32),
+                                              _p(_f64(drift)), int(n_iter), float(mu0),
+                                              _p(acc, _i32))
+        return s, rss, int(acc[0])
 
     def lm_refine(self, seed, cfg, K, wire_ends, offsets, drift, n_iter, mu0):
         """Levenberg-Marquardt refinement of one seed: (seed[6], rss, accepted steps)."""

@@ -794,12 +794,25 @@ static int cholesky_solve6(const double M[36], const double r[6], double x[6])
 }
 
 /* Refines seed[6] in place; returns the final RSS; *accepted counts accepted steps. */
-double oracle_lm_refine(double seed[6], const double cfg[4], int32_t K, const double *wire_ends,
-                        int32_t n_wires, const int32_t *offsets, const double *drift,
-                        int32_t n_iter, double mu0, int32_t *accepted)
+/* The problem the LM loop minimises: the RSS and normal equations at a seed. */
+typedef struct {
+    const double *cfg;
+    int32_t K;
+    const double *wire_ends;
+    int32_t n_wires;
+    const int32_t *offsets;
+    const double *drift;
+    const void *field; /* NULL: uniform field; else the map (oracle_field) */
+} lm_problem;
+
+static void lm_normal_equations(const lm_problem *pb, const double seed[6], double A[36],
+                                double b[6], double *rss);
+
+static double lm_loop(const lm_problem *pb, double seed[6], int32_t n_iter, double mu0,
+                      int32_t *accepted)
 {
     double A[36], b[6], rss;
-    normal_equations(seed, cfg, K, wire_ends, n_wires, offsets, drift, A, b, &rss);
+    lm_normal_equations(pb, seed, A, b, &rss);
     double mu = mu0;
     int32_t n_acc = 0;
     for (int32_t it = 0; it < n_iter; ++it) {
@@ -818,7 +831,7 @@ double oracle_lm_refine(double seed[6], const double cfg[4], int32_t K, const do
         for (int r = 0; r < 6; ++r)
             trial[r] = seed[r] + delta[r];
         double A2[36], b2[6], rss2;
-        normal_equations(trial, cfg, K, wire_ends, n_wires, offsets, drift, A2, b2, &rss2);
+        lm_normal_equations(pb, trial, A2, b2, &rss2);
         if (rss2 < rss) {
             for (int r = 0; r < 6; ++r) {
                 seed[r] = trial[r];
@@ -836,6 +849,14 @@ double oracle_lm_refine(double seed[6], const double cfg[4], int32_t K, const do
     if (accepted)
         *accepted = n_acc;
     return rss;
+}
+
+double oracle_lm_refine(double seed[6], const double cfg[4], int32_t K, const double *wire_ends,
+                        int32_t n_wires, const int32_t *offsets, const double *drift,
+                        int32_t n_iter, double mu0, int32_t *accepted)
+{
+    const lm_problem pb = {cfg, K, wire_ends, n_wires, offsets, drift, NULL};
+    return lm_loop(&pb, seed, n_iter, mu0, accepted);
 }
 
 /* ------------------------------------------------------------ several references
@@ -1430,4 +1451,54 @@ double oracle_rss_jacobian_field(const double seed[6], const double *b, const in
                                    resid, active, grad);
     free(pts);
     return rss;
+}
+
+/* Levenberg-Marquardt in a field map: oracle_lm_refine with the derivatives and RSS of
+ * the map's tracks (oracle_rss_jacobian_field). */
+static void lm_normal_equations(const lm_problem *pb, const double seed[6], double A[36],
+                                double b[6], double *rss)
+{
+    if (!pb->field) {
+        normal_equations(seed, pb->cfg, pb->K, pb->wire_ends, pb->n_wires, pb->offsets,
+                         pb->drift, A, b, rss);
+        return;
+    }
+    const oracle_field *f = (const oracle_field *)pb->field;
+    const int32_t n_w = pb->n_wires;
+    double *J = (double *)malloc(sizeof(double) * 6 * (size_t)(n_w > 0 ? n_w : 1));
+    double *e = (double *)malloc(sizeof(double) * (size_t)(n_w > 0 ? n_w : 1));
+    uint8_t *act = (uint8_t *)malloc((size_t)(n_w > 0 ? n_w : 1));
+    const int32_t n[3] = {f->nx, f->ny, f->nz};
+    const double origin[3] = {f->x0, f->y0, f->z0}, step[3] = {f->dx, f->dy, f->dz};
+    *rss = oracle_rss_jacobian_field(seed, f->b, n, origin, step, pb->cfg[1], pb->cfg[2], pb->K,
+                                     pb->cfg[3], pb->wire_ends, n_w, pb->offsets, pb->drift,
+                                     NULL, J, e, act, NULL);
+    for (int r = 0; r < 36; ++r)
+        A[r] = 0.0;
+    for (int r = 0; r < 6; ++r)
+        b[r] = 0.0;
+    for (int32_t i = 0; i < n_w; ++i) {
+        if (!act[i])
+            continue;
+        for (int r = 0; r < 6; ++r) {
+            b[r] += J[6 * i + r] * e[i];
+            for (int c = 0; c < 6; ++c)
+                A[6 * r + c] += J[6 * i + r] * J[6 * i + c];
+        }
+    }
+    free(J);
+    free(e);
+    free(act);
+}
+
+double oracle_lm_refine_field(double seed[6], const double *b, const int32_t n[3],
+                              const double origin[3], const double step[3], const double cfg[4],
+                              int32_t K, const double *wire_ends, int32_t n_wires,
+                              const int32_t *offsets, const double *drift, int32_t n_iter,
+                              double mu0, int32_t *accepted)
+{
+    const oracle_field fm = {b, n[0], n[1], n[2], origin[0], origin[1], origin[2],
+                             step[0], step[1], step[2]};
+    const lm_problem pb = {cfg, K, wire_ends, n_wires, offsets, drift, &fm};
+    return lm_loop(&pb, seed, n_iter, mu0, accepted);
 }

@@ -872,4 +872,52 @@ def pin_field_jacobian_fd(o):
     assert tested == 2, "too few kink-free test points"
 
 
-ALL_SIMPLE.extend([pin_field_jacobian_uniform, pin_field_jacobian_fd])
+def _field_event(o, fm, seed, charge, h, K):
+    """Wires of the plain event's chamber with sigma = 0 hits from the map track of seed:
+    every wire within 8 mm of the track gets one hit at exactly its DCA."""
+    ev = synth.event_plain(0)
+    pts = o.track_field(seed, fm, charge, h, K)
+    D = np.array([np.sqrt(o.dca2(pts, o.wire_frame(e))[0]) for e in ev.wire_ends])
+    keep = np.nonzero(D < 8.0)[0]
+    return ev.wire_ends[keep], np.arange(len(keep) + 1, dtype=np.int32), D[keep]
+
+
+def pin_field_lm_truth(o):
+    """Hits made (sigma = 0) from a track in a field with gradients: Levenberg-Marquardt
+    in the map from a perturbed seed drives the RSS to ~0 and recovers |p| of the truth
+    (a wrong dB/dx term or the uniform field's derivatives stall it)."""
+    ev = synth.event_plain(0)
+    fm = _linear_map(ev.bz, 2e-5, 2e-5)
+    truth = ev.ref_states[0]
+    K, h = 800, 2.0
+    ends, off, drift = _field_event(o, fm, truth, ev.charge, h, K)
+    assert len(drift) >= 20
+    cfg = [0.0, ev.charge, h, 1.0]
+    start = truth * np.array([1.0, 1.0, 1.0, 1.002, 0.998, 1.002])
+    start[0] += 0.2
+    pts0 = o.track_field(start, fm, ev.charge, h, K)
+    rss0 = o.rss_track(pts0, ends, off, drift, 1.0)
+    s, rss, acc = o.lm_refine_field(start, fm, cfg, K, ends, off, drift, 10, 1e-3)
+    assert acc >= 3 and rss < 1e-8 * rss0, (acc, rss, rss0)
+    assert abs(np.linalg.norm(s[3:]) - np.linalg.norm(truth[3:])) < 1e-3
+
+
+def pin_field_lm_uniform(o):
+    """In a constant map the map's LM takes the uniform LM's steps (same accepted count,
+    seeds equal to rounding)."""
+    ev = synth.event_plain(0)
+    b = np.zeros((2, 2, 2, 3))
+    b[..., 2] = ev.bz
+    fm = (b, np.array([-2000.0, -2000.0, -2000.0]), np.array([4000.0, 4000.0, 4000.0]))
+    start = ev.ref_states[0] * np.array([1.0, 1.0, 1.0, 1.002, 0.998, 1.003])
+    cfg = [ev.bz, ev.charge, 2.0, 1.0]
+    su, ru, au = o.lm_refine(start, cfg, 800, ev.wire_ends, ev.wire_offsets, ev.drift, 6, 1e-3)
+    sf, rf, af = o.lm_refine_field(start, fm, cfg, 800, ev.wire_ends, ev.wire_offsets, ev.drift,
+                                   6, 1e-3)
+    assert au == af and au >= 2
+    assert np.max(np.abs(sf - su) / np.maximum(np.abs(su), 1.0)) < 1e-8
+    assert abs(rf - ru) < 1e-8 * ru
+
+
+ALL_SIMPLE.extend([pin_field_jacobian_uniform, pin_field_jacobian_fd, pin_field_lm_truth,
+                   pin_field_lm_uniform])

@@ -80,6 +80,7 @@ MUTANTS = {
     "field_dual_cross_sign": ("    f[1] = dmul(g, dsub(dmul(p[2], B[0]), dmul(p[0], B[2])));", "    f[1] = dmul(g, dsub(dmul(p[0], B[2]), dmul(p[2], B[0])));"),
     "field_dual_stage3_uses_v1": ("            xs[c] = dadd(x[c], dmul(hh, v2[c]));", "            xs[c] = dadd(x[c], dmul(hh, v1[c]));"),
     "field_dual_y_cell_from_x": ("    dual_cell(ddiv(dsub(x[1], dc(f->y0)), dc(f->dy)), f->ny, &j, &tv);", "    dual_cell(ddiv(dsub(x[0], dc(f->y0)), dc(f->dy)), f->ny, &j, &tv);"),
+    "lm_field_uses_uniform": ("    if (!pb->field) {\n        normal_equations(", "    if (1) {\n        normal_equations("),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
