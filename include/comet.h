@@ -217,6 +217,34 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
                     int32_t *n_accepted, void *workspace, size_t workspace_bytes,
                     void *stream);
 
+/* Derivatives and Levenberg-Marquardt in a field map (Sec. 2.2.1: the tracks run
+ * through the solenoid's map, as comet_extrapolate_seeds_field records them).
+ *
+ * comet_rss_jacobian_field: the outputs of comet_rss_adjoint (same layouts, same
+ * active-wire rule, rss in the same tree order) for tracks in the map `field` (host
+ * struct, as in comet_extrapolate_seeds_field; cfg->bz_tesla is not used). The
+ * derivatives are taken in forward mode: six tangents of the RK4 state, one per seed
+ * component, are carried along the steps, with dB/dx of the trilinear interpolation
+ * (zero along a coordinate clamped to the grid), and J_i = n_i . dP/d(seed) at the
+ * wire's closest chord point. One block per seed; an event may hold at most 1024
+ * wires: a seed of a larger event gets NaN rss, grad, jtj and jte and no per-wire
+ * outputs. cfg->n_steps <= 2400.
+ *
+ * comet_lm_refine_field: comet_lm_refine with these derivatives and RSS (tracks in the
+ * map); arguments, workspace and iteration rule as there. */
+int comet_rss_jacobian_field(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                             const comet_field *field, const double *wire_ends, int32_t n_wires,
+                             const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                             const int32_t *event_wires, const int32_t *seed_event, double *rss,
+                             double *grad, double *jtj, double *jte, double *dca, double *resid,
+                             double *jac, void *stream);
+int comet_lm_refine_field(double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                          const comet_field *field, const double *wire_ends, int32_t n_wires,
+                          const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                          const int32_t *event_wires, const int32_t *seed_event, int32_t n_iter,
+                          double mu0, double *rss, int32_t *n_accepted, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------ batches of events
  * The whole Sec. 2.1 path (grid scan, argmin, n_refine finer re-scans, classification)
  * for every turn partition of many events with uneven wire, hit and turn counts.

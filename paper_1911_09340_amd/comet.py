@@ -320,6 +320,15 @@ def _bind_derivatives(lib):
                                     _vp, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp]
     lib.comet_lm_refine.restype = ctypes.c_int
+    FP = ctypes.POINTER(Field)
+    lib.comet_rss_jacobian_field.argtypes = [_vp, _i64, ctypes.POINTER(Config), FP, _vp, _i32,
+                                             _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                             _vp, _vp, _vp]
+    lib.comet_rss_jacobian_field.restype = ctypes.c_int
+    lib.comet_lm_refine_field.argtypes = [_vp, _i64, ctypes.POINTER(Config), FP, _vp, _i32, _vp,
+                                          _vp, _i32, _vp, _vp, _i32, ctypes.c_double, _vp, _vp,
+                                          _vp, ctypes.c_size_t, _vp]
+    lib.comet_lm_refine_field.restype = ctypes.c_int
     lib._derivs_bound = True
     return lib
 
@@ -327,13 +336,19 @@ def _bind_derivatives(lib):
 def rss_adjoint(seeds: torch.Tensor, cfg: Config, wire_ends: torch.Tensor,
                 wire_offsets: torch.Tensor, drift: torch.Tensor, rss=None, grad=None, jtj=None,
                 jte=None, dca=None, resid=None, jac=None, event_wires=None,
-                seed_event=None) -> None:
-    """comet_rss_adjoint: RSS, its seed gradient [S, 6], normal equations and per-wire rows."""
+                seed_event=None, field: "FieldMap" = None) -> None:
+    """comet_rss_adjoint: RSS, its seed gradient [S, 6], normal equations and per-wire rows;
+    with a field map, comet_rss_jacobian_field (tracks in the map, the same outputs)."""
     lib = _bind_derivatives(load())
     S = int(seeds.shape[1]) if seeds.dim() == 2 else -1
     n_w, n_h = int(wire_ends.shape[0]), int(drift.shape[0])
-    _check(lib.comet_rss_adjoint(
-        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
+    if field is None:
+        fn, name, head = lib.comet_rss_adjoint, "comet_rss_adjoint", ()
+    else:
+        fn, name = lib.comet_rss_jacobian_field, "comet_rss_jacobian_field"
+        head = (ctypes.byref(field.struct),)
+    _check(fn(
+        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg), *head,
         _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
         _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
         _ptr(drift, torch.float64, "drift", (n_h,)), n_h,
@@ -345,8 +360,7 @@ def rss_adjoint(seeds: torch.Tensor, cfg: Config, wire_ends: torch.Tensor,
         _ptr(jte, torch.float64, "jte", (S, 6), optional=True),
         _ptr(dca, torch.float64, "dca", (S, n_w), optional=True),
         _ptr(resid, torch.float64, "resid", (S, n_w), optional=True),
-        _ptr(jac, torch.float64, "jac", (S, n_w, 6), optional=True), _stream()),
-        "comet_rss_adjoint")
+        _ptr(jac, torch.float64, "jac", (S, n_w, 6), optional=True), _stream()), name)
 
 
 def lm_workspace(n_seeds: int, device=None) -> torch.Tensor:
@@ -357,13 +371,19 @@ def lm_workspace(n_seeds: int, device=None) -> torch.Tensor:
 def lm_refine(seeds: torch.Tensor, cfg: Config, wire_ends: torch.Tensor,
               wire_offsets: torch.Tensor, drift: torch.Tensor, n_iter: int, mu0: float,
               rss: torch.Tensor, workspace: torch.Tensor, n_accepted=None, event_wires=None,
-              seed_event=None) -> None:
-    """comet_lm_refine: Levenberg-Marquardt refinement of seeds [6, S] in place."""
+              seed_event=None, field: "FieldMap" = None) -> None:
+    """comet_lm_refine: Levenberg-Marquardt refinement of seeds [6, S] in place; with a
+    field map, comet_lm_refine_field."""
     lib = _bind_derivatives(load())
     S = int(seeds.shape[1]) if seeds.dim() == 2 else -1
     n_w, n_h = int(wire_ends.shape[0]), int(drift.shape[0])
-    _check(lib.comet_lm_refine(
-        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
+    if field is None:
+        fn, name, head = lib.comet_lm_refine, "comet_lm_refine", ()
+    else:
+        fn, name = lib.comet_lm_refine_field, "comet_lm_refine_field"
+        head = (ctypes.byref(field.struct),)
+    _check(fn(
+        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg), *head,
         _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
         _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
         _ptr(drift, torch.float64, "drift", (n_h,)), n_h,
@@ -371,8 +391,7 @@ def lm_refine(seeds: torch.Tensor, cfg: Config, wire_ends: torch.Tensor,
         _ptr(seed_event, torch.int32, "seed_event", (S,), optional=True),
         int(n_iter), float(mu0), _ptr(rss, torch.float64, "rss", (S,)),
         _ptr(n_accepted, torch.int32, "n_accepted", (S,), optional=True),
-        _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()),
-        "comet_lm_refine")
+        _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()), name)
 
 
 # ------------------------------------------------------------------ batches

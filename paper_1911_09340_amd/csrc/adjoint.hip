@@ -23,6 +23,7 @@
 
 #include "comet.h"
 #include "device_math.h"
+#include "field_math.h"
 #include "host_common.h"
 
 namespace {
@@ -62,6 +63,62 @@ __device__ __forceinline__ double chord_distance2_t(double axi, double aeta, dou
     pxi = fma(t, uxi, axi);
     peta = fma(t, ueta, aeta);
     return fma(pxi, pxi, peta * peta);
+}
+
+// A wire's DCA to the recorded track (lx, ly, lz; P points) as the forward contract
+// takes it: the closest recorded point (first index of the minimum), then the winning
+// refinement, the vertex or the interior of an adjacent chord. Returns D; the chord
+// starts at point ka with parameter t (0 at the vertex), closest point (pxi, peta) in
+// the wire's frame.
+__device__ __forceinline__ double closest_chord(const double *lx, const double *ly,
+                                                const double *lz, int P, const double (&f)[8],
+                                                int &ka, double &t, double &pxi, double &peta)
+{
+    int kb = 0;
+    double qb = INFINITY;
+    for (int k = 0; k < P; ++k) {
+        double xi, eta;
+        project(f, lx[k], ly[k], lz[k], xi, eta);
+        const double q = fma(xi, xi, eta * eta);
+        if (q < qb) {
+            qb = q;
+            kb = k;
+        }
+    }
+    double cxi, ceta;
+    project(f, lx[kb], ly[kb], lz[kb], cxi, ceta);
+    double d2 = qb;
+    pxi = cxi;
+    peta = ceta;
+    t = 0.0;
+    ka = kb;
+    if (kb > 0) {
+        double xi, eta, tt, qx, qe;
+        project(f, lx[kb - 1], ly[kb - 1], lz[kb - 1], xi, eta);
+        const double q = fma(xi, xi, eta * eta);
+        const double v = chord_distance2_t(xi, eta, q, cxi, ceta, qb, tt, qx, qe);
+        if (v < d2) {
+            d2 = v;
+            ka = kb - 1;
+            t = tt;
+            pxi = qx;
+            peta = qe;
+        }
+    }
+    if (kb < P - 1) {
+        double xi, eta, tt, qx, qe;
+        project(f, lx[kb + 1], ly[kb + 1], lz[kb + 1], xi, eta);
+        const double q = fma(xi, xi, eta * eta);
+        const double v = chord_distance2_t(cxi, ceta, qb, xi, eta, q, tt, qx, qe);
+        if (v < d2) {
+            d2 = v;
+            ka = kb;
+            t = tt;
+            pxi = qx;
+            peta = qe;
+        }
+    }
+    return sqrt(d2);
 }
 
 // Reverse sweep of one RK4 step (cdev::rk4_step) at start momentum (px, py): maps the
@@ -220,50 +277,9 @@ __global__ __launch_bounds__(kAdjThreads) void rss_adjoint_kernel(AdjArgs a)
     for (int wi = w0 + threadIdx.x; wi < w1; wi += kAdjThreads) {
         double f[8];
         wire_frame(a.ends + 6 * (int64_t)wi, f);
-        // closest recorded point (first index of the minimum)
-        int kb = 0;
-        double qb = INFINITY;
-        for (int k = 0; k < P; ++k) {
-            double xi, eta;
-            project(f, lx[k], ly[k], lz[k], xi, eta);
-            const double q = fma(xi, xi, eta * eta);
-            if (q < qb) {
-                qb = q;
-                kb = k;
-            }
-        }
-        // winning refinement: the vertex, or the interior of an adjacent chord
-        double cxi, ceta;
-        project(f, lx[kb], ly[kb], lz[kb], cxi, ceta);
-        double d2 = qb, pxi = cxi, peta = ceta, t = 0.0;
-        int ka = kb;
-        if (kb > 0) {
-            double xi, eta, tt, qx, qe;
-            project(f, lx[kb - 1], ly[kb - 1], lz[kb - 1], xi, eta);
-            const double q = fma(xi, xi, eta * eta);
-            const double v = chord_distance2_t(xi, eta, q, cxi, ceta, qb, tt, qx, qe);
-            if (v < d2) {
-                d2 = v;
-                ka = kb - 1;
-                t = tt;
-                pxi = qx;
-                peta = qe;
-            }
-        }
-        if (kb < P - 1) {
-            double xi, eta, tt, qx, qe;
-            project(f, lx[kb + 1], ly[kb + 1], lz[kb + 1], xi, eta);
-            const double q = fma(xi, xi, eta * eta);
-            const double v = chord_distance2_t(cxi, ceta, qb, xi, eta, q, tt, qx, qe);
-            if (v < d2) {
-                d2 = v;
-                ka = kb;
-                t = tt;
-                pxi = qx;
-                peta = qe;
-            }
-        }
-        const double D = sqrt(d2);
+        double t, pxi, peta;
+        int ka;
+        const double D = closest_chord(lx, ly, lz, P, f, ka, t, pxi, peta);
         // closest hit and Eq. 1's capped residual
         double eb = INFINITY, res = NAN;
         for (int j = a.offsets[wi]; j < a.offsets[wi + 1]; ++j) {
@@ -341,6 +357,204 @@ __global__ __launch_bounds__(kAdjThreads) void rss_adjoint_kernel(AdjArgs a)
         if (a.J)
             for (int r = 0; r < 6; ++r)
                 a.J[ow * 6 + r] = row[r];
+    }
+
+    block_sum(acc, scratch);
+    if (threadIdx.x == 0) {
+        if (a.rss)
+            a.rss[s] = acc[0];
+        if (a.grad)
+            for (int r = 0; r < 6; ++r)
+                a.grad[s * 6 + r] = acc[1 + r];
+        if (a.A)
+            for (int r = 0; r < kTri; ++r)
+                a.A[s * kTri + r] = acc[1 + 6 + r];
+        if (a.b)
+            for (int r = 0; r < 6; ++r)
+                a.b[s * 6 + r] = acc[1 + 6 + kTri + r];
+    }
+}
+
+// ------------------------------------------------------------------ field map
+// Derivatives in a field map (Sec. 2.2.1), in forward mode: the reverse sweep above
+// relies on the uniform field's rotation; in a map each stage's force depends on the
+// position through B(x), and six tangents (one per seed component) carried along the
+// RK4 steps with dB/dx from the trilinear interpolation give dP_k/d(seed) directly.
+//
+// One block per seed. Thread 0 records the track into LDS (rk4_field_step, as
+// comet_extrapolate_seeds_field); each thread takes up to kFieldWiresPerThread of the
+// event's wires, finds each wire's chord (closest_chord), its closest hit and Eq. 1's
+// capped residual, and keeps the active ones (ka, t, unit normal, e). Then threads 0-5
+// step the six tangents window by window (kWin steps), writing the position tangents
+// of the window's points to LDS, and after each window every thread forms the rows
+// J_i = n . ((1 - t) dP_ka + t dP_ka+1) of its wires whose chord starts in the window.
+constexpr int kWin = 64;
+constexpr int kFieldWiresPerThread = 4;
+constexpr int kMaxFieldWires = kAdjThreads * kFieldWiresPerThread;
+
+__host__ __device__ constexpr int field_region(int P)
+{
+    return 3 * P > 6 * (kWin + 1) * 3 ? 3 * P : 6 * (kWin + 1) * 3;
+}
+
+__global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs a, FieldMap m)
+{
+    extern __shared__ double lds[];
+    const int64_t s = blockIdx.x;
+    const int P = a.K + 1;
+    double *lx = lds, *ly = lds + P, *lz = lds + 2 * P;
+    double *buf = lds;  // after the wires' chords are taken: [6][kWin + 1][3]
+    double *scratch = lds + field_region(P);
+
+    const int e = a.seed_event ? a.seed_event[s] : 0;
+    const int w0 = a.ev_wires ? a.ev_wires[e] : 0;
+    const int w1 = a.ev_wires ? a.ev_wires[e + 1] : a.n_w_total;
+    if (w1 - w0 > kMaxFieldWires) {  // block-uniform: more wires than the records hold
+        if (threadIdx.x == 0) {
+            if (a.rss)
+                a.rss[s] = NAN;
+            for (int r = 0; r < 6; ++r) {
+                if (a.grad)
+                    a.grad[s * 6 + r] = NAN;
+                if (a.b)
+                    a.b[s * 6 + r] = NAN;
+            }
+            if (a.A)
+                for (int r = 0; r < kTri; ++r)
+                    a.A[s * kTri + r] = NAN;
+        }
+        return;
+    }
+    double sd[6];
+    for (int c = 0; c < 6; ++c)
+        sd[c] = a.seeds[c * a.S + s];
+    const double p0 = sqrt((sd[3] * sd[3] + sd[4] * sd[4]) + sd[5] * sd[5]);
+    const double inv = 1.0 / p0;
+    const double g = (kKappa * a.charge) * inv;
+
+    if (threadIdx.x == 0) {
+        double x[3] = {sd[0], sd[1], sd[2]}, p[3] = {sd[3], sd[4], sd[5]};
+        for (int j = 0; j < a.K; ++j) {
+            lx[j] = x[0];
+            ly[j] = x[1];
+            lz[j] = x[2];
+            rk4_field_step(m, inv, g, a.h, x, p);
+        }
+        lx[a.K] = x[0];
+        ly[a.K] = x[1];
+        lz[a.K] = x[2];
+    }
+    __syncthreads();
+
+    double acc[1 + 6 + kTri + 6];
+    for (int i = 0; i < 1 + 6 + kTri + 6; ++i)
+        acc[i] = 0.0;
+    int rk[kFieldWiresPerThread], rw[kFieldWiresPerThread];
+    double rt[kFieldWiresPerThread], rn0[kFieldWiresPerThread], rn1[kFieldWiresPerThread];
+    double rn2[kFieldWiresPerThread], re[kFieldWiresPerThread];
+#pragma unroll
+    for (int r = 0; r < kFieldWiresPerThread; ++r) {
+        rk[r] = -1;
+        rw[r] = 0;
+        rt[r] = rn0[r] = rn1[r] = rn2[r] = re[r] = 0.0;
+        const int wi = w0 + threadIdx.x + r * kAdjThreads;
+        if (wi >= w1)
+            continue;
+        double f[8];
+        wire_frame(a.ends + 6 * (int64_t)wi, f);
+        double t, pxi, peta;
+        int ka;
+        const double D = closest_chord(lx, ly, lz, P, f, ka, t, pxi, peta);
+        double eb = INFINITY, res = NAN;
+        for (int j = a.offsets[wi]; j < a.offsets[wi + 1]; ++j) {
+            const double rr = D - a.drift[j];
+            if (fabs(rr) < eb) {
+                eb = fabs(rr);
+                res = rr;
+            }
+        }
+        const bool active = eb < a.lambda;
+        const double d = active ? eb : a.lambda;
+        acc[0] += d * d;
+        const int64_t ow = s * (int64_t)a.n_w_total + wi;
+        if (a.D)
+            a.D[ow] = D;
+        if (a.resid)
+            a.resid[ow] = res;
+        if (active && D > 0.0) {
+            rk[r] = ka;
+            rw[r] = wi;
+            rt[r] = t;
+            rn0[r] = (pxi * f[0] + peta * f[4]) / D;
+            rn1[r] = (pxi * f[1] + peta * f[5]) / D;
+            rn2[r] = (pxi * f[2] + peta * f[6]) / D;
+            re[r] = res;
+        } else if (a.J) {
+            for (int c = 0; c < 6; ++c)
+                a.J[ow * 6 + c] = 0.0;
+        }
+    }
+    __syncthreads();  // the track's LDS becomes the tangent buffer
+
+    // threads 0-5: seed direction c = threadIdx.x; p0, inv, g differentiated at the seed
+    double x[3] = {sd[0], sd[1], sd[2]}, p[3] = {sd[3], sd[4], sd[5]};
+    double dx[3] = {0.0, 0.0, 0.0}, dp[3] = {0.0, 0.0, 0.0};
+    double dinv = 0.0, dg = 0.0;
+    const int dir = threadIdx.x;
+    if (dir < 3) {
+        dx[dir] = 1.0;
+    } else if (dir < 6) {
+        dp[dir - 3] = 1.0;
+        const double dp0 = sd[dir] / p0;
+        dinv = -(dp0 * inv) * inv;
+        dg = (kKappa * a.charge) * dinv;
+    }
+    const int n_win = a.K / kWin + 1;
+    for (int w = 0; w < n_win; ++w) {
+        const int base = w * kWin;
+        const int last = min(base + kWin, a.K);
+        if (dir < 6) {
+            double *bc = buf + dir * (kWin + 1) * 3;
+            for (int k = base; k <= last; ++k) {
+                bc[(k - base) * 3 + 0] = dx[0];
+                bc[(k - base) * 3 + 1] = dx[1];
+                bc[(k - base) * 3 + 2] = dx[2];
+                if (k < last)
+                    rk4_field_step_dir(m, inv, g, dinv, dg, a.h, x, p, dx, dp);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kFieldWiresPerThread; ++r) {
+            if (rk[r] < 0 || rk[r] / kWin != w)
+                continue;
+            const int o = rk[r] - base;
+            const double t = rt[r];
+            double row[6];
+            for (int c = 0; c < 6; ++c) {
+                const double *bc = buf + c * (kWin + 1) * 3 + o * 3;
+                double gx = bc[0], gy = bc[1], gz = bc[2];
+                if (t > 0.0) {
+                    gx = (1.0 - t) * gx + t * bc[3];
+                    gy = (1.0 - t) * gy + t * bc[4];
+                    gz = (1.0 - t) * gz + t * bc[5];
+                }
+                row[c] = (rn0[r] * gx + rn1[r] * gy) + rn2[r] * gz;
+            }
+            const double res = re[r];
+            for (int q = 0; q < 6; ++q) {
+                acc[1 + q] += 2.0 * res * row[q];
+                acc[1 + 6 + kTri + q] += row[q] * res;
+                for (int c2 = q; c2 < 6; ++c2)
+                    acc[1 + 6 + tri(q, c2)] += row[q] * row[c2];
+            }
+            if (a.J) {
+                const int64_t ow = s * (int64_t)a.n_w_total + rw[r];
+                for (int c = 0; c < 6; ++c)
+                    a.J[ow * 6 + c] = row[c];
+            }
+        }
+        __syncthreads();
     }
 
     block_sum(acc, scratch);
@@ -486,11 +700,27 @@ int check_adjoint_args(const char *who, const double *seeds6, int64_t n_seeds,
     return COMET_OK;
 }
 
-int launch_adjoint(const AdjArgs &a, hipStream_t hs)
+size_t field_jacobian_lds_bytes(int K)
 {
+    return sizeof(double) * ((size_t)field_region(K + 1) + (kAdjThreads / 64) * 34);
+}
+
+// The uniform-field reverse sweep, or the field map's forward tangents when fm is set.
+int launch_adjoint(const AdjArgs &a, hipStream_t hs, const FieldMap *fm = nullptr)
+{
+    if (fm) {
+        hipLaunchKernelGGL(rss_jacobian_field_kernel, dim3((unsigned)a.S), dim3(kAdjThreads),
+                           field_jacobian_lds_bytes(a.K), hs, a, *fm);
+        return launched("rss_jacobian_field_kernel");
+    }
     const size_t lds = adjoint_lds_bytes(a.K);
     hipLaunchKernelGGL(rss_adjoint_kernel, dim3((unsigned)a.S), dim3(kAdjThreads), lds, hs, a);
     return launched("rss_adjoint_kernel");
+}
+
+FieldMap field_map_of(const comet_field *f)
+{
+    return FieldMap{f->b, f->nx, f->ny, f->nz, f->x0, f->y0, f->z0, f->dx, f->dy, f->dz};
 }
 
 }  // namespace
@@ -527,29 +757,33 @@ size_t comet_lm_workspace_bytes(int64_t n_seeds)
            2 * align256(sizeof(int32_t) * S);
 }
 
-int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
-                    const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
-                    const double *drift, int32_t n_hits, const int32_t *event_wires,
-                    const int32_t *seed_event, int32_t n_iter, double mu0, double *rss,
-                    int32_t *n_accepted, void *workspace, size_t workspace_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+int lm_refine_impl(const char *who, double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                   const FieldMap *fm, const double *wire_ends, int32_t n_wires,
+                   const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                   const int32_t *event_wires, const int32_t *seed_event, int32_t n_iter,
+                   double mu0, double *rss, int32_t *n_accepted, void *workspace,
+                   size_t workspace_bytes, void *stream)
 {
-    clear_error();
-    int st = check_adjoint_args("comet_lm_refine", seeds6, n_seeds, cfg, wire_ends, n_wires,
-                                wire_offsets, drift, n_hits, event_wires, seed_event);
+    int st = check_adjoint_args(who, seeds6, n_seeds, cfg, wire_ends, n_wires, wire_offsets,
+                                drift, n_hits, event_wires, seed_event);
     if (st)
         return st;
     if (!rss)
-        return fail(COMET_EINVAL, "comet_lm_refine: NULL rss");
+        return fail(COMET_EINVAL, "%s: NULL rss", who);
     if (n_iter < 0 || n_iter > 1000)
-        return fail(COMET_EINVAL, "comet_lm_refine: n_iter must be in [0, 1000]");
+        return fail(COMET_EINVAL, "%s: n_iter must be in [0, 1000]", who);
     if (!(mu0 > 0.0) || !isfinite(mu0))
-        return fail(COMET_EINVAL, "comet_lm_refine: mu0 must be finite and > 0");
+        return fail(COMET_EINVAL, "%s: mu0 must be finite and > 0", who);
     const size_t need = comet_lm_workspace_bytes(n_seeds);
     if (!workspace || workspace_bytes < need)
-        return fail(COMET_EWORKSPACE, "comet_lm_refine: workspace %zu < %zu bytes",
-                    workspace_bytes, need);
+        return fail(COMET_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, workspace_bytes,
+                    need);
     if (((uintptr_t)workspace & 255) != 0)
-        return fail(COMET_EINVAL, "comet_lm_refine: workspace not 256-byte aligned");
+        return fail(COMET_EINVAL, "%s: workspace not 256-byte aligned", who);
     st = check_device();
     if (st)
         return st;
@@ -582,7 +816,7 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
     hipLaunchKernelGGL(lm_init_kernel, grid1, block1, 0, hs, n_seeds, mu0, mu, acc);
     st = launched("lm_init_kernel");
     if (!st)
-        st = launch_adjoint(a, hs);
+        st = launch_adjoint(a, hs, fm);
     AdjArgs at = a;
     at.seeds = trial;
     at.rss = rss_t;
@@ -594,7 +828,7 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
                            (const double *)mu, trial, ok);
         st = launched("lm_propose_kernel");
         if (!st)
-            st = launch_adjoint(at, hs);
+            st = launch_adjoint(at, hs, fm);
         if (!st) {
             hipLaunchKernelGGL(lm_accept_kernel, grid1, block1, 0, hs, n_seeds, seeds6,
                                (const double *)trial, rss, (const double *)rss_t, A,
@@ -604,6 +838,64 @@ int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
         }
     }
     return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                    const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                    const double *drift, int32_t n_hits, const int32_t *event_wires,
+                    const int32_t *seed_event, int32_t n_iter, double mu0, double *rss,
+                    int32_t *n_accepted, void *workspace, size_t workspace_bytes, void *stream)
+{
+    clear_error();
+    return lm_refine_impl("comet_lm_refine", seeds6, n_seeds, cfg, nullptr, wire_ends, n_wires,
+                          wire_offsets, drift, n_hits, event_wires, seed_event, n_iter, mu0,
+                          rss, n_accepted, workspace, workspace_bytes, stream);
+}
+
+int comet_rss_jacobian_field(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                             const comet_field *field, const double *wire_ends, int32_t n_wires,
+                             const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                             const int32_t *event_wires, const int32_t *seed_event, double *rss,
+                             double *grad, double *jtj, double *jte, double *dca, double *resid,
+                             double *jac, void *stream)
+{
+    clear_error();
+    int st = check_adjoint_args("comet_rss_jacobian_field", seeds6, n_seeds, cfg, wire_ends,
+                                n_wires, wire_offsets, drift, n_hits, event_wires, seed_event);
+    if (st)
+        return st;
+    st = check_field("comet_rss_jacobian_field", field);
+    if (st)
+        return st;
+    st = check_device();
+    if (st)
+        return st;
+    AdjArgs a{seeds6, n_seeds, cfg->bz_tesla, cfg->charge_e, cfg->step_mm, cfg->lambda_mm,
+              cfg->n_steps, wire_ends, n_wires, wire_offsets, drift, event_wires, seed_event,
+              rss, grad, jtj, jte, dca, resid, jac};
+    const FieldMap m = field_map_of(field);
+    return launch_adjoint(a, (hipStream_t)stream, &m);
+}
+
+int comet_lm_refine_field(double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                          const comet_field *field, const double *wire_ends, int32_t n_wires,
+                          const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                          const int32_t *event_wires, const int32_t *seed_event, int32_t n_iter,
+                          double mu0, double *rss, int32_t *n_accepted, void *workspace,
+                          size_t workspace_bytes, void *stream)
+{
+    clear_error();
+    const int st = check_field("comet_lm_refine_field", field);
+    if (st)
+        return st;
+    const FieldMap m = field_map_of(field);
+    return lm_refine_impl("comet_lm_refine_field", seeds6, n_seeds, cfg, &m, wire_ends,
+                          n_wires, wire_offsets, drift, n_hits, event_wires, seed_event, n_iter,
+                          mu0, rss, n_accepted, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -56,17 +56,15 @@ int comet_extrapolate_seeds_field(const double *seeds6, int64_t n_seeds, const c
                                   const comet_field *field, double *track_xyz, void *stream)
 {
     clear_error();
-    if (!seeds6 || !track_xyz || !field || !field->b)
+    if (!seeds6 || !track_xyz)
         return fail(COMET_EINVAL, "comet_extrapolate_seeds_field: NULL pointer");
     if (n_seeds < 1 || n_seeds > ((int64_t)1 << 40))
         return fail(COMET_EINVAL, "comet_extrapolate_seeds_field: n_seeds = %lld",
                     (long long)n_seeds);
-    if (field->nx < 2 || field->ny < 2 || field->nz < 2 || field->reserved != 0 ||
-        !finite_pos(field->dx) || !finite_pos(field->dy) || !finite_pos(field->dz) ||
-        !isfinite(field->x0) || !isfinite(field->y0) || !isfinite(field->z0))
-        return fail(COMET_EINVAL, "comet_extrapolate_seeds_field: need nx, ny, nz >= 2, "
-                                  "reserved 0, finite origin, spacings > 0");
-    int st = check_config(cfg);
+    int st = check_field("comet_extrapolate_seeds_field", field);
+    if (st)
+        return st;
+    st = check_config(cfg);
     if (st)
         return st;
     st = check_device();

@@ -112,4 +112,127 @@ __device__ __forceinline__ void rk4_field_step(const FieldMap &m, double inv, do
     }
 }
 
+// ------------------------------------------------------------------ derivatives
+// B at a point and its derivative along a direction (ddx, ddy, ddz): dB = sum over the
+// axes of dB/dt_a (dt_a/dx_a) ddx_a, with dt/dx = 1 / spacing, or 0 where the coordinate
+// is clamped to the grid (u <= 0, NaN, or u > n - 1: the value is constant there). B is
+// computed with the operations of field_at. The derivatives of the trilinear form:
+// dB/dt_u = lerp over (v, w) of the x-edge differences, dB/dt_v = lerp over w of the
+// y differences, dB/dt_w = the z difference.
+__device__ __forceinline__ double cell_slope(double u, int n, double step)
+{
+    return (!(u > 0.0) || u > (double)(n - 1)) ? 0.0 : 1.0 / step;
+}
+
+__device__ __forceinline__ void field_at_dir(const FieldMap &m, const double (&x)[3],
+                                             const double (&dx)[3], double (&B)[3],
+                                             double (&dB)[3])
+{
+    const double u = (x[0] - m.x0) / m.dx, v = (x[1] - m.y0) / m.dy, w = (x[2] - m.z0) / m.dz;
+    const double du = cell_slope(u, m.nx, m.dx) * dx[0];
+    const double dv = cell_slope(v, m.ny, m.dy) * dx[1];
+    const double dw = cell_slope(w, m.nz, m.dz) * dx[2];
+    int i, j, k;
+    double tu, tv, tw;
+    field_cell(u, m.nx, i, tu);
+    field_cell(v, m.ny, j, tv);
+    field_cell(w, m.nz, k, tw);
+    const int64_t sx = 3, sy = 3 * (int64_t)m.nx, sz = 3 * (int64_t)m.nx * m.ny;
+    const double *n000 = m.b + k * sz + j * sy + i * sx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double a000 = n000[c], a100 = n000[sx + c];
+        const double a010 = n000[sy + c], a110 = n000[sy + sx + c];
+        const double a001 = n000[sz + c], a101 = n000[sz + sx + c];
+        const double a011 = n000[sz + sy + c], a111 = n000[sz + sy + sx + c];
+        const double c00 = lerp(a000, a100, tu);
+        const double c10 = lerp(a010, a110, tu);
+        const double c01 = lerp(a001, a101, tu);
+        const double c11 = lerp(a011, a111, tu);
+        const double e0 = lerp(c00, c10, tv), e1 = lerp(c01, c11, tv);
+        B[c] = lerp(e0, e1, tw);
+        const double bu = lerp(lerp(a100 - a000, a110 - a010, tv),
+                               lerp(a101 - a001, a111 - a011, tv), tw);
+        const double bv = lerp(c10 - c00, c11 - c01, tw);
+        const double bw = e1 - e0;
+        dB[c] = (bu * du + bv * dv) + bw * dw;
+    }
+}
+
+// f = g (p x B(x)) and its derivative along (dx, dp) with dg the derivative of g:
+// df = dg (p x B) + g (dp x B + p x dB).
+__device__ __forceinline__ void field_force_dir(const FieldMap &m, double g, double dg,
+                                                const double (&x)[3], const double (&p)[3],
+                                                const double (&dx)[3], const double (&dp)[3],
+                                                double (&f)[3], double (&df)[3])
+{
+    double B[3], dB[3];
+    field_at_dir(m, x, dx, B, dB);
+    f[0] = g * (p[1] * B[2] - p[2] * B[1]);
+    f[1] = g * (p[2] * B[0] - p[0] * B[2]);
+    f[2] = g * (p[0] * B[1] - p[1] * B[0]);
+    const double q0 = (dp[1] * B[2] - dp[2] * B[1]) + (p[1] * dB[2] - p[2] * dB[1]);
+    const double q1 = (dp[2] * B[0] - dp[0] * B[2]) + (p[2] * dB[0] - p[0] * dB[2]);
+    const double q2 = (dp[0] * B[1] - dp[1] * B[0]) + (p[0] * dB[1] - p[1] * dB[0]);
+    df[0] = dg * (p[1] * B[2] - p[2] * B[1]) + g * q0;
+    df[1] = dg * (p[2] * B[0] - p[0] * B[2]) + g * q1;
+    df[2] = dg * (p[0] * B[1] - p[1] * B[0]) + g * q2;
+}
+
+// One RK4 step in the map (the primal exactly as rk4_field_step) with its tangent
+// (dx, dp) along one seed direction; dinv and dg are that direction's derivatives of
+// inv = 1 / |p of the seed| and g = (kappa q) inv.
+__device__ __forceinline__ void rk4_field_step_dir(const FieldMap &m, double inv, double g,
+                                                   double dinv, double dg, double h,
+                                                   double (&x)[3], double (&p)[3],
+                                                   double (&dx)[3], double (&dp)[3])
+{
+    const double hh = 0.5 * h, h6 = h / 6.0;
+    double v1[3], f1[3], v2[3], f2[3], v3[3], f3[3], v4[3], f4[3], xs[3], ps[3];
+    double dv1[3], df1[3], dv2[3], df2[3], dv3[3], df3[3], dv4[3], df4[3], dxs[3], dps[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v1[c] = p[c] * inv;
+        dv1[c] = dp[c] * inv + p[c] * dinv;
+    }
+    field_force_dir(m, g, dg, x, p, dx, dp, f1, df1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xs[c] = x[c] + hh * v1[c];
+        ps[c] = p[c] + hh * f1[c];
+        v2[c] = ps[c] * inv;
+        dxs[c] = dx[c] + hh * dv1[c];
+        dps[c] = dp[c] + hh * df1[c];
+        dv2[c] = dps[c] * inv + ps[c] * dinv;
+    }
+    field_force_dir(m, g, dg, xs, ps, dxs, dps, f2, df2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xs[c] = x[c] + hh * v2[c];
+        ps[c] = p[c] + hh * f2[c];
+        v3[c] = ps[c] * inv;
+        dxs[c] = dx[c] + hh * dv2[c];
+        dps[c] = dp[c] + hh * df2[c];
+        dv3[c] = dps[c] * inv + ps[c] * dinv;
+    }
+    field_force_dir(m, g, dg, xs, ps, dxs, dps, f3, df3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xs[c] = x[c] + h * v3[c];
+        ps[c] = p[c] + h * f3[c];
+        v4[c] = ps[c] * inv;
+        dxs[c] = dx[c] + h * dv3[c];
+        dps[c] = dp[c] + h * df3[c];
+        dv4[c] = dps[c] * inv + ps[c] * dinv;
+    }
+    field_force_dir(m, g, dg, xs, ps, dxs, dps, f4, df4);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = x[c] + h6 * (((v1[c] + 2.0 * v2[c]) + 2.0 * v3[c]) + v4[c]);
+        p[c] = p[c] + h6 * (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]);
+        dx[c] = dx[c] + h6 * (((dv1[c] + 2.0 * dv2[c]) + 2.0 * dv3[c]) + dv4[c]);
+        dp[c] = dp[c] + h6 * (((df1[c] + 2.0 * df2[c]) + 2.0 * df3[c]) + df4[c]);
+    }
+}
+
 }  // namespace cdev

@@ -24,6 +24,9 @@ int launched(const char *what);
 int check_config(const comet_config *cfg);
 bool finite_pos(double v);
 size_t align256(size_t v);
+// Checks a comet_field (not the map's values): b set, nx, ny, nz >= 2, reserved 0,
+// finite origin, spacings > 0.
+int check_field(const char *who, const comet_field *field);
 
 // Kernel kinds for comet_profile_end().
 enum { kProfTrack = 0, kProfDca = 1, kProfSum = 2, kProfSelect = 3 };

@@ -315,3 +315,36 @@ def test_field_call_rejects(lib):
                   comet.Field(_p(), 3, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 0.0, 1.0)):
         assert lib.comet_extrapolate_seeds_field(_p(), 4, ctypes.byref(cfg), ctypes.byref(field),
                                                  _p(), None) == comet.EINVAL
+
+
+def test_field_derivative_calls_reject(lib):
+    comet._bind_derivatives(lib)
+    cfg = _cfg()
+    good = comet.Field(_p(), 3, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    bad_field = comet.Field(_p(), 3, 1, 3, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    outs = [None] * 7
+    args = [_p(), 4, ctypes.byref(cfg), ctypes.byref(good), _p(), 10, _p(), _p(), 20, None, None]
+    bad = list(args)
+    bad[0] = None
+    assert lib.comet_rss_jacobian_field(*bad, *outs, None) == comet.EINVAL
+    bad = list(args)
+    bad[3] = None
+    assert lib.comet_rss_jacobian_field(*bad, *outs, None) == comet.EINVAL
+    bad[3] = ctypes.byref(bad_field)
+    assert lib.comet_rss_jacobian_field(*bad, *outs, None) == comet.EINVAL
+    bad = list(args)
+    bad[9] = _p()                                   # event_wires without seed_event
+    assert lib.comet_rss_jacobian_field(*bad, *outs, None) == comet.EINVAL
+    long_cfg = comet.make_config(1.0, -1.0, 1.0, 2401, 0.8)
+    bad = list(args)
+    bad[2] = ctypes.byref(long_cfg)
+    assert lib.comet_rss_jacobian_field(*bad, *outs, None) == comet.EUNSUPPORTED
+    lm = [_p(), 4, ctypes.byref(cfg), ctypes.byref(good), _p(), 10, _p(), _p(), 20, None, None,
+          8, 1e-3, _p(), None]
+    assert lib.comet_lm_refine_field(*lm, _p(0x100000), 16, None) == comet.EWORKSPACE
+    bad = list(lm)
+    bad[3] = ctypes.byref(bad_field)
+    assert lib.comet_lm_refine_field(*bad, _p(0x100000), 1 << 20, None) == comet.EINVAL
+    bad = list(lm)
+    bad[12] = 0.0
+    assert lib.comet_lm_refine_field(*bad, _p(0x100000), 1 << 20, None) == comet.EINVAL

@@ -68,3 +68,108 @@ def test_field_partition_rss_matches_cpu(orc, fmap):
                      for s in range(seeds.shape[1])])
     assert np.array_equal(got, want)
     assert int(r.best.item()) == int(np.argmin(want))
+
+
+def _map_hits(orc, fmap, seed, charge, h, K):
+    """Chamber wires within 8 mm of the map track of seed, each with one hit at its DCA
+    plus N(0, 0.2 mm) (the oracle's track; a stand-in event for the map)."""
+    rng = np.random.default_rng(3)
+    wires = synth.chamber_wires()
+    pts = orc.track_field(seed, fmap, charge, h, K)
+    D = np.array([np.sqrt(orc.dca2(pts, orc.wire_frame(w))[0]) for w in wires])
+    keep = np.nonzero(D < 8.0)[0]
+    drift = np.clip(D[keep] + rng.normal(0.0, 0.2, keep.size), 0.0, 8.0)
+    return wires[keep], np.arange(keep.size + 1, dtype=np.int32), drift
+
+
+def test_field_jacobian_matches_cpu(orc, fmap):
+    """Derivatives through the map (forward-mode tangents with dB/dx) vs the CPU dual
+    numbers: D and residuals bit for bit, rows J_i, gradient and normal equations to
+    1e-7 relative, RSS to 1e-12."""
+    ev = synth.event_plain(0)
+    K, h, lam = 900, 2.0, 0.8
+    ends, off, drift = _map_hits(orc, fmap, ev.ref_states[0], ev.charge, h, K)
+    assert len(drift) >= 20
+    rng = np.random.default_rng(6)
+    seeds = np.stack([ev.ref_states[0] * (1 + rng.normal(0, 1e-3, 6)) for _ in range(5)]
+                     + [ev.ref_states[0]], axis=1)
+    S, n_w = seeds.shape[1], ends.shape[0]
+    cfg = comet.make_config(0.0, ev.charge, h, K, lam)
+    d = dict(dtype=torch.float64, device="cuda")
+    out = {k: torch.full(shape, np.nan, **d) for k, shape in
+           (("rss", (S,)), ("grad", (S, 6)), ("jtj", (S, 21)), ("jte", (S, 6)),
+            ("dca", (S, n_w)), ("resid", (S, n_w)), ("jac", (S, n_w, 6)))}
+    comet.rss_adjoint(torch.as_tensor(seeds, **d), cfg, torch.as_tensor(ends, **d),
+                      torch.as_tensor(off, device="cuda"), torch.as_tensor(drift, **d),
+                      field=comet.FieldMap(*fmap), **out)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    iu = np.triu_indices(6)
+    n_active = 0
+    for s in range(S):
+        r = orc.rss_jacobian_field(seeds[:, s], fmap, ev.charge, h, K, lam, ends, off, drift)
+        assert np.array_equal(got["dca"][s], r["D"]), s
+        assert np.array_equal(got["resid"][s], r["resid"]), s
+        assert abs(got["rss"][s] - r["rss"]) <= 1e-12 * r["rss"], s
+        act = r["active"]
+        n_active += int(act.sum())
+        J = np.where(act[:, None], r["J"], 0.0)
+        scale = np.max(np.abs(J))
+        assert np.max(np.abs(got["jac"][s] - J)) < 1e-7 * scale, s
+        np.testing.assert_allclose(got["grad"][s], r["grad"], rtol=0,
+                                   atol=1e-7 * np.max(np.abs(r["grad"])))
+        A = J.T @ J
+        b = J.T @ np.where(act, r["resid"], 0.0)
+        np.testing.assert_allclose(got["jtj"][s], A[iu], rtol=0, atol=1e-7 * np.max(np.abs(A)))
+        np.testing.assert_allclose(got["jte"][s], b, rtol=0, atol=1e-7 * np.max(np.abs(b)))
+    assert n_active >= 5 * S
+
+
+def test_field_lm_matches_cpu(orc, fmap):
+    """Levenberg-Marquardt in the map vs the CPU reference: the same accepted steps, the
+    final seeds to 1e-7 relative and their RSS to 1e-9."""
+    ev = synth.event_plain(0)
+    K, h, lam = 900, 2.0, 0.8
+    truth = ev.ref_states[0]
+    ends, off, drift = _map_hits(orc, fmap, truth, ev.charge, h, K)
+    rng = np.random.default_rng(7)
+    starts = np.stack([truth * (1 + rng.normal(0, 1.5e-3, 6)) for _ in range(4)], axis=1)
+    S = starts.shape[1]
+    cfg = comet.make_config(0.0, ev.charge, h, K, lam)
+    d = dict(dtype=torch.float64, device="cuda")
+    x = torch.as_tensor(starts, **d).clone()
+    rss = torch.empty(S, **d)
+    acc = torch.empty(S, dtype=torch.int32, device="cuda")
+    comet.lm_refine(x, cfg, torch.as_tensor(ends, **d), torch.as_tensor(off, device="cuda"),
+                    torch.as_tensor(drift, **d), 8, 1e-3, rss, comet.lm_workspace(S),
+                    n_accepted=acc, field=comet.FieldMap(*fmap))
+    torch.cuda.synchronize()
+    gx, grss, gacc = x.cpu().numpy(), rss.cpu().numpy(), acc.cpu().numpy()
+    for s in range(S):
+        ws, wrss, wacc = orc.lm_refine_field(starts[:, s], fmap, [0.0, ev.charge, h, lam], K,
+                                             ends, off, drift, 8, 1e-3)
+        assert gacc[s] == wacc and wacc >= 2, s
+        np.testing.assert_allclose(gx[:, s], ws, rtol=1e-7, atol=1e-9)
+        assert abs(grss[s] - wrss) <= 1e-9 * wrss, s
+
+
+def test_field_jacobian_too_many_wires():
+    """An event with more than 1024 wires: NaN outputs for its seeds (no fault)."""
+    ev = synth.event_plain(0)
+    reps = 1100 // ev.n_wires + 1
+    ends = np.tile(ev.wire_ends, (reps, 1))
+    n_w = ends.shape[0]
+    assert n_w > 1024
+    off = np.arange(n_w + 1, dtype=np.int32)
+    drift = np.full(n_w, 2.0)
+    d = dict(dtype=torch.float64, device="cuda")
+    rss = torch.zeros(2, **d)
+    grad = torch.zeros(2, 6, **d)
+    seeds = torch.as_tensor(np.stack([ev.ref_states[0]] * 2, axis=1), **d)
+    cfg = comet.make_config(0.0, ev.charge, 2.0, 300, 0.8)
+    fm = synth.solenoid_map()
+    comet.rss_adjoint(seeds, cfg, torch.as_tensor(ends, **d), torch.as_tensor(off, device="cuda"),
+                      torch.as_tensor(drift, **d), rss=rss, grad=grad,
+                      field=comet.FieldMap(*fm))
+    torch.cuda.synchronize()
+    assert torch.isnan(rss).all() and torch.isnan(grad).all()
