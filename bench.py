@@ -488,7 +488,8 @@ def main():
     flops = FLOP_PER_POINT_WIRE * prof["scan_points"] / n_dca   # per launch, performed
     achieved = flops / dca_s / 1e12
     ms_trk, n_trk = prof["track"]
-    trk_bytes = 8 * 3 * P * sc.n_seeds + 8 * 6 * sc.n_seeds
+    # the track, the seeds read, and the radii of its 16-point windows written with it
+    trk_bytes = 8 * 3 * P * sc.n_seeds + 8 * 6 * sc.n_seeds + 8 * ((P - 1) // 16 + 1) * sc.n_seeds
     traffic = stored_traffic(variants[variant])
 
     out = {

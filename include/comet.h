@@ -138,6 +138,18 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
                   const double *drift, int32_t n_hits, const comet_config *cfg, double *rss,
                   void *workspace, size_t workspace_bytes, void *stream);
 
+/* comet_extrapolate_seeds (field == NULL) or comet_extrapolate_seeds_field (field set)
+ * followed by comet_dca_rss, in one call (Alg. 1 then Alg. 2 and Eq. 1): the track is
+ * written to track_xyz as there, and the radii of its 16-point windows, which the
+ * distance bound needs, are taken while it is recorded instead of by a second read of
+ * the track. rss and the track are those of the separate calls, bit for bit.
+ * Arguments as in those calls; n_points is cfg->n_steps + 1. */
+int comet_track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                        const comet_field *field, const double *wire_ends, int32_t n_wires,
+                        const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                        double *track_xyz, double *rss, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
 /* Seed selection and hit classification (Sec. 2.1).
  * best[0] = index of the lowest rss (ties: lowest index; NaN never chosen; -1 if
  * every value is NaN). When hit_mask is not NULL the chosen seed's track is read

@@ -68,11 +68,14 @@ __global__ void refine_grid_kernel(double *__restrict__ grid, int n0, int n1, in
 
 // ------------------------------------------------------------------ RK4 recording
 // Alg. 1, one seed per lane (the step is cdev::rk4_step). The store of point k
-// writes 64 consecutive doubles per coordinate row per wave.
+// writes 64 consecutive doubles per coordinate row per wave. With rho set, the chunk
+// radii of the track (as chunk_radius_kernel computes them, layout [window][S]) are
+// taken while recording, so the scan needs no second read of the track.
 __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restrict__ seeds,
                                                          int64_t S, double bz, double charge,
                                                          double h, int K,
-                                                         double *__restrict__ track)
+                                                         double *__restrict__ track,
+                                                         double *__restrict__ rho)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S)
@@ -85,15 +88,21 @@ __global__ __launch_bounds__(256) void rk4_record_kernel(const double *__restric
     double *tx = track + s;
     double *ty = track + P * S + s;
     double *tz = track + 2 * P * S + s;
+    cdev::ChunkRadius cr;
+    double *rs = rho ? rho + s : nullptr;
     for (int j = 0; j < K; ++j) {
         tx[(int64_t)j * S] = x;
         ty[(int64_t)j * S] = y;
         tz[(int64_t)j * S] = z;
+        if (rs)
+            cr.add(j, K + 1, x, y, z, rs, S);
         cdev::rk4_step(k, x, y, z, px, py);
     }
     tx[(int64_t)K * S] = x;
     ty[(int64_t)K * S] = y;
     tz[(int64_t)K * S] = z;
+    if (rs)
+        cr.add(K, K + 1, x, y, z, rs, S);
 }
 
 // Chunk radii of every seed's track (ChunkRadius: window n holds points 16 n ...
@@ -466,7 +475,7 @@ int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_c
     ProfScope prof(kProfTrack, (hipStream_t)stream);
     hipLaunchKernelGGL(rk4_record_kernel, dim3((unsigned)((n_seeds + threads - 1) / threads)),
                        dim3(threads), 0, (hipStream_t)stream, seeds6, n_seeds, cfg->bz_tesla,
-                       cfg->charge_e, cfg->step_mm, cfg->n_steps, track_xyz);
+                       cfg->charge_e, cfg->step_mm, cfg->n_steps, track_xyz, (double *)nullptr);
     return launched("rk4_record_kernel");
 }
 
@@ -607,6 +616,68 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
         ProfScope prof(kProfDca, hs);
         st = launch_dca(choose_variant(n_seeds, n_points, n_wires), track_xyz, n_seeds, n_points,
                         n_wires, wire_offsets, drift, cfg->lambda_mm, workspace, hs);
+    }
+    if (st)
+        return st;
+    ProfScope prof(kProfSum, hs);
+    hipLaunchKernelGGL(rss_sum_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256), 0, hs,
+                       (const double *)dca_dsq(workspace, n_wires), n_wires, n_seeds, rss);
+    return launched("rss_sum_kernel");
+}
+
+int comet_track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                        const comet_field *field, const double *wire_ends, int32_t n_wires,
+                        const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                        double *track_xyz, double *rss, void *workspace, size_t workspace_bytes,
+                        void *stream)
+{
+    clear_error();
+    if (!seeds6)
+        return fail(COMET_EINVAL, "comet_track_dca_rss: NULL seeds");
+    int st = check_dca_args("comet_track_dca_rss", track_xyz, n_seeds, cfg ? cfg->n_steps + 1 : 0,
+                            wire_ends, n_wires, wire_offsets, drift, n_hits, cfg, rss, workspace,
+                            workspace_bytes);
+    if (st)
+        return st;
+    if (field) {
+        st = check_field("comet_track_dca_rss", field);
+        if (st)
+            return st;
+    }
+    st = check_device();
+    if (st)
+        return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const int P = cfg->n_steps + 1;
+    double *rho = n_wires > 0 ? dca_rho(workspace, n_wires, n_seeds) : nullptr;
+    {
+        ProfScope prof(kProfTrack, hs);
+        if (field) {
+            st = launch_field_record(seeds6, n_seeds, field, cfg->charge_e, cfg->step_mm,
+                                     cfg->n_steps, track_xyz, rho, hs);
+        } else {
+            const int threads = 256;
+            hipLaunchKernelGGL(rk4_record_kernel,
+                               dim3((unsigned)((n_seeds + threads - 1) / threads)), dim3(threads),
+                               0, hs, seeds6, n_seeds, cfg->bz_tesla, cfg->charge_e,
+                               cfg->step_mm, cfg->n_steps, track_xyz, rho);
+            st = launched("rk4_record_kernel");
+        }
+    }
+    if (st)
+        return st;
+    if (n_wires == 0) {
+        hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256), 0, hs,
+                           rss, n_seeds, 0.0);
+        return launched("fill_kernel");
+    }
+    st = launch_frames(wire_ends, n_wires, workspace, hs);
+    if (st)
+        return st;
+    {
+        ProfScope prof(kProfDca, hs);
+        st = launch_dca(choose_variant(n_seeds, P, n_wires), track_xyz, n_seeds, P, n_wires,
+                        wire_offsets, drift, cfg->lambda_mm, workspace, hs);
     }
     if (st)
         return st;

@@ -19,11 +19,13 @@ using namespace cdev;
 using namespace chost;
 
 // One thread per seed: K RK4 steps in the map, positions stored [3][K + 1][S] with the
-// seed index fastest, so the stores of a wave are contiguous.
+// seed index fastest, so the stores of a wave are contiguous; with rho set, the chunk
+// radii of the track ([window][S]) are taken while recording.
 __global__ __launch_bounds__(256) void rk4_field_record_kernel(const double *__restrict__ seeds,
                                                                int64_t S, FieldMap m,
                                                                double charge, double h, int K,
-                                                               double *__restrict__ track)
+                                                               double *__restrict__ track,
+                                                               double *__restrict__ rho)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S)
@@ -37,18 +39,40 @@ __global__ __launch_bounds__(256) void rk4_field_record_kernel(const double *__r
     double *tx = track + s;
     double *ty = track + P * S + s;
     double *tz = track + 2 * P * S + s;
+    ChunkRadius cr;
+    double *rs = rho ? rho + s : nullptr;
     for (int j = 0; j < K; ++j) {
         tx[(int64_t)j * S] = x[0];
         ty[(int64_t)j * S] = x[1];
         tz[(int64_t)j * S] = x[2];
+        if (rs)
+            cr.add(j, K + 1, x[0], x[1], x[2], rs, S);
         rk4_field_step(m, inv, g, h, x, p);
     }
     tx[(int64_t)K * S] = x[0];
     ty[(int64_t)K * S] = x[1];
     tz[(int64_t)K * S] = x[2];
+    if (rs)
+        cr.add(K, K + 1, x[0], x[1], x[2], rs, S);
 }
 
 }  // namespace
+
+namespace chost {
+
+int launch_field_record(const double *seeds6, int64_t S, const comet_field *field,
+                        double charge, double h, int K, double *track, double *rho,
+                        hipStream_t stream)
+{
+    const FieldMap m{field->b, field->nx, field->ny, field->nz, field->x0, field->y0,
+                     field->z0, field->dx, field->dy, field->dz};
+    const int threads = 256;
+    hipLaunchKernelGGL(rk4_field_record_kernel, dim3((unsigned)((S + threads - 1) / threads)),
+                       dim3(threads), 0, stream, seeds6, S, m, charge, h, K, track, rho);
+    return launched("rk4_field_record_kernel");
+}
+
+}  // namespace chost
 
 extern "C" {
 
@@ -70,15 +94,9 @@ int comet_extrapolate_seeds_field(const double *seeds6, int64_t n_seeds, const c
     st = check_device();
     if (st)
         return st;
-    const FieldMap m{field->b, field->nx, field->ny, field->nz, field->x0, field->y0,
-                     field->z0, field->dx, field->dy, field->dz};
-    const int threads = 256;
     ProfScope prof(kProfTrack, (hipStream_t)stream);
-    hipLaunchKernelGGL(rk4_field_record_kernel,
-                       dim3((unsigned)((n_seeds + threads - 1) / threads)), dim3(threads), 0,
-                       (hipStream_t)stream, seeds6, n_seeds, m, cfg->charge_e, cfg->step_mm,
-                       cfg->n_steps, track_xyz);
-    return launched("rk4_field_record_kernel");
+    return launch_field_record(seeds6, n_seeds, field, cfg->charge_e, cfg->step_mm,
+                               cfg->n_steps, track_xyz, nullptr, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -27,6 +27,11 @@ size_t align256(size_t v);
 // Checks a comet_field (not the map's values): b set, nx, ny, nz >= 2, reserved 0,
 // finite origin, spacings > 0.
 int check_field(const char *who, const comet_field *field);
+// Launches the field map's track recording (one thread per seed); rho, when set,
+// receives the track's chunk radii [window][S] taken while recording.
+int launch_field_record(const double *seeds6, int64_t S, const comet_field *field,
+                        double charge, double h, int K, double *track, double *rho,
+                        hipStream_t stream);
 
 // Kernel kinds for comet_profile_end().
 enum { kProfTrack = 0, kProfDca = 1, kProfSum = 2, kProfSelect = 3 };

@@ -68,12 +68,8 @@ class PartitionScanner:
             if it:
                 comet.refine_grid(self.grid, self.n, self.best)
             comet.seed_grid(self.grid, self.n, self.seeds)
-            if self.field is None:
-                comet.extrapolate_seeds(self.seeds, self.cfg, self.track)
-            else:
-                comet.extrapolate_seeds_field(self.seeds, self.cfg, self.field, self.track)
-            comet.dca_rss(self.track, ev.wire_ends, ev.wire_offsets, ev.drift, self.cfg,
-                          self.rss, self.workspace)
+            comet.track_dca_rss(self.seeds, ev.wire_ends, ev.wire_offsets, ev.drift, self.cfg,
+                                self.track, self.rss, self.workspace, field=self.field)
             last = it == n_refine
             comet.select_classify(self.rss, self.best, self.cfg, self.track, ev.wire_ends,
                                   ev.wire_offsets, ev.drift,

@@ -399,3 +399,43 @@ def test_profile_counts_the_distance_evaluations(ev_signal):
         assert S * dev.n_wires * (P // 32) <= prof["scan_points"] <= 2 * full, far
         if far:
             assert prof["scan_points"] < 0.3 * full
+
+
+@pytest.mark.parametrize("K", [1, 16, 300, 1501])
+def test_fused_track_and_scan_equals_separate_calls(ev_signal, K):
+    """comet_track_dca_rss (the radii taken while recording) gives the track and RSS of
+    comet_extrapolate_seeds + comet_dca_rss bit for bit, in the uniform field and in a
+    field map, for step counts with and without a partial last window and a ragged seed
+    count; no wires gives zero RSS and still the track."""
+    sc = synth.ScanConfig("fused", (3, 5, 7, 9), (5.0, 5.0, 0.05, 0.05), K, 2.0, 0.8)
+    seeds = gpu_seeds(synth.grid_descriptor(ev_signal.ref_states[1], sc), _n(*sc.n))
+    cfg = scan.config_for(ev_signal, sc)
+    S = seeds.shape[1]
+    dev = scan.DeviceEvent.from_event(ev_signal)
+    d = dict(dtype=torch.float64, device="cuda")
+    fm = comet.FieldMap(*synth.solenoid_map())
+    uniform = None
+    for field in (None, fm):
+        t1 = torch.empty(3, K + 1, S, **d)
+        r1 = torch.empty(S, **d)
+        if field is None:
+            comet.extrapolate_seeds(seeds, cfg, t1)
+        else:
+            comet.extrapolate_seeds_field(seeds, cfg, field, t1)
+        comet.dca_rss(t1, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, r1,
+                      comet.dca_workspace(S, K + 1, dev.n_wires))
+        t2 = torch.full((3, K + 1, S), np.nan, **d)
+        r2 = torch.full((S,), np.nan, **d)
+        comet.track_dca_rss(seeds, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, t2, r2,
+                            comet.dca_workspace(S, K + 1, dev.n_wires), field=field)
+        torch.cuda.synchronize()
+        assert torch.equal(t1, t2) and torch.equal(r1, r2), (K, field is None)
+        if field is None:
+            uniform = t1
+    empty = torch.zeros(0, 6, **d)
+    t3 = torch.empty(3, K + 1, S, **d)
+    r3 = torch.full((S,), np.nan, **d)
+    comet.track_dca_rss(seeds, empty, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                        torch.zeros(0, **d), cfg, t3, r3, torch.zeros(1, **d))
+    torch.cuda.synchronize()
+    assert torch.equal(t3, uniform) and bool((r3 == 0).all())
