@@ -64,9 +64,9 @@ def stored_traffic(shape: dict):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    name = "dca_kernel<%d, %d, %d, %s, %s>" % (
+    name = "dca_kernel<%d, %d, %d, %s, %s, %d>" % (
         shape["w"], shape["nwv"], shape["chunk"], "true" if shape["chunk_argmin"] else "false",
-        "true" if shape.get("direct") else "false")
+        "true" if shape.get("direct") else "false", shape.get("runs", 1))
     if t.get("kernel_sha") != kernel_hash():
         return None
     return t.get("shapes", {}).get(name, {}).get("bytes_per_launch")

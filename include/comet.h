@@ -507,10 +507,15 @@ int comet_profile_scan_points(int64_t *points);
  *
  * comet_dca_set_variant(id) forces shape id for every call (-1 removes the override);
  * comet_dca_variant_for() reports the shape a call of that size would use;
- * comet_dca_variant_info() describes shape id (0 <= id < comet_dca_variant_count()). */
+ * comet_dca_variant_info() describes shape id (0 <= id < comet_dca_variant_count()):
+ * W wires per wave, NWV waves per block, chunk points, per-chunk argmin, XCD-aware
+ * block order, direct (every wave on its own, no LDS staging) and runs (direct shapes:
+ * chunks tested in runs of that many first, from the summed radii of their windows;
+ * 1 = no runs); direct and runs may be NULL. */
 int comet_dca_variant_count(void);
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
-                           int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct);
+                           int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct,
+                           int32_t *runs);
 int comet_dca_set_variant(int id);
 int comet_dca_variant_for(int64_t n_seeds, int32_t n_points, int32_t n_wires);
 int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_points,

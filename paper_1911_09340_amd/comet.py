@@ -65,7 +65,7 @@ def load(path: str = LIB_PATH):
     lib.comet_last_error.restype = ctypes.c_char_p
     lib.comet_version.restype = ctypes.c_int
     lib.comet_dca_variant_count.restype = ctypes.c_int
-    lib.comet_dca_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4, I4, I4]
+    lib.comet_dca_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4, I4, I4, I4]
     lib.comet_dca_variant_for.argtypes = [_i64, _i32, _i32]
     lib.comet_dca_variant_for.restype = ctypes.c_int
     lib.comet_dca_autotune.argtypes = [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _i32,
@@ -271,12 +271,12 @@ def dca_variants():
     lib = load()
     out = []
     for i in range(lib.comet_dca_variant_count()):
-        v = [ctypes.c_int32() for _ in range(6)]
+        v = [ctypes.c_int32() for _ in range(7)]
         _check(lib.comet_dca_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_dca_variant_info")
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value,
                         chunk_argmin=bool(v[3].value), xcd_remap=bool(v[4].value),
-                        direct=bool(v[5].value)))
+                        direct=bool(v[5].value), runs=v[6].value))
     return out
 
 

@@ -163,16 +163,17 @@ __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad
 // Registers are capped for 4 waves per SIMD (two 8-wave blocks or one 16-wave block
 // per CU); the frames live in scalar registers, so only the running minima, the
 // staged point and the prefetch buffer occupy vector registers.
-template <int W, int NWV, int C, bool CHUNK_ARGMIN, bool DIRECT>
+template <int W, int NWV, int C, bool CHUNK_ARGMIN, bool DIRECT, int SUP>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) void dca_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames,
     int n_w, const int32_t *__restrict__ offsets, const double *__restrict__ drift,
     double lambda, const double *__restrict__ rho, double *__restrict__ dsq, int n_groups,
     int n_blocks, int xcd_remap, unsigned long long *counter)
 {
-    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN, true>,
+    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN, true, SUP>,
                                     TileScan<W, NWV, C, CHUNK_ARGMIN>>;
-    using ScanFar = std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN, false>, Scan>;
+    using ScanFar =
+        std::conditional_t<DIRECT, TileScanDirect<W, C, CHUNK_ARGMIN, false, SUP>, Scan>;
     __shared__ __align__(16) double lds[Scan::kLdsDoubles];
 
     const int b = blockIdx.x;
@@ -337,32 +338,37 @@ __global__ void fill_kernel(double *__restrict__ out, int64_t n, double v)
 
 // ------------------------------------------------------------------ DCA variants
 struct DcaVariant {
-    int w, nwv, c, chunk_argmin, xcd_remap, direct;
+    int w, nwv, c, chunk_argmin, xcd_remap, direct, sup;
     void (*kernel)(const double *, int64_t, int, const double *, int, const int32_t *,
                    const double *, double, const double *, double *, int, int, int,
                    unsigned long long *);
 };
 
 const DcaVariant kDcaVariants[] = {
-    {6, 8, 16, 1, 1, 0, dca_kernel<6, 8, 16, true, false>},
-    {6, 8, 16, 1, 0, 0, dca_kernel<6, 8, 16, true, false>},
-    {6, 16, 16, 1, 1, 0, dca_kernel<6, 16, 16, true, false>},
-    {5, 16, 16, 1, 1, 0, dca_kernel<5, 16, 16, true, false>},
-    {4, 16, 16, 1, 1, 0, dca_kernel<4, 16, 16, true, false>},
-    {4, 8, 32, 0, 1, 0, dca_kernel<4, 8, 32, false, false>},
-    {4, 8, 32, 1, 1, 0, dca_kernel<4, 8, 32, true, false>},
-    {4, 8, 16, 1, 1, 0, dca_kernel<4, 8, 16, true, false>},
-    {5, 8, 16, 1, 1, 0, dca_kernel<5, 8, 16, true, false>},
-    {3, 8, 32, 1, 1, 0, dca_kernel<3, 8, 32, true, false>},
-    {4, 16, 32, 1, 1, 0, dca_kernel<4, 16, 32, true, false>},
-    {3, 16, 32, 1, 1, 0, dca_kernel<3, 16, 32, true, false>},
+    {6, 8, 16, 1, 1, 0, 1, dca_kernel<6, 8, 16, true, false, 1>},
+    {6, 8, 16, 1, 0, 0, 1, dca_kernel<6, 8, 16, true, false, 1>},
+    {6, 16, 16, 1, 1, 0, 1, dca_kernel<6, 16, 16, true, false, 1>},
+    {5, 16, 16, 1, 1, 0, 1, dca_kernel<5, 16, 16, true, false, 1>},
+    {4, 16, 16, 1, 1, 0, 1, dca_kernel<4, 16, 16, true, false, 1>},
+    {4, 8, 32, 0, 1, 0, 1, dca_kernel<4, 8, 32, false, false, 1>},
+    {4, 8, 32, 1, 1, 0, 1, dca_kernel<4, 8, 32, true, false, 1>},
+    {4, 8, 16, 1, 1, 0, 1, dca_kernel<4, 8, 16, true, false, 1>},
+    {5, 8, 16, 1, 1, 0, 1, dca_kernel<5, 8, 16, true, false, 1>},
+    {3, 8, 32, 1, 1, 0, 1, dca_kernel<3, 8, 32, true, false, 1>},
+    {4, 16, 32, 1, 1, 0, 1, dca_kernel<4, 16, 32, true, false, 1>},
+    {3, 16, 32, 1, 1, 0, 1, dca_kernel<3, 16, 32, true, false, 1>},
     // every wave on its own (no LDS staging)
-    {4, 8, 16, 1, 1, 1, dca_kernel<4, 8, 16, true, true>},
-    {3, 8, 16, 1, 1, 1, dca_kernel<3, 8, 16, true, true>},
-    {2, 8, 16, 1, 1, 1, dca_kernel<2, 8, 16, true, true>},
-    {4, 4, 16, 1, 1, 1, dca_kernel<4, 4, 16, true, true>},
-    {3, 4, 16, 1, 1, 1, dca_kernel<3, 4, 16, true, true>},
-    {4, 8, 32, 1, 1, 1, dca_kernel<4, 8, 32, true, true>},
+    {4, 8, 16, 1, 1, 1, 1, dca_kernel<4, 8, 16, true, true, 1>},
+    {3, 8, 16, 1, 1, 1, 1, dca_kernel<3, 8, 16, true, true, 1>},
+    {2, 8, 16, 1, 1, 1, 1, dca_kernel<2, 8, 16, true, true, 1>},
+    {4, 4, 16, 1, 1, 1, 1, dca_kernel<4, 4, 16, true, true, 1>},
+    {3, 4, 16, 1, 1, 1, 1, dca_kernel<3, 4, 16, true, true, 1>},
+    {4, 8, 32, 1, 1, 1, 1, dca_kernel<4, 8, 32, true, true, 1>},
+    // runs of 4 chunks tested first (two-level distance bound)
+    {4, 4, 16, 1, 1, 1, 4, dca_kernel<4, 4, 16, true, true, 4>},
+    {3, 4, 16, 1, 1, 1, 4, dca_kernel<3, 4, 16, true, true, 4>},
+    {4, 8, 16, 1, 1, 1, 4, dca_kernel<4, 8, 16, true, true, 4>},
+    {4, 4, 16, 1, 1, 1, 2, dca_kernel<4, 4, 16, true, true, 2>},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
 constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above
@@ -832,7 +838,8 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
 int comet_dca_variant_count(void) { return kNumDcaVariants; }
 
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
-                           int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct)
+                           int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct,
+                           int32_t *runs)
 {
     if (id < 0 || id >= kNumDcaVariants || !w || !nwv || !chunk || !chunk_argmin || !xcd_remap)
         return fail(COMET_EINVAL, "comet_dca_variant_info: bad id or NULL pointer");
@@ -843,6 +850,8 @@ int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
     *xcd_remap = kDcaVariants[id].xcd_remap;
     if (direct)
         *direct = kDcaVariants[id].direct;
+    if (runs)
+        *runs = kDcaVariants[id].sup;
     return COMET_OK;
 }
 

@@ -388,7 +388,7 @@ struct TileScan {
 // coordinate's rows, from the tile's first seed on, span less than 4 GiB) the loads
 // are buffer loads whose per-lane offset is fixed and whose row offset is a scalar,
 // so no per-point address arithmetic runs on the vector unit.
-template <int W, int C, bool CHUNK_ARGMIN, bool BUF>
+template <int W, int C, bool CHUNK_ARGMIN, bool BUF, int SUP = 1>
 struct TileScanDirect {
     static constexpr int kLdsDoubles = 1;
 
@@ -481,97 +481,128 @@ struct TileScanDirect {
             for (int w = 0; w < W; ++w)
                 sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
 
-            for (int k0 = 0; k0 < P; k0 += C) {
-                const int kn = min(C, P - k0);
-                double x, y, z, q0[W];
-                load(k0, x, y, z);
-                double r = 0.0;
-                if (kn == C) {
-                    const int nr = k0 / kRadiusChunk;
-                    r = rho[(int64_t)nr * ldr + col];
-                    if (C == 2 * kRadiusChunk)
-                        r = r + rho[(int64_t)(nr + 1) * ldr + col];
-                }
-                const float rf = (float)r * 1.000001f;
-                bool lane_need = false;
+            // Runs of SUP chunks first get one test from their first point with the sum
+            // of their windows' radii (consecutive windows share their end points, so
+            // every point of the run lies within that sum of its first point); a run
+            // that no lane and wire needs is skipped whole, otherwise each chunk is
+            // tested as usual. A run reaching past the track's end is tested per chunk.
+            for (int s0 = 0; s0 < P; s0 += SUP * C) {
+                const int s1 = min(P, s0 + SUP * C);
+                if (SUP > 1 && s0 + SUP * C <= P) {
+                    double x, y, z;
+                    load(s0, x, y, z);
+                    const int nr = s0 / kRadiusChunk;
+                    double r = 0.0;
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    q0[w] = proj_q(w, x, y, z);
-                    if (w < nw) {
-                        const float B = fmaf(rf + sub[w], 1.000001f, 1e-6f);
-                        lane_need = lane_need ||
-                                    !((float)q0[w] * 0.999999f > (B * B) * 1.000001f);
-                    }
-                }
-                evals += nw;
-                // the partial last chunk is always scanned
-                if (kn < C || __builtin_amdgcn_ballot_w64(lane_need && seed) != 0) {
-                    evals += (int64_t)nw * (kn - 1);
+                    for (int i = 0; i < SUP * C / kRadiusChunk; ++i)
+                        r = r + rho[(int64_t)(nr + i) * ldr + col];
+                    const float rf = (float)r * 1.000001f;
+                    bool lane_need = false;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        if (CHUNK_ARGMIN) {
-                            cmin[w] = q0[w];
-                        } else {
-                            kbest[w] = q0[w] < best[w] ? k0 : kbest[w];
-                            best[w] = fmin(best[w], q0[w]);
+                        const double q = proj_q(w, x, y, z);
+                        if (w < nw) {
+                            const float B = fmaf(rf + sub[w], 1.000001f, 1e-6f);
+                            lane_need = lane_need ||
+                                        !((float)q * 0.999999f > (B * B) * 1.000001f);
                         }
                     }
-                    auto use = [&](int k, double px, double py, double pz) {
+                    evals += nw;
+                    if (__builtin_amdgcn_ballot_w64(lane_need && seed) == 0)
+                        continue;
+                }
+                for (int k0 = s0; k0 < s1; k0 += C) {
+                    const int kn = min(C, P - k0);
+                    double x, y, z, q0[W];
+                    load(k0, x, y, z);
+                    double r = 0.0;
+                    if (kn == C) {
+                        const int nr = k0 / kRadiusChunk;
+                        r = rho[(int64_t)nr * ldr + col];
+                        if (C == 2 * kRadiusChunk)
+                            r = r + rho[(int64_t)(nr + 1) * ldr + col];
+                    }
+                    const float rf = (float)r * 1.000001f;
+                    bool lane_need = false;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        q0[w] = proj_q(w, x, y, z);
+                        if (w < nw) {
+                            const float B = fmaf(rf + sub[w], 1.000001f, 1e-6f);
+                            lane_need = lane_need ||
+                                        !((float)q0[w] * 0.999999f > (B * B) * 1.000001f);
+                        }
+                    }
+                    evals += nw;
+                    // the partial last chunk is always scanned
+                    if (kn < C || __builtin_amdgcn_ballot_w64(lane_need && seed) != 0) {
+                        evals += (int64_t)nw * (kn - 1);
 #pragma unroll
                         for (int w = 0; w < W; ++w) {
-                            const double q = proj_q(w, px, py, pz);
                             if (CHUNK_ARGMIN) {
-                                cmin[w] = fmin(cmin[w], q);
+                                cmin[w] = q0[w];
                             } else {
-                                kbest[w] = q < best[w] ? k : kbest[w];
-                                best[w] = fmin(best[w], q);
+                                kbest[w] = q0[w] < best[w] ? k0 : kbest[w];
+                                best[w] = fmin(best[w], q0[w]);
                             }
                         }
-                    };
-                    if (kn == C) {
-                        // points 1 .. C-1 in batches of 3, the next batch loading while
-                        // the current one is used
-                        constexpr int NB = (C + 1) / 3;
-                        double cx[3], cy[3], cz[3];
-                        auto load3 = [&](int b, double (&x)[3], double (&y)[3], double (&z)[3]) {
+                        auto use = [&](int k, double px, double py, double pz) {
 #pragma unroll
-                            for (int i = 0; i < 3; ++i)
-                                if (1 + 3 * b + i < C)
-                                    load(k0 + 1 + 3 * b + i, x[i], y[i], z[i]);
+                            for (int w = 0; w < W; ++w) {
+                                const double q = proj_q(w, px, py, pz);
+                                if (CHUNK_ARGMIN) {
+                                    cmin[w] = fmin(cmin[w], q);
+                                } else {
+                                    kbest[w] = q < best[w] ? k : kbest[w];
+                                    best[w] = fmin(best[w], q);
+                                }
+                            }
                         };
-                        load3(0, cx, cy, cz);
+                        if (kn == C) {
+                            // points 1 .. C-1 in batches of 3, the next batch loading while
+                            // the current one is used
+                            constexpr int NB = (C + 1) / 3;
+                            double cx[3], cy[3], cz[3];
+                            auto load3 = [&](int b, double (&x)[3], double (&y)[3], double (&z)[3]) {
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) {
-                            double nx[3], ny[3], nz[3];
-                            if (b + 1 < NB)
-                                load3(b + 1, nx, ny, nz);
+                                for (int i = 0; i < 3; ++i)
+                                    if (1 + 3 * b + i < C)
+                                        load(k0 + 1 + 3 * b + i, x[i], y[i], z[i]);
+                            };
+                            load3(0, cx, cy, cz);
 #pragma unroll
-                            for (int i = 0; i < 3; ++i)
-                                if (1 + 3 * b + i < C)
-                                    use(k0 + 1 + 3 * b + i, cx[i], cy[i], cz[i]);
+                            for (int b = 0; b < NB; ++b) {
+                                double nx[3], ny[3], nz[3];
+                                if (b + 1 < NB)
+                                    load3(b + 1, nx, ny, nz);
 #pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                cx[i] = nx[i];
-                                cy[i] = ny[i];
-                                cz[i] = nz[i];
+                                for (int i = 0; i < 3; ++i)
+                                    if (1 + 3 * b + i < C)
+                                        use(k0 + 1 + 3 * b + i, cx[i], cy[i], cz[i]);
+#pragma unroll
+                                for (int i = 0; i < 3; ++i) {
+                                    cx[i] = nx[i];
+                                    cy[i] = ny[i];
+                                    cz[i] = nz[i];
+                                }
+                            }
+                        } else {
+                            for (int kk = 1; kk < kn; ++kk) {
+                                double px, py, pz;
+                                load(k0 + kk, px, py, pz);
+                                use(k0 + kk, px, py, pz);
                             }
                         }
-                    } else {
-                        for (int kk = 1; kk < kn; ++kk) {
-                            double px, py, pz;
-                            load(k0 + kk, px, py, pz);
-                            use(k0 + kk, px, py, pz);
-                        }
-                    }
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        if (CHUNK_ARGMIN && cmin[w] < best[w]) {
-                            best[w] = cmin[w];
-                            kbest[w] = k0;
+                        for (int w = 0; w < W; ++w) {
+                            if (CHUNK_ARGMIN && cmin[w] < best[w]) {
+                                best[w] = cmin[w];
+                                kbest[w] = k0;
+                            }
+                            // the running minimum bounds the final one as well
+                            sub[w] = fminf(sub[w],
+                                           __builtin_amdgcn_sqrtf((float)best[w]) * 1.000001f);
                         }
-                        // the running minimum bounds the final one as well
-                        sub[w] = fminf(sub[w],
-                                       __builtin_amdgcn_sqrtf((float)best[w]) * 1.000001f);
                     }
                 }
             }
