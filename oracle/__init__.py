@@ -90,11 +90,12 @@ def _bind(lib):
     lib.oracle_rss_jacobian_field.restype = ctypes.c_double
     lib.oracle_rss_jacobian_field.argtypes = [_d, _d, _i32, _d, _d, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_int32, ctypes.c_double,
-                                              _d, ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _d]
+                                              _d, ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _d,
+                                              ctypes.c_int32]
     lib.oracle_lm_refine_field.restype = ctypes.c_double
     lib.oracle_lm_refine_field.argtypes = [_d, _d, _i32, _d, _d, _d, ctypes.c_int32, _d,
                                            ctypes.c_int32, _i32, _d, ctypes.c_int32,
-                                           ctypes.c_double, _i32]
+                                           ctypes.c_double, _i32, ctypes.c_int32]
     lib.oracle_self_refine.restype = ctypes.c_int32
     lib.oracle_self_refine.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _u8,
                                        ctypes.c_double, _u8]
@@ -104,6 +105,8 @@ def _bind(lib):
     lib.oracle_track_field.restype = None
     lib.oracle_track_field.argtypes = [_d, _d, _i32, _d, _d, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int32, _d]
+    lib.oracle_track_field_rkn.restype = None
+    lib.oracle_track_field_rkn.argtypes = lib.oracle_track_field.argtypes
     lib.oracle_sparse_select.restype = ctypes.c_int32
     lib.oracle_sparse_select.argtypes = [_d, _d, ctypes.c_int32, _i32, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int64), _d, _d]
@@ -245,7 +248,8 @@ class Oracle:
                                            _p(J), _p(e), _p(act, _u8), _p(grad))
         return {"rss": rss, "grad": grad, "D": D, "J": J, "resid": e, "active": act.astype(bool)}
 
-    def rss_jacobian_field(self, seed, fmap, charge, h, K, lam, wire_ends, offsets, drift):
+    def rss_jacobian_field(self, seed, fmap, charge, h, K, lam, wire_ends, offsets, drift,
+                           stepper=0):
         """rss_jacobian for the track in a field map (b [nz, ny, nx, 3], origin, step)."""
         b, origin, step = fmap
         b = np.ascontiguousarray(b, dtype=np.float64)
@@ -258,10 +262,11 @@ class Oracle:
         rss = self.lib.oracle_rss_jacobian_field(
             _p(_f64(seed)), _p(b), _p(n, _i32), _p(_f64(origin)), _p(_f64(step)), float(charge),
             float(h), int(K), float(lam), _p(ends), n_w, _p(_i32a(offsets), _i32),
-            _p(_f64(drift)), _p(D), _p(J), _p(e), _p(act, _u8), _p(grad))
+            _p(_f64(drift)), _p(D), _p(J), _p(e), _p(act, _u8), _p(grad), int(stepper))
         return {"rss": rss, "grad": grad, "D": D, "J": J, "resid": e, "active": act.astype(bool)}
 
-    def lm_refine_field(self, seed, fmap, cfg, K, wire_ends, offsets, drift, n_iter, mu0):
+    def lm_refine_field(self, seed, fmap, cfg, K, wire_ends, offsets, drift, n_iter, mu0,
+                        stepper=0):
         """lm_refine with tracks in a field map (cfg = [unused, charge, h, lambda])."""
         b, origin, step = fmap
         b = np.ascontiguousarray(b, dtype=np.float64)
@@ -273,7 +278,7 @@ class Oracle:
                                               _p(_f64(step)), _p(_f64(cfg)), int(K), _p(ends),
                                               ends.shape[0], _p(_i32a(offsets), _i32),
                                               _p(_f64(drift)), int(n_iter), float(mu0),
-                                              _p(acc, _i32))
+                                              _p(acc, _i32), int(stepper))
         return s, rss, int(acc[0])
 
     def lm_refine(self, seed, cfg, K, wire_ends, offsets, drift, n_iter, mu0):
@@ -377,14 +382,15 @@ class Oracle:
                                  _p(out))
         return out
 
-    def track_field(self, seed, fmap, charge, h, K):
-        """RK4 track in a field map: [K + 1, 3] positions."""
+    def track_field(self, seed, fmap, charge, h, K, stepper=0):
+        """Track in a field map, RK4 (stepper 0) or RKN (1): [K + 1, 3] positions."""
         b, origin, step = fmap
         b = _f64(b)
         n = np.array([b.shape[2], b.shape[1], b.shape[0]], np.int32)
         pts = np.empty((K + 1, 3))
-        self.lib.oracle_track_field(_p(_f64(seed)), _p(b), _p(n, _i32), _p(_f64(origin)),
-                                    _p(_f64(step)), charge, h, K, _p(pts))
+        fn = self.lib.oracle_track_field_rkn if stepper == 1 else self.lib.oracle_track_field
+        fn(_p(_f64(seed)), _p(b), _p(n, _i32), _p(_f64(origin)), _p(_f64(step)), charge, h, K,
+           _p(pts))
         return pts
 
     def topk(self, values, k):

@@ -803,6 +803,7 @@ typedef struct {
     const int32_t *offsets;
     const double *drift;
     const void *field; /* NULL: uniform field; else the map (oracle_field) */
+    int32_t stepper;   /* in the map: 0 RK4, 1 RKN */
 } lm_problem;
 
 static void lm_normal_equations(const lm_problem *pb, const double seed[6], double A[36],
@@ -855,7 +856,7 @@ double oracle_lm_refine(double seed[6], const double cfg[4], int32_t K, const do
                         int32_t n_wires, const int32_t *offsets, const double *drift,
                         int32_t n_iter, double mu0, int32_t *accepted)
 {
-    const lm_problem pb = {cfg, K, wire_ends, n_wires, offsets, drift, NULL};
+    const lm_problem pb = {cfg, K, wire_ends, n_wires, offsets, drift, NULL, 0};
     return lm_loop(&pb, seed, n_iter, mu0, accepted);
 }
 
@@ -1342,6 +1343,67 @@ void oracle_track_field(const double seed[6], const double *b, const int32_t n[3
         pts[3 * K + c] = x[c];
 }
 
+/* Runge-Kutta-Nystrom in a field map (the paper's tracks are extrapolated with RKN):
+ * Nystrom's fourth-order method for the second-order equation x'' = a(x, x') in arc
+ * length, with the unit direction t = x' (t = p / p0 at the seed) and
+ * a(x, t) = g (t x B(x)), g = (KAPPA q) / p0, cross product as in field_force:
+ *   a1 = a(x, t)
+ *   xm = (x + h/2 t) + h^2/8 a1;  a2 = a(xm, t + h/2 a1);  a3 = a(xm, t + h/2 a2)
+ *   xe = (x + h t) + h^2/2 a3;    a4 = a(xe, t + h a3)
+ *   x <- (x + h t) + h^2/6 ((a1 + a2) + a3)
+ *   t <- t + h/6 (((a1 + 2 a2) + 2 a3) + a4)
+ * with hh = 0.5 h, h6 = h / 6, q8 = (h h) / 8, q2 = (h h) * 0.5, q6 = (h h) / 6. a2 and
+ * a3 share one read of B at xm: three reads of the map per step instead of RK4's four. */
+static void accel(double g, const double t[3], const double B[3], double a[3])
+{
+    a[0] = g * (t[1] * B[2] - t[2] * B[1]);
+    a[1] = g * (t[2] * B[0] - t[0] * B[2]);
+    a[2] = g * (t[0] * B[1] - t[1] * B[0]);
+}
+
+void oracle_track_field_rkn(const double seed[6], const double *b, const int32_t n[3],
+                            const double origin[3], const double step[3], double charge,
+                            double h, int32_t K, double *pts)
+{
+    oracle_field fm = {b, n[0], n[1], n[2], origin[0], origin[1], origin[2],
+                       step[0], step[1], step[2]};
+    const double p0 = sqrt((seed[3] * seed[3] + seed[4] * seed[4]) + seed[5] * seed[5]);
+    const double inv = 1.0 / p0;
+    const double g = (ORACLE_KAPPA * charge) * inv;
+    const double hh = 0.5 * h, h6 = h / 6.0;
+    const double q8 = (h * h) / 8.0, q2 = (h * h) * 0.5, q6 = (h * h) / 6.0;
+    double x[3] = {seed[0], seed[1], seed[2]};
+    double t[3] = {seed[3] * inv, seed[4] * inv, seed[5] * inv};
+    for (int32_t j = 0; j < K; ++j) {
+        for (int c = 0; c < 3; ++c)
+            pts[3 * j + c] = x[c];
+        double B[3], a1[3], a2[3], a3[3], a4[3], xs[3], ts[3];
+        field_at(&fm, x[0], x[1], x[2], B);
+        accel(g, t, B, a1);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = (x[c] + hh * t[c]) + q8 * a1[c];
+            ts[c] = t[c] + hh * a1[c];
+        }
+        field_at(&fm, xs[0], xs[1], xs[2], B);
+        accel(g, ts, B, a2);
+        for (int c = 0; c < 3; ++c)
+            ts[c] = t[c] + hh * a2[c];
+        accel(g, ts, B, a3);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = (x[c] + h * t[c]) + q2 * a3[c];
+            ts[c] = t[c] + h * a3[c];
+        }
+        field_at(&fm, xs[0], xs[1], xs[2], B);
+        accel(g, ts, B, a4);
+        for (int c = 0; c < 3; ++c) {
+            x[c] = (x[c] + h * t[c]) + q6 * ((a1[c] + a2[c]) + a3[c]);
+            t[c] = t[c] + h6 * (((a1[c] + 2.0 * a2[c]) + 2.0 * a3[c]) + a4[c]);
+        }
+    }
+    for (int c = 0; c < 3; ++c)
+        pts[3 * K + c] = x[c];
+}
+
 /* Derivatives in a field map: the same per-wire outputs as oracle_rss_jacobian for the
  * track of oracle_track_field, in dual numbers. B(x) enters the chain through the
  * trilinear interpolation: the fractions t of a cell are duals, so each stage's force
@@ -1436,17 +1498,71 @@ static void dual_track_field(const double seed[6], const oracle_field *fm, doubl
         pts[3 * K + c] = x[c];
 }
 
+/* oracle_track_field_rkn in dual numbers (B and dB/dx shared by a2 and a3 as there). */
+static void dual_accel(dual g, const dual t[3], const dual B[3], dual a[3])
+{
+    a[0] = dmul(g, dsub(dmul(t[1], B[2]), dmul(t[2], B[1])));
+    a[1] = dmul(g, dsub(dmul(t[2], B[0]), dmul(t[0], B[2])));
+    a[2] = dmul(g, dsub(dmul(t[0], B[1]), dmul(t[1], B[0])));
+}
+
+static void dual_track_field_rkn(const double seed[6], const oracle_field *fm, double charge,
+                                 double h, int32_t K, dual *pts)
+{
+    dual x[3] = {dvar(seed[0], 0), dvar(seed[1], 1), dvar(seed[2], 2)};
+    dual p[3] = {dvar(seed[3], 3), dvar(seed[4], 4), dvar(seed[5], 5)};
+    const dual p0 = dsqrt(dadd(dadd(dmul(p[0], p[0]), dmul(p[1], p[1])), dmul(p[2], p[2])));
+    const dual inv = ddiv(dc(1.0), p0);
+    const dual g = dmul(dc(ORACLE_KAPPA * charge), inv);
+    const dual hh = dc(0.5 * h), hd = dc(h), h6 = dc(h / 6.0), two = dc(2.0);
+    const dual q8 = dc((h * h) / 8.0), q2 = dc((h * h) * 0.5), q6 = dc((h * h) / 6.0);
+    dual t[3] = {dmul(p[0], inv), dmul(p[1], inv), dmul(p[2], inv)};
+    for (int32_t j = 0; j < K; ++j) {
+        for (int c = 0; c < 3; ++c)
+            pts[3 * j + c] = x[c];
+        dual B[3], a1[3], a2[3], a3[3], a4[3], xs[3], ts[3];
+        dual_field_at(fm, x, B);
+        dual_accel(g, t, B, a1);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = dadd(dadd(x[c], dmul(hh, t[c])), dmul(q8, a1[c]));
+            ts[c] = dadd(t[c], dmul(hh, a1[c]));
+        }
+        dual_field_at(fm, xs, B);
+        dual_accel(g, ts, B, a2);
+        for (int c = 0; c < 3; ++c)
+            ts[c] = dadd(t[c], dmul(hh, a2[c]));
+        dual_accel(g, ts, B, a3);
+        for (int c = 0; c < 3; ++c) {
+            xs[c] = dadd(dadd(x[c], dmul(hd, t[c])), dmul(q2, a3[c]));
+            ts[c] = dadd(t[c], dmul(hd, a3[c]));
+        }
+        dual_field_at(fm, xs, B);
+        dual_accel(g, ts, B, a4);
+        for (int c = 0; c < 3; ++c) {
+            x[c] = dadd(dadd(x[c], dmul(hd, t[c])), dmul(q6, dadd(dadd(a1[c], a2[c]), a3[c])));
+            t[c] = dadd(t[c], dmul(h6, dadd(dadd(dadd(a1[c], dmul(two, a2[c])), dmul(two, a3[c])),
+                                            a4[c])));
+        }
+    }
+    for (int c = 0; c < 3; ++c)
+        pts[3 * K + c] = x[c];
+}
+
+/* stepper: 0 = RK4 (oracle_track_field), 1 = RKN (oracle_track_field_rkn). */
 double oracle_rss_jacobian_field(const double seed[6], const double *b, const int32_t n[3],
                                  const double origin[3], const double step[3], double charge,
                                  double h, int32_t K, double lambda, const double *wire_ends,
                                  int32_t n_wires, const int32_t *offsets, const double *drift,
                                  double *D, double *J, double *resid, uint8_t *active,
-                                 double grad[6])
+                                 double grad[6], int32_t stepper)
 {
     oracle_field fm = {b, n[0], n[1], n[2], origin[0], origin[1], origin[2],
                        step[0], step[1], step[2]};
     dual *pts = (dual *)malloc(sizeof(dual) * 3 * (size_t)(K + 1));
-    dual_track_field(seed, &fm, charge, h, K, pts);
+    if (stepper == 1)
+        dual_track_field_rkn(seed, &fm, charge, h, K, pts);
+    else
+        dual_track_field(seed, &fm, charge, h, K, pts);
     double rss = rss_of_dual_track(pts, K, lambda, wire_ends, n_wires, offsets, drift, D, J,
                                    resid, active, grad);
     free(pts);
@@ -1472,7 +1588,7 @@ static void lm_normal_equations(const lm_problem *pb, const double seed[6], doub
     const double origin[3] = {f->x0, f->y0, f->z0}, step[3] = {f->dx, f->dy, f->dz};
     *rss = oracle_rss_jacobian_field(seed, f->b, n, origin, step, pb->cfg[1], pb->cfg[2], pb->K,
                                      pb->cfg[3], pb->wire_ends, n_w, pb->offsets, pb->drift,
-                                     NULL, J, e, act, NULL);
+                                     NULL, J, e, act, NULL, pb->stepper);
     for (int r = 0; r < 36; ++r)
         A[r] = 0.0;
     for (int r = 0; r < 6; ++r)
@@ -1495,10 +1611,10 @@ double oracle_lm_refine_field(double seed[6], const double *b, const int32_t n[3
                               const double origin[3], const double step[3], const double cfg[4],
                               int32_t K, const double *wire_ends, int32_t n_wires,
                               const int32_t *offsets, const double *drift, int32_t n_iter,
-                              double mu0, int32_t *accepted)
+                              double mu0, int32_t *accepted, int32_t stepper)
 {
     const oracle_field fm = {b, n[0], n[1], n[2], origin[0], origin[1], origin[2],
                              step[0], step[1], step[2]};
-    const lm_problem pb = {cfg, K, wire_ends, n_wires, offsets, drift, &fm};
+    const lm_problem pb = {cfg, K, wire_ends, n_wires, offsets, drift, &fm, stepper};
     return lm_loop(&pb, seed, n_iter, mu0, accepted);
 }

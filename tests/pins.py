@@ -838,6 +838,11 @@ def pin_field_jacobian_fd(o):
     """In a field with gradients (so dB/dx matters: B_z changes by 0.2 % per 100 mm in x
     and by -0.1 % in y, B_x and B_y grow with z) the dual-number rows dD_i/d(seed) and the RSS gradient
     agree with central differences of the plain map tracking (1e-6 relative)."""
+    for stepper in (0, 1):
+        _field_jacobian_fd(o, stepper)
+
+
+def _field_jacobian_fd(o, stepper):
     ev = synth.event_plain(0)
     fm = _linear_map(ev.bz, 2e-5, 2e-5)
     lam, K, h = 1.5, 800, 2.0
@@ -846,7 +851,7 @@ def pin_field_jacobian_fd(o):
     for _ in range(10):
         seed = ev.ref_states[0] * (1 + rng.normal(0, 1e-3, 6))
         r = o.rss_jacobian_field(seed, fm, ev.charge, h, K, lam, ev.wire_ends, ev.wire_offsets,
-                                 ev.drift)
+                                 ev.drift, stepper=stepper)
         kink = False
         for i in range(ev.n_wires):
             j0, j1 = ev.wire_offsets[i], ev.wire_offsets[i + 1]
@@ -856,7 +861,7 @@ def pin_field_jacobian_fd(o):
             continue
 
         def track(s):
-            return o.track_field(s, fm, ev.charge, h, K)
+            return o.track_field(s, fm, ev.charge, h, K, stepper=stepper)
 
         def rss(s):
             return o.rss_track(track(s), ev.wire_ends, ev.wire_offsets, ev.drift, lam)
@@ -869,14 +874,14 @@ def pin_field_jacobian_fd(o):
         tested += 1
         if tested == 2:
             break
-    assert tested == 2, "too few kink-free test points"
+    assert tested == 2, ("too few kink-free test points", stepper)
 
 
-def _field_event(o, fm, seed, charge, h, K):
+def _field_event(o, fm, seed, charge, h, K, stepper=0):
     """Wires of the plain event's chamber with sigma = 0 hits from the map track of seed:
     every wire within 8 mm of the track gets one hit at exactly its DCA."""
     ev = synth.event_plain(0)
-    pts = o.track_field(seed, fm, charge, h, K)
+    pts = o.track_field(seed, fm, charge, h, K, stepper=stepper)
     D = np.array([np.sqrt(o.dca2(pts, o.wire_frame(e))[0]) for e in ev.wire_ends])
     keep = np.nonzero(D < 8.0)[0]
     return ev.wire_ends[keep], np.arange(len(keep) + 1, dtype=np.int32), D[keep]
@@ -890,16 +895,18 @@ def pin_field_lm_truth(o):
     fm = _linear_map(ev.bz, 2e-5, 2e-5)
     truth = ev.ref_states[0]
     K, h = 800, 2.0
-    ends, off, drift = _field_event(o, fm, truth, ev.charge, h, K)
-    assert len(drift) >= 20
-    cfg = [0.0, ev.charge, h, 1.0]
-    start = truth * np.array([1.0, 1.0, 1.0, 1.002, 0.998, 1.002])
-    start[0] += 0.2
-    pts0 = o.track_field(start, fm, ev.charge, h, K)
-    rss0 = o.rss_track(pts0, ends, off, drift, 1.0)
-    s, rss, acc = o.lm_refine_field(start, fm, cfg, K, ends, off, drift, 10, 1e-3)
-    assert acc >= 3 and rss < 1e-8 * rss0, (acc, rss, rss0)
-    assert abs(np.linalg.norm(s[3:]) - np.linalg.norm(truth[3:])) < 1e-3
+    for stepper in (0, 1):
+        ends, off, drift = _field_event(o, fm, truth, ev.charge, h, K, stepper)
+        assert len(drift) >= 20
+        cfg = [0.0, ev.charge, h, 1.0]
+        start = truth * np.array([1.0, 1.0, 1.0, 1.002, 0.998, 1.002])
+        start[0] += 0.2
+        pts0 = o.track_field(start, fm, ev.charge, h, K, stepper=stepper)
+        rss0 = o.rss_track(pts0, ends, off, drift, 1.0)
+        s, rss, acc = o.lm_refine_field(start, fm, cfg, K, ends, off, drift, 10, 1e-3,
+                                        stepper=stepper)
+        assert acc >= 3 and rss < 1e-8 * rss0, (stepper, acc, rss, rss0)
+        assert abs(np.linalg.norm(s[3:]) - np.linalg.norm(truth[3:])) < 1e-3, stepper
 
 
 def pin_field_lm_uniform(o):
@@ -921,3 +928,38 @@ def pin_field_lm_uniform(o):
 
 ALL_SIMPLE.extend([pin_field_jacobian_uniform, pin_field_jacobian_fd, pin_field_lm_truth,
                    pin_field_lm_uniform])
+
+
+def pin_field_rkn(o):
+    """Runge-Kutta-Nystrom in a map. A constant map B = (0, 0, 1 T) gives the helix within
+    the fourth-order error (there the field is constant, and the method is RK4's step
+    written in (x, t), so the two tracks differ only by rounding); each chord is h to the
+    arc's sagitta; in a field linear in the coordinates (trilinear exact
+    and smooth) halving h shrinks the endpoint error ~16x (fourth order, which needs the
+    h^2/8 and h^2/2 position terms and a3 from a2 at the midpoint)."""
+    b = np.zeros((3, 3, 3, 3))
+    b[..., 2] = 1.0
+    fm = (b, np.array([-2000.0, -2000.0, -2000.0]), np.array([2000.0, 2000.0, 2000.0]))
+    seed = synth.vertex_state(100.0, 1.1, 0.4)
+    pts = o.track_field(seed, fm, -1.0, 2.0, 600, stepper=1)
+    exact = synth.helix_state(seed, -1.0, 1.0, 2.0 * np.arange(601))[:, :3]
+    assert np.max(np.abs(pts - exact)) < 1e-4
+    rk4 = o.track_field(seed, fm, -1.0, 2.0, 600)
+    assert 0.0 < np.max(np.abs(pts - rk4)) < 1e-4
+    steps = np.linalg.norm(np.diff(pts, axis=0), axis=1)   # chords: h - h^3 / 24R^2
+    assert np.max(np.abs(steps - 2.0)) < 1e-5
+    g, Z = 0.5, 1000.0
+    xs = np.array([-1000.0, 1000.0])
+    zs = np.array([-1500.0, 1500.0])
+    K3, Y3, X3 = np.meshgrid(zs, xs, xs, indexing="ij")
+    lb = np.stack([-g * X3 / (2 * Z), -g * Y3 / (2 * Z), 1.0 + g * K3 / Z], axis=-1)
+    lin = (lb, np.array([-1000.0, -1000.0, -1500.0]), np.array([2000.0, 2000.0, 3000.0]))
+    seed = synth.vertex_state(90.0, 1.0, 0.7, vertex=(0.0, 0.0, -600.0))
+    L = 1200.0
+    ref = o.track_field(seed, lin, -1.0, 0.25, int(L / 0.25), stepper=1)[-1]
+    e = [np.linalg.norm(o.track_field(seed, lin, -1.0, h, int(L / h), stepper=1)[-1] - ref)
+         for h in (8.0, 4.0)]
+    assert 10.0 < e[0] / e[1] < 24.0, e
+
+
+ALL_SIMPLE.append(pin_field_rkn)

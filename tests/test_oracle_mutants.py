@@ -81,6 +81,10 @@ MUTANTS = {
     "field_dual_stage3_uses_v1": ("            xs[c] = dadd(x[c], dmul(hh, v2[c]));", "            xs[c] = dadd(x[c], dmul(hh, v1[c]));"),
     "field_dual_y_cell_from_x": ("    dual_cell(ddiv(dsub(x[1], dc(f->y0)), dc(f->dy)), f->ny, &j, &tv);", "    dual_cell(ddiv(dsub(x[0], dc(f->y0)), dc(f->dy)), f->ny, &j, &tv);"),
     "lm_field_uses_uniform": ("    if (!pb->field) {\n        normal_equations(", "    if (1) {\n        normal_equations("),
+    "rkn_midpoint_q2": ("            xs[c] = (x[c] + hh * t[c]) + q8 * a1[c];", "            xs[c] = (x[c] + hh * t[c]) + q2 * a1[c];"),
+    "rkn_a3_from_a1": ("        for (int c = 0; c < 3; ++c)\n            ts[c] = t[c] + hh * a2[c];\n        accel(g, ts, B, a3);", "        for (int c = 0; c < 3; ++c)\n            ts[c] = t[c] + hh * a1[c];\n        accel(g, ts, B, a3);"),
+    "rkn_x_drops_a3": ("            x[c] = (x[c] + h * t[c]) + q6 * ((a1[c] + a2[c]) + a3[c]);", "            x[c] = (x[c] + h * t[c]) + q6 * ((a1[c] + a2[c]) + a2[c]);"),
+    "rkn_dual_midpoint": ("            xs[c] = dadd(dadd(x[c], dmul(hh, t[c])), dmul(q8, a1[c]));", "            xs[c] = dadd(dadd(x[c], dmul(hh, t[c])), dmul(q2, a1[c]));"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
 }
 
