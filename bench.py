@@ -295,39 +295,42 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
 
 
 def bench_field(ev, sc, steps: int = 3):
-    """The signal workload's step with tracks recorded in the synthetic solenoid map
-    (the event's hits come from the uniform-field helix, so only the timing means
-    anything here)."""
+    """The signal workload's step with tracks recorded in the synthetic solenoid map,
+    with classical RK4 and with Runge-Kutta-Nystrom (the event's hits come from the
+    uniform-field helix, so only the timing means anything here)."""
     import torch
     from paper_1911_09340_amd import comet, scan, synth
-    fm = comet.FieldMap(*synth.solenoid_map())
     cfg = scan.config_for(ev, sc)
     dev = scan.DeviceEvent.from_event(ev)
     grids = [scan.grid_tensor(ev.ref_states[t], sc) for t in range(ev.n_turns)]
-    runners = [scan.PartitionScanner(sc.n, cfg, ev.n_wires, ev.n_hits, field=fm)
-               for _ in range(ev.n_turns)]
-
-    def step():
-        for t in range(ev.n_turns):
-            runners[t].run(dev, grids[t], sc.n_refine)
-    step()
-    torch.cuda.synchronize()
-    comet.profile_begin()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = comet.profile_end()
-    ms_trk, n_trk = prof["track"]
     P = sc.n_steps + 1
-    return {"map": "synthetic solenoid, 81 x 81 x 121 nodes, 25 mm, B_z = 1 T (1 + 0.1 (z / "
-                   "1.5 m)^2) with the matching radial field",
+    out = {"map": "synthetic solenoid, 81 x 81 x 121 nodes, 25 mm, B_z = 1 T (1 + 0.1 (z / "
+                  "1.5 m)^2) with the matching radial field"}
+    for name, stepper in (("rk4", 0), ("rkn", 1)):
+        fm = comet.FieldMap(*synth.solenoid_map(), stepper=stepper)
+        runners = [scan.PartitionScanner(sc.n, cfg, ev.n_wires, ev.n_hits, field=fm)
+                   for _ in range(ev.n_turns)]
+
+        def step():
+            for t in range(ev.n_turns):
+                runners[t].run(dev, grids[t], sc.n_refine)
+        step()
+        torch.cuda.synchronize()
+        comet.profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = comet.profile_end()
+        ms_trk, n_trk = prof["track"]
+        out[name] = {
             "ms_per_step": dt / steps * 1e3,
             "evals_per_s": ev.n_turns * (sc.n_refine + 1) * sc.n_seeds * ev.n_hits * steps / dt,
             "track_kernel_ms": ms_trk / n_trk,
             "track_write_gbs": 24.0 * P * sc.n_seeds / (ms_trk / n_trk * 1e-3) / 1e9,
             "dca_kernel_ms": prof["dca"][0] / prof["dca"][1]}
+    return out
 
 
 def bench_stress(events, sc, top_k: int = 64, n_iter: int = 8):
@@ -550,8 +553,10 @@ def main():
         log("signal workload with tracks in a field map ...")
         out["field_map"] = bench_field(ev, sc)
         fm = out["field_map"]
-        log("  %.1f ms per step (uniform field: %.1f), map track recording %.2f ms per scan"
-            % (fm["ms_per_step"], dt / args.steps * 1e3, fm["track_kernel_ms"]))
+        for name in ("rk4", "rkn"):
+            log("  %s: %.1f ms per step (uniform field: %.1f), map track recording %.2f ms per "
+                "scan" % (name, fm[name]["ms_per_step"], dt / args.steps * 1e3,
+                          fm[name]["track_kernel_ms"]))
     if batch_events:
         log("batched mix: %d events, persistent scans, HIP graph ..." % len(batch_events))
         out["batch"] = bench_batch(batch_events, synth.C2)

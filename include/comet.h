@@ -99,11 +99,18 @@ int comet_extrapolate_seeds(const double *seeds6, int64_t n_seeds, const comet_c
  * classical RK4 (every stage reads B at its own position), step cfg->step_mm,
  * cfg->n_steps steps; cfg->bz_tesla is not used. The output is as for
  * comet_extrapolate_seeds, so comet_dca_rss and comet_select_classify take it
- * unchanged. nx, ny, nz >= 2, reserved 0, spacings > 0. The caller owns the map. */
+ * unchanged. nx, ny, nz >= 2, spacings > 0. The caller owns the map.
+ * stepper 1 selects Runge-Kutta-Nystrom instead (the paper's extrapolation): Nystrom's
+ * fourth-order method for x'' = g (x' x B(x)) in the unit direction t = x' (t = p / |p|
+ * at the seed), a(x, t) = g (t x B): a1 = a(x, t); xm = (x + h/2 t) + h^2/8 a1;
+ * a2 = a(xm, t + h/2 a1); a3 = a(xm, t + h/2 a2); xe = (x + h t) + h^2/2 a3;
+ * a4 = a(xe, t + h a3); x <- (x + h t) + h^2/6 ((a1 + a2) + a3);
+ * t <- t + h/6 (((a1 + 2 a2) + 2 a3) + a4): three reads of the map per step. Every
+ * call that takes a comet_field honours it. */
 typedef struct comet_field {
     const double *b;
     int32_t nx, ny, nz;
-    int32_t reserved; /* must be 0 */
+    int32_t stepper; /* 0: classical RK4; 1: Runge-Kutta-Nystrom */
     double x0, y0, z0;
     double dx, dy, dz;
 } comet_field;

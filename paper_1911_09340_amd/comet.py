@@ -132,21 +132,22 @@ def make_config(bz: float, charge: float, step_mm: float, n_steps: int, lambda_m
 class Field(ctypes.Structure):
     """comet_field (host struct; b is a device pointer)."""
     _fields_ = [("b", _vp), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nz", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("stepper", ctypes.c_int32),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
 
 
 class FieldMap:
-    """A field map on the device: b [nz, ny, nx, 3] (tesla), origin and spacing (mm);
-    keeps the tensor alive for the struct's pointer."""
+    """A field map on the device: b [nz, ny, nx, 3] (tesla), origin and spacing (mm), and
+    the stepper (0 RK4, 1 Runge-Kutta-Nystrom); keeps the tensor alive for the struct's
+    pointer."""
 
-    def __init__(self, b, origin, step, device="cuda"):
+    def __init__(self, b, origin, step, stepper: int = 0, device="cuda"):
         self.b = torch.as_tensor(b, dtype=torch.float64, device=device).contiguous()
         if self.b.dim() != 4 or self.b.shape[3] != 3:
             raise ValueError("b must have shape [nz, ny, nx, 3]")
         nz, ny, nx = (int(v) for v in self.b.shape[:3])
-        self.struct = Field(_vp(self.b.data_ptr()), nx, ny, nz, 0, float(origin[0]),
+        self.struct = Field(_vp(self.b.data_ptr()), nx, ny, nz, int(stepper), float(origin[0]),
                             float(origin[1]), float(origin[2]), float(step[0]), float(step[1]),
                             float(step[2]))
 

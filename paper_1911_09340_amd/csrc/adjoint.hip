@@ -432,13 +432,21 @@ __global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs
     const double inv = 1.0 / p0;
     const double g = (kKappa * a.charge) * inv;
 
+    const bool rkn = m.stepper == 1;
+    const RknConsts kn = rkn_consts(a.h);
     if (threadIdx.x == 0) {
         double x[3] = {sd[0], sd[1], sd[2]}, p[3] = {sd[3], sd[4], sd[5]};
+        if (rkn)  // the unit direction
+            for (int c = 0; c < 3; ++c)
+                p[c] = p[c] * inv;
         for (int j = 0; j < a.K; ++j) {
             lx[j] = x[0];
             ly[j] = x[1];
             lz[j] = x[2];
-            rk4_field_step(m, inv, g, a.h, x, p);
+            if (rkn)
+                rkn_field_step(m, kn, g, x, p);
+            else
+                rk4_field_step(m, inv, g, a.h, x, p);
         }
         lx[a.K] = x[0];
         ly[a.K] = x[1];
@@ -509,6 +517,11 @@ __global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs
         dinv = -(dp0 * inv) * inv;
         dg = (kKappa * a.charge) * dinv;
     }
+    if (rkn)  // (p, dp) become the unit direction and its tangent
+        for (int c = 0; c < 3; ++c) {
+            dp[c] = dp[c] * inv + p[c] * dinv;
+            p[c] = p[c] * inv;
+        }
     const int n_win = a.K / kWin + 1;
     for (int w = 0; w < n_win; ++w) {
         const int base = w * kWin;
@@ -519,8 +532,12 @@ __global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs
                 bc[(k - base) * 3 + 0] = dx[0];
                 bc[(k - base) * 3 + 1] = dx[1];
                 bc[(k - base) * 3 + 2] = dx[2];
-                if (k < last)
-                    rk4_field_step_dir(m, inv, g, dinv, dg, a.h, x, p, dx, dp);
+                if (k < last) {
+                    if (rkn)
+                        rkn_field_step_dir(m, kn, g, dg, x, p, dx, dp);
+                    else
+                        rk4_field_step_dir(m, inv, g, dinv, dg, a.h, x, p, dx, dp);
+                }
             }
         }
         __syncthreads();
@@ -720,7 +737,8 @@ int launch_adjoint(const AdjArgs &a, hipStream_t hs, const FieldMap *fm = nullpt
 
 FieldMap field_map_of(const comet_field *f)
 {
-    return FieldMap{f->b, f->nx, f->ny, f->nz, f->x0, f->y0, f->z0, f->dx, f->dy, f->dz};
+    return FieldMap{f->b, f->nx, f->ny, f->nz, f->x0, f->y0, f->z0, f->dx, f->dy, f->dz,
+                    f->stepper};
 }
 
 }  // namespace

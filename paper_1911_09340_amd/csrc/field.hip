@@ -18,7 +18,8 @@ namespace {
 using namespace cdev;
 using namespace chost;
 
-// One thread per seed: K RK4 steps in the map, positions stored [3][K + 1][S] with the
+// One thread per seed: K steps in the map (RK4, or RKN when m.stepper is 1), positions
+// stored [3][K + 1][S] with the
 // seed index fastest, so the stores of a wave are contiguous; with rho set, the chunk
 // radii of the track ([window][S]) are taken while recording.
 __global__ __launch_bounds__(256) void rk4_field_record_kernel(const double *__restrict__ seeds,
@@ -41,13 +42,21 @@ __global__ __launch_bounds__(256) void rk4_field_record_kernel(const double *__r
     double *tz = track + 2 * P * S + s;
     ChunkRadius cr;
     double *rs = rho ? rho + s : nullptr;
+    const bool rkn = m.stepper == 1;
+    const RknConsts kn = rkn_consts(h);
+    if (rkn)  // Runge-Kutta-Nystrom carries the unit direction in p
+        for (int c = 0; c < 3; ++c)
+            p[c] = p[c] * inv;
     for (int j = 0; j < K; ++j) {
         tx[(int64_t)j * S] = x[0];
         ty[(int64_t)j * S] = x[1];
         tz[(int64_t)j * S] = x[2];
         if (rs)
             cr.add(j, K + 1, x[0], x[1], x[2], rs, S);
-        rk4_field_step(m, inv, g, h, x, p);
+        if (rkn)
+            rkn_field_step(m, kn, g, x, p);
+        else
+            rk4_field_step(m, inv, g, h, x, p);
     }
     tx[(int64_t)K * S] = x[0];
     ty[(int64_t)K * S] = x[1];
@@ -65,7 +74,7 @@ int launch_field_record(const double *seeds6, int64_t S, const comet_field *fiel
                         hipStream_t stream)
 {
     const FieldMap m{field->b, field->nx, field->ny, field->nz, field->x0, field->y0,
-                     field->z0, field->dx, field->dy, field->dz};
+                     field->z0, field->dx, field->dy, field->dz, field->stepper};
     const int threads = 256;
     hipLaunchKernelGGL(rk4_field_record_kernel, dim3((unsigned)((S + threads - 1) / threads)),
                        dim3(threads), 0, stream, seeds6, S, m, charge, h, K, track, rho);

@@ -24,6 +24,7 @@ struct FieldMap {
     const double *b;
     int nx, ny, nz;
     double x0, y0, z0, dx, dy, dz;
+    int stepper;  // 0: classical RK4 in (x, p); 1: Runge-Kutta-Nystrom in (x, t)
 };
 
 __device__ __forceinline__ double lerp(double a, double b, double t) { return fma(t, b - a, a); }
@@ -232,6 +233,122 @@ __device__ __forceinline__ void rk4_field_step_dir(const FieldMap &m, double inv
         p[c] = p[c] + h6 * (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]);
         dx[c] = dx[c] + h6 * (((dv1[c] + 2.0 * dv2[c]) + 2.0 * dv3[c]) + dv4[c]);
         dp[c] = dp[c] + h6 * (((df1[c] + 2.0 * df2[c]) + 2.0 * df3[c]) + df4[c]);
+    }
+}
+
+// ------------------------------------------------------------------ Runge-Kutta-Nystrom
+// Nystrom's fourth-order method for x'' = a(x, x') in arc length, with the unit
+// direction t = x' (t = p inv at the seed) and a(x, t) = g (t x B(x)):
+//   a1 = a(x, t)
+//   xm = (x + hh t) + q8 a1;  a2 = a(xm, t + hh a1);  a3 = a(xm, t + hh a2)
+//   xe = (x + h t) + q2 a3;   a4 = a(xe, t + h a3)
+//   x <- (x + h t) + q6 ((a1 + a2) + a3);  t <- t + h6 (((a1 + 2 a2) + 2 a3) + a4)
+// with hh = 0.5 h, h6 = h / 6, q8 = (h h) / 8, q2 = (h h) * 0.5, q6 = (h h) / 6; a2 and a3
+// share one read of B at xm, so a step reads the map three times (RK4: four).
+struct RknConsts {
+    double h, hh, h6, q8, q2, q6;
+};
+
+__device__ __forceinline__ RknConsts rkn_consts(double h)
+{
+    return RknConsts{h, 0.5 * h, h / 6.0, (h * h) / 8.0, (h * h) * 0.5, (h * h) / 6.0};
+}
+
+__device__ __forceinline__ void rkn_accel(double g, const double (&t)[3], const double (&B)[3],
+                                          double (&a)[3])
+{
+    a[0] = g * (t[1] * B[2] - t[2] * B[1]);
+    a[1] = g * (t[2] * B[0] - t[0] * B[2]);
+    a[2] = g * (t[0] * B[1] - t[1] * B[0]);
+}
+
+__device__ __forceinline__ void rkn_field_step(const FieldMap &m, const RknConsts &k, double g,
+                                               double (&x)[3], double (&t)[3])
+{
+    double B[3], a1[3], a2[3], a3[3], a4[3], xs[3], ts[3];
+    field_at(m, x[0], x[1], x[2], B);
+    rkn_accel(g, t, B, a1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xs[c] = (x[c] + k.hh * t[c]) + k.q8 * a1[c];
+        ts[c] = t[c] + k.hh * a1[c];
+    }
+    field_at(m, xs[0], xs[1], xs[2], B);
+    rkn_accel(g, ts, B, a2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        ts[c] = t[c] + k.hh * a2[c];
+    rkn_accel(g, ts, B, a3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xs[c] = (x[c] + k.h * t[c]) + k.q2 * a3[c];
+        ts[c] = t[c] + k.h * a3[c];
+    }
+    field_at(m, xs[0], xs[1], xs[2], B);
+    rkn_accel(g, ts, B, a4);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = (x[c] + k.h * t[c]) + k.q6 * ((a1[c] + a2[c]) + a3[c]);
+        t[c] = t[c] + k.h6 * (((a1[c] + 2.0 * a2[c]) + 2.0 * a3[c]) + a4[c]);
+    }
+}
+
+// a = g (t x B) and its derivative along (dt, dB) with dg: dg (t x B) + g (dt x B + t x dB).
+__device__ __forceinline__ void rkn_accel_dir(double g, double dg, const double (&t)[3],
+                                              const double (&dt)[3], const double (&B)[3],
+                                              const double (&dB)[3], double (&a)[3],
+                                              double (&da)[3])
+{
+    rkn_accel(g, t, B, a);
+    const double q0 = (dt[1] * B[2] - dt[2] * B[1]) + (t[1] * dB[2] - t[2] * dB[1]);
+    const double q1 = (dt[2] * B[0] - dt[0] * B[2]) + (t[2] * dB[0] - t[0] * dB[2]);
+    const double q2 = (dt[0] * B[1] - dt[1] * B[0]) + (t[0] * dB[1] - t[1] * dB[0]);
+    da[0] = dg * (t[1] * B[2] - t[2] * B[1]) + g * q0;
+    da[1] = dg * (t[2] * B[0] - t[0] * B[2]) + g * q1;
+    da[2] = dg * (t[0] * B[1] - t[1] * B[0]) + g * q2;
+}
+
+// One RKN step (the primal exactly as rkn_field_step) with its tangent (dx, dt) along one
+// seed direction; dg is that direction's derivative of g.
+__device__ __forceinline__ void rkn_field_step_dir(const FieldMap &m, const RknConsts &k,
+                                                   double g, double dg, double (&x)[3],
+                                                   double (&t)[3], double (&dx)[3],
+                                                   double (&dt)[3])
+{
+    double B[3], dB[3], a1[3], a2[3], a3[3], a4[3], xs[3], ts[3];
+    double da1[3], da2[3], da3[3], da4[3], dxs[3], dts[3];
+    field_at_dir(m, x, dx, B, dB);
+    rkn_accel_dir(g, dg, t, dt, B, dB, a1, da1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xs[c] = (x[c] + k.hh * t[c]) + k.q8 * a1[c];
+        ts[c] = t[c] + k.hh * a1[c];
+        dxs[c] = (dx[c] + k.hh * dt[c]) + k.q8 * da1[c];
+        dts[c] = dt[c] + k.hh * da1[c];
+    }
+    field_at_dir(m, xs, dxs, B, dB);
+    rkn_accel_dir(g, dg, ts, dts, B, dB, a2, da2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ts[c] = t[c] + k.hh * a2[c];
+        dts[c] = dt[c] + k.hh * da2[c];
+    }
+    rkn_accel_dir(g, dg, ts, dts, B, dB, a3, da3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xs[c] = (x[c] + k.h * t[c]) + k.q2 * a3[c];
+        ts[c] = t[c] + k.h * a3[c];
+        dxs[c] = (dx[c] + k.h * dt[c]) + k.q2 * da3[c];
+        dts[c] = dt[c] + k.h * da3[c];
+    }
+    field_at_dir(m, xs, dxs, B, dB);
+    rkn_accel_dir(g, dg, ts, dts, B, dB, a4, da4);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = (x[c] + k.h * t[c]) + k.q6 * ((a1[c] + a2[c]) + a3[c]);
+        t[c] = t[c] + k.h6 * (((a1[c] + 2.0 * a2[c]) + 2.0 * a3[c]) + a4[c]);
+        dx[c] = (dx[c] + k.h * dt[c]) + k.q6 * ((da1[c] + da2[c]) + da3[c]);
+        dt[c] = dt[c] + k.h6 * (((da1[c] + 2.0 * da2[c]) + 2.0 * da3[c]) + da4[c]);
     }
 }
 

@@ -24,7 +24,7 @@ int launched(const char *what);
 int check_config(const comet_config *cfg);
 bool finite_pos(double v);
 size_t align256(size_t v);
-// Checks a comet_field (not the map's values): b set, nx, ny, nz >= 2, reserved 0,
+// Checks a comet_field (not the map's values): b set, nx, ny, nz >= 2, stepper 0 or 1,
 // finite origin, spacings > 0.
 int check_field(const char *who, const comet_field *field);
 // Launches the field map's track recording (one thread per seed); rho, when set,

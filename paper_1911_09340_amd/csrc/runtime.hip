@@ -98,10 +98,11 @@ int check_field(const char *who, const comet_field *field)
 {
     if (!field || !field->b)
         return fail(COMET_EINVAL, "%s: NULL field map", who);
-    if (field->nx < 2 || field->ny < 2 || field->nz < 2 || field->reserved != 0 ||
+    if (field->nx < 2 || field->ny < 2 || field->nz < 2 ||
+        (field->stepper != 0 && field->stepper != 1) ||
         !finite_pos(field->dx) || !finite_pos(field->dy) || !finite_pos(field->dz) ||
         !isfinite(field->x0) || !isfinite(field->y0) || !isfinite(field->z0))
-        return fail(COMET_EINVAL, "%s: need nx, ny, nz >= 2, reserved 0, finite origin, "
+        return fail(COMET_EINVAL, "%s: need nx, ny, nz >= 2, stepper 0 or 1, finite origin, "
                                   "spacings > 0", who);
     return COMET_OK;
 }

@@ -311,7 +311,7 @@ def test_field_call_rejects(lib):
     assert lib.comet_extrapolate_seeds_field(None, 4, ctypes.byref(cfg), ctypes.byref(good), _p(), None) == comet.EINVAL
     for field in (comet.Field(None, 3, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0),
                   comet.Field(_p(), 1, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0),
-                  comet.Field(_p(), 3, 3, 3, 1, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0),
+                  comet.Field(_p(), 3, 3, 3, 2, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0),
                   comet.Field(_p(), 3, 3, 3, 0, 0.0, 0.0, 0.0, 1.0, 0.0, 1.0)):
         assert lib.comet_extrapolate_seeds_field(_p(), 4, ctypes.byref(cfg), ctypes.byref(field),
                                                  _p(), None) == comet.EINVAL

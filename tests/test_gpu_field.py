@@ -23,8 +23,8 @@ def fmap():
     return synth.solenoid_map(g=0.3, z_scale=1000.0, half_xy=700.0, half_z=900.0)
 
 
-def _gpu_tracks(seeds, cfg, fmap):
-    f = comet.FieldMap(*fmap)
+def _gpu_tracks(seeds, cfg, fmap, stepper=0):
+    f = comet.FieldMap(*fmap, stepper=stepper)
     S = seeds.shape[1]
     track = torch.empty(3, cfg.n_steps + 1, S, dtype=torch.float64, device="cuda")
     comet.extrapolate_seeds_field(torch.as_tensor(np.ascontiguousarray(seeds), device="cuda"),
@@ -33,7 +33,8 @@ def _gpu_tracks(seeds, cfg, fmap):
     return track
 
 
-def test_field_tracks_match_cpu(orc, fmap):
+@pytest.mark.parametrize("stepper", [0, 1])
+def test_field_tracks_match_cpu(orc, fmap, stepper):
     ev = synth.event_mix(1)
     sc = synth.ScanConfig("field", (2, 3, 4, 5), (5.0, 5.0, 0.05, 0.05), 700, 2.0, 0.8, 0)
     g = synth.grid_descriptor(ev.ref_states[0], sc)
@@ -43,18 +44,20 @@ def test_field_tracks_match_cpu(orc, fmap):
                       [100.0, 50.0, -300.0, -40.0, 70.0, 10.0]]).T
     seeds = np.concatenate([seeds, extra], axis=1)
     cfg = comet.make_config(1.0, ev.charge, sc.step_mm, sc.n_steps, sc.lambda_mm)
-    got = _gpu_tracks(seeds, cfg, fmap).cpu().numpy()
+    got = _gpu_tracks(seeds, cfg, fmap, stepper).cpu().numpy()
     for s in range(seeds.shape[1]):
-        want = orc.track_field(seeds[:, s], fmap, ev.charge, sc.step_mm, sc.n_steps)
+        want = orc.track_field(seeds[:, s], fmap, ev.charge, sc.step_mm, sc.n_steps,
+                               stepper=stepper)
         assert np.array_equal(got[:, :, s].T, want), s
 
 
-def test_field_partition_rss_matches_cpu(orc, fmap):
+@pytest.mark.parametrize("stepper", [0, 1])
+def test_field_partition_rss_matches_cpu(orc, fmap, stepper):
     """A 3x4x5x6 grid scanned with map tracks: every RSS and the argmin, bit for bit."""
     ev = synth.event_mix(4)
     sc = synth.ScanConfig("field-p", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 600, 2.0, 0.8, 0)
     cfg = scan.config_for(ev, sc)
-    f = comet.FieldMap(*fmap)
+    f = comet.FieldMap(*fmap, stepper=stepper)
     r = scan.PartitionScanner(sc.n, cfg, ev.n_wires, ev.n_hits, field=f)
     dev = scan.DeviceEvent.from_event(ev)
     r.run(dev, scan.grid_tensor(ev.ref_states[0], sc), 0)
@@ -63,7 +66,7 @@ def test_field_partition_rss_matches_cpu(orc, fmap):
     g = synth.grid_descriptor(ev.ref_states[0], sc)
     seeds = orc.seed_grid(g, np.array(sc.n, np.int32))
     want = np.array([orc.rss_track(orc.track_field(seeds[:, s], fmap, ev.charge, sc.step_mm,
-                                                   sc.n_steps),
+                                                   sc.n_steps, stepper=stepper),
                                    ev.wire_ends, ev.wire_offsets, ev.drift, sc.lambda_mm)
                      for s in range(seeds.shape[1])])
     assert np.array_equal(got, want)
@@ -82,7 +85,8 @@ def _map_hits(orc, fmap, seed, charge, h, K):
     return wires[keep], np.arange(keep.size + 1, dtype=np.int32), drift
 
 
-def test_field_jacobian_matches_cpu(orc, fmap):
+@pytest.mark.parametrize("stepper", [0, 1])
+def test_field_jacobian_matches_cpu(orc, fmap, stepper):
     """Derivatives through the map (forward-mode tangents with dB/dx) vs the CPU dual
     numbers: D and residuals bit for bit, rows J_i, gradient and normal equations to
     1e-7 relative, RSS to 1e-12."""
@@ -101,13 +105,14 @@ def test_field_jacobian_matches_cpu(orc, fmap):
             ("dca", (S, n_w)), ("resid", (S, n_w)), ("jac", (S, n_w, 6)))}
     comet.rss_adjoint(torch.as_tensor(seeds, **d), cfg, torch.as_tensor(ends, **d),
                       torch.as_tensor(off, device="cuda"), torch.as_tensor(drift, **d),
-                      field=comet.FieldMap(*fmap), **out)
+                      field=comet.FieldMap(*fmap, stepper=stepper), **out)
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in out.items()}
     iu = np.triu_indices(6)
     n_active = 0
     for s in range(S):
-        r = orc.rss_jacobian_field(seeds[:, s], fmap, ev.charge, h, K, lam, ends, off, drift)
+        r = orc.rss_jacobian_field(seeds[:, s], fmap, ev.charge, h, K, lam, ends, off, drift,
+                                   stepper=stepper)
         assert np.array_equal(got["dca"][s], r["D"]), s
         assert np.array_equal(got["resid"][s], r["resid"]), s
         assert abs(got["rss"][s] - r["rss"]) <= 1e-12 * r["rss"], s
@@ -125,7 +130,8 @@ def test_field_jacobian_matches_cpu(orc, fmap):
     assert n_active >= 5 * S
 
 
-def test_field_lm_matches_cpu(orc, fmap):
+@pytest.mark.parametrize("stepper", [0, 1])
+def test_field_lm_matches_cpu(orc, fmap, stepper):
     """Levenberg-Marquardt in the map vs the CPU reference: the same accepted steps, the
     final seeds to 1e-7 relative and their RSS to 1e-9."""
     ev = synth.event_plain(0)
@@ -142,12 +148,12 @@ def test_field_lm_matches_cpu(orc, fmap):
     acc = torch.empty(S, dtype=torch.int32, device="cuda")
     comet.lm_refine(x, cfg, torch.as_tensor(ends, **d), torch.as_tensor(off, device="cuda"),
                     torch.as_tensor(drift, **d), 8, 1e-3, rss, comet.lm_workspace(S),
-                    n_accepted=acc, field=comet.FieldMap(*fmap))
+                    n_accepted=acc, field=comet.FieldMap(*fmap, stepper=stepper))
     torch.cuda.synchronize()
     gx, grss, gacc = x.cpu().numpy(), rss.cpu().numpy(), acc.cpu().numpy()
     for s in range(S):
         ws, wrss, wacc = orc.lm_refine_field(starts[:, s], fmap, [0.0, ev.charge, h, lam], K,
-                                             ends, off, drift, 8, 1e-3)
+                                             ends, off, drift, 8, 1e-3, stepper=stepper)
         assert gacc[s] == wacc and wacc >= 2, s
         np.testing.assert_allclose(gx[:, s], ws, rtol=1e-7, atol=1e-9)
         assert abs(grss[s] - wrss) <= 1e-9 * wrss, s

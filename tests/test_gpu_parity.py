@@ -414,8 +414,9 @@ def test_fused_track_and_scan_equals_separate_calls(ev_signal, K):
     dev = scan.DeviceEvent.from_event(ev_signal)
     d = dict(dtype=torch.float64, device="cuda")
     fm = comet.FieldMap(*synth.solenoid_map())
+    fm_rkn = comet.FieldMap(*synth.solenoid_map(), stepper=1)
     uniform = None
-    for field in (None, fm):
+    for field in (None, fm, fm_rkn):
         t1 = torch.empty(3, K + 1, S, **d)
         r1 = torch.empty(S, **d)
         if field is None:
