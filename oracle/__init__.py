@@ -69,6 +69,10 @@ def _bind(lib):
     lib.oracle_scan_partition.argtypes = [_d, _i32, _d, ctypes.c_int32, ctypes.c_int32, _d,
                                           ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _i32,
                                           ctypes.c_int32]
+    lib.oracle_scan_partition_field.restype = ctypes.c_int64
+    lib.oracle_scan_partition_field.argtypes = [_d, _i32, _d, _i32, _d, _d, ctypes.c_int32, _d,
+                                                ctypes.c_int32, ctypes.c_int32, _d,
+                                                ctypes.c_int32, _i32, _d, _d, _d, _d, _u8, _i32]
     lib.oracle_rss_jacobian.restype = ctypes.c_double
     lib.oracle_rss_jacobian.argtypes = [_d, _d, ctypes.c_int32, _d, ctypes.c_int32, _i32, _d, _d,
                                         _d, _d, _u8, _d]
@@ -232,6 +236,30 @@ class Oracle:
                                            _p(drift), _p(rss), _p(best_seed), _p(best_rss),
                                            _p(mask, _u8), _p(nb, _i32), n_threads)
         return {"best": int(b), "grid": g, "rss": rss, "best_seed": best_seed,
+                "best_rss": float(best_rss[0]), "mask": mask, "n_borderline": int(nb[0])}
+
+    def scan_partition_field(self, grid, n, fmap, stepper, cfg, K, n_refine, wire_ends, offsets,
+                             drift):
+        """scan_partition with tracks in a field map (cfg = [unused, charge, h, lambda])."""
+        b, origin, step = fmap
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        nmap = np.array([b.shape[2], b.shape[1], b.shape[0]], np.int32)
+        g = _f64(grid).copy()
+        n = _i32a(n)
+        S = int(np.prod(n.astype(np.int64)))
+        ends = _f64(wire_ends).reshape(-1, 6)
+        drift = _f64(drift)
+        rss = np.empty(S)
+        best_seed = np.zeros(6)
+        best_rss = np.zeros(1)
+        mask = np.zeros(drift.size, dtype=np.uint8)
+        nb = np.zeros(1, dtype=np.int32)
+        bi = self.lib.oracle_scan_partition_field(
+            _p(g), _p(n, _i32), _p(b), _p(nmap, _i32), _p(_f64(origin)), _p(_f64(step)),
+            int(stepper), _p(_f64(cfg)), K, n_refine, _p(ends), ends.shape[0],
+            _p(_i32a(offsets), _i32), _p(drift), _p(rss), _p(best_seed), _p(best_rss),
+            _p(mask, _u8), _p(nb, _i32))
+        return {"best": int(bi), "grid": g, "rss": rss, "best_seed": best_seed,
                 "best_rss": float(best_rss[0]), "mask": mask, "n_borderline": int(nb[0])}
 
     def rss_jacobian(self, seed, cfg, K, wire_ends, offsets, drift):

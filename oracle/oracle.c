@@ -404,12 +404,10 @@ int64_t oracle_argmin(const double *rss, int64_t S)
  * (strictly). mask[j]: bit 0 = classified, bit 1 = borderline (the wire's closest
  * hit has ||D - r| - lambda| < 1e-9 mm). dca[i] receives D_i (may be NULL).
  * Returns the number of borderline hits. */
-int32_t oracle_classify(const double seed[6], const double cfg[4], int32_t K,
-                        const double *wire_ends, int32_t n_wires, const int32_t *offsets,
-                        const double *drift, uint8_t *mask, double *dca)
+static int32_t classify_track(const double *pts, int32_t K, const double cfg[4],
+                              const double *wire_ends, int32_t n_wires, const int32_t *offsets,
+                              const double *drift, uint8_t *mask, double *dca)
 {
-    double *pts = (double *)malloc(sizeof(double) * 3 * (size_t)(K + 1));
-    oracle_track(seed, cfg[0], cfg[1], cfg[2], K, pts);
     int32_t n_border = 0;
     for (int32_t i = 0; i < n_wires; ++i) {
         double frame[8];
@@ -438,6 +436,17 @@ int32_t oracle_classify(const double seed[6], const double cfg[4], int32_t K,
             mask[jb] = m;
         }
     }
+    return n_border;
+}
+
+int32_t oracle_classify(const double seed[6], const double cfg[4], int32_t K,
+                        const double *wire_ends, int32_t n_wires, const int32_t *offsets,
+                        const double *drift, uint8_t *mask, double *dca)
+{
+    double *pts = (double *)malloc(sizeof(double) * 3 * (size_t)(K + 1));
+    oracle_track(seed, cfg[0], cfg[1], cfg[2], K, pts);
+    int32_t n_border = classify_track(pts, K, cfg, wire_ends, n_wires, offsets, drift, mask,
+                                      dca);
     free(pts);
     return n_border;
 }
@@ -1617,4 +1626,60 @@ double oracle_lm_refine_field(double seed[6], const double *b, const int32_t n[3
                              step[0], step[1], step[2]};
     const lm_problem pb = {cfg, K, wire_ends, n_wires, offsets, drift, &fm, stepper};
     return lm_loop(&pb, seed, n_iter, mu0, accepted);
+}
+
+/* The whole path for one turn partition (oracle_scan_partition's steps: grid scan,
+ * n_refine finer re-scans, classification at the final best) with every track in a
+ * field map, RK4 (stepper 0, oracle_track_field) or RKN (1, oracle_track_field_rkn);
+ * cfg = (unused, charge, h, lambda). Single-threaded. */
+int64_t oracle_scan_partition_field(double grid[14], const int32_t n[4], const double *b,
+                                    const int32_t nmap[3], const double origin[3],
+                                    const double step[3], int32_t stepper, const double cfg[4],
+                                    int32_t K, int32_t n_refine, const double *wire_ends,
+                                    int32_t n_wires, const int32_t *offsets, const double *drift,
+                                    double *rss_out, double *best_seed, double *best_rss,
+                                    uint8_t *mask, int32_t *n_border)
+{
+    const int64_t S = (int64_t)n[0] * n[1] * n[2] * n[3];
+    double *seeds = (double *)malloc(sizeof(double) * 6 * (size_t)S);
+    double *rss = rss_out ? rss_out : (double *)malloc(sizeof(double) * (size_t)S);
+    double *frames = (double *)malloc(sizeof(double) * 8 * (size_t)(n_wires > 0 ? n_wires : 1));
+    double *pts = (double *)malloc(sizeof(double) * 3 * (size_t)(K + 1));
+    for (int32_t i = 0; i < n_wires; ++i)
+        oracle_wire_frame(wire_ends + 6 * i, frames + 8 * i);
+    int64_t best = -1;
+    for (int32_t it = 0; it <= n_refine; ++it) {
+        if (it > 0)
+            oracle_refine_grid(grid, n, best);
+        oracle_seed_grid(grid, n, seeds);
+        for (int64_t s = 0; s < S; ++s) {
+            double seed[6];
+            for (int c = 0; c < 6; ++c)
+                seed[c] = seeds[c * S + s];
+            if (stepper == 1)
+                oracle_track_field_rkn(seed, b, nmap, origin, step, cfg[1], cfg[2], K, pts);
+            else
+                oracle_track_field(seed, b, nmap, origin, step, cfg[1], cfg[2], K, pts);
+            rss[s] = oracle_rss_track(pts, K + 1, frames, n_wires, offsets, drift, cfg[3]);
+        }
+        best = oracle_argmin(rss, S);
+    }
+    if (best >= 0) {
+        oracle_seed(grid, n, best, best_seed);
+        *best_rss = rss[best];
+        if (stepper == 1)
+            oracle_track_field_rkn(best_seed, b, nmap, origin, step, cfg[1], cfg[2], K, pts);
+        else
+            oracle_track_field(best_seed, b, nmap, origin, step, cfg[1], cfg[2], K, pts);
+        const int32_t nb = classify_track(pts, K, cfg, wire_ends, n_wires, offsets, drift, mask,
+                                          NULL);
+        if (n_border)
+            *n_border = nb;
+    }
+    free(pts);
+    free(frames);
+    free(seeds);
+    if (!rss_out)
+        free(rss);
+    return best;
 }

@@ -963,3 +963,28 @@ def pin_field_rkn(o):
 
 
 ALL_SIMPLE.append(pin_field_rkn)
+
+
+def pin_scan_partition_field_uniform(o):
+    """In a constant map B = (0, 0, B_z) the field-map partition path (RK4 and RKN) chooses
+    the uniform path's seed and classifies the same hits (the tracks agree to rounding, far
+    below the RSS gaps between seeds and the hits' distances from lambda)."""
+    ev = synth.event_plain(0, sigma=0.0)
+    b = np.zeros((2, 2, 2, 3))
+    b[..., 2] = ev.bz
+    fm = (b, np.array([-2000.0, -2000.0, -2000.0]), np.array([4000.0, 4000.0, 4000.0]))
+    sc = synth.ScanConfig("pf", (3, 3, 3, 3), (5.0, 5.0, 0.05, 0.05), 700, 2.0, 1.0, 1)
+    g = synth.grid_descriptor(ev.ref_states[0], sc)
+    n = np.array(sc.n, np.int32)
+    cfg = [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+    u = o.scan_partition(g, n, cfg, sc.n_steps, sc.n_refine, ev.wire_ends, ev.wire_offsets,
+                         ev.drift)
+    for stepper in (0, 1):
+        f = o.scan_partition_field(g, n, fm, stepper, cfg, sc.n_steps, sc.n_refine,
+                                   ev.wire_ends, ev.wire_offsets, ev.drift)
+        assert f["best"] == u["best"] and np.array_equal(f["mask"], u["mask"]), stepper
+        assert np.allclose(f["rss"], u["rss"], rtol=1e-9, atol=1e-12), stepper
+        assert (f["mask"] & 1).sum() >= 10
+
+
+ALL_SIMPLE.append(pin_scan_partition_field_uniform)
