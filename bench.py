@@ -294,6 +294,25 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
                          else None, len(v)] for k, v in sorted(by_turns.items())}}
 
 
+def bench_field_batched(events, sc, reps: int = 2):
+    """The batched persistent scan of the mix with every track in the solenoid map (RKN),
+    eager runs, device-synchronised wall time."""
+    import torch
+    from paper_1911_09340_amd import comet, scan, synth
+    fm = comet.FieldMap(*synth.solenoid_map(), stepper=1)
+    run = scan.BatchRunner(events, sc, field=fm)
+    run.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"events": len(events), "partitions": run.n_part, "stepper": "rkn",
+            "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "evals_per_s": run.evals_per_run / dt}
+
+
 def bench_field(ev, sc, steps: int = 3):
     """The signal workload's step with tracks recorded in the synthetic solenoid map,
     with classical RK4 and with Runge-Kutta-Nystrom (the event's hits come from the
@@ -553,6 +572,10 @@ def main():
         log("signal workload with tracks in a field map ...")
         out["field_map"] = bench_field(ev, sc)
         fm = out["field_map"]
+        if batch_events:
+            fm["batched_rkn"] = bench_field_batched(batch_events, synth.C2)
+            log("  batched mix in the map (RKN): %.1f events/s (uniform field: see batch)"
+                % fm["batched_rkn"]["events_per_s"])
         for name in ("rk4", "rkn"):
             log("  %s: %.1f ms per step (uniform field: %.1f), map track recording %.2f ms per "
                 "scan" % (name, fm[name]["ms_per_step"], dt / args.steps * 1e3,

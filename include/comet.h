@@ -345,6 +345,21 @@ int comet_sparse_select(const double *grids, const double *rss, int32_t n_groups
                         const int32_t n[4], int32_t n_ref, int64_t *ref_idx, double *ref_rss,
                         double *new_grids, double *ref_grids, int64_t *ref_local, void *stream);
 
+/* comet_batch_scan with every track recorded in the field map `field` (host struct as in
+ * comet_extrapolate_seeds_field; RK4 or RKN by its stepper; cfg->bz_tesla is not used),
+ * in the persistent kernel as there (one fixed kernel shape: W = 4, 8 waves, 16-point
+ * chunks, every wave on its own), and the classification with the map's track. */
+int comet_batch_scan_field(const double *wire_ends, int32_t n_wires,
+                           const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                           const int32_t *event_wires, int32_t n_events,
+                           const int32_t *part_event, int32_t n_partitions,
+                           const double *grids_init, double *grids, const int32_t n[4],
+                           const comet_config *cfg, const comet_field *field, int32_t n_refine,
+                           double *rss, int64_t *best, double *best_seed, double *best_rss,
+                           uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
+                           int64_t max_items, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
 /* The classification step of comet_batch_scan on its own (Sec. 2.1, hit classification
  * of the chosen seed): for partition p, seed best[p] of grids[p] (best[p] < 0: NaN seed,
  * empty mask) is extrapolated and its hits classified as comet_select_classify does.
@@ -357,6 +372,15 @@ int comet_batch_classify(const double *grids, int32_t n_partitions, const int32_
                          const int32_t *part_event, const comet_config *cfg, double *best_seed,
                          double *best_rss, uint8_t *hit_mask, int64_t mask_stride,
                          int32_t *n_borderline, void *stream);
+/* The same with the chosen seed's track in the field map `field`. */
+int comet_batch_classify_field(const double *grids, int32_t n_partitions, const int32_t n[4],
+                               const int64_t *best, const double *rss, const double *wire_ends,
+                               int32_t n_wires, const int32_t *wire_offsets,
+                               const double *drift, int32_t n_hits, const int32_t *event_wires,
+                               int32_t n_events, const int32_t *part_event,
+                               const comet_config *cfg, const comet_field *field,
+                               double *best_seed, double *best_rss, uint8_t *hit_mask,
+                               int64_t mask_stride, int32_t *n_borderline, void *stream);
 
 /* Half tracks (Sec. 3.1): a turn partition is scanned as two half tracks, entrance and
  * exit, each with its own hits; each side ends with its finally selected seeds and

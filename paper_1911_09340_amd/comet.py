@@ -431,6 +431,10 @@ def _bind_batch(lib):
                                      ctypes.POINTER(Config), _i32, _vp, _vp, _vp, _vp, _vp, _i64,
                                      _vp, _i64, _vp, ctypes.c_size_t, _vp]
     lib.comet_batch_scan.restype = ctypes.c_int
+    FP = ctypes.POINTER(Field)
+    args = list(lib.comet_batch_scan.argtypes)
+    lib.comet_batch_scan_field.argtypes = args[:13] + [FP] + args[13:]
+    lib.comet_batch_scan_field.restype = ctypes.c_int
     lib.comet_batch_variant_count.restype = ctypes.c_int
     lib.comet_batch_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4, I4]
     lib.comet_batch_variant_info.restype = ctypes.c_int
@@ -483,29 +487,36 @@ def batch_workspace(n_wires: int, n_steps: int, n_partitions: int, device=None) 
 def batch_scan(packed, part_event: torch.Tensor, grids: torch.Tensor, n, cfg: Config,
                n_refine: int, rss: torch.Tensor, best: torch.Tensor, workspace: torch.Tensor,
                best_seed=None, best_rss=None, hit_mask=None, n_borderline=None,
-               max_items: int = 0, grids_init=None) -> None:
-    """comet_batch_scan over packed events (scan.PackedEvents)."""
+               max_items: int = 0, grids_init=None, field: FieldMap = None) -> None:
+    """comet_batch_scan over packed events (scan.PackedEvents); with a field map,
+    comet_batch_scan_field (tracks in the map)."""
     lib = _bind_batch(load())
     NP = int(part_event.shape[0])
     S = int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
     n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
     n_e = int(packed.event_wires.shape[0]) - 1
     stride = int(hit_mask.shape[1]) if hit_mask is not None else 0
-    _check(lib.comet_batch_scan(
+    if field is None:
+        fn, name, fld = lib.comet_batch_scan, "comet_batch_scan", ()
+    else:
+        _ptr(field.b, torch.float64, "field.b")
+        fn, name = lib.comet_batch_scan_field, "comet_batch_scan_field"
+        fld = (ctypes.byref(field.struct),)
+    _check(fn(
         _ptr(packed.wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
         _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
         _ptr(packed.drift, torch.float64, "drift", (n_h,)), n_h,
         _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e,
         _ptr(part_event, torch.int32, "part_event", (NP,)), NP,
         _ptr(grids_init, torch.float64, "grids_init", (NP, 14), optional=True),
-        _ptr(grids, torch.float64, "grids", (NP, 14)), _n4(n), ctypes.byref(cfg), int(n_refine),
+        _ptr(grids, torch.float64, "grids", (NP, 14)), _n4(n), ctypes.byref(cfg), *fld,
+        int(n_refine),
         _ptr(rss, torch.float64, "rss", (NP, S)), _ptr(best, torch.int64, "best", (NP,)),
         _ptr(best_seed, torch.float64, "best_seed", (NP, 6), optional=True),
         _ptr(best_rss, torch.float64, "best_rss", (NP,), optional=True),
         _ptr(hit_mask, torch.uint8, "hit_mask", (NP, stride), optional=True), stride,
         _ptr(n_borderline, torch.int32, "n_borderline", (NP,), optional=True), int(max_items),
-        _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()),
-        "comet_batch_scan")
+        _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()), name)
 
 
 def batch_variants():

@@ -25,6 +25,7 @@
 #include "comet.h"
 #include "dca_scan.h"
 #include "device_math.h"
+#include "field_math.h"
 #include "host_common.h"
 
 namespace {
@@ -57,13 +58,50 @@ struct BatchArgs {
     double *rss;              // [NP][S]
     int64_t *best;            // [NP]
     unsigned long long *evals;  // profiling: distance evaluations, or null
+    FieldMap fm;              // the field map of the FIELD kernel (tracks as field.hip records them)
 };
+
+// One seed's track in the map into a tile's scratch rows (stride 64) with its chunk
+// radii: the steps of rk4_field_record_kernel (RK4, or RKN for fm.stepper 1).
+__device__ __forceinline__ void record_field_track(const FieldMap &fm, const double (&st)[6],
+                                                   double charge, double h, int K,
+                                                   double *sx, double *sy, double *sz,
+                                                   double *rho, int lane)
+{
+    const int P = K + 1;
+    double x[3] = {st[0], st[1], st[2]}, p[3] = {st[3], st[4], st[5]};
+    const double p0 = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+    const double inv = 1.0 / p0;
+    const double g = (kKappa * charge) * inv;
+    const bool rkn = fm.stepper == 1;
+    const RknConsts kn = rkn_consts(h);
+    if (rkn)
+        for (int c = 0; c < 3; ++c)
+            p[c] = p[c] * inv;
+    ChunkRadius rad;
+    for (int k = 0; k < K; ++k) {
+        sx[(int64_t)k * 64 + lane] = x[0];
+        sy[(int64_t)k * 64 + lane] = x[1];
+        sz[(int64_t)k * 64 + lane] = x[2];
+        if (rho)
+            rad.add(k, P, x[0], x[1], x[2], rho, 64);
+        if (rkn)
+            rkn_field_step(fm, kn, g, x, p);
+        else
+            rk4_field_step(fm, inv, g, h, x, p);
+    }
+    sx[(int64_t)K * 64 + lane] = x[0];
+    sy[(int64_t)K * 64 + lane] = x[1];
+    sz[(int64_t)K * 64 + lane] = x[2];
+    if (rho)
+        rad.add(K, P, x[0], x[1], x[2], rho, 64);
+}
 
 // WPE: waves per SIMD the register allocation must allow (2 blocks of 8 waves per CU
 // need 4). A work item is a super-tile of up to NWV consecutive 64-seed tiles of one
 // partition: every wave records one tile's tracks (RK4 runs on all waves at once),
 // then the block scans the tiles one after the other against the event's wires.
-template <int W, int NWV, int C, int WPE, bool DIRECT>
+template <int W, int NWV, int C, int WPE, bool DIRECT, bool FIELD = false>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_scan_kernel(BatchArgs a)
 {
@@ -114,7 +152,14 @@ batch_scan_kernel(BatchArgs a)
             double *sx = block_scratch + (int64_t)wave * 3 * row;
             double *sy = sx + row, *sz = sy + row;
             double *rho = block_rho + (int64_t)wave * rrow + lane;
-            if (lane < n_valid) {
+            if constexpr (FIELD) {
+                if (lane < n_valid) {
+                    double st[6];
+                    seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3,
+                                   s0 + lane, st);
+                    record_field_track(a.fm, st, a.charge, a.h, a.K, sx, sy, sz, rho, lane);
+                }
+            } else if (lane < n_valid) {
                 ChunkRadius rad;
                 double st[6];
                 seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, s0 + lane,
@@ -219,7 +264,8 @@ __global__ __launch_bounds__(kBatchClassifyThreads) void batch_classify_kernel(
     const double *__restrict__ drift, const int32_t *__restrict__ ev_wires,
     const int32_t *__restrict__ part_event, double bz, double charge, double h, int K,
     double lambda, double *__restrict__ best_seed, double *__restrict__ best_rss,
-    uint8_t *__restrict__ mask, int64_t mask_stride, int32_t *__restrict__ n_border)
+    uint8_t *__restrict__ mask, int64_t mask_stride, int32_t *__restrict__ n_border,
+    FieldMap fm, int use_field)
 {
     extern __shared__ double pts[];  // [3][K + 1]
     __shared__ int32_t border;
@@ -232,7 +278,31 @@ __global__ __launch_bounds__(kBatchClassifyThreads) void batch_classify_kernel(
     if (threadIdx.x == 0) {
         border = 0;
         double st[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
-        if (b >= 0) {
+        if (b >= 0 && use_field) {
+            seed_from_grid(grids + 14 * (int64_t)p, n0, n1, n2, n3, b, st);
+            // the steps of rk4_field_record_kernel (RK4, or RKN for fm.stepper 1)
+            double x[3] = {st[0], st[1], st[2]}, q[3] = {st[3], st[4], st[5]};
+            const double p0 = sqrt((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
+            const double inv = 1.0 / p0;
+            const double g = (kKappa * charge) * inv;
+            const bool rkn = fm.stepper == 1;
+            const RknConsts kn = rkn_consts(h);
+            if (rkn)
+                for (int c = 0; c < 3; ++c)
+                    q[c] = q[c] * inv;
+            for (int k = 0; k < K; ++k) {
+                pts[k] = x[0];
+                pts[P + k] = x[1];
+                pts[2 * P + k] = x[2];
+                if (rkn)
+                    rkn_field_step(fm, kn, g, x, q);
+                else
+                    rk4_field_step(fm, inv, g, h, x, q);
+            }
+            pts[K] = x[0];
+            pts[P + K] = x[1];
+            pts[2 * P + K] = x[2];
+        } else if (b >= 0) {
             seed_from_grid(grids + 14 * (int64_t)p, n0, n1, n2, n3, b, st);
             double x = st[0], y = st[1], z = st[2], px = st[3], py = st[4];
             const StepConsts kc = step_consts(px, py, st[5], bz, charge, h);
@@ -589,11 +659,20 @@ const BatchVariant kBatchVariants[] = {
     {2, 8, 16, 1, batch_scan_kernel<2, 8, 16, 4, true>},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
+// Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
+// kernels above keep their registers.
+const BatchVariant kBatchFieldVariant = {4, 8, 16, 1, batch_scan_kernel<4, 8, 16, 4, true, true>};
 
 
 std::mutex g_batch_mu;
 int g_batch_variant = 0;
-int g_batch_blocks[kNumBatchVariants][64];  // persistent grid per (variant, device)
+// persistent grid per (variant, device); the last row is the field-map kernel's
+int g_batch_blocks[kNumBatchVariants + 1][64];
+
+const BatchVariant &batch_variant(int id)
+{
+    return id < kNumBatchVariants ? kBatchVariants[id] : kBatchFieldVariant;
+}
 
 // Persistent blocks for a shape: every block that can be resident at once.
 int batch_blocks(int id)
@@ -607,7 +686,7 @@ int batch_blocks(int id)
         int cus = 0, per_cu = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
-        const BatchVariant &v = kBatchVariants[id];
+        const BatchVariant &v = batch_variant(id);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)v.kernel,
                                                          64 * v.nwv, 0) != hipSuccess)
             return 0;
@@ -647,20 +726,29 @@ BatchLayout batch_layout(void *ws, int n_wires, int n_partitions)
     return l;
 }
 
+// The device view of a caller's field map (an empty map, unused, when there is none).
+FieldMap field_map(const comet_field *f)
+{
+    if (!f)
+        return FieldMap{nullptr, 0, 0, 0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0, 0};
+    return FieldMap{f->b, f->nx, f->ny, f->nz, f->x0, f->y0, f->z0, f->dx, f->dy, f->dz,
+                    f->stepper};
+}
+
 int launch_batch_classify(const double *grids, int n_partitions, const int32_t n[4], int64_t S,
                           const int64_t *best, const double *rss, const double *wire_ends,
                           const int32_t *wire_offsets, const double *drift,
                           const int32_t *event_wires, const int32_t *part_event,
                           const comet_config *cfg, double *best_seed, double *best_rss,
                           uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
-                          hipStream_t hs)
+                          const comet_field *field, hipStream_t hs)
 {
     const size_t lds = sizeof(double) * 3 * (size_t)(cfg->n_steps + 1);
     hipLaunchKernelGGL(batch_classify_kernel, dim3(n_partitions), dim3(kBatchClassifyThreads), lds,
                        hs, grids, n[0], n[1], n[2], n[3], S, best, rss, wire_ends, wire_offsets,
                        drift, event_wires, part_event, cfg->bz_tesla, cfg->charge_e,
                        cfg->step_mm, cfg->n_steps, cfg->lambda_mm, best_seed, best_rss, hit_mask,
-                       mask_stride, n_borderline);
+                       mask_stride, n_borderline, field_map(field), field ? 1 : 0);
     return launched("batch_classify_kernel");
 }
 
@@ -677,16 +765,19 @@ size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps, int32_t n_p
            (size_t)kMaxBatchBlocks * batch_scratch_bytes(n_steps);
 }
 
-int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
-                     const double *drift, int32_t n_hits, const int32_t *event_wires,
-                     int32_t n_events, const int32_t *part_event, int32_t n_partitions,
-                     const double *grids_init, double *grids, const int32_t n[4],
-                     const comet_config *cfg, int32_t n_refine, double *rss, int64_t *best,
-                     double *best_seed, double *best_rss, uint8_t *hit_mask,
-                     int64_t mask_stride, int32_t *n_borderline, int64_t max_items,
-                     void *workspace, size_t workspace_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                    const double *drift, int32_t n_hits, const int32_t *event_wires,
+                    int32_t n_events, const int32_t *part_event, int32_t n_partitions,
+                    const double *grids_init, double *grids, const int32_t n[4],
+                    const comet_config *cfg, const comet_field *field, int32_t n_refine,
+                    double *rss, int64_t *best, double *best_seed, double *best_rss,
+                    uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
+                    int64_t max_items, void *workspace, size_t workspace_bytes, void *stream)
 {
-    clear_error();
     if (!wire_ends || !wire_offsets || !event_wires || !part_event || !grids || !n || !rss ||
         !best)
         return fail(COMET_EINVAL, "comet_batch_scan: NULL pointer");
@@ -741,7 +832,9 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
         std::lock_guard<std::mutex> lock(g_batch_mu);
         id = g_batch_variant;
     }
-    const BatchVariant &v = kBatchVariants[id];
+    if (field)
+        id = kNumBatchVariants;  // the field-map kernel
+    const BatchVariant &v = batch_variant(id);
     const int blocks = batch_blocks(id);
     if (blocks < 1)
         return fail(COMET_EHIP, "comet_batch_scan: occupancy query failed");
@@ -756,7 +849,7 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
     BatchArgs args{l.frames, wire_offsets, drift, event_wires, part_event, grids, n[0], n[1],
                    n[2], n[3], S, tiles, supers, items, max_tiles, cfg->bz_tesla,
                    cfg->charge_e, cfg->step_mm, cfg->lambda_mm, cfg->n_steps, l.scratch,
-                   l.counter, l.done, rss, best, scan_counter()};
+                   l.counter, l.done, rss, best, scan_counter(), field_map(field)};
     for (int it = 0; it <= n_refine && st == COMET_OK; ++it) {
         if (it) {
             hipLaunchKernelGGL(batch_refine_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0,
@@ -781,18 +874,18 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
         return COMET_OK;  // no classification output asked for
     return launch_batch_classify(grids, n_partitions, n, S, best, rss, wire_ends, wire_offsets,
                                  drift, event_wires, part_event, cfg, best_seed, best_rss,
-                                 hit_mask, mask_stride, n_borderline, hs);
+                                 hit_mask, mask_stride, n_borderline, field, hs);
 }
 
-int comet_batch_classify(const double *grids, int32_t n_partitions, const int32_t n[4],
-                         const int64_t *best, const double *rss, const double *wire_ends,
-                         int32_t n_wires, const int32_t *wire_offsets, const double *drift,
-                         int32_t n_hits, const int32_t *event_wires, int32_t n_events,
-                         const int32_t *part_event, const comet_config *cfg, double *best_seed,
-                         double *best_rss, uint8_t *hit_mask, int64_t mask_stride,
-                         int32_t *n_borderline, void *stream)
+int batch_classify_impl(const double *grids, int32_t n_partitions, const int32_t n[4],
+                        const int64_t *best, const double *rss, const double *wire_ends,
+                        int32_t n_wires, const int32_t *wire_offsets, const double *drift,
+                        int32_t n_hits, const int32_t *event_wires, int32_t n_events,
+                        const int32_t *part_event, const comet_config *cfg,
+                        const comet_field *field, double *best_seed, double *best_rss,
+                        uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
+                        void *stream)
 {
-    clear_error();
     if (!grids || !n || !best || !wire_ends || !wire_offsets || !event_wires || !part_event)
         return fail(COMET_EINVAL, "comet_batch_classify: NULL pointer");
     if (n_partitions < 1 || n_wires < 1 || n_hits < 0 || (n_hits > 0 && !drift) || n_events < 1)
@@ -817,7 +910,83 @@ int comet_batch_classify(const double *grids, int32_t n_partitions, const int32_
         return st;
     return launch_batch_classify(grids, n_partitions, n, S, best, rss, wire_ends, wire_offsets,
                                  drift, event_wires, part_event, cfg, best_seed, best_rss,
-                                 hit_mask, mask_stride, n_borderline, (hipStream_t)stream);
+                                 hit_mask, mask_stride, n_borderline, field, (hipStream_t)stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                     const double *drift, int32_t n_hits, const int32_t *event_wires,
+                     int32_t n_events, const int32_t *part_event, int32_t n_partitions,
+                     const double *grids_init, double *grids, const int32_t n[4],
+                     const comet_config *cfg, int32_t n_refine, double *rss, int64_t *best,
+                     double *best_seed, double *best_rss, uint8_t *hit_mask,
+                     int64_t mask_stride, int32_t *n_borderline, int64_t max_items,
+                     void *workspace, size_t workspace_bytes, void *stream)
+{
+    clear_error();
+    return batch_scan_impl(wire_ends, n_wires, wire_offsets, drift, n_hits, event_wires,
+                           n_events, part_event, n_partitions, grids_init, grids, n, cfg,
+                           nullptr, n_refine, rss, best, best_seed, best_rss, hit_mask,
+                           mask_stride, n_borderline, max_items, workspace, workspace_bytes,
+                           stream);
+}
+
+int comet_batch_scan_field(const double *wire_ends, int32_t n_wires,
+                           const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                           const int32_t *event_wires, int32_t n_events,
+                           const int32_t *part_event, int32_t n_partitions,
+                           const double *grids_init, double *grids, const int32_t n[4],
+                           const comet_config *cfg, const comet_field *field, int32_t n_refine,
+                           double *rss, int64_t *best, double *best_seed, double *best_rss,
+                           uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
+                           int64_t max_items, void *workspace, size_t workspace_bytes,
+                           void *stream)
+{
+    clear_error();
+    const int st = check_field("comet_batch_scan_field", field);
+    if (st)
+        return st;
+    return batch_scan_impl(wire_ends, n_wires, wire_offsets, drift, n_hits, event_wires,
+                           n_events, part_event, n_partitions, grids_init, grids, n, cfg, field,
+                           n_refine, rss, best, best_seed, best_rss, hit_mask, mask_stride,
+                           n_borderline, max_items, workspace, workspace_bytes, stream);
+}
+
+int comet_batch_classify(const double *grids, int32_t n_partitions, const int32_t n[4],
+                         const int64_t *best, const double *rss, const double *wire_ends,
+                         int32_t n_wires, const int32_t *wire_offsets, const double *drift,
+                         int32_t n_hits, const int32_t *event_wires, int32_t n_events,
+                         const int32_t *part_event, const comet_config *cfg, double *best_seed,
+                         double *best_rss, uint8_t *hit_mask, int64_t mask_stride,
+                         int32_t *n_borderline, void *stream)
+{
+    clear_error();
+    return batch_classify_impl(grids, n_partitions, n, best, rss, wire_ends, n_wires,
+                               wire_offsets, drift, n_hits, event_wires, n_events, part_event,
+                               cfg, nullptr, best_seed, best_rss, hit_mask, mask_stride,
+                               n_borderline, stream);
+}
+
+int comet_batch_classify_field(const double *grids, int32_t n_partitions, const int32_t n[4],
+                               const int64_t *best, const double *rss, const double *wire_ends,
+                               int32_t n_wires, const int32_t *wire_offsets,
+                               const double *drift, int32_t n_hits, const int32_t *event_wires,
+                               int32_t n_events, const int32_t *part_event,
+                               const comet_config *cfg, const comet_field *field,
+                               double *best_seed, double *best_rss, uint8_t *hit_mask,
+                               int64_t mask_stride, int32_t *n_borderline, void *stream)
+{
+    clear_error();
+    const int st = check_field("comet_batch_classify_field", field);
+    if (st)
+        return st;
+    return batch_classify_impl(grids, n_partitions, n, best, rss, wire_ends, n_wires,
+                               wire_offsets, drift, n_hits, event_wires, n_events, part_event,
+                               cfg, field, best_seed, best_rss, hit_mask, mask_stride,
+                               n_borderline, stream);
 }
 
 int comet_sparse_select(const double *grids, const double *rss, int32_t n_groups, int32_t n_sub,

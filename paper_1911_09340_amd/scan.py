@@ -124,8 +124,10 @@ class BatchRunner:
     """All turn partitions of many events through comet_batch_scan (one call per run,
     capturable into a HIP graph)."""
 
-    def __init__(self, events, scan_cfg, device="cuda"):
+    def __init__(self, events, scan_cfg, device="cuda", field=None):
+        """field: a comet.FieldMap to record the tracks in (None: the uniform field)."""
         from .synth import grid_descriptor
+        self.field = field
         self.events = list(events)
         self.sc = scan_cfg
         self.cfg = config_for(self.events[0], scan_cfg)
@@ -163,7 +165,8 @@ class BatchRunner:
         comet.batch_scan(self.packed, self.part_event, self.grids, self.sc.n, self.cfg,
                          self.sc.n_refine, self.rss, self.best, self.workspace,
                          best_seed=self.best_seed, best_rss=self.best_rss, hit_mask=self.mask,
-                         n_borderline=self.n_border, max_items=max_items, grids_init=self.grids0)
+                         n_borderline=self.n_border, max_items=max_items, grids_init=self.grids0,
+                         field=self.field)
 
     def autotune(self, items_per_block: int = 4, reps: int = 2) -> dict:
         """Time every shape of the batched scan kernel on a prefix of this run's work

@@ -179,3 +179,31 @@ def test_field_jacobian_too_many_wires():
                       field=comet.FieldMap(*fm))
     torch.cuda.synchronize()
     assert torch.isnan(rss).all() and torch.isnan(grad).all()
+
+
+@pytest.mark.parametrize("stepper", [0, 1])
+def test_field_batched_scan_matches_cpu(orc, fmap, stepper):
+    """The persistent batched scan with tracks in the map (scan, two finer re-scans,
+    classification) for several events and turns: every RSS of the last scan, the chosen
+    seeds and the classified hits, bit for bit with the CPU reference's field scan."""
+    events = [synth.event_mix(i) for i in (1, 4)]
+    sc = synth.ScanConfig("field-batch", (2, 3, 4, 5), (5.0, 5.0, 0.05, 0.05), 500, 2.0, 0.8, 2)
+    f = comet.FieldMap(*fmap, stepper=stepper)
+    run = scan.BatchRunner(events, sc, field=f)
+    run.run()
+    torch.cuda.synchronize()
+    rss, best = run.rss.cpu().numpy(), run.best.cpu().numpy()
+    seeds, mask = run.best_seed.cpu().numpy(), run.mask.cpu().numpy()
+    n = np.array(sc.n, np.int32)
+    p = 0
+    for ev in events:
+        cfg = [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+        for t in range(ev.n_turns):
+            g = synth.grid_descriptor(ev.ref_states[t], sc)
+            r = orc.scan_partition_field(g, n, fmap, stepper, cfg, sc.n_steps, sc.n_refine,
+                                         ev.wire_ends, ev.wire_offsets, ev.drift)
+            assert np.array_equal(rss[p], r["rss"]), (p, stepper)
+            assert best[p] == r["best"], (p, stepper)
+            assert np.array_equal(seeds[p], r["best_seed"]), (p, stepper)
+            assert np.array_equal(mask[p, :ev.n_hits], r["mask"]), (p, stepper)
+            p += 1
