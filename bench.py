@@ -420,9 +420,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
-              "(--gpus 1); multi-GPU sharding is described in DESIGN.md, not run.",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus 1): it measures the single-GPU path; "
+              "sharding events across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     # events for the gradient comparison are drawn before the GPU is touched, so that
