@@ -493,12 +493,12 @@ int comet_stage_update(int32_t *active, int32_t n_events, const int64_t *best,
                        int32_t max_stages, int32_t min_wires, void *stream);
 
 /* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
- * per LDS chunk, the persistent block count on the current device, and direct as for
- * the DCA shapes; blocks and direct may be NULL); every shape gives the same results.
- * comet_batch_set_variant selects the shape (default 0). */
+ * per LDS chunk, the persistent block count on the current device, and direct and runs
+ * as for the DCA shapes; blocks, direct and runs may be NULL); every shape gives the
+ * same results. comet_batch_set_variant selects the shape (default 0). */
 int comet_batch_variant_count(void);
 int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks,
-                             int32_t *direct);
+                             int32_t *direct, int32_t *runs);
 int comet_batch_set_variant(int id);
 
 /* ------------------------------------------------------------ diagnostics

@@ -436,7 +436,7 @@ def _bind_batch(lib):
     lib.comet_batch_scan_field.argtypes = args[:13] + [FP] + args[13:]
     lib.comet_batch_scan_field.restype = ctypes.c_int
     lib.comet_batch_variant_count.restype = ctypes.c_int
-    lib.comet_batch_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4, I4]
+    lib.comet_batch_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4, I4, I4]
     lib.comet_batch_variant_info.restype = ctypes.c_int
     lib.comet_batch_set_variant.argtypes = [ctypes.c_int]
     lib.comet_batch_set_variant.restype = ctypes.c_int
@@ -523,11 +523,11 @@ def batch_variants():
     lib = _bind_batch(load())
     out = []
     for i in range(lib.comet_batch_variant_count()):
-        v = [ctypes.c_int32() for _ in range(5)]
+        v = [ctypes.c_int32() for _ in range(6)]
         _check(lib.comet_batch_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_batch_variant_info")
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value, blocks=v[3].value,
-                        direct=bool(v[4].value)))
+                        direct=bool(v[4].value), runs=v[5].value))
     return out
 
 

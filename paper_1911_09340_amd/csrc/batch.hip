@@ -101,11 +101,11 @@ __device__ __forceinline__ void record_field_track(const FieldMap &fm, const dou
 // need 4). A work item is a super-tile of up to NWV consecutive 64-seed tiles of one
 // partition: every wave records one tile's tracks (RK4 runs on all waves at once),
 // then the block scans the tiles one after the other against the event's wires.
-template <int W, int NWV, int C, int WPE, bool DIRECT, bool FIELD = false>
+template <int W, int NWV, int C, int WPE, bool DIRECT, bool FIELD = false, int SUP = 1>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_scan_kernel(BatchArgs a)
 {
-    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, true, true>,
+    using Scan = std::conditional_t<DIRECT, TileScanDirect<W, C, true, true, SUP>,
                                     TileScan<W, NWV, C, true>>;
     constexpr int G = W * NWV;  // wires per group
     static_assert(NWV <= kMaxBatchNwv && G <= kBatchWirePad, "shape exceeds the workspace");
@@ -644,6 +644,7 @@ __global__ void copy_kernel(const double *__restrict__ src, double *__restrict__
 struct BatchVariant {
     int w, nwv, c, direct;
     void (*kernel)(BatchArgs);
+    int runs;  // direct shapes: chunks tested in runs of this many first (1: no runs)
 };
 
 const BatchVariant kBatchVariants[] = {
@@ -657,6 +658,9 @@ const BatchVariant kBatchVariants[] = {
     {4, 8, 16, 1, batch_scan_kernel<4, 8, 16, 4, true>},
     {3, 8, 16, 1, batch_scan_kernel<3, 8, 16, 4, true>},
     {2, 8, 16, 1, batch_scan_kernel<2, 8, 16, 4, true>},
+    // runs of 4 chunks tested first (two-level distance bound)
+    {4, 8, 16, 1, batch_scan_kernel<4, 8, 16, 4, true, false, 4>, 4},
+    {3, 8, 16, 1, batch_scan_kernel<3, 8, 16, 4, true, false, 4>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
@@ -1058,7 +1062,7 @@ int comet_grid_seeds(const double *grids, int32_t n_partitions, const int32_t n[
 int comet_batch_variant_count(void) { return kNumBatchVariants; }
 
 int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks,
-                             int32_t *direct)
+                             int32_t *direct, int32_t *runs)
 {
     if (id < 0 || id >= kNumBatchVariants || !w || !nwv || !chunk)
         return fail(COMET_EINVAL, "comet_batch_variant_info: bad id or NULL pointer");
@@ -1069,6 +1073,8 @@ int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, i
         *blocks = batch_blocks(id);
     if (direct)
         *direct = kBatchVariants[id].direct;
+    if (runs)
+        *runs = kBatchVariants[id].runs > 0 ? kBatchVariants[id].runs : 1;
     return COMET_OK;
 }
 
