@@ -13,8 +13,13 @@ scans of seeds x hits, divided by wall time of the timed steps). `roofline` cove
 the dominant kernel (the DCA scan): FP64 flops of the distance evaluations it
 performs per launch (15 per (seed, wire, point) evaluated, counted by the kernel;
 the scan skips points that a distance bound rules out, with the results of the
-full scan) / its average device time from HIP events recorded on its stream. `cpu_baseline` times the CPU
-reference (oracle/) on a bounded sample of the same workload on the host cores.
+full scan) / its average device time from HIP events recorded on its stream.
+`cpu_baseline` times the CPU reference (oracle/) on a bounded sample of the same
+workload on the host cores. Further sections (each can be switched off): the same
+step with tracks in a field map (RK4 and Runge-Kutta-Nystrom, and the batched scan in
+the map), the batched persistent scan of a mix of events, several references, half
+tracks, the stage loop (with and without the self-refining), the gradient comparison
+(coarse grid + Levenberg-Marquardt vs a fine grid) and, on request, the stress mix.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
   python bench.py --sweep             # time every DCA kernel shape
