@@ -47,6 +47,10 @@ __global__ __launch_bounds__(256) void rk4_field_record_kernel(const double *__r
     if (rkn)  // Runge-Kutta-Nystrom carries the unit direction in p
         for (int c = 0; c < 3; ++c)
             p[c] = p[c] * inv;
+    CellCache cc;
+    auto look = [&](double px, double py, double pz, double (&B)[3]) {
+        field_at_cached(m, px, py, pz, B, cc);
+    };
     for (int j = 0; j < K; ++j) {
         tx[(int64_t)j * S] = x[0];
         ty[(int64_t)j * S] = x[1];
@@ -54,9 +58,9 @@ __global__ __launch_bounds__(256) void rk4_field_record_kernel(const double *__r
         if (rs)
             cr.add(j, K + 1, x[0], x[1], x[2], rs, S);
         if (rkn)
-            rkn_field_step(m, kn, g, x, p);
+            rkn_field_step_l(look, kn, g, x, p);
         else
-            rk4_field_step(m, inv, g, h, x, p);
+            rk4_field_step_l(look, inv, g, h, x, p);
     }
     tx[(int64_t)K * S] = x[0];
     ty[(int64_t)K * S] = x[1];

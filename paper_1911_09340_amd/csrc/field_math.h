@@ -62,55 +62,113 @@ __device__ __forceinline__ void field_at(const FieldMap &m, double x, double y, 
     }
 }
 
+// The 8 nodes of the last cell a thread read, kept in registers by the recording
+// kernels: consecutive stages mostly fall in the same cell (a step moves 2 mm, a cell
+// is 25 mm) and a step's first stage sits within ~h^2 |a| of the previous step's last
+// one, so reusing the nodes skips dependent global loads. B is computed from the same
+// values with the same operations as field_at: the result does not depend on the cache.
+struct CellCache {
+    double v[24];  // [component][node (0,0,0), (1,0,0), (0,1,0), (1,1,0), (0,0,1), ...]
+    int i = -1, j = -1, k = -1;
+};
+
+__device__ __forceinline__ void field_at_cached(const FieldMap &m, double x, double y, double z,
+                                                double (&B)[3], CellCache &cc)
+{
+    int i, j, k;
+    double tu, tv, tw;
+    field_cell((x - m.x0) / m.dx, m.nx, i, tu);
+    field_cell((y - m.y0) / m.dy, m.ny, j, tv);
+    field_cell((z - m.z0) / m.dz, m.nz, k, tw);
+    if (i != cc.i || j != cc.j || k != cc.k) {
+        const int64_t sx = 3, sy = 3 * (int64_t)m.nx, sz = 3 * (int64_t)m.nx * m.ny;
+        const double *n000 = m.b + k * sz + j * sy + i * sx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cc.v[8 * c + 0] = n000[c];
+            cc.v[8 * c + 1] = n000[sx + c];
+            cc.v[8 * c + 2] = n000[sy + c];
+            cc.v[8 * c + 3] = n000[sy + sx + c];
+            cc.v[8 * c + 4] = n000[sz + c];
+            cc.v[8 * c + 5] = n000[sz + sx + c];
+            cc.v[8 * c + 6] = n000[sz + sy + c];
+            cc.v[8 * c + 7] = n000[sz + sy + sx + c];
+        }
+        cc.i = i;
+        cc.j = j;
+        cc.k = k;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double c00 = lerp(cc.v[8 * c + 0], cc.v[8 * c + 1], tu);
+        const double c10 = lerp(cc.v[8 * c + 2], cc.v[8 * c + 3], tu);
+        const double c01 = lerp(cc.v[8 * c + 4], cc.v[8 * c + 5], tu);
+        const double c11 = lerp(cc.v[8 * c + 6], cc.v[8 * c + 7], tu);
+        B[c] = lerp(lerp(c00, c10, tv), lerp(c01, c11, tv), tw);
+    }
+}
+
 // RK4 in the map: dx/ds = p inv, dp/ds = g (p x B(x)), inv = 1 / |p of the seed|,
 // g = (kappa q) inv; every stage reads B at its own position (x, x + h/2 v1,
 // x + h/2 v2, x + h v3); cross product (p_y B_z - p_z B_y, p_z B_x - p_x B_z,
 // p_x B_y - p_y B_x); y <- y + h/6 (((k1 + 2 k2) + 2 k3) + k4).
-__device__ __forceinline__ void field_force(const FieldMap &m, double g, const double (&x)[3],
+// look(x, y, z, B) reads B: field_at, or field_at_cached in the recording kernels.
+template <class Look>
+__device__ __forceinline__ void field_force(Look &look, double g, const double (&x)[3],
                                             const double (&p)[3], double (&f)[3])
 {
     double B[3];
-    field_at(m, x[0], x[1], x[2], B);
+    look(x[0], x[1], x[2], B);
     f[0] = g * (p[1] * B[2] - p[2] * B[1]);
     f[1] = g * (p[2] * B[0] - p[0] * B[2]);
     f[2] = g * (p[0] * B[1] - p[1] * B[0]);
 }
 
-__device__ __forceinline__ void rk4_field_step(const FieldMap &m, double inv, double g, double h,
-                                               double (&x)[3], double (&p)[3])
+template <class Look>
+__device__ __forceinline__ void rk4_field_step_l(Look &look, double inv, double g, double h,
+                                                 double (&x)[3], double (&p)[3])
 {
     const double hh = 0.5 * h, h6 = h / 6.0;
     double v1[3], f1[3], v2[3], f2[3], v3[3], f3[3], v4[3], f4[3], xs[3], ps[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         v1[c] = p[c] * inv;
-    field_force(m, g, x, p, f1);
+    field_force(look, g, x, p, f1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         xs[c] = x[c] + hh * v1[c];
         ps[c] = p[c] + hh * f1[c];
         v2[c] = ps[c] * inv;
     }
-    field_force(m, g, xs, ps, f2);
+    field_force(look, g, xs, ps, f2);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         xs[c] = x[c] + hh * v2[c];
         ps[c] = p[c] + hh * f2[c];
         v3[c] = ps[c] * inv;
     }
-    field_force(m, g, xs, ps, f3);
+    field_force(look, g, xs, ps, f3);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         xs[c] = x[c] + h * v3[c];
         ps[c] = p[c] + h * f3[c];
         v4[c] = ps[c] * inv;
     }
-    field_force(m, g, xs, ps, f4);
+    field_force(look, g, xs, ps, f4);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         x[c] = x[c] + h6 * (((v1[c] + 2.0 * v2[c]) + 2.0 * v3[c]) + v4[c]);
         p[c] = p[c] + h6 * (((f1[c] + 2.0 * f2[c]) + 2.0 * f3[c]) + f4[c]);
     }
+}
+
+__device__ __forceinline__ void rk4_field_step(const FieldMap &m, double inv, double g, double h,
+                                               double (&x)[3], double (&p)[3])
+{
+    auto look = [&](double px, double py, double pz, double (&B)[3]) {
+        field_at(m, px, py, pz, B);
+    };
+    rk4_field_step_l(look, inv, g, h, x, p);
 }
 
 // ------------------------------------------------------------------ derivatives
@@ -262,18 +320,19 @@ __device__ __forceinline__ void rkn_accel(double g, const double (&t)[3], const 
     a[2] = g * (t[0] * B[1] - t[1] * B[0]);
 }
 
-__device__ __forceinline__ void rkn_field_step(const FieldMap &m, const RknConsts &k, double g,
-                                               double (&x)[3], double (&t)[3])
+template <class Look>
+__device__ __forceinline__ void rkn_field_step_l(Look &look, const RknConsts &k, double g,
+                                                 double (&x)[3], double (&t)[3])
 {
     double B[3], a1[3], a2[3], a3[3], a4[3], xs[3], ts[3];
-    field_at(m, x[0], x[1], x[2], B);
+    look(x[0], x[1], x[2], B);
     rkn_accel(g, t, B, a1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         xs[c] = (x[c] + k.hh * t[c]) + k.q8 * a1[c];
         ts[c] = t[c] + k.hh * a1[c];
     }
-    field_at(m, xs[0], xs[1], xs[2], B);
+    look(xs[0], xs[1], xs[2], B);
     rkn_accel(g, ts, B, a2);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -284,13 +343,22 @@ __device__ __forceinline__ void rkn_field_step(const FieldMap &m, const RknConst
         xs[c] = (x[c] + k.h * t[c]) + k.q2 * a3[c];
         ts[c] = t[c] + k.h * a3[c];
     }
-    field_at(m, xs[0], xs[1], xs[2], B);
+    look(xs[0], xs[1], xs[2], B);
     rkn_accel(g, ts, B, a4);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         x[c] = (x[c] + k.h * t[c]) + k.q6 * ((a1[c] + a2[c]) + a3[c]);
         t[c] = t[c] + k.h6 * (((a1[c] + 2.0 * a2[c]) + 2.0 * a3[c]) + a4[c]);
     }
+}
+
+__device__ __forceinline__ void rkn_field_step(const FieldMap &m, const RknConsts &k, double g,
+                                               double (&x)[3], double (&t)[3])
+{
+    auto look = [&](double px, double py, double pz, double (&B)[3]) {
+        field_at(m, px, py, pz, B);
+    };
+    rkn_field_step_l(look, k, g, x, t);
 }
 
 // a = g (t x B) and its derivative along (dt, dB) with dg: dg (t x B) + g (dt x B + t x dB).
