@@ -104,3 +104,40 @@ def test_lm_stress_size_matches_cpu(orc):
         assert int(acc[r]) == wacc, r
         assert np.max(np.abs(got[:, r] - ws) / np.maximum(np.abs(ws), 1.0)) < 1e-7, r
         assert abs(float(rss[r]) - wrss) <= 1e-7 * max(wrss, 1.0), r
+
+
+def test_dca_far_offsets_every_direct_shape(orc):
+    """A single-event scan whose track spans more than 2^29 doubles per coordinate
+    (524 288 seeds x 1025 points), where the wave-independent shapes address the track
+    with 64-bit pointers instead of 32-bit buffer offsets: sampled RSS bit for bit with
+    the CPU reference for every such shape, the last seed included."""
+    ev = synth.event_plain(0)
+    sc = synth.ScanConfig("far", (8, 16, 64, 64), (5.0, 5.0, 0.05, 0.05), 1024, 2.0, 1.0)
+    S, P = sc.n_seeds, sc.n_steps + 1
+    assert P * S >= (1 << 29) - 64
+    cfg = scan.config_for(ev, sc)
+    dev = scan.DeviceEvent.from_event(ev)
+    seeds = torch.empty(6, S, dtype=torch.float64, device="cuda")
+    g = synth.grid_descriptor(ev.ref_states[0], sc)
+    comet.seed_grid(torch.as_tensor(g, device="cuda"), np.array(sc.n, np.int32), seeds)
+    track = torch.empty(3, P, S, dtype=torch.float64, device="cuda")
+    comet.extrapolate_seeds(seeds, cfg, track)
+    rss = torch.empty(S, dtype=torch.float64, device="cuda")
+    ws = comet.dca_workspace(S, P, dev.n_wires)
+    rng = np.random.default_rng(12)
+    idx = np.unique(np.concatenate([rng.integers(0, S, 48), [0, S - 1]]))
+    n = np.array(sc.n, np.int32)
+    want, _ = orc.scan(np.stack([orc.seed(g, n, int(i)) for i in idx], axis=1), _cfg(ev, sc),
+                       sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+    shapes = [i for i, v in enumerate(comet.dca_variants()) if v["direct"]]
+    assert shapes
+    try:
+        for v in shapes:
+            comet.set_dca_variant(v)
+            rss.fill_(np.nan)
+            comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, rss, ws)
+            torch.cuda.synchronize()
+            got = rss.cpu().numpy()
+            assert np.array_equal(got[idx], want), v
+    finally:
+        comet.set_dca_variant(-1)
