@@ -207,3 +207,35 @@ def test_field_batched_scan_matches_cpu(orc, fmap, stepper):
             assert np.array_equal(seeds[p], r["best_seed"]), (p, stepper)
             assert np.array_equal(mask[p, :ev.n_hits], r["mask"]), (p, stepper)
             p += 1
+
+
+def test_field_jacobian_packed_equals_single(fmap):
+    """Seeds of several packed events (event_wires, seed_event) give the derivatives of
+    each event on its own, bit for bit."""
+    events = [synth.event_mix(i) for i in (2, 6)]
+    packed = scan.PackedEvents.from_events(events)
+    d = dict(dtype=torch.float64, device="cuda")
+    cfg = comet.make_config(0.0, events[0].charge, 2.0, 700, 0.8)
+    f = comet.FieldMap(*fmap, stepper=1)
+    seeds, owner = [], []
+    for e, ev in enumerate(events):
+        for t in range(ev.n_turns):
+            seeds.append(ev.ref_states[t])
+            owner.append(e)
+    x = torch.as_tensor(np.stack(seeds, axis=1), **d)
+    S = x.shape[1]
+    out = {k: torch.empty(shape, **d) for k, shape in
+           (("rss", (S,)), ("grad", (S, 6)), ("jtj", (S, 21)), ("jte", (S, 6)))}
+    comet.rss_adjoint(x, cfg, packed.wire_ends, packed.wire_offsets, packed.drift,
+                      event_wires=packed.event_wires,
+                      seed_event=torch.as_tensor(np.array(owner, np.int32), device="cuda"),
+                      field=f, **out)
+    for e, ev in enumerate(events):
+        cols = [i for i, o in enumerate(owner) if o == e]
+        dev = scan.DeviceEvent.from_event(ev)
+        one = {k: torch.empty((len(cols),) + v.shape[1:], **d) for k, v in out.items()}
+        comet.rss_adjoint(x[:, cols].contiguous(), cfg, dev.wire_ends, dev.wire_offsets,
+                          dev.drift, field=f, **one)
+        torch.cuda.synchronize()
+        for k in out:
+            assert torch.equal(out[k][cols], one[k]), (e, k)
