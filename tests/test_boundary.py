@@ -348,3 +348,29 @@ def test_field_derivative_calls_reject(lib):
     bad = list(lm)
     bad[12] = 0.0
     assert lib.comet_lm_refine_field(*bad, _p(0x100000), 1 << 20, None) == comet.EINVAL
+
+
+def test_batch_field_calls_reject(lib):
+    comet._bind_batch(lib)
+    cfg = _cfg()
+    n4 = (ctypes.c_int32 * 4)(2, 2, 2, 2)
+    bad_field = comet.Field(_p(), 3, 3, 3, 7, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    for field in (None, ctypes.byref(bad_field)):
+        assert lib.comet_batch_scan_field(
+            _p(), 10, _p(), _p(), 20, _p(), 2, _p(), 3, None, _p(), n4, ctypes.byref(cfg),
+            field, 0, _p(), _p(), None, None, None, 0, None, 0, _p(0x100000), 1 << 30,
+            None) == comet.EINVAL
+    lib.comet_batch_classify_field.argtypes = [ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.POINTER(comet.Config),
+                                               ctypes.POINTER(comet.Field), ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                               ctypes.c_void_p, ctypes.c_void_p]
+    lib.comet_batch_classify_field.restype = ctypes.c_int
+    for field in (None, ctypes.byref(bad_field)):
+        assert lib.comet_batch_classify_field(
+            _p(), 3, n4, _p(), _p(), _p(), 10, _p(), _p(), 20, _p(), 2, _p(), ctypes.byref(cfg),
+            field, None, None, None, 0, None, None) == comet.EINVAL
