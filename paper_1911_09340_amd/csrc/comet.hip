@@ -224,9 +224,21 @@ __global__ void rss_sum_kernel(const double *__restrict__ dsq, int n_w, int64_t 
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S)
         return;
+    // loads run ahead in batches of 8 (independent addresses); the adds stay in wire order
+    const double *p = dsq + s;
     double acc = 0.0;
-    for (int w = 0; w < n_w; ++w)
-        acc = acc + dsq[(int64_t)w * S + s];
+    int w = 0;
+    for (; w + 8 <= n_w; w += 8) {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            v[i] = p[(int64_t)(w + i) * S];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            acc = acc + v[i];
+    }
+    for (; w < n_w; ++w)
+        acc = acc + p[(int64_t)w * S];
     rss[s] = acc;
 }
 
@@ -246,6 +258,8 @@ __global__ __launch_bounds__(kSelectThreads) void argmin_kernel(const double *__
 // that residual is < lambda, bit 1 when it is within 1e-9 mm of lambda.
 constexpr int kClassifyThreads = 1024;
 constexpr int kClassifyChunk = 1024;
+constexpr int kClassifyLanes = 4;  // threads per wire (within one wave)
+constexpr int kClassifyWires = kClassifyThreads / kClassifyLanes;
 
 __global__ __launch_bounds__(kClassifyThreads) void classify_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ ends, int n_w,
@@ -258,8 +272,12 @@ __global__ __launch_bounds__(kClassifyThreads) void classify_kernel(
     if (threadIdx.x == 0)
         border = 0;
     const int64_t b = best[0];
-    for (int pass = 0; pass * kClassifyThreads < n_w; ++pass) {
-        const int wi = pass * kClassifyThreads + threadIdx.x;
+    // kClassifyLanes threads per wire, each taking every kClassifyLanes-th point; their
+    // (q, k) minima are combined with the lower index winning ties, which gives the first
+    // index of the minimum, as one thread scanning in order would.
+    const int lane_of_wire = threadIdx.x % kClassifyLanes;
+    for (int pass = 0; pass * kClassifyWires < n_w; ++pass) {
+        const int wi = pass * kClassifyWires + threadIdx.x / kClassifyLanes;
         const bool have = wi < n_w && b >= 0;
         double f[8];
         if (have)
@@ -276,7 +294,7 @@ __global__ __launch_bounds__(kClassifyThreads) void classify_kernel(
                 }
             __syncthreads();
             if (have)
-                for (int kk = 0; kk < kn; ++kk) {
+                for (int kk = lane_of_wire; kk < kn; kk += kClassifyLanes) {
                     double xi, eta;
                     project(f, pts[kk], pts[kClassifyChunk + kk], pts[2 * kClassifyChunk + kk], xi,
                             eta);
@@ -287,7 +305,16 @@ __global__ __launch_bounds__(kClassifyThreads) void classify_kernel(
                     }
                 }
         }
-        if (wi < n_w) {
+#pragma unroll
+        for (int off = 1; off < kClassifyLanes; off <<= 1) {
+            const double oq = __shfl_xor(qb, off);
+            const int ok = __shfl_xor(kb, off);
+            if (oq < qb || (oq == qb && ok < kb)) {
+                qb = oq;
+                kb = ok;
+            }
+        }
+        if (lane_of_wire == 0 && wi < n_w) {
             const int j0 = offsets[wi], j1 = offsets[wi + 1];
             if (!have) {
                 if (mask)
