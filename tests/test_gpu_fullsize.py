@@ -141,3 +141,32 @@ def test_dca_far_offsets_every_direct_shape(orc):
             assert np.array_equal(got[idx], want), v
     finally:
         comet.set_dca_variant(-1)
+
+
+@pytest.mark.parametrize("stepper", [0, 1])
+def test_field_signal_full_size_sampled(orc, stepper):
+    """The signal partition at full size (16^4 seeds, 1500 x 2 mm) with tracks in the
+    solenoid map, in the launch configuration the bench times (one fused track-and-scan
+    call per scan): sampled RSS bit for bit with the CPU reference's map tracks, and the
+    argmin of the whole row."""
+    ev = synth.event_signal(0)
+    sc = synth.C1
+    cfg = scan.config_for(ev, sc)
+    fmap = synth.solenoid_map()
+    f = comet.FieldMap(*fmap, stepper=stepper)
+    r = scan.PartitionScanner(sc.n, cfg, ev.n_wires, ev.n_hits, field=f)
+    dev = scan.DeviceEvent.from_event(ev)
+    r.run(dev, scan.grid_tensor(ev.ref_states[0], sc), 0)
+    torch.cuda.synchronize()
+    row = r.rss.cpu().numpy()
+    best = int(r.best.item())
+    assert best == int(np.argmin(row))
+    g = synth.grid_descriptor(ev.ref_states[0], sc)
+    n = np.array(sc.n, np.int32)
+    rng = np.random.default_rng(21)
+    idx = np.unique(np.concatenate([rng.integers(0, sc.n_seeds, 24), [0, sc.n_seeds - 1, best]]))
+    for i in idx:
+        pts = orc.track_field(orc.seed(g, n, int(i)), fmap, ev.charge, sc.step_mm, sc.n_steps,
+                              stepper=stepper)
+        want = orc.rss_track(pts, ev.wire_ends, ev.wire_offsets, ev.drift, sc.lambda_mm)
+        assert row[i] == want, (int(i), stepper)
