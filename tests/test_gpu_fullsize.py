@@ -170,3 +170,25 @@ def test_field_signal_full_size_sampled(orc, stepper):
                               stepper=stepper)
         want = orc.rss_track(pts, ev.wire_ends, ev.wire_offsets, ev.drift, sc.lambda_mm)
         assert row[i] == want, (int(i), stepper)
+
+
+def test_stage_loop_full_size_matches_cpu(orc):
+    """The stage loop at the grid size the bench runs it (per stage the 8 x 16 x 16 x 16
+    grid, 1000 x 2 mm, two finer re-scans), two stages of a five-turn event against the
+    CPU chain (about a minute of CPU work): both stages' chosen indices and seeds and the
+    stage of every hit, bit for bit."""
+    from paper_1911_09340_amd import stages
+    from test_gpu_stages import _oracle_stages
+    ev = synth.event_mix(3)
+    sc = synth.C2
+    run = stages.StageRunner([ev], sc, max_stages=2, min_wires=30, max_back_steps=4000)
+    run.run()
+    torch.cuda.synchronize()
+    soh = run.stage_of_hit.cpu().numpy()
+    best, seeds = run.best.cpu().numpy(), run.seeds.cpu().numpy()
+    want, per_stage = _oracle_stages(orc, ev, sc, 2, 30, 4000)
+    assert len(per_stage) == 2
+    assert np.array_equal(soh, want)
+    for s, (b, seed, _) in enumerate(per_stage):
+        assert best[s, 0] == b, s
+        assert np.array_equal(seeds[s, 0], seed), s
