@@ -3,6 +3,8 @@ comet_sparse_select on its own (ties, NaN, infinities, one-point axes, several g
 and sub-grids, up to 64 references), comet_batch_classify against the batched scan's
 own classification, and the whole iterative re-scan chain, every intermediate bit for
 bit."""
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import torch
@@ -220,3 +222,36 @@ def test_multiref_graph_replays_match_eager():
             if a.is_floating_point():
                 a, b = a.nan_to_num(123.0), b.nan_to_num(123.0)
             assert torch.equal(a, b), rep
+
+
+def test_multiref_chain_full_size_matches_cpu(orc):
+    """The several-reference chain at the size the bench runs it (first grid
+    8 x 16 x 16 x 16, 10 references, two re-scans of 10 x 4 x 8 x 8 x 8 grids, 10 final
+    seeds, 1000 x 2 mm) on a two-turn event, every intermediate against the CPU chain."""
+    ev = synth.event_mix(0)
+    assert ev.n_turns == 2
+    sc = replace(synth.C2, n_refine=0)
+    n_fine, R, F, n_iter = (4, 8, 8, 8), 10, 10, 2
+    run = multiref.MultiRefRunner([ev], sc, n_ref=R, n_iter=n_iter, n_fine=n_fine, n_final=F)
+    run.run()
+    torch.cuda.synchronize()
+    rss0 = run.rss0.cpu().numpy()
+    grids = [g.cpu().numpy() for g in run.grids]
+    rss = [r.cpu().numpy() for r in run.rss]
+    fidx, frss = run.final_idx.cpu().numpy(), run.final_rss.cpu().numpy()
+    fseed = run.final_seed.cpu().numpy().reshape(run.n_part, F, 6)
+    mask = run.mask.cpu().numpy().reshape(run.n_part, F, -1)
+    g0 = run.grids0.cpu().numpy()
+    for p in range(ev.n_turns):
+        steps, widx, wrss, wseeds, wmasks = _oracle_chain(orc, ev, g0[p], sc, sc.n, n_fine, R,
+                                                          n_iter, F)
+        assert np.array_equal(rss0[p], steps[0][1][0]), p
+        for k in range(n_iter):
+            assert np.array_equal(grids[k][p], steps[k + 1][0]), (p, k)
+            assert np.array_equal(rss[k][p], steps[k + 1][1]), (p, k)
+        assert np.array_equal(fidx[p], widx), p
+        assert np.array_equal(frss[p], wrss, equal_nan=True), p
+        for r in range(F):
+            if wseeds[r] is not None:
+                assert np.array_equal(fseed[p, r], wseeds[r]), (p, r)
+                assert np.array_equal(mask[p, r, :ev.n_hits], wmasks[r]), (p, r)
