@@ -113,12 +113,21 @@ def _check_side(orc, side, evs, sc, n_fine, R, n_iter, F):
     return np.asarray(wrss), wmasks
 
 
-def test_half_track_chain_matches_cpu(orc):
-    events = [synth.event_mix(i) for i in (4, 8)]
-    sc = synth.ScanConfig("half", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 800, 2.0, 0.8, 0)
-    n_fine, R, n_iter, F = (2, 3, 3, 4), 4, 1, 5
+@pytest.mark.parametrize("size", ["small", "bench"])
+def test_half_track_chain_matches_cpu(orc, size):
+    """Both sides' chains, vetoes and the ranked complete sets against the CPU; "bench"
+    runs the bench's sizes (each side: 8 x 16 x 16 x 16 first grid, 10 references, two
+    re-scans of 10 x 4 x 8 x 8 x 8, 10 final seeds, 500 x 2 mm) on a two-turn event."""
+    if size == "small":
+        events = [synth.event_mix(i) for i in (4, 8)]
+        sc = synth.ScanConfig("half", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 800, 2.0, 0.8, 0)
+        n_fine, R, n_iter, F = (2, 3, 3, 4), 4, 1, 5
+    else:
+        events = [synth.event_mix(0)]
+        sc = synth.C2
+        n_fine, R, n_iter, F = (4, 8, 8, 8), 10, 2, 10
     run = halves.HalfTrackRunner(events, sc, n_ref=R, n_iter=n_iter, n_fine=n_fine, n_final=F)
-    assert run.sc_half.n_steps == 400
+    assert run.sc_half.n_steps == sc.n_steps // 2
     run.run()
     torch.cuda.synchronize()
     vetoes = [v.cpu().numpy().reshape(run.n_part, F) for v in run.veto]
