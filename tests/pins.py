@@ -988,3 +988,116 @@ def pin_scan_partition_field_uniform(o):
 
 
 ALL_SIMPLE.append(pin_scan_partition_field_uniform)
+
+
+# ------------------------------------------------------------------ partition loop
+def _constant_map(bz):
+    b = np.zeros((2, 2, 2, 3))
+    b[..., 2] = bz
+    return (b, np.array([-2000.0, -2000.0, -2000.0]), np.array([4000.0, 4000.0, 4000.0]))
+
+
+def pin_scan_partition_dyadic(o, field=None):
+    """Sec. 2.1: scan, then finer re-scans around the best seed, then classification.
+
+    One axis at a time is scanned with 5 points (the other three axes hold one point at
+    the truth), on a sigma = 0 event. The scanned axis starts at offsets 5, 9, 13, 17,
+    21 times s from the truth (centre 13 s, half-span 8 s). Along one axis near the truth
+    the capped RSS does not decrease away from the truth, and argmin ties go to the lower
+    index, so every scan picks the point nearest the truth: offset 5 s (index 0) first;
+    the re-scan around it (half-span = one spacing, 4 s) gives 1, 3, 5, 7, 9 s and picks
+    1 s (index 0); the second re-scan (half-span 2 s) gives -1, 0, 1, 2, 3 s and picks
+    offset 0 (index 1). With s a power of two every grid value is exact, so after exactly
+    two re-scans the chosen seed is the truth-state point (RSS within the chord bound,
+    every signal hit classified) and the final grid is centre s, half-span 2 s. The
+    mirrored start (offsets -21 ... -5 s) picks index 4, 4, then 3 (the nearest point's
+    RSS is below N lambda^2, so no capped tie reaches it), and ends at centre -s. One
+    re-scan more or less, a re-scan around another point, or classification at an
+    earlier grid's choice gives another grid, index or hit set."""
+    ev = synth.event_plain(0, sigma=0.0)
+    lam, h, K = 1.0, 2.0, 1000
+    ref = ev.ref_states[0]
+    p_ref = float(np.sqrt(ref[3] ** 2 + ref[4] ** 2 + ref[5] ** 2))
+    R = np.hypot(ref[3], ref[4]) / (KAPPA * ev.bz)
+    bound = h * h / (8 * R) + 1e-6
+    cfg = [ev.bz, ev.charge, h, lam]
+    steps = [0.25, 0.125, 2.0 ** -10, 2.0 ** -10]   # mm, MeV/c, rad, rad
+    signal = ev.hit_turn >= 0
+    first_masks_differ = 0
+    for a, s in [(a, sg * s) for a, s in enumerate(steps) for sg in (1.0, -1.0)]:
+        n = np.ones(4, np.int32)
+        n[a] = 5
+        centre = np.array([0.0, p_ref, 0.0, 0.0])
+        half = np.zeros(4)
+        centre[a] += 13 * s
+        half[a] = 8 * abs(s)
+        grid = np.concatenate([ref, centre, half])
+        if field is None:
+            out = o.scan_partition(grid, n, cfg, K, 2, ev.wire_ends, ev.wire_offsets, ev.drift)
+        else:
+            out = o.scan_partition_field(grid, n, _constant_map(ev.bz), field, cfg, K, 2,
+                                         ev.wire_ends, ev.wire_offsets, ev.drift)
+        want_c = centre.copy()
+        want_c[a] = (0.0 if a != 1 else p_ref) + s
+        want_h = half.copy()
+        want_h[a] = 2 * abs(s)
+        want_b = 1 if s > 0 else 3
+        assert out["best"] == want_b, ("axis", a, "best", out["best"])
+        assert np.array_equal(out["grid"][6:10], want_c), ("axis", a, "centre", out["grid"][6:10])
+        assert np.array_equal(out["grid"][10:14], want_h), ("axis", a, "half", out["grid"][10:14])
+        assert np.array_equal(out["grid"][:6], ref), ("axis", a, "reference state")
+        assert np.array_equal(out["best_seed"], o.seed(out["grid"], n, want_b)), ("axis", a)
+        # offset 0 on every axis: the truth direction and |p| at the truth position
+        assert abs(np.linalg.norm(out["best_seed"][3:]) - p_ref) < 1e-12 * p_ref, ("axis", a)
+        assert np.abs(out["best_seed"][:3] - ref[:3]).max() < 1e-9, ("axis", a, "position")
+        assert out["best_rss"] <= ev.n_wires * bound ** 2, ("axis", a, "rss", out["best_rss"])
+        assert out["rss"][want_b] == out["best_rss"] and out["rss"].size == 5, ("axis", a)
+        assert np.all(out["mask"][signal] & 1), ("axis", a, "signal hits classified")
+        # the first scan's choice (offset 5 s) classifies a different hit set on some axis
+        g0 = grid.copy()
+        g0[6 + a] = grid[6 + a] - 8 * s   # offset 5 s (-5 s mirrored)
+        m0, _, _ = o.classify(o.seed(g0, np.ones(4, np.int32), 0), cfg, K, ev.wire_ends,
+                              ev.wire_offsets, ev.drift)
+        first_masks_differ += int(not np.array_equal(m0 & 1, out["mask"] & 1))
+    assert first_masks_differ >= 4, first_masks_differ
+
+
+def pin_scan_partition_dyadic_field(o):
+    """The same dyadic re-scan case through the field-map partition path in a constant
+    map B = (0, 0, B_z), with RK4 and with RKN: the tracks agree with the uniform ones to
+    rounding, far below the gaps between the grid points' RSS."""
+    for stepper in (0, 1):
+        pin_scan_partition_dyadic(o, field=stepper)
+
+
+def pin_scan_partition_steps(o):
+    """The partition path equals its steps taken one after the other as Sec. 2.1 states
+    them: seed grid, RSS of every seed, lowest RSS (lower index on ties), grid re-centred
+    on it with one spacing as half-span, again n_refine times, then the hit classification
+    of the last choice (each step pinned on its own above)."""
+    ev = synth.event_signal(0)
+    sc = synth.ScanConfig("ps", (3, 4, 3, 3), (8.0, 4.0, 0.08, 0.06), 400, 2.0, 0.8, 2)
+    cfg = [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+    n = np.array(sc.n, np.int32)
+    for turn in range(ev.n_turns):
+        grid = synth.grid_descriptor(ev.ref_states[turn], sc)
+        out = o.scan_partition(grid, n, cfg, sc.n_steps, sc.n_refine, ev.wire_ends,
+                               ev.wire_offsets, ev.drift)
+        g = grid.copy()
+        b = -1
+        for it in range(sc.n_refine + 1):
+            if it > 0:
+                g = o.refine_grid(g, n, b)
+            rss, _ = o.scan(o.seed_grid(g, n), cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                            ev.drift)
+            b = o.argmin(rss)
+        seed = o.seed(g, n, b)
+        mask, _, nb = o.classify(seed, cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+        assert out["best"] == b and np.array_equal(out["grid"], g), turn
+        assert np.array_equal(out["rss"], rss) and out["best_rss"] == rss[b], turn
+        assert np.array_equal(out["best_seed"], seed), turn
+        assert np.array_equal(out["mask"], mask) and out["n_borderline"] == nb, turn
+
+
+ALL_SIMPLE.extend([pin_scan_partition_dyadic, pin_scan_partition_dyadic_field,
+                   pin_scan_partition_steps])

@@ -86,6 +86,29 @@ MUTANTS = {
     "rkn_x_drops_a3": ("            x[c] = (x[c] + h * t[c]) + q6 * ((a1[c] + a2[c]) + a3[c]);", "            x[c] = (x[c] + h * t[c]) + q6 * ((a1[c] + a2[c]) + a2[c]);"),
     "rkn_dual_midpoint": ("            xs[c] = dadd(dadd(x[c], dmul(hh, t[c])), dmul(q8, a1[c]));", "            xs[c] = dadd(dadd(x[c], dmul(hh, t[c])), dmul(q2, a1[c]));"),
     "dca_no_sqrt": ("double D = sqrt(oracle_dca2(pts, P, frames + 8 * i, NULL));", "double D = (oracle_dca2(pts, P, frames + 8 * i, NULL));"),
+    # the partition loop of Sec. 2.1: scan, re-scans around the best, classification
+    "partition_one_rescan_short": ("    int64_t b = -1;\n    for (int32_t it = 0; it <= n_refine; ++it) {",
+                                   "    int64_t b = -1;\n    for (int32_t it = 0; it < n_refine; ++it) {"),
+    "partition_one_rescan_extra": ("    int64_t b = -1;\n    for (int32_t it = 0; it <= n_refine; ++it) {",
+                                   "    int64_t b = -1;\n    for (int32_t it = 0; it <= n_refine + 1; ++it) {"),
+    "partition_refine_before_first_scan": ("    int64_t b = -1;\n    for (int32_t it = 0; it <= n_refine; ++it) {\n        if (it > 0)",
+                                           "    int64_t b = 0;\n    for (int32_t it = 0; it <= n_refine; ++it) {\n        if (it >= 0)"),
+    "partition_classify_first_best": [
+        ("        b = oracle_argmin(rss, S);\n    }",
+         "        b = oracle_argmin(rss, S);\n        if (it == 0 && b >= 0)\n            oracle_seed(grid, n, b, best_seed);\n    }"),
+        ("        oracle_seed(grid, n, b, best_seed);\n        *best_rss = rss[b];",
+         "        *best_rss = rss[b];"),
+    ],
+    "field_partition_one_rescan_short": ("    int64_t best = -1;\n    for (int32_t it = 0; it <= n_refine; ++it) {",
+                                         "    int64_t best = -1;\n    for (int32_t it = 0; it < n_refine; ++it) {"),
+    "field_partition_classify_first_best": [
+        ("        best = oracle_argmin(rss, S);\n    }",
+         "        best = oracle_argmin(rss, S);\n        if (it == 0 && best >= 0)\n            oracle_seed(grid, n, best, best_seed);\n    }"),
+        ("        oracle_seed(grid, n, best, best_seed);\n        *best_rss = rss[best];",
+         "        *best_rss = rss[best];"),
+    ],
+    "partition_refine_around_index0": ("        if (it > 0)\n            oracle_refine_grid(grid, n, b);\n        oracle_seed_grid(grid, n, seeds);\n        oracle_scan(",
+                                       "        if (it > 0)\n            oracle_refine_grid(grid, n, 0);\n        oracle_seed_grid(grid, n, seeds);\n        oracle_scan("),
 }
 
 
@@ -114,13 +137,17 @@ def events():
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(name, events):
-    old, new = MUTANTS[name]
+    edits = MUTANTS[name]
+    if isinstance(edits, tuple):
+        edits = [edits]
     src = open(oracle.SRC).read()
-    assert src.count(old) == 1, "mutation anchor not found exactly once: %s" % name
+    for old, new in edits:
+        assert src.count(old) == 1, "mutation anchor not found exactly once: %s" % name
+        src = src.replace(old, new)
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "mutant.c")
         with open(path, "w") as f:
-            f.write(src.replace(old, new))
+            f.write(src)
         lib = oracle.load(oracle.build(src=path, out=os.path.join(d, "libmutant.so")))
         with np.errstate(all="ignore"):
             failed = _run_all_pins(oracle.Oracle(lib), *events)
