@@ -61,8 +61,10 @@ class PartitionScanner:
         self.n_border = torch.empty(1, dtype=torch.int32, device=device)
         self.dca_best = torch.empty(n_wires, **f64)
 
-    def run(self, ev: DeviceEvent, grid0: torch.Tensor, n_refine: int) -> None:
-        """The whole path for one partition; results stay in the buffers."""
+    def run(self, ev: DeviceEvent, grid0: torch.Tensor, n_refine: int, on_scan=None) -> None:
+        """The whole path for one partition; results stay in the buffers. on_scan (optional,
+        for inspection) is called as on_scan(it, self) after scan it's selection, while
+        self.grid, self.rss and self.best still hold that scan's grid, RSS and choice."""
         self.grid.copy_(grid0)
         for it in range(n_refine + 1):
             if it:
@@ -76,6 +78,8 @@ class PartitionScanner:
                                   hit_mask=self.mask if last else None,
                                   n_borderline=self.n_border if last else None,
                                   dca_best=self.dca_best if last else None)
+            if on_scan is not None:
+                on_scan(it, self)
 
     def result(self) -> dict:
         """Copy the partition's results to the host (synchronises)."""

@@ -2,7 +2,8 @@
 seeds against the CPU reference (which computes each seed on its own):
 
 - the batched mix: 32768 seeds per partition (8 x 16 x 16 x 16), 1000 x 2 mm, two
-  finer re-scans, graph-free eager run of the persistent kernel;
+  finer re-scans, graph-free eager run of the persistent kernel; every seed of the last
+  grid of each partition;
 - the stress mix: 131072 seeds per partition (8 x 16 x 32 x 32), 2000 x 1.5 mm;
 - the fine grid of the differentiation workload: 32^4 = 1048576 seeds;
 - Levenberg-Marquardt on stress-size tracks (2000 steps) vs the CPU LM.
@@ -30,8 +31,9 @@ def _cfg(ev, sc):
 
 
 def _check_partitions(orc, runner, events, sc, n_sample, seed):
-    """Sampled RSS of the last grid bit for bit, the argmin against the full RSS row,
-    and the classification of the chosen seed."""
+    """RSS of the last grid bit for bit (every seed when n_sample is None, else a sample
+    and the chosen one), the choice against the GPU row's first minimum (and against the
+    CPU row's when it is whole), and the classification of the chosen seed."""
     rss = runner.rss.cpu().numpy()
     best = runner.best.cpu().numpy()
     grids = runner.grids.cpu().numpy()
@@ -43,12 +45,18 @@ def _check_partitions(orc, runner, events, sc, n_sample, seed):
         for _ in range(ev.n_turns):
             row = rss[p]
             assert best[p] == int(np.argmin(row)), p      # first index of the minimum
-            idx = np.unique(np.concatenate([rng.integers(0, sc.n_seeds, n_sample),
-                                            [0, sc.n_seeds - 1, best[p]]]))
-            seeds = np.stack([orc.seed(grids[p], n, int(i)) for i in idx], axis=1)
-            want, _ = orc.scan(seeds, _cfg(ev, sc), sc.n_steps, ev.wire_ends, ev.wire_offsets,
-                               ev.drift)
-            assert np.array_equal(row[idx], want), p
+            if n_sample is None:
+                want, _ = orc.scan(orc.seed_grid(grids[p], n), _cfg(ev, sc), sc.n_steps,
+                                   ev.wire_ends, ev.wire_offsets, ev.drift)
+                assert np.array_equal(row, want), (p, int(np.sum(row != want)))
+                assert best[p] == orc.argmin(want), p
+            else:
+                idx = np.unique(np.concatenate([rng.integers(0, sc.n_seeds, n_sample),
+                                                [0, sc.n_seeds - 1, best[p]]]))
+                seeds = np.stack([orc.seed(grids[p], n, int(i)) for i in idx], axis=1)
+                want, _ = orc.scan(seeds, _cfg(ev, sc), sc.n_steps, ev.wire_ends,
+                                   ev.wire_offsets, ev.drift)
+                assert np.array_equal(row[idx], want), p
             wmask, _, _ = orc.classify(orc.seed(grids[p], n, int(best[p])), _cfg(ev, sc),
                                        sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
             assert np.array_equal(mask[p, :ev.n_hits], wmask), p
@@ -61,7 +69,7 @@ def test_batched_mix_full_size_sampled(orc):
     runner = scan.BatchRunner(events, sc)
     runner.run()
     torch.cuda.synchronize()
-    _check_partitions(orc, runner, events, sc, 24, 1)
+    _check_partitions(orc, runner, events, sc, None, 1)   # every partition's whole row
 
 
 def test_stress_full_size_sampled(orc):
