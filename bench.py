@@ -9,17 +9,22 @@ best seed, then hit classification. Inputs are synthetic and already resident in
 device memory when the timed region starts.
 
 Prints one JSON line. `value` = seed x hit DCA evaluations per second (sum over
-scans of seeds x hits, divided by wall time of the timed steps). `roofline` covers
-the dominant kernel (the DCA scan): FP64 flops of the distance evaluations it
-performs per launch (15 per (seed, wire, point) evaluated, counted by the kernel;
-the scan skips points that a distance bound rules out, with the results of the
-full scan) / its average device time from HIP events recorded on its stream.
+scans of seeds x hits, divided by wall time of the timed steps, which run without
+any event timing). `roofline` covers the dominant kernel (the DCA scan), from a
+separate pass that records HIP events around each launch on its stream: its two
+ceilings are the FP64 flops of the distance evaluations it performs (15 per (seed,
+wire, point) evaluated, counted by the kernel; the scan skips points that a distance
+bound rules out, with the results of the full scan) against the FP64 vector peak, and
+the HBM bytes the counters measured for its shape against the HBM peak; `bound` is
+the one used more, and for "hbm" `achieved` is the launch's algorithmic bytes (one
+read of the track and its window radii, d^2 written) per second.
 `cpu_baseline` times the CPU reference (oracle/) on a bounded sample of the same
 workload on the host cores. Further sections (each can be switched off): the same
 step with tracks in a field map (RK4 and Runge-Kutta-Nystrom, and the batched scan in
-the map), the batched persistent scan of a mix of events, several references, half
-tracks, the stage loop (with and without the self-refining), the gradient comparison
-(coarse grid + Levenberg-Marquardt vs a fine grid) and, on request, the stress mix.
+the map), the batched persistent scan of the 1024-event mix, several references, half
+tracks, the stage loop (with and without the self-refining) and the first stage's
+efficiency and purity against lambda on 64 events of the mix, the gradient comparison on 256 events (coarse grid + Levenberg-Marquardt vs a
+fine grid) and 64 events of the stress mix.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
   python bench.py --sweep             # time every DCA kernel shape
@@ -69,9 +74,8 @@ def stored_traffic(shape: dict):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    name = "dca_kernel<%d, %d, %d, %s, %s, %d>" % (
-        shape["w"], shape["nwv"], shape["chunk"], "true" if shape["chunk_argmin"] else "false",
-        "true" if shape.get("direct") else "false", shape.get("runs", 1))
+    from paper_1911_09340_amd import comet
+    name = comet.dca_kernel_name(shape)
     if t.get("kernel_sha") != kernel_hash():
         return None
     return t.get("shapes", {}).get(name, {}).get("bytes_per_launch")
@@ -114,7 +118,7 @@ def cpu_baseline(ev, sc, target_s: float):
                       (m, ev.n_hits, ev.n_wires)}
 
 
-def bench_batch(events, sc, reps: int = 3):
+def bench_batch(events, sc, reps: int = 2):
     """Every partition of `events` through the batched path, captured in a HIP graph."""
     import torch
     from paper_1911_09340_amd import comet, quality, refine, scan
@@ -299,6 +303,42 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
                          else None, len(v)] for k, v in sorted(by_turns.items())}}
 
 
+def bench_lambda_sweep(events, sc, lambdas=(0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2),
+                       fit_iters: int = 8, eta: float = 0.3):
+    """Hit-classification efficiency and purity of the first stage (each event's last
+    turn) against the cutoff lambda, before and after the self-refining (Sec. 3.3's
+    lambda scan at eta = 0.3 mm): the stage loop run for one stage per lambda."""
+    import torch
+    from dataclasses import replace
+    from paper_1911_09340_amd import quality, stages
+    rows = []
+    for lam in lambdas:
+        row = {"lambda_mm": lam}
+        for key, fi in (("before", 0), ("after", fit_iters)):
+            run = stages.StageRunner(events, replace(sc, lambda_mm=lam), max_stages=1,
+                                     min_wires=30, fit_iters=fi, eta=eta)
+            run.run()
+            torch.cuda.synchronize()
+            tm = run.turn_masks()
+            eff, pur = [], []
+            for ev, m in zip(events, tm):
+                if ev.n_wires < 30:
+                    continue
+                e, u, _ = quality.turn_metrics(m[ev.n_turns - 1], ev.hit_turn)
+                eff.append(e)
+                pur.append(u)
+            row[key] = {"efficiency_mean": float(np.mean(eff)),
+                        "purity_mean": float(np.nanmean(pur)), "events": len(eff)}
+        rows.append(row)
+        log("  lambda %.1f mm: efficiency %.3f -> %.3f, purity %.3f -> %.3f (before -> after "
+            "self-refining)" % (lam, row["before"]["efficiency_mean"],
+                                row["after"]["efficiency_mean"], row["before"]["purity_mean"],
+                                row["after"]["purity_mean"]))
+    return {"eta_mm": eta, "stage": "first (each event's last turn)",
+            "self_refining": "%d LM iterations, lambda re-test, eta re-admission" % fit_iters,
+            "rows": rows}
+
+
 def bench_field_batched(events, sc, reps: int = 2):
     """The batched persistent scan of the mix with every track in the solenoid map (RKN),
     eager runs, device-synchronised wall time."""
@@ -400,10 +440,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--batch-events", type=int, default=64,
+    ap.add_argument("--batch-events", type=int, default=1024,
                     help="events of the batched mix timed through the persistent batched path "
                          "(0 = skip; 1024 = the full batching workload)")
-    ap.add_argument("--grad-events", type=int, default=32,
+    ap.add_argument("--mix-events", type=int, default=64,
+                    help="events of the batched mix for the several-reference, half-track, "
+                         "stage-loop and batched field-map sections (0 = skip them)")
+    ap.add_argument("--grad-events", type=int, default=256,
                     help="events of the batched mix for the coarse+LM vs fine-grid comparison "
                          "(0 = skip; 256 = the full differentiation workload)")
     ap.add_argument("--grad-topk", type=int, default=16,
@@ -417,10 +460,11 @@ def main():
                     help="skip the field-map variant of the signal workload")
     ap.add_argument("--no-stages", dest="stages", action="store_false",
                     help="skip the stage loop on the batched mix")
-    ap.add_argument("--stress-events", type=int, default=0,
+    ap.add_argument("--stress-events", type=int, default=64,
                     help="events of the stress mix (1-6 turns, 200-1200 hits, 30%% noise, "
                          "131072 seeds, 2000 x 1.5 mm) through the batched scan and LM from "
-                         "the 64 lowest-RSS seeds per partition (0 = skip)")
+                         "the 64 lowest-RSS seeds per partition (0 = skip; the full workload "
+                         "is 8192 events)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -431,8 +475,8 @@ def main():
 
     # events for the gradient comparison are drawn before the GPU is touched, so that
     # worker processes can be forked safely
-    grad_events, batch_events, stress_events = [], [], []
-    n_mix = max(args.grad_events, args.batch_events)
+    grad_events, batch_events, mix_events, stress_events = [], [], [], []
+    n_mix = max(args.grad_events, args.batch_events, args.mix_events)
     if not args.calibrate_copy:
         from paper_1911_09340_amd import synth as _synth
         workers = min(16, os.cpu_count() or 1)
@@ -440,6 +484,7 @@ def main():
             t0 = time.perf_counter()
             mix = _synth.event_mix_batch(range(n_mix), workers=workers)
             grad_events, batch_events = mix[:args.grad_events], mix[:args.batch_events]
+            mix_events = mix[:args.mix_events]
             log("drew %d mix events in %.1f s" % (len(mix), time.perf_counter() - t0))
         if args.stress_events > 0:
             t0 = time.perf_counter()
@@ -473,17 +518,21 @@ def main():
         for t in range(ev.n_turns):
             runners[t].run(dev, grids[t], sc.n_refine)
 
-    def timed(steps, warmup):
+    def timed(steps, warmup, profile=False):
+        """Wall time of `steps` steps; with profile, per-kind kernel times from HIP events
+        and the DCA scans' evaluation count (a separate pass: the headline runs without
+        them)."""
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        comet.profile_begin()
+        if profile:
+            comet.profile_begin()
         t0 = time.perf_counter()
         for _ in range(steps):
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        return t1 - t0, comet.profile_end()
+        return t1 - t0, (comet.profile_end() if profile else None)
 
     variants = comet.dca_variants()
     # autotune the DCA kernel shape on the first partition's live buffers
@@ -496,7 +545,7 @@ def main():
     if args.sweep:
         for i, v in enumerate(variants):
             comet.set_dca_variant(i)
-            dt, prof = timed(max(2, args.steps // 2), 1)
+            dt, prof = timed(max(2, args.steps // 2), 1, profile=True)
             ms, n = prof["dca"]
             tfl = FLOP_PER_POINT_WIRE * prof["scan_points"] / n / (ms / n * 1e-3) / 1e12
             log("variant %d %s: %.3f ms/step, dca %.3f ms/launch, %.1f TFLOP/s (%.1f %% of FP64 peak)"
@@ -506,8 +555,11 @@ def main():
 
     log("warmup %d, timing %d steps (%d scans of %d seeds x %d hits each) ..."
         % (args.warmup, args.steps, scans_per_step, sc.n_seeds, ev.n_hits))
-    dt, prof = timed(args.steps, args.warmup)
-    log("timed region %.3f s" % dt)
+    dt, _ = timed(args.steps, args.warmup)
+    log("timed region %.3f s (no event timing)" % dt)
+    # per-kernel times and the evaluation count in a separate, event-timed pass
+    prof_steps = max(3, args.steps // 2)
+    _, prof = timed(prof_steps, 0, profile=True)
     ms_dca, n_dca = prof["dca"]
     dca_s = ms_dca / n_dca * 1e-3
     brute = FLOP_PER_POINT_WIRE * sc.n_seeds * ev.n_wires * P
@@ -517,6 +569,20 @@ def main():
     # the track, the seeds read, and the radii of its 16-point windows written with it
     trk_bytes = 8 * 3 * P * sc.n_seeds + 8 * 6 * sc.n_seeds + 8 * ((P - 1) // 16 + 1) * sc.n_seeds
     traffic = stored_traffic(variants[variant])
+    # the DCA launch's algorithmic bytes: one read of the track and of its window radii,
+    # the per-(wire, seed) d^2 written
+    n_win = (P - 1) // 16 + 1
+    dca_alg_bytes = 8 * 3 * P * sc.n_seeds + 8 * n_win * sc.n_seeds + 8 * ev.n_wires * sc.n_seeds
+    fp64_frac = achieved / PEAK_FP64_TFLOPS
+    hbm_used_frac = None if traffic is None else traffic / dca_s / 1e9 / PEAK_HBM_GBS
+    # the binding resource: the one the launch uses the larger share of
+    if hbm_used_frac is not None and hbm_used_frac > fp64_frac:
+        headline = {"bound": "hbm", "achieved": dca_alg_bytes / dca_s / 1e9,
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": dca_alg_bytes / dca_s / 1e9 / PEAK_HBM_GBS}
+    else:
+        headline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": fp64_frac}
 
     out = {
         "metric": METRIC,
@@ -544,22 +610,30 @@ def main():
             "dca_kernel_shape": variants[variant],
         },
         "events_per_s": args.steps / dt,
-        "roofline": {
-            "kernel": "dca_kernel",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
+        "roofline": dict(headline, **{
+            "kernel": comet.dca_kernel_name(variants[variant]),
             "traffic": traffic,
             "avg_launch_ms": dca_s * 1e3,
             "launches": n_dca,
+            "timing": "HIP events around each launch on its stream, in a separate pass of %d "
+                      "steps after the timed region" % prof_steps,
+            "ceilings": {
+                "fp64_executed": {"achieved_tflops": achieved, "peak_tflops": PEAK_FP64_TFLOPS,
+                                  "frac": fp64_frac},
+                "hbm_measured": None if traffic is None else {
+                    "bytes_per_launch": traffic, "achieved_gbs": traffic / dca_s / 1e9,
+                    "peak_gbs": PEAK_HBM_GBS, "frac": hbm_used_frac},
+                "hbm_algorithmic": {"bytes_per_launch": dca_alg_bytes,
+                                    "achieved_gbs": dca_alg_bytes / dca_s / 1e9,
+                                    "peak_gbs": PEAK_HBM_GBS,
+                                    "frac": dca_alg_bytes / dca_s / 1e9 / PEAK_HBM_GBS},
+            },
             "flop_per_launch": flops,
             "flop_unit": "%d FP64 flop per (seed, wire, track point) distance evaluated; the "
                          "scan skips points a distance bound rules out" % FLOP_PER_POINT_WIRE,
             "points_evaluated_frac": flops / brute,
             "full_scan_equivalent_tflops": brute / dca_s / 1e12,
-        },
+        }),
         "track_recording": {
             "kernel": "rk4_record_kernel",
             "bound": "hbm",
@@ -569,15 +643,15 @@ def main():
             "frac": trk_bytes / (ms_trk / n_trk * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "avg_launch_ms": ms_trk / n_trk,
         },
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()
+        "kernel_ms_per_step": {k: v[0] / prof_steps for k, v in prof.items()
                                if k in comet.PROFILE_KINDS},
     }
     if args.field:
         log("signal workload with tracks in a field map ...")
         out["field_map"] = bench_field(ev, sc)
         fm = out["field_map"]
-        if batch_events:
-            fm["batched_rkn"] = bench_field_batched(batch_events, synth.C2)
+        if mix_events:
+            fm["batched_rkn"] = bench_field_batched(mix_events, synth.C2)
             log("  batched mix in the map (RKN): %.1f events/s (uniform field: see batch)"
                 % fm["batched_rkn"]["events_per_s"])
         for name in ("rk4", "rkn"):
@@ -590,31 +664,27 @@ def main():
         log("  %.1f events/s, %.3g seed x hit evals/s, scan kernel %.1f %% of FP64 peak"
             % (out["batch"]["events_per_s"], out["batch"]["evals_per_s"],
                100 * out["batch"]["scan_fp64_frac"]))
-    if batch_events and args.multiref:
+    if mix_events and args.multiref:
         log("several references: %d events, 10 references, 2 re-scans of 4x8x8x8 ..."
-            % len(batch_events))
-        out["multiref"] = bench_multiref(batch_events, synth.C2)
+            % len(mix_events))
+        out["multiref"] = bench_multiref(mix_events, synth.C2)
         m = out["multiref"]
-        log("  %.1f events/s; |p| residual core %.3f MeV/c (single reference %.3f); "
-            "efficiency %.3f purity %.3f (single reference %.3f %.3f)"
+        log("  %.1f events/s; |p| residual core %.3f MeV/c; efficiency %.3f purity %.3f"
             % (m["events_per_s"], m["momentum_residual"]["core_sigma"],
-               out["batch"]["momentum_residual"]["core_sigma"],
-               m["classification"]["efficiency_mean"], m["classification"]["purity_mean"],
-               out["batch"]["classification"]["efficiency_mean"],
-               out["batch"]["classification"]["purity_mean"]))
-    if batch_events and args.halves:
+               m["classification"]["efficiency_mean"], m["classification"]["purity_mean"]))
+    if mix_events and args.halves:
         log("half tracks: %d events, both halves with several references, veto, merge ..."
-            % len(batch_events))
-        out["halves"] = bench_halves(batch_events, synth.C2)
+            % len(mix_events))
+        out["halves"] = bench_halves(mix_events, synth.C2)
         h = out["halves"]
         log("  %.1f events/s; complete sets in %.3f of partitions; efficiency %.3f purity %.3f"
             % (h["events_per_s"], h["partitions_with_complete_set"],
                h["classification"]["efficiency_mean"], h["classification"]["purity_mean"]))
-    if batch_events and args.stages:
-        log("stage loop: %d events, up to 5 stages from the last turn back ..." % len(batch_events))
-        out["stages"] = bench_stages(batch_events, synth.C2)
+    if mix_events and args.stages:
+        log("stage loop: %d events, up to 5 stages from the last turn back ..." % len(mix_events))
+        out["stages"] = bench_stages(mix_events, synth.C2)
         log("stage loop with self-refining (8 LM iterations, eta 0.3 mm) ...")
-        out["stages_self_refined"] = bench_stages(batch_events, synth.C2, fit_iters=8)
+        out["stages_self_refined"] = bench_stages(mix_events, synth.C2, fit_iters=8)
         for key in ("stages", "stages_self_refined"):
             st = out[key]
             log("  %s: %.1f events/s; efficiency %.3f purity %.3f over all turns; by turns: %s"
@@ -622,6 +692,9 @@ def main():
                    st["classification_all_turns"]["purity_mean"],
                    ", ".join("%s: %.2f/%s" % (k, v[0], "-" if v[1] is None else "%.2f" % v[1])
                              for k, v in st["efficiency_purity_by_turns"].items())))
+    if mix_events and args.stages:
+        log("lambda sweep of the first stage (eta 0.3 mm), %d events ..." % len(mix_events))
+        out["lambda_sweep"] = bench_lambda_sweep(mix_events, synth.C2)
     if grad_events:
         from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))

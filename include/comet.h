@@ -313,6 +313,22 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
                      int64_t mask_stride, int32_t *n_borderline, int64_t max_items,
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/* comet_batch_scan over the partitions of the events with event_active[e] != 0 only
+ * (device int32[n_events]; the stage loop of Sec. 3.1 passes the events still being
+ * reconstructed): the work items of the other partitions are skipped, so their rss is
+ * not written and their best stays -1 (and their hits get mask 0). Other arguments as
+ * comet_batch_scan (max_items is 0). */
+int comet_batch_scan_active(const double *wire_ends, int32_t n_wires,
+                            const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                            const int32_t *event_wires, int32_t n_events,
+                            const int32_t *part_event, int32_t n_partitions,
+                            const double *grids_init, double *grids, const int32_t n[4],
+                            const comet_config *cfg, int32_t n_refine, double *rss,
+                            int64_t *best, double *best_seed, double *best_rss,
+                            uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
+                            const int32_t *event_active, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
 /* Several reference seeds per partition (Sec. 2.1 selects several low-RSS seeds as
  * references for the next scan). comet_topk: for each of n_segments rows of n values,
  * idx[row][0..k) = the k smallest values' indices in increasing order (ties: lower
@@ -540,9 +556,12 @@ int comet_profile_scan_points(int64_t *points);
  * comet_dca_variant_for() reports the shape a call of that size would use;
  * comet_dca_variant_info() describes shape id (0 <= id < comet_dca_variant_count()):
  * W wires per wave, NWV waves per block, chunk points, per-chunk argmin, XCD-aware
- * block order, direct (every wave on its own, no LDS staging) and runs (direct shapes:
- * chunks tested in runs of that many first, from the summed radii of their windows;
- * 1 = no runs); direct and runs may be NULL. */
+ * block order, direct (0: the block's chunks staged through LDS; 1: every wave on its
+ * own, no LDS staging; 2: wide, every wave on its own with up to 16 wires taken in
+ * azimuth order, frames in LDS, each wire of a needed chunk scanned only where the
+ * bound needs it) and runs (direct and wide shapes: chunks tested in runs of that many
+ * first, from the summed radii of their windows; 1 = no runs); direct and runs may be
+ * NULL. */
 int comet_dca_variant_count(void);
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
                            int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct,

@@ -275,10 +275,21 @@ def dca_variants():
         v = [ctypes.c_int32() for _ in range(7)]
         _check(lib.comet_dca_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_dca_variant_info")
+        form = {0: "lds", 1: "direct", 2: "wide"}[v[5].value]
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value,
                         chunk_argmin=bool(v[3].value), xcd_remap=bool(v[4].value),
-                        direct=bool(v[5].value), runs=v[6].value))
+                        direct=form != "lds", form=form, runs=v[6].value))
     return out
+
+
+def dca_kernel_name(shape: dict) -> str:
+    """The kernel symbol (template form) of a DCA shape, as a profiler names it."""
+    if shape.get("form") == "wide":
+        return "dca_wide_kernel<%d, %d, %d, %d>" % (shape["w"], shape["nwv"], shape["runs"],
+                                                    shape.get("wpe", 2))
+    return "dca_kernel<%d, %d, %d, %s, %s, %d>" % (
+        shape["w"], shape["nwv"], shape["chunk"], "true" if shape["chunk_argmin"] else "false",
+        "true" if shape.get("direct") else "false", shape.get("runs", 1))
 
 
 def set_dca_variant(i: int) -> None:
@@ -435,6 +446,9 @@ def _bind_batch(lib):
     args = list(lib.comet_batch_scan.argtypes)
     lib.comet_batch_scan_field.argtypes = args[:13] + [FP] + args[13:]
     lib.comet_batch_scan_field.restype = ctypes.c_int
+    # (..., n_borderline, event_active, workspace, bytes, stream): max_items replaced
+    lib.comet_batch_scan_active.argtypes = args[:21] + [_vp] + args[22:]
+    lib.comet_batch_scan_active.restype = ctypes.c_int
     lib.comet_batch_variant_count.restype = ctypes.c_int
     lib.comet_batch_variant_info.argtypes = [ctypes.c_int, I4, I4, I4, I4, I4, I4]
     lib.comet_batch_variant_info.restype = ctypes.c_int
@@ -487,18 +501,28 @@ def batch_workspace(n_wires: int, n_steps: int, n_partitions: int, device=None) 
 def batch_scan(packed, part_event: torch.Tensor, grids: torch.Tensor, n, cfg: Config,
                n_refine: int, rss: torch.Tensor, best: torch.Tensor, workspace: torch.Tensor,
                best_seed=None, best_rss=None, hit_mask=None, n_borderline=None,
-               max_items: int = 0, grids_init=None, field: FieldMap = None) -> None:
+               max_items: int = 0, grids_init=None, field: FieldMap = None,
+               event_active=None) -> None:
     """comet_batch_scan over packed events (scan.PackedEvents); with a field map,
-    comet_batch_scan_field (tracks in the map)."""
+    comet_batch_scan_field (tracks in the map); with event_active (int32 [n_events]),
+    comet_batch_scan_active (only the partitions of active events)."""
     lib = _bind_batch(load())
     NP = int(part_event.shape[0])
     S = int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
     n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
     n_e = int(packed.event_wires.shape[0]) - 1
     stride = int(hit_mask.shape[1]) if hit_mask is not None else 0
-    if field is None:
+    last = (int(max_items),)
+    if field is None and event_active is None:
         fn, name, fld = lib.comet_batch_scan, "comet_batch_scan", ()
+    elif field is None:
+        if max_items:
+            raise ValueError("batch_scan: max_items does not combine with event_active")
+        fn, name, fld = lib.comet_batch_scan_active, "comet_batch_scan_active", ()
+        last = (_ptr(event_active, torch.int32, "event_active", (n_e,)),)
     else:
+        if event_active is not None:
+            raise ValueError("batch_scan: event_active is not offered with a field map")
         _ptr(field.b, torch.float64, "field.b")
         fn, name = lib.comet_batch_scan_field, "comet_batch_scan_field"
         fld = (ctypes.byref(field.struct),)
@@ -515,7 +539,7 @@ def batch_scan(packed, part_event: torch.Tensor, grids: torch.Tensor, n, cfg: Co
         _ptr(best_seed, torch.float64, "best_seed", (NP, 6), optional=True),
         _ptr(best_rss, torch.float64, "best_rss", (NP,), optional=True),
         _ptr(hit_mask, torch.uint8, "hit_mask", (NP, stride), optional=True), stride,
-        _ptr(n_borderline, torch.int32, "n_borderline", (NP,), optional=True), int(max_items),
+        _ptr(n_borderline, torch.int32, "n_borderline", (NP,), optional=True), *last,
         _ptr(workspace, torch.float64, "workspace"), workspace.numel() * 8, _stream()), name)
 
 
@@ -526,8 +550,9 @@ def batch_variants():
         v = [ctypes.c_int32() for _ in range(6)]
         _check(lib.comet_batch_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_batch_variant_info")
+        form = {0: "lds", 1: "direct", 2: "wide"}[v[4].value]
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value, blocks=v[3].value,
-                        direct=bool(v[4].value), runs=v[5].value))
+                        direct=form != "lds", form=form, runs=v[5].value))
     return out
 
 

@@ -59,6 +59,7 @@ struct BatchArgs {
     int64_t *best;            // [NP]
     unsigned long long *evals;  // profiling: distance evaluations, or null
     FieldMap fm;              // the field map of the FIELD kernel (tracks as field.hip records them)
+    const int32_t *active;    // [E] or null: the partitions of events with active[e] == 0 are skipped
 };
 
 // One seed's track in the map into a tile's scratch rows (stride 64) with its chunk
@@ -143,6 +144,8 @@ batch_scan_kernel(BatchArgs a)
         const int n_sub = (int)max((int64_t)0, min(min((int64_t)NWV, (int64_t)(a.tiles - t0)),
                                                    a.max_tiles - first_global));
         const int e = a.part_event[p];
+        if (a.active && a.active[e] == 0)
+            continue;  // block-uniform: the whole item is skipped, the partition keeps best -1
         const int w0 = a.ev_wires[e], w1 = a.ev_wires[e + 1];
 
         // seeds and tracks: wave w records tile t0 + w (one seed per lane)
@@ -240,6 +243,101 @@ batch_scan_kernel(BatchArgs a)
                 a.best[p] = b;
         }
         __syncthreads();
+    }
+}
+
+// The wide form, wave-persistent: every wave on its own takes work items (a partition
+// and one 64-seed tile) from the work counter, records the tile's tracks into its own
+// scratch rows, then scans them against the event's wires W at a time in wire order
+// (cdev::TileScanWide; the frames of each group go to the wave's own LDS rows), and
+// adds the d^2 of each wire to its lanes' RSS as they come, so the sum runs in wire
+// order as in the single-event path. No block barrier: a wave that finishes a
+// partition's last tile selects its best seed on its own. WPE: waves per SIMD the
+// registers are sized for.
+template <int W, int NWV, int SUP, int WPE, bool FIELD = false>
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
+batch_wide_kernel(BatchArgs a)
+{
+    __shared__ __align__(16) double fl_all[NWV * W * 8];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *const fl = fl_all + wave * W * 8;
+    const int P = a.K + 1;
+    const int64_t row = (int64_t)P * 64;                 // one coordinate of one tile
+    const int64_t rrow = (int64_t)radius_chunks(P) * 64;  // chunk radii of one tile
+    double *const sx = a.scratch + ((int64_t)blockIdx.x * NWV + wave) * (3 * row + rrow);
+    double *const sy = sx + row, *const sz = sy + row;
+    double *const rho = sz + row;
+
+    for (;;) {
+        const int64_t item = __builtin_amdgcn_readfirstlane(atomicAdd(a.counter, lane == 0 ? 1 : 0));
+        if (item >= a.n_items)
+            break;
+        const int p = (int)(item / a.tiles);
+        const int t = (int)(item - (int64_t)p * a.tiles);
+        const int64_t s0 = (int64_t)t * 64;
+        const int n_valid = (int)min((int64_t)64, a.S - s0);
+        const int e = a.part_event[p];
+        if (a.active && a.active[e] == 0)
+            continue;  // wave-uniform: the partition keeps best -1
+        const int w0 = a.ev_wires[e], w1 = a.ev_wires[e + 1];
+        if (lane < n_valid) {
+            double st[6];
+            seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, s0 + lane, st);
+            if constexpr (FIELD) {
+                record_field_track(a.fm, st, a.charge, a.h, a.K, sx, sy, sz, rho + lane, lane);
+            } else {
+                ChunkRadius rad;
+                double x = st[0], y = st[1], z = st[2], px = st[3], py = st[4];
+                const StepConsts kc = step_consts(px, py, st[5], a.bz, a.charge, a.h);
+                for (int k = 0; k < a.K; ++k) {
+                    sx[(int64_t)k * 64 + lane] = x;
+                    sy[(int64_t)k * 64 + lane] = y;
+                    sz[(int64_t)k * 64 + lane] = z;
+                    rad.add(k, P, x, y, z, rho + lane, 64);
+                    rk4_step(kc, x, y, z, px, py);
+                }
+                sx[(int64_t)a.K * 64 + lane] = x;
+                sy[(int64_t)a.K * 64 + lane] = y;
+                sz[(int64_t)a.K * 64 + lane] = z;
+                rad.add(a.K, P, x, y, z, rho + lane, 64);
+            }
+        }
+        // each lane reads back only its own column; the fence orders its stores before
+        // the scan's loads
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        double acc = 0.0;
+        for (int g0 = w0; g0 < w1; g0 += W) {
+            const int nw = min(W, w1 - g0);  // wave-uniform
+            // the group's frames into this wave's LDS rows (zero frames past the event)
+            for (int i = lane; i < W * 8; i += 64)
+                fl[i] = i < nw * 8 ? a.frames[8 * (int64_t)g0 + i] : 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            int32_t wire_of[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                wire_of[w] = g0 + w;
+            double d2[W];
+            TileScanWide<W, SUP, true>::run(sx, sy, sz, 64, P, n_valid, fl, nw, wire_of,
+                                            a.offsets, a.drift, a.lambda, rho, 64, a.evals, d2);
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (w < nw)
+                    acc = acc + d2[w];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // frames read before reuse
+        }
+        if (lane < n_valid)
+            a.rss[(int64_t)p * a.S + s0 + lane] = acc;
+        // completion counter of partition p; the wave that counts its last tile selects
+        // the partition's best seed (release before the count, acquire before the reads)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int old = __builtin_amdgcn_readfirstlane(atomicAdd(a.done + p, lane == 0 ? 1 : 0));
+        if (old + 1 == a.tiles) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int64_t b = wave_argmin(a.rss + (int64_t)p * a.S, a.S);
+            if (lane == 0)
+                a.best[p] = b;
+        }
     }
 }
 
@@ -642,9 +740,9 @@ __global__ void copy_kernel(const double *__restrict__ src, double *__restrict__
 
 // ------------------------------------------------------------------ shapes
 struct BatchVariant {
-    int w, nwv, c, direct;
+    int w, nwv, c, direct;  // direct: 0 LDS-staged, 1 every wave on its own, 2 wide
     void (*kernel)(BatchArgs);
-    int runs;  // direct shapes: chunks tested in runs of this many first (1: no runs)
+    int runs;  // direct and wide shapes: chunks tested in runs of this many first (1: no runs)
 };
 
 const BatchVariant kBatchVariants[] = {
@@ -661,6 +759,10 @@ const BatchVariant kBatchVariants[] = {
     // runs of 4 chunks tested first (two-level distance bound)
     {4, 8, 16, 1, batch_scan_kernel<4, 8, 16, 4, true, false, 4>, 4},
     {3, 8, 16, 1, batch_scan_kernel<3, 8, 16, 4, true, false, 4>, 4},
+    // wide, wave-persistent: one tile per wave item, W wires per pass in wire order
+    {16, 4, 16, 2, batch_wide_kernel<16, 4, 4, 2>, 4},
+    {16, 4, 16, 2, batch_wide_kernel<16, 4, 1, 2>, 1},
+    {12, 4, 16, 2, batch_wide_kernel<12, 4, 4, 2>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
@@ -780,7 +882,8 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
                     const comet_config *cfg, const comet_field *field, int32_t n_refine,
                     double *rss, int64_t *best, double *best_seed, double *best_rss,
                     uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
-                    int64_t max_items, void *workspace, size_t workspace_bytes, void *stream)
+                    int64_t max_items, void *workspace, size_t workspace_bytes, void *stream,
+                    const int32_t *event_active = nullptr)
 {
     if (!wire_ends || !wire_offsets || !event_wires || !part_event || !grids || !n || !rss ||
         !best)
@@ -843,17 +946,18 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
     if (blocks < 1)
         return fail(COMET_EHIP, "comet_batch_scan: occupancy query failed");
     const int tiles = (int)((S + 63) / 64);
-    const int supers = (tiles + v.nwv - 1) / v.nwv;
+    const int per_item = v.direct == 2 ? 1 : v.nwv;  // tiles per work item
+    const int supers = (tiles + per_item - 1) / per_item;
     int64_t max_tiles = (int64_t)n_partitions * tiles;
     if (max_items > 0 && max_items < max_tiles)
         max_tiles = max_items;
     // work items: the super-tiles that hold at least one of the first max_tiles tiles
     const int64_t full = max_tiles / tiles, rest = max_tiles - full * tiles;
-    const int64_t items = full * supers + (rest + v.nwv - 1) / v.nwv;
+    const int64_t items = full * supers + (rest + per_item - 1) / per_item;
     BatchArgs args{l.frames, wire_offsets, drift, event_wires, part_event, grids, n[0], n[1],
                    n[2], n[3], S, tiles, supers, items, max_tiles, cfg->bz_tesla,
                    cfg->charge_e, cfg->step_mm, cfg->lambda_mm, cfg->n_steps, l.scratch,
-                   l.counter, l.done, rss, best, scan_counter(), field_map(field)};
+                   l.counter, l.done, rss, best, scan_counter(), field_map(field), event_active};
     for (int it = 0; it <= n_refine && st == COMET_OK; ++it) {
         if (it) {
             hipLaunchKernelGGL(batch_refine_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0,
@@ -936,6 +1040,27 @@ int comet_batch_scan(const double *wire_ends, int32_t n_wires, const int32_t *wi
                            nullptr, n_refine, rss, best, best_seed, best_rss, hit_mask,
                            mask_stride, n_borderline, max_items, workspace, workspace_bytes,
                            stream);
+}
+
+int comet_batch_scan_active(const double *wire_ends, int32_t n_wires,
+                            const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                            const int32_t *event_wires, int32_t n_events,
+                            const int32_t *part_event, int32_t n_partitions,
+                            const double *grids_init, double *grids, const int32_t n[4],
+                            const comet_config *cfg, int32_t n_refine, double *rss,
+                            int64_t *best, double *best_seed, double *best_rss,
+                            uint8_t *hit_mask, int64_t mask_stride, int32_t *n_borderline,
+                            const int32_t *event_active, void *workspace,
+                            size_t workspace_bytes, void *stream)
+{
+    clear_error();
+    if (!event_active)
+        return fail(COMET_EINVAL, "comet_batch_scan_active: NULL event_active");
+    return batch_scan_impl(wire_ends, n_wires, wire_offsets, drift, n_hits, event_wires,
+                           n_events, part_event, n_partitions, grids_init, grids, n, cfg,
+                           nullptr, n_refine, rss, best, best_seed, best_rss, hit_mask,
+                           mask_stride, n_borderline, 0, workspace, workspace_bytes, stream,
+                           event_active);
 }
 
 int comet_batch_scan_field(const double *wire_ends, int32_t n_wires,

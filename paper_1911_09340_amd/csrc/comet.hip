@@ -137,18 +137,49 @@ __global__ __launch_bounds__(256) void chunk_radius_kernel(const double *__restr
 }
 
 // ------------------------------------------------------------------ wire frames
-// frames[w] for w < n_w; zero frames pad the array to n_pad entries.
+// frames[w] for w < n_w; zero frames pad the array to n_pad entries. key[w]: the
+// azimuth of the wire's midpoint (+inf for the padding), the order in which the wide
+// DCA form deals wires to waves.
 __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad,
-                             double *__restrict__ frames)
+                             double *__restrict__ frames, float *__restrict__ key)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= n_pad)
         return;
     double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (w < n_w)
-        wire_frame(ends + 6 * (int64_t)w, f);
+    float k = INFINITY;
+    if (w < n_w) {
+        const double *e = ends + 6 * (int64_t)w;
+        wire_frame(e, f);
+        k = atan2f((float)(e[1] + e[4]), (float)(e[0] + e[3]));
+        if (k != k)
+            k = 4.0f;  // a NaN endpoint: after every finite azimuth, before the padding
+    }
     for (int j = 0; j < 8; ++j)
         frames[8 * (int64_t)w + j] = f[j];
+    key[w] = k;
+}
+
+// The wide form's wire order: slot r of frames_sorted / wire_of holds the wire of rank r
+// in (key, index) order. Wires near each other in azimuth share a wave, so the wave's
+// wires need nearly the same track chunks. The order changes which wave evaluates a
+// wire, never a result.
+__global__ void wire_order_kernel(const double *__restrict__ frames, const float *__restrict__ key,
+                                  int n_pad, double *__restrict__ frames_sorted,
+                                  int32_t *__restrict__ wire_of)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad)
+        return;
+    const float ki = key[i];
+    int rank = 0;
+    for (int j = 0; j < n_pad; ++j) {
+        const float kj = key[j];
+        rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    for (int j = 0; j < 8; ++j)
+        frames_sorted[8 * (int64_t)rank + j] = frames[8 * (int64_t)i + j];
+    wire_of[rank] = i;
 }
 
 // ------------------------------------------------------------------ DCA / Eq. 1
@@ -215,6 +246,51 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) v
         for (int w = 0; w < W; ++w)
             if (w < nw)
                 dsq[(int64_t)(wbase + w) * S + s0 + lane] = d2[w];
+}
+
+// The wide form (TileScanWide): a block is a 64-seed tile x NWV waves of W wires in
+// azimuth order; the block's frames are copied to LDS once. WPE: waves per SIMD the
+// registers are sized for.
+template <int W, int NWV, int SUP, int WPE>
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void dca_wide_kernel(
+    const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames_sorted,
+    const int32_t *__restrict__ wire_of, int n_w, const int32_t *__restrict__ offsets,
+    const double *__restrict__ drift, double lambda, const double *__restrict__ rho,
+    double *__restrict__ dsq, int n_groups, int n_blocks, int xcd_remap,
+    unsigned long long *counter)
+{
+    __shared__ __align__(16) double fl[NWV * W * 8];
+    const int b = blockIdx.x;
+    const int q8 = n_blocks >> 3, r8 = n_blocks & 7;
+    const int xcd = b & 7;
+    const int L = xcd_remap ? xcd * q8 + min(xcd, r8) + (b >> 3) : b;
+    const int tile = __builtin_amdgcn_readfirstlane(L / n_groups);
+    const int group = L - tile * n_groups;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t s0 = (int64_t)tile * 64;
+    const int n_valid = (int)min((int64_t)64, S - s0);
+    const int gbase = group * (W * NWV);
+    const int wbase = gbase + wave * W;
+    const int nw = max(0, min(W, n_w - wbase));  // wave-uniform
+    for (int i = threadIdx.x; i < NWV * W * 8; i += 64 * NWV)
+        fl[i] = frames_sorted[8 * (int64_t)gbase + i];
+    __syncthreads();
+    const int64_t PS = (int64_t)P * S;
+    double d2[W];
+    if ((int64_t)P * S < ((int64_t)1 << 29) - 64)
+        TileScanWide<W, SUP, true>::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P,
+                                        n_valid, fl + wave * W * 8, nw, wire_of + wbase, offsets,
+                                        drift, lambda, rho + s0, S, counter, d2);
+    else
+        TileScanWide<W, SUP, false>::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P,
+                                         n_valid, fl + wave * W * 8, nw, wire_of + wbase, offsets,
+                                         drift, lambda, rho + s0, S, counter, d2);
+    if (lane < n_valid)
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            if (w < nw)
+                dsq[(int64_t)wire_of[wbase + w] * S + s0 + lane] = d2[w];
 }
 
 // Eq. 1's sum over wires in wire order: rss = ((0 + d_0^2) + d_1^2) + ...
@@ -369,6 +445,11 @@ struct DcaVariant {
     void (*kernel)(const double *, int64_t, int, const double *, int, const int32_t *,
                    const double *, double, const double *, double *, int, int, int,
                    unsigned long long *);
+    // the wide form (direct == 2): frames in azimuth order and each slot's wire
+    void (*wide)(const double *, int64_t, int, const double *, const int32_t *, int,
+                 const int32_t *, const double *, double, const double *, double *, int, int,
+                 int, unsigned long long *) = nullptr;
+    int wpe = 4;
 };
 
 const DcaVariant kDcaVariants[] = {
@@ -396,6 +477,13 @@ const DcaVariant kDcaVariants[] = {
     {3, 4, 16, 1, 1, 1, 4, dca_kernel<3, 4, 16, true, true, 4>},
     {4, 8, 16, 1, 1, 1, 4, dca_kernel<4, 8, 16, true, true, 4>},
     {4, 4, 16, 1, 1, 1, 2, dca_kernel<4, 4, 16, true, true, 2>},
+    // wide: up to 16 wires per wave in azimuth order, frames in LDS, per-wire skips
+    {16, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 1, 4, 2>, 2},
+    {16, 2, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 2, 4, 2>, 2},
+    {16, 1, 16, 1, 1, 2, 1, nullptr, dca_wide_kernel<16, 1, 1, 2>, 2},
+    {8, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<8, 1, 4, 2>, 2},
+    {16, 4, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 4, 4, 2>, 2},
+    {12, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<12, 1, 4, 2>, 2},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
 constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above
@@ -419,6 +507,12 @@ int g_dca_variant = -1;  // explicit override; -1 = tuned or default
 int wire_pad(int n_w)
 {
     return ((n_w + 63) / 64) * 64 + kMaxWiresPerGroup;
+}
+
+size_t frames_region_bytes(int n_w)
+{
+    const size_t pad = (size_t)wire_pad(n_w);
+    return 2 * align256(sizeof(double) * 8 * pad) + 2 * align256(sizeof(int32_t) * pad);
 }
 
 }  // namespace
@@ -516,7 +610,7 @@ size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_points, int32_t n_wi
 {
     if (n_seeds < 1 || n_points < 1 || n_wires < 0)
         return 0;
-    return align256(sizeof(double) * 8 * (size_t)wire_pad(n_wires)) +
+    return frames_region_bytes(n_wires) +
            align256(sizeof(double) * (size_t)n_wires * (size_t)n_seeds) +
            align256(sizeof(double) * (size_t)cdev::radius_chunks(n_points) * (size_t)n_seeds);
 }
@@ -557,11 +651,31 @@ int check_dca_args(const char *who, const double *track_xyz, int64_t n_seeds, in
     return COMET_OK;
 }
 
+// The workspace: frames in wire order, frames in azimuth order, each azimuth slot's
+// wire, the azimuth keys (together frames_region_bytes), then dsq[n_w][S], then the
+// chunk radii [radius_chunks(P)][S].
 double *dca_frames(void *workspace) { return (double *)workspace; }
+
+double *dca_frames_sorted(void *workspace, int n_wires)
+{
+    return (double *)((char *)workspace + align256(sizeof(double) * 8 * (size_t)wire_pad(n_wires)));
+}
+
+int32_t *dca_wire_of(void *workspace, int n_wires)
+{
+    return (int32_t *)((char *)workspace +
+                       2 * align256(sizeof(double) * 8 * (size_t)wire_pad(n_wires)));
+}
+
+float *dca_keys(void *workspace, int n_wires)
+{
+    return (float *)((char *)dca_wire_of(workspace, n_wires) +
+                     align256(sizeof(int32_t) * (size_t)wire_pad(n_wires)));
+}
 
 double *dca_dsq(void *workspace, int n_wires)
 {
-    return (double *)((char *)workspace + align256(sizeof(double) * 8 * (size_t)wire_pad(n_wires)));
+    return (double *)((char *)workspace + frames_region_bytes(n_wires));
 }
 
 double *dca_rho(void *workspace, int n_wires, int64_t n_seeds)
@@ -585,8 +699,15 @@ int launch_frames(const double *wire_ends, int n_wires, void *workspace, hipStre
 {
     const int pad = wire_pad(n_wires);
     hipLaunchKernelGGL(frame_kernel, dim3((pad + 63) / 64), dim3(64), 0, hs, wire_ends, n_wires,
-                       pad, dca_frames(workspace));
-    return launched("frame_kernel");
+                       pad, dca_frames(workspace), dca_keys(workspace, n_wires));
+    int st = launched("frame_kernel");
+    if (st)
+        return st;
+    hipLaunchKernelGGL(wire_order_kernel, dim3((pad + 255) / 256), dim3(256), 0, hs,
+                       (const double *)dca_frames(workspace),
+                       (const float *)dca_keys(workspace, n_wires), pad,
+                       dca_frames_sorted(workspace, n_wires), dca_wire_of(workspace, n_wires));
+    return launched("wire_order_kernel");
 }
 
 int launch_dca(int id, const double *track_xyz, int64_t n_seeds, int32_t n_points, int n_wires,
@@ -598,6 +719,15 @@ int launch_dca(int id, const double *track_xyz, int64_t n_seeds, int32_t n_point
     const int n_groups = (n_wires + per_group - 1) / per_group;
     const int64_t n_tiles = (n_seeds + 63) / 64;
     const int64_t n_blocks = n_tiles * n_groups;
+    if (v.wide) {
+        hipLaunchKernelGGL(v.wide, dim3((unsigned)n_blocks), dim3(64 * v.nwv), 0, hs, track_xyz,
+                           n_seeds, n_points, (const double *)dca_frames_sorted(workspace, n_wires),
+                           (const int32_t *)dca_wire_of(workspace, n_wires), n_wires, wire_offsets,
+                           drift, lambda, (const double *)dca_rho(workspace, n_wires, n_seeds),
+                           dca_dsq(workspace, n_wires), n_groups, (int)n_blocks, v.xcd_remap,
+                           scan_counter());
+        return launched("dca_wide_kernel");
+    }
     hipLaunchKernelGGL(v.kernel, dim3((unsigned)n_blocks), dim3(64 * v.nwv), 0, hs, track_xyz,
                        n_seeds, n_points, (const double *)dca_frames(workspace), n_wires,
                        wire_offsets, drift, lambda,
@@ -658,33 +788,22 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
     return launched("rss_sum_kernel");
 }
 
-int comet_track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
-                        const comet_field *field, const double *wire_ends, int32_t n_wires,
-                        const int32_t *wire_offsets, const double *drift, int32_t n_hits,
-                        double *track_xyz, double *rss, void *workspace, size_t workspace_bytes,
-                        void *stream)
+}  // extern "C"
+
+namespace {
+
+// The body of comet_track_dca_rss (arguments checked).
+int track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                  const comet_field *field, const double *wire_ends, int32_t n_wires,
+                  const int32_t *wire_offsets, const double *drift, double *track_xyz,
+                  double *rss, void *workspace, void *stream, bool timed)
 {
-    clear_error();
-    if (!seeds6)
-        return fail(COMET_EINVAL, "comet_track_dca_rss: NULL seeds");
-    int st = check_dca_args("comet_track_dca_rss", track_xyz, n_seeds, cfg ? cfg->n_steps + 1 : 0,
-                            wire_ends, n_wires, wire_offsets, drift, n_hits, cfg, rss, workspace,
-                            workspace_bytes);
-    if (st)
-        return st;
-    if (field) {
-        st = check_field("comet_track_dca_rss", field);
-        if (st)
-            return st;
-    }
-    st = check_device();
-    if (st)
-        return st;
+    int st = COMET_OK;
     hipStream_t hs = (hipStream_t)stream;
     const int P = cfg->n_steps + 1;
     double *rho = n_wires > 0 ? dca_rho(workspace, n_wires, n_seeds) : nullptr;
     {
-        ProfScope prof(kProfTrack, hs);
+        ProfScope prof(kProfTrack, hs, timed);
         if (field) {
             st = launch_field_record(seeds6, n_seeds, field, cfg->charge_e, cfg->step_mm,
                                      cfg->n_steps, track_xyz, rho, hs);
@@ -708,16 +827,57 @@ int comet_track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_confi
     if (st)
         return st;
     {
-        ProfScope prof(kProfDca, hs);
+        ProfScope prof(kProfDca, hs, timed);
         st = launch_dca(choose_variant(n_seeds, P, n_wires), track_xyz, n_seeds, P, n_wires,
                         wire_offsets, drift, cfg->lambda_mm, workspace, hs);
     }
     if (st)
         return st;
-    ProfScope prof(kProfSum, hs);
+    ProfScope prof(kProfSum, hs, timed);
     hipLaunchKernelGGL(rss_sum_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256), 0, hs,
                        (const double *)dca_dsq(workspace, n_wires), n_wires, n_seeds, rss);
     return launched("rss_sum_kernel");
+}
+
+int check_track_dca_args(const char *who, const double *seeds6, int64_t n_seeds,
+                         const comet_config *cfg, const comet_field *field,
+                         const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,
+                         const double *drift, int32_t n_hits, double *track_xyz, double *rss,
+                         void *workspace, size_t workspace_bytes)
+{
+    if (!seeds6)
+        return fail(COMET_EINVAL, "%s: NULL seeds", who);
+    int st = check_dca_args(who, track_xyz, n_seeds, cfg ? cfg->n_steps + 1 : 0, wire_ends,
+                            n_wires, wire_offsets, drift, n_hits, cfg, rss, workspace,
+                            workspace_bytes);
+    if (st)
+        return st;
+    if (field) {
+        st = check_field(who, field);
+        if (st)
+            return st;
+    }
+    return check_device();
+}
+
+}  // namespace
+
+extern "C" {
+
+int comet_track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                        const comet_field *field, const double *wire_ends, int32_t n_wires,
+                        const int32_t *wire_offsets, const double *drift, int32_t n_hits,
+                        double *track_xyz, double *rss, void *workspace, size_t workspace_bytes,
+                        void *stream)
+{
+    clear_error();
+    const int st = check_track_dca_args("comet_track_dca_rss", seeds6, n_seeds, cfg, field,
+                                        wire_ends, n_wires, wire_offsets, drift, n_hits, track_xyz,
+                                        rss, workspace, workspace_bytes);
+    if (st)
+        return st;
+    return track_dca_rss(seeds6, n_seeds, cfg, field, wire_ends, n_wires, wire_offsets, drift,
+                         track_xyz, rss, workspace, stream, true);
 }
 
 int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_points,

@@ -612,6 +612,272 @@ struct TileScanDirect {
     }
 };
 
+// The wide form: one wave scans up to 16 wires, so that every chunk it reads serves
+// many wires. The wires come in an order that keeps each wave's wires close in space
+// (by azimuth), so they need nearly the same chunks. The frames sit in LDS (the
+// block's wires, loaded once) and are read at each use, which leaves the vector
+// registers to the chunk's points and the per-wire minima. Within a chunk that some
+// wire needs, each wire is scanned only when some lane needs it for that wire (the
+// same bound per wire), and its minimum is tracked per half chunk (the first index is
+// recovered in the half that first reaches the final minimum, as in scan_finish). The
+// next chunk's first point is loaded while the current chunk is scanned.
+template <int W, int SUP, bool BUF>
+struct TileScanWide {
+    static constexpr int C = kRadiusChunk;  // one radius window per chunk
+    static constexpr int H = C / 2;         // the minimum is tracked per half chunk
+
+    __device__ __forceinline__ static void frame(const double *fl, int w, double (&f)[8])
+    {
+        const double2 *p = reinterpret_cast<const double2 *>(fl + 8 * w);
+        const double2 a = p[0], b = p[1], c = p[2], d = p[3];
+        f[0] = a.x;
+        f[1] = a.y;
+        f[2] = b.x;
+        f[3] = b.y;
+        f[4] = c.x;
+        f[5] = c.y;
+        f[6] = d.x;
+        f[7] = d.y;
+    }
+    __device__ __forceinline__ static double qf(const double (&f)[8], double x, double y, double z)
+    {
+        double xi, eta;
+        project(f, x, y, z, xi, eta);
+        return fma(xi, xi, eta * eta);
+    }
+    // the bound test of one (lane, wire): can a point within r of the tested point reach
+    // or tie the wire's final minimum (bounded by sub)? Margins as in TileScanDirect.
+    __device__ __forceinline__ static bool needs(double q0, float rf, float sub)
+    {
+        const float B = fmaf(rf + sub, 1.000001f, 1e-6f);
+        return !((float)q0 * 0.999999f > (B * B) * 1.000001f);
+    }
+
+    // bx, by, bz: the tile's track (point k of lane l at b[k * ld + l]); fl: this wave's
+    // W frames in LDS ([W][8], slots >= nw hold anything finite); wire_of: the wave's
+    // slots' wire indices (CSR rows of offsets/drift); rho: the tile's chunk radii.
+    // Returns d^2 of (lane, slot w) in dsq[w] for lanes < n_valid and w < nw.
+    __device__ __forceinline__ static void run(
+        const double *__restrict__ bx, const double *__restrict__ by,
+        const double *__restrict__ bz, int64_t ld, int P, int n_valid, const double *fl, int nw,
+        const int32_t *__restrict__ wire_of, const int32_t *__restrict__ offsets,
+        const double *__restrict__ drift, double lambda, const double *__restrict__ rho,
+        int64_t ldr, unsigned long long *counter, double (&dsq)[W])
+    {
+        const int lane = threadIdx.x & 63;
+        const bool seed = lane < n_valid;
+        const int64_t col = seed ? lane : 0;  // lanes without a seed read lane 0's column
+        double best[W];
+        float sub[W];
+        int kbest[W];
+        int64_t evals = 0;  // wave-uniform, per seed lane
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            best[w] = INFINITY;
+            kbest[w] = 0;
+            sub[w] = INFINITY;
+        }
+        const uint32_t voff = (uint32_t)col * 8u;
+        auto rsrc = [](const double *p) {
+            const uint64_t a = (uint64_t)p;
+            const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(a >> 32))
+                                << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+            return __builtin_amdgcn_make_buffer_rsrc((void *)u, 0, -1, 0x00020000);
+        };
+        auto load = [&](int k, double &x, double &y, double &z) {
+            if constexpr (BUF) {
+                const uint32_t soff = (uint32_t)k * (uint32_t)ld * 8u;  // wave-uniform
+                x = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(bx), voff, soff, 0));
+                y = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(by), voff, soff, 0));
+                z = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(bz), voff, soff, 0));
+            } else {
+                const int64_t o = (int64_t)k * ld + col;
+                x = bx[o];
+                y = by[o];
+                z = bz[o];
+            }
+        };
+        if (nw > 0) {
+            // (A) upper bounds of the final minima: every other chunk's first point, eight
+            // points per pass, each frame read once per pass
+            float ub[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                ub[w] = INFINITY;
+            int n_s = 0;
+            for (int k0 = 0; k0 < P; k0 += 8 * 2 * C) {
+                double x[8], y[8], z[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    x[i] = y[i] = z[i] = 0.0;
+                    if (k0 + i * 2 * C < P)
+                        load(k0 + i * 2 * C, x[i], y[i], z[i]);
+                }
+                n_s += min(8, (P - 1 - k0) / (2 * C) + 1);
+                __asm__ volatile("" ::: "memory");
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    double f[8];
+                    frame(fl, w, f);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (k0 + i * 2 * C < P)
+                            ub[w] = fminf(ub[w], (float)qf(f, x[i], y[i], z[i]));
+                }
+            }
+            evals += (int64_t)nw * n_s;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
+
+            const int nch = (P + C - 1) / C;
+            double cx, cy, cz;  // the first point of chunk n
+            load(0, cx, cy, cz);
+            for (int n = 0; n < nch;) {
+                __asm__ volatile("" ::: "memory");  // frames are re-read from LDS below
+                const int k0 = n * C;
+                if (SUP > 1 && n % SUP == 0 && k0 + SUP * C <= P) {
+                    // a run of SUP chunks: one test with the sum of its windows' radii
+                    double r = 0.0;
+#pragma unroll
+                    for (int i = 0; i < SUP; ++i)
+                        r = r + rho[(int64_t)(n + i) * ldr + col];
+                    const float rf = (float)r * 1.000001f;
+                    bool lane_need = false;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        double f[8];
+                        frame(fl, w, f);
+                        lane_need = lane_need || (w < nw && needs(qf(f, cx, cy, cz), rf, sub[w]));
+                    }
+                    evals += nw;
+                    if (__builtin_amdgcn_ballot_w64(lane_need && seed) == 0) {
+                        n += SUP;
+                        if (n < nch)
+                            load(n * C, cx, cy, cz);
+                        continue;
+                    }
+                }
+                const int kn = min(C, P - k0);
+                double nx = 0.0, ny = 0.0, nz = 0.0;
+                if (n + 1 < nch)
+                    load(k0 + C, nx, ny, nz);
+                if (kn == C) {
+                    const float rf = (float)rho[(int64_t)n * ldr + col] * 1.000001f;
+                    uint32_t needm = 0;  // wave-uniform: the wires some lane needs here
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        double f[8];
+                        frame(fl, w, f);
+                        const bool ln = w < nw && needs(qf(f, cx, cy, cz), rf, sub[w]);
+                        if (__builtin_amdgcn_ballot_w64(ln && seed) != 0)
+                            needm |= 1u << w;
+                    }
+                    evals += nw;
+                    if (needm != 0) {
+                        double x[C - 1], y[C - 1], z[C - 1];
+#pragma unroll
+                        for (int i = 1; i < C; ++i)
+                            load(k0 + i, x[i - 1], y[i - 1], z[i - 1]);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            if ((needm >> w) & 1u) {
+                                double f[8];
+                                frame(fl, w, f);
+                                double m = qf(f, cx, cy, cz);
+#pragma unroll
+                                for (int i = 1; i < H; ++i)
+                                    m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
+                                if (m < best[w]) {
+                                    best[w] = m;
+                                    kbest[w] = k0;
+                                }
+                                m = qf(f, x[H - 1], y[H - 1], z[H - 1]);
+#pragma unroll
+                                for (int i = H + 1; i < C; ++i)
+                                    m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
+                                if (m < best[w]) {
+                                    best[w] = m;
+                                    kbest[w] = k0 + H;
+                                }
+                                // the running minimum bounds the final one as well
+                                sub[w] = fminf(sub[w],
+                                               __builtin_amdgcn_sqrtf((float)best[w]) * 1.000001f);
+                                evals += C - 1;
+                            }
+                        }
+                    }
+                } else {
+                    // the partial last chunk: every wire, every point
+                    double x[C - 1], y[C - 1], z[C - 1];
+#pragma unroll
+                    for (int i = 1; i < C; ++i) {
+                        x[i - 1] = y[i - 1] = z[i - 1] = 0.0;
+                        if (i < kn)
+                            load(k0 + i, x[i - 1], y[i - 1], z[i - 1]);
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        if (w < nw) {
+                            double f[8];
+                            frame(fl, w, f);
+                            double m = qf(f, cx, cy, cz);
+#pragma unroll
+                            for (int i = 1; i < C; ++i)
+                                if (i < kn)
+                                    m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
+                            if (m < best[w]) {
+                                best[w] = m;
+                                kbest[w] = k0;
+                            }
+                        }
+                    }
+                    evals += (int64_t)nw * kn;
+                }
+                cx = nx;
+                cy = ny;
+                cz = nz;
+                ++n;
+            }
+        }
+        // the end: evaluation count, then per (lane, wire) the first index of the
+        // minimum (rescan of the half chunk that holds it), its chord refinement, D and
+        // Eq. 1's capped residual
+        if (counter && lane == 0 && evals > 0)
+            atomicAdd(counter, (unsigned long long)(evals * n_valid));
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            dsq[w] = 0.0;
+        if (nw <= 0 || !seed)
+            return;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (w < nw) {
+                double f[8];
+                frame(fl, w, f);
+                int k = kbest[w];
+                const int kend = min(k + C, P);
+                for (int j = k; j < kend; ++j) {
+                    const int64_t o = (int64_t)j * ld + lane;
+                    if (qf(f, bx[o], by[o], bz[o]) == best[w]) {
+                        k = j;
+                        break;
+                    }
+                }
+                const double d2 = refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f, k, best[w]);
+                const double D = sqrt(d2);
+                const int wi = wire_of[w];
+                const double d = capped_residual(D, drift, offsets[wi], offsets[wi + 1], lambda);
+                dsq[w] = d * d;
+            }
+        }
+    }
+};
+
 }  // namespace cdev
 
 #endif  // COMET_DCA_SCAN_H

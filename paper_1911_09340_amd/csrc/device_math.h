@@ -162,6 +162,26 @@ __device__ __forceinline__ int64_t block_argmin_n(const double *__restrict__ rss
     return a.i;
 }
 
+// The same selection by one wave on its own (no LDS, no barrier): every lane of the
+// wave returns the result.
+__device__ __forceinline__ int64_t wave_argmin(const double *__restrict__ rss, int64_t S)
+{
+    MinLoc m{INFINITY, -1};
+    for (int64_t s = threadIdx.x & 63; s < S; s += 64) {
+        const double v = rss[s];
+        if (v < m.v || (m.i < 0 && v == m.v)) {
+            m.v = v;
+            m.i = s;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        MinLoc o{__shfl_xor(m.v, off), __shfl_xor(m.i, off)};
+        if (beats(o, m))
+            m = o;
+    }
+    return m.i;
+}
+
 __device__ __forceinline__ int64_t block_argmin(const double *__restrict__ rss, int64_t S)
 {
     return block_argmin_n<kSelectThreads>(rss, S);

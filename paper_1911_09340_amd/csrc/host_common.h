@@ -41,10 +41,10 @@ enum { kProfTrack = 0, kProfDca = 1, kProfSum = 2, kProfSelect = 3 };
 unsigned long long *scan_counter();
 
 // Brackets the launches made during its lifetime with two HIP events on `stream`
-// when profiling is on (comet_profile_begin); does nothing otherwise.
+// when profiling is on (comet_profile_begin) and `enabled`; does nothing otherwise.
 class ProfScope {
   public:
-    ProfScope(int kind, hipStream_t stream);
+    ProfScope(int kind, hipStream_t stream, bool enabled = true);
     ~ProfScope();
     ProfScope(const ProfScope &) = delete;
     ProfScope &operator=(const ProfScope &) = delete;

@@ -135,8 +135,10 @@ int check_config(const comet_config *cfg)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-ProfScope::ProfScope(int kind, hipStream_t stream) : stream_(stream), kind_(kind)
+ProfScope::ProfScope(int kind, hipStream_t stream, bool enabled) : stream_(stream), kind_(kind)
 {
+    if (!enabled)
+        return;
     std::lock_guard<std::mutex> lock(g_prof_mu);
     if (!g_prof_on)
         return;

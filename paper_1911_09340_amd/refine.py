@@ -2,10 +2,12 @@
 
 For every turn partition of a set of events:
   coarse + LM: one batched scan of a coarse seed grid for all partitions
-               (comet_batch_scan), the k lowest-RSS seeds of each (comet_topk: the
-               paper's several reference seeds, Sec. 2.1), one batched Levenberg-
-               Marquardt refinement of all of them driven by the hand-written adjoint
-               (comet_lm_refine), and per partition the refined seed with the lowest RSS;
+               (comet_batch_scan), k starting seeds of each: the paper's several
+               reference seeds (Sec. 2.1), i.e. the lowest-RSS seeds whose finer seed
+               sets do not overlap (comet_sparse_select; or the k lowest, comet_topk),
+               one batched Levenberg-Marquardt refinement of all of them driven by the
+               hand-written adjoint (comet_lm_refine), and per partition the refined
+               seed with the lowest RSS;
   fine grid:   one batched scan of a fine grid over the same ranges; its argmin.
 Both report |p| of the final seed against the true |p| at the seed point, and their
 device time. Every step runs in the library's kernels; this module orders launches.
@@ -22,13 +24,19 @@ from . import comet, scan, synth
 
 
 def coarse_then_lm(events, sc: synth.ScanConfig, top_k: int = 8, n_iter: int = 8,
-                   mu0: float = 1e-3, device="cuda"):
+                   mu0: float = 1e-3, device="cuda", starts: str = "topk"):
+    """starts: "sparse" (several non-overlapping references) or "topk" (the k lowest)."""
     runner = scan.BatchRunner(events, replace(sc, n_refine=0), device)
     runner.run()
     NP = runner.n_part
-    k = min(top_k, sc.n_seeds)
+    k = min(top_k, sc.n_seeds, 64 if starts == "sparse" else sc.n_seeds)
     idx = torch.empty(NP, k, dtype=torch.int64, device=device)
-    comet.topk(runner.rss, k, idx)
+    if starts == "sparse":
+        new_grids = torch.empty(NP, k, 14, dtype=torch.float64, device=device)
+        comet.sparse_select(runner.grids.view(NP, 1, 14), runner.rss.view(NP, 1, -1), sc.n, k,
+                            idx, new_grids)
+    else:
+        comet.topk(runner.rss, k, idx)
     seeds = torch.empty(6, NP * k, dtype=torch.float64, device=device)
     comet.grid_seeds(runner.grids, sc.n, idx, seeds)
     coarse_best = seeds.view(6, NP, k)[:, :, 0].clone()
@@ -70,11 +78,11 @@ def summary(res: np.ndarray) -> dict:
 
 
 def compare(events, coarse: synth.ScanConfig, fine: synth.ScanConfig, top_k: int = 8,
-            n_iter: int = 8, mu0: float = 1e-3, device="cuda") -> dict:
+            n_iter: int = 8, mu0: float = 1e-3, device="cuda", starts: str = "topk") -> dict:
     """Both strategies on the same events (each timed with device synchronisation)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lm = coarse_then_lm(events, coarse, top_k, n_iter, mu0, device)
+    lm = coarse_then_lm(events, coarse, top_k, n_iter, mu0, device, starts=starts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     fg = fine_grid(events, fine, device)
@@ -87,7 +95,8 @@ def compare(events, coarse: synth.ScanConfig, fine: synth.ScanConfig, top_k: int
         "partitions": lm["partitions"],
         "coarse_lm": {"seconds": t1 - t0, **summary(momentum_residuals(lm["refined"], events)),
                       "mean_accepted_steps": float(lm["accepted"].float().mean().item()),
-                      "starts_per_partition": top_k, "lm_iterations": n_iter},
+                      "starts_per_partition": top_k, "starts": starts,
+                      "lm_iterations": n_iter},
         "coarse_only": summary(momentum_residuals(lm["coarse"], events)),
         "fine_grid": {"seconds": t2 - t1, **summary(momentum_residuals(fg["best"], events))},
         "rss_lm_below_fine": float(np.mean(lm_rss <= fg_rss)),

@@ -6,7 +6,8 @@ true state at the seed radius (the stand-in for the paper's Hough-transform seed
 longitudinal seed (z, p_z) is the true one at stage 0 (the stand-in for the hodoscope
 prior of the last turn) and, later, the previous stage's chosen seed extrapolated
 backwards by one turn (comet_backward_seeds). Per stage, on the device:
-  comet_stage_grids -> comet_batch_scan (scan, re-scans, classification)
+  comet_stage_grids -> comet_batch_scan_active (scan, re-scans, classification of the
+     events still active; the others are skipped)
   [-> with fit_iters > 0: comet_lm_refine from the chosen seed (the fitted track) and
      comet_self_refine (classified hits re-tested with lambda at the fitted track, wires
      left without one re-admit their closest hit below eta)]
@@ -110,7 +111,8 @@ class StageRunner:
             comet.batch_scan(src, self.part_event, self.grids, self.sc.n, self.cfg,
                              self.sc.n_refine, self.rss, self.best[s], self.workspace,
                              best_seed=self.seeds[s], best_rss=self.best_rss[s],
-                             hit_mask=self.mask, n_borderline=self.n_border)
+                             hit_mask=self.mask, n_borderline=self.n_border,
+                             event_active=self.active)
             if self.fit_iters > 0:
                 self.fit_soa.copy_(self.seeds[s].t())
                 comet.lm_refine(self.fit_soa, self.cfg, src.wire_ends, src.wire_offsets,

@@ -197,6 +197,10 @@ def test_batch_topk_and_seed_rejects(lib):
     bad = list(args)
     bad[0] = None
     assert lib.comet_batch_scan(*bad, _p(0x100000), ws, None) == comet.EINVAL
+    # the active-events form: event_active in place of max_items, and required
+    act = args[:21]
+    assert lib.comet_batch_scan_active(*act, None, _p(0x100000), ws, None) == comet.EINVAL
+    assert lib.comet_batch_scan_active(*act, _p(), _p(0x100000), 16, None) == comet.EWORKSPACE
 
 
 def test_sparse_select_and_classify_reject(lib):

@@ -215,11 +215,13 @@ def test_grid_seeds_match_cpu_reference(orc, events):
         assert np.all(np.isnan(got[:, p * 4 + 3]))
 
 
-def test_multistart_refinement_matches_cpu_lm(orc, events):
-    """coarse_then_lm: every start's LM result equals the CPU LM from the same start."""
+@pytest.mark.parametrize("starts", ["sparse", "topk"])
+def test_multistart_refinement_matches_cpu_lm(orc, events, starts):
+    """coarse_then_lm: every start's LM result equals the CPU LM from the same start
+    (the sparse references of Sec. 2.1, or the k lowest-RSS seeds)."""
     sc = synth.ScanConfig("c", (4, 4, 4, 4), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)
     evs = events[:2]
-    out = refine.coarse_then_lm(evs, sc, top_k=3, n_iter=6)
+    out = refine.coarse_then_lm(evs, sc, top_k=3, n_iter=6, starts=starts)
     final = out["refined"].cpu().numpy()
     p = 0
     o = oracle.Oracle()
@@ -229,9 +231,13 @@ def test_multistart_refinement_matches_cpu_lm(orc, events):
             g = synth.grid_descriptor(ev.ref_states[t], sc)
             seeds = o.seed_grid(g, np.array(sc.n, np.int32))
             rss, _ = o.scan(seeds, cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
-            starts = o.topk(rss, 3)
+            if starts == "topk":
+                first = o.topk(rss, 3)
+            else:
+                first, _, _, taken = o.sparse_select(g, rss, np.array(sc.n, np.int32), 3)
+                assert taken == 3
             res = [o.lm_refine(seeds[:, i], cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets,
-                               ev.drift, 6, 1e-3) for i in starts]
+                               ev.drift, 6, 1e-3) for i in first]
             best = min(range(3), key=lambda r: (res[r][1], r))
             ws = res[best][0]
             assert np.max(np.abs(final[:, p] - ws) / np.maximum(np.abs(ws), 1.0)) < 1e-7, p

@@ -211,6 +211,9 @@ def test_stage_loop_matches_cpu(orc):
         for s, (b, seed, _) in enumerate(per_stage):
             assert best[s, e] == b, (e, s)
             assert np.array_equal(seeds[s, e], seed), (e, s)
+        # stages after the event stopped are not scanned at all
+        for s in range(len(per_stage), 5):
+            assert best[s, e] == -1 and np.all(np.isnan(seeds[s, e])), (e, s)
         n_stages += len(per_stage)
         h0 += ev.n_hits
     assert n_stages > len(events)                # the loop went past the first stage
