@@ -157,6 +157,25 @@ int comet_track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_confi
                         double *track_xyz, double *rss, void *workspace, size_t workspace_bytes,
                         void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): comet_track_dca_rss with the
+ * workspace taken from a fixed array in device memory instead of an argument.
+ * comet_static_scratch_bytes() is that array's size (64 MiB); each GPU the library
+ * runs on holds its own copy until the process ends, and its address on a device is
+ * looked up on the first call made with that device current. The call allocates and
+ * frees nothing and does not time its launches (comet_profile_begin does not see it).
+ * It returns COMET_EWORKSPACE, before any device work, when
+ * comet_dca_workspace_bytes(n_seeds, cfg->n_steps + 1, n_wires) exceeds the array (split
+ * the seeds into smaller calls). Every call on one GPU uses the same array, so calls
+ * that overlap on one GPU (different streams or threads) race and give wrong results;
+ * the array needs no clearing between calls (every byte a call reads it writes first).
+ * Arguments otherwise as comet_track_dca_rss. */
+size_t comet_static_scratch_bytes(void);
+int comet_track_dca_rss_static(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                               const comet_field *field, const double *wire_ends,
+                               int32_t n_wires, const int32_t *wire_offsets, const double *drift,
+                               int32_t n_hits, double *track_xyz, double *rss, void *stream);
+
 /* Seed selection and hit classification (Sec. 2.1).
  * best[0] = index of the lowest rss (ties: lowest index; NaN never chosen; -1 if
  * every value is NaN). When hit_mask is not NULL the chosen seed's track is read

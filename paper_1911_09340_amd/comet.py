@@ -246,6 +246,37 @@ def track_dca_rss(seeds: torch.Tensor, wire_ends: torch.Tensor, wire_offsets: to
         workspace.numel() * 8, _stream()), "comet_track_dca_rss")
 
 
+def static_scratch_bytes() -> int:
+    lib = load()
+    lib.comet_static_scratch_bytes.restype = ctypes.c_size_t
+    lib.comet_static_scratch_bytes.argtypes = []
+    return int(lib.comet_static_scratch_bytes())
+
+
+def track_dca_rss_static(seeds: torch.Tensor, wire_ends: torch.Tensor,
+                         wire_offsets: torch.Tensor, drift: torch.Tensor, cfg: Config,
+                         track: torch.Tensor, rss: torch.Tensor, field: FieldMap = None) -> None:
+    """comet_track_dca_rss_static: track_dca_rss with the library's fixed device workspace
+    (no workspace argument, nothing allocated)."""
+    lib = load()
+    lib.comet_track_dca_rss_static.argtypes = [_vp, _i64, ctypes.POINTER(Config),
+                                               ctypes.POINTER(Field), _vp, _i32, _vp, _vp, _i32,
+                                               _vp, _vp, _vp]
+    lib.comet_track_dca_rss_static.restype = ctypes.c_int
+    S = int(seeds.shape[1]) if seeds.dim() == 2 else -1
+    n_w, n_h = int(wire_ends.shape[0]), int(drift.shape[0])
+    if field is not None:
+        _ptr(field.b, torch.float64, "field.b")
+    _check(lib.comet_track_dca_rss_static(
+        _ptr(seeds, torch.float64, "seeds", (6, S)), S, ctypes.byref(cfg),
+        ctypes.byref(field.struct) if field is not None else None,
+        _ptr(wire_ends, torch.float64, "wire_ends", (n_w, 6)), n_w,
+        _ptr(wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(drift, torch.float64, "drift", (n_h,)), n_h,
+        _ptr(track, torch.float64, "track", (3, cfg.n_steps + 1, S)),
+        _ptr(rss, torch.float64, "rss", (S,)), _stream()), "comet_track_dca_rss_static")
+
+
 def select_classify(rss: torch.Tensor, best: torch.Tensor, cfg: Config, track=None,
                     wire_ends=None, wire_offsets=None, drift=None, hit_mask=None,
                     n_borderline=None, dca_best=None, top_k: int = 1) -> None:

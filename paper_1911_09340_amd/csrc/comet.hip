@@ -792,7 +792,7 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
 
 namespace {
 
-// The body of comet_track_dca_rss (arguments checked).
+// The body of comet_track_dca_rss and comet_track_dca_rss_static (arguments checked).
 int track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
                   const comet_field *field, const double *wire_ends, int32_t n_wires,
                   const int32_t *wire_offsets, const double *drift, double *track_xyz,
@@ -860,6 +860,35 @@ int check_track_dca_args(const char *who, const double *seeds6, int64_t n_seeds,
     return check_device();
 }
 
+// The workspace of comet_track_dca_rss_static: a fixed array in device memory, one
+// copy per GPU, for callers that cannot allocate. Its host-side name is not a device
+// address; each device's address comes from hipGetSymbolAddress on the first call
+// made with that device current.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+int static_scratch(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(COMET_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= 64)
+        return fail(COMET_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(COMET_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return COMET_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -878,6 +907,38 @@ int comet_track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_confi
         return st;
     return track_dca_rss(seeds6, n_seeds, cfg, field, wire_ends, n_wires, wire_offsets, drift,
                          track_xyz, rss, workspace, stream, true);
+}
+
+size_t comet_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int comet_track_dca_rss_static(const double *seeds6, int64_t n_seeds, const comet_config *cfg,
+                               const comet_field *field, const double *wire_ends,
+                               int32_t n_wires, const int32_t *wire_offsets, const double *drift,
+                               int32_t n_hits, double *track_xyz, double *rss, void *stream)
+{
+    clear_error();
+    const int P = cfg ? cfg->n_steps + 1 : 0;
+    if (n_seeds >= 1 && P >= 1 && n_wires >= 0 &&
+        comet_dca_workspace_bytes(n_seeds, P, n_wires) > kStaticScratchBytes)
+        return fail(COMET_EWORKSPACE,
+                    "comet_track_dca_rss_static: %lld seeds x %d points x %d wires need %zu bytes "
+                    "of workspace, more than the fixed %zu (split the seeds)",
+                    (long long)n_seeds, P, n_wires, comet_dca_workspace_bytes(n_seeds, P, n_wires),
+                    kStaticScratchBytes);
+    // the arguments first (the array's address stands in until it is known), then the
+    // array's address on the current device
+    int st = check_track_dca_args("comet_track_dca_rss_static", seeds6, n_seeds, cfg, field,
+                                  wire_ends, n_wires, wire_offsets, drift, n_hits, track_xyz, rss,
+                                  (void *)256, kStaticScratchBytes);
+    if (st)
+        return st;
+    void *ws = nullptr;
+    st = static_scratch(&ws);
+    if (st)
+        return st;
+    // no event timing here: the profiler's events are created on demand
+    return track_dca_rss(seeds6, n_seeds, cfg, field, wire_ends, n_wires, wire_offsets, drift,
+                         track_xyz, rss, ws, stream, false);
 }
 
 int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_points,

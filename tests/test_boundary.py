@@ -203,6 +203,30 @@ def test_batch_topk_and_seed_rejects(lib):
     assert lib.comet_batch_scan_active(*act, _p(), _p(0x100000), 16, None) == comet.EWORKSPACE
 
 
+def test_static_workspace_call_rejects(lib):
+    """The allocation-free entry point checks sizes against its fixed array before any
+    device work, and its arguments as the workspace form does."""
+    lib.comet_static_scratch_bytes.restype = ctypes.c_size_t
+    cap = lib.comet_static_scratch_bytes()
+    assert cap == 64 << 20
+    lib.comet_dca_workspace_bytes.restype = ctypes.c_size_t
+    lib.comet_dca_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+    assert lib.comet_dca_workspace_bytes(65536, 1501, 172) > cap
+    assert lib.comet_dca_workspace_bytes(8192, 1501, 172) <= cap
+    lib.comet_track_dca_rss_static.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.comet_track_dca_rss_static.restype = ctypes.c_int
+    cfg = comet.make_config(1.0, -1.0, 2.0, 1500, 0.8)
+    st = lib.comet_track_dca_rss_static(_p(), 65536, ctypes.byref(cfg), None, _p(), 172, _p(),
+                                        _p(), 200, _p(), _p(), None)
+    assert st == comet.EWORKSPACE and b"split the seeds" in lib.comet_last_error()
+    st = lib.comet_track_dca_rss_static(None, 64, ctypes.byref(cfg), None, _p(), 172, _p(),
+                                        _p(), 200, _p(), _p(), None)
+    assert st == comet.EINVAL
+
+
 def test_sparse_select_and_classify_reject(lib):
     comet._bind_batch(lib)
     n = _n4(2, 3, 1, 4)
