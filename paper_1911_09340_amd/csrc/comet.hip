@@ -251,7 +251,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) v
 // The wide form (TileScanWide): a block is a 64-seed tile x NWV waves of W wires in
 // azimuth order; the block's frames are copied to LDS once. WPE: waves per SIMD the
 // registers are sized for.
-template <int W, int NWV, int SUP, int WPE>
+template <int W, int NWV, int SUP, int WPE, int NB = 0>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void dca_wide_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames_sorted,
     const int32_t *__restrict__ wire_of, int n_w, const int32_t *__restrict__ offsets,
@@ -278,14 +278,19 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE)))
     __syncthreads();
     const int64_t PS = (int64_t)P * S;
     double d2[W];
+    // NB > 0: the latency-hiding form (batches of NB chunk tests, double-buffered halves)
+    using Near = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), true>,
+                                    TileScanWide<W, SUP, true>>;
+    using Far = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), false>,
+                                   TileScanWide<W, SUP, false>>;
     if ((int64_t)P * S < ((int64_t)1 << 29) - 64)
-        TileScanWide<W, SUP, true>::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P,
-                                        n_valid, fl + wave * W * 8, nw, wire_of + wbase, offsets,
-                                        drift, lambda, rho + s0, S, counter, d2);
+        Near::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid,
+                  fl + wave * W * 8, nw, wire_of + wbase, offsets, drift, lambda, rho + s0, S,
+                  counter, d2);
     else
-        TileScanWide<W, SUP, false>::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P,
-                                         n_valid, fl + wave * W * 8, nw, wire_of + wbase, offsets,
-                                         drift, lambda, rho + s0, S, counter, d2);
+        Far::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid,
+                 fl + wave * W * 8, nw, wire_of + wbase, offsets, drift, lambda, rho + s0, S,
+                 counter, d2);
     if (lane < n_valid)
 #pragma unroll
         for (int w = 0; w < W; ++w)
@@ -484,6 +489,14 @@ const DcaVariant kDcaVariants[] = {
     {8, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<8, 1, 4, 2>, 2},
     {16, 4, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 4, 4, 2>, 2},
     {12, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<12, 1, 4, 2>, 2},
+    // wide with the chunk tests in batches of 8 or 16 and double-buffered half chunks
+    // (runs reports the batch: its first point is tested with the batch's summed radii)
+    {8, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<8, 1, 0, 2, 8>, 2},
+    {8, 1, 16, 1, 1, 2, 16, nullptr, dca_wide_kernel<8, 1, 0, 2, 16>, 2},
+    {12, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<12, 1, 0, 2, 8>, 2},
+    {16, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<16, 1, 0, 2, 8>, 2},
+    {6, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<6, 1, 0, 3, 8>, 3},
+    {4, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<4, 1, 0, 3, 8>, 3},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
 constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above

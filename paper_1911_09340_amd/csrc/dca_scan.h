@@ -878,6 +878,289 @@ struct TileScanWide {
     }
 };
 
+// The wide form with its memory latency hidden. The chunks are taken NB at a time: the
+// first points of all NB come in one round of loads, and every (chunk, wire) of the
+// batch is tested against the bounds as they stand before the batch (a bound only
+// tightens, so an older one is still valid); a batch whose first point, with the sum
+// of its windows' radii, rules out every lane and wire is passed over. The chunks the
+// batch needs are then scanned in half chunks of H points with two register buffers:
+// the next half is loading while the current one is evaluated. Each wire of a chunk
+// is evaluated only where some lane needs it; its minimum is tracked per half chunk.
+template <int W, int NB, bool BUF>
+struct TileScanWideP {
+    using Base = TileScanWide<W, 1, BUF>;
+    static constexpr int C = kRadiusChunk;
+    static constexpr int H = C / 2;
+
+    __device__ __forceinline__ static void run(
+        const double *__restrict__ bx, const double *__restrict__ by,
+        const double *__restrict__ bz, int64_t ld, int P, int n_valid, const double *fl, int nw,
+        const int32_t *__restrict__ wire_of, const int32_t *__restrict__ offsets,
+        const double *__restrict__ drift, double lambda, const double *__restrict__ rho,
+        int64_t ldr, unsigned long long *counter, double (&dsq)[W])
+    {
+        const int lane = threadIdx.x & 63;
+        const bool seed = lane < n_valid;
+        const int64_t col = seed ? lane : 0;  // lanes without a seed read lane 0's column
+        double best[W];
+        float sub[W];
+        int kbest[W];
+        int64_t evals = 0;  // wave-uniform, per seed lane
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            best[w] = INFINITY;
+            kbest[w] = 0;
+            sub[w] = INFINITY;
+        }
+        const uint32_t voff = (uint32_t)col * 8u;
+        auto rsrc = [](const double *p) {
+            const uint64_t a = (uint64_t)p;
+            const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(a >> 32))
+                                << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+            return __builtin_amdgcn_make_buffer_rsrc((void *)u, 0, -1, 0x00020000);
+        };
+        auto load = [&](int k, double &x, double &y, double &z) {
+            if constexpr (BUF) {
+                const uint32_t soff = (uint32_t)k * (uint32_t)ld * 8u;  // wave-uniform
+                x = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(bx), voff, soff, 0));
+                y = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(by), voff, soff, 0));
+                z = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rsrc(bz), voff, soff, 0));
+            } else {
+                const int64_t o = (int64_t)k * ld + col;
+                x = bx[o];
+                y = by[o];
+                z = bz[o];
+            }
+        };
+        // points k0 .. k0 + H - 1 (those below P; 0 elsewhere)
+        auto load_half = [&](int k0, double (&x)[H], double (&y)[H], double (&z)[H]) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                x[i] = y[i] = z[i] = 0.0;
+                if (k0 + i < P)
+                    load(k0 + i, x[i], y[i], z[i]);
+            }
+        };
+        // the first n points (n wave-uniform, 1..H) of a half starting at k0, for the
+        // wires in mask: per wire the half's minimum, recorded when it beats the best
+        // The compiler fences keep each frame's LDS read next to its use (no frame is
+        // hoisted out of the loops), so at most two frames are live: the next wire's
+        // frame loads while the current one is evaluated.
+        auto eval_half = [&](int k0, int n, uint32_t mask, const double (&x)[H],
+                             const double (&y)[H], const double (&z)[H]) {
+            double f[8];
+            Base::frame(fl, 0, f);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                double fn[8];
+                __asm__ volatile("" ::: "memory");
+                if (w + 1 < W)
+                    Base::frame(fl, w + 1, fn);
+                if ((mask >> w) & 1u) {
+                    double m = Base::qf(f, x[0], y[0], z[0]);
+#pragma unroll
+                    for (int i = 1; i < H; ++i)
+                        if (i < n)  // wave-uniform; every point of a full half
+                            m = fmin(m, Base::qf(f, x[i], y[i], z[i]));
+                    if (m < best[w]) {
+                        best[w] = m;
+                        kbest[w] = k0;
+                    }
+                }
+                if (w + 1 < W)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        f[j] = fn[j];
+            }
+            evals += (int64_t)__builtin_popcount(mask) * n;
+        };
+        if (nw > 0) {
+            // (A) upper bounds of the final minima: every other chunk's first point,
+            // eight per round, the next round loading while this one is evaluated
+            float ub[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                ub[w] = INFINITY;
+            int n_s = 0;
+            {
+                double x[8], y[8], z[8];
+                auto load8 = [&](int k0, double (&px)[8], double (&py)[8], double (&pz)[8]) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        px[i] = py[i] = pz[i] = 0.0;
+                        if (k0 + i * 2 * C < P)
+                            load(k0 + i * 2 * C, px[i], py[i], pz[i]);
+                    }
+                };
+                load8(0, x, y, z);
+                for (int k0 = 0; k0 < P; k0 += 8 * 2 * C) {
+                    double nx[8], ny[8], nz[8];
+                    if (k0 + 8 * 2 * C < P)
+                        load8(k0 + 8 * 2 * C, nx, ny, nz);
+                    n_s += min(8, (P - 1 - k0) / (2 * C) + 1);
+                    __asm__ volatile("" ::: "memory");
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        double f[8];
+                        __asm__ volatile("" ::: "memory");
+                        Base::frame(fl, w, f);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (k0 + i * 2 * C < P)
+                                ub[w] = fminf(ub[w], (float)Base::qf(f, x[i], y[i], z[i]));
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        x[i] = nx[i];
+                        y[i] = ny[i];
+                        z[i] = nz[i];
+                    }
+                }
+            }
+            evals += (int64_t)nw * n_s;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
+            const uint32_t all = nw >= 32 ? 0xffffffffu : ((1u << nw) - 1u);
+
+            const int nch = (P + C - 1) / C;
+            for (int b0 = 0; b0 < nch; b0 += NB) {
+                __asm__ volatile("" ::: "memory");  // frames are re-read from LDS below
+                const int nb = min(NB, nch - b0);
+                uint32_t needm[NB];
+                {
+                    double px[NB], py[NB], pz[NB], r[NB];
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) {
+                        px[i] = py[i] = pz[i] = r[i] = 0.0;
+                        if (i < nb) {
+                            load((b0 + i) * C, px[i], py[i], pz[i]);
+                            if ((b0 + i) * C + C <= P)
+                                r[i] = rho[(int64_t)(b0 + i) * ldr + col];
+                        }
+                    }
+                    // the whole batch from its first point, with the sum of its windows'
+                    // radii (consecutive windows share their end points)
+                    bool any = true;
+                    if (nb == NB && (b0 + NB) * C <= P) {
+                        double rs = 0.0;
+#pragma unroll
+                        for (int i = 0; i < NB; ++i)
+                            rs = rs + r[i];
+                        const float rf = (float)rs * 1.000001f;
+                        bool lane_need = false;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            double f[8];
+                            Base::frame(fl, w, f);
+                            lane_need = lane_need ||
+                                        (w < nw && Base::needs(Base::qf(f, px[0], py[0], pz[0]),
+                                                               rf, sub[w]));
+                        }
+                        evals += nw;
+                        any = __builtin_amdgcn_ballot_w64(lane_need && seed) != 0;
+                    }
+#pragma unroll
+                    for (int i = 0; i < NB; ++i)
+                        needm[i] = 0;
+                    if (!any)
+                        continue;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        double f[8];
+                        __asm__ volatile("" ::: "memory");
+                        Base::frame(fl, w, f);
+#pragma unroll
+                        for (int i = 0; i < NB; ++i) {
+                            if (i < nb) {
+                                const float rf = (float)r[i] * 1.000001f;
+                                const bool ln = w < nw && Base::needs(
+                                                              Base::qf(f, px[i], py[i], pz[i]),
+                                                              rf, sub[w]);
+                                if (__builtin_amdgcn_ballot_w64(ln && seed) != 0)
+                                    needm[i] |= 1u << w;
+                            }
+                        }
+                    }
+                    evals += (int64_t)nw * nb;
+                    // the partial last chunk is always scanned, every wire
+                    if ((b0 + nb) * C > P)
+                        needm[nb - 1] = all;
+                }
+                uint32_t act = 0;  // the batch's chunks some wire needs
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    act |= (needm[i] != 0 ? 1u : 0u) << i;
+                if (act == 0)
+                    continue;
+                double ax[H], ay[H], az[H], cx[H], cy[H], cz[H];
+                int i = __builtin_ctz(act);
+                load_half((b0 + i) * C, ax, ay, az);
+                while (true) {
+                    __asm__ volatile("" ::: "memory");
+                    const int k0 = (b0 + i) * C;
+                    const int kn = min(C, P - k0);
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+                        m = j == i ? needm[j] : m;
+                    if (kn > H)
+                        load_half(k0 + H, cx, cy, cz);
+                    eval_half(k0, min(H, kn), m, ax, ay, az);
+                    const uint32_t rest = act & ~((2u << i) - 1u);
+                    const int nxt = rest ? __builtin_ctz(rest) : -1;
+                    if (nxt >= 0)
+                        load_half((b0 + nxt) * C, ax, ay, az);
+                    if (kn > H)
+                        eval_half(k0 + H, kn - H, m, cx, cy, cz);
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        if ((m >> w) & 1u)
+                            sub[w] = fminf(sub[w],
+                                           __builtin_amdgcn_sqrtf((float)best[w]) * 1.000001f);
+                    if (nxt < 0)
+                        break;
+                    i = nxt;
+                }
+            }
+        }
+        // the end, as TileScanWide: the first index of the minimum within its half chunk,
+        // its chord refinement, D and Eq. 1's capped residual
+        if (counter && lane == 0 && evals > 0)
+            atomicAdd(counter, (unsigned long long)(evals * n_valid));
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            dsq[w] = 0.0;
+        if (nw <= 0 || !seed)
+            return;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (w < nw) {
+                double f[8];
+                Base::frame(fl, w, f);
+                int k = kbest[w];
+                const int kend = min(k + H, P);
+                for (int j = k; j < kend; ++j) {
+                    const int64_t o = (int64_t)j * ld + lane;
+                    if (Base::qf(f, bx[o], by[o], bz[o]) == best[w]) {
+                        k = j;
+                        break;
+                    }
+                }
+                const double d2 = refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f, k, best[w]);
+                const double D = sqrt(d2);
+                const int wi = wire_of[w];
+                const double d = capped_residual(D, drift, offsets[wi], offsets[wi + 1], lambda);
+                dsq[w] = d * d;
+            }
+        }
+    }
+};
+
 }  // namespace cdev
 
 #endif  // COMET_DCA_SCAN_H
