@@ -535,9 +535,12 @@ def main():
         return t1 - t0, (comet.profile_end() if profile else None)
 
     variants = comet.dca_variants()
-    # autotune the DCA kernel shape on the first partition's live buffers
+    # autotune the DCA kernel shape on the live buffers of the first partition's first
+    # scan (the costliest of the three: its seeds spread widest, so a wave's lanes need
+    # the most chunks); the shape then serves every scan of this size
     step()
     r0 = runners[0]
+    r0.run(dev, grids[0], 0)
     tuned, tune_ms = comet.dca_autotune(r0.track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg,
                                         r0.rss, r0.workspace, reps=2)
     log("autotune: shape %d %s (%.3f ms); all: %s" % (tuned, variants[tuned], tune_ms[tuned],
@@ -699,6 +702,7 @@ def main():
         from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))
         out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE,
+                                            local=(8, 8, 8, 8), local_topk=4, local_iters=16,
                                             top_k=args.grad_topk, n_iter=args.grad_iters)
         g = out["grad_refine"]
         log("  coarse+LM %.2f s, |p| residual rms %.3f core %.3f MeV/c; fine grid %.2f s, rms %.3f "

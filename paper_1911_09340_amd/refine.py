@@ -24,8 +24,13 @@ from . import comet, scan, synth
 
 
 def coarse_then_lm(events, sc: synth.ScanConfig, top_k: int = 8, n_iter: int = 8,
-                   mu0: float = 1e-3, device="cuda", starts: str = "topk"):
-    """starts: "sparse" (several non-overlapping references) or "topk" (the k lowest)."""
+                   mu0: float = 1e-3, device="cuda", starts: str = "topk", local=None,
+                   local_topk: int = 4, local_iters: int = 16):
+    """starts: "sparse" (several non-overlapping references) or "topk" (the k lowest).
+    local (points per axis, or None): after the LM, a finer grid around each partition's
+    refined seed (the grid descriptor of comet_stage_grids: the seed itself at offset 0,
+    half-spans of one coarse spacing, Sec. 2.1's finer re-scan), LM again from its
+    local_topk lowest seeds, and the lowest RSS of all refined seeds is kept."""
     runner = scan.BatchRunner(events, replace(sc, n_refine=0), device)
     runner.run()
     NP = runner.n_part
@@ -50,8 +55,36 @@ def coarse_then_lm(events, sc: synth.ScanConfig, top_k: int = 8, n_iter: int = 8
     comet.topk(rss.view(NP, k), 1, pick)
     cols = torch.arange(NP, device=device) * k + pick[:, 0].clamp(min=0)
     final = torch.index_select(seeds, 1, cols)
-    return {"coarse": coarse_best, "refined": final, "rss": torch.index_select(rss, 0, cols),
-            "accepted": acc, "partitions": NP}
+    final_rss = torch.index_select(rss, 0, cols)
+    out = {"coarse": coarse_best, "refined": final, "rss": final_rss, "accepted": acc,
+           "partitions": NP}
+    if local is None:
+        return out
+    half = tuple(2.0 * h / (n - 1) if n > 1 else h for h, n in zip(sc.half, sc.n))
+    lsc = replace(sc, n=tuple(int(v) for v in local), half=half, n_refine=0)
+    lrun = scan.BatchRunner(events, lsc, device)
+    ft = final.t().contiguous()
+    comet.stage_grids(ft, ft, lsc.half, lrun.grids0)
+    lrun.run()
+    k2 = min(local_topk, lsc.n_seeds)
+    idx2 = torch.empty(NP, k2, dtype=torch.int64, device=device)
+    comet.topk(lrun.rss, k2, idx2)
+    seeds2 = torch.empty(6, NP * k2, dtype=torch.float64, device=device)
+    comet.grid_seeds(lrun.grids, lsc.n, idx2, seeds2)
+    rss2 = torch.empty(NP * k2, dtype=torch.float64, device=device)
+    comet.lm_refine(seeds2, runner.cfg, runner.packed.wire_ends, runner.packed.wire_offsets,
+                    runner.packed.drift, local_iters, mu0, rss2,
+                    comet.lm_workspace(NP * k2, device), event_wires=runner.packed.event_wires,
+                    seed_event=runner.part_event.repeat_interleave(k2))
+    # the first LM result first, so that it wins ties
+    cand = torch.cat([final.view(6, NP, 1), seeds2.view(6, NP, k2)], dim=2).reshape(6, -1)
+    crss = torch.cat([final_rss.view(NP, 1), rss2.view(NP, k2)], dim=1).contiguous()
+    comet.topk(crss, 1, pick)
+    cols = torch.arange(NP, device=device) * (k2 + 1) + pick[:, 0].clamp(min=0)
+    out["refined"] = torch.index_select(cand, 1, cols)
+    out["rss"] = torch.index_select(crss.view(-1), 0, cols)
+    out["local_improved"] = (pick[:, 0] > 0)
+    return out
 
 
 def fine_grid(events, sc: synth.ScanConfig, device="cuda"):
@@ -78,11 +111,13 @@ def summary(res: np.ndarray) -> dict:
 
 
 def compare(events, coarse: synth.ScanConfig, fine: synth.ScanConfig, top_k: int = 8,
-            n_iter: int = 8, mu0: float = 1e-3, device="cuda", starts: str = "topk") -> dict:
+            n_iter: int = 8, mu0: float = 1e-3, device="cuda", starts: str = "topk",
+            local=None, local_topk: int = 4, local_iters: int = 16) -> dict:
     """Both strategies on the same events (each timed with device synchronisation)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lm = coarse_then_lm(events, coarse, top_k, n_iter, mu0, device, starts=starts)
+    lm = coarse_then_lm(events, coarse, top_k, n_iter, mu0, device, starts=starts, local=local,
+                        local_topk=local_topk, local_iters=local_iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     fg = fine_grid(events, fine, device)
@@ -96,7 +131,11 @@ def compare(events, coarse: synth.ScanConfig, fine: synth.ScanConfig, top_k: int
         "coarse_lm": {"seconds": t1 - t0, **summary(momentum_residuals(lm["refined"], events)),
                       "mean_accepted_steps": float(lm["accepted"].float().mean().item()),
                       "starts_per_partition": top_k, "starts": starts,
-                      "lm_iterations": n_iter},
+                      "lm_iterations": n_iter,
+                      "local_rescan": None if local is None else {
+                          "grid": "x".join(map(str, local)), "lm_starts": local_topk,
+                          "lm_iterations": local_iters,
+                          "partitions_improved": float(lm["local_improved"].float().mean())}},
         "coarse_only": summary(momentum_residuals(lm["coarse"], events)),
         "fine_grid": {"seconds": t2 - t1, **summary(momentum_residuals(fg["best"], events))},
         "rss_lm_below_fine": float(np.mean(lm_rss <= fg_rss)),

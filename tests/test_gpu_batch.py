@@ -242,3 +242,39 @@ def test_multistart_refinement_matches_cpu_lm(orc, events, starts):
             ws = res[best][0]
             assert np.max(np.abs(final[:, p] - ws) / np.maximum(np.abs(ws), 1.0)) < 1e-7, p
             p += 1
+
+
+def test_local_rescan_after_lm_matches_cpu(orc, events):
+    """coarse_then_lm with the local re-scan: a finer grid around each partition's LM seed
+    (stage-grid descriptor, half-spans of one coarse spacing), LM from its lowest seeds, and
+    the lowest RSS of all: the same chain on the CPU reference, to the LM bar (1e-7)."""
+    sc = synth.ScanConfig("c", (4, 4, 4, 4), (5.0, 5.0, 0.05, 0.05), 1000, 2.0, 0.8, 0)
+    evs = events[:2]
+    out = refine.coarse_then_lm(evs, sc, top_k=2, n_iter=4, local=(3, 3, 3, 3), local_topk=2,
+                                local_iters=3)
+    final = out["refined"].cpu().numpy()
+    frss = out["rss"].cpu().numpy()
+    half = [2 * h / (n - 1) for h, n in zip(sc.half, sc.n)]
+    p = 0
+    o = oracle.Oracle()
+    for ev in evs:
+        cfg = [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
+        for t in range(ev.n_turns):
+            g = synth.grid_descriptor(ev.ref_states[t], sc)
+            seeds = o.seed_grid(g, np.array(sc.n, np.int32))
+            rss, _ = o.scan(seeds, cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+            res = [o.lm_refine(seeds[:, i], cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                               ev.drift, 4, 1e-3) for i in o.topk(rss, 2)]
+            b1 = min(range(2), key=lambda r: (res[r][1], r))
+            s1, r1 = res[b1][0], res[b1][1]
+            g2 = o.stage_grid(s1, s1, half)
+            n2 = np.array([3, 3, 3, 3], np.int32)
+            seeds2 = o.seed_grid(g2, n2)
+            rss2, _ = o.scan(seeds2, cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets, ev.drift)
+            res2 = [o.lm_refine(seeds2[:, i], cfg, sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                                ev.drift, 3, 1e-3) for i in o.topk(rss2, 2)]
+            cands = [(r1, 0, s1)] + [(res2[r][1], r + 1, res2[r][0]) for r in range(2)]
+            wr, _, ws = min(cands, key=lambda c: (c[0], c[1]))
+            assert np.max(np.abs(final[:, p] - ws) / np.maximum(np.abs(ws), 1.0)) < 1e-7, p
+            assert abs(frss[p] - wr) <= 1e-7 * max(wr, 1.0), p
+            p += 1
