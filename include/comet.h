@@ -578,13 +578,15 @@ int comet_profile_scan_points(int64_t *points);
  * block order, direct (0: the block's chunks staged through LDS; 1: every wave on its
  * own, no LDS staging; 2: wide, every wave on its own with up to 16 wires taken in
  * azimuth order, frames in LDS, each wire of a needed chunk scanned only where the
- * bound needs it) and runs (direct and wide shapes: chunks tested in runs of that many
- * first, from the summed radii of their windows; 1 = no runs); direct and runs may be
- * NULL. */
+ * bound needs it; 3: wide with Eq. 1's residual cap in the bound) and runs (direct and
+ * wide shapes: chunks tested in runs of that many first, from the summed radii of their
+ * windows; 1 = no runs); direct and runs may be NULL. comet_dca_variant_name(id): the
+ * shape's kernel as a profiler names it ("" for an id out of range). */
 int comet_dca_variant_count(void);
 int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
                            int32_t *chunk_argmin, int32_t *xcd_remap, int32_t *direct,
                            int32_t *runs);
+const char *comet_dca_variant_name(int id);
 int comet_dca_set_variant(int id);
 int comet_dca_variant_for(int64_t n_seeds, int32_t n_points, int32_t n_wires);
 int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_points,

@@ -306,21 +306,19 @@ def dca_variants():
         v = [ctypes.c_int32() for _ in range(7)]
         _check(lib.comet_dca_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_dca_variant_info")
-        form = {0: "lds", 1: "direct", 2: "wide"}[v[5].value]
+        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap"}[v[5].value]
+        lib.comet_dca_variant_name.restype = ctypes.c_char_p
+        lib.comet_dca_variant_name.argtypes = [ctypes.c_int]
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value,
                         chunk_argmin=bool(v[3].value), xcd_remap=bool(v[4].value),
-                        direct=form != "lds", form=form, runs=v[6].value))
+                        direct=form != "lds", form=form, runs=v[6].value,
+                        kernel=lib.comet_dca_variant_name(i).decode()))
     return out
 
 
 def dca_kernel_name(shape: dict) -> str:
     """The kernel symbol (template form) of a DCA shape, as a profiler names it."""
-    if shape.get("form") == "wide":
-        return "dca_wide_kernel<%d, %d, %d, %d>" % (shape["w"], shape["nwv"], shape["runs"],
-                                                    shape.get("wpe", 2))
-    return "dca_kernel<%d, %d, %d, %s, %s, %d>" % (
-        shape["w"], shape["nwv"], shape["chunk"], "true" if shape["chunk_argmin"] else "false",
-        "true" if shape.get("direct") else "false", shape.get("runs", 1))
+    return shape["kernel"]
 
 
 def set_dca_variant(i: int) -> None:
@@ -581,7 +579,7 @@ def batch_variants():
         v = [ctypes.c_int32() for _ in range(6)]
         _check(lib.comet_batch_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_batch_variant_info")
-        form = {0: "lds", 1: "direct", 2: "wide"}[v[4].value]
+        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap"}[v[4].value]
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value, blocks=v[3].value,
                         direct=form != "lds", form=form, runs=v[5].value))
     return out

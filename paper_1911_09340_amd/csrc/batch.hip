@@ -119,7 +119,7 @@ batch_scan_kernel(BatchArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int P = a.K + 1;
     const int64_t row = (int64_t)P * 64;                 // one coordinate of one tile
-    const int64_t rrow = (int64_t)radius_chunks(P) * 64;  // chunk radii of one tile
+    const int64_t rrow = (int64_t)radius_rows(P) * 64;  // chunk radii and longest step of one tile
     double *const block_scratch = a.scratch + (int64_t)blockIdx.x * NWV * (3 * row + rrow);
     double *const block_rho = block_scratch + (int64_t)NWV * 3 * row;
 
@@ -254,17 +254,19 @@ batch_scan_kernel(BatchArgs a)
 // order as in the single-event path. No block barrier: a wave that finishes a
 // partition's last tile selects its best seed on its own. WPE: waves per SIMD the
 // registers are sized for.
-template <int W, int NWV, int SUP, int WPE, bool FIELD = false>
+template <int W, int NWV, int SUP, int WPE, bool FIELD = false, bool CAP = false>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_wide_kernel(BatchArgs a)
 {
     __shared__ __align__(16) double fl_all[NWV * W * 8];
+    __shared__ double rmax_all[NWV * W];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double *const fl = fl_all + wave * W * 8;
+    double *const rmx = rmax_all + wave * W;
     const int P = a.K + 1;
     const int64_t row = (int64_t)P * 64;                 // one coordinate of one tile
-    const int64_t rrow = (int64_t)radius_chunks(P) * 64;  // chunk radii of one tile
+    const int64_t rrow = (int64_t)radius_rows(P) * 64;  // chunk radii and longest step of one tile
     double *const sx = a.scratch + ((int64_t)blockIdx.x * NWV + wave) * (3 * row + rrow);
     double *const sy = sx + row, *const sz = sy + row;
     double *const rho = sz + row;
@@ -312,14 +314,23 @@ batch_wide_kernel(BatchArgs a)
             // the group's frames into this wave's LDS rows (zero frames past the event)
             for (int i = lane; i < W * 8; i += 64)
                 fl[i] = i < nw * 8 ? a.frames[8 * (int64_t)g0 + i] : 0.0;
+            if (CAP && lane < W) {
+                // each wire's largest drift distance (-1 without hits), for the cap
+                double r = -1.0;
+                if (lane < nw)
+                    for (int j = a.offsets[g0 + lane]; j < a.offsets[g0 + lane + 1]; ++j)
+                        r = a.drift[j] > r ? a.drift[j] : r;
+                rmx[lane] = r;
+            }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             int32_t wire_of[W];
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 wire_of[w] = g0 + w;
             double d2[W];
-            TileScanWide<W, SUP, true>::run(sx, sy, sz, 64, P, n_valid, fl, nw, wire_of,
-                                            a.offsets, a.drift, a.lambda, rho, 64, a.evals, d2);
+            TileScanWide<W, SUP, true, CAP>::run(sx, sy, sz, 64, P, n_valid, fl, nw, wire_of,
+                                                 a.offsets, a.drift, a.lambda, rho, 64, a.evals,
+                                                 d2, rmx);
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 if (w < nw)
@@ -763,6 +774,10 @@ const BatchVariant kBatchVariants[] = {
     {16, 4, 16, 2, batch_wide_kernel<16, 4, 4, 2>, 4},
     {16, 4, 16, 2, batch_wide_kernel<16, 4, 1, 2>, 1},
     {12, 4, 16, 2, batch_wide_kernel<12, 4, 4, 2>, 4},
+    // wide with the residual cap in the bound (direct == 3)
+    {16, 4, 16, 3, batch_wide_kernel<16, 4, 4, 2, false, true>, 4},
+    {12, 4, 16, 3, batch_wide_kernel<12, 4, 4, 2, false, true>, 4},
+    {8, 4, 16, 3, batch_wide_kernel<8, 4, 4, 2, false, true>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
@@ -805,7 +820,7 @@ int batch_blocks(int id)
 // 64 seeds.
 size_t batch_scratch_bytes(int K)
 {
-    return sizeof(double) * (3 * (size_t)(K + 1) + (size_t)radius_chunks(K + 1)) * 64 *
+    return sizeof(double) * (3 * (size_t)(K + 1) + (size_t)radius_rows(K + 1)) * 64 *
            kMaxBatchNwv;
 }
 
@@ -946,7 +961,7 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
     if (blocks < 1)
         return fail(COMET_EHIP, "comet_batch_scan: occupancy query failed");
     const int tiles = (int)((S + 63) / 64);
-    const int per_item = v.direct == 2 ? 1 : v.nwv;  // tiles per work item
+    const int per_item = v.direct >= 2 ? 1 : v.nwv;  // tiles per work item (wide: one)
     const int supers = (tiles + per_item - 1) / per_item;
     int64_t max_tiles = (int64_t)n_partitions * tiles;
     if (max_items > 0 && max_items < max_tiles)

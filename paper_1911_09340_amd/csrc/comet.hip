@@ -118,22 +118,37 @@ __global__ __launch_bounds__(256) void chunk_radius_kernel(const double *__restr
         return;
     const int64_t PS = (int64_t)P * S;
     const int nch = cdev::radius_chunks(P);
+    double s2 = 0.0;  // the longest step of this thread's windows
+    bool step_nan = false;
     for (int n = blockIdx.y; n < nch; n += gridDim.y) {
         const int k0 = n * cdev::kRadiusChunk;
         const int k1 = min(k0 + cdev::kRadiusChunk, P - 1);
         const int64_t o0 = (int64_t)k0 * S + s;
         const double x0 = track[o0], y0 = track[PS + o0], z0 = track[2 * PS + o0];
         double r2 = 0.0;
+        double xp = x0, yp = y0, zp = z0;
 #pragma unroll 4
         for (int k = k0 + 1; k <= k1; ++k) {
             const int64_t o = (int64_t)k * S + s;
-            const double dx = track[o] - x0, dy = track[PS + o] - y0,
-                         dz = track[2 * PS + o] - z0;
+            const double x = track[o], y = track[PS + o], z = track[2 * PS + o];
+            const double dx = x - x0, dy = y - y0, dz = z - z0;
             const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
             r2 = d2 > r2 ? d2 : r2;
+            const double ex = x - xp, ey = y - yp, ez = z - zp;
+            const double e2 = fma(ex, ex, fma(ey, ey, ez * ez));
+            step_nan = step_nan || !(e2 == e2);
+            s2 = e2 > s2 ? e2 : s2;
+            xp = x;
+            yp = y;
+            zp = z;
         }
         rho[(int64_t)n * S + s] = sqrt(r2);
     }
+    // row nch: the longest step over all windows (the row starts at 0; for non-negative
+    // doubles the order of the bit patterns is the order of the values)
+    const double st = step_nan ? INFINITY : sqrt(s2);
+    atomicMax(reinterpret_cast<unsigned long long *>(rho + (int64_t)nch * S + s),
+              (unsigned long long)__double_as_longlong(st));
 }
 
 // ------------------------------------------------------------------ wire frames
@@ -164,9 +179,13 @@ __global__ void frame_kernel(const double *__restrict__ ends, int n_w, int n_pad
 // in (key, index) order. Wires near each other in azimuth share a wave, so the wave's
 // wires need nearly the same track chunks. The order changes which wave evaluates a
 // wire, never a result.
+// caps[r]: the largest drift distance of the wire in slot r (-1 for a wire without hits
+// and for the padding), for the wide form's cap of the distance bound.
 __global__ void wire_order_kernel(const double *__restrict__ frames, const float *__restrict__ key,
-                                  int n_pad, double *__restrict__ frames_sorted,
-                                  int32_t *__restrict__ wire_of)
+                                  int n_pad, int n_w, const int32_t *__restrict__ offsets,
+                                  const double *__restrict__ drift,
+                                  double *__restrict__ frames_sorted,
+                                  int32_t *__restrict__ wire_of, double *__restrict__ caps)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pad)
@@ -180,6 +199,11 @@ __global__ void wire_order_kernel(const double *__restrict__ frames, const float
     for (int j = 0; j < 8; ++j)
         frames_sorted[8 * (int64_t)rank + j] = frames[8 * (int64_t)i + j];
     wire_of[rank] = i;
+    double rmax = -1.0;
+    if (i < n_w)
+        for (int j = offsets[i]; j < offsets[i + 1]; ++j)
+            rmax = drift[j] > rmax ? drift[j] : rmax;
+    caps[rank] = rmax;
 }
 
 // ------------------------------------------------------------------ DCA / Eq. 1
@@ -251,13 +275,13 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) v
 // The wide form (TileScanWide): a block is a 64-seed tile x NWV waves of W wires in
 // azimuth order; the block's frames are copied to LDS once. WPE: waves per SIMD the
 // registers are sized for.
-template <int W, int NWV, int SUP, int WPE, int NB = 0>
+template <int W, int NWV, int SUP, int WPE, int NB = 0, bool CAP = false>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void dca_wide_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames_sorted,
-    const int32_t *__restrict__ wire_of, int n_w, const int32_t *__restrict__ offsets,
-    const double *__restrict__ drift, double lambda, const double *__restrict__ rho,
-    double *__restrict__ dsq, int n_groups, int n_blocks, int xcd_remap,
-    unsigned long long *counter)
+    const int32_t *__restrict__ wire_of, const double *__restrict__ caps, int n_w,
+    const int32_t *__restrict__ offsets, const double *__restrict__ drift, double lambda,
+    const double *__restrict__ rho, double *__restrict__ dsq, int n_groups, int n_blocks,
+    int xcd_remap, unsigned long long *counter)
 {
     __shared__ __align__(16) double fl[NWV * W * 8];
     const int b = blockIdx.x;
@@ -279,18 +303,18 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int64_t PS = (int64_t)P * S;
     double d2[W];
     // NB > 0: the latency-hiding form (batches of NB chunk tests, double-buffered halves)
-    using Near = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), true>,
-                                    TileScanWide<W, SUP, true>>;
-    using Far = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), false>,
-                                   TileScanWide<W, SUP, false>>;
+    using Near = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), true, CAP>,
+                                    TileScanWide<W, SUP, true, CAP>>;
+    using Far = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), false, CAP>,
+                                   TileScanWide<W, SUP, false, CAP>>;
     if ((int64_t)P * S < ((int64_t)1 << 29) - 64)
         Near::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid,
                   fl + wave * W * 8, nw, wire_of + wbase, offsets, drift, lambda, rho + s0, S,
-                  counter, d2);
+                  counter, d2, caps + wbase);
     else
         Far::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid,
                  fl + wave * W * 8, nw, wire_of + wbase, offsets, drift, lambda, rho + s0, S,
-                 counter, d2);
+                 counter, d2, caps + wbase);
     if (lane < n_valid)
 #pragma unroll
         for (int w = 0; w < W; ++w)
@@ -451,52 +475,60 @@ struct DcaVariant {
                    const double *, double, const double *, double *, int, int, int,
                    unsigned long long *);
     // the wide form (direct == 2): frames in azimuth order and each slot's wire
-    void (*wide)(const double *, int64_t, int, const double *, const int32_t *, int,
-                 const int32_t *, const double *, double, const double *, double *, int, int,
-                 int, unsigned long long *) = nullptr;
+    void (*wide)(const double *, int64_t, int, const double *, const int32_t *, const double *,
+                 int, const int32_t *, const double *, double, const double *, double *, int,
+                 int, int, unsigned long long *) = nullptr;
     int wpe = 4;
+    const char *name = "";  // the kernel as a profiler names it
 };
 
 const DcaVariant kDcaVariants[] = {
-    {6, 8, 16, 1, 1, 0, 1, dca_kernel<6, 8, 16, true, false, 1>},
-    {6, 8, 16, 1, 0, 0, 1, dca_kernel<6, 8, 16, true, false, 1>},
-    {6, 16, 16, 1, 1, 0, 1, dca_kernel<6, 16, 16, true, false, 1>},
-    {5, 16, 16, 1, 1, 0, 1, dca_kernel<5, 16, 16, true, false, 1>},
-    {4, 16, 16, 1, 1, 0, 1, dca_kernel<4, 16, 16, true, false, 1>},
-    {4, 8, 32, 0, 1, 0, 1, dca_kernel<4, 8, 32, false, false, 1>},
-    {4, 8, 32, 1, 1, 0, 1, dca_kernel<4, 8, 32, true, false, 1>},
-    {4, 8, 16, 1, 1, 0, 1, dca_kernel<4, 8, 16, true, false, 1>},
-    {5, 8, 16, 1, 1, 0, 1, dca_kernel<5, 8, 16, true, false, 1>},
-    {3, 8, 32, 1, 1, 0, 1, dca_kernel<3, 8, 32, true, false, 1>},
-    {4, 16, 32, 1, 1, 0, 1, dca_kernel<4, 16, 32, true, false, 1>},
-    {3, 16, 32, 1, 1, 0, 1, dca_kernel<3, 16, 32, true, false, 1>},
+    {6, 8, 16, 1, 1, 0, 1, dca_kernel<6, 8, 16, true, false, 1>, nullptr, 4, "dca_kernel<6, 8, 16, true, false, 1>"},
+    {6, 8, 16, 1, 0, 0, 1, dca_kernel<6, 8, 16, true, false, 1>, nullptr, 4, "dca_kernel<6, 8, 16, true, false, 1>"},
+    {6, 16, 16, 1, 1, 0, 1, dca_kernel<6, 16, 16, true, false, 1>, nullptr, 4, "dca_kernel<6, 16, 16, true, false, 1>"},
+    {5, 16, 16, 1, 1, 0, 1, dca_kernel<5, 16, 16, true, false, 1>, nullptr, 4, "dca_kernel<5, 16, 16, true, false, 1>"},
+    {4, 16, 16, 1, 1, 0, 1, dca_kernel<4, 16, 16, true, false, 1>, nullptr, 4, "dca_kernel<4, 16, 16, true, false, 1>"},
+    {4, 8, 32, 0, 1, 0, 1, dca_kernel<4, 8, 32, false, false, 1>, nullptr, 4, "dca_kernel<4, 8, 32, false, false, 1>"},
+    {4, 8, 32, 1, 1, 0, 1, dca_kernel<4, 8, 32, true, false, 1>, nullptr, 4, "dca_kernel<4, 8, 32, true, false, 1>"},
+    {4, 8, 16, 1, 1, 0, 1, dca_kernel<4, 8, 16, true, false, 1>, nullptr, 4, "dca_kernel<4, 8, 16, true, false, 1>"},
+    {5, 8, 16, 1, 1, 0, 1, dca_kernel<5, 8, 16, true, false, 1>, nullptr, 4, "dca_kernel<5, 8, 16, true, false, 1>"},
+    {3, 8, 32, 1, 1, 0, 1, dca_kernel<3, 8, 32, true, false, 1>, nullptr, 4, "dca_kernel<3, 8, 32, true, false, 1>"},
+    {4, 16, 32, 1, 1, 0, 1, dca_kernel<4, 16, 32, true, false, 1>, nullptr, 4, "dca_kernel<4, 16, 32, true, false, 1>"},
+    {3, 16, 32, 1, 1, 0, 1, dca_kernel<3, 16, 32, true, false, 1>, nullptr, 4, "dca_kernel<3, 16, 32, true, false, 1>"},
     // every wave on its own (no LDS staging)
-    {4, 8, 16, 1, 1, 1, 1, dca_kernel<4, 8, 16, true, true, 1>},
-    {3, 8, 16, 1, 1, 1, 1, dca_kernel<3, 8, 16, true, true, 1>},
-    {2, 8, 16, 1, 1, 1, 1, dca_kernel<2, 8, 16, true, true, 1>},
-    {4, 4, 16, 1, 1, 1, 1, dca_kernel<4, 4, 16, true, true, 1>},
-    {3, 4, 16, 1, 1, 1, 1, dca_kernel<3, 4, 16, true, true, 1>},
-    {4, 8, 32, 1, 1, 1, 1, dca_kernel<4, 8, 32, true, true, 1>},
+    {4, 8, 16, 1, 1, 1, 1, dca_kernel<4, 8, 16, true, true, 1>, nullptr, 4, "dca_kernel<4, 8, 16, true, true, 1>"},
+    {3, 8, 16, 1, 1, 1, 1, dca_kernel<3, 8, 16, true, true, 1>, nullptr, 4, "dca_kernel<3, 8, 16, true, true, 1>"},
+    {2, 8, 16, 1, 1, 1, 1, dca_kernel<2, 8, 16, true, true, 1>, nullptr, 4, "dca_kernel<2, 8, 16, true, true, 1>"},
+    {4, 4, 16, 1, 1, 1, 1, dca_kernel<4, 4, 16, true, true, 1>, nullptr, 4, "dca_kernel<4, 4, 16, true, true, 1>"},
+    {3, 4, 16, 1, 1, 1, 1, dca_kernel<3, 4, 16, true, true, 1>, nullptr, 4, "dca_kernel<3, 4, 16, true, true, 1>"},
+    {4, 8, 32, 1, 1, 1, 1, dca_kernel<4, 8, 32, true, true, 1>, nullptr, 4, "dca_kernel<4, 8, 32, true, true, 1>"},
     // runs of 4 chunks tested first (two-level distance bound)
-    {4, 4, 16, 1, 1, 1, 4, dca_kernel<4, 4, 16, true, true, 4>},
-    {3, 4, 16, 1, 1, 1, 4, dca_kernel<3, 4, 16, true, true, 4>},
-    {4, 8, 16, 1, 1, 1, 4, dca_kernel<4, 8, 16, true, true, 4>},
-    {4, 4, 16, 1, 1, 1, 2, dca_kernel<4, 4, 16, true, true, 2>},
+    {4, 4, 16, 1, 1, 1, 4, dca_kernel<4, 4, 16, true, true, 4>, nullptr, 4, "dca_kernel<4, 4, 16, true, true, 4>"},
+    {3, 4, 16, 1, 1, 1, 4, dca_kernel<3, 4, 16, true, true, 4>, nullptr, 4, "dca_kernel<3, 4, 16, true, true, 4>"},
+    {4, 8, 16, 1, 1, 1, 4, dca_kernel<4, 8, 16, true, true, 4>, nullptr, 4, "dca_kernel<4, 8, 16, true, true, 4>"},
+    {4, 4, 16, 1, 1, 1, 2, dca_kernel<4, 4, 16, true, true, 2>, nullptr, 4, "dca_kernel<4, 4, 16, true, true, 2>"},
     // wide: up to 16 wires per wave in azimuth order, frames in LDS, per-wire skips
-    {16, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 1, 4, 2>, 2},
-    {16, 2, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 2, 4, 2>, 2},
-    {16, 1, 16, 1, 1, 2, 1, nullptr, dca_wide_kernel<16, 1, 1, 2>, 2},
-    {8, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<8, 1, 4, 2>, 2},
-    {16, 4, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 4, 4, 2>, 2},
-    {12, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<12, 1, 4, 2>, 2},
+    {16, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 1, 4, 2>, 2, "dca_wide_kernel<16, 1, 4, 2, 0, false>"},
+    {16, 2, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 2, 4, 2>, 2, "dca_wide_kernel<16, 2, 4, 2, 0, false>"},
+    {16, 1, 16, 1, 1, 2, 1, nullptr, dca_wide_kernel<16, 1, 1, 2>, 2, "dca_wide_kernel<16, 1, 1, 2, 0, false>"},
+    {8, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<8, 1, 4, 2>, 2, "dca_wide_kernel<8, 1, 4, 2, 0, false>"},
+    {16, 4, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<16, 4, 4, 2>, 2, "dca_wide_kernel<16, 4, 4, 2, 0, false>"},
+    {12, 1, 16, 1, 1, 2, 4, nullptr, dca_wide_kernel<12, 1, 4, 2>, 2, "dca_wide_kernel<12, 1, 4, 2, 0, false>"},
     // wide with the chunk tests in batches of 8 or 16 and double-buffered half chunks
     // (runs reports the batch: its first point is tested with the batch's summed radii)
-    {8, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<8, 1, 0, 2, 8>, 2},
-    {8, 1, 16, 1, 1, 2, 16, nullptr, dca_wide_kernel<8, 1, 0, 2, 16>, 2},
-    {12, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<12, 1, 0, 2, 8>, 2},
-    {16, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<16, 1, 0, 2, 8>, 2},
-    {6, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<6, 1, 0, 3, 8>, 3},
-    {4, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<4, 1, 0, 3, 8>, 3},
+    {8, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<8, 1, 0, 2, 8>, 2, "dca_wide_kernel<8, 1, 0, 2, 8, false>"},
+    {8, 1, 16, 1, 1, 2, 16, nullptr, dca_wide_kernel<8, 1, 0, 2, 16>, 2, "dca_wide_kernel<8, 1, 0, 2, 16, false>"},
+    {12, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<12, 1, 0, 2, 8>, 2, "dca_wide_kernel<12, 1, 0, 2, 8, false>"},
+    {16, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<16, 1, 0, 2, 8>, 2, "dca_wide_kernel<16, 1, 0, 2, 8, false>"},
+    {6, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<6, 1, 0, 3, 8>, 3, "dca_wide_kernel<6, 1, 0, 3, 8, false>"},
+    {4, 1, 16, 1, 1, 2, 8, nullptr, dca_wide_kernel<4, 1, 0, 3, 8>, 3, "dca_wide_kernel<4, 1, 0, 3, 8, false>"},
+    // wide with the residual cap in the bound (no upper-bound pass; direct == 3)
+    {16, 1, 16, 1, 1, 3, 4, nullptr, dca_wide_kernel<16, 1, 4, 2, 0, true>, 2, "dca_wide_kernel<16, 1, 4, 2, 0, true>"},
+    {12, 1, 16, 1, 1, 3, 4, nullptr, dca_wide_kernel<12, 1, 4, 2, 0, true>, 2, "dca_wide_kernel<12, 1, 4, 2, 0, true>"},
+    {8, 1, 16, 1, 1, 3, 4, nullptr, dca_wide_kernel<8, 1, 4, 2, 0, true>, 2, "dca_wide_kernel<8, 1, 4, 2, 0, true>"},
+    {16, 1, 16, 1, 1, 3, 8, nullptr, dca_wide_kernel<16, 1, 0, 2, 8, true>, 2, "dca_wide_kernel<16, 1, 0, 2, 8, true>"},
+    {8, 1, 16, 1, 1, 3, 8, nullptr, dca_wide_kernel<8, 1, 0, 2, 8, true>, 2, "dca_wide_kernel<8, 1, 0, 2, 8, true>"},
+    {16, 2, 16, 1, 1, 3, 4, nullptr, dca_wide_kernel<16, 2, 4, 2, 0, true>, 2, "dca_wide_kernel<16, 2, 4, 2, 0, true>"},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
 constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above
@@ -525,7 +557,8 @@ int wire_pad(int n_w)
 size_t frames_region_bytes(int n_w)
 {
     const size_t pad = (size_t)wire_pad(n_w);
-    return 2 * align256(sizeof(double) * 8 * pad) + 2 * align256(sizeof(int32_t) * pad);
+    return 2 * align256(sizeof(double) * 8 * pad) + 2 * align256(sizeof(int32_t) * pad) +
+           align256(sizeof(double) * pad);
 }
 
 }  // namespace
@@ -625,7 +658,7 @@ size_t comet_dca_workspace_bytes(int64_t n_seeds, int32_t n_points, int32_t n_wi
         return 0;
     return frames_region_bytes(n_wires) +
            align256(sizeof(double) * (size_t)n_wires * (size_t)n_seeds) +
-           align256(sizeof(double) * (size_t)cdev::radius_chunks(n_points) * (size_t)n_seeds);
+           align256(sizeof(double) * (size_t)cdev::radius_rows(n_points) * (size_t)n_seeds);
 }
 
 }  // extern "C"
@@ -665,8 +698,9 @@ int check_dca_args(const char *who, const double *track_xyz, int64_t n_seeds, in
 }
 
 // The workspace: frames in wire order, frames in azimuth order, each azimuth slot's
-// wire, the azimuth keys (together frames_region_bytes), then dsq[n_w][S], then the
-// chunk radii [radius_chunks(P)][S].
+// wire, each azimuth slot's cap (the wire's largest drift distance, -1 without hits),
+// the azimuth keys (together frames_region_bytes), then dsq[n_w][S], then the chunk
+// radii [radius_chunks(P)][S] followed by each track's longest step [S].
 double *dca_frames(void *workspace) { return (double *)workspace; }
 
 double *dca_frames_sorted(void *workspace, int n_wires)
@@ -686,6 +720,12 @@ float *dca_keys(void *workspace, int n_wires)
                      align256(sizeof(int32_t) * (size_t)wire_pad(n_wires)));
 }
 
+double *dca_caps(void *workspace, int n_wires)
+{
+    return (double *)((char *)dca_keys(workspace, n_wires) +
+                      align256(sizeof(float) * (size_t)wire_pad(n_wires)));
+}
+
 double *dca_dsq(void *workspace, int n_wires)
 {
     return (double *)((char *)workspace + frames_region_bytes(n_wires));
@@ -700,6 +740,14 @@ double *dca_rho(void *workspace, int n_wires, int64_t n_seeds)
 int launch_radius(const double *track_xyz, int64_t n_seeds, int32_t n_points, int n_wires,
                   void *workspace, hipStream_t hs)
 {
+    // the longest-step row starts at 0 (the radius kernel raises it with atomicMax)
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n_seeds + 255) / 256)), dim3(256), 0, hs,
+                       dca_rho(workspace, n_wires, n_seeds) +
+                           (int64_t)cdev::radius_chunks(n_points) * n_seeds,
+                       n_seeds, 0.0);
+    int st = launched("fill_kernel");
+    if (st)
+        return st;
     hipLaunchKernelGGL(chunk_radius_kernel,
                        dim3((unsigned)((n_seeds + 255) / 256),
                             (unsigned)std::min(cdev::radius_chunks(n_points), 65535)),
@@ -708,7 +756,8 @@ int launch_radius(const double *track_xyz, int64_t n_seeds, int32_t n_points, in
     return launched("chunk_radius_kernel");
 }
 
-int launch_frames(const double *wire_ends, int n_wires, void *workspace, hipStream_t hs)
+int launch_frames(const double *wire_ends, int n_wires, const int32_t *wire_offsets,
+                  const double *drift, void *workspace, hipStream_t hs)
 {
     const int pad = wire_pad(n_wires);
     hipLaunchKernelGGL(frame_kernel, dim3((pad + 63) / 64), dim3(64), 0, hs, wire_ends, n_wires,
@@ -718,8 +767,9 @@ int launch_frames(const double *wire_ends, int n_wires, void *workspace, hipStre
         return st;
     hipLaunchKernelGGL(wire_order_kernel, dim3((pad + 255) / 256), dim3(256), 0, hs,
                        (const double *)dca_frames(workspace),
-                       (const float *)dca_keys(workspace, n_wires), pad,
-                       dca_frames_sorted(workspace, n_wires), dca_wire_of(workspace, n_wires));
+                       (const float *)dca_keys(workspace, n_wires), pad, n_wires, wire_offsets,
+                       drift, dca_frames_sorted(workspace, n_wires), dca_wire_of(workspace, n_wires),
+                       dca_caps(workspace, n_wires));
     return launched("wire_order_kernel");
 }
 
@@ -735,7 +785,8 @@ int launch_dca(int id, const double *track_xyz, int64_t n_seeds, int32_t n_point
     if (v.wide) {
         hipLaunchKernelGGL(v.wide, dim3((unsigned)n_blocks), dim3(64 * v.nwv), 0, hs, track_xyz,
                            n_seeds, n_points, (const double *)dca_frames_sorted(workspace, n_wires),
-                           (const int32_t *)dca_wire_of(workspace, n_wires), n_wires, wire_offsets,
+                           (const int32_t *)dca_wire_of(workspace, n_wires),
+                           (const double *)dca_caps(workspace, n_wires), n_wires, wire_offsets,
                            drift, lambda, (const double *)dca_rho(workspace, n_wires, n_seeds),
                            dca_dsq(workspace, n_wires), n_groups, (int)n_blocks, v.xcd_remap,
                            scan_counter());
@@ -782,7 +833,7 @@ int comet_dca_rss(const double *track_xyz, int64_t n_seeds, int32_t n_points,
                            rss, n_seeds, 0.0);
         return launched("fill_kernel");
     }
-    st = launch_frames(wire_ends, n_wires, workspace, hs);
+    st = launch_frames(wire_ends, n_wires, wire_offsets, drift, workspace, hs);
     if (st)
         return st;
     st = launch_radius(track_xyz, n_seeds, n_points, n_wires, workspace, hs);
@@ -836,7 +887,7 @@ int track_dca_rss(const double *seeds6, int64_t n_seeds, const comet_config *cfg
                            rss, n_seeds, 0.0);
         return launched("fill_kernel");
     }
-    st = launch_frames(wire_ends, n_wires, workspace, hs);
+    st = launch_frames(wire_ends, n_wires, wire_offsets, drift, workspace, hs);
     if (st)
         return st;
     {
@@ -974,7 +1025,7 @@ int comet_dca_autotune(const double *track_xyz, int64_t n_seeds, int32_t n_point
     if (st)
         return st;
     hipStream_t hs = (hipStream_t)stream;
-    st = launch_frames(wire_ends, n_wires, workspace, hs);
+    st = launch_frames(wire_ends, n_wires, wire_offsets, drift, workspace, hs);
     if (st)
         return st;
     st = launch_radius(track_xyz, n_seeds, n_points, n_wires, workspace, hs);
@@ -1114,6 +1165,13 @@ int comet_dca_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk,
     if (runs)
         *runs = kDcaVariants[id].sup;
     return COMET_OK;
+}
+
+const char *comet_dca_variant_name(int id)
+{
+    if (id < 0 || id >= kNumDcaVariants)
+        return "";
+    return kDcaVariants[id].name;
 }
 
 int comet_dca_set_variant(int id)

@@ -621,7 +621,24 @@ struct TileScanDirect {
 // same bound per wire), and its minimum is tracked per half chunk (the first index is
 // recovered in the half that first reaches the final minimum, as in scan_finish). The
 // next chunk's first point is loaded while the current chunk is scanned.
-template <int W, int SUP, bool BUF>
+// CAP: the bound also uses the residual cap of Eq. 1. A wire's d is lambda whenever
+// its DCA D exceeds its largest drift distance r_max plus lambda, so D is needed
+// exactly only if some recorded point lies within cap = r_max + lambda + sigma (+ a
+// margin) of the wire, sigma being the track's longest step. Every bound is then
+// min(cap, the running minimum): if some point lies within the cap, the chunks holding
+// the first minimum are never skipped and D is exact; if none does, every chord lies
+// farther than r_max + lambda (a chord is within half its length, at most sigma / 2,
+// of one of its end points), so whatever the scan finds gives d = lambda, exactly as
+// the full scan. A wire without hits (d = lambda always) gets the cap 0. With the cap
+// the pass over every other chunk's first point is not needed and is left out.
+__device__ __forceinline__ float wide_cap(double rmax, double lambda, double sigma)
+{
+    if (rmax < 0.0)
+        return 0.0f;
+    return (float)((rmax + lambda) + sigma) * 1.000001f + 1e-5f;
+}
+
+template <int W, int SUP, bool BUF, bool CAP = false>
 struct TileScanWide {
     static constexpr int C = kRadiusChunk;  // one radius window per chunk
     static constexpr int H = C / 2;         // the minimum is tracked per half chunk
@@ -655,14 +672,17 @@ struct TileScanWide {
 
     // bx, by, bz: the tile's track (point k of lane l at b[k * ld + l]); fl: this wave's
     // W frames in LDS ([W][8], slots >= nw hold anything finite); wire_of: the wave's
-    // slots' wire indices (CSR rows of offsets/drift); rho: the tile's chunk radii.
+    // slots' wire indices (CSR rows of offsets/drift); rho: the tile's chunk radii, with
+    // each track's longest step in row radius_chunks(P); rmax (CAP): the wave's slots'
+    // largest drift distances (-1: no hits).
     // Returns d^2 of (lane, slot w) in dsq[w] for lanes < n_valid and w < nw.
     __device__ __forceinline__ static void run(
         const double *__restrict__ bx, const double *__restrict__ by,
         const double *__restrict__ bz, int64_t ld, int P, int n_valid, const double *fl, int nw,
         const int32_t *__restrict__ wire_of, const int32_t *__restrict__ offsets,
         const double *__restrict__ drift, double lambda, const double *__restrict__ rho,
-        int64_t ldr, unsigned long long *counter, double (&dsq)[W])
+        int64_t ldr, unsigned long long *counter, double (&dsq)[W],
+        const double *__restrict__ rmax = nullptr)
     {
         const int lane = threadIdx.x & 63;
         const bool seed = lane < n_valid;
@@ -701,15 +721,21 @@ struct TileScanWide {
                 z = bz[o];
             }
         };
+        if (CAP && nw > 0) {
+            const double sig = rho[(int64_t)radius_chunks(P) * ldr + col];
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sub[w] = w < nw ? wide_cap(rmax[w], lambda, sig) : 0.0f;
+        }
         if (nw > 0) {
             // (A) upper bounds of the final minima: every other chunk's first point, eight
-            // points per pass, each frame read once per pass
+            // points per pass, each frame read once per pass (not needed with the cap)
             float ub[W];
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 ub[w] = INFINITY;
             int n_s = 0;
-            for (int k0 = 0; k0 < P; k0 += 8 * 2 * C) {
+            for (int k0 = 0; !CAP && k0 < P; k0 += 8 * 2 * C) {
                 double x[8], y[8], z[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
@@ -730,9 +756,10 @@ struct TileScanWide {
                 }
             }
             evals += (int64_t)nw * n_s;
+            if (!CAP)
 #pragma unroll
-            for (int w = 0; w < W; ++w)
-                sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
+                for (int w = 0; w < W; ++w)
+                    sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
 
             const int nch = (P + C - 1) / C;
             double cx, cy, cz;  // the first point of chunk n
@@ -886,7 +913,7 @@ struct TileScanWide {
 // batch needs are then scanned in half chunks of H points with two register buffers:
 // the next half is loading while the current one is evaluated. Each wire of a chunk
 // is evaluated only where some lane needs it; its minimum is tracked per half chunk.
-template <int W, int NB, bool BUF>
+template <int W, int NB, bool BUF, bool CAP = false>
 struct TileScanWideP {
     using Base = TileScanWide<W, 1, BUF>;
     static constexpr int C = kRadiusChunk;
@@ -897,7 +924,8 @@ struct TileScanWideP {
         const double *__restrict__ bz, int64_t ld, int P, int n_valid, const double *fl, int nw,
         const int32_t *__restrict__ wire_of, const int32_t *__restrict__ offsets,
         const double *__restrict__ drift, double lambda, const double *__restrict__ rho,
-        int64_t ldr, unsigned long long *counter, double (&dsq)[W])
+        int64_t ldr, unsigned long long *counter, double (&dsq)[W],
+        const double *__restrict__ rmax = nullptr)
     {
         const int lane = threadIdx.x & 63;
         const bool seed = lane < n_valid;
@@ -978,15 +1006,22 @@ struct TileScanWideP {
             }
             evals += (int64_t)__builtin_popcount(mask) * n;
         };
+        if (CAP && nw > 0) {
+            const double sig = rho[(int64_t)radius_chunks(P) * ldr + col];
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sub[w] = w < nw ? wide_cap(rmax[w], lambda, sig) : 0.0f;
+        }
         if (nw > 0) {
             // (A) upper bounds of the final minima: every other chunk's first point,
-            // eight per round, the next round loading while this one is evaluated
+            // eight per round, the next round loading while this one is evaluated (not
+            // needed with the cap)
             float ub[W];
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 ub[w] = INFINITY;
             int n_s = 0;
-            {
+            if (!CAP) {
                 double x[8], y[8], z[8];
                 auto load8 = [&](int k0, double (&px)[8], double (&py)[8], double (&pz)[8]) {
 #pragma unroll
@@ -1022,9 +1057,10 @@ struct TileScanWideP {
                 }
             }
             evals += (int64_t)nw * n_s;
+            if (!CAP)
 #pragma unroll
-            for (int w = 0; w < W; ++w)
-                sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
+                for (int w = 0; w < W; ++w)
+                    sub[w] = __builtin_amdgcn_sqrtf(ub[w]) * 1.000001f;
             const uint32_t all = nw >= 32 ? 0xffffffffu : ((1u << nw) - 1u);
 
             const int nch = (P + C - 1) / C;

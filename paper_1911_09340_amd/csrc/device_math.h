@@ -339,11 +339,19 @@ __device__ __forceinline__ double refine_dca2(const double *__restrict__ track, 
 // point) and rho[n] = max |p_k - p_(16 n)| over it, so that a 32-point chunk starting
 // at 16 n lies within rho[n] + rho[n + 1] of its first point. Feed every point in
 // order; NaN distances are ignored (a NaN first point makes the bound unused: its q
-// is NaN and the scan never skips such a chunk).
+// is NaN and the scan never skips such a chunk). Row radius_chunks(P) receives the
+// longest step |p_(k+1) - p_k| of the track (+inf when a step is NaN), which bounds
+// the length of every chord (the wide scan's cap, TileScanWide).
 constexpr int kRadiusChunk = 16;
+
+__host__ __device__ constexpr int radius_chunks(int P) { return (P - 1) / kRadiusChunk + 1; }
+// rows of a track's radius array: the windows, then the longest step
+__host__ __device__ constexpr int radius_rows(int P) { return radius_chunks(P) + 1; }
 
 struct ChunkRadius {
     double x0 = 0.0, y0 = 0.0, z0 = 0.0, r2 = 0.0;
+    double xp = 0.0, yp = 0.0, zp = 0.0, s2 = 0.0;  // previous point, longest step squared
+    bool step_nan = false;
     __device__ __forceinline__ void add(int k, int P, double x, double y, double z,
                                         double *__restrict__ rho, int64_t ld)
     {
@@ -351,7 +359,14 @@ struct ChunkRadius {
             const double dx = x - x0, dy = y - y0, dz = z - z0;
             const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
             r2 = d2 > r2 ? d2 : r2;
+            const double ex = x - xp, ey = y - yp, ez = z - zp;
+            const double e2 = fma(ex, ex, fma(ey, ey, ez * ez));
+            step_nan = step_nan || !(e2 == e2);
+            s2 = e2 > s2 ? e2 : s2;
         }
+        xp = x;
+        yp = y;
+        zp = z;
         if (k % kRadiusChunk == 0) {
             if (k > 0)
                 rho[(int64_t)(k / kRadiusChunk - 1) * ld] = sqrt(r2);
@@ -360,12 +375,12 @@ struct ChunkRadius {
             z0 = z;
             r2 = 0.0;
         }
-        if (k == P - 1)
+        if (k == P - 1) {
             rho[(int64_t)(k / kRadiusChunk) * ld] = sqrt(r2);
+            rho[(int64_t)radius_chunks(P) * ld] = step_nan ? INFINITY : sqrt(s2);
+        }
     }
 };
-
-__host__ __device__ constexpr int radius_chunks(int P) { return (P - 1) / kRadiusChunk + 1; }
 
 // Eq. 1 for one wire: d = min(lambda, min_j |D - r_j|).
 __device__ __forceinline__ double capped_residual(double D, const double *__restrict__ drift,

@@ -97,7 +97,7 @@ def test_track_bitwise(orc, bz, charge, h, K):
 
 
 # ------------------------------------------------------------------ A3/A4 RSS
-@pytest.mark.parametrize("variant", range(34))
+@pytest.mark.parametrize("variant", range(40))
 def test_rss_bitwise_plain_every_variant(orc, ev_plain, variant):
     """Ragged 7x9x8x9 grid (4536 seeds, 71 tiles with a partial last tile)."""
     assert variant < len(comet.dca_variants())
