@@ -506,6 +506,14 @@ int comet_backward_seeds(const double *seeds6, int32_t n, const comet_config *cf
                          int32_t max_steps, double *out6, int32_t *steps, void *stream);
 int comet_stage_grids(const double *transverse6, const double *ext6, int32_t n,
                       const double half[4], double *grids, void *stream);
+/* The seed's z as a fifth grid axis (Sec. 3.1: the seed has five degrees of freedom):
+ * grids[i][u][14] for u < n_z is comet_stage_grids' descriptor of seed i with the
+ * reference z replaced by ext6[i][2] + z_half (2u - (n_z - 1)) / (n_z - 1) (the axis
+ * rule of comet_seed_grid; ext6[i][2] itself when n_z = 1). n, n_z >= 1; z_half finite
+ * and >= 0; grids device double[n][n_z][14]. */
+int comet_stage_grids_z(const double *transverse6, const double *ext6, int32_t n,
+                        const double half[4], int32_t n_z, double z_half, double *grids,
+                        void *stream);
 size_t comet_exclude_workspace_bytes(int32_t n_events);
 int comet_exclude_hits(const int32_t *event_wires, int32_t n_events, const int32_t *wire_offsets,
                        int32_t n_wires, const double *drift, const double *wire_ends,

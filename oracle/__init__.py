@@ -88,6 +88,8 @@ def _bind(lib):
                                          ctypes.c_double, ctypes.c_int32, _d]
     lib.oracle_stage_grid.restype = None
     lib.oracle_stage_grid.argtypes = [_d, _d, _d, _d]
+    lib.oracle_stage_grids_z.restype = None
+    lib.oracle_stage_grids_z.argtypes = [_d, _d, _d, ctypes.c_int32, ctypes.c_double, _d]
     lib.oracle_exclude_hits.restype = ctypes.c_int32
     lib.oracle_exclude_hits.argtypes = [ctypes.c_int32, _i32, _d, _d, ctypes.POINTER(ctypes.c_uint8),
                                         _i32, _d, _d, _i32, _i32]
@@ -364,6 +366,12 @@ class Oracle:
     def stage_grid(self, transverse6, ext6, half):
         g = np.empty(14)
         self.lib.oracle_stage_grid(_p(_f64(transverse6)), _p(_f64(ext6)), _p(_f64(half)), _p(g))
+        return g
+
+    def stage_grids_z(self, transverse6, ext6, half, n_z, z_half):
+        g = np.empty((n_z, 14))
+        self.lib.oracle_stage_grids_z(_p(_f64(transverse6)), _p(_f64(ext6)), _p(_f64(half)),
+                                      int(n_z), float(z_half), _p(g))
         return g
 
     def exclude_hits(self, offsets, drift, ends, exclude):

@@ -1143,6 +1143,19 @@ void oracle_stage_grid(const double transverse6[6], const double ext6[6], const 
         grid[10 + a] = half[a];
 }
 
+/* The seed's z as a fifth grid axis (Sec. 3.1: the seed has five degrees of freedom):
+ * grids[u] (u < n_z) is the stage grid with the reference z moved to the u-th of n_z
+ * values spread evenly over ext6[2] +- z_half (the rule of the other axes). */
+void oracle_stage_grids_z(const double transverse6[6], const double ext6[6],
+                          const double half[4], int32_t n_z, double z_half, double *grids)
+{
+    for (int32_t u = 0; u < n_z; ++u) {
+        double *g = grids + 14 * (size_t)u;
+        oracle_stage_grid(transverse6, ext6, half, g);
+        g[2] = oracle_axis_value(ext6[2], z_half, n_z, u);
+    }
+}
+
 /* Exclusion of classified hits (Sec. 3.1: hits classified at earlier stages are left
  * out of later scans, so the wire count shrinks). One event in CSR (wire i owns hits
  * [offsets[i], offsets[i+1]), offsets[0] = 0): hits with exclude[j] != 0 are dropped,

@@ -505,6 +505,8 @@ def _bind_batch(lib):
     lib.comet_backward_seeds.restype = ctypes.c_int
     lib.comet_stage_grids.argtypes = [_vp, _vp, _i32, D4, _vp, _vp]
     lib.comet_stage_grids.restype = ctypes.c_int
+    lib.comet_stage_grids_z.argtypes = [_vp, _vp, _i32, D4, _i32, ctypes.c_double, _vp, _vp]
+    lib.comet_stage_grids_z.restype = ctypes.c_int
     lib.comet_exclude_workspace_bytes.argtypes = [_i32]
     lib.comet_exclude_workspace_bytes.restype = ctypes.c_size_t
     lib.comet_exclude_hits.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
@@ -705,6 +707,19 @@ def stage_grids(transverse: torch.Tensor, ext: torch.Tensor, half, grids: torch.
                                  _ptr(ext, torch.float64, "ext", (n, 6)), n, h,
                                  _ptr(grids, torch.float64, "grids", (n, 14)), _stream()),
            "comet_stage_grids")
+
+
+def stage_grids_z(transverse: torch.Tensor, ext: torch.Tensor, half, n_z: int, z_half: float,
+                  grids: torch.Tensor) -> None:
+    """comet_stage_grids_z: grids [n, n_z, 14], the seed's z as a fifth axis."""
+    lib = _bind_batch(load())
+    n = int(transverse.shape[0])
+    h = (ctypes.c_double * 4)(*[float(v) for v in half])
+    _check(lib.comet_stage_grids_z(_ptr(transverse, torch.float64, "transverse", (n, 6)),
+                                   _ptr(ext, torch.float64, "ext", (n, 6)), n, h, int(n_z),
+                                   float(z_half),
+                                   _ptr(grids, torch.float64, "grids", (n, int(n_z), 14)),
+                                   _stream()), "comet_stage_grids_z")
 
 
 def exclude_workspace(n_events: int, device=None) -> torch.Tensor:

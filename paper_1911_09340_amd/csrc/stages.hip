@@ -96,6 +96,40 @@ __global__ __launch_bounds__(256) void stage_grid_kernel(const double *__restric
     g[13] = h3;
 }
 
+// The seed's z as a fifth grid axis (Sec. 3.1 gives the seed five degrees of freedom):
+// grids[i][u] for u < n_z is stage_grid_kernel's descriptor with the reference z set to
+// axis_value(ext z, z_half, n_z, u), the same spacing rule as the other axes.
+__global__ __launch_bounds__(256) void stage_grid_z_kernel(const double *__restrict__ transverse6,
+                                                           const double *__restrict__ ext6, int n,
+                                                           double h0, double h1, double h2,
+                                                           double h3, int n_z, double z_half,
+                                                           double *__restrict__ grids)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)n * n_z)
+        return;
+    const int64_t i = q / n_z;
+    const int u = (int)(q - i * n_z);
+    const double *t = transverse6 + 6 * i;
+    const double *e = ext6 + 6 * i;
+    double *g = grids + 14 * q;
+    const double gx = t[0], gy = t[1], gpx = t[3], gpy = t[4], gpz = e[5];
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = axis_value(e[2], z_half, n_z, u);
+    g[3] = gpx;
+    g[4] = gpy;
+    g[5] = gpz;
+    g[6] = 0.0;
+    g[7] = sqrt((gpx * gpx + gpy * gpy) + gpz * gpz);
+    g[8] = 0.0;
+    g[9] = 0.0;
+    g[10] = h0;
+    g[11] = h1;
+    g[12] = h2;
+    g[13] = h3;
+}
+
 constexpr int kStageThreads = 256;
 
 // Inclusive sum over the block of one int per thread (kStageThreads threads); every
@@ -378,6 +412,30 @@ int comet_stage_grids(const double *transverse6, const double *ext6, int32_t n,
     hipLaunchKernelGGL(stage_grid_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                        transverse6, ext6, n, half[0], half[1], half[2], half[3], grids);
     return launched("stage_grid_kernel");
+}
+
+int comet_stage_grids_z(const double *transverse6, const double *ext6, int32_t n,
+                        const double half[4], int32_t n_z, double z_half, double *grids,
+                        void *stream)
+{
+    clear_error();
+    if (!transverse6 || !ext6 || !half || !grids)
+        return fail(COMET_EINVAL, "comet_stage_grids_z: NULL pointer");
+    if (n < 1 || n_z < 1 || (int64_t)n * n_z > ((int64_t)1 << 31) - 1)
+        return fail(COMET_EINVAL, "comet_stage_grids_z: n and n_z must be >= 1");
+    for (int a = 0; a < 4; ++a)
+        if (!(half[a] >= 0.0) || !isfinite(half[a]))
+            return fail(COMET_EINVAL, "comet_stage_grids_z: half[%d] must be finite and >= 0", a);
+    if (!(z_half >= 0.0) || !isfinite(z_half))
+        return fail(COMET_EINVAL, "comet_stage_grids_z: z_half must be finite and >= 0");
+    const int st = check_device();
+    if (st)
+        return st;
+    const int64_t total = (int64_t)n * n_z;
+    hipLaunchKernelGGL(stage_grid_z_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, transverse6, ext6, n, half[0], half[1], half[2],
+                       half[3], n_z, z_half, grids);
+    return launched("stage_grid_z_kernel");
 }
 
 size_t comet_exclude_workspace_bytes(int32_t n_events)

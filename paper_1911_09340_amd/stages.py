@@ -8,6 +8,10 @@ prior of the last turn) and, later, the previous stage's chosen seed extrapolate
 backwards by one turn (comet_backward_seeds). Per stage, on the device:
   comet_stage_grids -> comet_batch_scan_active (scan, re-scans, classification of the
      events still active; the others are skipped)
+  [with n_z > 1, the seed's z as a fifth axis (Sec. 3.1: five degrees of freedom):
+     comet_stage_grids_z (n_z values of z over ext z +- z_half) -> one scan of all n_z
+     grids -> comet_sparse_select (the lowest RSS of the n_z grids, the grid re-centred
+     on it, z kept) -> comet_batch_scan_active from that grid with n_refine - 1 re-scans]
   [-> with fit_iters > 0: comet_lm_refine from the chosen seed (the fitted track) and
      comet_self_refine (classified hits re-tested with lambda at the fitted track, wires
      left without one re-admit their closest hit below eta)]
@@ -53,9 +57,13 @@ class StagePacked:
 class StageRunner:
     def __init__(self, events, scan_cfg: synth.ScanConfig, max_stages: int = 5,
                  min_wires: int = 30, max_back_steps: int = 4000, fit_iters: int = 0,
-                 eta: float = 0.3, mu0: float = 1e-3, device="cuda"):
+                 eta: float = 0.3, mu0: float = 1e-3, device="cuda", n_z: int = 1,
+                 z_half: float = 0.0):
         self.events = list(events)
         self.sc = scan_cfg
+        self.n_z, self.z_half = int(n_z), float(z_half)
+        if self.n_z > 1 and scan_cfg.n_refine < 1:
+            raise ValueError("a z axis needs at least one re-scan (n_refine >= 1)")
         self.max_stages, self.min_wires = int(max_stages), int(min_wires)
         self.max_back_steps = int(max_back_steps)
         self.fit_iters, self.eta, self.mu0 = int(fit_iters), float(eta), float(mu0)
@@ -99,6 +107,17 @@ class StageRunner:
             self.fit_soa = torch.empty(6, E, **f64)
             self.fit_rss = torch.empty(E, **f64)
             self.lm_ws = comet.lm_workspace(E, device)
+        if self.n_z > 1:
+            Z = self.n_z
+            self.part_event_z = torch.arange(E, dtype=torch.int32,
+                                             device=device).repeat_interleave(Z)
+            self.grids_z = torch.empty(E, Z, 14, **f64)
+            self.rss_z = torch.empty(E * Z, S, **f64)
+            self.best_z = torch.empty(E * Z, dtype=torch.int64, device=device)
+            self.ref_z = torch.empty(E, 1, dtype=torch.int64, device=device)
+            self.grids_ref = torch.empty(E, 1, 14, **f64)
+            self.workspace_z = comet.batch_workspace(int(self.packed0.wire_ends.shape[0]),
+                                                     scan_cfg.n_steps, E * Z, device)
 
     def run(self) -> None:
         self.stage_of_hit.fill_(-1)
@@ -107,12 +126,29 @@ class StageRunner:
             src = self.packed0 if s == 0 else self.bufs[(s - 1) % 2]
             dst = self.bufs[s % 2]
             ext = self.transverse[0] if s == 0 else self.ext
-            comet.stage_grids(self.transverse[s], ext, self.sc.half, self.grids)
-            comet.batch_scan(src, self.part_event, self.grids, self.sc.n, self.cfg,
-                             self.sc.n_refine, self.rss, self.best[s], self.workspace,
-                             best_seed=self.seeds[s], best_rss=self.best_rss[s],
-                             hit_mask=self.mask, n_borderline=self.n_border,
-                             event_active=self.active)
+            if self.n_z > 1:
+                # the z sub-grids: one scan of all, the lowest RSS over each event's grids
+                # (lowest sub-grid and seed index on ties), its grid re-centred on it
+                comet.stage_grids_z(self.transverse[s], ext, self.sc.half, self.n_z,
+                                    self.z_half, self.grids_z)
+                comet.batch_scan(src, self.part_event_z, self.grids_z.view(-1, 14), self.sc.n,
+                                 self.cfg, 0, self.rss_z, self.best_z, self.workspace_z,
+                                 event_active=self.active)
+                comet.sparse_select(self.grids_z, self.rss_z.view(self.n_events, self.n_z, -1),
+                                    self.sc.n, 1, self.ref_z, self.grids_ref)
+                comet.batch_scan(src, self.part_event, self.grids, self.sc.n, self.cfg,
+                                 self.sc.n_refine - 1, self.rss, self.best[s], self.workspace,
+                                 best_seed=self.seeds[s], best_rss=self.best_rss[s],
+                                 hit_mask=self.mask, n_borderline=self.n_border,
+                                 grids_init=self.grids_ref.view(-1, 14),
+                                 event_active=self.active)
+            else:
+                comet.stage_grids(self.transverse[s], ext, self.sc.half, self.grids)
+                comet.batch_scan(src, self.part_event, self.grids, self.sc.n, self.cfg,
+                                 self.sc.n_refine, self.rss, self.best[s], self.workspace,
+                                 best_seed=self.seeds[s], best_rss=self.best_rss[s],
+                                 hit_mask=self.mask, n_borderline=self.n_border,
+                                 event_active=self.active)
             if self.fit_iters > 0:
                 self.fit_soa.copy_(self.seeds[s].t())
                 comet.lm_refine(self.fit_soa, self.cfg, src.wire_ends, src.wire_offsets,

@@ -661,6 +661,25 @@ def pin_stage_grid(o):
                           0.5, 1.5, 0.01, 0.02]
 
 
+def pin_stage_grids_z(o):
+    """The seed's z axis (Sec. 3.1): n_z sub-grids whose reference z runs evenly over
+    ext_z +- z_half with both ends included (the rule of the grid's axes); everything
+    else is the stage grid; one point sits at ext_z."""
+    tr = np.array([300.0, -400.0, 11.0, 60.0, 45.0, 9.0])
+    ext = np.array([1.0, 2.0, -125.5, 4.0, 5.0, 17.25])
+    half = np.array([4.0, 3.0, 0.02, 0.03])
+    base = o.stage_grid(tr, ext, half)
+    for n_z, zh in [(1, 7.0), (2, 8.0), (5, 10.0), (4, 0.0)]:
+        g = o.stage_grids_z(tr, ext, half, n_z, zh)
+        for u in range(n_z):
+            want = ext[2] if n_z == 1 else ext[2] - zh + 2.0 * zh * u / (n_z - 1)
+            assert abs(g[u, 2] - want) <= 1e-12 * max(1.0, abs(want)), (n_z, u)
+            rest = np.delete(np.arange(14), 2)
+            assert np.array_equal(g[u, rest], base[rest]), (n_z, u)
+        if n_z == 5:
+            assert g[2, 2] == ext[2] and g[0, 2] < g[1, 2] < g[2, 2] < g[3, 2] < g[4, 2]
+
+
 def pin_exclude_hits(o):
     """Wires with 2, 1, 3 hits; dropping hit 0, both hits of wire 1 (hit 2) and hit 4
     leaves wires 0 (hit 1) and 2 (hits 3, 5), in order."""
@@ -733,7 +752,7 @@ def pin_self_refine_at_scan_seed(o):
     assert (mask & 1).any() and np.array_equal(out, mask & 1) and n == int((mask & 1).sum())
 
 
-ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_exclude_hits,
+ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_stage_grids_z, pin_exclude_hits,
                    pin_self_refine_hand, pin_self_refine_at_scan_seed])
 
 

@@ -62,6 +62,20 @@ def test_stage_grids_match_cpu(orc):
         assert np.array_equal(got[i], orc.stage_grid(tr[i], ex[i], half)), i
 
 
+@pytest.mark.parametrize("n_z,z_half", [(1, 4.0), (3, 6.0), (5, 10.0), (2, 0.0)])
+def test_stage_grids_z_match_cpu(orc, n_z, z_half):
+    rng = np.random.default_rng(5)
+    tr, ex = rng.normal(0, 100, (7, 6)), rng.normal(0, 100, (7, 6))
+    half = (5.0, 5.0, 0.05, 0.05)
+    g = torch.empty(7, n_z, 14, dtype=torch.float64, device="cuda")
+    comet.stage_grids_z(torch.as_tensor(tr, device="cuda"), torch.as_tensor(ex, device="cuda"),
+                        half, n_z, z_half, g)
+    torch.cuda.synchronize()
+    got = g.cpu().numpy()
+    for i in range(7):
+        assert np.array_equal(got[i], orc.stage_grids_z(tr[i], ex[i], half, n_z, z_half)), i
+
+
 def test_exclude_hits_match_cpu(orc):
     rng = np.random.default_rng(4)
     evs = []
@@ -158,8 +172,22 @@ def _cfg(ev, sc):
     return [ev.bz, ev.charge, sc.step_mm, sc.lambda_mm]
 
 
+def _oracle_scan_z(orc, ev, sc, ext, t, n_z, z_half):
+    """The z-axis scan of one stage: every sub-grid scanned, the lowest RSS over all of
+    them (lowest sub-grid, then seed index, on ties), that grid re-centred on it, then
+    the partition path with the remaining re-scans."""
+    n = np.array(sc.n, np.int32)
+    gz = orc.stage_grids_z(ev.ref_states[t], ext, sc.half, n_z, z_half)
+    rows = [orc.scan(orc.seed_grid(g, n), _cfg(ev, sc), sc.n_steps, ev.wire_ends, ev.wire_offsets,
+                     ev.drift)[0] for g in gz]
+    j = orc.argmin(np.concatenate(rows))
+    u, i = divmod(j, sc.n_seeds)
+    g = orc.refine_grid(gz[u], n, i)
+    return g
+
+
 def _oracle_stages(orc, ev, sc, max_stages, min_wires, max_back, fit_iters=0, eta=0.3,
-                   mu0=1e-3):
+                   mu0=1e-3, n_z=1, z_half=0.0):
     soh = np.full(ev.n_hits, -1, np.int32)
     off, drift, ends = ev.wire_offsets, ev.drift, ev.wire_ends
     ids = np.arange(ev.n_hits)
@@ -170,9 +198,17 @@ def _oracle_stages(orc, ev, sc, max_stages, min_wires, max_back, fit_iters=0, et
         if not active:
             break
         t = ev.n_turns - 1 - s
-        g = orc.stage_grid(ev.ref_states[t], ext, sc.half)
-        r = orc.scan_partition(g, np.array(sc.n, np.int32), _cfg(ev, sc), sc.n_steps,
-                               sc.n_refine, ends, off, drift)
+        if n_z > 1:
+            evs = type("Ev", (), dict(ref_states=ev.ref_states, wire_ends=ends,
+                                      wire_offsets=off, drift=drift, bz=ev.bz,
+                                      charge=ev.charge))
+            g = _oracle_scan_z(orc, evs, sc, ext, t, n_z, z_half)
+            r = orc.scan_partition(g, np.array(sc.n, np.int32), _cfg(ev, sc), sc.n_steps,
+                                   sc.n_refine - 1, ends, off, drift)
+        else:
+            g = orc.stage_grid(ev.ref_states[t], ext, sc.half)
+            r = orc.scan_partition(g, np.array(sc.n, np.int32), _cfg(ev, sc), sc.n_steps,
+                                   sc.n_refine, ends, off, drift)
         mask, fit = r["mask"] & 1, r["best_seed"]
         if fit_iters > 0:
             fit, _, _ = orc.lm_refine(fit, _cfg(ev, sc), sc.n_steps, ends, off, drift,
@@ -245,3 +281,28 @@ def test_stage_loop_with_fit_matches_cpu(orc):
         n_stages += len(per_stage)
         h0 += ev.n_hits
     assert n_stages > len(events) and n_moved > 0
+
+
+def test_stage_loop_with_z_axis_matches_cpu(orc):
+    """The seed's z as a fifth axis in every stage (three sub-grids over +-6 mm): the
+    stage of every hit, every stage's chosen index and seed, bit for bit with the CPU
+    chain (sub-grid scans, lowest RSS over them, re-centred grid, remaining re-scans)."""
+    events = [synth.event_mix(i) for i in (2, 3, 5, 8)]
+    sc = synth.ScanConfig("stages", (3, 4, 5, 6), (5.0, 5.0, 0.05, 0.05), 800, 2.0, 0.8, 1)
+    run = stages.StageRunner(events, sc, max_stages=5, min_wires=30, max_back_steps=3000,
+                             n_z=3, z_half=6.0)
+    run.run()
+    torch.cuda.synchronize()
+    soh = run.stage_of_hit.cpu().numpy()
+    best = run.best.cpu().numpy()
+    seeds = run.seeds.cpu().numpy()
+    h0, n_stages = 0, 0
+    for e, ev in enumerate(events):
+        want, per_stage = _oracle_stages(orc, ev, sc, 5, 30, 3000, n_z=3, z_half=6.0)
+        assert np.array_equal(soh[h0:h0 + ev.n_hits], want), e
+        for s, (b, seed, _) in enumerate(per_stage):
+            assert best[s, e] == b, (e, s)
+            assert np.array_equal(seeds[s, e], seed), (e, s)
+        n_stages += len(per_stage)
+        h0 += ev.n_hits
+    assert n_stages > len(events)

@@ -107,6 +107,10 @@ MUTANTS = {
         ("        oracle_seed(grid, n, best, best_seed);\n        *best_rss = rss[best];",
          "        *best_rss = rss[best];"),
     ],
+    "stage_z_index_reversed": ("        g[2] = oracle_axis_value(ext6[2], z_half, n_z, u);",
+                               "        g[2] = oracle_axis_value(ext6[2], z_half, n_z, n_z - 1 - u);"),
+    "stage_z_from_transverse": ("        g[2] = oracle_axis_value(ext6[2], z_half, n_z, u);",
+                                "        g[2] = oracle_axis_value(transverse6[2], z_half, n_z, u);"),
     "partition_refine_around_index0": ("        if (it > 0)\n            oracle_refine_grid(grid, n, b);\n        oracle_seed_grid(grid, n, seeds);\n        oracle_scan(",
                                        "        if (it > 0)\n            oracle_refine_grid(grid, n, 0);\n        oracle_seed_grid(grid, n, seeds);\n        oracle_scan("),
 }
