@@ -205,11 +205,13 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
  * residuals are differentiable in the six seed components (x, y, z, px, py, pz).
  *
  * comet_rss_adjoint: for every seed, the track is recomputed (the same RK4 steps as
- * comet_extrapolate_seeds, so every D_i and choice equals the forward path's) and
- * a reverse sweep runs from each active wire's chord back through the RK4 steps,
- * recomputing the momenta from checkpoints every 8 steps (nothing is stored per
- * step). A wire is active when its closest hit's residual e_i = D_i - r_j satisfies
- * |e_i| < lambda; its row is J_i = dD_i/d(seed).
+ * comet_extrapolate_seeds, so every D_i and choice equals the forward path's; the
+ * closest point is searched with a distance bound that keeps the first index of the
+ * minimum). The derivatives of the recorded points come in closed form: in a uniform
+ * field the RK4 step is linear in the transverse momentum (a complex factor per
+ * step), so point k is the seed plus a geometric sum of k such factors, taken by
+ * binary powering. A wire is active when its closest hit's residual e_i = D_i - r_j
+ * satisfies |e_i| < lambda; its row is J_i = dD_i/d(seed).
  *   seeds6       device double[6][n_seeds] (SoA)
  *   cfg          host; n_steps <= 2400
  *   wire_ends, wire_offsets, drift: as in comet_dca_rss
@@ -218,8 +220,8 @@ int comet_select_classify(const double *rss, int64_t n_seeds, const double *trac
  *                [event_wires[seed_event[s]], event_wires[seed_event[s]+1]); with
  *                NULL every seed uses all wires
  * Outputs (device, each may be NULL):
- *   rss   double[n_seeds]: Eq. 1 (summed in a fixed tree order: equal to
- *         comet_dca_rss up to rounding, identical run to run)
+ *   rss   double[n_seeds]: Eq. 1, summed in wire order (bit for bit the forward
+ *         path's RSS, comet_dca_rss)
  *   grad  double[n_seeds][6]: d rss / d seed = sum over active wires of 2 e_i J_i
  *   jtj   double[n_seeds][21]: sum over active wires of J_i J_i^T, packed upper
  *         triangle, row-major ((0,0), (0,1), ..., (0,5), (1,1), ...)
@@ -233,8 +235,12 @@ int comet_rss_adjoint(const double *seeds6, int64_t n_seeds, const comet_config 
                       const int32_t *seed_event, double *rss, double *grad, double *jtj,
                       double *jte, double *dca, double *resid, double *jac, void *stream);
 
-/* Bytes of workspace comet_lm_refine needs for n_seeds seeds. */
-size_t comet_lm_workspace_bytes(int64_t n_seeds);
+/* Bytes of workspace comet_lm_refine (and comet_lm_refine_field) needs for n_seeds
+ * seeds with tracks of n_steps RK4 steps (0 if n_seeds < 1 or n_steps is outside
+ * 1..2400). In a uniform field the refinement records every evaluation's tracks, one
+ * seed per lane, into the workspace (24 (n_steps + 1) bytes per seed) before the
+ * adjoint blocks load them. */
+size_t comet_lm_workspace_bytes(int64_t n_seeds, int32_t n_steps);
 
 /* Levenberg-Marquardt refinement of every seed in place, on the device, with a
  * fixed number of iterations (no host synchronisation, so it can be captured in a
@@ -246,7 +252,8 @@ size_t comet_lm_workspace_bytes(int64_t n_seeds);
  *   n_iter     0..1000 iterations; mu0 > 0 initial damping
  *   rss        device double[n_seeds]: RSS at the final seeds
  *   n_accepted device int32[n_seeds] or NULL: accepted steps per seed
- *   workspace  device, >= comet_lm_workspace_bytes(n_seeds), 256-byte aligned
+ *   workspace  device, >= comet_lm_workspace_bytes(n_seeds, cfg->n_steps), 256-byte
+ *              aligned
  * Other arguments as in comet_rss_adjoint. */
 int comet_lm_refine(double *seeds6, int64_t n_seeds, const comet_config *cfg,
                     const double *wire_ends, int32_t n_wires, const int32_t *wire_offsets,

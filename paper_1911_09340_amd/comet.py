@@ -380,7 +380,7 @@ def _bind_derivatives(lib):
     lib.comet_rss_adjoint.argtypes = [_vp, _i64, ctypes.POINTER(Config), _vp, _i32, _vp, _vp, _i32,
                                       _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.comet_rss_adjoint.restype = ctypes.c_int
-    lib.comet_lm_workspace_bytes.argtypes = [_i64]
+    lib.comet_lm_workspace_bytes.argtypes = [_i64, _i32]
     lib.comet_lm_workspace_bytes.restype = ctypes.c_size_t
     lib.comet_lm_refine.argtypes = [_vp, _i64, ctypes.POINTER(Config), _vp, _i32, _vp, _vp, _i32,
                                     _vp, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
@@ -429,8 +429,8 @@ def rss_adjoint(seeds: torch.Tensor, cfg: Config, wire_ends: torch.Tensor,
         _ptr(jac, torch.float64, "jac", (S, n_w, 6), optional=True), _stream()), name)
 
 
-def lm_workspace(n_seeds: int, device=None) -> torch.Tensor:
-    nbytes = int(_bind_derivatives(load()).comet_lm_workspace_bytes(int(n_seeds)))
+def lm_workspace(n_seeds: int, n_steps: int, device=None) -> torch.Tensor:
+    nbytes = int(_bind_derivatives(load()).comet_lm_workspace_bytes(int(n_seeds), int(n_steps)))
     return torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=device or "cuda")
 
 

@@ -1,6 +1,5 @@
 // adjoint.hip -- derivatives of the seed scan's RSS with respect to the six seed
-// components, by a hand-written reverse sweep through the RK4 steps and the active
-// DCA chord, and the Levenberg-Marquardt refinement they drive.
+// components, and the Levenberg-Marquardt refinement they drive.
 //
 // Paper: Yeo, Lee and Kuno, "GPU-accelerated event reconstruction for the COMET
 // Phase-I experiment" (arXiv:1911.09340). Eq. 1 defines the RSS; Sec. 2.1 notes that
@@ -9,13 +8,19 @@
 // and the capped residuals are differentiable, and Gauss-Newton steps on the active
 // residuals (|D_i - r_j| < lambda) refine a coarse grid's best seed.
 //
-// One block per seed, one thread per wire. Thread 0 recomputes the seed's track (the
-// same cdev::rk4_step as the forward path, so every D_i, closest index and hit choice
-// equals the forward path's) into LDS, with the momentum checkpointed every 8 steps.
-// Each wire thread finds its closest point and winning chord exactly as the forward
-// contract does, then runs the reverse sweep from that chord's far end back to the
-// seed, recomputing each 8-step segment's momenta from its checkpoint (RK4 is
-// recomputed, never stored per step).
+// Uniform field: one block per seed. Thread 0 records the seed's track into LDS with
+// the forward path's cdev::rk4_step, so every D_i, closest index and hit choice equals
+// the forward path's. The block then takes the radius of every 16-point window of the
+// track, and each wire thread finds its closest point with the forward contract's
+// first-index rule, scanning only the windows that a distance bound cannot rule out.
+// The derivatives of the recorded points come in closed form: in a uniform B_z the
+// RK4 step is linear in the transverse momentum, p_(k+1) = m p_k and
+// x_(k+1) = x_k + h inv sigma p_k with complex m and sigma (polynomials in -i h c), so
+// x_k = x_0 + h inv sigma G_k p_0 with G_k the geometric sum of m^j, j < k. m^k, G_k and
+// dG_k/dm follow by binary powering (O(log k) complex products per active wire), and
+// the chain through inv = 1/|p|, c = kappa q B inv and v_z = p_z inv gives the row.
+// (The derivatives of the discrete map, as the step-by-step dual numbers of the CPU
+// reference give them, up to rounding.)
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -31,8 +36,9 @@ namespace {
 using namespace cdev;
 using namespace chost;
 
-constexpr int kAdjThreads = 256;
-constexpr int kCheckEvery = 8;
+constexpr int kAdjThreads = 256;     // field-map kernel
+constexpr int kUniThreads = 64;      // uniform-field kernel (one wave)
+constexpr int kWindow = 16;  // points per window of the distance bound
 constexpr int kTri = 21;  // packed upper triangle of a symmetric 6x6 matrix
 
 // Index of (r, c), r <= c, in the packed row-major upper triangle.
@@ -65,25 +71,72 @@ __device__ __forceinline__ double chord_distance2_t(double axi, double aeta, dou
     return fma(pxi, pxi, peta * peta);
 }
 
+// The radius of every kWindow-point window of a recorded track in LDS: the largest
+// distance of the window's points from its first point (NaN points are passed over;
+// they never become a closest point). One thread per window.
+__device__ __forceinline__ void window_radii(const double *lx, const double *ly,
+                                             const double *lz, int P, double *rho)
+{
+    const int n_win = (P + kWindow - 1) / kWindow;
+    for (int c = threadIdx.x; c < n_win; c += blockDim.x) {
+        const int k0 = c * kWindow, k1 = min(P, k0 + kWindow);
+        double r2 = 0.0;
+        for (int k = k0 + 1; k < k1; ++k) {
+            const double dx = lx[k] - lx[k0], dy = ly[k] - ly[k0], dz = lz[k] - lz[k0];
+            const double v = fma(dx, dx, fma(dy, dy, dz * dz));
+            r2 = v > r2 ? v : r2;
+        }
+        rho[c] = sqrt(r2);
+    }
+}
+
 // A wire's DCA to the recorded track (lx, ly, lz; P points) as the forward contract
 // takes it: the closest recorded point (first index of the minimum), then the winning
 // refinement, the vertex or the interior of an adjacent chord. Returns D; the chord
 // starts at point ka with parameter t (0 at the vertex), closest point (pxi, peta) in
 // the wire's frame.
+//
+// The closest point is searched window by window. Every point of window c lies within
+// rho[c] of its first point, so its distance to the wire is at least that point's
+// minus rho[c]; a window is skipped when this lower bound exceeds the best distance
+// known so far (the smallest over every window's first point, then the running
+// minimum) by a relative 1e-9 and 1e-9 mm, far above the rounding of q and rho. A
+// skipped window holds no point at or below the final minimum, so the first index of
+// the minimum is the full scan's; NaN or infinite values never skip.
 __device__ __forceinline__ double closest_chord(const double *lx, const double *ly,
-                                                const double *lz, int P, const double (&f)[8],
-                                                int &ka, double &t, double &pxi, double &peta)
+                                                const double *lz, const double *rho, int P,
+                                                const double (&f)[8], int &ka, double &t,
+                                                double &pxi, double &peta)
 {
-    int kb = 0;
-    double qb = INFINITY;
-    for (int k = 0; k < P; ++k) {
+    const int n_win = (P + kWindow - 1) / kWindow;
+    double ub = INFINITY;
+    for (int c = 0; c < n_win; ++c) {
+        const int k = c * kWindow;
         double xi, eta;
         project(f, lx[k], ly[k], lz[k], xi, eta);
         const double q = fma(xi, xi, eta * eta);
-        if (q < qb) {
-            qb = q;
-            kb = k;
+        ub = q < ub ? q : ub;
+    }
+    double bound = sqrt(ub);
+    int kb = 0;
+    double qb = INFINITY;
+    for (int c = 0; c < n_win; ++c) {
+        const int k0 = c * kWindow, k1 = min(P, k0 + kWindow);
+        double xi, eta;
+        project(f, lx[k0], ly[k0], lz[k0], xi, eta);
+        const double d0 = sqrt(fma(xi, xi, eta * eta));
+        if (d0 > (rho[c] + bound) * (1.0 + 1e-9) + 1e-9)
+            continue;
+        for (int k = k0; k < k1; ++k) {
+            project(f, lx[k], ly[k], lz[k], xi, eta);
+            const double q = fma(xi, xi, eta * eta);
+            if (q < qb) {
+                qb = q;
+                kb = k;
+            }
         }
+        const double sb = sqrt(qb);
+        bound = sb < bound ? sb : bound;
     }
     double cxi, ceta;
     project(f, lx[kb], ly[kb], lz[kb], cxi, ceta);
@@ -121,69 +174,66 @@ __device__ __forceinline__ double closest_chord(const double *lx, const double *
     return sqrt(d2);
 }
 
-// Reverse sweep of one RK4 step (cdev::rk4_step) at start momentum (px, py): maps the
-// adjoint of the step's output momentum (pxb, pyb) and position (xb, yb, zb) to the
-// adjoint of its input, accumulating the adjoints of inv, c and vz. Positions enter
-// the step linearly with unit Jacobian, so their adjoint passes through unchanged.
-__device__ __forceinline__ void rk4_step_adjoint(const StepConsts &k, double px, double py,
-                                                 double xb, double yb, double zb, double &pxb,
-                                                 double &pyb, double &invb, double &cb,
-                                                 double &vzb)
+// Complex numbers for the uniform-field step: a transverse vector (x, y) is x + i y,
+// and the magnetic rotation (p_x, p_y) -> c (p_y, -p_x) is multiplication by -i c.
+struct Cx {
+    double re, im;
+};
+__device__ __forceinline__ Cx cmul(Cx a, Cx b)
 {
-    const double c = k.c, inv = k.inv, h = k.h, hh = k.hh, h6 = k.h6;
-    // forward stage values
-    const double f1x = c * py, f1y = -(c * px);
-    const double q2x = px + hh * f1x, q2y = py + hh * f1y;
-    const double f2x = c * q2y, f2y = -(c * q2x);
-    const double q3x = px + hh * f2x, q3y = py + hh * f2y;
-    const double f3x = c * q3y, f3y = -(c * q3x);
-    const double q4x = px + h * f3x, q4y = py + h * f3y;
-    // output adjoints spread over the stages (weights 1, 2, 2, 1 times h/6)
-    const double v1bx = h6 * xb, v1by = h6 * yb;
-    const double v2bx = 2.0 * v1bx, v2by = 2.0 * v1by;
-    double f1bx = h6 * pxb, f1by = h6 * pyb;
-    double f2bx = 2.0 * f1bx, f2by = 2.0 * f1by;
-    double f3bx = f2bx, f3by = f2by;
-    const double f4bx = f1bx, f4by = f1by;
-    vzb += 6.0 * h6 * zb;
-    double pnx = pxb, pny = pyb;
-    // stage 4: v4 = q4 inv, f4 = c (q4y, -q4x)
-    {
-        const double qbx = v1bx * inv + c * (-f4by), qby = v1by * inv + c * f4bx;
-        invb += v1bx * q4x + v1by * q4y;
-        cb += f4bx * q4y - f4by * q4x;
-        pnx += qbx;
-        pny += qby;
-        f3bx += h * qbx;
-        f3by += h * qby;
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ Cx cadd(Cx a, Cx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ Cx cscale(double s, Cx a) { return {s * a.re, s * a.im}; }
+
+// For n steps of p -> m p: A = m^n, D = dA/dm, G = sum_(j<n) m^j, H = dG/dm.
+struct Geo {
+    Cx A, D, G, H;
+};
+// n1 steps then n2 steps (the sums are symmetric in the order).
+__device__ __forceinline__ Geo geo_join(const Geo &x, const Geo &y)
+{
+    return {cmul(x.A, y.A), cadd(cmul(x.D, y.A), cmul(x.A, y.D)), cadd(x.G, cmul(x.A, y.G)),
+            cadd(cadd(x.H, cmul(x.D, y.G)), cmul(x.A, y.H))};
+}
+__device__ __forceinline__ Geo geo_one(Cx m) { return {m, {1.0, 0.0}, {1.0, 0.0}, {0.0, 0.0}}; }
+// n >= 0 steps, by binary powering.
+__device__ __forceinline__ Geo geo_pow(Cx m, int n)
+{
+    Geo r{{1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    Geo b = geo_one(m);
+    while (n > 0) {
+        if (n & 1)
+            r = geo_join(r, b);
+        n >>= 1;
+        if (n > 0)
+            b = geo_join(b, b);
     }
-    // stage 3
-    {
-        const double qbx = v2bx * inv + c * (-f3by), qby = v2by * inv + c * f3bx;
-        invb += v2bx * q3x + v2by * q3y;
-        cb += f3bx * q3y - f3by * q3x;
-        pnx += qbx;
-        pny += qby;
-        f2bx += hh * qbx;
-        f2by += hh * qby;
-    }
-    // stage 2
-    {
-        const double qbx = v2bx * inv + c * (-f2by), qby = v2by * inv + c * f2bx;
-        invb += v2bx * q2x + v2by * q2y;
-        cb += f2bx * q2y - f2by * q2x;
-        pnx += qbx;
-        pny += qby;
-        f1bx += hh * qbx;
-        f1by += hh * qby;
-    }
-    // stage 1: v1 = p inv, f1 = c (py, -px)
-    pnx += v1bx * inv + c * (-f1by);
-    pny += v1by * inv + c * f1bx;
-    invb += v1bx * px + v1by * py;
-    cb += f1bx * py - f1by * px;
-    pxb = pnx;
-    pyb = pny;
+    return r;
+}
+
+// Per-seed constants of the closed-form derivatives: with w = -i h c,
+//   m = 1 + w + w^2/2 + w^3/6 + w^4/24   (p_(k+1) = m p_k),
+//   sigma = 1 + w/2 + w^2/6 + w^3/24     (x_(k+1) = x_k + h inv sigma p_k),
+// and their derivatives with respect to c (dw/dc = -i h).
+struct StepPoly {
+    Cx m, sigma, dm_dc, dsigma_dc;
+};
+__device__ __forceinline__ StepPoly step_poly(double h, double c)
+{
+    const Cx w{0.0, -(h * c)};
+    const Cx w2 = cmul(w, w), w3 = cmul(w2, w), w4 = cmul(w3, w);
+    const Cx dw{0.0, -h};
+    StepPoly sp;
+    sp.m = cadd(cadd(cadd(Cx{1.0, 0.0}, w), cadd(cscale(0.5, w2), cscale(1.0 / 6.0, w3))),
+                cscale(1.0 / 24.0, w4));
+    sp.sigma = cadd(cadd(Cx{1.0, 0.0}, cscale(0.5, w)),
+                    cadd(cscale(1.0 / 6.0, w2), cscale(1.0 / 24.0, w3)));
+    const Cx dm = cadd(cadd(Cx{1.0, 0.0}, w), cadd(cscale(0.5, w2), cscale(1.0 / 6.0, w3)));
+    const Cx ds = cadd(cadd(Cx{0.5, 0.0}, cscale(1.0 / 3.0, w)), cscale(0.125, w2));
+    sp.dm_dc = cmul(dm, dw);
+    sp.dsigma_dc = cmul(ds, dw);
+    return sp;
 }
 
 // Block reduction of NV doubles per thread into thread 0 (fixed order).
@@ -226,17 +276,45 @@ struct AdjArgs {
     const int32_t *seed_event;
     double *rss, *grad, *A, *b;
     double *D, *resid, *J;  // indexed by global wire: [S][n_w_total]
+    const double *tracks;   // uniform field: recorded tracks [S][3][K + 1], or NULL
 };
 
-__global__ __launch_bounds__(kAdjThreads) void rss_adjoint_kernel(AdjArgs a)
+// One seed per lane: every seed's track with the forward path's cdev::rk4_step, each
+// seed's points contiguous ([S][3][K + 1]) so that an adjoint block loads its seed's
+// track whole. The store of point k writes one double of 64 rows per wave; the rows'
+// cache lines fill over consecutive points and stay in L2 until they are whole.
+__global__ __launch_bounds__(64) void adj_record_kernel(const double *__restrict__ seeds,
+                                                        int64_t S, double bz, double charge,
+                                                        double h, int K,
+                                                        double *__restrict__ tracks)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S)
+        return;
+    double x = seeds[0 * S + s], y = seeds[1 * S + s], z = seeds[2 * S + s];
+    double px = seeds[3 * S + s], py = seeds[4 * S + s];
+    const StepConsts kc = step_consts(px, py, seeds[5 * S + s], bz, charge, h);
+    const int P = K + 1;
+    double *tx = tracks + (size_t)s * 3 * P, *ty = tx + P, *tz = ty + P;
+    for (int j = 0; j < K; ++j) {
+        tx[j] = x;
+        ty[j] = y;
+        tz[j] = z;
+        rk4_step(kc, x, y, z, px, py);
+    }
+    tx[K] = x;
+    ty[K] = y;
+    tz[K] = z;
+}
+
+__global__ __launch_bounds__(kUniThreads) void rss_adjoint_kernel(AdjArgs a)
 {
     extern __shared__ double lds[];
     const int64_t s = blockIdx.x;
     const int P = a.K + 1;
     double *lx = lds, *ly = lds + P, *lz = lds + 2 * P;
-    double *ck = lds + 3 * P;                        // checkpoints: (px, py) pairs
-    const int n_ck = a.K / kCheckEvery + 1;
-    double *scratch = ck + 2 * n_ck;                 // reductions
+    double *rho = lds + 3 * P;                             // window radii
+    double *wbuf = rho + (P + kWindow - 1) / kWindow;      // [kUniThreads][8] per wire
 
     const int e = a.seed_event ? a.seed_event[s] : 0;
     const int w0 = a.ev_wires ? a.ev_wires[e] : 0;
@@ -247,132 +325,140 @@ __global__ __launch_bounds__(kAdjThreads) void rss_adjoint_kernel(AdjArgs a)
     const double spz = a.seeds[5 * a.S + s];
     const StepConsts kc = step_consts(spx, spy, spz, a.bz, a.charge, a.h);
 
-    if (threadIdx.x == 0) {
+    if (a.tracks) {  // recorded by adj_record_kernel: load it whole
+        const double *src = a.tracks + (size_t)s * 3 * P;
+        for (int i = threadIdx.x; i < 3 * P; i += kUniThreads)
+            lds[i] = src[i];
+    } else if (threadIdx.x == 0) {
         double x = sx, y = sy, z = sz, px = spx, py = spy;
         for (int j = 0; j < a.K; ++j) {
             lx[j] = x;
             ly[j] = y;
             lz[j] = z;
-            if (j % kCheckEvery == 0) {
-                ck[2 * (j / kCheckEvery)] = px;
-                ck[2 * (j / kCheckEvery) + 1] = py;
-            }
             rk4_step(kc, x, y, z, px, py);
         }
         lx[a.K] = x;
         ly[a.K] = y;
         lz[a.K] = z;
-        if (a.K % kCheckEvery == 0) {
-            ck[2 * (a.K / kCheckEvery)] = px;
-            ck[2 * (a.K / kCheckEvery) + 1] = py;
-        }
     }
     __syncthreads();
+    window_radii(lx, ly, lz, P, rho);
+    __syncthreads();
 
-    // per-thread partial sums: rss, grad[6], A[21], b[6]
-    double acc[1 + 6 + kTri + 6];
-    for (int i = 0; i < 1 + 6 + kTri + 6; ++i)
-        acc[i] = 0.0;
+    // chain from the step's constants to the seed: inv = 1/|p|, c = (kappa q B) inv,
+    // v_z = p_z inv; d inv / d p_j = -p_j inv^3
+    const StepPoly sp = step_poly(a.h, kc.c);
+    const double kqb = (kKappa * a.charge) * a.bz;
+    const double inv3 = (kc.inv * kc.inv) * kc.inv;
+    const Cx p0c{spx, spy};
 
-    for (int wi = w0 + threadIdx.x; wi < w1; wi += kAdjThreads) {
-        double f[8];
-        wire_frame(a.ends + 6 * (int64_t)wi, f);
-        double t, pxi, peta;
-        int ka;
-        const double D = closest_chord(lx, ly, lz, P, f, ka, t, pxi, peta);
-        // closest hit and Eq. 1's capped residual
-        double eb = INFINITY, res = NAN;
-        for (int j = a.offsets[wi]; j < a.offsets[wi + 1]; ++j) {
-            const double r = D - a.drift[j];
-            if (fabs(r) < eb) {
-                eb = fabs(r);
-                res = r;
-            }
-        }
-        const bool active = eb < a.lambda;
-        const double d = active ? eb : a.lambda;
-        acc[0] += d * d;
-        const int64_t ow = s * (int64_t)a.n_w_total + wi;
-        if (a.D)
-            a.D[ow] = D;
-        if (a.resid)
-            a.resid[ow] = res;
-        double row[6] = {0, 0, 0, 0, 0, 0};
-        if (active && D > 0.0) {
-            // dD/dP at the closest point, spread over the chord's two ends
-            const double nx = (pxi * f[0] + peta * f[4]) / D;
-            const double ny = (pxi * f[1] + peta * f[5]) / D;
-            const double nz = (pxi * f[2] + peta * f[6]) / D;
-            const int kend = t > 0.0 ? ka + 1 : ka;  // farthest point with a cotangent
-            double xb = (kend == ka ? 1.0 - t : t) * nx;
-            double yb = (kend == ka ? 1.0 - t : t) * ny;
-            double zb = (kend == ka ? 1.0 - t : t) * nz;
-            double pxb = 0.0, pyb = 0.0, invb = 0.0, cb = 0.0, vzb = 0.0;
-            // reverse over segments [g * 8, g * 8 + 8) from the one holding kend - 1
-            for (int g = (kend - 1) / kCheckEvery; kend > 0 && g >= 0; --g) {
-                const int k0 = g * kCheckEvery;
-                double mpx[kCheckEvery], mpy[kCheckEvery];
-                {
-                    double x = 0.0, y = 0.0, z = 0.0, px = ck[2 * g], py = ck[2 * g + 1];
-#pragma unroll
-                    for (int j = 0; j < kCheckEvery; ++j) {
-                        mpx[j] = px;
-                        mpy[j] = py;
-                        rk4_step(kc, x, y, z, px, py);
-                    }
+    // The sums run in wire order, one quantity per thread (q < 34: rss, grad[6], the
+    // packed A[21], b[6]): each round of up to kUniThreads wires leaves every wire's
+    // d^2, row and residual in LDS, then the quantity threads add them up. The RSS is
+    // thus summed in the forward path's order.
+    const int q = threadIdx.x;
+    double acc = 0.0;
+    int qr = 0, qc = 0;  // row and column of A's entry for 7 <= q < 28
+    if (q >= 7 && q < 7 + kTri)
+        for (int r = 0, i = 0; r < 6; ++r)
+            for (int c2 = r; c2 < 6; ++c2, ++i)
+                if (i == q - 7) {
+                    qr = r;
+                    qc = c2;
                 }
-#pragma unroll
-                for (int j = kCheckEvery - 1; j >= 0; --j) {
-                    const int k = k0 + j;  // step k maps point k to point k + 1
-                    if (k < kend) {
-                        rk4_step_adjoint(kc, mpx[j], mpy[j], xb, yb, zb, pxb, pyb, invb, cb,
-                                         vzb);
-                        if (k == ka && kend != ka) {
-                            xb += (1.0 - t) * nx;
-                            yb += (1.0 - t) * ny;
-                            zb += (1.0 - t) * nz;
-                        }
-                    }
+    for (int base = w0; base < w1; base += kUniThreads) {
+        const int wi = base + threadIdx.x;
+        double d2 = 0.0, res_a = 0.0, row[6] = {0, 0, 0, 0, 0, 0};
+        if (wi < w1) {
+            double f[8];
+            wire_frame(a.ends + 6 * (int64_t)wi, f);
+            double t, pxi, peta;
+            int ka;
+            const double D = closest_chord(lx, ly, lz, rho, P, f, ka, t, pxi, peta);
+            // closest hit and Eq. 1's capped residual
+            double eb = INFINITY, res = NAN;
+            for (int j = a.offsets[wi]; j < a.offsets[wi + 1]; ++j) {
+                const double r = D - a.drift[j];
+                if (fabs(r) < eb) {
+                    eb = fabs(r);
+                    res = r;
                 }
             }
-            // constants: vz = pz inv, c = ((kappa q) B) inv, inv = 1 / |p|
-            double gpz = vzb * kc.inv;
-            invb += vzb * spz;
-            invb += cb * ((kKappa * a.charge) * a.bz);
-            const double p0b = -invb * kc.inv * kc.inv;
-            const double p0 = 1.0 / kc.inv;
-            row[0] = xb;
-            row[1] = yb;
-            row[2] = zb;
-            row[3] = pxb + p0b * spx / p0;
-            row[4] = pyb + p0b * spy / p0;
-            row[5] = gpz + p0b * spz / p0;
-            for (int r = 0; r < 6; ++r) {
-                acc[1 + r] += 2.0 * res * row[r];
-                acc[1 + 6 + kTri + r] += row[r] * res;
-                for (int c2 = r; c2 < 6; ++c2)
-                    acc[1 + 6 + tri(r, c2)] += row[r] * row[c2];
+            const bool active = eb < a.lambda;
+            const double d = active ? eb : a.lambda;
+            d2 = d * d;
+            const int64_t ow = s * (int64_t)a.n_w_total + wi;
+            if (a.D)
+                a.D[ow] = D;
+            if (a.resid)
+                a.resid[ow] = res;
+            if (active && D > 0.0) {
+                res_a = res;
+                // dD/dP at the closest point (unit normal from the wire)
+                const double nx = (pxi * f[0] + peta * f[4]) / D;
+                const double ny = (pxi * f[1] + peta * f[5]) / D;
+                const double nz = (pxi * f[2] + peta * f[6]) / D;
+                // G and dG/dm at the chord's ends, weighted (1 - t, t)
+                const Geo g0 = geo_pow(sp.m, ka);
+                const Geo g1 = geo_join(g0, geo_one(sp.m));
+                const Cx G = cadd(cscale(1.0 - t, g0.G), cscale(t, g1.G));
+                const Cx H = cadd(cscale(1.0 - t, g0.H), cscale(t, g1.H));
+                // d(x + i y)/d(p_x0) at fixed c and inv; d/d(p_y0) is i times it
+                const Cx sG = cmul(sp.sigma, G);
+                const Cx t_p = cscale(a.h * kc.inv, sG);
+                // d(x + i y)/dc and d(x + i y)/d inv
+                const Cx t_c = cscale(
+                    a.h * kc.inv,
+                    cmul(cadd(cmul(sp.dsigma_dc, G), cmul(sp.sigma, cmul(H, sp.dm_dc))), p0c));
+                const Cx t_inv = cscale(a.h, cmul(sG, p0c));
+                const double t_vz = ((double)ka + t) * a.h;  // z_k = z_0 + k h v_z
+                const double d_px = t_p.re * nx + t_p.im * ny;
+                const double d_py = -t_p.im * nx + t_p.re * ny;
+                const double d_c = t_c.re * nx + t_c.im * ny;
+                const double d_inv = t_inv.re * nx + t_inv.im * ny;
+                const double d_vz = t_vz * nz;
+                const double via_inv = (d_inv + kqb * d_c) + spz * d_vz;  // per unit d inv
+                row[0] = nx;
+                row[1] = ny;
+                row[2] = nz;
+                row[3] = d_px - via_inv * (spx * inv3);
+                row[4] = d_py - via_inv * (spy * inv3);
+                row[5] = d_vz * kc.inv - via_inv * (spz * inv3);
             }
+            if (a.J)
+                for (int r = 0; r < 6; ++r)
+                    a.J[ow * 6 + r] = row[r];
         }
-        if (a.J)
-            for (int r = 0; r < 6; ++r)
-                a.J[ow * 6 + r] = row[r];
+        double *wb = wbuf + 8 * threadIdx.x;
+        wb[0] = d2;
+        wb[7] = res_a;
+        for (int r = 0; r < 6; ++r)
+            wb[1 + r] = row[r];
+        __syncthreads();
+        const int n = min(kUniThreads, w1 - base);
+        if (q == 0) {
+            for (int j = 0; j < n; ++j)
+                acc += wbuf[8 * j];
+        } else if (q < 7) {
+            for (int j = 0; j < n; ++j)
+                acc += 2.0 * wbuf[8 * j + 7] * wbuf[8 * j + q];
+        } else if (q < 7 + kTri) {
+            for (int j = 0; j < n; ++j)
+                acc += wbuf[8 * j + 1 + qr] * wbuf[8 * j + 1 + qc];
+        } else if (q < 7 + kTri + 6) {
+            for (int j = 0; j < n; ++j)
+                acc += wbuf[8 * j + 1 + (q - 7 - kTri)] * wbuf[8 * j + 7];
+        }
+        __syncthreads();
     }
-
-    block_sum(acc, scratch);
-    if (threadIdx.x == 0) {
-        if (a.rss)
-            a.rss[s] = acc[0];
-        if (a.grad)
-            for (int r = 0; r < 6; ++r)
-                a.grad[s * 6 + r] = acc[1 + r];
-        if (a.A)
-            for (int r = 0; r < kTri; ++r)
-                a.A[s * kTri + r] = acc[1 + 6 + r];
-        if (a.b)
-            for (int r = 0; r < 6; ++r)
-                a.b[s * 6 + r] = acc[1 + 6 + kTri + r];
-    }
+    if (q == 0 && a.rss)
+        a.rss[s] = acc;
+    else if (q >= 1 && q < 7 && a.grad)
+        a.grad[s * 6 + (q - 1)] = acc;
+    else if (q >= 7 && q < 7 + kTri && a.A)
+        a.A[s * kTri + (q - 7)] = acc;
+    else if (q >= 7 + kTri && q < 7 + kTri + 6 && a.b)
+        a.b[s * 6 + (q - 7 - kTri)] = acc;
 }
 
 // ------------------------------------------------------------------ field map
@@ -394,7 +480,9 @@ constexpr int kMaxFieldWires = kAdjThreads * kFieldWiresPerThread;
 
 __host__ __device__ constexpr int field_region(int P)
 {
-    return 3 * P > 6 * (kWin + 1) * 3 ? 3 * P : 6 * (kWin + 1) * 3;
+    return 3 * P + (P + kWindow - 1) / kWindow > 6 * (kWin + 1) * 3
+               ? 3 * P + (P + kWindow - 1) / kWindow
+               : 6 * (kWin + 1) * 3;
 }
 
 __global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs a, FieldMap m)
@@ -403,6 +491,7 @@ __global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs
     const int64_t s = blockIdx.x;
     const int P = a.K + 1;
     double *lx = lds, *ly = lds + P, *lz = lds + 2 * P;
+    double *rho = lds + 3 * P;  // window radii
     double *buf = lds;  // after the wires' chords are taken: [6][kWin + 1][3]
     double *scratch = lds + field_region(P);
 
@@ -453,6 +542,8 @@ __global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs
         lz[a.K] = x[2];
     }
     __syncthreads();
+    window_radii(lx, ly, lz, P, rho);
+    __syncthreads();
 
     double acc[1 + 6 + kTri + 6];
     for (int i = 0; i < 1 + 6 + kTri + 6; ++i)
@@ -472,7 +563,7 @@ __global__ __launch_bounds__(kAdjThreads) void rss_jacobian_field_kernel(AdjArgs
         wire_frame(a.ends + 6 * (int64_t)wi, f);
         double t, pxi, peta;
         int ka;
-        const double D = closest_chord(lx, ly, lz, P, f, ka, t, pxi, peta);
+        const double D = closest_chord(lx, ly, lz, rho, P, f, ka, t, pxi, peta);
         double eb = INFINITY, res = NAN;
         for (int j = a.offsets[wi]; j < a.offsets[wi + 1]; ++j) {
             const double rr = D - a.drift[j];
@@ -689,8 +780,8 @@ constexpr int kMaxAdjointSteps = 2400;
 size_t adjoint_lds_bytes(int K)
 {
     const int P = K + 1;
-    const int n_ck = K / kCheckEvery + 1;
-    return sizeof(double) * (3 * (size_t)P + 2 * (size_t)n_ck + (kAdjThreads / 64) * 34);
+    const int n_win = (P + kWindow - 1) / kWindow;
+    return sizeof(double) * (3 * (size_t)P + (size_t)n_win + 8 * (size_t)kUniThreads);
 }
 
 int check_adjoint_args(const char *who, const double *seeds6, int64_t n_seeds,
@@ -731,7 +822,7 @@ int launch_adjoint(const AdjArgs &a, hipStream_t hs, const FieldMap *fm = nullpt
         return launched("rss_jacobian_field_kernel");
     }
     const size_t lds = adjoint_lds_bytes(a.K);
-    hipLaunchKernelGGL(rss_adjoint_kernel, dim3((unsigned)a.S), dim3(kAdjThreads), lds, hs, a);
+    hipLaunchKernelGGL(rss_adjoint_kernel, dim3((unsigned)a.S), dim3(kUniThreads), lds, hs, a);
     return launched("rss_adjoint_kernel");
 }
 
@@ -765,14 +856,15 @@ int comet_rss_adjoint(const double *seeds6, int64_t n_seeds, const comet_config 
     return launch_adjoint(a, (hipStream_t)stream);
 }
 
-size_t comet_lm_workspace_bytes(int64_t n_seeds)
+size_t comet_lm_workspace_bytes(int64_t n_seeds, int32_t n_steps)
 {
-    if (n_seeds < 1)
+    if (n_seeds < 1 || n_steps < 1 || n_steps > kMaxAdjointSteps)
         return 0;
     const size_t S = (size_t)n_seeds;
     return align256(sizeof(double) * 6 * S) + 2 * align256(sizeof(double) * kTri * S) +
            2 * align256(sizeof(double) * 6 * S) + 3 * align256(sizeof(double) * S) +
-           2 * align256(sizeof(int32_t) * S);
+           2 * align256(sizeof(int32_t) * S) +
+           align256(sizeof(double) * 3 * ((size_t)n_steps + 1) * S);
 }
 
 }  // extern "C"
@@ -796,7 +888,7 @@ int lm_refine_impl(const char *who, double *seeds6, int64_t n_seeds, const comet
         return fail(COMET_EINVAL, "%s: n_iter must be in [0, 1000]", who);
     if (!(mu0 > 0.0) || !isfinite(mu0))
         return fail(COMET_EINVAL, "%s: mu0 must be finite and > 0", who);
-    const size_t need = comet_lm_workspace_bytes(n_seeds);
+    const size_t need = comet_lm_workspace_bytes(n_seeds, cfg->n_steps);
     if (!workspace || workspace_bytes < need)
         return fail(COMET_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, workspace_bytes,
                     need);
@@ -824,15 +916,27 @@ int lm_refine_impl(const char *who, double *seeds6, int64_t n_seeds, const comet
     (void)unused;
     int32_t *ok = (int32_t *)take(sizeof(int32_t) * S);
     int32_t *acc = (int32_t *)take(sizeof(int32_t) * S);
+    double *tracks = (double *)take(sizeof(double) * 3 * ((size_t)cfg->n_steps + 1) * S);
     if (n_accepted)
         acc = n_accepted;
+    // uniform field: every evaluation's tracks are recorded one seed per lane first
+    auto record = [&](const double *x) -> int {
+        if (fm)
+            return COMET_OK;
+        hipLaunchKernelGGL(adj_record_kernel, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, hs,
+                           x, n_seeds, cfg->bz_tesla, cfg->charge_e, cfg->step_mm, cfg->n_steps,
+                           tracks);
+        return launched("adj_record_kernel");
+    };
 
     const dim3 grid1((unsigned)((S + 255) / 256)), block1(256);
     AdjArgs a{seeds6, n_seeds, cfg->bz_tesla, cfg->charge_e, cfg->step_mm, cfg->lambda_mm,
               cfg->n_steps, wire_ends, n_wires, wire_offsets, drift, event_wires, seed_event,
-              rss, nullptr, A, b, nullptr, nullptr, nullptr};
+              rss, nullptr, A, b, nullptr, nullptr, nullptr, fm ? nullptr : tracks};
     hipLaunchKernelGGL(lm_init_kernel, grid1, block1, 0, hs, n_seeds, mu0, mu, acc);
     st = launched("lm_init_kernel");
+    if (!st)
+        st = record(seeds6);
     if (!st)
         st = launch_adjoint(a, hs, fm);
     AdjArgs at = a;
@@ -845,6 +949,8 @@ int lm_refine_impl(const char *who, double *seeds6, int64_t n_seeds, const comet
                            (const double *)seeds6, (const double *)A, (const double *)b,
                            (const double *)mu, trial, ok);
         st = launched("lm_propose_kernel");
+        if (!st)
+            st = record(trial);
         if (!st)
             st = launch_adjoint(at, hs, fm);
         if (!st) {

@@ -49,7 +49,8 @@ def coarse_then_lm(events, sc: synth.ScanConfig, top_k: int = 8, n_iter: int = 8
     acc = torch.empty(NP * k, dtype=torch.int32, device=device)
     seed_event = runner.part_event.repeat_interleave(k)
     comet.lm_refine(seeds, runner.cfg, runner.packed.wire_ends, runner.packed.wire_offsets,
-                    runner.packed.drift, n_iter, mu0, rss, comet.lm_workspace(NP * k, device),
+                    runner.packed.drift, n_iter, mu0, rss,
+                    comet.lm_workspace(NP * k, sc.n_steps, device),
                     n_accepted=acc, event_wires=runner.packed.event_wires, seed_event=seed_event)
     pick = torch.empty(NP, 1, dtype=torch.int64, device=device)
     comet.topk(rss.view(NP, k), 1, pick)
@@ -74,7 +75,8 @@ def coarse_then_lm(events, sc: synth.ScanConfig, top_k: int = 8, n_iter: int = 8
     rss2 = torch.empty(NP * k2, dtype=torch.float64, device=device)
     comet.lm_refine(seeds2, runner.cfg, runner.packed.wire_ends, runner.packed.wire_offsets,
                     runner.packed.drift, local_iters, mu0, rss2,
-                    comet.lm_workspace(NP * k2, device), event_wires=runner.packed.event_wires,
+                    comet.lm_workspace(NP * k2, sc.n_steps, device),
+                    event_wires=runner.packed.event_wires,
                     seed_event=runner.part_event.repeat_interleave(k2))
     # the first LM result first, so that it wins ties
     cand = torch.cat([final.view(6, NP, 1), seeds2.view(6, NP, k2)], dim=2).reshape(6, -1)

@@ -106,7 +106,7 @@ class StageRunner:
         if self.fit_iters > 0:
             self.fit_soa = torch.empty(6, E, **f64)
             self.fit_rss = torch.empty(E, **f64)
-            self.lm_ws = comet.lm_workspace(E, device)
+            self.lm_ws = comet.lm_workspace(E, scan_cfg.n_steps, device)
         if self.n_z > 1:
             Z = self.n_z
             self.part_event_z = torch.arange(E, dtype=torch.int32,

@@ -169,7 +169,7 @@ def test_adjoint_and_lm_reject(lib):
     long_cfg = _cfg(n_steps=5000)
     assert lib.comet_rss_adjoint(_p(), 8, ctypes.byref(long_cfg), _p(), 4, _p(), _p(), 5, None,
                                  None, *([None] * 7), None) == comet.EUNSUPPORTED
-    need = lib.comet_lm_workspace_bytes(8)
+    need = lib.comet_lm_workspace_bytes(8, 10)
     assert need > 0 and need % 256 == 0
     args = ok + (None, None)
     assert lib.comet_lm_refine(*args, 4, 1e-3, _p(), None, _p(0x100000), 16, None) == comet.EWORKSPACE

@@ -52,15 +52,18 @@ def _compare_to_duals(orc, ev, seeds, sc, got, wire_slice=slice(None)):
         r = got["resid"][s, wire_slice]
         assert np.array_equal(np.isnan(r), np.isnan(want["resid"]))
         assert np.array_equal(r[~np.isnan(r)], want["resid"][~np.isnan(want["resid"])])
-        assert abs(got["rss"][s] - want["rss"]) <= 1e-13 * want["rss"]
+        assert got["rss"][s] == want["rss"], (s, got["rss"][s], want["rss"])  # wire order
         scale = np.max(np.abs(want["grad"]))
         assert np.max(np.abs(got["grad"][s] - want["grad"])) <= 1e-7 * scale, (s, got["grad"][s],
                                                                                want["grad"])
         act = want["active"]
         J = got["jac"][s, wire_slice]
+        assert np.all(J[~act] == 0.0)
+        if not act.any():
+            assert np.all(got["jtj"][s] == 0.0) and np.all(got["jte"][s] == 0.0)
+            continue
         jw = want["J"][act]
         assert np.max(np.abs(J[act] - jw)) <= 1e-7 * np.max(np.abs(jw)), s
-        assert np.all(J[~act] == 0.0)
         A = np.zeros((6, 6))
         k = 0
         for i in range(6):
@@ -102,6 +105,46 @@ def test_adjoint_packed_events(orc):
         sub = {k: (v[3 * i:3 * i + 3] if v.ndim >= 1 else v) for k, v in got.items()}
         _compare_to_duals(orc, ev, seeds[:, 3 * i:3 * i + 3], sc, sub, slice(w0, w0 + ev.n_wires))
         w0 += ev.n_wires
+
+
+@pytest.mark.parametrize("bz", [1.0, 0.0])
+@pytest.mark.parametrize("K", [1, 15, 16, 17, 40, 1000])
+def test_adjoint_window_edges_and_straight_tracks(orc, ev_plain, K, bz):
+    """Track lengths around the 16-point windows of the closest-point bound (one point
+    past a window, a ragged last window) and a field-free straight track, where the
+    closed-form step factor is exactly 1: D, residuals and RSS bit for bit, rows 1e-7."""
+    from dataclasses import replace
+    ev = replace(ev_plain, bz=bz)
+    sc = replace(synth.C0, n_steps=K, lambda_mm=3.0)
+    seeds = _seeds_near(ev.ref_states[0], 8, 2e-3, K)
+    got = _gpu_adjoint(ev, seeds, scan.config_for(ev, sc))
+    assert np.isfinite(got["rss"]).all()
+    _compare_to_duals(orc, ev, seeds, sc, got)
+
+
+def test_adjoint_rss_equals_forward_rss(ev_signal):
+    """The adjoint's RSS is the forward path's, bit for bit, on a spread of 300 seeds
+    (near and far from the track), and its closest points are the forward path's."""
+    sc = synth.C1
+    cfg = scan.config_for(ev_signal, sc)
+    dev = scan.DeviceEvent.from_event(ev_signal)
+    rng = np.random.default_rng(11)
+    ref = ev_signal.ref_states[0]
+    seeds = np.stack([ref * (1 + rng.normal(0, rel, 6)) for rel in
+                      np.repeat([1e-4, 1e-3, 1e-2, 5e-2], 75)], axis=1)
+    X = torch.as_tensor(seeds, device="cuda")
+    got = _gpu_adjoint(ev_signal, seeds, cfg)
+    track = torch.empty(3, sc.n_steps + 1, 300, dtype=torch.float64, device="cuda")
+    comet.extrapolate_seeds(X, cfg, track)
+    ref_rss = torch.empty(300, dtype=torch.float64, device="cuda")
+    comet.dca_rss(track, dev.wire_ends, dev.wire_offsets, dev.drift, cfg, ref_rss,
+                  comet.dca_workspace(300, sc.n_steps + 1, dev.n_wires))
+    assert np.array_equal(got["rss"], ref_rss.cpu().numpy())
+    # the refinement's own path (tracks recorded one seed per lane, then loaded whole)
+    lm_rss = torch.empty(300, dtype=torch.float64, device="cuda")
+    comet.lm_refine(X.clone(), cfg, dev.wire_ends, dev.wire_offsets, dev.drift, 0, 1e-3, lm_rss,
+                    comet.lm_workspace(300, sc.n_steps))
+    assert torch.equal(lm_rss, ref_rss)
 
 
 def test_adjoint_matches_central_differences(ev_plain):
@@ -168,7 +211,7 @@ def test_lm_matches_cpu_reference(orc, ev_plain):
     rss = torch.empty(6, dtype=torch.float64, device="cuda")
     acc = torch.empty(6, dtype=torch.int32, device="cuda")
     comet.lm_refine(x, cfg, dev.wire_ends, dev.wire_offsets, dev.drift, 8, 1e-3, rss,
-                    comet.lm_workspace(6), n_accepted=acc)
+                    comet.lm_workspace(6, sc.n_steps), n_accepted=acc)
     got = x.cpu().numpy()
     for s in range(6):
         ws, wrss, wacc = orc.lm_refine(start[:, s], ocfg, sc.n_steps, ev_plain.wire_ends,
@@ -189,12 +232,12 @@ def test_lm_packed_equals_single(ev_plain):
     se = torch.tensor([0, 0, 1, 1, 2, 2], dtype=torch.int32, device="cuda")
     rss = torch.empty(6, dtype=torch.float64, device="cuda")
     comet.lm_refine(x, cfg, packed.wire_ends, packed.wire_offsets, packed.drift, 6, 1e-3, rss,
-                    comet.lm_workspace(6), event_wires=packed.event_wires, seed_event=se)
+                    comet.lm_workspace(6, sc.n_steps), event_wires=packed.event_wires, seed_event=se)
     for i, ev in enumerate(evs):
         dev = scan.DeviceEvent.from_event(ev)
         y = torch.as_tensor(starts[i], device="cuda").clone()
         r1 = torch.empty(2, dtype=torch.float64, device="cuda")
         comet.lm_refine(y, cfg, dev.wire_ends, dev.wire_offsets, dev.drift, 6, 1e-3, r1,
-                        comet.lm_workspace(2))
+                        comet.lm_workspace(2, sc.n_steps))
         assert torch.equal(x[:, 2 * i:2 * i + 2], y)
         assert torch.equal(rss[2 * i:2 * i + 2], r1)

@@ -147,7 +147,7 @@ def test_field_lm_matches_cpu(orc, fmap, stepper):
     rss = torch.empty(S, **d)
     acc = torch.empty(S, dtype=torch.int32, device="cuda")
     comet.lm_refine(x, cfg, torch.as_tensor(ends, **d), torch.as_tensor(off, device="cuda"),
-                    torch.as_tensor(drift, **d), 8, 1e-3, rss, comet.lm_workspace(S),
+                    torch.as_tensor(drift, **d), 8, 1e-3, rss, comet.lm_workspace(S, K),
                     n_accepted=acc, field=comet.FieldMap(*fmap, stepper=stepper))
     torch.cuda.synchronize()
     gx, grss, gacc = x.cpu().numpy(), rss.cpu().numpy(), acc.cpu().numpy()

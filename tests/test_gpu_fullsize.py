@@ -104,7 +104,7 @@ def test_lm_stress_size_matches_cpu(orc):
     rss = torch.empty(seeds.shape[1], dtype=torch.float64, device="cuda")
     acc = torch.empty(seeds.shape[1], dtype=torch.int32, device="cuda")
     comet.lm_refine(seeds, cfg, dev.wire_ends, dev.wire_offsets, dev.drift, 6, 1e-3, rss,
-                    comet.lm_workspace(seeds.shape[1], "cuda"), n_accepted=acc)
+                    comet.lm_workspace(seeds.shape[1], sc.n_steps, "cuda"), n_accepted=acc)
     got = seeds.cpu().numpy()
     for r, s0 in enumerate(starts):
         ws, wrss, wacc = orc.lm_refine(s0, _cfg(ev, sc), sc.n_steps, ev.wire_ends,
