@@ -255,16 +255,17 @@ def bench_halves(events, sc, n_ref: int = 10, n_iter: int = 2, n_fine=(4, 8, 8, 
 
 
 def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int = 3,
-                 fit_iters: int = 0, eta: float = 0.3):
+                 fit_iters: int = 0, eta: float = 0.3, n_z: int = 1, z_half: float = 0.0):
     """The stage loop: every event reconstructed turn by turn from its last turn, the
     hits of each stage left out of the next, each next stage's (z, p_z) from the
     backward extrapolation of the previous stage's seed (eager runs, device-synchronised
     wall time). With fit_iters > 0 each stage's seed is refined by Levenberg-Marquardt
-    and its hits self-refined (lambda at the fitted track, eta re-admission)."""
+    and its hits self-refined (lambda at the fitted track, eta re-admission). With
+    n_z > 1 every stage also scans n_z values of the seed's z over z +- z_half."""
     import torch
     from paper_1911_09340_amd import quality, stages
     run = stages.StageRunner(events, sc, max_stages=max_stages, min_wires=min_wires,
-                             fit_iters=fit_iters, eta=eta)
+                             fit_iters=fit_iters, eta=eta, n_z=n_z, z_half=z_half)
     run.run()
     torch.cuda.synchronize()
     dts = []
@@ -293,7 +294,8 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
     act = run.active_after.cpu().numpy()
     return {"events": len(events), "seeds_per_stage_scan": sc.n_seeds, "rescans": sc.n_refine,
             "max_stages": max_stages, "min_wires": min_wires, "fit_iters": fit_iters,
-            "eta_mm": eta if fit_iters > 0 else None,
+            "eta_mm": eta if fit_iters > 0 else None, "z_axis": None if n_z < 2 else {
+                "points": n_z, "half_span_mm": z_half},
             "seconds_per_run": dt, "events_per_s": len(events) / dt,
             "events_active_after_stage": [int(a.sum()) for a in act],
             "classification_all_turns": quality.classification(masks, events),
@@ -688,7 +690,9 @@ def main():
         out["stages"] = bench_stages(mix_events, synth.C2)
         log("stage loop with self-refining (8 LM iterations, eta 0.3 mm) ...")
         out["stages_self_refined"] = bench_stages(mix_events, synth.C2, fit_iters=8)
-        for key in ("stages", "stages_self_refined"):
+        log("stage loop with self-refining and the seed's z as a fifth axis (5 x 4 mm) ...")
+        out["stages_z"] = bench_stages(mix_events, synth.C2, fit_iters=8, n_z=5, z_half=8.0)
+        for key in ("stages", "stages_self_refined", "stages_z"):
             st = out[key]
             log("  %s: %.1f events/s; efficiency %.3f purity %.3f over all turns; by turns: %s"
                 % (key, st["events_per_s"], st["classification_all_turns"]["efficiency_mean"],
