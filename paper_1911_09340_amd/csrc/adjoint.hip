@@ -37,7 +37,9 @@ using namespace cdev;
 using namespace chost;
 
 constexpr int kAdjThreads = 256;     // field-map kernel
-constexpr int kUniThreads = 64;      // uniform-field kernel (one wave)
+// uniform-field kernel: four waves per block while its LDS fits in 64 KB, else one
+constexpr int kUniThreadsWide = 256;
+constexpr int kUniThreadsNarrow = 64;
 constexpr int kWindow = 16;  // points per window of the distance bound
 constexpr int kTri = 21;  // packed upper triangle of a symmetric 6x6 matrix
 
@@ -109,8 +111,23 @@ __device__ __forceinline__ double closest_chord(const double *lx, const double *
                                                 double &pxi, double &peta)
 {
     const int n_win = (P + kWindow - 1) / kWindow;
+    // the windows' first points, eight at a time (independent loads and products)
     double ub = INFINITY;
-    for (int c = 0; c < n_win; ++c) {
+    int c = 0;
+    for (; c + 8 <= n_win; c += 8) {
+        double qv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = (c + u) * kWindow;
+            double xi, eta;
+            project(f, lx[k], ly[k], lz[k], xi, eta);
+            qv[u] = fma(xi, xi, eta * eta);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            ub = qv[u] < ub ? qv[u] : ub;
+    }
+    for (; c < n_win; ++c) {
         const int k = c * kWindow;
         double xi, eta;
         project(f, lx[k], ly[k], lz[k], xi, eta);
@@ -120,19 +137,35 @@ __device__ __forceinline__ double closest_chord(const double *lx, const double *
     double bound = sqrt(ub);
     int kb = 0;
     double qb = INFINITY;
-    for (int c = 0; c < n_win; ++c) {
-        const int k0 = c * kWindow, k1 = min(P, k0 + kWindow);
+    for (c = 0; c < n_win; ++c) {
+        const int k0 = c * kWindow;
         double xi, eta;
         project(f, lx[k0], ly[k0], lz[k0], xi, eta);
-        const double d0 = sqrt(fma(xi, xi, eta * eta));
-        if (d0 > (rho[c] + bound) * (1.0 + 1e-9) + 1e-9)
+        // skip when sqrt(q0) exceeds rho + bound (compared squared: both sides >= 0)
+        const double tb = (rho[c] + bound) * (1.0 + 1e-9) + 1e-9;
+        if (fma(xi, xi, eta * eta) > tb * tb)
             continue;
-        for (int k = k0; k < k1; ++k) {
-            project(f, lx[k], ly[k], lz[k], xi, eta);
-            const double q = fma(xi, xi, eta * eta);
-            if (q < qb) {
-                qb = q;
-                kb = k;
+        if (k0 + kWindow <= P) {
+            double qv[kWindow];
+#pragma unroll
+            for (int j = 0; j < kWindow; ++j) {
+                project(f, lx[k0 + j], ly[k0 + j], lz[k0 + j], xi, eta);
+                qv[j] = fma(xi, xi, eta * eta);
+            }
+#pragma unroll
+            for (int j = 0; j < kWindow; ++j)
+                if (qv[j] < qb) {
+                    qb = qv[j];
+                    kb = k0 + j;
+                }
+        } else {
+            for (int k = k0; k < P; ++k) {
+                project(f, lx[k], ly[k], lz[k], xi, eta);
+                const double q = fma(xi, xi, eta * eta);
+                if (q < qb) {
+                    qb = q;
+                    kb = k;
+                }
             }
         }
         const double sb = sqrt(qb);
@@ -307,6 +340,7 @@ __global__ __launch_bounds__(64) void adj_record_kernel(const double *__restrict
     tz[K] = z;
 }
 
+template <int kUniThreads>
 __global__ __launch_bounds__(kUniThreads) void rss_adjoint_kernel(AdjArgs a)
 {
     extern __shared__ double lds[];
@@ -327,6 +361,7 @@ __global__ __launch_bounds__(kUniThreads) void rss_adjoint_kernel(AdjArgs a)
 
     if (a.tracks) {  // recorded by adj_record_kernel: load it whole
         const double *src = a.tracks + (size_t)s * 3 * P;
+#pragma unroll 4
         for (int i = threadIdx.x; i < 3 * P; i += kUniThreads)
             lds[i] = src[i];
     } else if (threadIdx.x == 0) {
@@ -777,11 +812,11 @@ __global__ void lm_init_kernel(int64_t S, double mu0, double *__restrict__ mu,
 
 constexpr int kMaxAdjointSteps = 2400;
 
-size_t adjoint_lds_bytes(int K)
+size_t adjoint_lds_bytes(int K, int threads)
 {
     const int P = K + 1;
     const int n_win = (P + kWindow - 1) / kWindow;
-    return sizeof(double) * (3 * (size_t)P + (size_t)n_win + 8 * (size_t)kUniThreads);
+    return sizeof(double) * (3 * (size_t)P + (size_t)n_win + 8 * (size_t)threads);
 }
 
 int check_adjoint_args(const char *who, const double *seeds6, int64_t n_seeds,
@@ -821,8 +856,14 @@ int launch_adjoint(const AdjArgs &a, hipStream_t hs, const FieldMap *fm = nullpt
                            field_jacobian_lds_bytes(a.K), hs, a, *fm);
         return launched("rss_jacobian_field_kernel");
     }
-    const size_t lds = adjoint_lds_bytes(a.K);
-    hipLaunchKernelGGL(rss_adjoint_kernel, dim3((unsigned)a.S), dim3(kUniThreads), lds, hs, a);
+    if (adjoint_lds_bytes(a.K, kUniThreadsWide) <= 65536) {
+        hipLaunchKernelGGL(rss_adjoint_kernel<kUniThreadsWide>, dim3((unsigned)a.S),
+                           dim3(kUniThreadsWide), adjoint_lds_bytes(a.K, kUniThreadsWide), hs, a);
+    } else {
+        hipLaunchKernelGGL(rss_adjoint_kernel<kUniThreadsNarrow>, dim3((unsigned)a.S),
+                           dim3(kUniThreadsNarrow), adjoint_lds_bytes(a.K, kUniThreadsNarrow), hs,
+                           a);
+    }
     return launched("rss_adjoint_kernel");
 }
 
