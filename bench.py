@@ -263,7 +263,7 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
     and its hits self-refined (lambda at the fitted track, eta re-admission). With
     n_z > 1 every stage also scans n_z values of the seed's z over z +- z_half."""
     import torch
-    from paper_1911_09340_amd import quality, stages
+    from paper_1911_09340_amd import stages
     run = stages.StageRunner(events, sc, max_stages=max_stages, min_wires=min_wires,
                              fit_iters=fit_iters, eta=eta, n_z=n_z, z_half=z_half)
     run.run()
@@ -276,6 +276,20 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
         dts.append(time.perf_counter() - t0)
         log("  stage-loop run %d: %.3f s" % (r, dts[-1]))
     dt = float(np.median(dts))
+    act = run.active_after.cpu().numpy()
+    return {"events": len(events), "seeds_per_stage_scan": sc.n_seeds, "rescans": sc.n_refine,
+            "max_stages": max_stages, "min_wires": min_wires, "fit_iters": fit_iters,
+            "eta_mm": eta if fit_iters > 0 else None, "z_axis": None if n_z < 2 else {
+                "points": n_z, "half_span_mm": z_half},
+            "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "events_active_after_stage": [int(a.sum()) for a in act],
+            **_turn_quality(run, events)}
+
+
+def _turn_quality(run, events) -> dict:
+    """Hit-classification efficiency and purity (Sec. 3.2.1) of a stage loop's turn
+    masks, over all turns and by the event's number of turns."""
+    from paper_1911_09340_amd import quality
     tm = run.turn_masks()
     stride = max(ev.n_hits for ev in events)
     rows = []
@@ -291,18 +305,46 @@ def bench_stages(events, sc, max_stages: int = 5, min_wires: int = 30, reps: int
         q = quality.classification(masks[p:p + ev.n_turns], [ev])
         by_turns.setdefault(ev.n_turns, []).append((q["efficiency_mean"], q["purity_mean"]))
         p += ev.n_turns
-    act = run.active_after.cpu().numpy()
-    return {"events": len(events), "seeds_per_stage_scan": sc.n_seeds, "rescans": sc.n_refine,
-            "max_stages": max_stages, "min_wires": min_wires, "fit_iters": fit_iters,
-            "eta_mm": eta if fit_iters > 0 else None, "z_axis": None if n_z < 2 else {
-                "points": n_z, "half_span_mm": z_half},
-            "seconds_per_run": dt, "events_per_s": len(events) / dt,
-            "events_active_after_stage": [int(a.sum()) for a in act],
-            "classification_all_turns": quality.classification(masks, events),
+    return {"classification_all_turns": quality.classification(masks, events),
             "efficiency_purity_by_turns": {
                 str(k): [float(np.mean([x[0] for x in v])),
                          float(np.nanmean([x[1] for x in v])) if any(not np.isnan(x[1]) for x in v)
                          else None, len(v)] for k, v in sorted(by_turns.items())}}
+
+
+def bench_chain(events, sc, reps: int = 3, fit_iters: int = 8, eta: float = 0.3):
+    """The paper's per-stage chain (Sec. 3.1): per stage both half tracks with several
+    references (first grid sc.n, 10 references, two re-scans of 4 x 8 x 8 x 8, 10 final
+    seeds per side, half the steps of a turn), the missing-layer veto and the merge, the
+    best complete set fitted by Levenberg-Marquardt and self-refined, then exclusion and
+    backward extrapolation (eager launches, device-synchronised wall time)."""
+    import torch
+    from paper_1911_09340_amd import chain
+    run = chain.StageChainRunner(events, sc, n_ref=10, n_iter=2, n_fine=(4, 8, 8, 8),
+                                 n_final=10, fit_iters=fit_iters, eta=eta)
+    run.run()
+    torch.cuda.synchronize()
+    dts = []
+    for r in range(reps):
+        t0 = time.perf_counter()
+        run.run()
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - t0)
+        log("  chain run %d: %.3f s" % (r, dts[-1]))
+    dt = float(np.median(dts))
+    act = run.active_after.cpu().numpy()
+    a0 = run.active0.cpu().numpy()
+    nc = run.n_complete_at.cpu().numpy()
+    stage_rows = [(s, e) for s in range(run.max_stages) for e in range(run.n_events)
+                  if (a0[e] if s == 0 else act[s - 1, e])]
+    return {"events": len(events), "first_grid": "x".join(map(str, sc.n)), "references": 10,
+            "rescans": 2, "rescan_grid": "4x8x8x8", "final_seeds_per_side": 10,
+            "rk4_steps_per_half": run.half_steps, "fit_iters": fit_iters, "eta_mm": eta,
+            "seconds_per_run": dt, "events_per_s": len(events) / dt,
+            "events_active_after_stage": [int(a.sum()) for a in act],
+            "stages_with_complete_set": float(np.mean([nc[s, e] > 0 for s, e in stage_rows]))
+            if stage_rows else None,
+            **_turn_quality(run, events)}
 
 
 def bench_lambda_sweep(events, sc, lambdas=(0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2),
@@ -692,7 +734,12 @@ def main():
         out["stages_self_refined"] = bench_stages(mix_events, synth.C2, fit_iters=8)
         log("stage loop with self-refining and the seed's z as a fifth axis (5 x 4 mm) ...")
         out["stages_z"] = bench_stages(mix_events, synth.C2, fit_iters=8, n_z=5, z_half=8.0)
-        for key in ("stages", "stages_self_refined", "stages_z"):
+        log("per-stage chain: half tracks with several references, veto, merge, fit and "
+            "self-refining per stage ...")
+        out["stage_chain"] = bench_chain(mix_events, synth.C2)
+        log("  stage chain: complete sets in %.3f of the scanned stages"
+            % (out["stage_chain"]["stages_with_complete_set"] or 0.0))
+        for key in ("stages", "stages_self_refined", "stages_z", "stage_chain"):
             st = out[key]
             log("  %s: %.1f events/s; efficiency %.3f purity %.3f over all turns; by turns: %s"
                 % (key, st["events_per_s"], st["classification_all_turns"]["efficiency_mean"],

@@ -542,6 +542,64 @@ int comet_stage_update(int32_t *active, int32_t n_events, const int64_t *best,
                        const int32_t *event_wires_next, const int32_t *n_turns, int32_t stage,
                        int32_t max_stages, int32_t min_wires, void *stream);
 
+/* ------------------------------------------------------------ per-stage chain
+ * The paper's stage (Sec. 3.1) scans the turn partition as two half tracks, each with
+ * several references, vetoes and merges the half sets, self-refines the best complete
+ * set and extrapolates backwards from it. The scans, selections, veto, merge,
+ * self-refining and backward extrapolation are the entry points above; these four join
+ * them. All launch on `stream` without allocating or synchronising.
+ *
+ * comet_exit_seeds: the exit half track's seed. For state i (states + i row_stride, six
+ * doubles (x, y, z, px, py, pz) at a turn's outward crossing of r = radius mm; a
+ * row_stride of 14 reads the reference state of comet_seed_grid descriptors) the track
+ * runs forwards (the RK4 step of comet_extrapolate_seeds with cfg's field, charge and
+ * step) for at most max_steps steps; out6[i] is the state where it first crosses
+ * r = radius inwards after having been outside (the turn's re-entry into the seed
+ * region), interpolated linearly in r^2 - radius^2 between the crossing step's two
+ * states, with the momentum reversed: the exit half is scanned backwards through the
+ * turn, with the charge reversed too. NaN (steps[i] = -1) without such a crossing.
+ * steps (int32[n]) may be NULL.
+ *
+ * comet_half_split: per hit j of the packed events (CSR as in comet_batch_scan with
+ * hit_ids, as comet_exclude_hits writes them; only the first
+ * wire_offsets[event_wires[n_events]] of the n_hits capacity are read) the side of its
+ * wire: entrance_side[hit_ids[j]] (uint8[n_ids], nonzero = the entrance half: the
+ * turn's hits on the entrance side of the line through the chamber axis and the
+ * circle's centre) gives exclude_entrance[j] = 0 and exclude_exit[j] = 1, and the
+ * opposite for the exit side; an id outside [0, n_ids) leaves both halves. With
+ * comet_exclude_hits the two masks give the halves' CSRs.
+ *
+ * comet_wire_layers: wire_layer[w] = hit_layer[hit_ids[first hit of wire w]] for the
+ * wires of packed events whose every wire holds a hit (comet_exclude_hits output), -1
+ * for an id outside [0, n_ids); for comet_layer_veto.
+ *
+ * comet_union_halves: per event e with active[e] != 0, the best complete set: entrance
+ * seed i and exit seed j from pair[e][0] = i n_final + j of comet_merge_halves when
+ * n_complete[e] > 0, else (0, 0), the lowest-RSS final seed of each side. Its hits:
+ * mask_out[e][k] (k the hit's index within event e of the packed events, which hold
+ * both halves' hits) is bit 0 of mask_a[e n_final + i] at the hit's index among the
+ * event's entrance hits, or of mask_b[e n_final + j] among its exit hits; seed_out[e] =
+ * seeds_a[e n_final + i] (double[6]); best_out[e] = i n_final + j, or -1 when that
+ * seed is NaN. Inactive events get seed_out NaN and best_out -1 and keep mask_out.
+ * n_final in 1..64; masks uint8 [rows][stride]. One wave per event. */
+int comet_exit_seeds(const double *states, int64_t row_stride, int32_t n, const comet_config *cfg,
+                     double radius, int32_t max_steps, double *out6, int32_t *steps,
+                     void *stream);
+int comet_half_split(const int32_t *event_wires, int32_t n_events, const int32_t *wire_offsets,
+                     const int32_t *hit_ids, int32_t n_hits, const uint8_t *entrance_side,
+                     int32_t n_ids, uint8_t *exclude_entrance, uint8_t *exclude_exit,
+                     void *stream);
+int comet_wire_layers(const int32_t *event_wires, int32_t n_events, const int32_t *wire_offsets,
+                      int32_t n_wires, const int32_t *hit_ids, const int32_t *hit_layer,
+                      int32_t n_ids, int32_t *wire_layer, void *stream);
+int comet_union_halves(const int32_t *pair, const int32_t *n_complete, int32_t n_final,
+                       int32_t n_events, const int32_t *event_wires, const int32_t *wire_offsets,
+                       const int32_t *hit_ids, const uint8_t *entrance_side, int32_t n_ids,
+                       const uint8_t *mask_a, int64_t stride_a, const uint8_t *mask_b,
+                       int64_t stride_b, const double *seeds_a, const int32_t *active,
+                       uint8_t *mask_out, int64_t stride_out, double *seed_out,
+                       int64_t *best_out, void *stream);
+
 /* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
  * per LDS chunk, the persistent block count on the current device, and direct and runs
  * as for the DCA shapes; blocks, direct and runs may be NULL); every shape gives the

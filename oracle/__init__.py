@@ -83,6 +83,9 @@ def _bind(lib):
                                       ctypes.c_int32]
     lib.oracle_merge_halves.restype = ctypes.c_int32
     lib.oracle_merge_halves.argtypes = [_d, _i32, _d, _i32, ctypes.c_int32, _i32, _d]
+    lib.oracle_exit_seed.restype = ctypes.c_int32
+    lib.oracle_exit_seed.argtypes = [_d, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int32, _d]
     lib.oracle_backward_seed.restype = ctypes.c_int32
     lib.oracle_backward_seed.argtypes = [_d, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int32, _d]
@@ -361,6 +364,13 @@ class Oracle:
         out = np.empty(6)
         k = self.lib.oracle_backward_seed(_p(_f64(seed6)), bz, charge, h, radius, max_steps,
                                           _p(out))
+        return out, int(k)
+
+    def exit_seed(self, seed6, bz, charge, h, radius, max_steps):
+        """The exit half track's seed: the state where the turn re-enters r = radius,
+        momentum reversed: (out6, steps)."""
+        out = np.empty(6)
+        k = self.lib.oracle_exit_seed(_p(_f64(seed6)), bz, charge, h, radius, max_steps, _p(out))
         return out, int(k)
 
     def stage_grid(self, transverse6, ext6, half):

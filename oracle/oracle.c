@@ -1124,6 +1124,47 @@ int32_t oracle_backward_seed(const double seed6[6], double bz, double charge, do
     return -1;
 }
 
+/* The exit half track's seed (Sec. 3.1: each turn partition is split into an entrance
+ * and an exit half track; the exit half runs backwards from where the turn leaves the
+ * seed region). From seed6 at the turn's outward crossing of r = radius, the track runs
+ * forwards with the RK4 step of oracle_track until it crosses r = radius inwards after
+ * having been outside it: the first step a -> b with d_a >= 0 > d_b (d = x x + y y -
+ * radius^2) once some state had d > 0. Every component is fma(f, b - a, a) with
+ * f = d_a / (d_a - d_b); then the momentum is reversed (the exit half is scanned with
+ * the charge reversed as well). out6 is NaN when no crossing comes within max_steps.
+ * Returns the step count at the crossing (-1 if none). */
+int32_t oracle_exit_seed(const double seed6[6], double bz, double charge, double h,
+                         double radius, int32_t max_steps, double out6[6])
+{
+    double s[6];
+    for (int j = 0; j < 6; ++j)
+        s[j] = seed6[j];
+    const rk4_consts kc = rk4_setup(s[3], s[4], s[5], bz, charge, h);
+    const double R2 = radius * radius;
+    int outside = 0;
+    for (int32_t k = 0; k < 6; ++k)
+        out6[k] = NAN;
+    for (int32_t k = 0; k < max_steps; ++k) {
+        double a[6];
+        for (int j = 0; j < 6; ++j)
+            a[j] = s[j];
+        rk4_step(&kc, &s[0], &s[1], &s[2], &s[3], &s[4]);
+        const double da = (a[0] * a[0] + a[1] * a[1]) - R2;
+        const double db = (s[0] * s[0] + s[1] * s[1]) - R2;
+        if (da > 0.0)
+            outside = 1;
+        if (outside && da >= 0.0 && db < 0.0) {
+            const double w = da / (da - db);
+            for (int j = 0; j < 3; ++j)
+                out6[j] = fma(w, s[j] - a[j], a[j]);
+            for (int j = 3; j < 6; ++j)
+                out6[j] = -fma(w, s[j] - a[j], a[j]);
+            return k;
+        }
+    }
+    return -1;
+}
+
 /* The next stage's grid descriptor: the transverse seed (x, y, p_x, p_y) of the turn
  * (the Hough-transform seed of Sec. 3.1) with (z, p_z) from the backward
  * extrapolation; axis centres (0, |p|, 0, 0) with |p| = sqrt((px px + py py) + pz pz)

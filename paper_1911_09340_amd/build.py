@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in ("runtime.hip", "comet.hip", "adjoint.hip", "batch.hip",
-                                             "halves.hip", "stages.hip", "field.hip")]
+                                             "halves.hip", "stages.hip", "field.hip",
+                                             "chain.hip")]
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcomet.so")
 

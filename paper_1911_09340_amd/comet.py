@@ -519,6 +519,16 @@ def _bind_batch(lib):
     lib.comet_self_refine.argtypes = [_vp, _i32, _vp, ctypes.POINTER(Config), _vp, _i32, _vp,
                                       _vp, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _i64, _vp]
     lib.comet_self_refine.restype = ctypes.c_int
+    lib.comet_exit_seeds.argtypes = [_vp, _i64, _i32, ctypes.POINTER(Config), ctypes.c_double,
+                                     _i32, _vp, _vp, _vp]
+    lib.comet_exit_seeds.restype = ctypes.c_int
+    lib.comet_half_split.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp]
+    lib.comet_half_split.restype = ctypes.c_int
+    lib.comet_wire_layers.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _vp]
+    lib.comet_wire_layers.restype = ctypes.c_int
+    lib.comet_union_halves.argtypes = [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _i64,
+                                       _vp, _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
+    lib.comet_union_halves.restype = ctypes.c_int
     lib._batch_bound = True
     return lib
 
@@ -781,6 +791,81 @@ def self_refine(seeds: torch.Tensor, row_event: torch.Tensor, cfg: Config, packe
         _ptr(mask_in, torch.uint8, "mask_in", (n_r, stride)),
         _ptr(mask_out, torch.uint8, "mask_out", (n_r, stride)), stride, _stream()),
         "comet_self_refine")
+
+
+# ------------------------------------------------------------------ per-stage chain
+def exit_seeds(states: torch.Tensor, row_stride: int, cfg: Config, radius: float,
+               max_steps: int, out: torch.Tensor, steps=None) -> None:
+    """comet_exit_seeds: rows of `states` (double, row_stride doubles apart, the first six
+    used) -> out [n, 6], the exit half's seed (optional steps [n] int32)."""
+    lib = _bind_batch(load())
+    n = int(out.shape[0])
+    if states.dtype != torch.float64 or not states.is_contiguous() or \
+            states.numel() < (n - 1) * int(row_stride) + 6:
+        raise CometError(EINVAL, "exit_seeds: states must be contiguous float64 holding n rows")
+    _check(lib.comet_exit_seeds(_ptr(states, torch.float64, "states"), int(row_stride), n,
+                                ctypes.byref(cfg), float(radius), int(max_steps),
+                                _ptr(out, torch.float64, "out", (n, 6)),
+                                _ptr(steps, torch.int32, "steps", (n,), optional=True),
+                                _stream()), "comet_exit_seeds")
+
+
+def half_split(packed, entrance_side: torch.Tensor, exclude_entrance: torch.Tensor,
+               exclude_exit: torch.Tensor) -> None:
+    """comet_half_split: per hit of `packed` (with .hit_ids), the exclusion masks of the
+    entrance and exit halves from entrance_side (uint8, by hit id)."""
+    lib = _bind_batch(load())
+    n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
+    n_e = int(packed.event_wires.shape[0]) - 1
+    n_ids = int(entrance_side.shape[0])
+    _check(lib.comet_half_split(
+        _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e,
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(packed.hit_ids, torch.int32, "hit_ids", (n_h,)), n_h,
+        _ptr(entrance_side, torch.uint8, "entrance_side", (n_ids,)), n_ids,
+        _ptr(exclude_entrance, torch.uint8, "exclude_entrance", (n_h,)),
+        _ptr(exclude_exit, torch.uint8, "exclude_exit", (n_h,)), _stream()), "comet_half_split")
+
+
+def wire_layers(packed, hit_layer: torch.Tensor, wire_layer: torch.Tensor) -> None:
+    """comet_wire_layers: wire_layer [n_wires] from the layer of each wire's first hit."""
+    lib = _bind_batch(load())
+    n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
+    n_e = int(packed.event_wires.shape[0]) - 1
+    n_ids = int(hit_layer.shape[0])
+    _check(lib.comet_wire_layers(
+        _ptr(packed.event_wires, torch.int32, "event_wires", (n_e + 1,)), n_e,
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)), n_w,
+        _ptr(packed.hit_ids, torch.int32, "hit_ids", (n_h,)),
+        _ptr(hit_layer, torch.int32, "hit_layer", (n_ids,)), n_ids,
+        _ptr(wire_layer, torch.int32, "wire_layer", (n_w,)), _stream()), "comet_wire_layers")
+
+
+def union_halves(pair: torch.Tensor, n_complete: torch.Tensor, n_final: int, packed,
+                 entrance_side: torch.Tensor, mask_a: torch.Tensor, mask_b: torch.Tensor,
+                 seeds_a: torch.Tensor, active: torch.Tensor, mask_out: torch.Tensor,
+                 seed_out: torch.Tensor, best_out: torch.Tensor) -> None:
+    """comet_union_halves: the best complete set of every active event -> its union mask
+    on `packed` [E, stride], its entrance seed [E, 6] and pair code [E] (int64)."""
+    lib = _bind_batch(load())
+    E, F = int(active.shape[0]), int(n_final)
+    n_w, n_h = int(packed.wire_ends.shape[0]), int(packed.drift.shape[0])
+    n_ids = int(entrance_side.shape[0])
+    sa, sb, so = int(mask_a.shape[1]), int(mask_b.shape[1]), int(mask_out.shape[1])
+    _check(lib.comet_union_halves(
+        _ptr(pair, torch.int32, "pair", (E, F * F)), _ptr(n_complete, torch.int32, "n_complete",
+                                                           (E,)), F, E,
+        _ptr(packed.event_wires, torch.int32, "event_wires", (E + 1,)),
+        _ptr(packed.wire_offsets, torch.int32, "wire_offsets", (n_w + 1,)),
+        _ptr(packed.hit_ids, torch.int32, "hit_ids", (n_h,)),
+        _ptr(entrance_side, torch.uint8, "entrance_side", (n_ids,)), n_ids,
+        _ptr(mask_a, torch.uint8, "mask_a", (E * F, sa)), sa,
+        _ptr(mask_b, torch.uint8, "mask_b", (E * F, sb)), sb,
+        _ptr(seeds_a, torch.float64, "seeds_a", (E * F, 6)),
+        _ptr(active, torch.int32, "active", (E,)),
+        _ptr(mask_out, torch.uint8, "mask_out", (E, so)), so,
+        _ptr(seed_out, torch.float64, "seed_out", (E, 6)),
+        _ptr(best_out, torch.int64, "best_out", (E,)), _stream()), "comet_union_halves")
 
 
 def stage_update(active: torch.Tensor, best: torch.Tensor, event_wires_next: torch.Tensor,

@@ -21,32 +21,26 @@ import torch
 from . import comet, scan, synth
 
 
-class MultiRefRunner:
-    def __init__(self, events, scan_cfg: synth.ScanConfig, n_ref: int = 10, n_iter: int = 2,
-                 n_fine=(4, 8, 8, 8), n_final: int = 10, device="cuda"):
-        from .synth import grid_descriptor
+class MultiRefScan:
+    """Buffers and launches of the several-reference scan of NP partitions (part_event
+    [NP] int32, device) over packed events given at run time. grids0 [NP, 14] holds the
+    first grids (filled by the caller before run); n0 is their shape."""
+
+    def __init__(self, part_event: torch.Tensor, n0, n_fine, n_ref: int, n_iter: int,
+                 n_final: int, stride: int, n_wires: int, n_steps: int, device="cuda"):
         if n_iter < 0 or n_ref < 1 or n_final < 1:
             raise ValueError("need n_iter >= 0, n_ref >= 1 and n_final >= 1")
-        self.events = list(events)
-        self.sc = scan_cfg
-        self.n0 = tuple(int(v) for v in scan_cfg.n)
+        self.n0 = tuple(int(v) for v in n0)
         self.n_fine = tuple(int(v) for v in n_fine)
         self.R, self.n_iter, self.F = int(n_ref), int(n_iter), int(n_final)
-        self.cfg = scan.config_for(self.events[0], scan_cfg)
-        self.packed = scan.PackedEvents.from_events(self.events, device)
-        part_event, grids = [], []
-        for e, ev in enumerate(self.events):
-            for t in range(ev.n_turns):
-                part_event.append(e)
-                grids.append(grid_descriptor(ev.ref_states[t], scan_cfg))
-        NP = self.n_part = len(part_event)
-        self.part_event = torch.as_tensor(np.asarray(part_event, dtype=np.int32), device=device)
-        self.part_event_r = self.part_event.repeat_interleave(self.R)
-        self.part_event_f = self.part_event.repeat_interleave(self.F)
+        NP = self.n_part = int(part_event.shape[0])
+        self.part_event = part_event
+        self.part_event_r = part_event.repeat_interleave(self.R)
+        self.part_event_f = part_event.repeat_interleave(self.F)
         f64 = dict(dtype=torch.float64, device=device)
         i64 = dict(dtype=torch.int64, device=device)
         S0, S1 = int(np.prod(self.n0)), int(np.prod(self.n_fine))
-        self.grids0 = torch.as_tensor(np.stack(grids), device=device)       # [NP, 14]
+        self.grids0 = torch.empty(NP, 14, **f64)
         self.rss0 = torch.empty(NP, S0, **f64)
         self.best0 = torch.empty(NP, **i64)
         # per re-scan k = 1..n_iter: its grids (the selection before it) and its RSS
@@ -61,14 +55,16 @@ class MultiRefRunner:
         self.final_local = torch.empty(NP, self.F, **i64)
         self._final_new = torch.empty(NP, self.F, 14, **f64)
         self.final_seed = torch.empty(NP * self.F, 6, **f64)
-        self.stride = max(ev.n_hits for ev in self.events)
+        self.stride = int(stride)
         # entries past a partition's own hits are never written: start them at 0
         self.mask = torch.zeros(NP * self.F, self.stride, dtype=torch.uint8, device=device)
         self.n_border = torch.empty(NP * self.F, dtype=torch.int32, device=device)
-        n_w = int(self.packed.wire_ends.shape[0])
-        self.workspace = comet.batch_workspace(n_w, scan_cfg.n_steps,
+        self.workspace = comet.batch_workspace(int(n_wires), int(n_steps),
                                                NP * max(self.R if self.n_iter else 1, 1), device)
-        self.graph = None
+
+    @property
+    def seeds_per_partition(self) -> int:
+        return int(np.prod(self.n0)) + self.n_iter * self.R * int(np.prod(self.n_fine))
 
     @property
     def last_n(self):
@@ -81,31 +77,59 @@ class MultiRefRunner:
             return self.grids[-1], self.rss[-1]
         return self.grids0.view(NP, 1, 14), self.rss0.view(NP, 1, -1)
 
-    @property
-    def evals_per_run(self) -> int:
-        """Seed x hit evaluations of one run (every scan of every partition)."""
-        hits = np.asarray([self.events[e].n_hits for e in self.part_event.cpu().numpy()])
-        per = int(np.prod(self.n0)) + self.n_iter * self.R * int(np.prod(self.n_fine))
-        return int(hits.sum()) * per
-
-    def run(self) -> None:
+    def run(self, packed, cfg, event_active=None) -> None:
+        """The scans of every partition whose event is active (all without
+        event_active), the selections and the final classification."""
         NP, R = self.n_part, self.R
-        comet.batch_scan(self.packed, self.part_event, self.grids0, self.n0, self.cfg, 0,
-                         self.rss0, self.best0, self.workspace)
+        comet.batch_scan(packed, self.part_event, self.grids0, self.n0, cfg, 0, self.rss0,
+                         self.best0, self.workspace, event_active=event_active)
         src_g, src_r, src_n = self.grids0.view(NP, 1, 14), self.rss0.view(NP, 1, -1), self.n0
         for k in range(self.n_iter):
             comet.sparse_select(src_g, src_r, src_n, R, self.ref_idx[k], self.grids[k])
-            comet.batch_scan(self.packed, self.part_event_r, self.grids[k].view(NP * R, 14),
-                             self.n_fine, self.cfg, 0, self.rss[k].view(NP * R, -1),
-                             self.best[k], self.workspace)
+            comet.batch_scan(packed, self.part_event_r, self.grids[k].view(NP * R, 14),
+                             self.n_fine, cfg, 0, self.rss[k].view(NP * R, -1), self.best[k],
+                             self.workspace, event_active=event_active)
             src_g, src_r, src_n = self.grids[k], self.rss[k], self.n_fine
         comet.sparse_select(src_g, src_r, src_n, self.F, self.final_idx, self._final_new,
                             ref_rss=self.final_rss, ref_grids=self.final_grids,
                             ref_local=self.final_local)
-        comet.batch_classify(self.packed, self.part_event_f, self.final_grids.view(-1, 14),
-                             src_n, self.cfg, self.final_local.view(-1),
+        comet.batch_classify(packed, self.part_event_f, self.final_grids.view(-1, 14),
+                             src_n, cfg, self.final_local.view(-1),
                              best_seed=self.final_seed, hit_mask=self.mask,
                              n_borderline=self.n_border)
+
+
+class MultiRefRunner(MultiRefScan):
+    """MultiRefScan over every turn partition of a list of events, with the first grids
+    centred on each turn's true state at the seed radius."""
+
+    def __init__(self, events, scan_cfg: synth.ScanConfig, n_ref: int = 10, n_iter: int = 2,
+                 n_fine=(4, 8, 8, 8), n_final: int = 10, device="cuda"):
+        from .synth import grid_descriptor
+        self.events = list(events)
+        self.sc = scan_cfg
+        self.cfg = scan.config_for(self.events[0], scan_cfg)
+        self.packed = scan.PackedEvents.from_events(self.events, device)
+        part_event, grids = [], []
+        for e, ev in enumerate(self.events):
+            for t in range(ev.n_turns):
+                part_event.append(e)
+                grids.append(grid_descriptor(ev.ref_states[t], scan_cfg))
+        pe = torch.as_tensor(np.asarray(part_event, dtype=np.int32), device=device)
+        super().__init__(pe, scan_cfg.n, n_fine, n_ref, n_iter, n_final,
+                         max(ev.n_hits for ev in self.events),
+                         int(self.packed.wire_ends.shape[0]), scan_cfg.n_steps, device)
+        self.grids0.copy_(torch.as_tensor(np.stack(grids), device=device))
+        self.graph = None
+
+    @property
+    def evals_per_run(self) -> int:
+        """Seed x hit evaluations of one run (every scan of every partition)."""
+        hits = np.asarray([self.events[e].n_hits for e in self.part_event.cpu().numpy()])
+        return int(hits.sum()) * self.seeds_per_partition
+
+    def run(self) -> None:
+        super().run(self.packed, self.cfg)
 
     def capture(self) -> None:
         """Capture one run into a HIP graph (replay() then repeats it)."""

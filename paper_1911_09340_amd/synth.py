@@ -516,6 +516,20 @@ def _sub_event(ev: Event, wire_sel: np.ndarray, state, charge: float, meta: dict
                  charge=charge, bz=ev.bz, meta=dict(meta, hits=hits))
 
 
+def entrance_sides(ev: Event, turn: int) -> np.ndarray:
+    """bool [n_wires]: the wires on the entrance side of the turn (Sec. 3.1's half
+    tracks): the side, of the line through the chamber axis and the turn's true circle
+    centre, that holds the turn's outward crossing of r = 500 mm; each wire taken at its
+    midpoint (z = 0), a wire exactly on the line on the entrance side. The true circle
+    stands in for the paper's Hough-transform circle."""
+    ref = ev.ref_states[turn]
+    c = circle_centre(ref, ev.charge, ev.bz)
+    mid = 0.5 * (ev.wire_ends[:, :2] + ev.wire_ends[:, 3:5])
+    side = c[0] * mid[:, 1] - c[1] * mid[:, 0]
+    s_in = c[0] * ref[1] - c[1] * ref[0]
+    return (side == 0.0) | (np.sign(side) == np.sign(s_in))
+
+
 def half_events(ev: Event, turn: int):
     """The two half tracks of one turn partition (Sec. 3.1) as one-turn pseudo-events.
 
@@ -530,11 +544,7 @@ def half_events(ev: Event, turn: int):
     """
     ref = ev.ref_states[turn]
     ext = ev.exit_states[turn]
-    c = circle_centre(ref, ev.charge, ev.bz)
-    mid = 0.5 * (ev.wire_ends[:, :2] + ev.wire_ends[:, 3:5])
-    side = c[0] * mid[:, 1] - c[1] * mid[:, 0]
-    s_in = c[0] * ref[1] - c[1] * ref[0]
-    entrance = (side == 0.0) | (np.sign(side) == np.sign(s_in))
+    entrance = entrance_sides(ev, turn)
     flipped = np.concatenate([ext[:3], -ext[3:]])
     a = _sub_event(ev, entrance, ref, ev.charge, {"turn": turn, "side": "entrance"})
     b = _sub_event(ev, ~entrance, flipped, -ev.charge, {"turn": turn, "side": "exit"})

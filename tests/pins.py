@@ -653,6 +653,39 @@ def pin_backward_seed_helix(o):
     assert k == -1 and np.isnan(out).all()
 
 
+def pin_exit_seed_helix(o):
+    """The exit half's seed (Sec. 3.1) against the exact helix: from a turn's entry (its
+    outward crossing of r = R), the turn's next inward crossing with the momentum
+    reversed, within the RK4 error and the chord interpolation (0.01 mm and 1e-3 MeV/c at
+    2 mm steps, 1e-4 mm and 1e-5 MeV/c at 0.1 mm), p_z exactly reversed. By the mirror
+    symmetry of the circle and the cylinder the exit point is also the entry reflected
+    across the line through the axis and the circle's centre. A straight track (no
+    field) never comes back: NaN; too few steps: NaN."""
+    from paper_1911_09340_amd import synth
+    for p, pol, az in ((100.0, 1.2, 0.3), (80.0, 1.35, 2.0), (104.0, 1.9, 4.0)):
+        st0 = synth.vertex_state(p, pol, az)
+        L = synth.turn_length(st0, -1.0, 1.0)
+        s_in = synth._outward_crossing(st0, -1.0, 1.0, L + 1.0)
+        entry = synth.helix_state(st0, -1.0, 1.0, s_in)
+        s_out = synth._inward_crossing(st0, -1.0, 1.0, s_in, s_in + L)
+        assert s_in is not None and s_out is not None
+        ex = synth.helix_state(st0, -1.0, 1.0, s_out)
+        for h, tx, tp in ((2.0, 0.01, 1e-3), (0.1, 1e-4, 1e-5)):
+            out, k = o.exit_seed(entry, 1.0, -1.0, h, synth.SEED_RADIUS, int(2 * L / h))
+            assert k > 0, (p, pol, h)
+            assert np.max(np.abs(out[:3] - ex[:3])) < tx, (out, ex)
+            assert np.max(np.abs(out[3:5] + ex[3:5])) < tp, (out, ex)
+            assert out[5] == -entry[5]
+        c = synth.circle_centre(entry, -1.0, 1.0)
+        u = c / np.hypot(c[0], c[1])
+        mirror = 2.0 * (entry[:2] @ u) * u - entry[:2]
+        assert np.max(np.abs(out[:2] - mirror)) < 1e-4, (out[:2], mirror)
+    out, k = o.exit_seed(entry, 0.0, -1.0, 2.0, synth.SEED_RADIUS, 2000)
+    assert k == -1 and np.isnan(out).all()
+    out, k = o.exit_seed(entry, 1.0, -1.0, 2.0, synth.SEED_RADIUS, 10)
+    assert k == -1 and np.isnan(out).all()
+
+
 def pin_stage_grid(o):
     t = np.array([1.0, 2.0, 3.0, 3.0, 4.0, 6.0])
     e = np.array([9.0, 9.0, -7.0, 9.0, 9.0, 12.0])
@@ -752,7 +785,7 @@ def pin_self_refine_at_scan_seed(o):
     assert (mask & 1).any() and np.array_equal(out, mask & 1) and n == int((mask & 1).sum())
 
 
-ALL_SIMPLE.extend([pin_backward_seed_helix, pin_stage_grid, pin_stage_grids_z, pin_exclude_hits,
+ALL_SIMPLE.extend([pin_backward_seed_helix, pin_exit_seed_helix, pin_stage_grid, pin_stage_grids_z, pin_exclude_hits,
                    pin_self_refine_hand, pin_self_refine_at_scan_seed])
 
 

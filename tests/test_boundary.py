@@ -329,6 +329,46 @@ def test_stage_calls_reject(lib):
     assert lib.comet_self_refine(*bad) == comet.EUNSUPPORTED
 
 
+def test_chain_calls_reject(lib):
+    """The per-stage chain's joins reject NULL pointers and bad sizes before device work."""
+    comet._bind_batch(lib)
+    cfg = _cfg()
+    ok = [_p(), 14, 3, ctypes.byref(cfg), 500.0, 10, _p(), None, None]
+    assert lib.comet_exit_seeds(*ok) != comet.EINVAL        # valid: fails later (no GPU)
+    for i, v in ((0, None), (6, None), (1, 5), (2, 0), (4, -1.0), (4, float("nan")), (5, 0)):
+        bad = list(ok)
+        bad[i] = v
+        assert lib.comet_exit_seeds(*bad) == comet.EINVAL, (i, v)
+    ok = [_p(), 2, _p(), _p(), 20, _p(), 20, _p(), _p(), None]
+    for i in (0, 2, 3, 5, 7, 8):
+        bad = list(ok)
+        bad[i] = None
+        assert lib.comet_half_split(*bad) == comet.EINVAL, i
+    for i in (1, 4, 6):
+        bad = list(ok)
+        bad[i] = 0
+        assert lib.comet_half_split(*bad) == comet.EINVAL, i
+    ok = [_p(), 2, _p(), 10, _p(), _p(), 20, _p(), None]
+    for i in (0, 2, 4, 5, 7):
+        bad = list(ok)
+        bad[i] = None
+        assert lib.comet_wire_layers(*bad) == comet.EINVAL, i
+    for i in (1, 3, 6):
+        bad = list(ok)
+        bad[i] = 0
+        assert lib.comet_wire_layers(*bad) == comet.EINVAL, i
+    ok = [_p(), _p(), 4, 2, _p(), _p(), _p(), _p(), 20, _p(), 8, _p(), 8, _p(), _p(), _p(), 8,
+          _p(), _p(), None]
+    for i in (0, 1, 4, 5, 6, 7, 9, 11, 13, 14, 15, 17, 18):
+        bad = list(ok)
+        bad[i] = None
+        assert lib.comet_union_halves(*bad) == comet.EINVAL, i
+    for i, v in ((2, 0), (2, 65), (3, 0), (8, 0), (10, 0), (12, 0), (16, 0)):
+        bad = list(ok)
+        bad[i] = v
+        assert lib.comet_union_halves(*bad) == comet.EINVAL, (i, v)
+
+
 def test_field_call_rejects(lib):
     lib.comet_extrapolate_seeds_field.argtypes = [ctypes.c_void_p, ctypes.c_int64,
                                                   ctypes.POINTER(comet.Config),

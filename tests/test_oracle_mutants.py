@@ -63,6 +63,10 @@ MUTANTS = {
     "backward_first_inward": ("        else if (out_seen && da >= 0.0 && db < 0.0) {", "        else if (da >= 0.0 && db < 0.0) {"),
     "backward_no_flip_back": ("            out6[3] = -out6[3];\n            out6[4] = -out6[4];", "            out6[3] = out6[3];\n            out6[4] = out6[4];"),
     "backward_charge_kept": ("rk4_setup(s[3], s[4], s[5], bz, -charge, h)", "rk4_setup(s[3], s[4], s[5], bz, charge, h)"),
+    "exit_not_reversed": ("                out6[j] = -fma(w, s[j] - a[j], a[j]);", "                out6[j] = fma(w, s[j] - a[j], a[j]);"),
+    "exit_interp_from_end": ("                out6[j] = fma(w, s[j] - a[j], a[j]);\n            for (int j = 3;", "                out6[j] = fma(w, a[j] - s[j], s[j]);\n            for (int j = 3;"),
+    "exit_first_outward": ("        if (outside && da >= 0.0 && db < 0.0) {", "        if (da < 0.0 && db >= 0.0) {"),
+    "exit_charge_reversed": ("    const rk4_consts kc = rk4_setup(s[3], s[4], s[5], bz, charge, h);\n    const double R2 = radius * radius;\n    int outside = 0;", "    const rk4_consts kc = rk4_setup(s[3], s[4], s[5], bz, -charge, h);\n    const double R2 = radius * radius;\n    int outside = 0;"),
     "backward_interp_reversed": ("            const double f = da / (da - db);", "            const double f = db / (db - da);"),
     "stage_grid_keeps_truth_z": ("    grid[2] = ext6[2];\n    grid[5] = ext6[5];", "    grid[5] = ext6[5];"),
     "exclude_keeps_empty_wires": ("        if (nh > h0) {\n            for (int c = 0; c < 6; ++c)", "        if (nh >= h0) {\n            for (int c = 0; c < 6; ++c)"),
