@@ -670,6 +670,61 @@ struct TileScanWide {
         return !((float)q0 * 0.999999f > (B * B) * 1.000001f);
     }
 
+    // The end of a wide scan for one seed lane: per wire the first index of the minimum
+    // within the SPAN points from kbest (eight loads at a time, no dependent load
+    // chain), its chord refinement, D and Eq. 1's capped residual. With the cap, a wire
+    // whose minimum stayed above the cap (or that no point came near) has every point
+    // farther than r_max + lambda + the longest step, hence every chord farther than
+    // r_max + lambda: its term is lambda^2, the full scan's, without a rescan.
+    template <int SPAN, bool CAPPED>
+    __device__ __forceinline__ static void finish(
+        const double *__restrict__ bx, const double *__restrict__ by,
+        const double *__restrict__ bz, int64_t ld, int P, int lane, const double *fl, int nw,
+        const int32_t *__restrict__ wire_of, const int32_t *__restrict__ offsets,
+        const double *__restrict__ drift, double lambda, const double (&best)[W],
+        const int (&kbest)[W], const double *__restrict__ rmax, double sig, double (&dsq)[W])
+    {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (w >= nw)
+                continue;
+            if constexpr (CAPPED) {
+                const double c = (double)wide_cap(rmax[w], lambda, sig);
+                if (!(best[w] <= c * c)) {
+                    dsq[w] = lambda * lambda;
+                    continue;
+                }
+            }
+            double f[8];
+            frame(fl, w, f);
+            const int k = kbest[w];
+            int kf = -1;
+            for (int h0 = 0; h0 < SPAN && kf < 0; h0 += 8) {
+                double q[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int j = k + h0 + i;
+                    q[i] = NAN;  // never equal: past the track's end
+                    if (j < P) {
+                        const int64_t o = (int64_t)j * ld + lane;
+                        q[i] = qf(f, bx[o], by[o], bz[o]);
+                    }
+                }
+#pragma unroll
+                for (int i = 7; i >= 0; --i)
+                    if (q[i] == best[w])
+                        kf = k + h0 + i;
+            }
+            if (kf < 0)
+                kf = k;
+            const double d2 = refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f, kf, best[w]);
+            const double D = sqrt(d2);
+            const int wi = wire_of[w];
+            const double d = capped_residual(D, drift, offsets[wi], offsets[wi + 1], lambda);
+            dsq[w] = d * d;
+        }
+    }
+
     // bx, by, bz: the tile's track (point k of lane l at b[k * ld + l]); fl: this wave's
     // W frames in LDS ([W][8], slots >= nw hold anything finite); wire_of: the wave's
     // slots' wire indices (CSR rows of offsets/drift); rho: the tile's chunk radii, with
@@ -721,8 +776,9 @@ struct TileScanWide {
                 z = bz[o];
             }
         };
+        double sig = 0.0;  // the track's longest step (the cap)
         if (CAP && nw > 0) {
-            const double sig = rho[(int64_t)radius_chunks(P) * ldr + col];
+            sig = rho[(int64_t)radius_chunks(P) * ldr + col];
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 sub[w] = w < nw ? wide_cap(rmax[w], lambda, sig) : 0.0f;
@@ -881,27 +937,9 @@ struct TileScanWide {
             dsq[w] = 0.0;
         if (nw <= 0 || !seed)
             return;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            if (w < nw) {
-                double f[8];
-                frame(fl, w, f);
-                int k = kbest[w];
-                const int kend = min(k + C, P);
-                for (int j = k; j < kend; ++j) {
-                    const int64_t o = (int64_t)j * ld + lane;
-                    if (qf(f, bx[o], by[o], bz[o]) == best[w]) {
-                        k = j;
-                        break;
-                    }
-                }
-                const double d2 = refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f, k, best[w]);
-                const double D = sqrt(d2);
-                const int wi = wire_of[w];
-                const double d = capped_residual(D, drift, offsets[wi], offsets[wi + 1], lambda);
-                dsq[w] = d * d;
-            }
-        }
+        // the last chunk may hold up to C points in its one recorded span
+        finish<C, CAP>(bx, by, bz, ld, P, lane, fl, nw, wire_of, offsets, drift, lambda, best,
+                       kbest, rmax, sig, dsq);
     }
 };
 
@@ -1006,8 +1044,9 @@ struct TileScanWideP {
             }
             evals += (int64_t)__builtin_popcount(mask) * n;
         };
+        double sig = 0.0;  // the track's longest step (the cap)
         if (CAP && nw > 0) {
-            const double sig = rho[(int64_t)radius_chunks(P) * ldr + col];
+            sig = rho[(int64_t)radius_chunks(P) * ldr + col];
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 sub[w] = w < nw ? wide_cap(rmax[w], lambda, sig) : 0.0f;
@@ -1173,27 +1212,8 @@ struct TileScanWideP {
             dsq[w] = 0.0;
         if (nw <= 0 || !seed)
             return;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            if (w < nw) {
-                double f[8];
-                Base::frame(fl, w, f);
-                int k = kbest[w];
-                const int kend = min(k + H, P);
-                for (int j = k; j < kend; ++j) {
-                    const int64_t o = (int64_t)j * ld + lane;
-                    if (Base::qf(f, bx[o], by[o], bz[o]) == best[w]) {
-                        k = j;
-                        break;
-                    }
-                }
-                const double d2 = refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f, k, best[w]);
-                const double D = sqrt(d2);
-                const int wi = wire_of[w];
-                const double d = capped_residual(D, drift, offsets[wi], offsets[wi + 1], lambda);
-                dsq[w] = d * d;
-            }
-        }
+        Base::template finish<H, CAP>(bx, by, bz, ld, P, lane, fl, nw, wire_of, offsets, drift,
+                                      lambda, best, kbest, rmax, sig, dsq);
     }
 };
 
