@@ -602,8 +602,10 @@ int comet_union_halves(const int32_t *pair, const int32_t *n_complete, int32_t n
 
 /* Shapes of the batched scan kernel (W wires per wave, NWV waves per block, C points
  * per LDS chunk, the persistent block count on the current device, and direct and runs
- * as for the DCA shapes; blocks, direct and runs may be NULL); every shape gives the
- * same results. comet_batch_set_variant selects the shape (default 0). */
+ * as for the DCA shapes, with direct = 4 for the wide form with the residual cap whose
+ * waves take each event's wires in azimuth order (events of more than 3 (n_steps + 1)
+ * wires in wire order); blocks, direct and runs may be NULL); every shape gives the same results.
+ * comet_batch_set_variant selects the shape (default 0). */
 int comet_batch_variant_count(void);
 int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks,
                              int32_t *direct, int32_t *runs);

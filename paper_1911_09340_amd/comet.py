@@ -591,7 +591,7 @@ def batch_variants():
         v = [ctypes.c_int32() for _ in range(6)]
         _check(lib.comet_batch_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_batch_variant_info")
-        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap"}[v[4].value]
+        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap", 4: "wide_cap_az"}[v[4].value]
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value, blocks=v[3].value,
                         direct=form != "lds", form=form, runs=v[5].value))
     return out

@@ -60,6 +60,11 @@ struct BatchArgs {
     unsigned long long *evals;  // profiling: distance evaluations, or null
     FieldMap fm;              // the field map of the FIELD kernel (tracks as field.hip records them)
     const int32_t *active;    // [E] or null: the partitions of events with active[e] == 0 are skipped
+    // wires in azimuth order within each event (slot r holds wire wire_of_az[r], its frame
+    // and its largest drift distance)
+    const double *frames_az;
+    const int32_t *wire_of_az;
+    const double *caps_az;
 };
 
 // One seed's track in the map into a tile's scratch rows (stride 64) with its chunk
@@ -254,10 +259,20 @@ batch_scan_kernel(BatchArgs a)
 // order as in the single-event path. No block barrier: a wave that finishes a
 // partition's last tile selects its best seed on its own. WPE: waves per SIMD the
 // registers are sized for.
-template <int W, int NWV, int SUP, int WPE, bool FIELD = false, bool CAP = false>
+//
+// AZ: the wires are taken in azimuth order within the event (the order of the
+// single-event wide form: a wave's wires then need nearly the same track chunks), each
+// wire's d^2 goes to the wave's own rows and the tile's RSS is summed from them in wire
+// order at the end, so that every sum is the same as in wire order. The rows lie in the
+// half of the scratch that shapes of at most kMaxBatchNwv / 2 waves leave unused (one
+// tile's room per wave: 3 (K + 1) + the radius rows, at least 3 (K + 1) wires); an event
+// with more wires takes them in wire order.
+template <int W, int NWV, int SUP, int WPE, bool FIELD = false, bool CAP = false,
+          bool AZ = false>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_wide_kernel(BatchArgs a)
 {
+    static_assert(!AZ || 2 * NWV <= kMaxBatchNwv, "the d^2 rows need the scratch's other half");
     __shared__ __align__(16) double fl_all[NWV * W * 8];
     __shared__ double rmax_all[NWV * W];
     const int lane = threadIdx.x & 63;
@@ -309,34 +324,55 @@ batch_wide_kernel(BatchArgs a)
         // the scan's loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         double acc = 0.0;
+        const int64_t tile_room = 3 * row + rrow;  // doubles of one tile's scratch
+        const bool az = AZ && (int64_t)(w1 - w0) * 64 <= tile_room;  // wave-uniform
+        double *const dq =
+            AZ ? a.scratch + ((int64_t)kMaxBatchBlocks * NWV + (int64_t)blockIdx.x * NWV + wave) *
+                                 tile_room
+               : nullptr;
+        const double *const frames = az ? a.frames_az : a.frames;
         for (int g0 = w0; g0 < w1; g0 += W) {
             const int nw = min(W, w1 - g0);  // wave-uniform
             // the group's frames into this wave's LDS rows (zero frames past the event)
             for (int i = lane; i < W * 8; i += 64)
-                fl[i] = i < nw * 8 ? a.frames[8 * (int64_t)g0 + i] : 0.0;
+                fl[i] = i < nw * 8 ? frames[8 * (int64_t)g0 + i] : 0.0;
             if (CAP && lane < W) {
                 // each wire's largest drift distance (-1 without hits), for the cap
                 double r = -1.0;
-                if (lane < nw)
-                    for (int j = a.offsets[g0 + lane]; j < a.offsets[g0 + lane + 1]; ++j)
-                        r = a.drift[j] > r ? a.drift[j] : r;
+                if (lane < nw) {
+                    if (az)
+                        r = a.caps_az[g0 + lane];
+                    else
+                        for (int j = a.offsets[g0 + lane]; j < a.offsets[g0 + lane + 1]; ++j)
+                            r = a.drift[j] > r ? a.drift[j] : r;
+                }
                 rmx[lane] = r;
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             int32_t wire_of[W];
 #pragma unroll
             for (int w = 0; w < W; ++w)
-                wire_of[w] = g0 + w;
+                wire_of[w] = az && w < nw ? a.wire_of_az[g0 + w] : g0 + w;
             double d2[W];
             TileScanWide<W, SUP, true, CAP>::run(sx, sy, sz, 64, P, n_valid, fl, nw, wire_of,
                                                  a.offsets, a.drift, a.lambda, rho, 64, a.evals,
                                                  d2, rmx);
+            if (az) {
 #pragma unroll
-            for (int w = 0; w < W; ++w)
-                if (w < nw)
-                    acc = acc + d2[w];
+                for (int w = 0; w < W; ++w)
+                    if (w < nw)
+                        dq[(int64_t)(wire_of[w] - w0) * 64 + lane] = d2[w];
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (w < nw)
+                        acc = acc + d2[w];
+            }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // frames read before reuse
         }
+        if (az)  // each lane reads back its own column, in wire order
+            for (int i = 0; i < w1 - w0; ++i)
+                acc = acc + dq[(int64_t)i * 64 + lane];
         if (lane < n_valid)
             a.rss[(int64_t)p * a.S + s0 + lane] = acc;
         // completion counter of partition p; the wave that counts its last tile selects
@@ -718,16 +754,64 @@ __global__ void grid_seeds_kernel(const double *__restrict__ grids, int n0, int 
 }
 
 __global__ void batch_frames_kernel(const double *__restrict__ ends, int n_w, int n_pad,
-                                    double *__restrict__ frames)
+                                    double *__restrict__ frames, float *__restrict__ key)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= n_pad)
         return;
     double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (w < n_w)
-        wire_frame(ends + 6 * (int64_t)w, f);
+    float k = INFINITY;
+    if (w < n_w) {
+        const double *e = ends + 6 * (int64_t)w;
+        wire_frame(e, f);
+        // the azimuth of the wire's midpoint; a NaN endpoint sorts after every azimuth
+        k = atan2f((float)(e[1] + e[4]), (float)(e[0] + e[3]));
+        if (k != k)
+            k = 4.0f;
+    }
     for (int j = 0; j < 8; ++j)
         frames[8 * (int64_t)w + j] = f[j];
+    key[w] = k;
+}
+
+// The wires of each event in azimuth order: wire i of event e goes to slot w0 + its rank
+// among the event's wires in (key, index) order, with its frame and its largest drift
+// distance (-1 without hits). Only the wires of the events are touched.
+__global__ void batch_wire_order_kernel(const double *__restrict__ frames,
+                                        const float *__restrict__ key,
+                                        const int32_t *__restrict__ ev_wires, int n_events,
+                                        const int32_t *__restrict__ offsets,
+                                        const double *__restrict__ drift,
+                                        double *__restrict__ frames_az,
+                                        int32_t *__restrict__ wire_of_az,
+                                        double *__restrict__ caps_az)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ev_wires[n_events] || i < ev_wires[0])
+        return;
+    int lo = 0, hi = n_events;  // the event e with ev_wires[e] <= i < ev_wires[e + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (ev_wires[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int w0 = ev_wires[lo], w1 = ev_wires[lo + 1];
+    const float ki = key[i];
+    int rank = 0;
+    for (int j = w0; j < w1; ++j) {
+        const float kj = key[j];
+        rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    const int r = w0 + rank;
+    for (int j = 0; j < 8; ++j)
+        frames_az[8 * (int64_t)r + j] = frames[8 * (int64_t)i + j];
+    wire_of_az[r] = i;
+    double rmax = -1.0;
+    for (int j = offsets[i]; j < offsets[i + 1]; ++j)
+        rmax = drift[j] > rmax ? drift[j] : rmax;
+    caps_az[r] = rmax;
 }
 
 // Start of a scan: empty work queue, no tile finished, no partition selected yet.
@@ -778,6 +862,10 @@ const BatchVariant kBatchVariants[] = {
     {16, 4, 16, 3, batch_wide_kernel<16, 4, 4, 2, false, true>, 4},
     {12, 4, 16, 3, batch_wide_kernel<12, 4, 4, 2, false, true>, 4},
     {8, 4, 16, 3, batch_wide_kernel<8, 4, 4, 2, false, true>, 4},
+    // wide with the cap, wires in azimuth order within each event (direct == 4)
+    {16, 4, 16, 4, batch_wide_kernel<16, 4, 4, 2, false, true, true>, 4},
+    {12, 4, 16, 4, batch_wide_kernel<12, 4, 4, 2, false, true, true>, 4},
+    {8, 4, 16, 4, batch_wide_kernel<8, 4, 4, 2, false, true, true>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
@@ -831,19 +919,32 @@ struct BatchLayout {
     int *counter;
     int *done;
     double *scratch;
+    float *key;
+    double *frames_az;
+    int32_t *wire_of_az;
+    double *caps_az;
 };
 
-BatchLayout batch_layout(void *ws, int n_wires, int n_partitions)
+BatchLayout batch_layout(void *ws, int n_wires, int n_partitions, int K)
 {
     char *p = (char *)ws;
+    const size_t pad = (size_t)frames_pad(n_wires);
     BatchLayout l;
     l.frames = (double *)p;
-    p += align256(sizeof(double) * 8 * (size_t)frames_pad(n_wires));
+    p += align256(sizeof(double) * 8 * pad);
     l.counter = (int *)p;
     p += 256;
     l.done = (int *)p;
     p += align256(sizeof(int) * (size_t)n_partitions);
     l.scratch = (double *)p;
+    p += (size_t)kMaxBatchBlocks * batch_scratch_bytes(K);
+    l.key = (float *)p;
+    p += align256(sizeof(float) * pad);
+    l.frames_az = (double *)p;
+    p += align256(sizeof(double) * 8 * pad);
+    l.wire_of_az = (int32_t *)p;
+    p += align256(sizeof(int32_t) * pad);
+    l.caps_az = (double *)p;
     return l;
 }
 
@@ -881,9 +982,12 @@ size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps, int32_t n_p
 {
     if (n_wires < 0 || n_steps < 1 || n_partitions < 0)
         return 0;
-    return align256(sizeof(double) * 8 * (size_t)frames_pad(n_wires)) + 256 +
+    const size_t pad = (size_t)frames_pad(n_wires);
+    return align256(sizeof(double) * 8 * pad) + 256 +
            align256(sizeof(int) * (size_t)n_partitions) +
-           (size_t)kMaxBatchBlocks * batch_scratch_bytes(n_steps);
+           (size_t)kMaxBatchBlocks * batch_scratch_bytes(n_steps) + align256(sizeof(float) * pad) +
+           align256(sizeof(double) * 8 * pad) + align256(sizeof(int32_t) * pad) +
+           align256(sizeof(double) * pad);
 }
 
 }  // extern "C"
@@ -934,7 +1038,7 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
     if (st)
         return st;
     hipStream_t hs = (hipStream_t)stream;
-    const BatchLayout l = batch_layout(workspace, n_wires, n_partitions);
+    const BatchLayout l = batch_layout(workspace, n_wires, n_partitions, cfg->n_steps);
     if (grids_init) {
         const int64_t nd = 14 * (int64_t)n_partitions;
         hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, hs,
@@ -945,7 +1049,7 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
     }
     const int pad = frames_pad(n_wires);
     hipLaunchKernelGGL(batch_frames_kernel, dim3((pad + 63) / 64), dim3(64), 0, hs, wire_ends,
-                       n_wires, pad, l.frames);
+                       n_wires, pad, l.frames, l.key);
     st = launched("batch_frames_kernel");
     if (st)
         return st;
@@ -957,6 +1061,14 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
     if (field)
         id = kNumBatchVariants;  // the field-map kernel
     const BatchVariant &v = batch_variant(id);
+    if (v.direct == 4) {
+        hipLaunchKernelGGL(batch_wire_order_kernel, dim3((n_wires + 255) / 256), dim3(256), 0, hs,
+                           (const double *)l.frames, (const float *)l.key, event_wires, n_events,
+                           wire_offsets, drift, l.frames_az, l.wire_of_az, l.caps_az);
+        st = launched("batch_wire_order_kernel");
+        if (st)
+            return st;
+    }
     const int blocks = batch_blocks(id);
     if (blocks < 1)
         return fail(COMET_EHIP, "comet_batch_scan: occupancy query failed");
@@ -972,7 +1084,8 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
     BatchArgs args{l.frames, wire_offsets, drift, event_wires, part_event, grids, n[0], n[1],
                    n[2], n[3], S, tiles, supers, items, max_tiles, cfg->bz_tesla,
                    cfg->charge_e, cfg->step_mm, cfg->lambda_mm, cfg->n_steps, l.scratch,
-                   l.counter, l.done, rss, best, scan_counter(), field_map(field), event_active};
+                   l.counter, l.done, rss, best, scan_counter(), field_map(field), event_active,
+                   l.frames_az, l.wire_of_az, l.caps_az};
     for (int it = 0; it <= n_refine && st == COMET_OK; ++it) {
         if (it) {
             hipLaunchKernelGGL(batch_refine_kernel, dim3((n_partitions + 255) / 256), dim3(256), 0,

@@ -83,6 +83,33 @@ def test_batch_many_tiles_per_partition(events):
     comet.set_batch_variant(0)
 
 
+def test_batch_azimuth_shapes_on_an_event_past_their_wire_limit(events):
+    """The shapes that take each event's wires in azimuth order keep the d^2 of
+    3 (K + 1) + (K / 16 + 2) wires per wave; an event with more (here ~1200 wires, most of
+    them noise, at K = 300: a limit of 923) takes the wires in wire order. Every such shape
+    gives the bits of shape 0 on it and on a normal event."""
+    import numpy as np
+    from dataclasses import replace
+    sc = replace(SC, n_steps=300)
+    big = synth.event_mix(3, noise_frac=0.85, hits=(1000, 2000))
+    assert big.n_wires > 3 * 301 + 301 // 16 + 2 and events[0].n_wires < 900
+    evs = [big, events[0]]
+    az = [i for i, v in enumerate(comet.batch_variants()) if v["form"] == "wide_cap_az"]
+    assert az
+    ref = None
+    for i in [0] + az:
+        comet.set_batch_variant(i)
+        runner = scan.BatchRunner(evs, sc)
+        runner.run()
+        got = (runner.rss.cpu().numpy(), runner.best.cpu().numpy(), runner.mask.cpu().numpy())
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), i
+    comet.set_batch_variant(0)
+
+
 def test_batch_every_shape_identical(events):
     ref = None
     for i in range(len(comet.batch_variants())):
