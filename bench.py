@@ -10,7 +10,7 @@ device memory when the timed region starts.
 
 Prints one JSON line. `value` = seed x hit DCA evaluations per second (sum over
 scans of seeds x hits, divided by wall time of the timed steps, which run without
-any event timing). `roofline` covers the dominant kernel (the DCA scan), from a
+any event timing; the three partitions are independent and run on a stream each). `roofline` covers the dominant kernel (the DCA scan), from a
 separate pass that records HIP events around each launch on its stream: its two
 ceilings are the FP64 flops of the distance evaluations it performs (15 per (seed,
 wire, point) evaluated, counted by the kernel; the scan skips points that a distance
@@ -22,9 +22,10 @@ read of the track and its window radii, d^2 written) per second.
 workload on the host cores. Further sections (each can be switched off): the same
 step with tracks in a field map (RK4 and Runge-Kutta-Nystrom, and the batched scan in
 the map), the batched persistent scan of the 1024-event mix, several references, half
-tracks, the stage loop (with and without the self-refining) and the first stage's
-efficiency and purity against lambda on 64 events of the mix, the gradient comparison on 256 events (coarse grid + Levenberg-Marquardt vs a
-fine grid) and 64 events of the stress mix.
+tracks, the stage loop (plain, with the self-refining, with the seed's z axis), the
+paper's per-stage chain and the first stage's efficiency and purity against lambda on
+64 events of the mix, the gradient comparison on 256 events (coarse grid +
+Levenberg-Marquardt vs a fine grid) and 64 events of the stress mix.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
   python bench.py --sweep             # time every DCA kernel shape
@@ -484,6 +485,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="time the signal step's partitions one after another on one stream")
     ap.add_argument("--batch-events", type=int, default=1024,
                     help="events of the batched mix timed through the persistent batched path "
                          "(0 = skip; 1024 = the full batching workload)")
@@ -558,22 +561,37 @@ def main():
     evals_per_step = scans_per_step * sc.n_seeds * ev.n_hits
     P = sc.n_steps + 1
 
-    def step():
+    # the partitions are independent: each runs its chain of scans on a stream of its own
+    # (default priority), so that one partition's small kernels and launch gaps overlap
+    # another's scans
+    streams = [torch.cuda.Stream() for _ in range(ev.n_turns)]
+
+    def step(concurrent=True):
+        if not concurrent or args.one_stream:
+            for t in range(ev.n_turns):
+                runners[t].run(dev, grids[t], sc.n_refine)
+            return
+        cur = torch.cuda.current_stream()
         for t in range(ev.n_turns):
-            runners[t].run(dev, grids[t], sc.n_refine)
+            streams[t].wait_stream(cur)
+            with torch.cuda.stream(streams[t]):
+                runners[t].run(dev, grids[t], sc.n_refine)
+        for t in range(ev.n_turns):
+            cur.wait_stream(streams[t])
 
     def timed(steps, warmup, profile=False):
         """Wall time of `steps` steps; with profile, per-kind kernel times from HIP events
-        and the DCA scans' evaluation count (a separate pass: the headline runs without
-        them)."""
+        and the DCA scans' evaluation count (a separate pass, with the partitions one
+        after another on one stream so that each launch's time is its own: the headline
+        runs without them, the partitions on streams of their own)."""
         for _ in range(warmup):
-            step()
+            step(not profile)
         torch.cuda.synchronize()
         if profile:
             comet.profile_begin()
         t0 = time.perf_counter()
         for _ in range(steps):
-            step()
+            step(not profile)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         return t1 - t0, (comet.profile_end() if profile else None)
