@@ -312,3 +312,30 @@ def test_stage_chain_matches_cpu(orc, fit_iters):
         n_stages += len(per_stage)
         h0 += ev.n_hits
     assert n_stages > len(events) and n_complete > 0
+
+
+def test_stage_chain_bench_size_matches_cpu(orc):
+    """The chain at the bench's sizes (each half: 8 x 16 x 16 x 16 first grid, 10
+    references, two re-scans of 10 x 4 x 8 x 8 x 8, 10 final seeds, 500 x 2 mm; the fit
+    with 8 LM iterations over 1000 x 2 mm) on a two-turn event: both stages' pairs,
+    complete-set counts and seeds, and the stage of every hit."""
+    events = [synth.event_mix(0)]
+    sc = synth.C2
+    F = 10
+    run = chain.StageChainRunner(events, sc, n_ref=10, n_iter=2, n_fine=(4, 8, 8, 8),
+                                 n_final=F, fit_iters=8, eta=0.3)
+    run.run()
+    torch.cuda.synchronize()
+    want, per_stage = _oracle_chain_stages(orc, events[0], sc, 5, 30, 4000, (4, 8, 8, 8), 10, 2,
+                                           F, 8, 0.3)
+    assert np.array_equal(run.stage_of_hit.cpu().numpy(), want)
+    best, nc = run.best.cpu().numpy(), run.n_complete_at.cpu().numpy()
+    chosen, fitted = run.chosen.cpu().numpy(), run.fitted.cpu().numpy()
+    assert len(per_stage) == 2
+    for s, (b, seed, fit, wnc) in enumerate(per_stage):
+        assert best[s, 0] == b and nc[s, 0] == wnc, s
+        if s == 0:
+            assert np.array_equal(chosen[s, 0], seed), s
+        else:
+            np.testing.assert_allclose(chosen[s, 0], seed, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(fitted[s, 0], fit, rtol=1e-7, atol=1e-9)
