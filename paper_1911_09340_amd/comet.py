@@ -306,7 +306,7 @@ def dca_variants():
         v = [ctypes.c_int32() for _ in range(7)]
         _check(lib.comet_dca_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_dca_variant_info")
-        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap"}[v[5].value]
+        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap", 5: "wide_cap_x"}[v[5].value]
         lib.comet_dca_variant_name.restype = ctypes.c_char_p
         lib.comet_dca_variant_name.argtypes = [ctypes.c_int]
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value,
@@ -591,7 +591,8 @@ def batch_variants():
         v = [ctypes.c_int32() for _ in range(6)]
         _check(lib.comet_batch_variant_info(i, *[ctypes.byref(x) for x in v]),
                "comet_batch_variant_info")
-        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap", 4: "wide_cap_az"}[v[4].value]
+        form = {0: "lds", 1: "direct", 2: "wide", 3: "wide_cap", 4: "wide_cap_az",
+                5: "wide_cap_az_x"}[v[4].value]
         out.append(dict(w=v[0].value, nwv=v[1].value, chunk=v[2].value, blocks=v[3].value,
                         direct=form != "lds", form=form, runs=v[5].value))
     return out

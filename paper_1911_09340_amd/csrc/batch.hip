@@ -266,9 +266,10 @@ batch_scan_kernel(BatchArgs a)
 // order at the end, so that every sum is the same as in wire order. The rows lie in the
 // half of the scratch that shapes of at most kMaxBatchNwv / 2 waves leave unused (one
 // tile's room per wave: 3 (K + 1) + the radius rows, at least 3 (K + 1) wires); an event
-// with more wires takes them in wire order.
+// with more wires takes them in wire order. EXACT: the scan tracks the first index of
+// each minimum point by point (no rescan at the end).
 template <int W, int NWV, int SUP, int WPE, bool FIELD = false, bool CAP = false,
-          bool AZ = false>
+          bool AZ = false, bool EXACT = false>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_wide_kernel(BatchArgs a)
 {
@@ -354,9 +355,9 @@ batch_wide_kernel(BatchArgs a)
             for (int w = 0; w < W; ++w)
                 wire_of[w] = az && w < nw ? a.wire_of_az[g0 + w] : g0 + w;
             double d2[W];
-            TileScanWide<W, SUP, true, CAP>::run(sx, sy, sz, 64, P, n_valid, fl, nw, wire_of,
-                                                 a.offsets, a.drift, a.lambda, rho, 64, a.evals,
-                                                 d2, rmx);
+            TileScanWide<W, SUP, true, CAP, EXACT>::run(sx, sy, sz, 64, P, n_valid, fl, nw,
+                                                        wire_of, a.offsets, a.drift, a.lambda,
+                                                        rho, 64, a.evals, d2, rmx);
             if (az) {
 #pragma unroll
                 for (int w = 0; w < W; ++w)
@@ -866,6 +867,9 @@ const BatchVariant kBatchVariants[] = {
     {16, 4, 16, 4, batch_wide_kernel<16, 4, 4, 2, false, true, true>, 4},
     {12, 4, 16, 4, batch_wide_kernel<12, 4, 4, 2, false, true, true>, 4},
     {8, 4, 16, 4, batch_wide_kernel<8, 4, 4, 2, false, true, true>, 4},
+    // the same with the first index of the minimum tracked point by point (direct == 5)
+    {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true>, 4},
+    {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
@@ -1061,7 +1065,7 @@ int batch_scan_impl(const double *wire_ends, int32_t n_wires, const int32_t *wir
     if (field)
         id = kNumBatchVariants;  // the field-map kernel
     const BatchVariant &v = batch_variant(id);
-    if (v.direct == 4) {
+    if (v.direct >= 4) {
         hipLaunchKernelGGL(batch_wire_order_kernel, dim3((n_wires + 255) / 256), dim3(256), 0, hs,
                            (const double *)l.frames, (const float *)l.key, event_wires, n_events,
                            wire_offsets, drift, l.frames_az, l.wire_of_az, l.caps_az);

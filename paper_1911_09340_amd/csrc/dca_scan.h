@@ -631,6 +631,11 @@ struct TileScanDirect {
 // of one of its end points), so whatever the scan finds gives d = lambda, exactly as
 // the full scan. A wire without hits (d = lambda always) gets the cap 0. With the cap
 // the pass over every other chunk's first point is not needed and is left out.
+// EXACT: each evaluated point is compared with the running minimum, so the scan ends
+// with the first index of the minimum itself (the definition: the first k whose q is
+// below every earlier q) and the end needs only the three points of the chord
+// refinement, not a rescan of the half chunk that holds it; each lane's rescan reads
+// rows of its own, so the rescan costs far more HBM traffic than its point count says.
 __device__ __forceinline__ float wide_cap(double rmax, double lambda, double sigma)
 {
     if (rmax < 0.0)
@@ -638,7 +643,7 @@ __device__ __forceinline__ float wide_cap(double rmax, double lambda, double sig
     return (float)((rmax + lambda) + sigma) * 1.000001f + 1e-5f;
 }
 
-template <int W, int SUP, bool BUF, bool CAP = false>
+template <int W, int SUP, bool BUF, bool CAP = false, bool EXACT = false>
 struct TileScanWide {
     static constexpr int C = kRadiusChunk;  // one radius window per chunk
     static constexpr int H = C / 2;         // the minimum is tracked per half chunk
@@ -676,7 +681,8 @@ struct TileScanWide {
     // whose minimum stayed above the cap (or that no point came near) has every point
     // farther than r_max + lambda + the longest step, hence every chord farther than
     // r_max + lambda: its term is lambda^2, the full scan's, without a rescan.
-    template <int SPAN, bool CAPPED>
+    // EXACT_K: kbest already holds the first index (no rescan).
+    template <int SPAN, bool CAPPED, bool EXACT_K = false>
     __device__ __forceinline__ static void finish(
         const double *__restrict__ bx, const double *__restrict__ by,
         const double *__restrict__ bz, int64_t ld, int P, int lane, const double *fl, int nw,
@@ -698,25 +704,28 @@ struct TileScanWide {
             double f[8];
             frame(fl, w, f);
             const int k = kbest[w];
-            int kf = -1;
-            for (int h0 = 0; h0 < SPAN && kf < 0; h0 += 8) {
-                double q[8];
+            int kf = k;  // EXACT_K: kbest is the first index itself
+            if constexpr (!EXACT_K) {
+                kf = -1;
+                for (int h0 = 0; h0 < SPAN && kf < 0; h0 += 8) {
+                    double q[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int j = k + h0 + i;
-                    q[i] = NAN;  // never equal: past the track's end
-                    if (j < P) {
-                        const int64_t o = (int64_t)j * ld + lane;
-                        q[i] = qf(f, bx[o], by[o], bz[o]);
+                    for (int i = 0; i < 8; ++i) {
+                        const int j = k + h0 + i;
+                        q[i] = NAN;  // never equal: past the track's end
+                        if (j < P) {
+                            const int64_t o = (int64_t)j * ld + lane;
+                            q[i] = qf(f, bx[o], by[o], bz[o]);
+                        }
                     }
-                }
 #pragma unroll
-                for (int i = 7; i >= 0; --i)
-                    if (q[i] == best[w])
-                        kf = k + h0 + i;
+                    for (int i = 7; i >= 0; --i)
+                        if (q[i] == best[w])
+                            kf = k + h0 + i;
+                }
+                if (kf < 0)
+                    kf = k;
             }
-            if (kf < 0)
-                kf = k;
             const double d2 = refine_dca2(bx + lane, by + lane, bz + lane, ld, P, f, kf, best[w]);
             const double D = sqrt(d2);
             const int wi = wire_of[w];
@@ -871,21 +880,40 @@ struct TileScanWide {
                             if ((needm >> w) & 1u) {
                                 double f[8];
                                 frame(fl, w, f);
-                                double m = qf(f, cx, cy, cz);
+                                if constexpr (EXACT) {
+                                    // point by point: k replaces kbest only below the
+                                    // running minimum (fmin equals that select here: the
+                                    // minimum is never NaN and q is never -0)
+                                    double b = best[w];
+                                    int kb = kbest[w];
+                                    double q = qf(f, cx, cy, cz);
+                                    kb = q < b ? k0 : kb;
+                                    b = fmin(b, q);
 #pragma unroll
-                                for (int i = 1; i < H; ++i)
-                                    m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
-                                if (m < best[w]) {
-                                    best[w] = m;
-                                    kbest[w] = k0;
-                                }
-                                m = qf(f, x[H - 1], y[H - 1], z[H - 1]);
+                                    for (int i = 1; i < C; ++i) {
+                                        q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
+                                        kb = q < b ? k0 + i : kb;
+                                        b = fmin(b, q);
+                                    }
+                                    best[w] = b;
+                                    kbest[w] = kb;
+                                } else {
+                                    double m = qf(f, cx, cy, cz);
 #pragma unroll
-                                for (int i = H + 1; i < C; ++i)
-                                    m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
-                                if (m < best[w]) {
-                                    best[w] = m;
-                                    kbest[w] = k0 + H;
+                                    for (int i = 1; i < H; ++i)
+                                        m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
+                                    if (m < best[w]) {
+                                        best[w] = m;
+                                        kbest[w] = k0;
+                                    }
+                                    m = qf(f, x[H - 1], y[H - 1], z[H - 1]);
+#pragma unroll
+                                    for (int i = H + 1; i < C; ++i)
+                                        m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
+                                    if (m < best[w]) {
+                                        best[w] = m;
+                                        kbest[w] = k0 + H;
+                                    }
                                 }
                                 // the running minimum bounds the final one as well
                                 sub[w] = fminf(sub[w],
@@ -908,14 +936,32 @@ struct TileScanWide {
                         if (w < nw) {
                             double f[8];
                             frame(fl, w, f);
-                            double m = qf(f, cx, cy, cz);
+                            if constexpr (EXACT) {
+                                double b = best[w];
+                                int kb = kbest[w];
+                                double q = qf(f, cx, cy, cz);
+                                kb = q < b ? k0 : kb;
+                                b = fmin(b, q);
 #pragma unroll
-                            for (int i = 1; i < C; ++i)
-                                if (i < kn)
-                                    m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
-                            if (m < best[w]) {
-                                best[w] = m;
-                                kbest[w] = k0;
+                                for (int i = 1; i < C; ++i) {
+                                    if (i < kn) {
+                                        q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
+                                        kb = q < b ? k0 + i : kb;
+                                        b = fmin(b, q);
+                                    }
+                                }
+                                best[w] = b;
+                                kbest[w] = kb;
+                            } else {
+                                double m = qf(f, cx, cy, cz);
+#pragma unroll
+                                for (int i = 1; i < C; ++i)
+                                    if (i < kn)
+                                        m = fmin(m, qf(f, x[i - 1], y[i - 1], z[i - 1]));
+                                if (m < best[w]) {
+                                    best[w] = m;
+                                    kbest[w] = k0;
+                                }
                             }
                         }
                     }
@@ -928,8 +974,8 @@ struct TileScanWide {
             }
         }
         // the end: evaluation count, then per (lane, wire) the first index of the
-        // minimum (rescan of the half chunk that holds it), its chord refinement, D and
-        // Eq. 1's capped residual
+        // minimum (EXACT: already known; else a rescan of the half chunk that holds it),
+        // its chord refinement, D and Eq. 1's capped residual
         if (counter && lane == 0 && evals > 0)
             atomicAdd(counter, (unsigned long long)(evals * n_valid));
 #pragma unroll
@@ -938,8 +984,8 @@ struct TileScanWide {
         if (nw <= 0 || !seed)
             return;
         // the last chunk may hold up to C points in its one recorded span
-        finish<C, CAP>(bx, by, bz, ld, P, lane, fl, nw, wire_of, offsets, drift, lambda, best,
-                       kbest, rmax, sig, dsq);
+        finish<C, CAP, EXACT>(bx, by, bz, ld, P, lane, fl, nw, wire_of, offsets, drift, lambda,
+                              best, kbest, rmax, sig, dsq);
     }
 };
 

@@ -94,7 +94,7 @@ def test_batch_azimuth_shapes_on_an_event_past_their_wire_limit(events):
     big = synth.event_mix(3, noise_frac=0.85, hits=(1000, 2000))
     assert big.n_wires > 3 * 301 + 301 // 16 + 2 and events[0].n_wires < 900
     evs = [big, events[0]]
-    az = [i for i, v in enumerate(comet.batch_variants()) if v["form"] == "wide_cap_az"]
+    az = [i for i, v in enumerate(comet.batch_variants()) if v["form"].startswith("wide_cap_az")]
     assert az
     ref = None
     for i in [0] + az:
