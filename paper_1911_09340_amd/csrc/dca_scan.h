@@ -681,7 +681,8 @@ struct TileScanWide {
     // whose minimum stayed above the cap (or that no point came near) has every point
     // farther than r_max + lambda + the longest step, hence every chord farther than
     // r_max + lambda: its term is lambda^2, the full scan's, without a rescan.
-    // EXACT_K: kbest already holds the first index (no rescan).
+    // EXACT_K: kbest already holds the first index (no rescan), and the three points of
+    // four wires at a time are loaded before any of them is refined.
     template <int SPAN, bool CAPPED, bool EXACT_K = false>
     __device__ __forceinline__ static void finish(
         const double *__restrict__ bx, const double *__restrict__ by,
@@ -690,6 +691,66 @@ struct TileScanWide {
         const double *__restrict__ drift, double lambda, const double (&best)[W],
         const int (&kbest)[W], const double *__restrict__ rmax, double sig, double (&dsq)[W])
     {
+        if constexpr (EXACT_K) {
+            // the three points of G wires are loaded before any of them is refined (one
+            // round of loads per G wires instead of one per wire)
+            constexpr int G = 4;
+#pragma unroll
+            for (int w0 = 0; w0 < W; w0 += G) {
+                double pm[G][3], pc[G][3], pn[G][3];
+                bool in[G];
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int w = w0 + j;
+                    in[j] = w < W && w < nw;
+                    if constexpr (CAPPED) {
+                        if (in[j]) {
+                            const double c = (double)wide_cap(rmax[w], lambda, sig);
+                            in[j] = best[w] <= c * c;
+                        }
+                    }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        pm[j][a] = pc[j][a] = pn[j][a] = 0.0;
+                    if (in[j]) {
+                        const int k = kbest[w];
+                        const int64_t o = (int64_t)k * ld + lane;
+                        pc[j][0] = bx[o];
+                        pc[j][1] = by[o];
+                        pc[j][2] = bz[o];
+                        if (k > 0) {
+                            pm[j][0] = bx[o - ld];
+                            pm[j][1] = by[o - ld];
+                            pm[j][2] = bz[o - ld];
+                        }
+                        if (k < P - 1) {
+                            pn[j][0] = bx[o + ld];
+                            pn[j][1] = by[o + ld];
+                            pn[j][2] = bz[o + ld];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int w = w0 + j;
+                    if (w >= W || w >= nw)
+                        continue;
+                    if (!in[j]) {
+                        // CAPPED: every chord farther than r_max + lambda
+                        dsq[w] = lambda * lambda;
+                        continue;
+                    }
+                    double f[8];
+                    frame(fl, w, f);
+                    const double d2 = refine_dca2_at(f, kbest[w], P, best[w], pm[j], pc[j], pn[j]);
+                    const double D = sqrt(d2);
+                    const int wi = wire_of[w];
+                    const double d = capped_residual(D, drift, offsets[wi], offsets[wi + 1], lambda);
+                    dsq[w] = d * d;
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             if (w >= nw)
@@ -704,7 +765,7 @@ struct TileScanWide {
             double f[8];
             frame(fl, w, f);
             const int k = kbest[w];
-            int kf = k;  // EXACT_K: kbest is the first index itself
+            int kf = k;
             if constexpr (!EXACT_K) {
                 kf = -1;
                 for (int h0 = 0; h0 < SPAN && kf < 0; h0 += 8) {

@@ -325,6 +325,35 @@ __device__ __forceinline__ double refine_dca2(const double *__restrict__ tx,
     return d2;
 }
 
+// The same with the three points already loaded (pm: point k - 1, read only when k > 0;
+// pc: point k; pn: point k + 1, read only when k < P - 1): the same arithmetic in the
+// same order, for callers that load the points of several wires before refining any.
+__device__ __forceinline__ double refine_dca2_at(const double f[8], int k, int P, double qk,
+                                                 const double (&pm)[3], const double (&pc)[3],
+                                                 const double (&pn)[3])
+{
+    double cxi, ceta;
+    project(f, pc[0], pc[1], pc[2], cxi, ceta);
+    double d2 = qk;
+    if (k > 0) {
+        double xi, eta;
+        project(f, pm[0], pm[1], pm[2], xi, eta);
+        const double q = fma(xi, xi, eta * eta);
+        const double v = chord_distance2(xi, eta, q, cxi, ceta, qk);
+        if (v < d2)
+            d2 = v;
+    }
+    if (k < P - 1) {
+        double xi, eta;
+        project(f, pn[0], pn[1], pn[2], xi, eta);
+        const double q = fma(xi, xi, eta * eta);
+        const double v = chord_distance2(cxi, ceta, qk, xi, eta, q);
+        if (v < d2)
+            d2 = v;
+    }
+    return d2;
+}
+
 // The same with the seed-fastest track layout [3][P][S]: point j of seed s is
 // track[(c P + j) S + s].
 __device__ __forceinline__ double refine_dca2(const double *__restrict__ track, int64_t S, int P,
