@@ -496,7 +496,7 @@ def main():
     ap.add_argument("--grad-events", type=int, default=256,
                     help="events of the batched mix for the coarse+LM vs fine-grid comparison "
                          "(0 = skip; 256 = the full differentiation workload)")
-    ap.add_argument("--grad-topk", type=int, default=16,
+    ap.add_argument("--grad-topk", type=int, default=128,
                     help="LM starts per partition (the lowest-RSS coarse seeds)")
     ap.add_argument("--grad-iters", type=int, default=32, help="LM iterations")
     ap.add_argument("--no-multiref", dest="multiref", action="store_false",
@@ -771,13 +771,17 @@ def main():
         from paper_1911_09340_amd import refine
         log("coarse 8^4 + LM vs fine 32^4 grid on %d events ..." % len(grad_events))
         out["grad_refine"] = refine.compare(grad_events, synth.C3_COARSE, synth.C3_FINE,
-                                            local=(8, 8, 8, 8), local_topk=4, local_iters=16,
+                                            local=(16, 16, 8, 8), local_topk=16, local_iters=32,
                                             top_k=args.grad_topk, n_iter=args.grad_iters)
         g = out["grad_refine"]
         log("  coarse+LM %.2f s, |p| residual rms %.3f core %.3f MeV/c; fine grid %.2f s, rms %.3f "
-            "core %.3f" % (g["coarse_lm"]["seconds"], g["coarse_lm"]["rms"],
-                           g["coarse_lm"]["core_sigma"], g["fine_grid"]["seconds"],
-                           g["fine_grid"]["rms"], g["fine_grid"]["core_sigma"]))
+            "core %.3f; LM at or below the fine grid's RSS in %.3f of partitions" % (
+                g["coarse_lm"]["seconds"], g["coarse_lm"]["rms"], g["coarse_lm"]["core_sigma"],
+                g["fine_grid"]["seconds"], g["fine_grid"]["rms"], g["fine_grid"]["core_sigma"],
+                g["rss_lm_below_fine"]))
+        log("  by the event's turns (rms coarse+LM / fine, RSS below): " + ", ".join(
+            "%s: %.3f / %.3f, %.3f" % (k, v["coarse_lm_rms"], v["fine_grid_rms"],
+                                       v["rss_lm_below_fine"]) for k, v in g["by_turns"].items()))
     if stress_events:
         log("stress mix: %d events, batched scan + LM from the top 64 seeds ..." % len(stress_events))
         out["stress"] = bench_stress(stress_events, synth.C4)

@@ -127,10 +127,22 @@ def compare(events, coarse: synth.ScanConfig, fine: synth.ScanConfig, top_k: int
     t2 = time.perf_counter()
     lm_rss = lm["rss"].cpu().numpy()
     fg_rss = fg["rss"].cpu().numpy()
+    lm_res = momentum_residuals(lm["refined"], events)
+    fg_res = momentum_residuals(fg["best"], events)
+    # per partition: its event's number of turns (the other turns' hits enter Eq. 1 too)
+    turns = np.concatenate([np.full(ev.n_turns, ev.n_turns) for ev in events])
+    by_turns = {}
+    for lo, hi, name in ((1, 1, "1"), (2, 2, "2"), (3, 99, "3+")):
+        sel = (turns >= lo) & (turns <= hi)
+        if sel.any():
+            by_turns[name] = {"partitions": int(sel.sum()),
+                              "coarse_lm_rms": float(np.sqrt(np.mean(lm_res[sel] ** 2))),
+                              "fine_grid_rms": float(np.sqrt(np.mean(fg_res[sel] ** 2))),
+                              "rss_lm_below_fine": float(np.mean(lm_rss[sel] <= fg_rss[sel]))}
     return {
         "events": len(events),
         "partitions": lm["partitions"],
-        "coarse_lm": {"seconds": t1 - t0, **summary(momentum_residuals(lm["refined"], events)),
+        "coarse_lm": {"seconds": t1 - t0, **summary(lm_res),
                       "mean_accepted_steps": float(lm["accepted"].float().mean().item()),
                       "starts_per_partition": top_k, "starts": starts,
                       "lm_iterations": n_iter,
@@ -139,8 +151,9 @@ def compare(events, coarse: synth.ScanConfig, fine: synth.ScanConfig, top_k: int
                           "lm_iterations": local_iters,
                           "partitions_improved": float(lm["local_improved"].float().mean())}},
         "coarse_only": summary(momentum_residuals(lm["coarse"], events)),
-        "fine_grid": {"seconds": t2 - t1, **summary(momentum_residuals(fg["best"], events))},
+        "fine_grid": {"seconds": t2 - t1, **summary(fg_res)},
         "rss_lm_below_fine": float(np.mean(lm_rss <= fg_rss)),
+        "by_turns": by_turns,
         "coarse_grid": "%s = %d seeds" % ("x".join(map(str, coarse.n)), coarse.n_seeds),
         "fine_grid_shape": "%s = %d seeds" % ("x".join(map(str, fine.n)), fine.n_seeds),
     }
