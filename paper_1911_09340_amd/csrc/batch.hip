@@ -269,7 +269,7 @@ batch_scan_kernel(BatchArgs a)
 // with more wires takes them in wire order. EXACT: the scan tracks the first index of
 // each minimum point by point (no rescan at the end).
 template <int W, int NWV, int SUP, int WPE, bool FIELD = false, bool CAP = false,
-          bool AZ = false, bool EXACT = false>
+          bool AZ = false, bool EXACT = false, int HS = 0>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_wide_kernel(BatchArgs a)
 {
@@ -355,7 +355,7 @@ batch_wide_kernel(BatchArgs a)
             for (int w = 0; w < W; ++w)
                 wire_of[w] = az && w < nw ? a.wire_of_az[g0 + w] : g0 + w;
             double d2[W];
-            TileScanWide<W, SUP, true, CAP, EXACT>::run(sx, sy, sz, 64, P, n_valid, fl, nw,
+            TileScanWide<W, SUP, true, CAP, EXACT, HS>::run(sx, sy, sz, 64, P, n_valid, fl, nw,
                                                         wire_of, a.offsets, a.drift, a.lambda,
                                                         rho, 64, a.evals, d2, rmx);
             if (az) {
@@ -870,6 +870,9 @@ const BatchVariant kBatchVariants[] = {
     // the same with the first index of the minimum tracked point by point (direct == 5)
     {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true>, 4},
     {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true>, 4},
+    // ... with each half (or quarter) of a needed chunk tested per wire
+    {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true, 2>, 4},
+    {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true, 4>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform

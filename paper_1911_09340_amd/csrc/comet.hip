@@ -274,8 +274,11 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(4))) v
 
 // The wide form (TileScanWide): a block is a 64-seed tile x NWV waves of W wires in
 // azimuth order; the block's frames are copied to LDS once. WPE: waves per SIMD the
-// registers are sized for; EXACT: the first index of the minimum tracked point by point.
-template <int W, int NWV, int SUP, int WPE, int NB = 0, bool CAP = false, bool EXACT = false>
+// registers are sized for; EXACT: the first index of the minimum tracked point by point;
+// HS (with CAP and EXACT): a needed chunk in HS parts, each tested per wire before it is
+// scanned (0: no parts).
+template <int W, int NWV, int SUP, int WPE, int NB = 0, bool CAP = false, bool EXACT = false,
+          int HS = 0>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void dca_wide_kernel(
     const double *__restrict__ track, int64_t S, int P, const double *__restrict__ frames_sorted,
     const int32_t *__restrict__ wire_of, const double *__restrict__ caps, int n_w,
@@ -304,9 +307,9 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE)))
     double d2[W];
     // NB > 0: the latency-hiding form (batches of NB chunk tests, double-buffered halves)
     using Near = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), true, CAP>,
-                                    TileScanWide<W, SUP, true, CAP, EXACT>>;
+                                    TileScanWide<W, SUP, true, CAP, EXACT, HS>>;
     using Far = std::conditional_t<(NB > 0), TileScanWideP<W, (NB > 0 ? NB : 1), false, CAP>,
-                                   TileScanWide<W, SUP, false, CAP, EXACT>>;
+                                   TileScanWide<W, SUP, false, CAP, EXACT, HS>>;
     if ((int64_t)P * S < ((int64_t)1 << 29) - 64)
         Near::run(track + s0, track + PS + s0, track + 2 * PS + s0, S, P, n_valid,
                   fl + wave * W * 8, nw, wire_of + wbase, offsets, drift, lambda, rho + s0, S,
@@ -533,6 +536,12 @@ const DcaVariant kDcaVariants[] = {
     {16, 1, 16, 0, 1, 5, 4, nullptr, dca_wide_kernel<16, 1, 4, 2, 0, true, true>, 2, "dca_wide_kernel<16, 1, 4, 2, 0, true, true>"},
     {12, 1, 16, 0, 1, 5, 4, nullptr, dca_wide_kernel<12, 1, 4, 2, 0, true, true>, 2, "dca_wide_kernel<12, 1, 4, 2, 0, true, true>"},
     {8, 1, 16, 0, 1, 5, 4, nullptr, dca_wide_kernel<8, 1, 4, 2, 0, true, true>, 2, "dca_wide_kernel<8, 1, 4, 2, 0, true, true>"},
+    // ... with each half (or quarter) of a needed chunk tested per wire (within 7 (3) longest
+    // steps of its first point)
+    {16, 1, 16, 0, 1, 5, 4, nullptr, dca_wide_kernel<16, 1, 4, 2, 0, true, true, 2>, 2, "dca_wide_kernel<16, 1, 4, 2, 0, true, true, 2>"},
+    {12, 1, 16, 0, 1, 5, 4, nullptr, dca_wide_kernel<12, 1, 4, 2, 0, true, true, 2>, 2, "dca_wide_kernel<12, 1, 4, 2, 0, true, true, 2>"},
+    {16, 1, 16, 0, 1, 5, 4, nullptr, dca_wide_kernel<16, 1, 4, 2, 0, true, true, 4>, 2, "dca_wide_kernel<16, 1, 4, 2, 0, true, true, 4>"},
+    {12, 1, 16, 0, 1, 5, 4, nullptr, dca_wide_kernel<12, 1, 4, 2, 0, true, true, 4>, 2, "dca_wide_kernel<12, 1, 4, 2, 0, true, true, 4>"},
 };
 constexpr int kNumDcaVariants = sizeof(kDcaVariants) / sizeof(kDcaVariants[0]);
 constexpr int kMaxWiresPerGroup = 96;  // largest W * NWV in the table above

@@ -643,7 +643,7 @@ __device__ __forceinline__ float wide_cap(double rmax, double lambda, double sig
     return (float)((rmax + lambda) + sigma) * 1.000001f + 1e-5f;
 }
 
-template <int W, int SUP, bool BUF, bool CAP = false, bool EXACT = false>
+template <int W, int SUP, bool BUF, bool CAP = false, bool EXACT = false, int HS = 0>
 struct TileScanWide {
     static constexpr int C = kRadiusChunk;  // one radius window per chunk
     static constexpr int H = C / 2;         // the minimum is tracked per half chunk
@@ -941,7 +941,37 @@ struct TileScanWide {
                             if ((needm >> w) & 1u) {
                                 double f[8];
                                 frame(fl, w, f);
-                                if constexpr (EXACT) {
+                                if constexpr (EXACT && HS > 1 && CAP) {
+                                    // the chunk in HS parts of L points: each part lies
+                                    // within (L - 1) sig of its first point (sig: the
+                                    // track's longest step), so a part is evaluated only
+                                    // where some lane's bound needs it
+                                    constexpr int L = C / HS;
+                                    static_assert(L * HS == C && L > 1, "parts of a chunk");
+                                    const float rh = (float)(sig * (L - 1)) * 1.000001f;
+                                    double b = best[w];
+                                    int kb = kbest[w];
+#pragma unroll
+                                    for (int g = 0; g < HS; ++g) {
+                                        const int i0 = g * L;
+                                        const double q0 = i0 == 0 ? qf(f, cx, cy, cz)
+                                                                  : qf(f, x[i0 - 1], y[i0 - 1], z[i0 - 1]);
+                                        if (__builtin_amdgcn_ballot_w64(needs(q0, rh, sub[w]) && seed) != 0) {
+                                            kb = q0 < b ? k0 + i0 : kb;
+                                            b = fmin(b, q0);
+#pragma unroll
+                                            for (int i = i0 + 1; i < i0 + L; ++i) {
+                                                const double q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
+                                                kb = q < b ? k0 + i : kb;
+                                                b = fmin(b, q);
+                                            }
+                                            evals += L - 1;
+                                        }
+                                    }
+                                    evals += (HS - 1) - (C - 1);  // the parts' test points
+                                    best[w] = b;
+                                    kbest[w] = kb;
+                                } else if constexpr (EXACT) {
                                     // point by point: k replaces kbest only below the
                                     // running minimum (fmin equals that select here: the
                                     // minimum is never NaN and q is never -0)
