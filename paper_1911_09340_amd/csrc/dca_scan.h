@@ -941,7 +941,42 @@ struct TileScanWide {
                             if ((needm >> w) & 1u) {
                                 double f[8];
                                 frame(fl, w, f);
-                                if constexpr (EXACT && HS > 1 && CAP) {
+                                if constexpr (EXACT && HS == 2 && CAP) {
+                                    // each half chunk lies within (H - 1) sig of its first
+                                    // point (sig: the track's longest step), so a half is
+                                    // evaluated only where some lane's bound needs it (the
+                                    // loop below with two parts compiles to slower code)
+                                    const float rh = (float)(sig * (H - 1)) * 1.000001f;
+                                    double b = best[w];
+                                    int kb = kbest[w];
+                                    const double qa = qf(f, cx, cy, cz);
+                                    if (__builtin_amdgcn_ballot_w64(needs(qa, rh, sub[w]) && seed) != 0) {
+                                        kb = qa < b ? k0 : kb;
+                                        b = fmin(b, qa);
+#pragma unroll
+                                        for (int i = 1; i < H; ++i) {
+                                            const double q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
+                                            kb = q < b ? k0 + i : kb;
+                                            b = fmin(b, q);
+                                        }
+                                        evals += H - 1;
+                                    }
+                                    const double qh = qf(f, x[H - 1], y[H - 1], z[H - 1]);
+                                    if (__builtin_amdgcn_ballot_w64(needs(qh, rh, sub[w]) && seed) != 0) {
+                                        kb = qh < b ? k0 + H : kb;
+                                        b = fmin(b, qh);
+#pragma unroll
+                                        for (int i = H + 1; i < C; ++i) {
+                                            const double q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
+                                            kb = q < b ? k0 + i : kb;
+                                            b = fmin(b, q);
+                                        }
+                                        evals += H - 1;
+                                    }
+                                    evals += 1 - (C - 1);  // the second half's test point
+                                    best[w] = b;
+                                    kbest[w] = kb;
+                                } else if constexpr (EXACT && HS > 2 && CAP) {
                                     // the chunk in HS parts of L points: each part lies
                                     // within (L - 1) sig of its first point (sig: the
                                     // track's longest step), so a part is evaluated only
