@@ -605,8 +605,8 @@ int comet_union_halves(const int32_t *pair, const int32_t *n_complete, int32_t n
  * as for the DCA shapes, with direct = 4 for the wide form with the residual cap whose
  * waves take each event's wires in azimuth order (events of more than 3 (n_steps + 1)
  * wires in wire order) and 5 for that form with the first index of each minimum
- * tracked point by point; blocks, direct and runs may be NULL); every shape gives the
- * same results.
+ * tracked point by point (one shape also testing each half of a needed chunk per wire);
+ * blocks, direct and runs may be NULL); every shape gives the same results.
  * comet_batch_set_variant selects the shape (default 0). */
 int comet_batch_variant_count(void);
 int comet_batch_variant_info(int id, int32_t *w, int32_t *nwv, int32_t *chunk, int32_t *blocks,
@@ -657,7 +657,8 @@ int comet_profile_scan_points(int64_t *points);
  * azimuth order, frames in LDS, each wire of a needed chunk scanned only where the
  * bound needs it; 3: wide with Eq. 1's residual cap in the bound; 5: that form with the
  * first index of each minimum tracked point by point, so that the end reads only the
- * chord refinement's points) and runs (direct and
+ * chord refinement's points, some shapes also testing each half or quarter of a needed
+ * chunk per wire before scanning it) and runs (direct and
  * wide shapes: chunks tested in runs of that many first, from the summed radii of their
  * windows; 1 = no runs); direct and runs may be NULL. comet_dca_variant_name(id): the
  * shape's kernel as a profiler names it ("" for an id out of range). */
