@@ -853,7 +853,138 @@ struct TileScanWide {
             for (int w = 0; w < W; ++w)
                 sub[w] = w < nw ? wide_cap(rmax[w], lambda, sig) : 0.0f;
         }
-        if (nw > 0) {
+        if constexpr (EXACT && HS > 0 && CAP) {
+            // Chunk parts (HS > 0). Every test measures from the middle of its stretch, all
+            // of whose points lie within half its length times sig (the track's longest
+            // step) of that point: a run of SUP chunks from its point SUP C / 2, a chunk
+            // from its point C / 2, and each of the HS parts of a needed chunk, per wire,
+            // from its own middle point; a part is scanned only where some lane's bound
+            // needs it. The next chunk's middle point loads while the current chunk is
+            // tested and scanned.
+            constexpr int L = C / HS;  // points per part
+            static_assert(L * HS == C && L > 1, "parts of a chunk");
+            const float r_run = (float)(sig * (SUP * C / 2)) * 1.000001f;
+            const float r_chk = (float)(sig * (C / 2)) * 1.000001f;
+            const float r_prt = (float)(sig * (L / 2)) * 1.000001f;
+            const int nch = (P + C - 1) / C;
+            double mx = 0.0, my = 0.0, mz = 0.0;  // chunk n's middle point, when m_ok
+            bool m_ok = false;
+            for (int n = 0; nw > 0 && n < nch;) {
+                __asm__ volatile("" ::: "memory");  // frames are re-read from LDS below
+                const int k0 = n * C;
+                const int kn = min(C, P - k0);
+                if (SUP > 1 && n % SUP == 0 && k0 + SUP * C <= P) {
+                    double rx, ry, rz;
+                    load(k0 + SUP * C / 2, rx, ry, rz);
+                    if (!m_ok) {
+                        load(k0 + C / 2, mx, my, mz);
+                        m_ok = true;
+                    }
+                    bool lane_need = false;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        double f[8];
+                        frame(fl, w, f);
+                        lane_need = lane_need || (w < nw && needs(qf(f, rx, ry, rz), r_run, sub[w]));
+                    }
+                    evals += nw;
+                    if (__builtin_amdgcn_ballot_w64(lane_need && seed) == 0) {
+                        n += SUP;
+                        m_ok = false;
+                        continue;
+                    }
+                }
+                if (kn == C) {
+                    if (!m_ok)
+                        load(k0 + C / 2, mx, my, mz);
+                    const bool next_full = (n + 2) * C <= P;
+                    double nx = 0.0, ny = 0.0, nz = 0.0;
+                    if (next_full)
+                        load(k0 + C + C / 2, nx, ny, nz);
+                    uint32_t needm = 0;  // wave-uniform: the wires some lane needs here
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        double f[8];
+                        frame(fl, w, f);
+                        const bool ln = w < nw && needs(qf(f, mx, my, mz), r_chk, sub[w]);
+                        if (__builtin_amdgcn_ballot_w64(ln && seed) != 0)
+                            needm |= 1u << w;
+                    }
+                    evals += nw;
+                    if (needm != 0) {
+                        double x[C], y[C], z[C];
+#pragma unroll
+                        for (int i = 0; i < C; ++i)
+                            load(k0 + i, x[i], y[i], z[i]);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            if ((needm >> w) & 1u) {
+                                double f[8];
+                                frame(fl, w, f);
+                                double b = best[w];
+                                int kb = kbest[w];
+#pragma unroll
+                                for (int g = 0; g < HS; ++g) {
+                                    const int i0 = g * L, im = i0 + L / 2;
+                                    const double qm = qf(f, x[im], y[im], z[im]);
+                                    if (__builtin_amdgcn_ballot_w64(needs(qm, r_prt, sub[w]) && seed) != 0) {
+                                        // point by point, in order (the middle one's q reused)
+#pragma unroll
+                                        for (int i = i0; i < i0 + L; ++i) {
+                                            const double q = i == im ? qm : qf(f, x[i], y[i], z[i]);
+                                            kb = q < b ? k0 + i : kb;
+                                            b = fmin(b, q);
+                                        }
+                                        evals += L - 1;
+                                    }
+                                }
+                                evals += HS;  // the parts' middle points
+                                best[w] = b;
+                                kbest[w] = kb;
+                                // the running minimum bounds the final one as well
+                                sub[w] = fminf(sub[w], __builtin_amdgcn_sqrtf((float)b) * 1.000001f);
+                            }
+                        }
+                    }
+                    mx = nx;
+                    my = ny;
+                    mz = nz;
+                    m_ok = next_full;
+                } else {
+                    // the partial last chunk: every wire, every point
+                    double x[C], y[C], z[C];
+#pragma unroll
+                    for (int i = 0; i < C; ++i) {
+                        x[i] = y[i] = z[i] = 0.0;
+                        if (i < kn)
+                            load(k0 + i, x[i], y[i], z[i]);
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        if (w < nw) {
+                            double f[8];
+                            frame(fl, w, f);
+                            double b = best[w];
+                            int kb = kbest[w];
+#pragma unroll
+                            for (int i = 0; i < C; ++i) {
+                                if (i < kn) {
+                                    const double q = qf(f, x[i], y[i], z[i]);
+                                    kb = q < b ? k0 + i : kb;
+                                    b = fmin(b, q);
+                                }
+                            }
+                            best[w] = b;
+                            kbest[w] = kb;
+                        }
+                    }
+                    evals += (int64_t)nw * kn;
+                    m_ok = false;
+                }
+                ++n;
+            }
+        }
+        if (!(EXACT && HS > 0 && CAP) && nw > 0) {
             // (A) upper bounds of the final minima: every other chunk's first point, eight
             // points per pass, each frame read once per pass (not needed with the cap)
             float ub[W];
@@ -941,72 +1072,7 @@ struct TileScanWide {
                             if ((needm >> w) & 1u) {
                                 double f[8];
                                 frame(fl, w, f);
-                                if constexpr (EXACT && HS == 2 && CAP) {
-                                    // each half chunk lies within (H - 1) sig of its first
-                                    // point (sig: the track's longest step), so a half is
-                                    // evaluated only where some lane's bound needs it (the
-                                    // loop below with two parts compiles to slower code)
-                                    const float rh = (float)(sig * (H - 1)) * 1.000001f;
-                                    double b = best[w];
-                                    int kb = kbest[w];
-                                    const double qa = qf(f, cx, cy, cz);
-                                    if (__builtin_amdgcn_ballot_w64(needs(qa, rh, sub[w]) && seed) != 0) {
-                                        kb = qa < b ? k0 : kb;
-                                        b = fmin(b, qa);
-#pragma unroll
-                                        for (int i = 1; i < H; ++i) {
-                                            const double q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
-                                            kb = q < b ? k0 + i : kb;
-                                            b = fmin(b, q);
-                                        }
-                                        evals += H - 1;
-                                    }
-                                    const double qh = qf(f, x[H - 1], y[H - 1], z[H - 1]);
-                                    if (__builtin_amdgcn_ballot_w64(needs(qh, rh, sub[w]) && seed) != 0) {
-                                        kb = qh < b ? k0 + H : kb;
-                                        b = fmin(b, qh);
-#pragma unroll
-                                        for (int i = H + 1; i < C; ++i) {
-                                            const double q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
-                                            kb = q < b ? k0 + i : kb;
-                                            b = fmin(b, q);
-                                        }
-                                        evals += H - 1;
-                                    }
-                                    evals += 1 - (C - 1);  // the second half's test point
-                                    best[w] = b;
-                                    kbest[w] = kb;
-                                } else if constexpr (EXACT && HS > 2 && CAP) {
-                                    // the chunk in HS parts of L points: each part lies
-                                    // within (L - 1) sig of its first point (sig: the
-                                    // track's longest step), so a part is evaluated only
-                                    // where some lane's bound needs it
-                                    constexpr int L = C / HS;
-                                    static_assert(L * HS == C && L > 1, "parts of a chunk");
-                                    const float rh = (float)(sig * (L - 1)) * 1.000001f;
-                                    double b = best[w];
-                                    int kb = kbest[w];
-#pragma unroll
-                                    for (int g = 0; g < HS; ++g) {
-                                        const int i0 = g * L;
-                                        const double q0 = i0 == 0 ? qf(f, cx, cy, cz)
-                                                                  : qf(f, x[i0 - 1], y[i0 - 1], z[i0 - 1]);
-                                        if (__builtin_amdgcn_ballot_w64(needs(q0, rh, sub[w]) && seed) != 0) {
-                                            kb = q0 < b ? k0 + i0 : kb;
-                                            b = fmin(b, q0);
-#pragma unroll
-                                            for (int i = i0 + 1; i < i0 + L; ++i) {
-                                                const double q = qf(f, x[i - 1], y[i - 1], z[i - 1]);
-                                                kb = q < b ? k0 + i : kb;
-                                                b = fmin(b, q);
-                                            }
-                                            evals += L - 1;
-                                        }
-                                    }
-                                    evals += (HS - 1) - (C - 1);  // the parts' test points
-                                    best[w] = b;
-                                    kbest[w] = kb;
-                                } else if constexpr (EXACT) {
+                                if constexpr (EXACT) {
                                     // point by point: k replaces kbest only below the
                                     // running minimum (fmin equals that select here: the
                                     // minimum is never NaN and q is never -0)
