@@ -870,9 +870,12 @@ const BatchVariant kBatchVariants[] = {
     // the same with the first index of the minimum tracked point by point (direct == 5)
     {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true>, 4},
     {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true>, 4},
-    // ... with each half of a needed chunk tested per wire (quarters measured slower here:
-    // 169 against 178 events/s on the 1024-event mix)
+    // ... with each half (or quarter) of a needed chunk tested per wire, every test from
+    // the middle of its stretch (on the full 1024-event mix: 196 events/s for 12 wires
+    // in halves, 183 for 16; 16 wires in quarters 183, 8 wires in halves 175)
     {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true, 2>, 4},
+    {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true, 2>, 4},
+    {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true, 4>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
