@@ -605,7 +605,8 @@ int comet_union_halves(const int32_t *pair, const int32_t *n_complete, int32_t n
  * as for the DCA shapes, with direct = 4 for the wide form with the residual cap whose
  * waves take each event's wires in azimuth order (events of more than 3 (n_steps + 1)
  * wires in wire order) and 5 for that form with the first index of each minimum
- * tracked point by point (one shape also testing each half of a needed chunk per wire);
+ * tracked point by point (three shapes also testing each half or quarter of a needed
+ * chunk per wire, every test from the middle of its stretch);
  * blocks, direct and runs may be NULL); every shape gives the same results.
  * comet_batch_set_variant selects the shape (default 0). */
 int comet_batch_variant_count(void);
