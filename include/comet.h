@@ -326,7 +326,9 @@ int comet_lm_refine_field(double *seeds6, int64_t n_seeds, const comet_config *c
  *   n_borderline device int32[n_partitions] or NULL
  *   max_items    > 0: scan only the first max_items 64-seed tiles (partition-major) of
  *                every scan (for timing shapes; the other RSS are not written, and a
- *                partition not scanned in full keeps best = -1)
+ *                partition not scanned in full keeps best = -1). A tile is 64
+ *                consecutive seeds, or for the blocked shapes a 2 x 2 x 4 x 4 block of the
+ *                grid when its axes allow one.
  *   workspace    >= comet_batch_workspace_bytes(n_wires, n_steps, n_partitions),
  *                256-byte aligned */
 size_t comet_batch_workspace_bytes(int32_t n_wires, int32_t n_steps, int32_t n_partitions);
@@ -605,8 +607,9 @@ int comet_union_halves(const int32_t *pair, const int32_t *n_complete, int32_t n
  * as for the DCA shapes, with direct = 4 for the wide form with the residual cap whose
  * waves take each event's wires in azimuth order (events of more than 3 (n_steps + 1)
  * wires in wire order) and 5 for that form with the first index of each minimum
- * tracked point by point (three shapes also testing each half or quarter of a needed
- * chunk per wire, every test from the middle of its stretch);
+ * tracked point by point (five shapes also testing each half or quarter of a needed
+ * chunk per wire, every test from the middle of its stretch, two of them taking each
+ * tile as a 2 x 2 x 4 x 4 block of the grid);
  * blocks, direct and runs may be NULL); every shape gives the same results.
  * comet_batch_set_variant selects the shape (default 0). */
 int comet_batch_variant_count(void);

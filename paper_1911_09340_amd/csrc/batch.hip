@@ -269,7 +269,7 @@ batch_scan_kernel(BatchArgs a)
 // with more wires takes them in wire order. EXACT: the scan tracks the first index of
 // each minimum point by point (no rescan at the end).
 template <int W, int NWV, int SUP, int WPE, bool FIELD = false, bool CAP = false,
-          bool AZ = false, bool EXACT = false, int HS = 0>
+          bool AZ = false, bool EXACT = false, int HS = 0, bool BLK = false>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(WPE))) void
 batch_wide_kernel(BatchArgs a)
 {
@@ -286,6 +286,26 @@ batch_wide_kernel(BatchArgs a)
     double *const sx = a.scratch + ((int64_t)blockIdx.x * NWV + wave) * (3 * row + rrow);
     double *const sy = sx + row, *const sz = sy + row;
     double *const rho = sz + row;
+    // BLK: a tile is a 2 x 2 x 4 x 4 block of the grid (the four axes, the last fastest)
+    // when the axes allow it, so that its 64 tracks stay closer together than those of
+    // 64 consecutive seeds (fewer chunks pass the bound); every tile is then full. Lane
+    // l of tile t takes seed seed_at(64 t + l), and its RSS goes to that seed's place.
+    const bool blk = BLK && a.n0 % 2 == 0 && a.n1 % 2 == 0 && a.n2 % 4 == 0 && a.n3 % 4 == 0;
+    auto seed_at = [&](int64_t c) -> int64_t {
+        if (!blk)
+            return c;
+        int64_t r = c >> 6;
+        const int l = (int)(c & 63);
+        const int b3 = (int)(r % (a.n3 >> 2));
+        r /= a.n3 >> 2;
+        const int b2 = (int)(r % (a.n2 >> 2));
+        r /= a.n2 >> 2;
+        const int b1 = (int)(r % (a.n1 >> 1));
+        r /= a.n1 >> 1;
+        const int64_t i0 = 2 * r + (l >> 5);
+        const int i1 = 2 * b1 + ((l >> 4) & 1), i2 = 4 * b2 + ((l >> 2) & 3), i3 = 4 * b3 + (l & 3);
+        return ((i0 * a.n1 + i1) * a.n2 + i2) * a.n3 + i3;
+    };
 
     for (;;) {
         const int64_t item = __builtin_amdgcn_readfirstlane(atomicAdd(a.counter, lane == 0 ? 1 : 0));
@@ -301,7 +321,8 @@ batch_wide_kernel(BatchArgs a)
         const int w0 = a.ev_wires[e], w1 = a.ev_wires[e + 1];
         if (lane < n_valid) {
             double st[6];
-            seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, s0 + lane, st);
+            seed_from_grid(a.grids + 14 * (int64_t)p, a.n0, a.n1, a.n2, a.n3, seed_at(s0 + lane),
+                           st);
             if constexpr (FIELD) {
                 record_field_track(a.fm, st, a.charge, a.h, a.K, sx, sy, sz, rho + lane, lane);
             } else {
@@ -375,7 +396,7 @@ batch_wide_kernel(BatchArgs a)
             for (int i = 0; i < w1 - w0; ++i)
                 acc = acc + dq[(int64_t)i * 64 + lane];
         if (lane < n_valid)
-            a.rss[(int64_t)p * a.S + s0 + lane] = acc;
+            a.rss[(int64_t)p * a.S + seed_at(s0 + lane)] = acc;
         // completion counter of partition p; the wave that counts its last tile selects
         // the partition's best seed (release before the count, acquire before the reads)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -876,6 +897,9 @@ const BatchVariant kBatchVariants[] = {
     {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true, 2>, 4},
     {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true, 2>, 4},
     {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true, 4>, 4},
+    // ... with each tile a 2 x 2 x 4 x 4 block of the grid
+    {12, 4, 16, 5, batch_wide_kernel<12, 4, 4, 2, false, true, true, true, 2, true>, 4},
+    {16, 4, 16, 5, batch_wide_kernel<16, 4, 4, 2, false, true, true, true, 2, true>, 4},
 };
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 // Tracks in a field map: one shape (the wave-independent 4 x 8 x 16), so the uniform
