@@ -129,6 +129,28 @@ def test_batch_every_shape_identical(events):
     comet.set_batch_variant(0)
 
 
+def test_batch_every_shape_identical_on_a_blocked_grid(events):
+    """A grid whose axes hold 2 x 2 x 4 x 4 blocks (2 x 4 x 8 x 8 = 512 seeds, 8 tiles):
+    the blocked shapes take each tile as such a block and write every RSS to its seed's
+    place; every shape must give the bits of shape 0 (RSS in grid order, best seeds,
+    masks), also after a re-scan."""
+    sc = synth.ScanConfig("blocked", (2, 4, 8, 8), (5.0, 5.0, 0.05, 0.05), 400, 2.0, 0.8, 1)
+    ref = None
+    try:
+        for i in range(len(comet.batch_variants())):
+            comet.set_batch_variant(i)
+            runner = scan.BatchRunner(events[:3], sc)
+            runner.run()
+            got = (runner.rss.cpu().numpy(), runner.best.cpu().numpy(), runner.mask.cpu().numpy())
+            if ref is None:
+                ref = got
+            else:
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b), i
+    finally:
+        comet.set_batch_variant(0)
+
+
 def test_batch_matches_cpu_reference(orc, events):
     runner = scan.BatchRunner(events[:2], SC)
     runner.run()
